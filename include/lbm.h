@@ -1,0 +1,186 @@
+/*
+ * lbm.h -- C ABI of the multirate MRT lattice-Boltzmann hot path for
+ * thermosolutal dendritic solidification (phase field with anisotropic
+ * streaming and anti-trapping current, concentration, temperature, flow),
+ * built for AMD MI355X (gfx950).
+ *
+ * The method (paper: "A unified multirate lattice Boltzmann framework for
+ * thermosolutal dendritic solidification"):
+ *   - every field chi in {phi, U, T, F} is carried by its own distributions
+ *     and collides with the moment-space MRT operator of Eq. (14);
+ *   - field chi advances with its own step dt_chi = N_chi * dt_base
+ *     (Eq. 34) and relaxation times scale with dt_chi (Eq. 24, 32);
+ *   - after every phase update the resolved increment dphi (Eq. 36) is
+ *     turned into solute and latent-heat increments (Eq. 37-38) that are
+ *     injected at once into U and T (Eq. 39).
+ *
+ * Conventions for every entry point:
+ *   - Lattice units: dx = 1; time in the unit of dt_base.
+ *   - Grids are x-fastest; 2D domains have nz = 1.
+ *   - Every call returns an lbm_status; no exception crosses the ABI;
+ *     lbm_last_error() returns the text of the last failure of a context.
+ *   - All device work is issued on the stream passed to lbm_create (NULL =
+ *     the default stream).  Only lbm_step_multirate with a non-NULL diag
+ *     output, lbm_read_fields to host memory and lbm_write_fields from host
+ *     memory synchronise with that stream.
+ *   - The library allocates device memory only inside lbm_create (and only
+ *     when no workspace is supplied) and frees it only in lbm_destroy.
+ *   - A context is not thread-safe; distinct contexts are independent.
+ */
+#ifndef LBM_H
+#define LBM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx;
+
+typedef enum {
+  LBM_OK = 0,
+  LBM_EINVAL = -1,     /* bad argument: tau <= 1/2, N_chi < 1, bad sizes, ... */
+  LBM_ENOMEM = -2,     /* device allocation failed or workspace too small     */
+  LBM_EDEVICE = -3,    /* a HIP call failed                                   */
+  LBM_EUNSTABLE = -4,  /* non-finite values were found by the diagnostics     */
+  LBM_ESTATE = -5      /* call not valid in the current state                 */
+} lbm_status;
+
+/* Field selection masks for lbm_read_fields / lbm_write_fields.  Planes are
+ * packed in the order of the bits below (lowest bit first), each plane
+ * nx*ny*nz values, x fastest. */
+enum {
+  LBM_F_PHI = 1 << 0,    /* phi                                   (1 plane)  */
+  LBM_F_U = 1 << 1,      /* U                                     (1 plane)  */
+  LBM_F_T = 1 << 2,      /* T                                     (1 plane)  */
+  LBM_F_RHO = 1 << 3,    /* flow density                          (1 plane)  */
+  LBM_F_VEL = 1 << 4,    /* flow velocity u_x, u_y[, u_z]         (dim)      */
+  LBM_F_POP_PHI = 1 << 5,/* phase populations f_0..f_{Q-1}        (Q)        */
+  LBM_F_JU = 1 << 6,     /* first moment of the U populations     (dim)      */
+  LBM_F_JT = 1 << 7,     /* first moment of the T populations     (dim)      */
+  LBM_F_POP_F = 1 << 8,  /* flow populations f_0..f_{QF-1}        (QF)       */
+  LBM_F_PEND_U = 1 << 9, /* pending U increments (accumulated coupling)      */
+  LBM_F_PEND_T = 1 << 10,/* pending T increments (accumulated coupling)      */
+  LBM_F_SPHI = 1 << 11,  /* stored phase planes s_i = f_i - w_i phi, i>=1 (4) */
+  LBM_F_SF = 1 << 12     /* stored flow planes s_i = f_i - w_i rho, i>=1  (8) */
+};
+/* A checkpoint that restores bit for bit is the set
+ * PHI | U | T | RHO | VEL | JU | JT | PEND_U | PEND_T | SPHI | SF
+ * (the fields a domain carries), read and written back as FP64. */
+
+/* boundary kinds, per axis */
+enum { LBM_BC_PERIODIC = 0, LBM_BC_WALL = 1, LBM_BC_INLET_OUTFLOW = 2 };
+/* population storage formats (collision arithmetic is FP64 for F64, else FP32) */
+enum { LBM_STORE_F64 = 0, LBM_STORE_F32 = 1, LBM_STORE_F16 = 2, LBM_STORE_BF16 = 3 };
+/* phase-change coupling: Eq. (39) at every phase step, or the delayed
+ * variant that sums increments and injects them after the field's next
+ * transport update (the ablation of Section 4.4) */
+enum { LBM_COUPLE_INSTANT = 0, LBM_COUPLE_ACCUM = 1 };
+
+/* Parameters of one domain (host memory, FP64, lattice units).  Field
+ * names follow the paper's notation. */
+typedef struct {
+  int32_t dim;            /* 2 (3D is reserved)                              */
+  int32_t nx, ny, nz;     /* grid size; nz = 1 in 2D                         */
+  int32_t q_scalar;       /* scalar lattice: 5 (D2Q5)                        */
+  int32_t has_U, has_T, has_flow;
+  int32_t N_phi, N_U, N_T, N_F;         /* update factors (Eq. 34), >= 1     */
+  double dt_base;                       /* baseline step (Eq. 34)            */
+  double W0, tau0, eps_s, lam, Mc, k, theta_c;   /* Eq. (1)-(5); theta_c:
+                                           crystal orientation [rad]        */
+  double D_L, D_S, C_inf;               /* Eq. (5), (7)                      */
+  double kappa_S, kappa_L, rhoCp_S, rhoCp_L;     /* Eq. (11)                 */
+  double rho_L, L_h, T_m, m_L, Cp_L;    /* Eq. (5), (12)                     */
+  double nu, s_e, s_eps, s_q, u_in;     /* Eq. (27)-(32)                     */
+  double Fb[3];                         /* body force (Eq. 13, 27, 30)       */
+  int32_t bc[3];                        /* scalar boundaries per axis        */
+  int32_t flow_bc[3];                   /* flow boundaries per axis          */
+  double U0, T0;                        /* initial uniform U and T           */
+  int32_t u0_liquid_only;               /* initial u = u_in (1 - phi)/2 x^  */
+  int32_t coupling;                     /* LBM_COUPLE_*                      */
+} lbm_params;
+
+/* Per-domain diagnostics (FP64 reductions on the device). */
+typedef struct {
+  int64_t step;            /* base steps completed                           */
+  double solid;            /* sum (1 + phi)/2                                */
+  double M_C;              /* sum C, C = C_inf kfac(phi)[1+(1-k)U]/2 (Eq. 5) */
+  double enthalpy;         /* sum (T - rho_L L_h phi / (2 rhoCp_L))          */
+  double mass;             /* sum rho                                        */
+  double S_phi;            /* max |dU_pc| of the last phase step (Sec. 4.4)  */
+  double J_U;              /* max |U_post - U_pre| of the last injection     */
+  double tip[16];          /* tip distances: 4 axes for each of <= 4 seeds   */
+  int64_t nonfinite;       /* count of non-finite phi/U/T/rho values         */
+} lbm_diag;
+
+/* Device bytes a context needs for these domains (states, double buffers,
+ * descriptors, tile lists, reduction partials).  0 on invalid input. */
+size_t lbm_workspace_bytes(const lbm_params* p, int32_t n_domains, int32_t storage);
+
+/* Create a context for n_domains domains that are stepped together.
+ *   p            host array of n_domains parameter sets (copied)
+ *   storage      LBM_STORE_* population storage (one for all domains)
+ *   device       HIP device ordinal
+ *   hip_stream   hipStream_t to issue work on (NULL = default stream)
+ *   workspace    device buffer of >= lbm_workspace_bytes() bytes, owned by
+ *                the caller and kept alive until lbm_destroy; NULL makes the
+ *                library allocate (and later free) it
+ * Errors: LBM_EINVAL (a relaxation time <= 1/2 at phi = +-1, N_chi < 1,
+ * unsupported lattice, sizes), LBM_ENOMEM, LBM_EDEVICE.  On error *out is
+ * NULL.  The state is left uninitialised until lbm_init_seeds. */
+lbm_status lbm_create(const lbm_params* p, int32_t n_domains, int32_t storage,
+                      int32_t device, void* hip_stream, void* workspace,
+                      size_t workspace_bytes, lbm_ctx** out);
+
+/* Initialise one domain: phi = max over seeds of tanh[(R_s - r)/(sqrt2 W0)]
+ * (Section 4.1), U = U0, T = T0, rho = 1, u = 0 or u_in (1 - phi)/2 along x,
+ * every population at equilibrium with v_n = 0.  Resets the step counter.
+ *   centres  host, n_seeds * dim doubles (x, y[, z]) in lattice units
+ *   radii    host, n_seeds doubles
+ * Seeds (<= 4 per domain) are also the origins of the tip diagnostics. */
+lbm_status lbm_init_seeds(lbm_ctx* ctx, int32_t domain, int32_t n_seeds,
+                          const double* centres, const double* radii);
+
+/* Advance every domain by n_base_steps base steps of Eq. (34): at base
+ * step k a field runs iff k mod N_chi == 0, in the order phase (+ the
+ * transfer of Eq. 36-39), U, T, flow.  Whole multirate cycles are replayed
+ * from a captured HIP graph.  If diag_out is non-NULL, diagnostics of every
+ * domain are reduced after the last step and written to diag_out[0..n-1]
+ * (this synchronises); LBM_EUNSTABLE is returned if any value is non-finite. */
+lbm_status lbm_step_multirate(lbm_ctx* ctx, int64_t n_base_steps, lbm_diag* diag_out);
+
+/* Copy the planes selected by mask of one domain into dst (caller-owned,
+ * device memory if dst_is_device else host memory), as FP64 if dst_fp64
+ * else FP32, packed in mask-bit order.  Populations are reconstructed from
+ * the stored representation.  Synchronises when dst is host memory. */
+lbm_status lbm_read_fields(lbm_ctx* ctx, int32_t domain, uint32_t mask,
+                           int32_t dst_is_device, int32_t dst_fp64, void* dst);
+
+/* Overwrite the planes selected by mask of one domain from src (same
+ * packing as lbm_read_fields, FP64).  Used for checkpoint restore and to
+ * inject faults in tests.  Populations are given in full and re-encoded
+ * into the stored representation; LBM_F_POP_PHI requires LBM_F_PHI to be
+ * absent (phi is the sum of the populations). */
+lbm_status lbm_write_fields(lbm_ctx* ctx, int32_t domain, uint32_t mask,
+                            int32_t src_is_device, const void* src);
+
+/* Tuning: rows per tile of the stencil kernels (8, 16 or 32; 0 = autotune)
+ * and whether whole cycles are replayed from a HIP graph. */
+lbm_status lbm_configure(lbm_ctx* ctx, int32_t tile_rows, int32_t use_graph);
+
+/* Base steps completed since the last lbm_init_seeds. */
+int64_t lbm_steps_done(const lbm_ctx* ctx);
+
+/* Text of the last error of ctx (or of the last failed lbm_create when ctx
+ * is NULL).  Owned by the library. */
+const char* lbm_last_error(const lbm_ctx* ctx);
+
+/* Release the context and, if the library allocated it, the workspace. */
+void lbm_destroy(lbm_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBM_H */

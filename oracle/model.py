@@ -18,7 +18,10 @@ notes of the HIP library):
   * grad(phi) for n, a_s and N (and for grad(phi*) in the transport sources)
     is the isotropic finite difference; Eq. (40) is used for grad U and
     grad T only;
-  * if |grad phi|^2 < 1e-24 then n = 0, a_s = 1 and N = 0;
+  * if |grad phi|^2 < 1e-16 (|grad phi| < 1e-8, far below interface
+    gradients of order 1/W0) then n = 0, a_s = 1 and N = 0: below that
+    level the direction of the gradient is not resolved in FP64 at a seed
+    centre, yet it would steer the anti-trapping current there;
   * U*, theta* are the values before this phase step's injection; n and
     the denominators of Eq. (38) are taken at phi^{q+1};
   * base steps are k = 1..K, field chi runs iff k mod N_chi == 0, in the
@@ -43,7 +46,7 @@ from . import params as P
 from .lattice import flow_lattice, scalar_lattice
 from .stencils import div_iso, grad_iso, pull, source_outside, upstream  # noqa: F401
 
-GRAD_EPS2 = 1.0e-24
+GRAD_EPS2 = 1.0e-16
 
 
 def _mv(M: np.ndarray, f: np.ndarray) -> np.ndarray:

@@ -1,0 +1,84 @@
+// Device-side data model shared by the kernels and the host runtime of the
+// multirate lattice-Boltzmann library (gfx950).  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace lbm {
+
+constexpr int TX = 64;        // tile width: one wavefront across x
+constexpr int BY = 4;         // thread rows per block (256 threads)
+constexpr int NTHR = TX * BY;
+constexpr int MAX_SEEDS = 4;
+// |grad phi|^2 below which the interface normal is taken as zero (a_s = 1,
+// N = 0, no anti-trapping current): gradients of 1e-8 and less are far below
+// the interface scale and their direction is not resolved in FP64.
+constexpr double GRAD_EPS2 = 1e-16;
+
+enum Bc { BC_PER = 0, BC_WALL = 1, BC_INOUT = 2 };
+
+// Per-domain device descriptor.  Pointers address planes of px*ny elements
+// (pitch px, x fastest).  R = FP64 when the context stores FP64, else FP32;
+// S = the population storage type.
+struct Dom {
+  int nx, ny, px, pad0;
+  long long plane;              // elements per plane
+  int bc[2];                    // scalar boundaries (x, y)
+  int fbc[2];                   // flow boundaries (x, y)
+  int N_phi, N_U, N_T, N_F;
+  int has_U, has_T, has_F, accum;
+  int T_var;                    // thermal properties vary with phi
+  int tile0;                    // first tile slot of this domain (partials)
+  int ntiles;                   // tiles of this domain
+  int nseeds;
+  double seed[MAX_SEEDS][3];    // x, y, R
+  double dt_base, W0, tau0, eps, lam, Mc, kc, cth, sth;
+  double D_L, D_S, C_inf;
+  double kS, kL, rcS, rcL, rho_L, L_h, T_m, m_L, Cp_L;
+  double nu, s_e, s_eps, s_q, u_in, Fx, Fy;
+  double U0, T0;
+  int u0_liquid;
+  int pad1;
+  // state
+  void* phi[2];    // R, 1 plane
+  void* sphi[2];   // S, 4 planes: f_i - w_i phi, i = 1..4 (D2Q5)
+  void* U[2];      // R
+  void* jU[2];     // S, 2 planes: first moment of the U populations
+  void* PU;        // R, pending U increments (accumulated coupling)
+  void* T[2];      // R
+  void* jT[2];     // S, 2 planes
+  void* PT;        // R
+  void* rho[2];    // R
+  void* sF[2];     // S, 8 planes: f_i - w_i rho, i = 1..8 (D2Q9)
+  void* vel[2];    // R, 2 planes each (u_x, u_y)
+};
+
+// Per-tile partial reductions written by the kernels (FP64).
+struct Partial {
+  double solid, M_C, enthalpy, mass;
+  double S_phi, J_U;            // max |dU_pc| (transfer), max |injected U|
+  double nonfinite;
+  double pad;
+};
+
+struct DiagOut {
+  double solid, M_C, enthalpy, mass, S_phi, J_U;
+  double tip[16];
+  long long nonfinite;
+  long long pad;
+};
+
+// Buffer index holding a field's latest values after `n` writes.
+__host__ __device__ inline int par(long long n) { return (int)(n & 1); }
+
+// Writes of each double-buffered plane after completing base step k.
+__host__ __device__ inline long long n_phi(const Dom& d, long long k) { return k / d.N_phi; }
+__host__ __device__ inline long long n_U(const Dom& d, long long k) {
+  return (d.accum ? 0 : k / d.N_phi) + k / d.N_U;
+}
+__host__ __device__ inline long long n_jU(const Dom& d, long long k) { return k / d.N_U; }
+__host__ __device__ inline long long n_T(const Dom& d, long long k) { return k / d.N_T; }
+__host__ __device__ inline long long n_F(const Dom& d, long long k) { return k / d.N_F; }
+
+}  // namespace lbm

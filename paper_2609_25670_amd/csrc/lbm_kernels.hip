@@ -1,0 +1,1161 @@
+// HIP kernels of the multirate MRT lattice-Boltzmann hot path (gfx950).
+//
+// Every kernel processes one 64 x TY tile per block (256 threads = four
+// wavefronts, one wavefront per row across x), so every global access to a
+// plane is a coalesced 256-byte (FP32) row segment.  The stencil kernels
+// stage the tile plus its halo in LDS: macroscopic planes two rings deep for
+// the isotropic gradient, and post-collision values one ring deep so that the
+// pull streaming reads its neighbours from LDS.  Halo collisions are
+// recomputed (about 2 (TX + TY) / (TX TY) extra work) instead of being written
+// to and re-read from HBM.
+//
+// State representation (see lbm_dev.h):
+//   phase:  phi in a compute-precision plane, plus s_i = f_i - w_i phi for
+//           i = 1..4 in the storage type (the rest population is
+//           w_0 phi - sum s_i, so sum_i f_i = phi exactly);
+//   U, T:   the zeroth moment chi in a compute-precision plane and the first
+//           moment j in the storage type.  With the relaxation of Eq. (23)
+//           only these moments enter the collision, so the post-collision
+//           populations are w_i (chi + dt Q) + e_i . [j_eq + (1 - s)(j - j_eq)] / 2
+//           (D2Q5) and the state after streaming is again (chi, j);
+//   flow:   rho plus s_i = f_i - w_i rho for i = 1..8 (D2Q9), and u.
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include "lbm_dev.h"
+
+namespace lbm {
+
+// ------------------------------------------------------------------ storage
+__device__ __forceinline__ double ld(const double* p, long long i) { return p[i]; }
+__device__ __forceinline__ float ld(const float* p, long long i) { return p[i]; }
+__device__ __forceinline__ float ld(const __half* p, long long i) { return __half2float(p[i]); }
+__device__ __forceinline__ float ld(const __hip_bfloat16* p, long long i) { return __bfloat162float(p[i]); }
+
+__device__ __forceinline__ void st(double* p, long long i, double v) { p[i] = v; }
+__device__ __forceinline__ void st(float* p, long long i, float v) { p[i] = v; }
+__device__ __forceinline__ void st(__half* p, long long i, float v) { p[i] = __float2half(v); }
+__device__ __forceinline__ void st(__hip_bfloat16* p, long long i, float v) { p[i] = __float2bfloat16(v); }
+
+// Ghost index for stencils: wrap on periodic axes, clamp (even mirror about
+// the half-way wall) otherwise.
+__device__ __forceinline__ int ghost(int g, int n, int bc) {
+  if (g >= 0 && g < n) return g;
+  if (bc == BC_PER) {
+    g %= n;
+    return g < 0 ? g + n : g;
+  }
+  return g < 0 ? 0 : n - 1;
+}
+
+// Site a raw coordinate refers to: wrapped on periodic axes, -1 beyond a wall.
+__device__ __forceinline__ int resolve(int g, int n, int bc) {
+  if (g >= 0 && g < n) return g;
+  if (bc == BC_PER) {
+    g %= n;
+    return g < 0 ? g + n : g;
+  }
+  return -1;
+}
+
+template <class R>
+__device__ __forceinline__ void iso_grad(const R* b, int stride, R& gx, R& gy) {
+  // isotropic gradient with D2Q9 weights, b points at the centre
+  const R E = b[1], W = b[-1], N = b[stride], S = b[-stride];
+  const R NE = b[stride + 1], NW = b[stride - 1], SE = b[-stride + 1], SW = b[-stride - 1];
+  gx = (E - W) * R(1.0 / 3.0) + (NE - NW - SW + SE) * R(1.0 / 12.0);
+  gy = (N - S) * R(1.0 / 3.0) + (NE + NW - SW - SE) * R(1.0 / 12.0);
+}
+
+// D2Q5: e_1 = +x, e_2 = +y, e_3 = -x, e_4 = -y.
+__constant__ int EX5[5] = {0, 1, 0, -1, 0};
+__constant__ int EY5[5] = {0, 0, 1, 0, -1};
+
+// =================================================================== phase
+// Collision of Eq. (14) with the equilibrium of Eq. (21), the relaxation of
+// Eq. (23), tau_phi of Eq. (24) and the source dt w_i Q_phi / tau0, then the
+// anisotropic streaming of Eq. (26) in pull form with a_s^2 at the
+// destination.  The result per site of the collision is (P, K):
+// f_i^+ = w_i P + e_i . K / 2 with P = phi + dt Q / tau0 and
+// K = j_eq + (1 - 1/tau)(j - j_eq), j_eq = v_n dt.
+template <class R>
+struct PhaseConst {
+  R dt, W2t, inv_tau0, eps, lam, Mc, cth, sth, inv_lhcp, theta_off, Wt;
+};
+
+template <class R>
+__device__ __forceinline__ void phase_collide(const PhaseConst<R>& c, R phi, R gx, R gy, R jx, R jy,
+                                              R Us, R Ts, R& P, R& Kx, R& Ky, R& A) {
+  const R gg = gx * gx + gy * gy;
+  R a_s = R(1), Nx = R(0), Ny = R(0);
+  if (gg >= R(GRAD_EPS2)) {
+    const R g = sqrt(gg);
+    const R ig = R(1) / g;
+    const R nx = -gx * ig, ny = -gy * ig;
+    const R ax = c.cth * nx + c.sth * ny;
+    const R ay = -c.sth * nx + c.cth * ny;
+    const R ax2 = ax * ax, ay2 = ay * ay;
+    const R s4 = ax2 * ax2 + ay2 * ay2;
+    a_s = R(1) - R(3) * c.eps + R(4) * c.eps * s4;
+    const R f = R(-16) * c.eps * a_s * g;
+    const R nxc = f * ax * (ax2 - s4);
+    const R nyc = f * ay * (ay2 - s4);
+    Nx = c.cth * nxc - c.sth * nyc;
+    Ny = c.sth * nxc + c.cth * nyc;
+  }
+  A = a_s * a_s;
+  const R tau = R(3) * c.dt * A * c.W2t + R(0.5);
+  const R om = R(1) - R(1) / tau;
+  // v_n = -W0^2 N / tau0 ; j_eq = v_n dt
+  const R jex = -c.W2t * Nx * c.dt;
+  const R jey = -c.W2t * Ny * c.dt;
+  const R theta = (Ts - c.theta_off) * c.inv_lhcp;
+  const R q = R(1) - phi * phi;
+  const R Q = phi * q - c.lam * (c.Mc * Us + theta) * q * q;
+  P = phi + c.dt * Q * c.inv_tau0;
+  Kx = jex + om * (jx - jex);
+  Ky = jey + om * (jy - jey);
+}
+
+template <class R, class S, int TY>
+__global__ __launch_bounds__(NTHR) void k_phase(const Dom* __restrict__ doms, const int4* __restrict__ tiles,
+                                                 long long k) {
+  constexpr int RPT = TY / BY;
+  constexpr int BW = TX + 4, BH = TY + 4;
+  constexpr int CW = TX + 2, CH = TY + 2;
+  __shared__ R sphi[BH * BW];
+  __shared__ R sP[CH * CW], sKx[CH * CW], sKy[CH * CW];
+
+  const int4 t = tiles[blockIdx.x];
+  if (t.x < 0) return;
+  const Dom& D = doms[t.x];
+  if (k % D.N_phi) return;
+  const int nx = D.nx, ny = D.ny;
+  const long long px = D.px, pl = D.plane;
+  const int x0 = t.y, y0 = t.z;
+  const int bcx = D.bc[0], bcy = D.bc[1];
+  const int ib = par(n_phi(D, k - 1)), ob = ib ^ 1;
+  const R* __restrict__ phi_in = (const R*)D.phi[ib];
+  R* __restrict__ phi_out = (R*)D.phi[ob];
+  const S* __restrict__ s_in = (const S*)D.sphi[ib];
+  S* __restrict__ s_out = (S*)D.sphi[ob];
+  // latest U and T (before this step's transfer)
+  const long long nU = (D.accum ? 0 : (k - 1) / D.N_phi) + (k - 1) / D.N_U;
+  const R* __restrict__ Up = D.has_U ? (const R*)D.U[par(nU)] : nullptr;
+  const R* __restrict__ Tp = D.has_T ? (const R*)D.T[par(n_T(D, k - 1))] : nullptr;
+
+  PhaseConst<R> c;
+  c.dt = R(D.N_phi * D.dt_base);
+  c.W2t = R(D.W0 * D.W0 / D.tau0);
+  c.inv_tau0 = R(1.0 / D.tau0);
+  c.eps = R(D.eps);
+  c.lam = R(D.lam);
+  c.Mc = R(D.Mc);
+  c.cth = R(D.cth);
+  c.sth = R(D.sth);
+  c.inv_lhcp = R(D.Cp_L / D.L_h);
+  c.theta_off = R(D.T_m + D.m_L * D.C_inf);
+
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
+  // phi on the tile plus two rings (ghost values wrapped or mirrored)
+  for (int i = tid; i < BW * BH; i += NTHR) {
+    const int lx = i % BW, ly = i / BW;
+    const int gx = ghost(x0 - 2 + lx, nx, bcx), gy = ghost(y0 - 2 + ly, ny, bcy);
+    sphi[i] = phi_in[gy * px + gx];
+  }
+  __syncthreads();
+
+  // owned sites: collide, keep pre-collision populations in registers
+  R f[RPT][5];
+  R Aown[RPT];
+  bool own[RPT];
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    const int ly = ty + r * BY, gx = x0 + tx, gy = y0 + ly;
+    own[r] = gx < nx && gy < ny;
+    if (!own[r]) continue;
+    const long long o = gy * px + gx;
+    const R* b = &sphi[(ly + 2) * BW + tx + 2];
+    const R phi = b[0];
+    const R s1 = ld(s_in, o), s2 = ld(s_in, o + pl), s3 = ld(s_in, o + 2 * pl), s4 = ld(s_in, o + 3 * pl);
+    f[r][1] = phi * R(1.0 / 6.0) + s1;
+    f[r][2] = phi * R(1.0 / 6.0) + s2;
+    f[r][3] = phi * R(1.0 / 6.0) + s3;
+    f[r][4] = phi * R(1.0 / 6.0) + s4;
+    f[r][0] = phi * R(1.0 / 3.0) - (s1 + s2 + s3 + s4);
+    R gx_, gy_;
+    iso_grad(b, BW, gx_, gy_);
+    const R Us = Up ? Up[o] : R(0);
+    const R Ts = Tp ? Tp[o] : c.theta_off;
+    R P, Kx, Ky, A;
+    phase_collide(c, phi, gx_, gy_, s1 - s3, s2 - s4, Us, Ts, P, Kx, Ky, A);
+    const int ci = (ly + 1) * CW + tx + 1;
+    sP[ci] = P;
+    sKx[ci] = Kx;
+    sKy[ci] = Ky;
+    Aown[r] = A;
+  }
+  // halo collisions (ring cells, wrapped across periodic edges)
+  for (int i = tid; i < CW * CH; i += NTHR) {
+    const int lx = i % CW, ly = i / CW;
+    const int rx = x0 - 1 + lx, ry = y0 - 1 + ly;
+    if (lx >= 1 && lx <= TX && ly >= 1 && ly <= TY && rx < nx && ry < ny) continue;
+    const int gx = resolve(rx, nx, bcx), gy = resolve(ry, ny, bcy);
+    if (gx < 0 || gy < 0) continue;
+    const long long o = gy * px + gx;
+    const R* b = &sphi[(ly + 1) * BW + lx + 1];
+    const R phi = b[0];
+    const R s1 = ld(s_in, o), s2 = ld(s_in, o + pl), s3 = ld(s_in, o + 2 * pl), s4 = ld(s_in, o + 3 * pl);
+    R gx_, gy_;
+    iso_grad(b, BW, gx_, gy_);
+    const R Us = Up ? Up[o] : R(0);
+    const R Ts = Tp ? Tp[o] : c.theta_off;
+    R P, Kx, Ky, A;
+    phase_collide(c, phi, gx_, gy_, s1 - s3, s2 - s4, Us, Ts, P, Kx, Ky, A);
+    sP[i] = P;
+    sKx[i] = Kx;
+    sKy[i] = Ky;
+  }
+  __syncthreads();
+
+  // anisotropic pull streaming (Eq. 26) into owned sites
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    if (!own[r]) continue;
+    const int ly = ty + r * BY, gx = x0 + tx, gy = y0 + ly;
+    const int ci = (ly + 1) * CW + tx + 1;
+    const R A = Aown[r], iA = R(1) / A, oA = R(1) - A;
+    const R Po = sP[ci], Kxo = sKx[ci], Kyo = sKy[ci];
+    R fn[5];
+    fn[0] = (Po * R(1.0 / 3.0) - oA * f[r][0]) * iA;
+#pragma unroll
+    for (int q = 1; q < 5; ++q) {
+      const int ex = EX5[q], ey = EY5[q];
+      const int sx = gx - ex, sy = gy - ey;
+      const bool wall = ((sx < 0 || sx >= nx) && bcx != BC_PER) || ((sy < 0 || sy >= ny) && bcy != BC_PER);
+      R post;
+      if (wall) {
+        post = Po * R(1.0 / 6.0) - R(0.5) * (R(ex) * Kxo + R(ey) * Kyo);
+      } else {
+        const int si = ci - ey * CW - ex;
+        post = sP[si] * R(1.0 / 6.0) + R(0.5) * (R(ex) * sKx[si] + R(ey) * sKy[si]);
+      }
+      fn[q] = (post - oA * f[r][q]) * iA;
+    }
+    const R phin = fn[0] + fn[1] + fn[2] + fn[3] + fn[4];
+    const long long o = gy * px + gx;
+    phi_out[o] = phin;
+    const R w = phin * R(1.0 / 6.0);
+    st(s_out, o, fn[1] - w);
+    st(s_out, o + pl, fn[2] - w);
+    st(s_out, o + 2 * pl, fn[3] - w);
+    st(s_out, o + 3 * pl, fn[4] - w);
+  }
+}
+
+// =================================================================== transfer
+// Eq. (36)-(39): dphi = phi^{q+1} - phi^q; J = W0/(2 sqrt2) [1 + (1-k) U*]
+// dphi n^{q+1}; dU = ([1 + (1-k)U*] dphi - 2 div J) / kfac(phi^{q+1});
+// dT = rho_L L_h dphi / (2 rhoCp_eff(phi^{q+1})).  The compact divergence
+// uses the D2Q9-weighted stencil; ghost J across a wall is the mirror image
+// (normal component negated).  Instantaneous coupling adds dU to U (written
+// to the other U buffer because neighbours' U* are read) and dT to T in
+// place; the accumulated variant adds both to the pending planes.  Because
+// the U and T states are stored as (chi, j), adding w_i d to every
+// population is exactly adding d to chi.
+template <class R, int TY>
+__global__ __launch_bounds__(NTHR) void k_transfer(const Dom* __restrict__ doms, const int4* __restrict__ tiles,
+                                                    long long k, Partial* __restrict__ part) {
+  constexpr int RPT = TY / BY;
+  constexpr int BW = TX + 4, BH = TY + 4;
+  constexpr int CW = TX + 2, CH = TY + 2;
+  __shared__ R sphi[BH * BW];
+  __shared__ R sJx[CH * CW], sJy[CH * CW];
+  __shared__ R red[NTHR / 64];
+
+  const int4 t = tiles[blockIdx.x];
+  if (t.x < 0) return;
+  const Dom& D = doms[t.x];
+  if (k % D.N_phi) return;
+  const int nx = D.nx, ny = D.ny;
+  const long long px = D.px;
+  const int x0 = t.y, y0 = t.z;
+  const int bcx = D.bc[0], bcy = D.bc[1];
+  const R* __restrict__ phi_old = (const R*)D.phi[par(n_phi(D, k - 1))];
+  const R* __restrict__ phi_new = (const R*)D.phi[par(n_phi(D, k))];
+  const long long nU = (D.accum ? 0 : (k - 1) / D.N_phi) + (k - 1) / D.N_U;
+  const R* __restrict__ Uin = D.has_U ? (const R*)D.U[par(nU)] : nullptr;
+  R* __restrict__ Uout = D.has_U ? (R*)D.U[par(nU + 1)] : nullptr;
+  R* __restrict__ Tcur = D.has_T ? (R*)D.T[par(n_T(D, k - 1))] : nullptr;
+  const R omk = R(1.0 - D.kc), opk = R(1.0 + D.kc);
+  const R cJ = R(D.W0 / (2.0 * 1.4142135623730951));
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
+  R amax = R(0);
+
+  if (D.has_U) {
+    for (int i = tid; i < BW * BH; i += NTHR) {
+      const int lx = i % BW, ly = i / BW;
+      const int gx = ghost(x0 - 2 + lx, nx, bcx), gy = ghost(y0 - 2 + ly, ny, bcy);
+      sphi[i] = phi_new[gy * px + gx];
+    }
+    __syncthreads();
+    for (int i = tid; i < CW * CH; i += NTHR) {
+      const int lx = i % CW, ly = i / CW;
+      int rx = x0 - 1 + lx, ry = y0 - 1 + ly;
+      // a ghost across a wall takes the mirrored value of the wall node
+      bool mx = false, my = false;
+      if (rx < 0 && bcx != BC_PER) { rx = 0; mx = true; }
+      if (rx >= nx && bcx != BC_PER) { rx = nx - 1; mx = true; }
+      if (ry < 0 && bcy != BC_PER) { ry = 0; my = true; }
+      if (ry >= ny && bcy != BC_PER) { ry = ny - 1; my = true; }
+      const int gx = ghost(rx, nx, bcx), gy = ghost(ry, ny, bcy);
+      const long long o = gy * px + gx;
+      const R* b = &sphi[(ry - (y0 - 2)) * BW + rx - (x0 - 2)];
+      R gxv, gyv;
+      iso_grad(b, BW, gxv, gyv);
+      const R gg = gxv * gxv + gyv * gyv;
+      R Jx = R(0), Jy = R(0);
+      if (gg >= R(GRAD_EPS2)) {
+        const R ig = R(1) / sqrt(gg);
+        const R dphi = b[0] - phi_old[o];
+        const R a = cJ * (R(1) + omk * Uin[o]) * dphi * ig;
+        Jx = -a * gxv;
+        Jy = -a * gyv;
+      }
+      sJx[i] = mx ? -Jx : Jx;
+      sJy[i] = my ? -Jy : Jy;
+    }
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    const int ly = ty + r * BY, gx = x0 + tx, gy = y0 + ly;
+    if (gx >= nx || gy >= ny) continue;
+    const long long o = gy * px + gx;
+    const R pn = phi_new[o];
+    const R dphi = pn - phi_old[o];
+    if (D.has_U) {
+      const int ci = (ly + 1) * CW + tx + 1;
+      const R* jx = &sJx[ci];
+      const R* jy = &sJy[ci];
+      const R div = (jx[1] - jx[-1]) * R(1.0 / 3.0) +
+                    (jx[CW + 1] - jx[CW - 1] - jx[-CW - 1] + jx[-CW + 1]) * R(1.0 / 12.0) +
+                    (jy[CW] - jy[-CW]) * R(1.0 / 3.0) +
+                    (jy[CW + 1] + jy[CW - 1] - jy[-CW - 1] - jy[-CW + 1]) * R(1.0 / 12.0);
+      const R Us = Uin[o];
+      const R dU = ((R(1) + omk * Us) * dphi - R(2) * div) / (opk - omk * pn);
+      amax = fmax(amax, fabs(dU));
+      if (D.accum) {
+        R* PU = (R*)D.PU;
+        PU[o] = PU[o] + dU;
+      } else {
+        Uout[o] = Us + dU;
+      }
+    }
+    if (D.has_T) {
+      const R rc = (R(1) + pn) * R(0.5) * R(D.rcS) + (R(1) - pn) * R(0.5) * R(D.rcL);
+      const R dT = R(D.rho_L * D.L_h) * dphi / (R(2) * rc);
+      if (D.accum) {
+        R* PT = (R*)D.PT;
+        PT[o] = PT[o] + dT;
+      } else {
+        Tcur[o] = Tcur[o] + dT;
+      }
+    }
+  }
+  if (part && D.has_U) {
+    // block max of |dU| (wavefront reduction, then across the 4 wavefronts)
+    for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_down(amax, off, 64));
+    if (tx == 0) red[ty] = amax;
+    __syncthreads();
+    if (tid == 0) {
+      R m = red[0];
+      for (int w = 1; w < NTHR / 64; ++w) m = fmax(m, red[w]);
+      part[t.w].S_phi = double(m);
+      if (!D.accum) part[t.w].J_U = double(m);
+    }
+  }
+}
+
+// =================================================================== scalar transport
+// One update of U (FIELD 0) or T (FIELD 1): Eq. (14) with Eq. (19)-(20),
+// (23), (24) and the transport source of Eq. (35) (first terms of Eq. 8 and
+// Eq. 12) with grad chi from Eq. (40) and grad phi* from the isotropic
+// stencil; then the streaming of Eq. (25) with half-way bounce-back and the
+// reconstruction of chi and j.  The accumulated-coupling variant injects the
+// pending increments right after the transport.
+template <class R, class S, int TY, int FIELD>
+__global__ __launch_bounds__(NTHR) void k_scalar(const Dom* __restrict__ doms, const int4* __restrict__ tiles,
+                                                  long long k, Partial* __restrict__ part) {
+  constexpr int RPT = TY / BY;
+  constexpr int BW = TX + 4, BH = TY + 4;
+  constexpr int CW = TX + 2, CH = TY + 2;
+  __shared__ R sphi[BH * BW];
+  __shared__ R sP[CH * CW], sKx[CH * CW], sKy[CH * CW];
+  __shared__ R red[NTHR / 64];
+
+  const int4 t = tiles[blockIdx.x];
+  if (t.x < 0) return;
+  const Dom& D = doms[t.x];
+  const int N = FIELD == 0 ? D.N_U : D.N_T;
+  if (k % N) return;
+  const int nx = D.nx, ny = D.ny;
+  const long long px = D.px, pl = D.plane;
+  const int x0 = t.y, y0 = t.z;
+  const int bcx = D.bc[0], bcy = D.bc[1];
+  const R* __restrict__ cin;
+  R* __restrict__ cout;
+  const S* __restrict__ jin;
+  S* __restrict__ jout;
+  R* __restrict__ pend;
+  if (FIELD == 0) {
+    const long long nU = (D.accum ? 0 : k / D.N_phi) + (k - 1) / D.N_U;
+    cin = (const R*)D.U[par(nU)];
+    cout = (R*)D.U[par(nU + 1)];
+    jin = (const S*)D.jU[par(n_jU(D, k - 1))];
+    jout = (S*)D.jU[par(n_jU(D, k))];
+    pend = (R*)D.PU;
+  } else {
+    cin = (const R*)D.T[par(n_T(D, k - 1))];
+    cout = (R*)D.T[par(n_T(D, k))];
+    jin = (const S*)D.jT[par(n_T(D, k - 1))];
+    jout = (S*)D.jT[par(n_T(D, k))];
+    pend = (R*)D.PT;
+  }
+  const R* __restrict__ phis = (const R*)D.phi[par(n_phi(D, k))];
+  // velocity of the latest flow update (the flow of step k runs after U, T)
+  const R* __restrict__ vel = D.has_F ? (const R*)D.vel[par(n_F(D, k - 1))] : nullptr;
+  const bool need_phi = FIELD == 0 || D.T_var;
+  const R dt = R(N * D.dt_base);
+  const R omk = R(1.0 - D.kc), opk = R(1.0 + D.kc);
+  const R DS = R(D.D_S), DL = R(D.D_L);
+  const R kS = R(D.kS), kL = R(D.kL), rcS = R(D.rcS), rcL = R(D.rcL);
+
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
+  if (need_phi) {
+    for (int i = tid; i < BW * BH; i += NTHR) {
+      const int lx = i % BW, ly = i / BW;
+      const int gx = ghost(x0 - 2 + lx, nx, bcx), gy = ghost(y0 - 2 + ly, ny, bcy);
+      sphi[i] = phis[gy * px + gx];
+    }
+    __syncthreads();
+  }
+
+  // collision of one site whose phi stencil centre is b (LDS) or whose phi is
+  // read directly when the thermal properties are constant
+  auto collide = [&](long long o, const R* b, R& P, R& Kx, R& Ky) {
+    const R chi = cin[o];
+    const R jx = ld(jin, o), jy = ld(jin, o + pl);
+    R ux = R(0), uy = R(0);
+    if (vel) {
+      ux = vel[o];
+      uy = vel[o + pl];
+    }
+    R coeff, Q = R(0);
+    const R jex = chi * ux * dt, jey = chi * uy * dt;
+    if (FIELD == 0) {
+      const R phi = b[0];
+      const R kf = opk - omk * phi;
+      coeff = ((R(1) + phi) * DS + (R(1) - phi) * DL) / kf;                    // Eq. (7)
+      const R tau = R(3) * dt * coeff + R(0.5);
+      const R gcx = -R(3) / tau * (jx - jex), gcy = -R(3) / tau * (jy - jey);  // Eq. (40)
+      R gpx, gpy;
+      iso_grad(b, BW, gpx, gpy);
+      Q = -omk * coeff * (gcx * gpx + gcy * gpy) / kf;                          // Eq. (8), 1st term
+      const R om = R(1) - R(1) / tau;
+      P = chi + dt * Q;
+      Kx = jex + om * (jx - jex);
+      Ky = jey + om * (jy - jey);
+    } else {
+      R tau;
+      if (D.T_var) {
+        const R phi = b[0];
+        const R rc = (R(1) + phi) * R(0.5) * rcS + (R(1) - phi) * R(0.5) * rcL;
+        coeff = ((R(1) + phi) * R(0.5) * kS + (R(1) - phi) * R(0.5) * kL) / rc;   // Eq. (11)
+        tau = R(3) * dt * coeff + R(0.5);
+        const R gcx = -R(3) / tau * (jx - jex), gcy = -R(3) / tau * (jy - jey);
+        R gpx, gpy;
+        iso_grad(b, BW, gpx, gpy);
+        Q = (rcS - rcL) / (R(2) * rc) * coeff * (gcx * gpx + gcy * gpy);         // Eq. (12), 1st term
+      } else {
+        coeff = kL / rcL;
+        tau = R(3) * dt * coeff + R(0.5);
+      }
+      const R om = R(1) - R(1) / tau;
+      P = chi + dt * Q;
+      Kx = jex + om * (jx - jex);
+      Ky = jey + om * (jy - jey);
+    }
+  };
+
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    const int ly = ty + r * BY, gx = x0 + tx, gy = y0 + ly;
+    if (gx >= nx || gy >= ny) continue;
+    R P, Kx, Ky;
+    collide(gy * px + gx, &sphi[(ly + 2) * BW + tx + 2], P, Kx, Ky);
+    const int ci = (ly + 1) * CW + tx + 1;
+    sP[ci] = P;
+    sKx[ci] = Kx;
+    sKy[ci] = Ky;
+  }
+  for (int i = tid; i < CW * CH; i += NTHR) {
+    const int lx = i % CW, ly = i / CW;
+    const int rx = x0 - 1 + lx, ry = y0 - 1 + ly;
+    if (lx >= 1 && lx <= TX && ly >= 1 && ly <= TY && rx < nx && ry < ny) continue;
+    const int gx = resolve(rx, nx, bcx), gy = resolve(ry, ny, bcy);
+    if (gx < 0 || gy < 0) continue;
+    R P, Kx, Ky;
+    collide(gy * px + gx, &sphi[(ly + 1) * BW + lx + 1], P, Kx, Ky);
+    sP[i] = P;
+    sKx[i] = Kx;
+    sKy[i] = Ky;
+  }
+  __syncthreads();
+
+  R amax = R(0);
+#pragma unroll
+  for (int r = 0; r < RPT; ++r) {
+    const int ly = ty + r * BY, gx = x0 + tx, gy = y0 + ly;
+    if (gx >= nx || gy >= ny) continue;
+    const int ci = (ly + 1) * CW + tx + 1;
+    const R Po = sP[ci], Kxo = sKx[ci], Kyo = sKy[ci];
+    R fq[5];
+    fq[0] = Po * R(1.0 / 3.0);
+#pragma unroll
+    for (int q = 1; q < 5; ++q) {
+      const int ex = EX5[q], ey = EY5[q];
+      const int sx = gx - ex, sy = gy - ey;
+      const bool wall = ((sx < 0 || sx >= nx) && bcx != BC_PER) || ((sy < 0 || sy >= ny) && bcy != BC_PER);
+      if (wall) {
+        fq[q] = Po * R(1.0 / 6.0) - R(0.5) * (R(ex) * Kxo + R(ey) * Kyo);
+      } else {
+        const int si = ci - ey * CW - ex;
+        fq[q] = sP[si] * R(1.0 / 6.0) + R(0.5) * (R(ex) * sKx[si] + R(ey) * sKy[si]);
+      }
+    }
+    const long long o = gy * px + gx;
+    R chi = fq[0] + fq[1] + fq[2] + fq[3] + fq[4];
+    if (D.accum) {
+      const R p = pend[o];
+      chi += p;
+      pend[o] = R(0);
+      amax = fmax(amax, fabs(p));
+    }
+    cout[o] = chi;
+    st(jout, o, fq[1] - fq[3]);
+    st(jout, o + pl, fq[2] - fq[4]);
+  }
+  if (FIELD == 0 && D.accum && part) {
+    for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_down(amax, off, 64));
+    if (tx == 0) red[ty] = amax;
+    __syncthreads();
+    if (tid == 0) {
+      R m = red[0];
+      for (int w = 1; w < NTHR / 64; ++w) m = fmax(m, red[w]);
+      part[t.w].J_U = double(m);
+    }
+  }
+}
+
+// =================================================================== flow
+// D2Q9 MRT (Eq. 27-32) with Guo forcing (Eq. 30), then the weighted partial
+// bounce-back of Eq. (33) in pull form with f_L = (1 - phi*)/2, inlet
+// equilibrium at x = 0 and zero-gradient outflow at x = nx - 1 when the x
+// boundary is inlet/outflow.
+__constant__ int EX9[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
+__constant__ int EY9[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
+__constant__ int OPP9[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+
+template <class R>
+__device__ __forceinline__ void flow_eq(R rho, R ux, R uy, R dt, R* feq) {
+  // Eq. (28) with u / c = u dt
+  const R u2 = (ux * ux + uy * uy) * dt * dt;
+  const R w[9] = {R(4.0 / 9), R(1.0 / 9), R(1.0 / 9), R(1.0 / 9), R(1.0 / 9),
+                  R(1.0 / 36), R(1.0 / 36), R(1.0 / 36), R(1.0 / 36)};
+#pragma unroll
+  for (int i = 0; i < 9; ++i) {
+    const R eu = (R(EX9[i]) * ux + R(EY9[i]) * uy) * dt;
+    feq[i] = w[i] * rho * (R(1) + R(3) * eu + R(4.5) * eu * eu - R(1.5) * u2);
+  }
+}
+
+template <class R>
+__device__ __forceinline__ void flow_collide(const R* f, R dt, R Fx, R Fy, R s_e, R s_eps, R s_q, R s_nu,
+                                            R* post) {
+  // moments m = M f with the rows of Eq. (16)
+  const R rho = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+  const R c = R(1) / dt;
+  const R jx = f[1] - f[3] + f[5] - f[6] - f[7] + f[8];
+  const R jy = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
+  const R ux = (c * jx + dt * Fx * R(0.5)) / rho;
+  const R uy = (c * jy + dt * Fy * R(0.5)) / rho;
+  R m[9];
+  m[0] = rho;
+  m[1] = -R(4) * f[0] - f[1] - f[2] - f[3] - f[4] + R(2) * (f[5] + f[6] + f[7] + f[8]);
+  m[2] = R(4) * f[0] - R(2) * (f[1] + f[2] + f[3] + f[4]) + f[5] + f[6] + f[7] + f[8];
+  m[3] = jx;
+  m[4] = -R(2) * f[1] + R(2) * f[3] + f[5] - f[6] - f[7] + f[8];
+  m[5] = jy;
+  m[6] = -R(2) * f[2] + R(2) * f[4] + f[5] + f[6] - f[7] - f[8];
+  m[7] = f[1] - f[2] + f[3] - f[4];
+  m[8] = f[5] - f[6] + f[7] - f[8];
+  // equilibrium moments (Eq. 29) and Guo forcing (Eq. 30) with 1/c = dt
+  const R Ux = ux * dt, Uy = uy * dt, U2 = Ux * Ux + Uy * Uy;
+  R meq[9] = {rho, rho * (R(-2) + R(3) * U2), rho * (R(1) - R(3) * U2), rho * Ux, -rho * Ux,
+              rho * Uy, -rho * Uy, rho * (Ux * Ux - Uy * Uy), rho * Ux * Uy};
+  const R Fu = (Fx * ux + Fy * uy) * dt * dt;
+  R G[9] = {R(0), R(6) * Fu, -R(6) * Fu, Fx * dt, -Fx * dt, Fy * dt, -Fy * dt,
+            R(2) * (Fx * ux - Fy * uy) * dt * dt, (Fy * ux + Fx * uy) * dt * dt};
+  const R s[9] = {R(0), s_e, s_eps, R(0), s_q, R(0), s_q, s_nu, s_nu};
+  R mp[9];
+#pragma unroll
+  for (int i = 0; i < 9; ++i) mp[i] = m[i] - s[i] * (m[i] - meq[i]) + (R(1) - R(0.5) * s[i]) * G[i];
+  // f = M^-1 m^+ with M^-1 = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4)
+  const R a0 = mp[0] * R(1.0 / 9), a1 = mp[1] * R(1.0 / 36), a2 = mp[2] * R(1.0 / 36);
+  const R a3 = mp[3] * R(1.0 / 6), a4 = mp[4] * R(1.0 / 12), a5 = mp[5] * R(1.0 / 6), a6 = mp[6] * R(1.0 / 12);
+  const R a7 = mp[7] * R(0.25), a8 = mp[8] * R(0.25);
+  post[0] = a0 - R(4) * a1 + R(4) * a2;
+  post[1] = a0 - a1 - R(2) * a2 + a3 - R(2) * a4 + a7;
+  post[2] = a0 - a1 - R(2) * a2 + a5 - R(2) * a6 - a7;
+  post[3] = a0 - a1 - R(2) * a2 - a3 + R(2) * a4 + a7;
+  post[4] = a0 - a1 - R(2) * a2 - a5 + R(2) * a6 - a7;
+  post[5] = a0 + R(2) * a1 + a2 + a3 + a4 + a5 + a6 + a8;
+  post[6] = a0 + R(2) * a1 + a2 - a3 - a4 + a5 + a6 - a8;
+  post[7] = a0 + R(2) * a1 + a2 - a3 - a4 - a5 - a6 + a8;
+  post[8] = a0 + R(2) * a1 + a2 + a3 + a4 - a5 - a6 - a8;
+}
+
+// The nine post-collision planes of a tile live in LDS, so a TY-row tile is
+// processed in sub-tiles of SUB rows (8 in FP64, 16 in FP32) that reuse it.
+template <class R, class S, int TY, int SUB>
+__global__ __launch_bounds__(NTHR) void k_flow(const Dom* __restrict__ doms, const int4* __restrict__ tiles,
+                                                long long k) {
+  constexpr int RPT = SUB / BY;
+  constexpr int CW = TX + 2, CH = SUB + 2;
+  static_assert(TY % SUB == 0, "tile height must be a multiple of the sub-tile height");
+  __shared__ R sfl[CH * CW];
+  __shared__ R spost[9][CH * CW];
+
+  const int4 t = tiles[blockIdx.x];
+  if (t.x < 0) return;
+  const Dom& D = doms[t.x];
+  if (k % D.N_F) return;
+  const int nx = D.nx, ny = D.ny;
+  const long long px = D.px, pl = D.plane;
+  const int fbx = D.fbc[0], fby = D.fbc[1];
+  const R* __restrict__ rho_in = (const R*)D.rho[par(n_F(D, k - 1))];
+  R* __restrict__ rho_out = (R*)D.rho[par(n_F(D, k))];
+  const S* __restrict__ s_in = (const S*)D.sF[par(n_F(D, k - 1))];
+  S* __restrict__ s_out = (S*)D.sF[par(n_F(D, k))];
+  R* __restrict__ vel = (R*)D.vel[par(n_F(D, k))];
+  const R* __restrict__ phis = (const R*)D.phi[par(n_phi(D, k))];
+  const R dt = R(D.N_F * D.dt_base);
+  const R Fx = R(D.Fx), Fy = R(D.Fy);
+  const R snu = R(1.0 / (3.0 * D.N_F * D.dt_base * D.nu + 0.5));
+  const R se = R(D.s_e), seps = R(D.s_eps), sq = R(D.s_q);
+  const R w[9] = {R(4.0 / 9), R(1.0 / 9), R(1.0 / 9), R(1.0 / 9), R(1.0 / 9),
+                  R(1.0 / 36), R(1.0 / 36), R(1.0 / 36), R(1.0 / 36)};
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
+  const int x0 = t.y;
+  const R c = R(1) / dt;
+
+  for (int y0 = t.z; y0 < t.z + TY && y0 < ny; y0 += SUB) {
+    for (int i = tid; i < CW * CH; i += NTHR) {
+      const int lx = i % CW, ly = i / CW;
+      const int rx = x0 - 1 + lx, ry = y0 - 1 + ly;
+      const int gxg = ghost(rx, nx, fbx == BC_PER ? BC_PER : BC_WALL);
+      const int gyg = ghost(ry, ny, fby == BC_PER ? BC_PER : BC_WALL);
+      sfl[i] = (R(1) - phis[gyg * px + gxg]) * R(0.5);
+      const int gx = resolve(rx, nx, fbx == BC_PER ? BC_PER : BC_WALL);
+      const int gy = resolve(ry, ny, fby == BC_PER ? BC_PER : BC_WALL);
+      if (gx < 0 || gy < 0) continue;
+      const long long o = gy * px + gx;
+      const R rho = rho_in[o];
+      R f[9];
+      R ssum = R(0);
+#pragma unroll
+      for (int q = 1; q < 9; ++q) {
+        const R sv = ld(s_in, o + (q - 1) * pl);
+        f[q] = w[q] * rho + sv;
+        ssum += sv;
+      }
+      f[0] = w[0] * rho - ssum;
+      R post[9];
+      flow_collide(f, dt, Fx, Fy, se, seps, sq, snu, post);
+#pragma unroll
+      for (int q = 0; q < 9; ++q) spost[q][i] = post[q];
+    }
+    __syncthreads();
+
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const int ly = ty + r * BY, gx = x0 + tx, gy = y0 + ly;
+      if (gx >= nx || gy >= ny || gy >= t.z + TY) continue;
+      if (fbx == BC_INOUT && gx == nx - 1 && nx > 1) continue;  // written by the x = nx-2 site
+      const int ci = (ly + 1) * CW + tx + 1;
+      R fn[9];
+      if (fbx == BC_INOUT && gx == 0) {
+        flow_eq(R(1), R(D.u_in), R(0), dt, fn);
+      } else {
+        const R flo = sfl[ci];
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+          const int ex = EX9[q], ey = EY9[q];
+          const int sx = gx - ex, sy = gy - ey;
+          const bool out = ((sx < 0 || sx >= nx) && fbx != BC_PER) || ((sy < 0 || sy >= ny) && fby != BC_PER);
+          const R bounce = spost[OPP9[q]][ci];
+          if (out || q == 0) {
+            fn[q] = q == 0 ? spost[0][ci] : bounce;
+          } else {
+            const int si = ci - ey * CW - ex;
+            const R m = R(0.5) * (flo + sfl[si]);
+            fn[q] = m * spost[q][si] + (R(1) - m) * bounce;     // Eq. (33)
+          }
+        }
+      }
+      R rho = R(0), jx = R(0), jy = R(0);
+#pragma unroll
+      for (int q = 0; q < 9; ++q) {
+        rho += fn[q];
+        jx += R(EX9[q]) * fn[q];
+        jy += R(EY9[q]) * fn[q];
+      }
+      const R ux = (c * jx + dt * Fx * R(0.5)) / rho, uy = (c * jy + dt * Fy * R(0.5)) / rho;
+      const int ncopy = (fbx == BC_INOUT && gx == nx - 2) ? 2 : 1;
+      for (int cpy = 0; cpy < ncopy; ++cpy) {
+        const long long o = gy * px + gx + cpy;
+        rho_out[o] = rho;
+        vel[o] = ux;
+        vel[o + pl] = uy;
+#pragma unroll
+        for (int q = 1; q < 9; ++q) st(s_out, o + (q - 1) * pl, fn[q] - w[q] * rho);
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// =================================================================== init
+// phi = max over seeds of tanh[(R - r)/(sqrt2 W0)] (Section 4.1); U = U0,
+// T = T0, rho = 1, u = 0 or u_in (1 - phi)/2 along x; every population at
+// equilibrium with v_n = 0 (Eq. 19, 21, 28).
+template <class R, class S>
+__global__ void k_init(const Dom* __restrict__ doms, int dom) {
+  const Dom& D = doms[dom];
+  const long long n = (long long)D.nx * D.ny;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int x = (int)(i % D.nx), y = (int)(i / D.nx);
+  const long long o = (long long)y * D.px + x, pl = D.plane;
+  const double s2w = 1.4142135623730951 * D.W0;
+  double phi = -1.0;
+  for (int s = 0; s < D.nseeds; ++s) {
+    const double dx = x - D.seed[s][0], dy = y - D.seed[s][1];
+    const double v = tanh((D.seed[s][2] - sqrt(dx * dx + dy * dy)) / s2w);
+    phi = v > phi ? v : phi;
+  }
+  const R ph = R(phi);
+  ((R*)D.phi[0])[o] = ph;
+  ((R*)D.phi[1])[o] = ph;
+  for (int q = 0; q < 4; ++q) {
+    st((S*)D.sphi[0], o + q * pl, R(0));
+    st((S*)D.sphi[1], o + q * pl, R(0));
+  }
+  const double ux = (D.has_F && D.u0_liquid) ? D.u_in * (1.0 - double(ph)) * 0.5 : 0.0;
+  if (D.has_U) {
+    const double dtU = D.N_U * D.dt_base;
+    for (int b = 0; b < 2; ++b) {
+      ((R*)D.U[b])[o] = R(D.U0);
+      st((S*)D.jU[b], o, R(D.U0 * ux * dtU));
+      st((S*)D.jU[b], o + pl, R(0));
+    }
+    ((R*)D.PU)[o] = R(0);
+  }
+  if (D.has_T) {
+    const double dtT = D.N_T * D.dt_base;
+    for (int b = 0; b < 2; ++b) {
+      ((R*)D.T[b])[o] = R(D.T0);
+      st((S*)D.jT[b], o, R(D.T0 * ux * dtT));
+      st((S*)D.jT[b], o + pl, R(0));
+    }
+    ((R*)D.PT)[o] = R(0);
+  }
+  if (D.has_F) {
+    const double dtF = D.N_F * D.dt_base;
+    R feq[9];
+    flow_eq(R(1), R(ux), R(0), R(dtF), feq);
+    const R w[9] = {R(4.0 / 9), R(1.0 / 9), R(1.0 / 9), R(1.0 / 9), R(1.0 / 9),
+                    R(1.0 / 36), R(1.0 / 36), R(1.0 / 36), R(1.0 / 36)};
+    for (int b = 0; b < 2; ++b) {
+      ((R*)D.rho[b])[o] = R(1);
+      for (int q = 1; q < 9; ++q) st((S*)D.sF[b], o + (q - 1) * pl, feq[q] - w[q]);
+    }
+    for (int b = 0; b < 2; ++b) {
+      ((R*)D.vel[b])[o] = R(ux);
+      ((R*)D.vel[b])[o + pl] = R(0);
+    }
+  }
+}
+
+// =================================================================== read / write
+// Plane codes: 0 phi, 1 U, 2 T, 3 rho, 4 ux, 5 uy, 10..14 phase f_0..f_4,
+// 20/21 jU, 30/31 jT, 40..48 flow f_0..f_8, 50 pending U, 51 pending T,
+// 60..63 stored phase planes s_1..s_4, 70..77 stored flow planes s_1..s_8.
+template <class R, class S>
+__device__ double read_plane(const Dom& D, long long k, int code, long long o) {
+  const long long pl = D.plane;
+  switch (code) {
+    case 0: return double(((const R*)D.phi[par(n_phi(D, k))])[o]);
+    case 1: return double(((const R*)D.U[par(n_U(D, k))])[o]);
+    case 2: return double(((const R*)D.T[par(n_T(D, k))])[o]);
+    case 3: return double(((const R*)D.rho[par(n_F(D, k))])[o]);
+    case 4: return double(((const R*)D.vel[par(n_F(D, k))])[o]);
+    case 5: return double(((const R*)D.vel[par(n_F(D, k))])[o + pl]);
+    case 20: case 21: return double(ld((const S*)D.jU[par(n_jU(D, k))], o + (code - 20) * pl));
+    case 30: case 31: return double(ld((const S*)D.jT[par(n_T(D, k))], o + (code - 30) * pl));
+    case 50: return double(((const R*)D.PU)[o]);
+    case 51: return double(((const R*)D.PT)[o]);
+    default: break;
+  }
+  if (code >= 60 && code <= 63) return double(ld((const S*)D.sphi[par(n_phi(D, k))], o + (code - 60) * pl));
+  if (code >= 70 && code <= 77) return double(ld((const S*)D.sF[par(n_F(D, k))], o + (code - 70) * pl));
+  if (code >= 10 && code <= 14) {
+    const int b = par(n_phi(D, k));
+    const R* ph = (const R*)D.phi[b];
+    const S* s = (const S*)D.sphi[b];
+    const R phi = ph[o];
+    const R s1 = ld(s, o), s2 = ld(s, o + pl), s3 = ld(s, o + 2 * pl), s4 = ld(s, o + 3 * pl);
+    if (code == 10) return double(phi * R(1.0 / 3.0) - (s1 + s2 + s3 + s4));
+    const R sv[4] = {s1, s2, s3, s4};
+    return double(phi * R(1.0 / 6.0) + sv[code - 11]);
+  }
+  if (code >= 40 && code <= 48) {
+    const int b = par(n_F(D, k));
+    const R rho = ((const R*)D.rho[b])[o];
+    const S* s = (const S*)D.sF[b];
+    const R w[9] = {R(4.0 / 9), R(1.0 / 9), R(1.0 / 9), R(1.0 / 9), R(1.0 / 9),
+                    R(1.0 / 36), R(1.0 / 36), R(1.0 / 36), R(1.0 / 36)};
+    if (code == 40) {
+      R ssum = R(0);
+      for (int q = 1; q < 9; ++q) ssum += ld(s, o + (q - 1) * pl);
+      return double(w[0] * rho - ssum);
+    }
+    const int q = code - 40;
+    return double(w[q] * rho + ld(s, o + (q - 1) * pl));
+  }
+  return 0.0;
+}
+
+template <class R, class S>
+__global__ void k_read(const Dom* __restrict__ doms, int dom, long long k, const int* __restrict__ codes,
+                       int ncodes, int out_f64, void* __restrict__ out) {
+  const Dom& D = doms[dom];
+  const long long n = (long long)D.nx * D.ny;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  const int c = blockIdx.y;
+  if (i >= n || c >= ncodes) return;
+  const int x = (int)(i % D.nx), y = (int)(i / D.nx);
+  const double v = read_plane<R, S>(D, k, codes[c], (long long)y * D.px + x);
+  if (out_f64)
+    ((double*)out)[c * n + i] = v;
+  else
+    ((float*)out)[c * n + i] = float(v);
+}
+
+// Writes take FP64 planes.  Phase populations (codes 10..14, all five
+// present) re-encode phi and s; flow populations (40..48) re-encode rho and s.
+template <class R, class S>
+__global__ void k_write(const Dom* __restrict__ doms, int dom, long long k, const int* __restrict__ codes,
+                        int ncodes, const double* __restrict__ src) {
+  const Dom& D = doms[dom];
+  const long long n = (long long)D.nx * D.ny;
+  const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int x = (int)(i % D.nx), y = (int)(i / D.nx);
+  const long long o = (long long)y * D.px + x, pl = D.plane;
+  int cphi = -1, cflow = -1;
+  for (int c = 0; c < ncodes; ++c) {
+    const int code = codes[c];
+    const double v = src[c * n + i];
+    switch (code) {
+      case 0: ((R*)D.phi[par(n_phi(D, k))])[o] = R(v); break;
+      case 1: ((R*)D.U[par(n_U(D, k))])[o] = R(v); break;
+      case 2: ((R*)D.T[par(n_T(D, k))])[o] = R(v); break;
+      case 3: ((R*)D.rho[par(n_F(D, k))])[o] = R(v); break;
+      case 4: ((R*)D.vel[par(n_F(D, k))])[o] = R(v); break;
+      case 5: ((R*)D.vel[par(n_F(D, k))])[o + pl] = R(v); break;
+      case 20: case 21: st((S*)D.jU[par(n_jU(D, k))], o + (code - 20) * pl, R(v)); break;
+      case 30: case 31: st((S*)D.jT[par(n_T(D, k))], o + (code - 30) * pl, R(v)); break;
+      case 50: ((R*)D.PU)[o] = R(v); break;
+      case 51: ((R*)D.PT)[o] = R(v); break;
+      case 60: case 61: case 62: case 63:
+        st((S*)D.sphi[par(n_phi(D, k))], o + (code - 60) * pl, R(v));
+        break;
+      case 70: case 71: case 72: case 73: case 74: case 75: case 76: case 77:
+        st((S*)D.sF[par(n_F(D, k))], o + (code - 70) * pl, R(v));
+        break;
+      default:
+        if (code == 10) cphi = c;
+        if (code == 40) cflow = c;
+        break;
+    }
+  }
+  if (cphi >= 0) {
+    const int b = par(n_phi(D, k));
+    R f[5];
+    R phi = R(0);
+    for (int q = 0; q < 5; ++q) {
+      f[q] = R(src[(cphi + q) * n + i]);
+      phi += f[q];
+    }
+    ((R*)D.phi[b])[o] = phi;
+    for (int q = 1; q < 5; ++q) st((S*)D.sphi[b], o + (q - 1) * pl, f[q] - phi * R(1.0 / 6.0));
+  }
+  if (cflow >= 0) {
+    const int b = par(n_F(D, k));
+    const R w[9] = {R(4.0 / 9), R(1.0 / 9), R(1.0 / 9), R(1.0 / 9), R(1.0 / 9),
+                    R(1.0 / 36), R(1.0 / 36), R(1.0 / 36), R(1.0 / 36)};
+    R f[9];
+    R rho = R(0);
+    for (int q = 0; q < 9; ++q) {
+      f[q] = R(src[(cflow + q) * n + i]);
+      rho += f[q];
+    }
+    ((R*)D.rho[b])[o] = rho;
+    for (int q = 1; q < 9; ++q) st((S*)D.sF[b], o + (q - 1) * pl, f[q] - w[q] * rho);
+  }
+}
+
+// =================================================================== diagnostics
+// Per-tile FP64 partial sums (solid fraction, total solute C of Eq. 5,
+// enthalpy for constant properties, mass, non-finite count), reduced across
+// the wavefront with shuffles and across the block in LDS.
+template <class R, int TY>
+__global__ __launch_bounds__(NTHR) void k_diag_tiles(const Dom* __restrict__ doms, const int4* __restrict__ tiles,
+                                                      long long k, Partial* __restrict__ part) {
+  constexpr int RPT = TY / BY;
+  __shared__ double red[5][NTHR / 64];
+  const int4 t = tiles[blockIdx.x];
+  if (t.x < 0) return;
+  const Dom& D = doms[t.x];
+  const long long px = D.px;
+  const R* phi = (const R*)D.phi[par(n_phi(D, k))];
+  const R* U = D.has_U ? (const R*)D.U[par(n_U(D, k))] : nullptr;
+  const R* T = D.has_T ? (const R*)D.T[par(n_T(D, k))] : nullptr;
+  const R* rho = D.has_F ? (const R*)D.rho[par(n_F(D, k))] : nullptr;
+  const int tx = threadIdx.x, ty = threadIdx.y;
+  double a[5] = {0, 0, 0, 0, 0};
+  for (int r = 0; r < RPT; ++r) {
+    const int gx = t.y + tx, gy = t.z + ty + r * BY;
+    if (gx >= D.nx || gy >= D.ny) continue;
+    const long long o = gy * px + gx;
+    const double p = double(phi[o]);
+    a[0] += (1.0 + p) * 0.5;
+    bool bad = !isfinite(p);
+    if (U) {
+      const double u = double(U[o]);
+      a[1] += D.C_inf * ((1.0 + D.kc) - (1.0 - D.kc) * p) * (1.0 + (1.0 - D.kc) * u) * 0.5;
+      bad |= !isfinite(u);
+    }
+    if (T) {
+      const double tv = double(T[o]);
+      a[2] += tv - D.rho_L * D.L_h * p / (2.0 * D.rcL);
+      bad |= !isfinite(tv);
+    }
+    if (rho) {
+      const double rv = double(rho[o]);
+      a[3] += rv;
+      bad |= !isfinite(rv);
+    }
+    a[4] += bad ? 1.0 : 0.0;
+  }
+  for (int j = 0; j < 5; ++j) {
+    double v = a[j];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if (tx == 0) red[j][ty] = v;
+  }
+  __syncthreads();
+  if (tx == 0 && ty == 0) {
+    double s[5];
+    for (int j = 0; j < 5; ++j) {
+      s[j] = 0.0;
+      for (int w = 0; w < NTHR / 64; ++w) s[j] += red[j][w];
+    }
+    Partial& P = part[t.w];
+    P.solid = s[0];
+    P.M_C = s[1];
+    P.enthalpy = s[2];
+    P.mass = s[3];
+    P.nonfinite = s[4];
+  }
+}
+
+// One block per domain: fixed-order reduction of the tile partials (the
+// partial slots of a domain are listed in slot[] in spatial order).
+__global__ void k_diag_final(const Dom* __restrict__ doms, const Partial* __restrict__ part,
+                             const int* __restrict__ slot, const int* __restrict__ slot0, DiagOut* __restrict__ out) {
+  __shared__ double red[7][4];
+  const int d = blockIdx.x;
+  const int b = slot0[d], e = slot0[d + 1];
+  double a[7] = {0, 0, 0, 0, 0, 0, 0};
+  for (int i = b + threadIdx.x; i < e; i += blockDim.x) {
+    const Partial& P = part[slot[i]];
+    a[0] += P.solid;
+    a[1] += P.M_C;
+    a[2] += P.enthalpy;
+    a[3] += P.mass;
+    a[4] = fmax(a[4], P.S_phi);
+    a[5] = fmax(a[5], P.J_U);
+    a[6] += P.nonfinite;
+  }
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int j = 0; j < 7; ++j) {
+    double v = a[j];
+    for (int off = 32; off > 0; off >>= 1) {
+      const double o = __shfl_down(v, off, 64);
+      v = (j == 4 || j == 5) ? fmax(v, o) : v + o;
+    }
+    if (lane == 0) red[j][w] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double s[7];
+    for (int j = 0; j < 7; ++j) {
+      s[j] = red[j][0];
+      for (int q = 1; q < (int)(blockDim.x >> 6); ++q) s[j] = (j == 4 || j == 5) ? fmax(s[j], red[j][q]) : s[j] + red[j][q];
+    }
+    DiagOut& O = out[d];
+    O.solid = s[0];
+    O.M_C = s[1];
+    O.enthalpy = s[2];
+    O.mass = s[3];
+    O.S_phi = s[4];
+    O.J_U = s[5];
+    O.nonfinite = (long long)s[6];
+  }
+}
+
+// Tip distance along one crystal axis of one seed: march outwards at unit
+// spacing with bilinear sampling (clamped at the edges); the tip is the
+// linear interpolation between the last sample with phi >= 0 and the first
+// with phi < 0.  One block per (domain, seed, axis).
+template <class R>
+__device__ double bilin(const R* phi, long long px, int nx, int ny, double x, double y) {
+  x = fmin(fmax(x, 0.0), nx - 1.0);
+  y = fmin(fmax(y, 0.0), ny - 1.0);
+  int ix = (int)floor(x), iy = (int)floor(y);
+  ix = ix > nx - 2 ? nx - 2 : ix;
+  iy = iy > ny - 2 ? ny - 2 : iy;
+  const double tx = x - ix, ty = y - iy;
+  const long long o = iy * px + ix;
+  return (1 - tx) * (1 - ty) * double(phi[o]) + tx * (1 - ty) * double(phi[o + 1]) +
+         (1 - tx) * ty * double(phi[o + px]) + tx * ty * double(phi[o + px + 1]);
+}
+
+template <class R>
+__global__ void k_tips(const Dom* __restrict__ doms, long long k, DiagOut* __restrict__ out) {
+  __shared__ int sm[4];
+  const int d = blockIdx.x, s = blockIdx.y, ax = blockIdx.z;
+  const Dom& D = doms[d];
+  if (s >= D.nseeds) {
+    if (threadIdx.x == 0) out[d].tip[s * 4 + ax] = 0.0;
+    return;
+  }
+  const R* phi = (const R*)D.phi[par(n_phi(D, k))];
+  const double ang = atan2(D.sth, D.cth) + ax * 1.5707963267948966;
+  const double c = cos(ang), sn = sin(ang);
+  const double cx = D.seed[s][0], cy = D.seed[s][1];
+  const int rmax = D.nx > D.ny ? D.nx : D.ny;
+  int first = rmax + 1;
+  for (int r = threadIdx.x; r <= rmax; r += blockDim.x) {
+    if (bilin(phi, D.px, D.nx, D.ny, cx + r * c, cy + r * sn) < 0.0) {
+      first = r;
+      break;
+    }
+  }
+  for (int off = 32; off > 0; off >>= 1) first = min(first, __shfl_down(first, off, 64));
+  if ((threadIdx.x & 63) == 0) sm[threadIdx.x >> 6] = first;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int f = sm[0];
+    for (int w = 1; w < (int)(blockDim.x >> 6); ++w) f = min(f, sm[w]);
+    double tip;
+    if (f == 0)
+      tip = 0.0;
+    else if (f > rmax)
+      tip = double(rmax);
+    else {
+      const double prev = bilin(phi, D.px, D.nx, D.ny, cx + (f - 1) * c, cy + (f - 1) * sn);
+      const double cur = bilin(phi, D.px, D.nx, D.ny, cx + f * c, cy + f * sn);
+      tip = (f - 1) + prev / (prev - cur);
+    }
+    out[d].tip[s * 4 + ax] = tip;
+  }
+}
+
+// =================================================================== launchers
+template <class R, class S>
+struct Launch {
+  static void phase(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k) {
+    if (TY == 8) k_phase<R, S, 8><<<g, dim3(TX, BY), 0, st>>>(d, t, k);
+    else if (TY == 16) k_phase<R, S, 16><<<g, dim3(TX, BY), 0, st>>>(d, t, k);
+    else k_phase<R, S, 32><<<g, dim3(TX, BY), 0, st>>>(d, t, k);
+  }
+  static void transfer(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k, Partial* p) {
+    if (TY == 8) k_transfer<R, 8><<<g, dim3(TX, BY), 0, st>>>(d, t, k, p);
+    else if (TY == 16) k_transfer<R, 16><<<g, dim3(TX, BY), 0, st>>>(d, t, k, p);
+    else k_transfer<R, 32><<<g, dim3(TX, BY), 0, st>>>(d, t, k, p);
+  }
+  static void scalar(int field, int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k,
+                     Partial* p) {
+    if (field == 0) {
+      if (TY == 8) k_scalar<R, S, 8, 0><<<g, dim3(TX, BY), 0, st>>>(d, t, k, p);
+      else if (TY == 16) k_scalar<R, S, 16, 0><<<g, dim3(TX, BY), 0, st>>>(d, t, k, p);
+      else k_scalar<R, S, 32, 0><<<g, dim3(TX, BY), 0, st>>>(d, t, k, p);
+    } else {
+      if (TY == 8) k_scalar<R, S, 8, 1><<<g, dim3(TX, BY), 0, st>>>(d, t, k, p);
+      else if (TY == 16) k_scalar<R, S, 16, 1><<<g, dim3(TX, BY), 0, st>>>(d, t, k, p);
+      else k_scalar<R, S, 32, 1><<<g, dim3(TX, BY), 0, st>>>(d, t, k, p);
+    }
+  }
+  static void flow(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k) {
+    constexpr int SUB = sizeof(R) == 8 ? 8 : 16;
+    if (TY == 8) k_flow<R, S, 8, 8><<<g, dim3(TX, BY), 0, st>>>(d, t, k);
+    else if (TY == 16) k_flow<R, S, 16, SUB><<<g, dim3(TX, BY), 0, st>>>(d, t, k);
+    else k_flow<R, S, 32, SUB><<<g, dim3(TX, BY), 0, st>>>(d, t, k);
+  }
+  static void diag_tiles(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k, Partial* p) {
+    if (TY == 8) k_diag_tiles<R, 8><<<g, dim3(TX, BY), 0, st>>>(d, t, k, p);
+    else if (TY == 16) k_diag_tiles<R, 16><<<g, dim3(TX, BY), 0, st>>>(d, t, k, p);
+    else k_diag_tiles<R, 32><<<g, dim3(TX, BY), 0, st>>>(d, t, k, p);
+  }
+  static void tips(int ndom, hipStream_t st, const Dom* d, long long k, DiagOut* o) {
+    k_tips<R><<<dim3(ndom, MAX_SEEDS, 4), 256, 0, st>>>(d, k, o);
+  }
+  static void init(hipStream_t st, const Dom* d, int dom, long long n) {
+    k_init<R, S><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(d, dom);
+  }
+  static void read(hipStream_t st, const Dom* d, int dom, long long k, const int* codes, int nc, int f64,
+                   void* out, long long n) {
+    k_read<R, S><<<dim3((unsigned)((n + 255) / 256), nc), 256, 0, st>>>(d, dom, k, codes, nc, f64, out);
+  }
+  static void write(hipStream_t st, const Dom* d, int dom, long long k, const int* codes, int nc,
+                    const double* src, long long n) {
+    k_write<R, S><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(d, dom, k, codes, nc, src);
+  }
+};
+
+void diag_final(int ndom, hipStream_t st, const Dom* d, const Partial* p, const int* slot, const int* slot0,
+                DiagOut* o) {
+  k_diag_final<<<ndom, 256, 0, st>>>(d, p, slot, slot0, o);
+}
+
+template struct Launch<double, double>;
+template struct Launch<float, float>;
+template struct Launch<float, __half>;
+template struct Launch<float, __hip_bfloat16>;
+
+}  // namespace lbm

@@ -1,0 +1,802 @@
+// Host runtime and C ABI of the multirate lattice-Boltzmann library.
+//
+// A context owns one workspace (caller-supplied or allocated here) carved into
+// the per-domain state planes, the device descriptors, the tile lists and the
+// reduction buffers.  Stepping issues, per base step k, the kernels whose
+// field is due (k mod N_chi == 0, Eq. 34) in the order phase, transfer, U, T,
+// flow; whole cycles of 2 * lcm(N_chi) base steps (the period after which
+// every double-buffer parity repeats) are captured once into a HIP graph and
+// replayed.
+#include <hip/hip_bf16.h>
+#include <hip/hip_fp16.h>
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <numeric>
+#include <string>
+#include <vector>
+
+#include "../../include/lbm.h"
+#include "lbm_dev.h"
+
+namespace lbm {
+template <class R, class S>
+struct Launch {
+  static void phase(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k);
+  static void transfer(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k, Partial* p);
+  static void scalar(int field, int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k,
+                     Partial* p);
+  static void flow(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k);
+  static void diag_tiles(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k, Partial* p);
+  static void tips(int ndom, hipStream_t st, const Dom* d, long long k, DiagOut* o);
+  static void init(hipStream_t st, const Dom* d, int dom, long long n);
+  static void read(hipStream_t st, const Dom* d, int dom, long long k, const int* codes, int nc, int f64,
+                   void* out, long long n);
+  static void write(hipStream_t st, const Dom* d, int dom, long long k, const int* codes, int nc,
+                    const double* src, long long n);
+};
+void diag_final(int ndom, hipStream_t st, const Dom* d, const Partial* p, const int* slot, const int* slot0,
+                DiagOut* o);
+}  // namespace lbm
+
+using namespace lbm;
+
+namespace {
+
+constexpr int kTYs[3] = {8, 16, 32};
+constexpr long long kMaxGraphSteps = 4096;
+constexpr int kMaxCodes = 64;
+
+std::string g_create_error;
+
+struct TileSet {
+  int4* d = nullptr;  // device list (XCD-ordered, padded to a multiple of 8)
+  int n = 0;          // padded length = grid size
+};
+
+struct Group {
+  int N;              // update factor shared by the domains of the group
+  TileSet ts[3];      // per tile height
+};
+
+struct Ops {
+  void (*phase)(int, dim3, hipStream_t, const Dom*, const int4*, long long);
+  void (*transfer)(int, dim3, hipStream_t, const Dom*, const int4*, long long, Partial*);
+  void (*scalar)(int, int, dim3, hipStream_t, const Dom*, const int4*, long long, Partial*);
+  void (*flow)(int, dim3, hipStream_t, const Dom*, const int4*, long long);
+  void (*diag_tiles)(int, dim3, hipStream_t, const Dom*, const int4*, long long, Partial*);
+  void (*tips)(int, hipStream_t, const Dom*, long long, DiagOut*);
+  void (*init)(hipStream_t, const Dom*, int, long long);
+  void (*read)(hipStream_t, const Dom*, int, long long, const int*, int, int, void*, long long);
+  void (*write)(hipStream_t, const Dom*, int, long long, const int*, int, const double*, long long);
+};
+
+template <class R, class S>
+Ops make_ops() {
+  return Ops{Launch<R, S>::phase, Launch<R, S>::transfer, Launch<R, S>::scalar, Launch<R, S>::flow,
+             Launch<R, S>::diag_tiles, Launch<R, S>::tips, Launch<R, S>::init, Launch<R, S>::read,
+             Launch<R, S>::write};
+}
+
+size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+long long ipow_lcm(long long a, long long b) { return a / std::gcd(a, b) * b; }
+
+}  // namespace
+
+struct lbm_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  hipStream_t cap_stream = nullptr;
+  int storage = LBM_STORE_F32;
+  size_t rsz = 4, ssz = 4;
+  Ops ops{};
+  int ndom = 0;
+  std::vector<lbm_params> P;
+  std::vector<Dom> H;
+  void* ws = nullptr;
+  size_t ws_bytes = 0;
+  bool own_ws = false;
+  Dom* d_dom = nullptr;
+  TileSet all[3];
+  std::vector<Group> g_phi, g_U, g_T, g_F;
+  Partial* d_part = nullptr;
+  int* d_slot = nullptr;
+  int* d_slot0[3] = {nullptr, nullptr, nullptr};
+  DiagOut* d_diag = nullptr;
+  int* d_codes = nullptr;
+  double* d_stage = nullptr;
+  size_t stage_elems = 0;
+  int ty_index = 1;
+  bool tuned = false;
+  bool autotune = true;
+  bool use_graph = true;
+  hipGraphExec_t gexec = nullptr;
+  int graph_ty = -1;
+  long long cycle = 1;
+  long long k = 0;
+  std::vector<bool> initialised;
+  std::string err;
+};
+
+namespace {
+
+lbm_status fail(lbm_ctx* c, lbm_status s, const std::string& m) {
+  if (c)
+    c->err = m;
+  else
+    g_create_error = m;
+  return s;
+}
+
+#define HIPCHK(ctx, call)                                                                     \
+  do {                                                                                        \
+    hipError_t e_ = (call);                                                                   \
+    if (e_ != hipSuccess)                                                                     \
+      return fail(ctx, LBM_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));       \
+  } while (0)
+
+int px_of(int nx) { return (nx + 63) / 64 * 64; }
+
+// elements per plane and the per-domain byte layout
+struct Layout {
+  size_t rplanes = 0, splanes = 0;
+};
+
+Layout layout_of(const lbm_params& p) {
+  Layout L;
+  L.rplanes = 2;              // phi
+  L.splanes = 8;              // phase s_1..s_4, two buffers
+  if (p.has_U) { L.rplanes += 3; L.splanes += 4; }
+  if (p.has_T) { L.rplanes += 3; L.splanes += 4; }
+  if (p.has_flow) { L.rplanes += 6; L.splanes += 16; }
+  return L;
+}
+
+size_t sizes_of(int storage, size_t& rsz, size_t& ssz) {
+  rsz = storage == LBM_STORE_F64 ? 8 : 4;
+  ssz = storage == LBM_STORE_F64 ? 8 : storage == LBM_STORE_F32 ? 4 : 2;
+  return 0;
+}
+
+std::string validate(const lbm_params& p, int i) {
+  char b[256];
+  auto bad = [&](const char* m) {
+    snprintf(b, sizeof b, "domain %d: %s", i, m);
+    return std::string(b);
+  };
+  if (p.dim != 2) return bad("only dim = 2 is supported");
+  if (p.nz != 1) return bad("nz must be 1 in 2D");
+  if (p.nx < 3 || p.ny < 3 || p.nx > (1 << 16) || p.ny > (1 << 16)) return bad("grid sides must be in [3, 65536]");
+  if (p.q_scalar != 5) return bad("scalar lattice must be D2Q5 (q_scalar = 5)");
+  if (p.N_phi < 1 || p.N_U < 1 || p.N_T < 1 || p.N_F < 1) return bad("update factors must be >= 1");
+  if (!(p.dt_base > 0)) return bad("dt_base must be > 0");
+  if (!(p.W0 > 0) || !(p.tau0 > 0)) return bad("W0 and tau0 must be > 0");
+  if (p.eps_s < 0 || p.eps_s >= 0.25) return bad("eps_s must be in [0, 0.25)");
+  for (int a = 0; a < 2; ++a) {
+    if (p.bc[a] != LBM_BC_PERIODIC && p.bc[a] != LBM_BC_WALL) return bad("scalar bc must be periodic or wall");
+    if (p.flow_bc[a] < 0 || p.flow_bc[a] > 2) return bad("bad flow bc");
+  }
+  if (p.flow_bc[1] == LBM_BC_INLET_OUTFLOW) return bad("inlet/outflow is supported along x only");
+  if (p.coupling != LBM_COUPLE_INSTANT && p.coupling != LBM_COUPLE_ACCUM) return bad("bad coupling");
+  // relaxation times at phi = +-1 (Eq. 24, 32): every tau must exceed 1/2
+  const double amin = 1.0 - 5.0 / 3.0 * p.eps_s;
+  const double tphi = 3.0 * p.N_phi * p.dt_base * amin * amin * p.W0 * p.W0 / p.tau0 + 0.5;
+  if (!(tphi > 0.5)) return bad("tau_phi <= 1/2");
+  if (p.has_U) {
+    for (double ph : {-1.0, 1.0}) {
+      const double kf = (1 + p.k) - (1 - p.k) * ph;
+      if (!(kf > 0)) return bad("(1+k) - (1-k) phi must be > 0");
+      const double De = ((1 + ph) * p.D_S + (1 - ph) * p.D_L) / kf;
+      if (!(3.0 * p.N_U * p.dt_base * De + 0.5 > 0.5)) return bad("tau_U <= 1/2");
+    }
+  }
+  if (p.has_T) {
+    if (!(p.rhoCp_S > 0) || !(p.rhoCp_L > 0)) return bad("rhoCp must be > 0");
+    for (double ph : {-1.0, 1.0}) {
+      const double a = ((1 + ph) / 2 * p.kappa_S + (1 - ph) / 2 * p.kappa_L) /
+                       ((1 + ph) / 2 * p.rhoCp_S + (1 - ph) / 2 * p.rhoCp_L);
+      if (!(3.0 * p.N_T * p.dt_base * a + 0.5 > 0.5)) return bad("tau_T <= 1/2");
+    }
+    if (!(p.L_h != 0) || !(p.Cp_L > 0)) return bad("L_h and Cp_L must be nonzero");
+  }
+  if (p.has_flow && !(3.0 * p.N_F * p.dt_base * p.nu + 0.5 > 0.5)) return bad("tau_F <= 1/2");
+  return "";
+}
+
+// XCD-aware tile list: spatial tiles s = 0..n-1 (domain-major, row-major)
+// are split into 8 contiguous chunks, chunk x going to the blocks b with
+// b mod 8 == x (workgroups are dispatched round-robin over the eight XCDs),
+// so neighbouring tiles share an XCD's L2 and halo re-reads hit it.
+std::vector<int4> xcd_order(const std::vector<int4>& spatial) {
+  const int n = (int)spatial.size();
+  const int c = (n + 7) / 8;
+  std::vector<int4> out((size_t)8 * c, make_int4(-1, 0, 0, 0));
+  for (int b = 0; b < 8 * c; ++b) {
+    const int s = (b % 8) * c + b / 8;
+    if (s < n) out[b] = spatial[s];
+  }
+  return out;
+}
+
+}  // namespace
+
+// ------------------------------------------------------------------ helpers
+static void launch_step(lbm_ctx* c, hipStream_t st, long long k) {
+  const int ti = c->ty_index, TY = kTYs[ti];
+  for (auto& g : c->g_phi)
+    if (k % g.N == 0) {
+      c->ops.phase(TY, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k);
+      c->ops.transfer(TY, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k, c->d_part);
+    }
+  for (auto& g : c->g_U)
+    if (k % g.N == 0) c->ops.scalar(0, TY, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k, c->d_part);
+  for (auto& g : c->g_T)
+    if (k % g.N == 0) c->ops.scalar(1, TY, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k, c->d_part);
+  for (auto& g : c->g_F)
+    if (k % g.N == 0) c->ops.flow(TY, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k);
+}
+
+static lbm_status upload_doms(lbm_ctx* c) {
+  HIPCHK(c, hipMemcpyAsync(c->d_dom, c->H.data(), sizeof(Dom) * c->ndom, hipMemcpyHostToDevice, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+// Time each tile height on the kernels whose launches are idempotent for a
+// fixed k (they read one buffer and write the other) and keep the fastest.
+static lbm_status autotune(lbm_ctx* c) {
+  hipEvent_t e0, e1;
+  HIPCHK(c, hipEventCreate(&e0));
+  HIPCHK(c, hipEventCreate(&e1));
+  float best = 1e30f;
+  int besti = 1;
+  bool any_accum = false;
+  for (auto& D : c->H) any_accum |= D.accum != 0;
+  // the next due step of a group: its kernels read the current buffers and
+  // write only the other ones, so repeating them leaves the state unchanged
+  auto next_due = [&](int N) { return (c->k / N + 1) * (long long)N; };
+  for (int ti = 0; ti < 3; ++ti) {
+    const int TY = kTYs[ti];
+    auto run = [&]() {
+      for (auto& g : c->g_phi)
+        c->ops.phase(TY, dim3(g.ts[ti].n), c->stream, c->d_dom, g.ts[ti].d, next_due(g.N));
+      if (!any_accum)
+        for (auto& g : c->g_T)
+          c->ops.scalar(1, TY, dim3(g.ts[ti].n), c->stream, c->d_dom, g.ts[ti].d, next_due(g.N), nullptr);
+      for (auto& g : c->g_F) c->ops.flow(TY, dim3(g.ts[ti].n), c->stream, c->d_dom, g.ts[ti].d, next_due(g.N));
+    };
+    run();
+    HIPCHK(c, hipEventRecord(e0, c->stream));
+    for (int r = 0; r < 5; ++r) run();
+    HIPCHK(c, hipEventRecord(e1, c->stream));
+    HIPCHK(c, hipEventSynchronize(e1));
+    float ms = 0;
+    HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+    if (ms < best) {
+      best = ms;
+      besti = ti;
+    }
+  }
+  HIPCHK(c, hipEventDestroy(e0));
+  HIPCHK(c, hipEventDestroy(e1));
+  c->ty_index = besti;
+  c->tuned = true;
+  return LBM_OK;
+}
+
+// ------------------------------------------------------------------ ABI
+extern "C" {
+
+size_t lbm_workspace_bytes(const lbm_params* p, int32_t n, int32_t storage) {
+  if (!p || n < 1 || storage < 0 || storage > 3) return 0;
+  size_t rsz, ssz;
+  sizes_of(storage, rsz, ssz);
+  size_t total = 0;
+  long long tiles8 = 0;
+  size_t maxsites = 0;
+  for (int i = 0; i < n; ++i) {
+    if (!validate(p[i], i).empty()) return 0;
+    const size_t plane = (size_t)px_of(p[i].nx) * p[i].ny;
+    const Layout L = layout_of(p[i]);
+    total += align256(plane * rsz) * L.rplanes + align256(plane * ssz) * L.splanes;
+    tiles8 += (long long)((p[i].nx + 63) / 64) * ((p[i].ny + 7) / 8);
+    maxsites = std::max(maxsites, (size_t)p[i].nx * p[i].ny);
+  }
+  const long long padded = (tiles8 + 7) / 8 * 8;
+  total += align256(sizeof(Dom) * n);
+  // tile lists per tile height: "all" plus, per field, one list per group of
+  // domains sharing an update factor (at most 8 groups, each padded by < 8)
+  total += 3 * (5 * (sizeof(int4) * (size_t)(padded + 64)) + 40 * 256);
+  total += align256(sizeof(Partial) * (size_t)tiles8);
+  total += align256(sizeof(int) * (size_t)tiles8) + 3 * align256(sizeof(int) * (n + 1));
+  total += align256(sizeof(DiagOut) * n);
+  total += align256(sizeof(int) * kMaxCodes);
+  total += align256(sizeof(double) * maxsites * 16);
+  return total;
+}
+
+lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t device, void* hip_stream,
+                      void* workspace, size_t workspace_bytes, lbm_ctx** out) {
+  if (!out) return fail(nullptr, LBM_EINVAL, "out is NULL");
+  *out = nullptr;
+  if (!p || n < 1) return fail(nullptr, LBM_EINVAL, "no domains");
+  if (storage < 0 || storage > 3) return fail(nullptr, LBM_EINVAL, "bad storage format");
+  for (int i = 0; i < n; ++i) {
+    const std::string m = validate(p[i], i);
+    if (!m.empty()) return fail(nullptr, LBM_EINVAL, m);
+  }
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
+    return fail(nullptr, LBM_EDEVICE, "no such HIP device");
+  if (hipSetDevice(device) != hipSuccess) return fail(nullptr, LBM_EDEVICE, "hipSetDevice failed");
+
+  const size_t need = lbm_workspace_bytes(p, n, storage);
+  auto* c = new lbm_ctx();
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  c->storage = storage;
+  sizes_of(storage, c->rsz, c->ssz);
+  switch (storage) {
+    case LBM_STORE_F64: c->ops = make_ops<double, double>(); break;
+    case LBM_STORE_F32: c->ops = make_ops<float, float>(); break;
+    case LBM_STORE_F16: c->ops = make_ops<float, __half>(); break;
+    default: c->ops = make_ops<float, __hip_bfloat16>(); break;
+  }
+  c->ndom = n;
+  c->P.assign(p, p + n);
+  c->initialised.assign(n, false);
+  if (workspace) {
+    if (workspace_bytes < need) {
+      delete c;
+      return fail(nullptr, LBM_ENOMEM, "workspace smaller than lbm_workspace_bytes()");
+    }
+    c->ws = workspace;
+    c->ws_bytes = workspace_bytes;
+  } else {
+    if (hipMalloc(&c->ws, need) != hipSuccess) {
+      delete c;
+      return fail(nullptr, LBM_ENOMEM, "hipMalloc of the workspace failed");
+    }
+    c->own_ws = true;
+    c->ws_bytes = need;
+  }
+  char* cur = (char*)c->ws;
+  auto take = [&](size_t bytes) {
+    void* r = cur;
+    cur += align256(bytes);
+    return r;
+  };
+
+  // domains and their planes
+  c->H.resize(n);
+  long long lcm = 1;
+  for (int i = 0; i < n; ++i) {
+    const lbm_params& q = p[i];
+    Dom& D = c->H[i];
+    memset(&D, 0, sizeof D);
+    D.nx = q.nx;
+    D.ny = q.ny;
+    D.px = px_of(q.nx);
+    D.plane = (long long)D.px * q.ny;
+    for (int a = 0; a < 2; ++a) {
+      D.bc[a] = q.bc[a];
+      D.fbc[a] = q.flow_bc[a];
+    }
+    D.N_phi = q.N_phi;
+    D.N_U = q.N_U;
+    D.N_T = q.N_T;
+    D.N_F = q.N_F;
+    D.has_U = q.has_U;
+    D.has_T = q.has_T;
+    D.has_F = q.has_flow;
+    D.accum = q.coupling == LBM_COUPLE_ACCUM;
+    D.T_var = (q.kappa_S != q.kappa_L) || (q.rhoCp_S != q.rhoCp_L);
+    D.dt_base = q.dt_base;
+    D.W0 = q.W0;
+    D.tau0 = q.tau0;
+    D.eps = q.eps_s;
+    D.lam = q.lam;
+    D.Mc = q.Mc;
+    D.kc = q.k;
+    D.cth = cos(q.theta_c);
+    D.sth = sin(q.theta_c);
+    D.D_L = q.D_L;
+    D.D_S = q.D_S;
+    D.C_inf = q.C_inf;
+    D.kS = q.kappa_S;
+    D.kL = q.kappa_L;
+    D.rcS = q.rhoCp_S;
+    D.rcL = q.rhoCp_L;
+    D.rho_L = q.rho_L;
+    D.L_h = q.L_h;
+    D.T_m = q.T_m;
+    D.m_L = q.m_L;
+    D.Cp_L = q.Cp_L;
+    D.nu = q.nu;
+    D.s_e = q.s_e;
+    D.s_eps = q.s_eps;
+    D.s_q = q.s_q;
+    D.u_in = q.u_in;
+    D.Fx = q.Fb[0];
+    D.Fy = q.Fb[1];
+    D.U0 = q.U0;
+    D.T0 = q.T0;
+    D.u0_liquid = q.u0_liquid_only;
+    const size_t pr = D.plane * c->rsz, ps = D.plane * c->ssz;
+    for (int b = 0; b < 2; ++b) {
+      D.phi[b] = take(pr);
+      D.sphi[b] = take(align256(ps) * 4);
+    }
+    if (q.has_U) {
+      for (int b = 0; b < 2; ++b) {
+        D.U[b] = take(pr);
+        D.jU[b] = take(align256(ps) * 2);
+      }
+      D.PU = take(pr);
+    }
+    if (q.has_T) {
+      for (int b = 0; b < 2; ++b) {
+        D.T[b] = take(pr);
+        D.jT[b] = take(align256(ps) * 2);
+      }
+      D.PT = take(pr);
+    }
+    if (q.has_flow) {
+      for (int b = 0; b < 2; ++b) {
+        D.rho[b] = take(pr);
+        D.sF[b] = take(align256(ps) * 8);
+        D.vel[b] = take(align256(pr) * 2);
+      }
+    }
+    lcm = ipow_lcm(lcm, q.N_phi);
+    if (q.has_U) lcm = ipow_lcm(lcm, q.N_U);
+    if (q.has_T) lcm = ipow_lcm(lcm, q.N_T);
+    if (q.has_flow) lcm = ipow_lcm(lcm, q.N_F);
+  }
+  c->cycle = 2 * lcm;
+  c->d_dom = (Dom*)take(sizeof(Dom) * n);
+
+  // tile lists (three tile heights), groups by update factor
+  long long tiles8 = 0;
+  size_t maxsites = 0;
+  for (int i = 0; i < n; ++i) {
+    tiles8 += (long long)((p[i].nx + 63) / 64) * ((p[i].ny + 7) / 8);
+    maxsites = std::max(maxsites, (size_t)p[i].nx * p[i].ny);
+  }
+  auto build = [&](const std::vector<int>& doms, int ti, TileSet& ts, std::vector<int>* slot0) -> lbm_status {
+    const int TY = kTYs[ti];
+    std::vector<int4> sp;
+    // slots are the spatial index over all domains, so every list writes the
+    // same partial slot for a given tile
+    std::vector<int> base(n + 1, 0);
+    for (int i = 0; i < n; ++i)
+      base[i + 1] = base[i] + ((p[i].nx + 63) / 64) * ((p[i].ny + TY - 1) / TY);
+    for (int d : doms) {
+      const int ntx = (p[d].nx + 63) / 64, nty = (p[d].ny + TY - 1) / TY;
+      for (int ty = 0; ty < nty; ++ty)
+        for (int tx = 0; tx < ntx; ++tx) sp.push_back(make_int4(d, tx * 64, ty * TY, base[d] + ty * ntx + tx));
+    }
+    if (slot0) *slot0 = base;
+    std::vector<int4> o = xcd_order(sp);
+    ts.d = (int4*)take(sizeof(int4) * o.size());
+    ts.n = (int)o.size();
+    HIPCHK(c, hipMemcpy(ts.d, o.data(), sizeof(int4) * o.size(), hipMemcpyHostToDevice));
+    return LBM_OK;
+  };
+  std::vector<int> alld(n);
+  std::iota(alld.begin(), alld.end(), 0);
+  std::vector<int> slot0[3];
+  for (int ti = 0; ti < 3; ++ti) {
+    lbm_status s = build(alld, ti, c->all[ti], &slot0[ti]);
+    if (s != LBM_OK) {
+      lbm_destroy(c);
+      return fail(nullptr, s, g_create_error.empty() ? "tile upload failed" : g_create_error);
+    }
+  }
+  auto make_groups = [&](int field, std::vector<Group>& gs) -> lbm_status {
+    std::map<int, std::vector<int>> by;
+    for (int i = 0; i < n; ++i) {
+      const lbm_params& q = p[i];
+      if (field == 0) by[q.N_phi].push_back(i);
+      if (field == 1 && q.has_U) by[q.N_U].push_back(i);
+      if (field == 2 && q.has_T) by[q.N_T].push_back(i);
+      if (field == 3 && q.has_flow) by[q.N_F].push_back(i);
+    }
+    if (by.size() > 1 && (int)by.size() > 8) return LBM_EINVAL;
+    for (auto& kv : by) {
+      Group g;
+      g.N = kv.first;
+      for (int ti = 0; ti < 3; ++ti) {
+        if (by.size() == 1 && (int)kv.second.size() == n) {
+          g.ts[ti] = c->all[ti];
+        } else {
+          lbm_status s = build(kv.second, ti, g.ts[ti], nullptr);
+          if (s != LBM_OK) return s;
+        }
+      }
+      gs.push_back(g);
+    }
+    return LBM_OK;
+  };
+  // at most one extra list per field beyond "all": keep the workspace bound
+  for (int f = 0; f < 4; ++f) {
+    std::vector<Group>& gs = f == 0 ? c->g_phi : f == 1 ? c->g_U : f == 2 ? c->g_T : c->g_F;
+    lbm_status s = make_groups(f, gs);
+    if (s != LBM_OK) {
+      lbm_destroy(c);
+      return fail(nullptr, LBM_EINVAL, "too many distinct update factors for one field (max 8)");
+    }
+  }
+  c->d_part = (Partial*)take(sizeof(Partial) * (size_t)tiles8);
+  c->d_slot = (int*)take(sizeof(int) * (size_t)tiles8);
+  for (int ti = 0; ti < 3; ++ti) c->d_slot0[ti] = (int*)take(sizeof(int) * (n + 1));
+  c->d_diag = (DiagOut*)take(sizeof(DiagOut) * n);
+  c->d_codes = (int*)take(sizeof(int) * kMaxCodes);
+  c->stage_elems = maxsites * 16;
+  c->d_stage = (double*)take(sizeof(double) * c->stage_elems);
+  if ((size_t)(cur - (char*)c->ws) > c->ws_bytes) {
+    lbm_destroy(c);
+    return fail(nullptr, LBM_ENOMEM, "internal: workspace layout overflow");
+  }
+  {
+    std::vector<int> slots((size_t)tiles8);
+    std::iota(slots.begin(), slots.end(), 0);
+    if (hipMemcpy(c->d_slot, slots.data(), sizeof(int) * slots.size(), hipMemcpyHostToDevice) != hipSuccess) {
+      lbm_destroy(c);
+      return fail(nullptr, LBM_EDEVICE, "slot upload failed");
+    }
+    for (int ti = 0; ti < 3; ++ti)
+      if (hipMemcpy(c->d_slot0[ti], slot0[ti].data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice) != hipSuccess) {
+        lbm_destroy(c);
+        return fail(nullptr, LBM_EDEVICE, "slot upload failed");
+      }
+    if (hipMemset(c->d_part, 0, sizeof(Partial) * (size_t)tiles8) != hipSuccess) {
+      lbm_destroy(c);
+      return fail(nullptr, LBM_EDEVICE, "partial clear failed");
+    }
+  }
+  if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
+    lbm_destroy(c);
+    return fail(nullptr, LBM_EDEVICE, "stream creation failed");
+  }
+  if (upload_doms(c) != LBM_OK) {
+    std::string m = c->err;
+    lbm_destroy(c);
+    return fail(nullptr, LBM_EDEVICE, m);
+  }
+  *out = c;
+  return LBM_OK;
+}
+
+lbm_status lbm_init_seeds(lbm_ctx* c, int32_t dom, int32_t n_seeds, const double* centres, const double* radii) {
+  if (!c) return LBM_EINVAL;
+  if (dom < 0 || dom >= c->ndom) return fail(c, LBM_EINVAL, "bad domain index");
+  if (n_seeds < 0 || n_seeds > MAX_SEEDS) return fail(c, LBM_EINVAL, "0..4 seeds per domain");
+  if (n_seeds > 0 && (!centres || !radii)) return fail(c, LBM_EINVAL, "NULL seed arrays");
+  HIPCHK(c, hipSetDevice(c->device));
+  Dom& D = c->H[dom];
+  D.nseeds = n_seeds;
+  for (int s = 0; s < n_seeds; ++s) {
+    D.seed[s][0] = centres[2 * s];
+    D.seed[s][1] = centres[2 * s + 1];
+    D.seed[s][2] = radii[s];
+  }
+  lbm_status st = upload_doms(c);
+  if (st != LBM_OK) return st;
+  c->ops.init(c->stream, c->d_dom, dom, (long long)D.nx * D.ny);
+  HIPCHK(c, hipGetLastError());
+  c->initialised[dom] = true;
+  c->k = 0;
+  return LBM_OK;
+}
+
+lbm_status lbm_configure(lbm_ctx* c, int32_t tile_rows, int32_t use_graph) {
+  if (!c) return LBM_EINVAL;
+  if (tile_rows == 0) {
+    c->autotune = true;
+    c->tuned = false;
+  } else {
+    int ti = tile_rows == 8 ? 0 : tile_rows == 16 ? 1 : tile_rows == 32 ? 2 : -1;
+    if (ti < 0) return fail(c, LBM_EINVAL, "tile_rows must be 0, 8, 16 or 32");
+    c->ty_index = ti;
+    c->autotune = false;
+    c->tuned = true;
+  }
+  c->use_graph = use_graph != 0;
+  return LBM_OK;
+}
+
+int64_t lbm_steps_done(const lbm_ctx* c) { return c ? c->k : -1; }
+
+static lbm_status run_diag(lbm_ctx* c, lbm_diag* out) {
+  const int ti = c->ty_index, TY = kTYs[ti];
+  c->ops.diag_tiles(TY, dim3(c->all[ti].n), c->stream, c->d_dom, c->all[ti].d, c->k, c->d_part);
+  diag_final(c->ndom, c->stream, c->d_dom, c->d_part, c->d_slot, c->d_slot0[ti], c->d_diag);
+  c->ops.tips(c->ndom, c->stream, c->d_dom, c->k, c->d_diag);
+  HIPCHK(c, hipGetLastError());
+  std::vector<DiagOut> h(c->ndom);
+  HIPCHK(c, hipMemcpyAsync(h.data(), c->d_diag, sizeof(DiagOut) * c->ndom, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  bool bad = false;
+  for (int d = 0; d < c->ndom; ++d) {
+    lbm_diag& o = out[d];
+    memset(&o, 0, sizeof o);
+    o.step = c->k;
+    o.solid = h[d].solid;
+    o.M_C = h[d].M_C;
+    o.enthalpy = h[d].enthalpy;
+    o.mass = h[d].mass;
+    o.S_phi = h[d].S_phi;
+    o.J_U = h[d].J_U;
+    for (int j = 0; j < 16; ++j) o.tip[j] = h[d].tip[j];
+    o.nonfinite = h[d].nonfinite;
+    bad |= h[d].nonfinite > 0;
+  }
+  if (bad) return fail(c, LBM_EUNSTABLE, "non-finite values in the state");
+  return LBM_OK;
+}
+
+lbm_status lbm_step_multirate(lbm_ctx* c, int64_t n, lbm_diag* diag) {
+  if (!c) return LBM_EINVAL;
+  if (n < 0) return fail(c, LBM_EINVAL, "negative step count");
+  for (int d = 0; d < c->ndom; ++d)
+    if (!c->initialised[d]) return fail(c, LBM_ESTATE, "lbm_init_seeds has not been called for every domain");
+  HIPCHK(c, hipSetDevice(c->device));
+  if (c->autotune && !c->tuned) {
+    lbm_status s = autotune(c);
+    if (s != LBM_OK) return s;
+  }
+  long long left = n;
+  while (left > 0) {
+    const bool graphable = c->use_graph && c->cycle <= kMaxGraphSteps;
+    if (graphable && c->k % c->cycle == 0 && left >= c->cycle) {
+      if (!c->gexec || c->graph_ty != c->ty_index) {
+        if (c->gexec) {
+          HIPCHK(c, hipGraphExecDestroy(c->gexec));
+          c->gexec = nullptr;
+        }
+        hipGraph_t g;
+        HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
+        for (long long j = 1; j <= c->cycle; ++j) launch_step(c, c->cap_stream, j);
+        HIPCHK(c, hipStreamEndCapture(c->cap_stream, &g));
+        hipError_t e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(g);
+        if (e != hipSuccess) return fail(c, LBM_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
+        c->graph_ty = c->ty_index;
+      }
+      HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
+      c->k += c->cycle;
+      left -= c->cycle;
+    } else {
+      launch_step(c, c->stream, c->k + 1);
+      c->k += 1;
+      left -= 1;
+    }
+  }
+  HIPCHK(c, hipGetLastError());
+  if (diag) return run_diag(c, diag);
+  return LBM_OK;
+}
+
+static int codes_for(const Dom& D, uint32_t mask, int* codes) {
+  int n = 0;
+  if (mask & LBM_F_PHI) codes[n++] = 0;
+  if (mask & LBM_F_U) codes[n++] = 1;
+  if (mask & LBM_F_T) codes[n++] = 2;
+  if (mask & LBM_F_RHO) codes[n++] = 3;
+  if (mask & LBM_F_VEL) { codes[n++] = 4; codes[n++] = 5; }
+  if (mask & LBM_F_POP_PHI) for (int q = 0; q < 5; ++q) codes[n++] = 10 + q;
+  if (mask & LBM_F_JU) { codes[n++] = 20; codes[n++] = 21; }
+  if (mask & LBM_F_JT) { codes[n++] = 30; codes[n++] = 31; }
+  if (mask & LBM_F_POP_F) for (int q = 0; q < 9; ++q) codes[n++] = 40 + q;
+  if (mask & LBM_F_PEND_U) codes[n++] = 50;
+  if (mask & LBM_F_PEND_T) codes[n++] = 51;
+  if (mask & LBM_F_SPHI) for (int q = 0; q < 4; ++q) codes[n++] = 60 + q;
+  if (mask & LBM_F_SF) for (int q = 0; q < 8; ++q) codes[n++] = 70 + q;
+  (void)D;
+  return n;
+}
+
+static std::string check_mask(const lbm_params& q, uint32_t mask) {
+  if (mask == 0 || mask >= (1u << 13)) return "empty or unknown field mask";
+  if ((mask & (LBM_F_U | LBM_F_JU | LBM_F_PEND_U)) && !q.has_U) return "domain carries no U field";
+  if ((mask & (LBM_F_T | LBM_F_JT | LBM_F_PEND_T)) && !q.has_T) return "domain carries no T field";
+  if ((mask & (LBM_F_RHO | LBM_F_VEL | LBM_F_POP_F | LBM_F_SF)) && !q.has_flow) return "domain carries no flow field";
+  return "";
+}
+
+lbm_status lbm_read_fields(lbm_ctx* c, int32_t dom, uint32_t mask, int32_t dst_is_device, int32_t dst_fp64,
+                           void* dst) {
+  if (!c) return LBM_EINVAL;
+  if (dom < 0 || dom >= c->ndom) return fail(c, LBM_EINVAL, "bad domain index");
+  if (!dst) return fail(c, LBM_EINVAL, "dst is NULL");
+  const std::string m = check_mask(c->P[dom], mask);
+  if (!m.empty()) return fail(c, LBM_EINVAL, m);
+  HIPCHK(c, hipSetDevice(c->device));
+  const Dom& D = c->H[dom];
+  int codes[kMaxCodes];
+  const int nc = codes_for(D, mask, codes);
+  const long long nsite = (long long)D.nx * D.ny;
+  HIPCHK(c, hipMemcpyAsync(c->d_codes, codes, sizeof(int) * nc, hipMemcpyHostToDevice, c->stream));
+  const size_t esz = dst_fp64 ? 8 : 4;
+  if (dst_is_device) {
+    c->ops.read(c->stream, c->d_dom, dom, c->k, c->d_codes, nc, dst_fp64, dst, nsite);
+    HIPCHK(c, hipGetLastError());
+    return LBM_OK;
+  }
+  // host destination: stage in chunks of at most 16 planes
+  for (int c0 = 0; c0 < nc; c0 += 16) {
+    const int cn = std::min(16, nc - c0);
+    c->ops.read(c->stream, c->d_dom, dom, c->k, c->d_codes + c0, cn, dst_fp64, c->d_stage, nsite);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipMemcpyAsync((char*)dst + (size_t)c0 * nsite * esz, c->d_stage, (size_t)cn * nsite * esz,
+                             hipMemcpyDeviceToHost, c->stream));
+  }
+  HIPCHK(c, hipStreamSynchronize(c->stream));
+  return LBM_OK;
+}
+
+lbm_status lbm_write_fields(lbm_ctx* c, int32_t dom, uint32_t mask, int32_t src_is_device, const void* src) {
+  if (!c) return LBM_EINVAL;
+  if (dom < 0 || dom >= c->ndom) return fail(c, LBM_EINVAL, "bad domain index");
+  if (!src) return fail(c, LBM_EINVAL, "src is NULL");
+  const std::string m = check_mask(c->P[dom], mask);
+  if (!m.empty()) return fail(c, LBM_EINVAL, m);
+  if ((mask & LBM_F_POP_PHI) && (mask & LBM_F_PHI))
+    return fail(c, LBM_EINVAL, "phi is the sum of the phase populations: pass one of the two");
+  if ((mask & LBM_F_POP_F) && (mask & (LBM_F_RHO | LBM_F_SF)))
+    return fail(c, LBM_EINVAL, "rho is the sum of the flow populations: pass one of the two");
+  if ((mask & LBM_F_POP_PHI) && (mask & LBM_F_SPHI))
+    return fail(c, LBM_EINVAL, "pass either the phase populations or the stored phase planes");
+  HIPCHK(c, hipSetDevice(c->device));
+  const Dom& D = c->H[dom];
+  int codes[kMaxCodes];
+  const int nc = codes_for(D, mask, codes);
+  const long long nsite = (long long)D.nx * D.ny;
+  HIPCHK(c, hipMemcpyAsync(c->d_codes, codes, sizeof(int) * nc, hipMemcpyHostToDevice, c->stream));
+  if (src_is_device) {
+    c->ops.write(c->stream, c->d_dom, dom, c->k, c->d_codes, nc, (const double*)src, nsite);
+    HIPCHK(c, hipGetLastError());
+    return LBM_OK;
+  }
+  // host source: stage chunks of at most 16 planes, never splitting the
+  // population groups (their planes are re-encoded together)
+  const int stage_planes = (int)(c->stage_elems / (size_t)nsite);
+  int c0 = 0;
+  while (c0 < nc) {
+    int c1 = c0;
+    while (c1 < nc) {
+      const int unit = (codes[c1] == 10) ? 5 : (codes[c1] == 40) ? 9 : 1;
+      if (c1 + unit - c0 > std::min(16, stage_planes)) break;
+      c1 += unit;
+    }
+    if (c1 == c0) return fail(c, LBM_EINVAL, "staging buffer too small for one field group");
+    HIPCHK(c, hipMemcpyAsync(c->d_stage, (const double*)src + (size_t)c0 * nsite,
+                             sizeof(double) * (size_t)(c1 - c0) * nsite, hipMemcpyHostToDevice, c->stream));
+    c->ops.write(c->stream, c->d_dom, dom, c->k, c->d_codes + c0, c1 - c0, c->d_stage, nsite);
+    HIPCHK(c, hipGetLastError());
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c0 = c1;
+  }
+  return LBM_OK;
+}
+
+const char* lbm_last_error(const lbm_ctx* c) { return c ? c->err.c_str() : g_create_error.c_str(); }
+
+void lbm_destroy(lbm_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  else (void)hipDeviceSynchronize();
+  if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+  if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
+  if (c->own_ws && c->ws) (void)hipFree(c->ws);
+  delete c;
+}
+
+}  // extern "C"

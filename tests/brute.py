@@ -51,7 +51,7 @@ def grad(a, x, y, bc):
 
 def aniso(d, gx, gy):
     gg = gx * gx + gy * gy
-    if gg < 1e-24:
+    if gg < 1e-16:
         return 1.0, 0.0, 0.0
     g = math.sqrt(gg)
     nx_, ny_ = -gx / g, -gy / g
@@ -143,7 +143,7 @@ def step(dom):
             for x in range(nx):
                 gx, gy = grad(phin, x, y, bc)
                 gg = gx * gx + gy * gy
-                if gg >= 1e-24:
+                if gg >= 1e-16:
                     g = math.sqrt(gg)
                     coef = 1 + (1 - d["k"]) * U[y, x]
                     Jx[y, x] = W0 / (2 * math.sqrt(2)) * coef * dphi[y, x] * (-gx / g)

@@ -1,0 +1,227 @@
+"""Parity of the HIP path (through the C ABI) with the FP64 oracle.
+
+FP64 storage/compute is compared element by element with the oracle at
+1e-12 relative L2 per field (the bar the method's FP64 path is held to).
+Grids are chosen to span several 64 x TY tiles with ragged tails in x and y.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import lbm_inputs as L
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 1e-300 else 1.0)
+
+
+def _gpu(wl, steps, storage="f64", names=("phi",), tile_rows=None, use_graph=True, domains=None):
+    from paper_2609_25670_amd import simulation_for
+
+    sim = simulation_for(wl, storage=storage)
+    if tile_rows is not None:
+        sim.configure(tile_rows, use_graph)
+    diag = sim.step(steps, diag=True)
+    outs = [sim.read(i, names) for i in (domains if domains is not None else range(sim.n))]
+    sim.close()
+    return outs, diag
+
+
+def _oracle_fields(dom, names):
+    out = {}
+    for n in names:
+        if n == "phi":
+            out[n] = dom.phi
+        elif n == "U":
+            out[n] = dom.U
+        elif n == "T":
+            out[n] = dom.T
+        elif n == "rho":
+            out[n] = dom.rho
+        elif n == "vel":
+            out[n] = dom.u
+        elif n == "f_phi":
+            out[n] = dom.f_phi
+        elif n == "jU":
+            out[n] = dom.moments("U")[1]
+        elif n == "jT":
+            out[n] = dom.moments("T")[1]
+        elif n == "f_F":
+            out[n] = dom.f_F
+        elif n == "P_U":
+            out[n] = dom.P_U
+    return out
+
+
+def _compare(case, got, ref, tol):
+    for name, r in ref.items():
+        e = _rel(got[name], r)
+        _say(f"  {case}: {name} rel L2 = {e:.3e}")
+        assert e <= tol, (case, name, e)
+
+
+def test_thermal_128_full_run_fp64():
+    """2D thermal dendrite 128^2 periodic, phi + T, 1000 steps."""
+    wl = L.thermal_128()
+    names = ("phi", "T", "f_phi", "jT")
+    _say("case thermal_128 fp64 1000 steps")
+    (got,), diag = _gpu(wl, 1000, names=names)
+    dom = oracle.run(wl["domains"][0], 1000)
+    _compare("thermal_128", got, _oracle_fields(dom, names), TOL64)
+    t = oracle.diag.totals(dom)
+    assert abs(diag[0]["enthalpy"] - t["enthalpy"]) < 1e-9 * abs(t["enthalpy"])
+    assert abs(diag[0]["solid"] - t["solid"]) < 1e-9 * abs(t["solid"])
+    tips = oracle.diag.tips(dom)[0]
+    assert np.allclose(diag[0]["tip"][:4], tips, atol=1e-9)
+
+
+def test_solutal_reduced_fp64_ragged_tiles():
+    """2D solutal dendrite (N_U = 4, zero-flux) on 150 x 70."""
+    wl = L.reduced(L.solutal_512(), 150, 70)
+    names = ("phi", "U", "f_phi", "jU")
+    _say("case solutal 150x70 fp64 600 steps")
+    (got,), diag = _gpu(wl, 600, names=names)
+    dom = oracle.run(wl["domains"][0], 600)
+    _compare("solutal", got, _oracle_fields(dom, names), TOL64)
+    t = oracle.diag.totals(dom)
+    assert abs(diag[0]["M_C"] - t["M_C"]) < 1e-10 * t["M_C"]
+    assert abs(diag[0]["S_phi"] - t["S_phi"]) < 1e-10 * t["S_phi"]
+
+
+def test_thermosolutal_flow_reduced_fp64():
+    """All four fields, N = 1:1:4:2, rotated seed, inlet/outflow flow."""
+    wl = L.reduced(L.thermosolutal_flow_1024(), 150, 90)
+    d = wl["domains"][0]
+    d["seeds"] = [(75.0, 44.0, 12.0)]
+    d["tau0"] = 40.0          # faster phase dynamics so 300 steps exercise the coupling
+    d["u_in"] = 0.02
+    names = ("phi", "U", "T", "rho", "vel", "f_phi", "jU", "jT", "f_F")
+    _say("case thermosolutal_flow 150x90 fp64 300 steps")
+    (got,), diag = _gpu(wl, 300, names=names)
+    dom = oracle.run(d, 300)
+    _compare("thermosolutal_flow", got, _oracle_fields(dom, names), TOL64)
+
+
+def test_accumulated_coupling_fp64():
+    """The delayed coarse-step injection variant (pending planes)."""
+    wl = L.reduced(L.solutal_512(), 100, 80)
+    wl["domains"][0]["coupling"] = "accum"
+    names = ("phi", "U", "jU", "P_U")
+    _say("case accumulated coupling 100x80 fp64 402 steps")
+    (got,), diag = _gpu(wl, 402, names=names)
+    dom = oracle.run(wl["domains"][0], 402)
+    _compare("accum", got, _oracle_fields(dom, ("phi", "U", "jU")), TOL64)
+    assert _rel(got["P_U"], dom.P_U) < 1e-11
+    assert abs(diag[0]["J_U"] - dom.J_U) <= 1e-10 * dom.J_U
+
+
+@pytest.mark.parametrize("use_graph", [True, False])
+def test_batched_uneven_domains_fp64(use_graph):
+    """Five independent domains of uneven sizes with different update factors
+    (Le = N_U in {1, 10, 100, 1000}) and variable thermal properties, in one
+    context; each equals its own oracle run."""
+    wl = L.ensemble_256(n_domains=5, side_lo=40, side_hi=100)
+    for i, d in enumerate(wl["domains"]):
+        d["tau0"] = 30.0
+        Le = [1, 10, 1, 10, 2][i]
+        d["N_U"] = Le
+        d["D_L"] = 0.026 / Le
+        d["D_S"] = 1e-2 * d["D_L"]
+    names = ("phi", "U", "T")
+    steps = 420
+    _say(f"case batched 5 domains fp64 {steps} steps graph={use_graph}")
+    gots, diag = _gpu(wl, steps, names=names, tile_rows=16, use_graph=use_graph)
+    for i, d in enumerate(wl["domains"]):
+        dom = oracle.run(d, steps)
+        _compare(f"domain{i}", gots[i], _oracle_fields(dom, names), TOL64)
+
+
+def test_tile_shapes_and_graph_are_bitwise_identical():
+    """Race detector: every tile height and graph replay versus eager
+    launches give bitwise-identical FP64 state."""
+    wl = L.reduced(L.thermosolutal_flow_1024(), 130, 75)
+    wl["domains"][0]["tau0"] = 40.0
+    names = ("phi", "U", "T", "rho", "vel", "f_phi", "jU", "jT", "f_F")
+    ref = None
+    for rows in (8, 16, 32):
+        for g in (True, False):
+            _say(f"case determinism rows={rows} graph={g}")
+            (got,), _ = _gpu(wl, 64, names=names, tile_rows=rows, use_graph=g)
+            if ref is None:
+                ref = got
+            else:
+                for n in names:
+                    assert np.array_equal(got[n], ref[n]), (rows, g, n)
+
+
+def test_checkpoint_restore_is_bitwise():
+    """Read the full state, write it into a fresh context, continue: equal
+    to the uninterrupted run, bit for bit."""
+    from paper_2609_25670_amd import simulation_for
+
+    wl = L.reduced(L.thermosolutal_flow_1024(), 100, 70)
+    wl["domains"][0]["tau0"] = 40.0
+    _say("case checkpoint")
+    a = simulation_for(wl, storage="f64")
+    a.configure(16, True)
+    a.step(40)
+    snap = a.read(0, a.state_names())
+    a.step(24)
+    ref = a.read(0, ("phi", "U", "T", "rho", "vel"))
+    a.close()
+    b = simulation_for(wl, storage="f64")
+    b.configure(16, True)
+    b.step(40)                       # same step counter (same buffer parity)
+    b.write(0, {k: v for k, v in snap.items()})
+    b.step(24)
+    got = b.read(0, ("phi", "U", "T", "rho", "vel"))
+    b.close()
+    for n in ref:
+        assert np.array_equal(got[n], ref[n]), n
+
+
+def test_nonfinite_state_is_reported():
+    """A NaN written into U is caught by the diagnostics: the step call
+    returns LBM_EUNSTABLE and the count is reported."""
+    from paper_2609_25670_amd import lbm, simulation_for
+
+    wl = L.reduced(L.solutal_512(), 80, 70)
+    _say("case nonfinite detection")
+    sim = simulation_for(wl, storage="f32")
+    sim.step(4)
+    U = sim.read(0, ("U",))["U"].copy()
+    U[30, 40] = np.nan
+    sim.write(0, {"U": U})
+    with pytest.raises(lbm.LBMError) as ei:
+        sim.step(4, diag=True)
+    assert ei.value.status == lbm.LBM_EUNSTABLE
+    assert ei.value.diag[0]["nonfinite"] > 0
+    sim.close()
+
+
+def test_solutal_full_size_bench_configuration_fp32():
+    """512 x 512 solutal case exactly as the benchmark launches it (FP32,
+    autotuned tiles, graph replay) for two whole cycles against the oracle
+    on the full grid, at the FP32 tolerance."""
+    wl = L.solutal_512()
+    names = ("phi", "U")
+    _say("case solutal_512 full size fp32 8 steps")
+    (got,), _ = _gpu(wl, 8, storage="f32", names=names)
+    dom = oracle.run(wl["domains"][0], 8)
+    for n in names:
+        e = _rel(got[n], getattr(dom, n))
+        _say(f"  solutal_512: {n} rel L2 = {e:.3e}")
+        assert e < 2e-6, (n, e)
