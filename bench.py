@@ -1,0 +1,258 @@
+#!/usr/bin/env python
+"""Throughput of the multirate coupled-field step on one MI355X.
+
+A bench "step" is one multirate cycle: lcm(N_chi) base steps, in which every
+kernel of the hot path (phase collision + anisotropic streaming, phase-step
+transfer, each scalar transport, flow) runs at least once.  The default
+workload is the 2D isothermal solutal dendrite on 512 x 512 with FP32
+arithmetic and storage, N_phi : N_U = 1 : 4.
+
+    python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
+
+Prints one JSON line.  ``value`` is coupled-field MLUPS
+(sites x base steps / wall time).  ``roofline`` describes the kernel with the
+largest share of device time per base step: its algorithmic bytes per launch
+divided by its average launch time, measured with HIP events on the stream
+the library issues its work on.  ``cpu_baseline`` times the FP64 oracle on
+a bounded sample of the same workload on one host core.
+"""
+
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import platform
+import subprocess
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("coupled-field MLUPS + % HBM peak; FP32/FP16-store vs FP64 at stated tip-velocity error")
+HBM_PEAK_GBS = 8000.0
+STORAGE_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
+KERNEL_SOURCES = [os.path.join(ROOT, "paper_2609_25670_amd", "csrc", f)
+                  for f in ("lbm_kernels.hip", "lbm_dev.h")]
+KERNEL_NAMES = {"phase": "k_phase", "transfer": "k_transfer", "U": "k_scalar<..., 0>",
+                "T": "k_scalar<..., 1>", "flow": "k_flow"}
+
+
+def kernel_source_sha() -> str:
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def algorithmic_bytes(kind: str, d: dict, storage: str) -> int:
+    """Compulsory HBM bytes per site of one launch of a kernel kind: every
+    plane the kernel must read once and write once for the representation
+    it keeps (stencil and halo re-reads excluded)."""
+    s = STORAGE_BYTES[storage]
+    r = 8 if storage == "f64" else 4
+    U, T, F = int(d["has_U"]), int(d["has_T"]), int(d["has_flow"])
+    acc = d.get("coupling", "instant") == "accum"
+    if kind == "phase":      # s_1..s_4 in/out, phi in/out, U*, T*
+        return 8 * s + (2 + U + T) * r
+    if kind == "transfer":   # phi^q, phi^{q+1}; U in/out (or pending), T in place
+        return (2 + 2 * U + 2 * T) * r
+    if kind == "U":          # U, j_U, phi*, [u]; U, j_U out; [pending]
+        return (3 + 2 * F + 2 * acc) * r + 4 * s
+    if kind == "T":
+        tvar = d["kappa_S"] != d["kappa_L"] or d["rhoCp_S"] != d["rhoCp_L"]
+        return (2 + int(tvar) + 2 * F + 2 * acc) * r + 4 * s
+    if kind == "flow":       # rho, s_1..s_8, phi* in; rho, s_1..s_8, u out
+        return 5 * r + 16 * s
+    raise ValueError(kind)
+
+
+def cycle_of(wl: dict) -> int:
+    L = 1
+    for d in wl["domains"]:
+        for key, flag in (("N_phi", True), ("N_U", d["has_U"]), ("N_T", d["has_T"]), ("N_F", d["has_flow"])):
+            if flag:
+                L = L * d[key] // math.gcd(L, d[key])
+    return L
+
+
+def traffic_from_profiles(workload: str, kind: str, sha: str):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if
+    it was taken on the current kernel source; else None."""
+    path = os.path.join(ROOT, "profiles", f"counters_{KERNEL_NAMES[kind].split('<')[0]}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_source_sha") != sha:
+        return None
+    return rec.get("hbm_bytes_per_dispatch")
+
+
+def cpu_baseline(workload: str, steps: int) -> dict:
+    """Time the FP64 oracle on one host core for ``steps`` base steps of the
+    workload (run in a child process pinned to one BLAS/OpenMP thread)."""
+    env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-child", "--workload", workload,
+           "--cpu-steps", str(steps)]
+    out = subprocess.run(cmd, env=env, capture_output=True, text=True, check=True).stdout
+    return json.loads(out.strip().splitlines()[-1])
+
+
+def cpu_child(workload: str, steps: int) -> None:
+    import lbm_inputs as L
+    import oracle
+
+    wl = L.workload(workload)
+    sites = sum(d["nx"] * d["ny"] for d in wl["domains"][:1])
+    dom = oracle.Domain(wl["domains"][0])
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        dom.step()
+    dt = time.perf_counter() - t0
+    print(json.dumps(dict(seconds=dt, steps=steps, sites=sites, mlups=sites * steps / dt / 1e6)))
+
+
+def main() -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5000)
+    ap.add_argument("--warmup", type=int, default=250)
+    ap.add_argument("--workload", default="solutal_512")
+    ap.add_argument("--storage", default=None, help="override the workload's population storage")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-steps", type=int, default=384)
+    ap.add_argument("--cpu-child", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device-to-device copy of BYTES (counter calibration)")
+    args = ap.parse_args()
+
+    if args.cpu_child:
+        cpu_child(args.workload, args.cpu_steps)
+        return 0
+    if args.copy_probe:
+        import torch
+
+        n = args.copy_probe // 4
+        a = torch.ones(n, dtype=torch.float32, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps(dict(copy_probe_bytes=n * 4, reps=3)), flush=True)
+        return 0
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); "
+              "a multi-GPU run is not part of it", file=sys.stderr)
+        return 2
+    rank = int(os.environ.get("RANK", "0"))
+
+    import torch
+
+    import lbm_inputs as L
+    from paper_2609_25670_amd import simulation_for
+
+    wl = L.workload(args.workload)
+    storage = args.storage or wl["storage"]
+    cyc = cycle_of(wl)
+    sites = sum(d["nx"] * d["ny"] for d in wl["domains"])
+    sim = simulation_for(wl, storage=storage)
+    # warm-up: autotune, graph capture, clocks
+    sim.step(args.warmup * cyc)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    sim.step(args.steps * cyc)
+    ev1.record()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    ev_ms = ev0.elapsed_time(ev1)
+    diag = sim.step(0, diag=True)
+    finite = all(dd["nonfinite"] == 0 for dd in diag)
+    base_steps = args.steps * cyc
+    mlups = sites * base_steps / wall / 1e6
+
+    # per-kernel launch times (HIP events on the library's stream)
+    kt = sim.kernel_times(reps=200)
+    sim.close()
+    d0 = wl["domains"][0]
+    per_kind = {}
+    for kind, (ms, per) in kt.items():
+        nbytes = algorithmic_bytes(kind, d0, storage) * sites
+        per_kind[kind] = dict(ms_per_launch=ms, launches_per_base_step=per,
+                              alg_bytes_per_launch=nbytes,
+                              alg_GBs=nbytes / (ms * 1e-3) / 1e9 if ms > 0 else None,
+                              share_ms_per_base_step=ms * per)
+    dom_kind = max(per_kind, key=lambda k: per_kind[k]["share_ms_per_base_step"])
+    dk = per_kind[dom_kind]
+    sha = kernel_source_sha()
+    traffic = traffic_from_profiles(args.workload, dom_kind, sha)
+    achieved = dk["alg_GBs"]
+    bytes_per_base_step = sum(algorithmic_bytes(k, d0, storage) * v["launches_per_base_step"]
+                              for k, v in per_kind.items())   # per site
+
+    result = {
+        "metric": METRIC,
+        "value": round(mlups, 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if storage == "f64" else "f32",
+        "data": "synthetic",
+        "config": {
+            "workload": wl["name"],
+            "grid": [d0["nx"], d0["ny"]] if len(wl["domains"]) == 1 else f"{len(wl['domains'])} domains",
+            "sites": sites,
+            "fields": "+".join(["phi"] + [f for f, k in (("U", "has_U"), ("T", "has_T"), ("flow", "has_flow"))
+                                          if d0[k]]),
+            "update_factors": {k: d0[k] for k in ("N_phi", "N_U", "N_T", "N_F")},
+            "storage": storage,
+            "base_steps_per_step": cyc,
+            "parallelism": "single_gpu",
+        },
+        "roofline": {
+            "bound": "hbm",
+            "kernel": KERNEL_NAMES[dom_kind],
+            "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "traffic": traffic,
+        },
+        "kernels": {k: {kk: (round(vv, 6) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                    for k, v in per_kind.items()},
+        "alg_bytes_per_site_per_base_step": bytes_per_base_step,
+        "event_ms_timed_region": ev_ms,
+        "finite": finite,
+    }
+    if rank == 0 and not args.no_cpu_baseline:
+        cb = cpu_baseline(args.workload, args.cpu_steps)
+        result["cpu_baseline"] = {
+            "value": round(cb["mlups"], 4),
+            "unit": "MLUPS",
+            "cores": 1,
+            "kind": "oracle",
+            "sample": (f"FP64 NumPy oracle, first domain of {wl['name']} "
+                       f"({wl['domains'][0]['nx']}x{wl['domains'][0]['ny']}), {cb['steps']} base steps, "
+                       f"{cb['seconds']:.1f} s on one core of {platform.processor() or platform.machine()}"),
+        }
+    if rank == 0:
+        print(json.dumps(result), flush=True)
+    return 0 if finite else 1
+
+
+if __name__ == "__main__":
+    sys.exit(main())

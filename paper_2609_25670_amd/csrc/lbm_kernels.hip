@@ -118,10 +118,41 @@ __device__ __forceinline__ void phase_collide(const PhaseConst<R>& c, R phi, R g
   Ky = jey + om * (jy - jey);
 }
 
+// Ring cell r of the collision box of a w x h tile (box cells (lx, ly) in
+// [0, w+1] x [0, h+1], the tile being 1..w x 1..h): top row, bottom row,
+// left column, right column.  There are 2 (w + 2) + 2 h <= 196 of them, so
+// every thread of a block handles at most one.
+__device__ __forceinline__ bool ring_cell(int r, int w, int h, int& lx, int& ly) {
+  const int W2 = w + 2;
+  if (r < W2) { lx = r; ly = 0; return true; }
+  r -= W2;
+  if (r < W2) { lx = r; ly = h + 1; return true; }
+  r -= W2;
+  if (r < h) { lx = 0; ly = 1 + r; return true; }
+  r -= h;
+  if (r < h) { lx = w + 1; ly = 1 + r; return true; }
+  return false;
+}
+
+// Load the tile's field plane plus two rings (ghosts wrapped or mirrored)
+// into LDS.  Issued before the first barrier together with every other
+// global load of the block, so a block waits for memory once.
+template <class R>
+__device__ __forceinline__ void load_box2(R* box, const R* __restrict__ plane, long long px, int x0, int y0,
+                                          int nx, int ny, int bcx, int bcy, int BW, int BH, int tid) {
+  for (int i = tid; i < BW * BH; i += NTHR) {
+    const int lx = i % BW, ly = i / BW;
+    const int gx = ghost(x0 - 2 + lx, nx, bcx), gy = ghost(y0 - 2 + ly, ny, bcy);
+    box[i] = plane[gy * px + gx];
+  }
+}
+
+// =================================================================== phase kernel
 template <class R, class S, int TY>
 __global__ __launch_bounds__(NTHR) void k_phase(const Dom* __restrict__ doms, const int4* __restrict__ tiles,
                                                  long long k) {
   constexpr int RPT = TY / BY;
+  constexpr int NS = RPT + 1;  // owned sites + one ring cell per thread
   constexpr int BW = TX + 4, BH = TY + 4;
   constexpr int CW = TX + 2, CH = TY + 2;
   __shared__ R sphi[BH * BW];
@@ -134,6 +165,7 @@ __global__ __launch_bounds__(NTHR) void k_phase(const Dom* __restrict__ doms, co
   const int nx = D.nx, ny = D.ny;
   const long long px = D.px, pl = D.plane;
   const int x0 = t.y, y0 = t.z;
+  const int w = min(TX, nx - x0), h = min(TY, ny - y0);
   const int bcx = D.bc[0], bcy = D.bc[1];
   const int ib = par(n_phi(D, k - 1)), ob = ib ^ 1;
   const R* __restrict__ phi_in = (const R*)D.phi[ib];
@@ -158,73 +190,70 @@ __global__ __launch_bounds__(NTHR) void k_phase(const Dom* __restrict__ doms, co
   c.theta_off = R(D.T_m + D.m_L * D.C_inf);
 
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
-  // phi on the tile plus two rings (ghost values wrapped or mirrored)
-  for (int i = tid; i < BW * BH; i += NTHR) {
-    const int lx = i % BW, ly = i / BW;
-    const int gx = ghost(x0 - 2 + lx, nx, bcx), gy = ghost(y0 - 2 + ly, ny, bcy);
-    sphi[i] = phi_in[gy * px + gx];
+  // sites of this thread: RPT owned sites, then at most one ring cell
+  int cl[NS];                 // collision-box index (-1: inactive)
+  R sv[NS][4], Uv[NS], Tv[NS];
+#pragma unroll
+  for (int r = 0; r < NS; ++r) {
+    int lx, ly, gx, gy;
+    cl[r] = -1;
+    if (r < RPT) {
+      lx = tx + 1;
+      ly = ty + r * BY + 1;
+      if (tx >= w || ly > h) continue;
+      gx = x0 + tx;
+      gy = y0 + ly - 1;
+    } else {
+      if (!ring_cell(tid, w, h, lx, ly)) continue;
+      gx = resolve(x0 - 1 + lx, nx, bcx);
+      gy = resolve(y0 - 1 + ly, ny, bcy);
+      if (gx < 0 || gy < 0) continue;  // beyond a wall: never pulled from
+    }
+    cl[r] = ly * CW + lx;
+    const long long o = gy * px + gx;
+    sv[r][0] = ld(s_in, o);
+    sv[r][1] = ld(s_in, o + pl);
+    sv[r][2] = ld(s_in, o + 2 * pl);
+    sv[r][3] = ld(s_in, o + 3 * pl);
+    Uv[r] = Up ? Up[o] : R(0);
+    Tv[r] = Tp ? Tp[o] : c.theta_off;
   }
+  load_box2(sphi, phi_in, px, x0, y0, nx, ny, bcx, bcy, BW, BH, tid);
   __syncthreads();
 
-  // owned sites: collide, keep pre-collision populations in registers
   R f[RPT][5];
   R Aown[RPT];
-  bool own[RPT];
 #pragma unroll
-  for (int r = 0; r < RPT; ++r) {
-    const int ly = ty + r * BY, gx = x0 + tx, gy = y0 + ly;
-    own[r] = gx < nx && gy < ny;
-    if (!own[r]) continue;
-    const long long o = gy * px + gx;
-    const R* b = &sphi[(ly + 2) * BW + tx + 2];
-    const R phi = b[0];
-    const R s1 = ld(s_in, o), s2 = ld(s_in, o + pl), s3 = ld(s_in, o + 2 * pl), s4 = ld(s_in, o + 3 * pl);
-    f[r][1] = phi * R(1.0 / 6.0) + s1;
-    f[r][2] = phi * R(1.0 / 6.0) + s2;
-    f[r][3] = phi * R(1.0 / 6.0) + s3;
-    f[r][4] = phi * R(1.0 / 6.0) + s4;
-    f[r][0] = phi * R(1.0 / 3.0) - (s1 + s2 + s3 + s4);
-    R gx_, gy_;
-    iso_grad(b, BW, gx_, gy_);
-    const R Us = Up ? Up[o] : R(0);
-    const R Ts = Tp ? Tp[o] : c.theta_off;
-    R P, Kx, Ky, A;
-    phase_collide(c, phi, gx_, gy_, s1 - s3, s2 - s4, Us, Ts, P, Kx, Ky, A);
-    const int ci = (ly + 1) * CW + tx + 1;
-    sP[ci] = P;
-    sKx[ci] = Kx;
-    sKy[ci] = Ky;
-    Aown[r] = A;
-  }
-  // halo collisions (ring cells, wrapped across periodic edges)
-  for (int i = tid; i < CW * CH; i += NTHR) {
-    const int lx = i % CW, ly = i / CW;
-    const int rx = x0 - 1 + lx, ry = y0 - 1 + ly;
-    if (lx >= 1 && lx <= TX && ly >= 1 && ly <= TY && rx < nx && ry < ny) continue;
-    const int gx = resolve(rx, nx, bcx), gy = resolve(ry, ny, bcy);
-    if (gx < 0 || gy < 0) continue;
-    const long long o = gy * px + gx;
+  for (int r = 0; r < NS; ++r) {
+    if (cl[r] < 0) continue;
+    const int lx = cl[r] % CW, ly = cl[r] / CW;
     const R* b = &sphi[(ly + 1) * BW + lx + 1];
     const R phi = b[0];
-    const R s1 = ld(s_in, o), s2 = ld(s_in, o + pl), s3 = ld(s_in, o + 2 * pl), s4 = ld(s_in, o + 3 * pl);
     R gx_, gy_;
     iso_grad(b, BW, gx_, gy_);
-    const R Us = Up ? Up[o] : R(0);
-    const R Ts = Tp ? Tp[o] : c.theta_off;
     R P, Kx, Ky, A;
-    phase_collide(c, phi, gx_, gy_, s1 - s3, s2 - s4, Us, Ts, P, Kx, Ky, A);
-    sP[i] = P;
-    sKx[i] = Kx;
-    sKy[i] = Ky;
+    phase_collide(c, phi, gx_, gy_, sv[r][0] - sv[r][2], sv[r][1] - sv[r][3], Uv[r], Tv[r], P, Kx, Ky, A);
+    sP[cl[r]] = P;
+    sKx[cl[r]] = Kx;
+    sKy[cl[r]] = Ky;
+    if (r < RPT) {
+      const R w6 = phi * R(1.0 / 6.0);
+      f[r][1] = w6 + sv[r][0];
+      f[r][2] = w6 + sv[r][1];
+      f[r][3] = w6 + sv[r][2];
+      f[r][4] = w6 + sv[r][3];
+      f[r][0] = phi * R(1.0 / 3.0) - (sv[r][0] + sv[r][1] + sv[r][2] + sv[r][3]);
+      Aown[r] = A;
+    }
   }
   __syncthreads();
 
   // anisotropic pull streaming (Eq. 26) into owned sites
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
-    if (!own[r]) continue;
-    const int ly = ty + r * BY, gx = x0 + tx, gy = y0 + ly;
-    const int ci = (ly + 1) * CW + tx + 1;
+    if (cl[r] < 0) continue;
+    const int ci = cl[r];
+    const int gx = x0 + tx, gy = y0 + ty + r * BY;
     const R A = Aown[r], iA = R(1) / A, oA = R(1) - A;
     const R Po = sP[ci], Kxo = sKx[ci], Kyo = sKy[ci];
     R fn[5];
@@ -246,11 +275,11 @@ __global__ __launch_bounds__(NTHR) void k_phase(const Dom* __restrict__ doms, co
     const R phin = fn[0] + fn[1] + fn[2] + fn[3] + fn[4];
     const long long o = gy * px + gx;
     phi_out[o] = phin;
-    const R w = phin * R(1.0 / 6.0);
-    st(s_out, o, fn[1] - w);
-    st(s_out, o + pl, fn[2] - w);
-    st(s_out, o + 2 * pl, fn[3] - w);
-    st(s_out, o + 3 * pl, fn[4] - w);
+    const R w6 = phin * R(1.0 / 6.0);
+    st(s_out, o, fn[1] - w6);
+    st(s_out, o + pl, fn[2] - w6);
+    st(s_out, o + 2 * pl, fn[3] - w6);
+    st(s_out, o + 3 * pl, fn[4] - w6);
   }
 }
 
@@ -268,6 +297,7 @@ template <class R, int TY>
 __global__ __launch_bounds__(NTHR) void k_transfer(const Dom* __restrict__ doms, const int4* __restrict__ tiles,
                                                     long long k, Partial* __restrict__ part) {
   constexpr int RPT = TY / BY;
+  constexpr int NS = RPT + 1;
   constexpr int BW = TX + 4, BH = TY + 4;
   constexpr int CW = TX + 2, CH = TY + 2;
   __shared__ R sphi[BH * BW];
@@ -281,6 +311,7 @@ __global__ __launch_bounds__(NTHR) void k_transfer(const Dom* __restrict__ doms,
   const int nx = D.nx, ny = D.ny;
   const long long px = D.px;
   const int x0 = t.y, y0 = t.z;
+  const int w = min(TX, nx - x0), h = min(TY, ny - y0);
   const int bcx = D.bc[0], bcy = D.bc[1];
   const R* __restrict__ phi_old = (const R*)D.phi[par(n_phi(D, k - 1))];
   const R* __restrict__ phi_new = (const R*)D.phi[par(n_phi(D, k))];
@@ -288,91 +319,123 @@ __global__ __launch_bounds__(NTHR) void k_transfer(const Dom* __restrict__ doms,
   const R* __restrict__ Uin = D.has_U ? (const R*)D.U[par(nU)] : nullptr;
   R* __restrict__ Uout = D.has_U ? (R*)D.U[par(nU + 1)] : nullptr;
   R* __restrict__ Tcur = D.has_T ? (R*)D.T[par(n_T(D, k - 1))] : nullptr;
+  R* __restrict__ PU = (R*)D.PU;
+  R* __restrict__ PT = (R*)D.PT;
   const R omk = R(1.0 - D.kc), opk = R(1.0 + D.kc);
   const R cJ = R(D.W0 / (2.0 * 1.4142135623730951));
+  const R cT = R(D.rho_L * D.L_h);
+  const R rcS = R(D.rcS), rcL = R(D.rcL);
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
-  R amax = R(0);
 
-  if (D.has_U) {
-    for (int i = tid; i < BW * BH; i += NTHR) {
-      const int lx = i % BW, ly = i / BW;
-      const int gx = ghost(x0 - 2 + lx, nx, bcx), gy = ghost(y0 - 2 + ly, ny, bcy);
-      sphi[i] = phi_new[gy * px + gx];
-    }
-    __syncthreads();
-    for (int i = tid; i < CW * CH; i += NTHR) {
-      const int lx = i % CW, ly = i / CW;
-      int rx = x0 - 1 + lx, ry = y0 - 1 + ly;
-      // a ghost across a wall takes the mirrored value of the wall node
-      bool mx = false, my = false;
-      if (rx < 0 && bcx != BC_PER) { rx = 0; mx = true; }
-      if (rx >= nx && bcx != BC_PER) { rx = nx - 1; mx = true; }
-      if (ry < 0 && bcy != BC_PER) { ry = 0; my = true; }
-      if (ry >= ny && bcy != BC_PER) { ry = ny - 1; my = true; }
-      const int gx = ghost(rx, nx, bcx), gy = ghost(ry, ny, bcy);
+  if (!D.has_U) {
+    // latent heat only: an own-site update, no stencil
+    if (!D.has_T) return;
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      const int gx = x0 + tx, gy = y0 + ty + r * BY;
+      if (tx >= w || ty + r * BY >= h) continue;
       const long long o = gy * px + gx;
-      const R* b = &sphi[(ry - (y0 - 2)) * BW + rx - (x0 - 2)];
-      R gxv, gyv;
-      iso_grad(b, BW, gxv, gyv);
-      const R gg = gxv * gxv + gyv * gyv;
-      R Jx = R(0), Jy = R(0);
-      if (gg >= R(GRAD_EPS2)) {
-        const R ig = R(1) / sqrt(gg);
-        const R dphi = b[0] - phi_old[o];
-        const R a = cJ * (R(1) + omk * Uin[o]) * dphi * ig;
-        Jx = -a * gxv;
-        Jy = -a * gyv;
-      }
-      sJx[i] = mx ? -Jx : Jx;
-      sJy[i] = my ? -Jy : Jy;
+      const R pn = phi_new[o];
+      const R dphi = pn - phi_old[o];
+      const R rc = (R(1) + pn) * R(0.5) * rcS + (R(1) - pn) * R(0.5) * rcL;
+      const R dT = cT * dphi / (R(2) * rc);
+      if (D.accum)
+        PT[o] = PT[o] + dT;
+      else
+        Tcur[o] = Tcur[o] + dT;
     }
-    __syncthreads();
+    return;
   }
 
+  // J on the owned sites and the ring (ghosts across walls mirror the wall
+  // node with the normal component negated)
+  int cl[NS], bi[NS];
+  bool mxs[NS], mys[NS];
+  R pold[NS], Us[NS], Tv[RPT];
+#pragma unroll
+  for (int r = 0; r < NS; ++r) {
+    int lx, ly;
+    cl[r] = -1;
+    if (r < RPT) {
+      lx = tx + 1;
+      ly = ty + r * BY + 1;
+      if (tx >= w || ly > h) continue;
+    } else {
+      if (!ring_cell(tid, w, h, lx, ly)) continue;
+    }
+    int rx = x0 - 1 + lx, ry = y0 - 1 + ly;
+    bool mx = false, my = false;
+    if (rx < 0 && bcx != BC_PER) { rx = 0; mx = true; }
+    if (rx >= nx && bcx != BC_PER) { rx = nx - 1; mx = true; }
+    if (ry < 0 && bcy != BC_PER) { ry = 0; my = true; }
+    if (ry >= ny && bcy != BC_PER) { ry = ny - 1; my = true; }
+    cl[r] = ly * CW + lx;
+    bi[r] = (ry - (y0 - 2)) * BW + rx - (x0 - 2);
+    mxs[r] = mx;
+    mys[r] = my;
+    const long long o = (long long)ghost(ry, ny, bcy) * px + ghost(rx, nx, bcx);
+    pold[r] = phi_old[o];
+    Us[r] = Uin[o];
+    if (r < RPT && D.has_T) Tv[r] = D.accum ? PT[o] : Tcur[o];
+  }
+  load_box2(sphi, phi_new, px, x0, y0, nx, ny, bcx, bcy, BW, BH, tid);
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < NS; ++r) {
+    if (cl[r] < 0) continue;
+    const R* b = &sphi[bi[r]];
+    R gxv, gyv;
+    iso_grad(b, BW, gxv, gyv);
+    const R gg = gxv * gxv + gyv * gyv;
+    R Jx = R(0), Jy = R(0);
+    if (gg >= R(GRAD_EPS2)) {
+      const R ig = R(1) / sqrt(gg);
+      const R a = cJ * (R(1) + omk * Us[r]) * (b[0] - pold[r]) * ig;
+      Jx = -a * gxv;
+      Jy = -a * gyv;
+    }
+    sJx[cl[r]] = mxs[r] ? -Jx : Jx;
+    sJy[cl[r]] = mys[r] ? -Jy : Jy;
+  }
+  __syncthreads();
+
+  R amax = R(0);
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
-    const int ly = ty + r * BY, gx = x0 + tx, gy = y0 + ly;
-    if (gx >= nx || gy >= ny) continue;
-    const long long o = gy * px + gx;
-    const R pn = phi_new[o];
-    const R dphi = pn - phi_old[o];
-    if (D.has_U) {
-      const int ci = (ly + 1) * CW + tx + 1;
-      const R* jx = &sJx[ci];
-      const R* jy = &sJy[ci];
-      const R div = (jx[1] - jx[-1]) * R(1.0 / 3.0) +
-                    (jx[CW + 1] - jx[CW - 1] - jx[-CW - 1] + jx[-CW + 1]) * R(1.0 / 12.0) +
-                    (jy[CW] - jy[-CW]) * R(1.0 / 3.0) +
-                    (jy[CW + 1] + jy[CW - 1] - jy[-CW - 1] - jy[-CW + 1]) * R(1.0 / 12.0);
-      const R Us = Uin[o];
-      const R dU = ((R(1) + omk * Us) * dphi - R(2) * div) / (opk - omk * pn);
-      amax = fmax(amax, fabs(dU));
-      if (D.accum) {
-        R* PU = (R*)D.PU;
-        PU[o] = PU[o] + dU;
-      } else {
-        Uout[o] = Us + dU;
-      }
-    }
+    if (cl[r] < 0) continue;
+    const int ci = cl[r];
+    const long long o = (long long)(y0 + ty + r * BY) * px + x0 + tx;
+    const R pn = sphi[bi[r]];
+    const R dphi = pn - pold[r];
+    const R* jx = &sJx[ci];
+    const R* jy = &sJy[ci];
+    const R div = (jx[1] - jx[-1]) * R(1.0 / 3.0) +
+                  (jx[CW + 1] - jx[CW - 1] - jx[-CW - 1] + jx[-CW + 1]) * R(1.0 / 12.0) +
+                  (jy[CW] - jy[-CW]) * R(1.0 / 3.0) +
+                  (jy[CW + 1] + jy[CW - 1] - jy[-CW - 1] - jy[-CW + 1]) * R(1.0 / 12.0);
+    const R dU = ((R(1) + omk * Us[r]) * dphi - R(2) * div) / (opk - omk * pn);
+    amax = fmax(amax, fabs(dU));
+    if (D.accum)
+      PU[o] = PU[o] + dU;
+    else
+      Uout[o] = Us[r] + dU;
     if (D.has_T) {
-      const R rc = (R(1) + pn) * R(0.5) * R(D.rcS) + (R(1) - pn) * R(0.5) * R(D.rcL);
-      const R dT = R(D.rho_L * D.L_h) * dphi / (R(2) * rc);
-      if (D.accum) {
-        R* PT = (R*)D.PT;
-        PT[o] = PT[o] + dT;
-      } else {
-        Tcur[o] = Tcur[o] + dT;
-      }
+      const R rc = (R(1) + pn) * R(0.5) * rcS + (R(1) - pn) * R(0.5) * rcL;
+      const R dT = cT * dphi / (R(2) * rc);
+      if (D.accum)
+        PT[o] = Tv[r] + dT;
+      else
+        Tcur[o] = Tv[r] + dT;
     }
   }
-  if (part && D.has_U) {
+  if (part) {
     // block max of |dU| (wavefront reduction, then across the 4 wavefronts)
     for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_down(amax, off, 64));
     if (tx == 0) red[ty] = amax;
     __syncthreads();
     if (tid == 0) {
       R m = red[0];
-      for (int w = 1; w < NTHR / 64; ++w) m = fmax(m, red[w]);
+      for (int wv = 1; wv < NTHR / 64; ++wv) m = fmax(m, red[wv]);
       part[t.w].S_phi = double(m);
       if (!D.accum) part[t.w].J_U = double(m);
     }
@@ -390,6 +453,7 @@ template <class R, class S, int TY, int FIELD>
 __global__ __launch_bounds__(NTHR) void k_scalar(const Dom* __restrict__ doms, const int4* __restrict__ tiles,
                                                   long long k, Partial* __restrict__ part) {
   constexpr int RPT = TY / BY;
+  constexpr int NS = RPT + 1;
   constexpr int BW = TX + 4, BH = TY + 4;
   constexpr int CW = TX + 2, CH = TY + 2;
   __shared__ R sphi[BH * BW];
@@ -404,6 +468,7 @@ __global__ __launch_bounds__(NTHR) void k_scalar(const Dom* __restrict__ doms, c
   const int nx = D.nx, ny = D.ny;
   const long long px = D.px, pl = D.plane;
   const int x0 = t.y, y0 = t.z;
+  const int w = min(TX, nx - x0), h = min(TY, ny - y0);
   const int bcx = D.bc[0], bcy = D.bc[1];
   const R* __restrict__ cin;
   R* __restrict__ cout;
@@ -432,95 +497,79 @@ __global__ __launch_bounds__(NTHR) void k_scalar(const Dom* __restrict__ doms, c
   const R omk = R(1.0 - D.kc), opk = R(1.0 + D.kc);
   const R DS = R(D.D_S), DL = R(D.D_L);
   const R kS = R(D.kS), kL = R(D.kL), rcS = R(D.rcS), rcL = R(D.rcL);
-
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
-  if (need_phi) {
-    for (int i = tid; i < BW * BH; i += NTHR) {
-      const int lx = i % BW, ly = i / BW;
-      const int gx = ghost(x0 - 2 + lx, nx, bcx), gy = ghost(y0 - 2 + ly, ny, bcy);
-      sphi[i] = phis[gy * px + gx];
-    }
-    __syncthreads();
-  }
 
-  // collision of one site whose phi stencil centre is b (LDS) or whose phi is
-  // read directly when the thermal properties are constant
-  auto collide = [&](long long o, const R* b, R& P, R& Kx, R& Ky) {
-    const R chi = cin[o];
-    const R jx = ld(jin, o), jy = ld(jin, o + pl);
-    R ux = R(0), uy = R(0);
-    if (vel) {
-      ux = vel[o];
-      uy = vel[o + pl];
+  int cl[NS];
+  R chi[NS], jxv[NS], jyv[NS], uxv[NS], uyv[NS], pv[RPT];
+#pragma unroll
+  for (int r = 0; r < NS; ++r) {
+    int lx, ly, gx, gy;
+    cl[r] = -1;
+    if (r < RPT) {
+      lx = tx + 1;
+      ly = ty + r * BY + 1;
+      if (tx >= w || ly > h) continue;
+      gx = x0 + tx;
+      gy = y0 + ly - 1;
+    } else {
+      if (!ring_cell(tid, w, h, lx, ly)) continue;
+      gx = resolve(x0 - 1 + lx, nx, bcx);
+      gy = resolve(y0 - 1 + ly, ny, bcy);
+      if (gx < 0 || gy < 0) continue;
     }
-    R coeff, Q = R(0);
-    const R jex = chi * ux * dt, jey = chi * uy * dt;
+    cl[r] = ly * CW + lx;
+    const long long o = gy * px + gx;
+    chi[r] = cin[o];
+    jxv[r] = ld(jin, o);
+    jyv[r] = ld(jin, o + pl);
+    uxv[r] = vel ? vel[o] : R(0);
+    uyv[r] = vel ? vel[o + pl] : R(0);
+    if (r < RPT && D.accum) pv[r] = pend[o];
+  }
+  if (need_phi) load_box2(sphi, phis, px, x0, y0, nx, ny, bcx, bcy, BW, BH, tid);
+  __syncthreads();
+
+#pragma unroll
+  for (int r = 0; r < NS; ++r) {
+    if (cl[r] < 0) continue;
+    const int lx = cl[r] % CW, ly = cl[r] / CW;
+    const R* b = &sphi[(ly + 1) * BW + lx + 1];
+    const R jex = chi[r] * uxv[r] * dt, jey = chi[r] * uyv[r] * dt;
+    R tau, Q = R(0);
     if (FIELD == 0) {
       const R phi = b[0];
       const R kf = opk - omk * phi;
-      coeff = ((R(1) + phi) * DS + (R(1) - phi) * DL) / kf;                    // Eq. (7)
-      const R tau = R(3) * dt * coeff + R(0.5);
-      const R gcx = -R(3) / tau * (jx - jex), gcy = -R(3) / tau * (jy - jey);  // Eq. (40)
+      const R coeff = ((R(1) + phi) * DS + (R(1) - phi) * DL) / kf;             // Eq. (7)
+      tau = R(3) * dt * coeff + R(0.5);
+      const R gcx = -R(3) / tau * (jxv[r] - jex), gcy = -R(3) / tau * (jyv[r] - jey);  // Eq. (40)
       R gpx, gpy;
       iso_grad(b, BW, gpx, gpy);
-      Q = -omk * coeff * (gcx * gpx + gcy * gpy) / kf;                          // Eq. (8), 1st term
-      const R om = R(1) - R(1) / tau;
-      P = chi + dt * Q;
-      Kx = jex + om * (jx - jex);
-      Ky = jey + om * (jy - jey);
+      Q = -omk * coeff * (gcx * gpx + gcy * gpy) / kf;                           // Eq. (8), 1st term
+    } else if (D.T_var) {
+      const R phi = b[0];
+      const R rc = (R(1) + phi) * R(0.5) * rcS + (R(1) - phi) * R(0.5) * rcL;
+      const R coeff = ((R(1) + phi) * R(0.5) * kS + (R(1) - phi) * R(0.5) * kL) / rc;  // Eq. (11)
+      tau = R(3) * dt * coeff + R(0.5);
+      const R gcx = -R(3) / tau * (jxv[r] - jex), gcy = -R(3) / tau * (jyv[r] - jey);
+      R gpx, gpy;
+      iso_grad(b, BW, gpx, gpy);
+      Q = (rcS - rcL) / (R(2) * rc) * coeff * (gcx * gpx + gcy * gpy);          // Eq. (12), 1st term
     } else {
-      R tau;
-      if (D.T_var) {
-        const R phi = b[0];
-        const R rc = (R(1) + phi) * R(0.5) * rcS + (R(1) - phi) * R(0.5) * rcL;
-        coeff = ((R(1) + phi) * R(0.5) * kS + (R(1) - phi) * R(0.5) * kL) / rc;   // Eq. (11)
-        tau = R(3) * dt * coeff + R(0.5);
-        const R gcx = -R(3) / tau * (jx - jex), gcy = -R(3) / tau * (jy - jey);
-        R gpx, gpy;
-        iso_grad(b, BW, gpx, gpy);
-        Q = (rcS - rcL) / (R(2) * rc) * coeff * (gcx * gpx + gcy * gpy);         // Eq. (12), 1st term
-      } else {
-        coeff = kL / rcL;
-        tau = R(3) * dt * coeff + R(0.5);
-      }
-      const R om = R(1) - R(1) / tau;
-      P = chi + dt * Q;
-      Kx = jex + om * (jx - jex);
-      Ky = jey + om * (jy - jey);
+      tau = R(3) * dt * (kL / rcL) + R(0.5);
     }
-  };
-
-#pragma unroll
-  for (int r = 0; r < RPT; ++r) {
-    const int ly = ty + r * BY, gx = x0 + tx, gy = y0 + ly;
-    if (gx >= nx || gy >= ny) continue;
-    R P, Kx, Ky;
-    collide(gy * px + gx, &sphi[(ly + 2) * BW + tx + 2], P, Kx, Ky);
-    const int ci = (ly + 1) * CW + tx + 1;
-    sP[ci] = P;
-    sKx[ci] = Kx;
-    sKy[ci] = Ky;
-  }
-  for (int i = tid; i < CW * CH; i += NTHR) {
-    const int lx = i % CW, ly = i / CW;
-    const int rx = x0 - 1 + lx, ry = y0 - 1 + ly;
-    if (lx >= 1 && lx <= TX && ly >= 1 && ly <= TY && rx < nx && ry < ny) continue;
-    const int gx = resolve(rx, nx, bcx), gy = resolve(ry, ny, bcy);
-    if (gx < 0 || gy < 0) continue;
-    R P, Kx, Ky;
-    collide(gy * px + gx, &sphi[(ly + 1) * BW + lx + 1], P, Kx, Ky);
-    sP[i] = P;
-    sKx[i] = Kx;
-    sKy[i] = Ky;
+    const R om = R(1) - R(1) / tau;
+    sP[cl[r]] = chi[r] + dt * Q;
+    sKx[cl[r]] = jex + om * (jxv[r] - jex);
+    sKy[cl[r]] = jey + om * (jyv[r] - jey);
   }
   __syncthreads();
 
   R amax = R(0);
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
-    const int ly = ty + r * BY, gx = x0 + tx, gy = y0 + ly;
-    if (gx >= nx || gy >= ny) continue;
-    const int ci = (ly + 1) * CW + tx + 1;
+    if (cl[r] < 0) continue;
+    const int ci = cl[r];
+    const int gx = x0 + tx, gy = y0 + ty + r * BY;
     const R Po = sP[ci], Kxo = sKx[ci], Kyo = sKy[ci];
     R fq[5];
     fq[0] = Po * R(1.0 / 3.0);
@@ -537,14 +586,13 @@ __global__ __launch_bounds__(NTHR) void k_scalar(const Dom* __restrict__ doms, c
       }
     }
     const long long o = gy * px + gx;
-    R chi = fq[0] + fq[1] + fq[2] + fq[3] + fq[4];
+    R chin = fq[0] + fq[1] + fq[2] + fq[3] + fq[4];
     if (D.accum) {
-      const R p = pend[o];
-      chi += p;
+      chin += pv[r];
       pend[o] = R(0);
-      amax = fmax(amax, fabs(p));
+      amax = fmax(amax, fabs(pv[r]));
     }
-    cout[o] = chi;
+    cout[o] = chin;
     st(jout, o, fq[1] - fq[3]);
     st(jout, o + pl, fq[2] - fq[4]);
   }
@@ -554,7 +602,7 @@ __global__ __launch_bounds__(NTHR) void k_scalar(const Dom* __restrict__ doms, c
     __syncthreads();
     if (tid == 0) {
       R m = red[0];
-      for (int w = 1; w < NTHR / 64; ++w) m = fmax(m, red[w]);
+      for (int wv = 1; wv < NTHR / 64; ++wv) m = fmax(m, red[wv]);
       part[t.w].J_U = double(m);
     }
   }
@@ -1099,38 +1147,48 @@ __global__ void k_tips(const Dom* __restrict__ doms, long long k, DiagOut* __res
 // =================================================================== launchers
 template <class R, class S>
 struct Launch {
+  // TY selects the tile height: 4, 8, 16 or 32 rows
   static void phase(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k) {
-    if (TY == 8) k_phase<R, S, 8><<<g, dim3(TX, BY), 0, st>>>(d, t, k);
-    else if (TY == 16) k_phase<R, S, 16><<<g, dim3(TX, BY), 0, st>>>(d, t, k);
-    else k_phase<R, S, 32><<<g, dim3(TX, BY), 0, st>>>(d, t, k);
+    const dim3 b(TX, BY);
+    if (TY == 4) k_phase<R, S, 4><<<g, b, 0, st>>>(d, t, k);
+    else if (TY == 8) k_phase<R, S, 8><<<g, b, 0, st>>>(d, t, k);
+    else if (TY == 16) k_phase<R, S, 16><<<g, b, 0, st>>>(d, t, k);
+    else k_phase<R, S, 32><<<g, b, 0, st>>>(d, t, k);
   }
   static void transfer(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k, Partial* p) {
-    if (TY == 8) k_transfer<R, 8><<<g, dim3(TX, BY), 0, st>>>(d, t, k, p);
-    else if (TY == 16) k_transfer<R, 16><<<g, dim3(TX, BY), 0, st>>>(d, t, k, p);
-    else k_transfer<R, 32><<<g, dim3(TX, BY), 0, st>>>(d, t, k, p);
+    const dim3 b(TX, BY);
+    if (TY == 4) k_transfer<R, 4><<<g, b, 0, st>>>(d, t, k, p);
+    else if (TY == 8) k_transfer<R, 8><<<g, b, 0, st>>>(d, t, k, p);
+    else if (TY == 16) k_transfer<R, 16><<<g, b, 0, st>>>(d, t, k, p);
+    else k_transfer<R, 32><<<g, b, 0, st>>>(d, t, k, p);
+  }
+  template <int F>
+  static void scalar_f(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k, Partial* p) {
+    const dim3 b(TX, BY);
+    if (TY == 4) k_scalar<R, S, 4, F><<<g, b, 0, st>>>(d, t, k, p);
+    else if (TY == 8) k_scalar<R, S, 8, F><<<g, b, 0, st>>>(d, t, k, p);
+    else if (TY == 16) k_scalar<R, S, 16, F><<<g, b, 0, st>>>(d, t, k, p);
+    else k_scalar<R, S, 32, F><<<g, b, 0, st>>>(d, t, k, p);
   }
   static void scalar(int field, int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k,
                      Partial* p) {
-    if (field == 0) {
-      if (TY == 8) k_scalar<R, S, 8, 0><<<g, dim3(TX, BY), 0, st>>>(d, t, k, p);
-      else if (TY == 16) k_scalar<R, S, 16, 0><<<g, dim3(TX, BY), 0, st>>>(d, t, k, p);
-      else k_scalar<R, S, 32, 0><<<g, dim3(TX, BY), 0, st>>>(d, t, k, p);
-    } else {
-      if (TY == 8) k_scalar<R, S, 8, 1><<<g, dim3(TX, BY), 0, st>>>(d, t, k, p);
-      else if (TY == 16) k_scalar<R, S, 16, 1><<<g, dim3(TX, BY), 0, st>>>(d, t, k, p);
-      else k_scalar<R, S, 32, 1><<<g, dim3(TX, BY), 0, st>>>(d, t, k, p);
-    }
+    if (field == 0) scalar_f<0>(TY, g, st, d, t, k, p);
+    else scalar_f<1>(TY, g, st, d, t, k, p);
   }
   static void flow(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k) {
     constexpr int SUB = sizeof(R) == 8 ? 8 : 16;
-    if (TY == 8) k_flow<R, S, 8, 8><<<g, dim3(TX, BY), 0, st>>>(d, t, k);
-    else if (TY == 16) k_flow<R, S, 16, SUB><<<g, dim3(TX, BY), 0, st>>>(d, t, k);
-    else k_flow<R, S, 32, SUB><<<g, dim3(TX, BY), 0, st>>>(d, t, k);
+    const dim3 b(TX, BY);
+    if (TY == 4) k_flow<R, S, 4, 4><<<g, b, 0, st>>>(d, t, k);
+    else if (TY == 8) k_flow<R, S, 8, 8><<<g, b, 0, st>>>(d, t, k);
+    else if (TY == 16) k_flow<R, S, 16, SUB><<<g, b, 0, st>>>(d, t, k);
+    else k_flow<R, S, 32, SUB><<<g, b, 0, st>>>(d, t, k);
   }
   static void diag_tiles(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k, Partial* p) {
-    if (TY == 8) k_diag_tiles<R, 8><<<g, dim3(TX, BY), 0, st>>>(d, t, k, p);
-    else if (TY == 16) k_diag_tiles<R, 16><<<g, dim3(TX, BY), 0, st>>>(d, t, k, p);
-    else k_diag_tiles<R, 32><<<g, dim3(TX, BY), 0, st>>>(d, t, k, p);
+    const dim3 b(TX, BY);
+    if (TY == 4) k_diag_tiles<R, 4><<<g, b, 0, st>>>(d, t, k, p);
+    else if (TY == 8) k_diag_tiles<R, 8><<<g, b, 0, st>>>(d, t, k, p);
+    else if (TY == 16) k_diag_tiles<R, 16><<<g, b, 0, st>>>(d, t, k, p);
+    else k_diag_tiles<R, 32><<<g, b, 0, st>>>(d, t, k, p);
   }
   static void tips(int ndom, hipStream_t st, const Dom* d, long long k, DiagOut* o) {
     k_tips<R><<<dim3(ndom, MAX_SEEDS, 4), 256, 0, st>>>(d, k, o);

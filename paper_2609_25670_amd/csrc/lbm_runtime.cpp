@@ -47,7 +47,8 @@ using namespace lbm;
 
 namespace {
 
-constexpr int kTYs[3] = {8, 16, 32};
+constexpr int kNTY = 4;
+constexpr int kTYs[kNTY] = {4, 8, 16, 32};
 constexpr long long kMaxGraphSteps = 4096;
 constexpr int kMaxCodes = 64;
 
@@ -60,7 +61,7 @@ struct TileSet {
 
 struct Group {
   int N;              // update factor shared by the domains of the group
-  TileSet ts[3];      // per tile height
+  TileSet ts[kNTY];   // per tile height
 };
 
 struct Ops {
@@ -102,16 +103,16 @@ struct lbm_ctx {
   size_t ws_bytes = 0;
   bool own_ws = false;
   Dom* d_dom = nullptr;
-  TileSet all[3];
+  TileSet all[kNTY];
   std::vector<Group> g_phi, g_U, g_T, g_F;
   Partial* d_part = nullptr;
   int* d_slot = nullptr;
-  int* d_slot0[3] = {nullptr, nullptr, nullptr};
+  int* d_slot0[kNTY] = {nullptr, nullptr, nullptr, nullptr};
   DiagOut* d_diag = nullptr;
   int* d_codes = nullptr;
   double* d_stage = nullptr;
   size_t stage_elems = 0;
-  int ty_index = 1;
+  int ty_index = 2;
   bool tuned = false;
   bool autotune = true;
   bool use_graph = true;
@@ -260,7 +261,7 @@ static lbm_status autotune(lbm_ctx* c) {
   // the next due step of a group: its kernels read the current buffers and
   // write only the other ones, so repeating them leaves the state unchanged
   auto next_due = [&](int N) { return (c->k / N + 1) * (long long)N; };
-  for (int ti = 0; ti < 3; ++ti) {
+  for (int ti = 0; ti < kNTY; ++ti) {
     const int TY = kTYs[ti];
     auto run = [&]() {
       for (auto& g : c->g_phi)
@@ -297,23 +298,23 @@ size_t lbm_workspace_bytes(const lbm_params* p, int32_t n, int32_t storage) {
   size_t rsz, ssz;
   sizes_of(storage, rsz, ssz);
   size_t total = 0;
-  long long tiles8 = 0;
+  long long tilesmax = 0;   // tiles at the smallest tile height
   size_t maxsites = 0;
   for (int i = 0; i < n; ++i) {
     if (!validate(p[i], i).empty()) return 0;
     const size_t plane = (size_t)px_of(p[i].nx) * p[i].ny;
     const Layout L = layout_of(p[i]);
     total += align256(plane * rsz) * L.rplanes + align256(plane * ssz) * L.splanes;
-    tiles8 += (long long)((p[i].nx + 63) / 64) * ((p[i].ny + 7) / 8);
+    tilesmax += (long long)((p[i].nx + 63) / 64) * ((p[i].ny + kTYs[0] - 1) / kTYs[0]);
     maxsites = std::max(maxsites, (size_t)p[i].nx * p[i].ny);
   }
-  const long long padded = (tiles8 + 7) / 8 * 8;
+  const long long padded = (tilesmax + 7) / 8 * 8;
   total += align256(sizeof(Dom) * n);
   // tile lists per tile height: "all" plus, per field, one list per group of
   // domains sharing an update factor (at most 8 groups, each padded by < 8)
-  total += 3 * (5 * (sizeof(int4) * (size_t)(padded + 64)) + 40 * 256);
-  total += align256(sizeof(Partial) * (size_t)tiles8);
-  total += align256(sizeof(int) * (size_t)tiles8) + 3 * align256(sizeof(int) * (n + 1));
+  total += kNTY * (5 * (sizeof(int4) * (size_t)(padded + 64)) + 40 * 256);
+  total += align256(sizeof(Partial) * (size_t)tilesmax);
+  total += align256(sizeof(int) * (size_t)tilesmax) + kNTY * align256(sizeof(int) * (n + 1));
   total += align256(sizeof(DiagOut) * n);
   total += align256(sizeof(int) * kMaxCodes);
   total += align256(sizeof(double) * maxsites * 16);
@@ -462,10 +463,10 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
   c->d_dom = (Dom*)take(sizeof(Dom) * n);
 
   // tile lists (three tile heights), groups by update factor
-  long long tiles8 = 0;
+  long long tilesmax = 0;
   size_t maxsites = 0;
   for (int i = 0; i < n; ++i) {
-    tiles8 += (long long)((p[i].nx + 63) / 64) * ((p[i].ny + 7) / 8);
+    tilesmax += (long long)((p[i].nx + 63) / 64) * ((p[i].ny + kTYs[0] - 1) / kTYs[0]);
     maxsites = std::max(maxsites, (size_t)p[i].nx * p[i].ny);
   }
   auto build = [&](const std::vector<int>& doms, int ti, TileSet& ts, std::vector<int>* slot0) -> lbm_status {
@@ -490,8 +491,8 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
   };
   std::vector<int> alld(n);
   std::iota(alld.begin(), alld.end(), 0);
-  std::vector<int> slot0[3];
-  for (int ti = 0; ti < 3; ++ti) {
+  std::vector<int> slot0[kNTY];
+  for (int ti = 0; ti < kNTY; ++ti) {
     lbm_status s = build(alld, ti, c->all[ti], &slot0[ti]);
     if (s != LBM_OK) {
       lbm_destroy(c);
@@ -511,7 +512,7 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
     for (auto& kv : by) {
       Group g;
       g.N = kv.first;
-      for (int ti = 0; ti < 3; ++ti) {
+      for (int ti = 0; ti < kNTY; ++ti) {
         if (by.size() == 1 && (int)kv.second.size() == n) {
           g.ts[ti] = c->all[ti];
         } else {
@@ -532,9 +533,9 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
       return fail(nullptr, LBM_EINVAL, "too many distinct update factors for one field (max 8)");
     }
   }
-  c->d_part = (Partial*)take(sizeof(Partial) * (size_t)tiles8);
-  c->d_slot = (int*)take(sizeof(int) * (size_t)tiles8);
-  for (int ti = 0; ti < 3; ++ti) c->d_slot0[ti] = (int*)take(sizeof(int) * (n + 1));
+  c->d_part = (Partial*)take(sizeof(Partial) * (size_t)tilesmax);
+  c->d_slot = (int*)take(sizeof(int) * (size_t)tilesmax);
+  for (int ti = 0; ti < kNTY; ++ti) c->d_slot0[ti] = (int*)take(sizeof(int) * (n + 1));
   c->d_diag = (DiagOut*)take(sizeof(DiagOut) * n);
   c->d_codes = (int*)take(sizeof(int) * kMaxCodes);
   c->stage_elems = maxsites * 16;
@@ -544,18 +545,18 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
     return fail(nullptr, LBM_ENOMEM, "internal: workspace layout overflow");
   }
   {
-    std::vector<int> slots((size_t)tiles8);
+    std::vector<int> slots((size_t)tilesmax);
     std::iota(slots.begin(), slots.end(), 0);
     if (hipMemcpy(c->d_slot, slots.data(), sizeof(int) * slots.size(), hipMemcpyHostToDevice) != hipSuccess) {
       lbm_destroy(c);
       return fail(nullptr, LBM_EDEVICE, "slot upload failed");
     }
-    for (int ti = 0; ti < 3; ++ti)
+    for (int ti = 0; ti < kNTY; ++ti)
       if (hipMemcpy(c->d_slot0[ti], slot0[ti].data(), sizeof(int) * (n + 1), hipMemcpyHostToDevice) != hipSuccess) {
         lbm_destroy(c);
         return fail(nullptr, LBM_EDEVICE, "slot upload failed");
       }
-    if (hipMemset(c->d_part, 0, sizeof(Partial) * (size_t)tiles8) != hipSuccess) {
+    if (hipMemset(c->d_part, 0, sizeof(Partial) * (size_t)tilesmax) != hipSuccess) {
       lbm_destroy(c);
       return fail(nullptr, LBM_EDEVICE, "partial clear failed");
     }
@@ -601,8 +602,10 @@ lbm_status lbm_configure(lbm_ctx* c, int32_t tile_rows, int32_t use_graph) {
     c->autotune = true;
     c->tuned = false;
   } else {
-    int ti = tile_rows == 8 ? 0 : tile_rows == 16 ? 1 : tile_rows == 32 ? 2 : -1;
-    if (ti < 0) return fail(c, LBM_EINVAL, "tile_rows must be 0, 8, 16 or 32");
+    int ti = -1;
+    for (int i = 0; i < kNTY; ++i)
+      if (kTYs[i] == tile_rows) ti = i;
+    if (ti < 0) return fail(c, LBM_EINVAL, "tile_rows must be 0, 4, 8, 16 or 32");
     c->ty_index = ti;
     c->autotune = false;
     c->tuned = true;
@@ -612,6 +615,61 @@ lbm_status lbm_configure(lbm_ctx* c, int32_t tile_rows, int32_t use_graph) {
 }
 
 int64_t lbm_steps_done(const lbm_ctx* c) { return c ? c->k : -1; }
+
+lbm_status lbm_kernel_times(lbm_ctx* c, int32_t reps, double* ms_out, double* per_step) {
+  if (!c || !ms_out || reps < 1) return c ? fail(c, LBM_EINVAL, "bad arguments") : LBM_EINVAL;
+  for (int d = 0; d < c->ndom; ++d)
+    if (!c->initialised[d]) return fail(c, LBM_ESTATE, "lbm_init_seeds has not been called for every domain");
+  HIPCHK(c, hipSetDevice(c->device));
+  if (c->autotune && !c->tuned) {
+    lbm_status s = autotune(c);
+    if (s != LBM_OK) return s;
+  }
+  const int ti = c->ty_index, TY = kTYs[ti];
+  hipEvent_t e0, e1;
+  HIPCHK(c, hipEventCreate(&e0));
+  HIPCHK(c, hipEventCreate(&e1));
+  auto due = [&](int N) { return (c->k / N + 1) * (long long)N; };
+  for (int kind = 0; kind < 5; ++kind) {
+    const std::vector<Group>& gs = kind <= 1 ? c->g_phi : kind == 2 ? c->g_U : kind == 3 ? c->g_T : c->g_F;
+    if (gs.empty()) {
+      ms_out[kind] = -1.0;
+      if (per_step) per_step[kind] = 0.0;
+      continue;
+    }
+    auto launch = [&]() {
+      for (auto& g : gs) {
+        const long long k = due(g.N);
+        const dim3 grid(g.ts[ti].n);
+        if (kind == 0) c->ops.phase(TY, grid, c->stream, c->d_dom, g.ts[ti].d, k);
+        if (kind == 1) c->ops.transfer(TY, grid, c->stream, c->d_dom, g.ts[ti].d, k, c->d_part);
+        if (kind == 2) c->ops.scalar(0, TY, grid, c->stream, c->d_dom, g.ts[ti].d, k, c->d_part);
+        if (kind == 3) c->ops.scalar(1, TY, grid, c->stream, c->d_dom, g.ts[ti].d, k, c->d_part);
+        if (kind == 4) c->ops.flow(TY, grid, c->stream, c->d_dom, g.ts[ti].d, k);
+      }
+    };
+    launch();
+    HIPCHK(c, hipEventRecord(e0, c->stream));
+    for (int r = 0; r < reps; ++r) launch();
+    HIPCHK(c, hipEventRecord(e1, c->stream));
+    HIPCHK(c, hipEventSynchronize(e1));
+    float ms = 0;
+    HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+    ms_out[kind] = double(ms) / reps;
+    if (per_step) {
+      // launches of this kind per base step over one cycle
+      double n = 0;
+      for (long long k = 1; k <= c->cycle; ++k)
+        for (auto& g : gs) n += (k % g.N == 0) ? 1.0 : 0.0;
+      per_step[kind] = n / double(c->cycle);
+    }
+  }
+  HIPCHK(c, hipEventDestroy(e0));
+  HIPCHK(c, hipEventDestroy(e1));
+  HIPCHK(c, hipGetLastError());
+  for (int d = 0; d < c->ndom; ++d) c->initialised[d] = false;
+  return LBM_OK;
+}
 
 static lbm_status run_diag(lbm_ctx* c, lbm_diag* out) {
   const int ti = c->ty_index, TY = kTYs[ti];

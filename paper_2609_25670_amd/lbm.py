@@ -31,7 +31,9 @@ FIELD_BITS = [("phi", F_PHI, 1), ("U", F_U, 1), ("T", F_T, 1), ("rho", F_RHO, 1)
               ("P_U", F_PEND_U, 1), ("P_T", F_PEND_T, 1), ("s_phi", F_SPHI, 4), ("s_F", F_SF, 8)]
 
 EXPORTS = ["lbm_workspace_bytes", "lbm_create", "lbm_init_seeds", "lbm_step_multirate", "lbm_read_fields",
-           "lbm_write_fields", "lbm_configure", "lbm_steps_done", "lbm_last_error", "lbm_destroy"]
+           "lbm_write_fields", "lbm_configure", "lbm_kernel_times", "lbm_steps_done", "lbm_last_error",
+           "lbm_destroy"]
+KERNEL_KINDS = ("phase", "transfer", "U", "T", "flow")
 
 
 class Params(ctypes.Structure):
@@ -98,6 +100,8 @@ def load() -> ctypes.CDLL:
                                      ctypes.c_void_p]
     lib.lbm_configure.restype = ctypes.c_int
     lib.lbm_configure.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32]
+    lib.lbm_kernel_times.restype = ctypes.c_int
+    lib.lbm_kernel_times.argtypes = [ctypes.c_void_p, ctypes.c_int32, P(ctypes.c_double), P(ctypes.c_double)]
     lib.lbm_steps_done.restype = ctypes.c_int64
     lib.lbm_steps_done.argtypes = [ctypes.c_void_p]
     lib.lbm_last_error.restype = ctypes.c_char_p
@@ -199,6 +203,14 @@ class Simulation:
             raise err
         _check(self.lib, self.ctx, s)
         return res
+
+    def kernel_times(self, reps=200):
+        """Per-kind average launch time (ms) and launches per base step.
+        Leaves the state undefined (call ``init`` before stepping again)."""
+        ms = (ctypes.c_double * 5)()
+        per = (ctypes.c_double * 5)()
+        _check(self.lib, self.ctx, self.lib.lbm_kernel_times(self.ctx, int(reps), ms, per))
+        return {k: (ms[i], per[i]) for i, k in enumerate(KERNEL_KINDS) if ms[i] >= 0}
 
     @property
     def steps_done(self) -> int:
