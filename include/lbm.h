@@ -170,14 +170,16 @@ lbm_status lbm_write_fields(lbm_ctx* ctx, int32_t domain, uint32_t mask,
  * and whether whole cycles are replayed from a HIP graph. */
 lbm_status lbm_configure(lbm_ctx* ctx, int32_t tile_rows, int32_t use_graph);
 
-/* Average device time per launch, in milliseconds, of each kernel kind of
- * the step, measured with HIP events around `reps` back-to-back launches on
- * the context stream: ms_out[0] phase, [1] transfer, [2] U transport,
- * [3] T transport, [4] flow (-1 where the context has no such kernel).
- * Also reports the launches of each kind per base step, averaged over one
- * multirate cycle, in per_step_out[0..4] (may be NULL).  The timing launches
- * overwrite the state: every domain must be re-initialised with
- * lbm_init_seeds before the next lbm_step_multirate. */
+/* Average device time, in milliseconds, of one launch of each kernel kind
+ * over every domain, measured with HIP events around `reps` back-to-back
+ * launches on the context stream: ms_out[0] phase, [1] transfer, [2] U
+ * transport, [3] T transport, [4] flow (-1 where the context has no such
+ * kernel).  per_step_out[0..4] (may be NULL) receives the fraction of that
+ * time spent per base step (each group of domains sharing an update factor
+ * N contributes 1/N of its own launch time), so ms_out * per_step_out is the
+ * device time per base step.  The timing launches overwrite the state:
+ * every domain must be re-initialised with lbm_init_seeds before the next
+ * lbm_step_multirate. */
 lbm_status lbm_kernel_times(lbm_ctx* ctx, int32_t reps, double* ms_out, double* per_step_out);
 
 /* Base steps completed since the last lbm_init_seeds. */

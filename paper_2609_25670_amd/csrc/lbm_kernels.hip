@@ -76,9 +76,16 @@ __constant__ int EY5[5] = {0, 0, 1, 0, -1};
 // Collision of Eq. (14) with the equilibrium of Eq. (21), the relaxation of
 // Eq. (23), tau_phi of Eq. (24) and the source dt w_i Q_phi / tau0, then the
 // anisotropic streaming of Eq. (26) in pull form with a_s^2 at the
-// destination.  The result per site of the collision is (P, K):
-// f_i^+ = w_i P + e_i . K / 2 with P = phi + dt Q / tau0 and
+// destination.  The result per site of the collision is (dP, K):
+// f_i^+ = w_i (phi + dP) + e_i . K / 2 with dP = dt Q / tau0 and
 // K = j_eq + (1 - 1/tau)(j - j_eq), j_eq = v_n dt.
+//
+// Deviation form: every population is handled as its deviation from
+// w_i times the zeroth moment of the site it is written to, and the new
+// zeroth moment is the old one plus the sum of the deviations.  This is
+// the same arithmetic rearranged; a uniform state is then reproduced
+// exactly in any precision instead of drifting by the rounding of
+// w_i chi summed over i at every step.
 template <class R>
 struct PhaseConst {
   R dt, W2t, inv_tau0, eps, lam, Mc, cth, sth, inv_lhcp, theta_off, Wt;
@@ -86,7 +93,7 @@ struct PhaseConst {
 
 template <class R>
 __device__ __forceinline__ void phase_collide(const PhaseConst<R>& c, R phi, R gx, R gy, R jx, R jy,
-                                              R Us, R Ts, R& P, R& Kx, R& Ky, R& A) {
+                                              R Us, R Ts, R& dP, R& Kx, R& Ky, R& A) {
   const R gg = gx * gx + gy * gy;
   R a_s = R(1), Nx = R(0), Ny = R(0);
   if (gg >= R(GRAD_EPS2)) {
@@ -113,7 +120,7 @@ __device__ __forceinline__ void phase_collide(const PhaseConst<R>& c, R phi, R g
   const R theta = (Ts - c.theta_off) * c.inv_lhcp;
   const R q = R(1) - phi * phi;
   const R Q = phi * q - c.lam * (c.Mc * Us + theta) * q * q;
-  P = phi + c.dt * Q * c.inv_tau0;
+  dP = c.dt * Q * c.inv_tau0;
   Kx = jex + om * (jx - jex);
   Ky = jey + om * (jy - jey);
 }
@@ -221,65 +228,61 @@ __global__ __launch_bounds__(NTHR) void k_phase(const Dom* __restrict__ doms, co
   load_box2(sphi, phi_in, px, x0, y0, nx, ny, bcx, bcy, BW, BH, tid);
   __syncthreads();
 
-  R f[RPT][5];
   R Aown[RPT];
 #pragma unroll
   for (int r = 0; r < NS; ++r) {
     if (cl[r] < 0) continue;
     const int lx = cl[r] % CW, ly = cl[r] / CW;
     const R* b = &sphi[(ly + 1) * BW + lx + 1];
-    const R phi = b[0];
     R gx_, gy_;
     iso_grad(b, BW, gx_, gy_);
-    R P, Kx, Ky, A;
-    phase_collide(c, phi, gx_, gy_, sv[r][0] - sv[r][2], sv[r][1] - sv[r][3], Uv[r], Tv[r], P, Kx, Ky, A);
-    sP[cl[r]] = P;
+    R dP, Kx, Ky, A;
+    phase_collide(c, b[0], gx_, gy_, sv[r][0] - sv[r][2], sv[r][1] - sv[r][3], Uv[r], Tv[r], dP, Kx, Ky, A);
+    sP[cl[r]] = dP;
     sKx[cl[r]] = Kx;
     sKy[cl[r]] = Ky;
-    if (r < RPT) {
-      const R w6 = phi * R(1.0 / 6.0);
-      f[r][1] = w6 + sv[r][0];
-      f[r][2] = w6 + sv[r][1];
-      f[r][3] = w6 + sv[r][2];
-      f[r][4] = w6 + sv[r][3];
-      f[r][0] = phi * R(1.0 / 3.0) - (sv[r][0] + sv[r][1] + sv[r][2] + sv[r][3]);
-      Aown[r] = A;
-    }
+    if (r < RPT) Aown[r] = A;
   }
   __syncthreads();
 
-  // anisotropic pull streaming (Eq. 26) into owned sites
+  // anisotropic pull streaming (Eq. 26) into owned sites, in deviations
+  // d_i = f_i - w_i phi(y) of the destination y:
+  //   A d_i^new = [f_i^+(y - e_i) - w_i phi(y)] - (1 - A) d_i
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
     if (cl[r] < 0) continue;
     const int ci = cl[r];
+    const int bc = ci + (ci / CW) * (BW - CW) + BW + 1;   // same site in the phi box
     const int gx = x0 + tx, gy = y0 + ty + r * BY;
     const R A = Aown[r], iA = R(1) / A, oA = R(1) - A;
-    const R Po = sP[ci], Kxo = sKx[ci], Kyo = sKy[ci];
-    R fn[5];
-    fn[0] = (Po * R(1.0 / 3.0) - oA * f[r][0]) * iA;
+    const R phy = sphi[bc];
+    const R dPo = sP[ci], Kxo = sKx[ci], Kyo = sKy[ci];
+    const R s0 = -(sv[r][0] + sv[r][1] + sv[r][2] + sv[r][3]);
+    R dn[5];
+    dn[0] = (dPo * R(1.0 / 3.0) - oA * s0) * iA;
 #pragma unroll
     for (int q = 1; q < 5; ++q) {
       const int ex = EX5[q], ey = EY5[q];
       const int sx = gx - ex, sy = gy - ey;
       const bool wall = ((sx < 0 || sx >= nx) && bcx != BC_PER) || ((sy < 0 || sy >= ny) && bcy != BC_PER);
-      R post;
+      R dpost;
       if (wall) {
-        post = Po * R(1.0 / 6.0) - R(0.5) * (R(ex) * Kxo + R(ey) * Kyo);
+        dpost = dPo * R(1.0 / 6.0) - R(0.5) * (R(ex) * Kxo + R(ey) * Kyo);
       } else {
         const int si = ci - ey * CW - ex;
-        post = sP[si] * R(1.0 / 6.0) + R(0.5) * (R(ex) * sKx[si] + R(ey) * sKy[si]);
+        const R dphi = sphi[bc - ey * BW - ex] - phy;
+        dpost = (dphi + sP[si]) * R(1.0 / 6.0) + R(0.5) * (R(ex) * sKx[si] + R(ey) * sKy[si]);
       }
-      fn[q] = (post - oA * f[r][q]) * iA;
+      dn[q] = (dpost - oA * sv[r][q - 1]) * iA;
     }
-    const R phin = fn[0] + fn[1] + fn[2] + fn[3] + fn[4];
+    const R dphin = dn[0] + dn[1] + dn[2] + dn[3] + dn[4];
     const long long o = gy * px + gx;
-    phi_out[o] = phin;
-    const R w6 = phin * R(1.0 / 6.0);
-    st(s_out, o, fn[1] - w6);
-    st(s_out, o + pl, fn[2] - w6);
-    st(s_out, o + 2 * pl, fn[3] - w6);
-    st(s_out, o + 3 * pl, fn[4] - w6);
+    phi_out[o] = phy + dphin;
+    const R w6 = dphin * R(1.0 / 6.0);
+    st(s_out, o, dn[1] - w6);
+    st(s_out, o + pl, dn[2] - w6);
+    st(s_out, o + 2 * pl, dn[3] - w6);
+    st(s_out, o + 3 * pl, dn[4] - w6);
   }
 }
 
@@ -457,7 +460,7 @@ __global__ __launch_bounds__(NTHR) void k_scalar(const Dom* __restrict__ doms, c
   constexpr int BW = TX + 4, BH = TY + 4;
   constexpr int CW = TX + 2, CH = TY + 2;
   __shared__ R sphi[BH * BW];
-  __shared__ R sP[CH * CW], sKx[CH * CW], sKy[CH * CW];
+  __shared__ R sC[CH * CW], sP[CH * CW], sKx[CH * CW], sKy[CH * CW];
   __shared__ R red[NTHR / 64];
 
   const int4 t = tiles[blockIdx.x];
@@ -558,43 +561,45 @@ __global__ __launch_bounds__(NTHR) void k_scalar(const Dom* __restrict__ doms, c
       tau = R(3) * dt * (kL / rcL) + R(0.5);
     }
     const R om = R(1) - R(1) / tau;
-    sP[cl[r]] = chi[r] + dt * Q;
+    sC[cl[r]] = chi[r];
+    sP[cl[r]] = dt * Q;
     sKx[cl[r]] = jex + om * (jxv[r] - jex);
     sKy[cl[r]] = jey + om * (jyv[r] - jey);
   }
   __syncthreads();
 
+  // pull streaming (Eq. 25) in deviations d_i = f_i - w_i chi(y)
   R amax = R(0);
 #pragma unroll
   for (int r = 0; r < RPT; ++r) {
     if (cl[r] < 0) continue;
     const int ci = cl[r];
     const int gx = x0 + tx, gy = y0 + ty + r * BY;
-    const R Po = sP[ci], Kxo = sKx[ci], Kyo = sKy[ci];
-    R fq[5];
-    fq[0] = Po * R(1.0 / 3.0);
+    const R cy = sC[ci], dPo = sP[ci], Kxo = sKx[ci], Kyo = sKy[ci];
+    R dq[5];
+    dq[0] = dPo * R(1.0 / 3.0);
 #pragma unroll
     for (int q = 1; q < 5; ++q) {
       const int ex = EX5[q], ey = EY5[q];
       const int sx = gx - ex, sy = gy - ey;
       const bool wall = ((sx < 0 || sx >= nx) && bcx != BC_PER) || ((sy < 0 || sy >= ny) && bcy != BC_PER);
       if (wall) {
-        fq[q] = Po * R(1.0 / 6.0) - R(0.5) * (R(ex) * Kxo + R(ey) * Kyo);
+        dq[q] = dPo * R(1.0 / 6.0) - R(0.5) * (R(ex) * Kxo + R(ey) * Kyo);
       } else {
         const int si = ci - ey * CW - ex;
-        fq[q] = sP[si] * R(1.0 / 6.0) + R(0.5) * (R(ex) * sKx[si] + R(ey) * sKy[si]);
+        dq[q] = (sC[si] - cy + sP[si]) * R(1.0 / 6.0) + R(0.5) * (R(ex) * sKx[si] + R(ey) * sKy[si]);
       }
     }
     const long long o = gy * px + gx;
-    R chin = fq[0] + fq[1] + fq[2] + fq[3] + fq[4];
+    R chin = cy + (dq[0] + dq[1] + dq[2] + dq[3] + dq[4]);
     if (D.accum) {
       chin += pv[r];
       pend[o] = R(0);
       amax = fmax(amax, fabs(pv[r]));
     }
     cout[o] = chin;
-    st(jout, o, fq[1] - fq[3]);
-    st(jout, o + pl, fq[2] - fq[4]);
+    st(jout, o, dq[1] - dq[3]);
+    st(jout, o + pl, dq[2] - dq[4]);
   }
   if (FIELD == 0 && D.accum && part) {
     for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_down(amax, off, 64));
@@ -630,50 +635,61 @@ __device__ __forceinline__ void flow_eq(R rho, R ux, R uy, R dt, R* feq) {
   }
 }
 
+// MRT collision of Eq. (14) for the flow in deviation form: input rho and
+// d_i = f_i - w_i rho (sum_i d_i = 0); output dp_i = f_i^+ - w_i rho.
+// The moments of w_i rho are rho (1, -2, 1, 0, ..., 0), so the
+// non-equilibrium moments m - m^eq (Eq. 29) follow from M d without
+// forming the O(1) populations.
 template <class R>
-__device__ __forceinline__ void flow_collide(const R* f, R dt, R Fx, R Fy, R s_e, R s_eps, R s_q, R s_nu,
-                                            R* post) {
-  // moments m = M f with the rows of Eq. (16)
-  const R rho = f[0] + f[1] + f[2] + f[3] + f[4] + f[5] + f[6] + f[7] + f[8];
+__device__ __forceinline__ void flow_collide(R rho, const R* d, R dt, R Fx, R Fy, R s_e, R s_eps, R s_q,
+                                            R s_nu, R* dp) {
   const R c = R(1) / dt;
-  const R jx = f[1] - f[3] + f[5] - f[6] - f[7] + f[8];
-  const R jy = f[2] - f[4] + f[5] + f[6] - f[7] - f[8];
-  const R ux = (c * jx + dt * Fx * R(0.5)) / rho;
-  const R uy = (c * jy + dt * Fy * R(0.5)) / rho;
-  R m[9];
-  m[0] = rho;
-  m[1] = -R(4) * f[0] - f[1] - f[2] - f[3] - f[4] + R(2) * (f[5] + f[6] + f[7] + f[8]);
-  m[2] = R(4) * f[0] - R(2) * (f[1] + f[2] + f[3] + f[4]) + f[5] + f[6] + f[7] + f[8];
-  m[3] = jx;
-  m[4] = -R(2) * f[1] + R(2) * f[3] + f[5] - f[6] - f[7] + f[8];
-  m[5] = jy;
-  m[6] = -R(2) * f[2] + R(2) * f[4] + f[5] + f[6] - f[7] - f[8];
-  m[7] = f[1] - f[2] + f[3] - f[4];
-  m[8] = f[5] - f[6] + f[7] - f[8];
-  // equilibrium moments (Eq. 29) and Guo forcing (Eq. 30) with 1/c = dt
+  // M d with the rows of Eq. (16)
+  R md[9];
+  md[1] = -R(4) * d[0] - d[1] - d[2] - d[3] - d[4] + R(2) * (d[5] + d[6] + d[7] + d[8]);
+  md[2] = R(4) * d[0] - R(2) * (d[1] + d[2] + d[3] + d[4]) + d[5] + d[6] + d[7] + d[8];
+  md[3] = d[1] - d[3] + d[5] - d[6] - d[7] + d[8];
+  md[4] = -R(2) * d[1] + R(2) * d[3] + d[5] - d[6] - d[7] + d[8];
+  md[5] = d[2] - d[4] + d[5] + d[6] - d[7] - d[8];
+  md[6] = -R(2) * d[2] + R(2) * d[4] + d[5] + d[6] - d[7] - d[8];
+  md[7] = d[1] - d[2] + d[3] - d[4];
+  md[8] = d[5] - d[6] + d[7] - d[8];
+  // velocity (Eq. 27) and u / c = u dt
+  const R ux = (c * md[3] + dt * Fx * R(0.5)) / rho;
+  const R uy = (c * md[5] + dt * Fy * R(0.5)) / rho;
   const R Ux = ux * dt, Uy = uy * dt, U2 = Ux * Ux + Uy * Uy;
-  R meq[9] = {rho, rho * (R(-2) + R(3) * U2), rho * (R(1) - R(3) * U2), rho * Ux, -rho * Ux,
-              rho * Uy, -rho * Uy, rho * (Ux * Ux - Uy * Uy), rho * Ux * Uy};
+  // m - m^eq (Eq. 29); the conserved rows 0, 3, 5 relax at rate 0
+  R neq[9];
+  neq[0] = R(0);
+  neq[1] = md[1] - R(3) * rho * U2;
+  neq[2] = md[2] + R(3) * rho * U2;
+  neq[3] = md[3] - rho * Ux;
+  neq[4] = md[4] + rho * Ux;
+  neq[5] = md[5] - rho * Uy;
+  neq[6] = md[6] + rho * Uy;
+  neq[7] = md[7] - rho * (Ux * Ux - Uy * Uy);
+  neq[8] = md[8] - rho * Ux * Uy;
+  // Guo forcing in moment space (Eq. 30) with 1/c = dt
   const R Fu = (Fx * ux + Fy * uy) * dt * dt;
-  R G[9] = {R(0), R(6) * Fu, -R(6) * Fu, Fx * dt, -Fx * dt, Fy * dt, -Fy * dt,
-            R(2) * (Fx * ux - Fy * uy) * dt * dt, (Fy * ux + Fx * uy) * dt * dt};
-  const R s[9] = {R(0), s_e, s_eps, R(0), s_q, R(0), s_q, s_nu, s_nu};
-  R mp[9];
+  const R G[9] = {R(0), R(6) * Fu, -R(6) * Fu, Fx * dt, -Fx * dt, Fy * dt, -Fy * dt,
+                  R(2) * (Fx * ux - Fy * uy) * dt * dt, (Fy * ux + Fx * uy) * dt * dt};
+  const R sr[9] = {R(0), s_e, s_eps, R(0), s_q, R(0), s_q, s_nu, s_nu};
+  R dm[9];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) mp[i] = m[i] - s[i] * (m[i] - meq[i]) + (R(1) - R(0.5) * s[i]) * G[i];
-  // f = M^-1 m^+ with M^-1 = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4)
-  const R a0 = mp[0] * R(1.0 / 9), a1 = mp[1] * R(1.0 / 36), a2 = mp[2] * R(1.0 / 36);
-  const R a3 = mp[3] * R(1.0 / 6), a4 = mp[4] * R(1.0 / 12), a5 = mp[5] * R(1.0 / 6), a6 = mp[6] * R(1.0 / 12);
-  const R a7 = mp[7] * R(0.25), a8 = mp[8] * R(0.25);
-  post[0] = a0 - R(4) * a1 + R(4) * a2;
-  post[1] = a0 - a1 - R(2) * a2 + a3 - R(2) * a4 + a7;
-  post[2] = a0 - a1 - R(2) * a2 + a5 - R(2) * a6 - a7;
-  post[3] = a0 - a1 - R(2) * a2 - a3 + R(2) * a4 + a7;
-  post[4] = a0 - a1 - R(2) * a2 - a5 + R(2) * a6 - a7;
-  post[5] = a0 + R(2) * a1 + a2 + a3 + a4 + a5 + a6 + a8;
-  post[6] = a0 + R(2) * a1 + a2 - a3 - a4 + a5 + a6 - a8;
-  post[7] = a0 + R(2) * a1 + a2 - a3 - a4 - a5 - a6 + a8;
-  post[8] = a0 + R(2) * a1 + a2 + a3 + a4 - a5 - a6 - a8;
+  for (int i = 0; i < 9; ++i) dm[i] = -sr[i] * neq[i] + (R(1) - R(0.5) * sr[i]) * G[i];
+  // f^+ - f = M^-1 dm, M^-1 = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4)
+  const R a0 = dm[0] * R(1.0 / 9), a1 = dm[1] * R(1.0 / 36), a2 = dm[2] * R(1.0 / 36);
+  const R a3 = dm[3] * R(1.0 / 6), a4 = dm[4] * R(1.0 / 12), a5 = dm[5] * R(1.0 / 6), a6 = dm[6] * R(1.0 / 12);
+  const R a7 = dm[7] * R(0.25), a8 = dm[8] * R(0.25);
+  dp[0] = d[0] + a0 - R(4) * a1 + R(4) * a2;
+  dp[1] = d[1] + a0 - a1 - R(2) * a2 + a3 - R(2) * a4 + a7;
+  dp[2] = d[2] + a0 - a1 - R(2) * a2 + a5 - R(2) * a6 - a7;
+  dp[3] = d[3] + a0 - a1 - R(2) * a2 - a3 + R(2) * a4 + a7;
+  dp[4] = d[4] + a0 - a1 - R(2) * a2 - a5 + R(2) * a6 - a7;
+  dp[5] = d[5] + a0 + R(2) * a1 + a2 + a3 + a4 + a5 + a6 + a8;
+  dp[6] = d[6] + a0 + R(2) * a1 + a2 - a3 - a4 + a5 + a6 - a8;
+  dp[7] = d[7] + a0 + R(2) * a1 + a2 - a3 - a4 - a5 - a6 + a8;
+  dp[8] = d[8] + a0 + R(2) * a1 + a2 + a3 + a4 - a5 - a6 - a8;
 }
 
 // The nine post-collision planes of a tile live in LDS, so a TY-row tile is
@@ -685,7 +701,8 @@ __global__ __launch_bounds__(NTHR) void k_flow(const Dom* __restrict__ doms, con
   constexpr int CW = TX + 2, CH = SUB + 2;
   static_assert(TY % SUB == 0, "tile height must be a multiple of the sub-tile height");
   __shared__ R sfl[CH * CW];
-  __shared__ R spost[9][CH * CW];
+  __shared__ R srho[CH * CW];
+  __shared__ R spost[9][CH * CW];   // f_i^+ - w_i rho of the cell
 
   const int4 t = tiles[blockIdx.x];
   if (t.x < 0) return;
@@ -709,32 +726,30 @@ __global__ __launch_bounds__(NTHR) void k_flow(const Dom* __restrict__ doms, con
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
   const int x0 = t.y;
   const R c = R(1) / dt;
+  const int fbxw = fbx == BC_PER ? BC_PER : BC_WALL, fbyw = fby == BC_PER ? BC_PER : BC_WALL;
 
   for (int y0 = t.z; y0 < t.z + TY && y0 < ny; y0 += SUB) {
     for (int i = tid; i < CW * CH; i += NTHR) {
       const int lx = i % CW, ly = i / CW;
       const int rx = x0 - 1 + lx, ry = y0 - 1 + ly;
-      const int gxg = ghost(rx, nx, fbx == BC_PER ? BC_PER : BC_WALL);
-      const int gyg = ghost(ry, ny, fby == BC_PER ? BC_PER : BC_WALL);
-      sfl[i] = (R(1) - phis[gyg * px + gxg]) * R(0.5);
-      const int gx = resolve(rx, nx, fbx == BC_PER ? BC_PER : BC_WALL);
-      const int gy = resolve(ry, ny, fby == BC_PER ? BC_PER : BC_WALL);
+      sfl[i] = (R(1) - phis[ghost(ry, ny, fbyw) * px + ghost(rx, nx, fbxw)]) * R(0.5);
+      const int gx = resolve(rx, nx, fbxw), gy = resolve(ry, ny, fbyw);
       if (gx < 0 || gy < 0) continue;
       const long long o = gy * px + gx;
       const R rho = rho_in[o];
-      R f[9];
+      R d[9];
       R ssum = R(0);
 #pragma unroll
       for (int q = 1; q < 9; ++q) {
-        const R sv = ld(s_in, o + (q - 1) * pl);
-        f[q] = w[q] * rho + sv;
-        ssum += sv;
+        d[q] = ld(s_in, o + (q - 1) * pl);
+        ssum += d[q];
       }
-      f[0] = w[0] * rho - ssum;
-      R post[9];
-      flow_collide(f, dt, Fx, Fy, se, seps, sq, snu, post);
+      d[0] = -ssum;
+      R dp[9];
+      flow_collide(rho, d, dt, Fx, Fy, se, seps, sq, snu, dp);
+      srho[i] = rho;
 #pragma unroll
-      for (int q = 0; q < 9; ++q) spost[q][i] = post[q];
+      for (int q = 0; q < 9; ++q) spost[q][i] = dp[q];
     }
     __syncthreads();
 
@@ -744,10 +759,20 @@ __global__ __launch_bounds__(NTHR) void k_flow(const Dom* __restrict__ doms, con
       if (gx >= nx || gy >= ny || gy >= t.z + TY) continue;
       if (fbx == BC_INOUT && gx == nx - 1 && nx > 1) continue;  // written by the x = nx-2 site
       const int ci = (ly + 1) * CW + tx + 1;
-      R fn[9];
+      // deviations d_i = f_i - w_i rho(y) of the new populations
+      R dn[9];
+      R rho_y;
       if (fbx == BC_INOUT && gx == 0) {
-        flow_eq(R(1), R(D.u_in), R(0), dt, fn);
+        // inlet: f = f^eq(1, (u_in, 0))
+        rho_y = R(1);
+        const R u = R(D.u_in) * dt;
+#pragma unroll
+        for (int q = 0; q < 9; ++q) {
+          const R eu = R(EX9[q]) * u;
+          dn[q] = w[q] * (R(3) * eu + R(4.5) * eu * eu - R(1.5) * u * u);
+        }
       } else {
+        rho_y = srho[ci];
         const R flo = sfl[ci];
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
@@ -755,22 +780,25 @@ __global__ __launch_bounds__(NTHR) void k_flow(const Dom* __restrict__ doms, con
           const int sx = gx - ex, sy = gy - ey;
           const bool out = ((sx < 0 || sx >= nx) && fbx != BC_PER) || ((sy < 0 || sy >= ny) && fby != BC_PER);
           const R bounce = spost[OPP9[q]][ci];
-          if (out || q == 0) {
-            fn[q] = q == 0 ? spost[0][ci] : bounce;
+          if (q == 0) {
+            dn[0] = spost[0][ci];
+          } else if (out) {
+            dn[q] = bounce;
           } else {
             const int si = ci - ey * CW - ex;
             const R m = R(0.5) * (flo + sfl[si]);
-            fn[q] = m * spost[q][si] + (R(1) - m) * bounce;     // Eq. (33)
+            dn[q] = m * (w[q] * (srho[si] - rho_y) + spost[q][si]) + (R(1) - m) * bounce;   // Eq. (33)
           }
         }
       }
-      R rho = R(0), jx = R(0), jy = R(0);
+      R drho = R(0), jx = R(0), jy = R(0);
 #pragma unroll
       for (int q = 0; q < 9; ++q) {
-        rho += fn[q];
-        jx += R(EX9[q]) * fn[q];
-        jy += R(EY9[q]) * fn[q];
+        drho += dn[q];
+        jx += R(EX9[q]) * dn[q];
+        jy += R(EY9[q]) * dn[q];
       }
+      const R rho = rho_y + drho;
       const R ux = (c * jx + dt * Fx * R(0.5)) / rho, uy = (c * jy + dt * Fy * R(0.5)) / rho;
       const int ncopy = (fbx == BC_INOUT && gx == nx - 2) ? 2 : 1;
       for (int cpy = 0; cpy < ncopy; ++cpy) {
@@ -779,7 +807,7 @@ __global__ __launch_bounds__(NTHR) void k_flow(const Dom* __restrict__ doms, con
         vel[o] = ux;
         vel[o + pl] = uy;
 #pragma unroll
-        for (int q = 1; q < 9; ++q) st(s_out, o + (q - 1) * pl, fn[q] - w[q] * rho);
+        for (int q = 1; q < 9; ++q) st(s_out, o + (q - 1) * pl, dn[q] - w[q] * drho);
       }
     }
     __syncthreads();

@@ -637,32 +637,33 @@ lbm_status lbm_kernel_times(lbm_ctx* c, int32_t reps, double* ms_out, double* pe
       if (per_step) per_step[kind] = 0.0;
       continue;
     }
-    auto launch = [&]() {
-      for (auto& g : gs) {
-        const long long k = due(g.N);
-        const dim3 grid(g.ts[ti].n);
+    // each group of domains sharing an update factor is timed on its own:
+    // ms_out is one launch over every domain, per_step the fraction of it
+    // spent per base step (groups weighted by how often they are due)
+    double all = 0.0, weighted = 0.0;
+    for (auto& g : gs) {
+      const long long k = due(g.N);
+      const dim3 grid(g.ts[ti].n);
+      auto launch = [&]() {
         if (kind == 0) c->ops.phase(TY, grid, c->stream, c->d_dom, g.ts[ti].d, k);
         if (kind == 1) c->ops.transfer(TY, grid, c->stream, c->d_dom, g.ts[ti].d, k, c->d_part);
         if (kind == 2) c->ops.scalar(0, TY, grid, c->stream, c->d_dom, g.ts[ti].d, k, c->d_part);
         if (kind == 3) c->ops.scalar(1, TY, grid, c->stream, c->d_dom, g.ts[ti].d, k, c->d_part);
         if (kind == 4) c->ops.flow(TY, grid, c->stream, c->d_dom, g.ts[ti].d, k);
-      }
-    };
-    launch();
-    HIPCHK(c, hipEventRecord(e0, c->stream));
-    for (int r = 0; r < reps; ++r) launch();
-    HIPCHK(c, hipEventRecord(e1, c->stream));
-    HIPCHK(c, hipEventSynchronize(e1));
-    float ms = 0;
-    HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
-    ms_out[kind] = double(ms) / reps;
-    if (per_step) {
-      // launches of this kind per base step over one cycle
-      double n = 0;
-      for (long long k = 1; k <= c->cycle; ++k)
-        for (auto& g : gs) n += (k % g.N == 0) ? 1.0 : 0.0;
-      per_step[kind] = n / double(c->cycle);
+      };
+      launch();
+      HIPCHK(c, hipEventRecord(e0, c->stream));
+      for (int r = 0; r < reps; ++r) launch();
+      HIPCHK(c, hipEventRecord(e1, c->stream));
+      HIPCHK(c, hipEventSynchronize(e1));
+      float ms = 0;
+      HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+      const double per_launch = double(ms) / reps;
+      all += per_launch;
+      weighted += per_launch / g.N;
     }
+    ms_out[kind] = all;
+    if (per_step) per_step[kind] = weighted / all;
   }
   HIPCHK(c, hipEventDestroy(e0));
   HIPCHK(c, hipEventDestroy(e1));
