@@ -130,6 +130,9 @@ def main() -> int:
     ap.add_argument("--cpu-child", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (counter calibration)")
+    ap.add_argument("--profile-steps", type=int, default=0, metavar="N",
+                    help="only run N warm-up and N measured base steps (for profiler runs); no JSON")
+    ap.add_argument("--tile-rows", type=int, default=0, help="fix the tile height (0 = autotune)")
     args = ap.parse_args()
 
     if args.cpu_child:
@@ -162,6 +165,16 @@ def main() -> int:
     cyc = cycle_of(wl)
     sites = sum(d["nx"] * d["ny"] for d in wl["domains"])
     sim = simulation_for(wl, storage=storage)
+    if args.tile_rows:
+        sim.configure(args.tile_rows, True)
+    if args.profile_steps:
+        sim.step(args.profile_steps)
+        torch.cuda.synchronize()
+        sim.step(args.profile_steps)
+        torch.cuda.synchronize()
+        sim.close()
+        print(json.dumps(dict(profile_steps=args.profile_steps, workload=wl["name"], storage=storage)), flush=True)
+        return 0
     # warm-up: autotune, graph capture, clocks
     sim.step(args.warmup * cyc)
     torch.cuda.synchronize()

@@ -38,25 +38,27 @@ __device__ __forceinline__ void st(float* p, long long i, float v) { p[i] = v; }
 __device__ __forceinline__ void st(__half* p, long long i, float v) { p[i] = __float2half(v); }
 __device__ __forceinline__ void st(__hip_bfloat16* p, long long i, float v) { p[i] = __float2bfloat16(v); }
 
+// Reciprocal and inverse square root: the hardware approximations (about
+// 1 ulp) in the FP32 path, exact division and square root in FP64.
+__device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ double rcp(double x) { return 1.0 / x; }
+__device__ __forceinline__ float rsq(float x) { return __builtin_amdgcn_rsqf(x); }
+__device__ __forceinline__ double rsq(double x) { return 1.0 / sqrt(x); }
+
 // Ghost index for stencils: wrap on periodic axes, clamp (even mirror about
-// the half-way wall) otherwise.
+// the half-way wall) otherwise.  Callers stay within two nodes of the domain
+// and every side is at least three nodes long.
 __device__ __forceinline__ int ghost(int g, int n, int bc) {
-  if (g >= 0 && g < n) return g;
-  if (bc == BC_PER) {
-    g %= n;
-    return g < 0 ? g + n : g;
-  }
-  return g < 0 ? 0 : n - 1;
+  if (g < 0) return bc == BC_PER ? g + n : 0;
+  if (g >= n) return bc == BC_PER ? g - n : n - 1;
+  return g;
 }
 
 // Site a raw coordinate refers to: wrapped on periodic axes, -1 beyond a wall.
 __device__ __forceinline__ int resolve(int g, int n, int bc) {
-  if (g >= 0 && g < n) return g;
-  if (bc == BC_PER) {
-    g %= n;
-    return g < 0 ? g + n : g;
-  }
-  return -1;
+  if (g < 0) return bc == BC_PER ? g + n : -1;
+  if (g >= n) return bc == BC_PER ? g - n : -1;
+  return g;
 }
 
 template <class R>
@@ -68,9 +70,10 @@ __device__ __forceinline__ void iso_grad(const R* b, int stride, R& gx, R& gy) {
   gy = (N - S) * R(1.0 / 3.0) + (NE + NW - SW - SE) * R(1.0 / 12.0);
 }
 
-// D2Q5: e_1 = +x, e_2 = +y, e_3 = -x, e_4 = -y.
-__constant__ int EX5[5] = {0, 1, 0, -1, 0};
-__constant__ int EY5[5] = {0, 0, 1, 0, -1};
+// D2Q5: e_1 = +x, e_2 = +y, e_3 = -x, e_4 = -y (compile-time tables so that
+// unrolled loops fold them into immediates).
+#define EX5(q) ((q) == 1 ? 1 : (q) == 3 ? -1 : 0)
+#define EY5(q) ((q) == 2 ? 1 : (q) == 4 ? -1 : 0)
 
 // =================================================================== phase
 // Collision of Eq. (14) with the equilibrium of Eq. (21), the relaxation of
@@ -97,8 +100,8 @@ __device__ __forceinline__ void phase_collide(const PhaseConst<R>& c, R phi, R g
   const R gg = gx * gx + gy * gy;
   R a_s = R(1), Nx = R(0), Ny = R(0);
   if (gg >= R(GRAD_EPS2)) {
-    const R g = sqrt(gg);
-    const R ig = R(1) / g;
+    const R ig = rsq(gg);
+    const R g = gg * ig;
     const R nx = -gx * ig, ny = -gy * ig;
     const R ax = c.cth * nx + c.sth * ny;
     const R ay = -c.sth * nx + c.cth * ny;
@@ -113,7 +116,7 @@ __device__ __forceinline__ void phase_collide(const PhaseConst<R>& c, R phi, R g
   }
   A = a_s * a_s;
   const R tau = R(3) * c.dt * A * c.W2t + R(0.5);
-  const R om = R(1) - R(1) / tau;
+  const R om = R(1) - rcp(tau);
   // v_n = -W0^2 N / tau0 ; j_eq = v_n dt
   const R jex = -c.W2t * Nx * c.dt;
   const R jey = -c.W2t * Ny * c.dt;
@@ -142,15 +145,21 @@ __device__ __forceinline__ bool ring_cell(int r, int w, int h, int& lx, int& ly)
 }
 
 // Load the tile's field plane plus two rings (ghosts wrapped or mirrored)
-// into LDS.  Issued before the first barrier together with every other
+// into LDS, BW = TX + 4 columns (thread column tx and, for tx < 4, tx + 64)
+// by BH rows.  Issued before the first barrier together with every other
 // global load of the block, so a block waits for memory once.
-template <class R>
-__device__ __forceinline__ void load_box2(R* box, const R* __restrict__ plane, long long px, int x0, int y0,
-                                          int nx, int ny, int bcx, int bcy, int BW, int BH, int tid) {
-  for (int i = tid; i < BW * BH; i += NTHR) {
-    const int lx = i % BW, ly = i / BW;
-    const int gx = ghost(x0 - 2 + lx, nx, bcx), gy = ghost(y0 - 2 + ly, ny, bcy);
-    box[i] = plane[gy * px + gx];
+template <class R, int BW, int BH>
+__device__ __forceinline__ void load_box2(R* box, const R* __restrict__ plane, int px, int x0, int y0, int nx,
+                                          int ny, int bcx, int bcy, int tx, int ty) {
+  static_assert(BW == TX + 4, "box width");
+  const int gx0 = ghost(x0 - 2 + tx, nx, bcx);
+  const bool two = tx < BW - TX;
+  const int gx1 = two ? ghost(x0 - 2 + tx + TX, nx, bcx) : 0;
+#pragma unroll
+  for (int ly = ty; ly < BH; ly += BY) {
+    const R* row = plane + ghost(y0 - 2 + ly, ny, bcy) * px;
+    box[ly * BW + tx] = row[gx0];
+    if (two) box[ly * BW + tx + TX] = row[gx1];
   }
 }
 
@@ -170,7 +179,7 @@ __global__ __launch_bounds__(NTHR) void k_phase(const Dom* __restrict__ doms, co
   const Dom& D = doms[t.x];
   if (k % D.N_phi) return;
   const int nx = D.nx, ny = D.ny;
-  const long long px = D.px, pl = D.plane;
+  const int px = D.px, pl = (int)D.plane;
   const int x0 = t.y, y0 = t.z;
   const int w = min(TX, nx - x0), h = min(TY, ny - y0);
   const int bcx = D.bc[0], bcy = D.bc[1];
@@ -199,6 +208,7 @@ __global__ __launch_bounds__(NTHR) void k_phase(const Dom* __restrict__ doms, co
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
   // sites of this thread: RPT owned sites, then at most one ring cell
   int cl[NS];                 // collision-box index (-1: inactive)
+  int bi[NS];                 // the same cell in the phi box
   R sv[NS][4], Uv[NS], Tv[NS];
 #pragma unroll
   for (int r = 0; r < NS; ++r) {
@@ -217,7 +227,8 @@ __global__ __launch_bounds__(NTHR) void k_phase(const Dom* __restrict__ doms, co
       if (gx < 0 || gy < 0) continue;  // beyond a wall: never pulled from
     }
     cl[r] = ly * CW + lx;
-    const long long o = gy * px + gx;
+    bi[r] = (ly + 1) * BW + lx + 1;
+    const unsigned o = gy * px + gx;
     sv[r][0] = ld(s_in, o);
     sv[r][1] = ld(s_in, o + pl);
     sv[r][2] = ld(s_in, o + 2 * pl);
@@ -225,15 +236,14 @@ __global__ __launch_bounds__(NTHR) void k_phase(const Dom* __restrict__ doms, co
     Uv[r] = Up ? Up[o] : R(0);
     Tv[r] = Tp ? Tp[o] : c.theta_off;
   }
-  load_box2(sphi, phi_in, px, x0, y0, nx, ny, bcx, bcy, BW, BH, tid);
+  load_box2<R, BW, BH>(sphi, phi_in, px, x0, y0, nx, ny, bcx, bcy, tx, ty);
   __syncthreads();
 
   R Aown[RPT];
 #pragma unroll
   for (int r = 0; r < NS; ++r) {
     if (cl[r] < 0) continue;
-    const int lx = cl[r] % CW, ly = cl[r] / CW;
-    const R* b = &sphi[(ly + 1) * BW + lx + 1];
+    const R* b = &sphi[bi[r]];
     R gx_, gy_;
     iso_grad(b, BW, gx_, gy_);
     R dP, Kx, Ky, A;
@@ -252,19 +262,21 @@ __global__ __launch_bounds__(NTHR) void k_phase(const Dom* __restrict__ doms, co
   for (int r = 0; r < RPT; ++r) {
     if (cl[r] < 0) continue;
     const int ci = cl[r];
-    const int bc = ci + (ci / CW) * (BW - CW) + BW + 1;   // same site in the phi box
+    const int bc = bi[r];
     const int gx = x0 + tx, gy = y0 + ty + r * BY;
-    const R A = Aown[r], iA = R(1) / A, oA = R(1) - A;
+    const R A = Aown[r], iA = rcp(A), oA = R(1) - A;
     const R phy = sphi[bc];
     const R dPo = sP[ci], Kxo = sKx[ci], Kyo = sKy[ci];
     const R s0 = -(sv[r][0] + sv[r][1] + sv[r][2] + sv[r][3]);
+    // directions whose upstream node lies beyond a wall (bounce-back)
+    const bool wx = bcx != BC_PER, wy = bcy != BC_PER;
+    const bool bb[5] = {false, wx && gx == 0, wy && gy == 0, wx && gx == nx - 1, wy && gy == ny - 1};
     R dn[5];
     dn[0] = (dPo * R(1.0 / 3.0) - oA * s0) * iA;
 #pragma unroll
     for (int q = 1; q < 5; ++q) {
-      const int ex = EX5[q], ey = EY5[q];
-      const int sx = gx - ex, sy = gy - ey;
-      const bool wall = ((sx < 0 || sx >= nx) && bcx != BC_PER) || ((sy < 0 || sy >= ny) && bcy != BC_PER);
+      const int ex = EX5(q), ey = EY5(q);
+      const bool wall = bb[q];
       R dpost;
       if (wall) {
         dpost = dPo * R(1.0 / 6.0) - R(0.5) * (R(ex) * Kxo + R(ey) * Kyo);
@@ -276,7 +288,7 @@ __global__ __launch_bounds__(NTHR) void k_phase(const Dom* __restrict__ doms, co
       dn[q] = (dpost - oA * sv[r][q - 1]) * iA;
     }
     const R dphin = dn[0] + dn[1] + dn[2] + dn[3] + dn[4];
-    const long long o = gy * px + gx;
+    const unsigned o = gy * px + gx;
     phi_out[o] = phy + dphin;
     const R w6 = dphin * R(1.0 / 6.0);
     st(s_out, o, dn[1] - w6);
@@ -312,7 +324,7 @@ __global__ __launch_bounds__(NTHR) void k_transfer(const Dom* __restrict__ doms,
   const Dom& D = doms[t.x];
   if (k % D.N_phi) return;
   const int nx = D.nx, ny = D.ny;
-  const long long px = D.px;
+  const int px = D.px;
   const int x0 = t.y, y0 = t.z;
   const int w = min(TX, nx - x0), h = min(TY, ny - y0);
   const int bcx = D.bc[0], bcy = D.bc[1];
@@ -337,11 +349,11 @@ __global__ __launch_bounds__(NTHR) void k_transfer(const Dom* __restrict__ doms,
     for (int r = 0; r < RPT; ++r) {
       const int gx = x0 + tx, gy = y0 + ty + r * BY;
       if (tx >= w || ty + r * BY >= h) continue;
-      const long long o = gy * px + gx;
+      const unsigned o = gy * px + gx;
       const R pn = phi_new[o];
       const R dphi = pn - phi_old[o];
       const R rc = (R(1) + pn) * R(0.5) * rcS + (R(1) - pn) * R(0.5) * rcL;
-      const R dT = cT * dphi / (R(2) * rc);
+      const R dT = cT * dphi * rcp(R(2) * rc);
       if (D.accum)
         PT[o] = PT[o] + dT;
       else
@@ -376,12 +388,12 @@ __global__ __launch_bounds__(NTHR) void k_transfer(const Dom* __restrict__ doms,
     bi[r] = (ry - (y0 - 2)) * BW + rx - (x0 - 2);
     mxs[r] = mx;
     mys[r] = my;
-    const long long o = (long long)ghost(ry, ny, bcy) * px + ghost(rx, nx, bcx);
+    const unsigned o = ghost(ry, ny, bcy) * px + ghost(rx, nx, bcx);
     pold[r] = phi_old[o];
     Us[r] = Uin[o];
     if (r < RPT && D.has_T) Tv[r] = D.accum ? PT[o] : Tcur[o];
   }
-  load_box2(sphi, phi_new, px, x0, y0, nx, ny, bcx, bcy, BW, BH, tid);
+  load_box2<R, BW, BH>(sphi, phi_new, px, x0, y0, nx, ny, bcx, bcy, tx, ty);
   __syncthreads();
 #pragma unroll
   for (int r = 0; r < NS; ++r) {
@@ -392,7 +404,7 @@ __global__ __launch_bounds__(NTHR) void k_transfer(const Dom* __restrict__ doms,
     const R gg = gxv * gxv + gyv * gyv;
     R Jx = R(0), Jy = R(0);
     if (gg >= R(GRAD_EPS2)) {
-      const R ig = R(1) / sqrt(gg);
+      const R ig = rsq(gg);
       const R a = cJ * (R(1) + omk * Us[r]) * (b[0] - pold[r]) * ig;
       Jx = -a * gxv;
       Jy = -a * gyv;
@@ -407,7 +419,7 @@ __global__ __launch_bounds__(NTHR) void k_transfer(const Dom* __restrict__ doms,
   for (int r = 0; r < RPT; ++r) {
     if (cl[r] < 0) continue;
     const int ci = cl[r];
-    const long long o = (long long)(y0 + ty + r * BY) * px + x0 + tx;
+    const unsigned o = (y0 + ty + r * BY) * px + x0 + tx;
     const R pn = sphi[bi[r]];
     const R dphi = pn - pold[r];
     const R* jx = &sJx[ci];
@@ -416,7 +428,7 @@ __global__ __launch_bounds__(NTHR) void k_transfer(const Dom* __restrict__ doms,
                   (jx[CW + 1] - jx[CW - 1] - jx[-CW - 1] + jx[-CW + 1]) * R(1.0 / 12.0) +
                   (jy[CW] - jy[-CW]) * R(1.0 / 3.0) +
                   (jy[CW + 1] + jy[CW - 1] - jy[-CW - 1] - jy[-CW + 1]) * R(1.0 / 12.0);
-    const R dU = ((R(1) + omk * Us[r]) * dphi - R(2) * div) / (opk - omk * pn);
+    const R dU = ((R(1) + omk * Us[r]) * dphi - R(2) * div) * rcp(opk - omk * pn);
     amax = fmax(amax, fabs(dU));
     if (D.accum)
       PU[o] = PU[o] + dU;
@@ -424,7 +436,7 @@ __global__ __launch_bounds__(NTHR) void k_transfer(const Dom* __restrict__ doms,
       Uout[o] = Us[r] + dU;
     if (D.has_T) {
       const R rc = (R(1) + pn) * R(0.5) * rcS + (R(1) - pn) * R(0.5) * rcL;
-      const R dT = cT * dphi / (R(2) * rc);
+      const R dT = cT * dphi * rcp(R(2) * rc);
       if (D.accum)
         PT[o] = Tv[r] + dT;
       else
@@ -469,7 +481,7 @@ __global__ __launch_bounds__(NTHR) void k_scalar(const Dom* __restrict__ doms, c
   const int N = FIELD == 0 ? D.N_U : D.N_T;
   if (k % N) return;
   const int nx = D.nx, ny = D.ny;
-  const long long px = D.px, pl = D.plane;
+  const int px = D.px, pl = (int)D.plane;
   const int x0 = t.y, y0 = t.z;
   const int w = min(TX, nx - x0), h = min(TY, ny - y0);
   const int bcx = D.bc[0], bcy = D.bc[1];
@@ -500,9 +512,10 @@ __global__ __launch_bounds__(NTHR) void k_scalar(const Dom* __restrict__ doms, c
   const R omk = R(1.0 - D.kc), opk = R(1.0 + D.kc);
   const R DS = R(D.D_S), DL = R(D.D_L);
   const R kS = R(D.kS), kL = R(D.kL), rcS = R(D.rcS), rcL = R(D.rcL);
+  const R itau_const = rcp(R(3) * dt * (kL / rcL) + R(0.5));
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
 
-  int cl[NS];
+  int cl[NS], bi[NS];
   R chi[NS], jxv[NS], jyv[NS], uxv[NS], uyv[NS], pv[RPT];
 #pragma unroll
   for (int r = 0; r < NS; ++r) {
@@ -521,7 +534,8 @@ __global__ __launch_bounds__(NTHR) void k_scalar(const Dom* __restrict__ doms, c
       if (gx < 0 || gy < 0) continue;
     }
     cl[r] = ly * CW + lx;
-    const long long o = gy * px + gx;
+    bi[r] = (ly + 1) * BW + lx + 1;
+    const unsigned o = gy * px + gx;
     chi[r] = cin[o];
     jxv[r] = ld(jin, o);
     jyv[r] = ld(jin, o + pl);
@@ -529,38 +543,37 @@ __global__ __launch_bounds__(NTHR) void k_scalar(const Dom* __restrict__ doms, c
     uyv[r] = vel ? vel[o + pl] : R(0);
     if (r < RPT && D.accum) pv[r] = pend[o];
   }
-  if (need_phi) load_box2(sphi, phis, px, x0, y0, nx, ny, bcx, bcy, BW, BH, tid);
+  if (need_phi) load_box2<R, BW, BH>(sphi, phis, px, x0, y0, nx, ny, bcx, bcy, tx, ty);
   __syncthreads();
 
 #pragma unroll
   for (int r = 0; r < NS; ++r) {
     if (cl[r] < 0) continue;
-    const int lx = cl[r] % CW, ly = cl[r] / CW;
-    const R* b = &sphi[(ly + 1) * BW + lx + 1];
+    const R* b = &sphi[bi[r]];
     const R jex = chi[r] * uxv[r] * dt, jey = chi[r] * uyv[r] * dt;
-    R tau, Q = R(0);
+    R itau, Q = R(0);
     if (FIELD == 0) {
       const R phi = b[0];
-      const R kf = opk - omk * phi;
-      const R coeff = ((R(1) + phi) * DS + (R(1) - phi) * DL) / kf;             // Eq. (7)
-      tau = R(3) * dt * coeff + R(0.5);
-      const R gcx = -R(3) / tau * (jxv[r] - jex), gcy = -R(3) / tau * (jyv[r] - jey);  // Eq. (40)
+      const R ikf = rcp(opk - omk * phi);
+      const R coeff = ((R(1) + phi) * DS + (R(1) - phi) * DL) * ikf;            // Eq. (7)
+      itau = rcp(R(3) * dt * coeff + R(0.5));
+      const R gcx = -R(3) * itau * (jxv[r] - jex), gcy = -R(3) * itau * (jyv[r] - jey);  // Eq. (40)
       R gpx, gpy;
       iso_grad(b, BW, gpx, gpy);
-      Q = -omk * coeff * (gcx * gpx + gcy * gpy) / kf;                           // Eq. (8), 1st term
+      Q = -omk * coeff * (gcx * gpx + gcy * gpy) * ikf;                          // Eq. (8), 1st term
     } else if (D.T_var) {
       const R phi = b[0];
-      const R rc = (R(1) + phi) * R(0.5) * rcS + (R(1) - phi) * R(0.5) * rcL;
-      const R coeff = ((R(1) + phi) * R(0.5) * kS + (R(1) - phi) * R(0.5) * kL) / rc;  // Eq. (11)
-      tau = R(3) * dt * coeff + R(0.5);
-      const R gcx = -R(3) / tau * (jxv[r] - jex), gcy = -R(3) / tau * (jyv[r] - jey);
+      const R irc = rcp((R(1) + phi) * R(0.5) * rcS + (R(1) - phi) * R(0.5) * rcL);
+      const R coeff = ((R(1) + phi) * R(0.5) * kS + (R(1) - phi) * R(0.5) * kL) * irc;  // Eq. (11)
+      itau = rcp(R(3) * dt * coeff + R(0.5));
+      const R gcx = -R(3) * itau * (jxv[r] - jex), gcy = -R(3) * itau * (jyv[r] - jey);
       R gpx, gpy;
       iso_grad(b, BW, gpx, gpy);
-      Q = (rcS - rcL) / (R(2) * rc) * coeff * (gcx * gpx + gcy * gpy);          // Eq. (12), 1st term
+      Q = (rcS - rcL) * R(0.5) * irc * coeff * (gcx * gpx + gcy * gpy);         // Eq. (12), 1st term
     } else {
-      tau = R(3) * dt * (kL / rcL) + R(0.5);
+      itau = itau_const;
     }
-    const R om = R(1) - R(1) / tau;
+    const R om = R(1) - itau;
     sC[cl[r]] = chi[r];
     sP[cl[r]] = dt * Q;
     sKx[cl[r]] = jex + om * (jxv[r] - jex);
@@ -576,21 +589,21 @@ __global__ __launch_bounds__(NTHR) void k_scalar(const Dom* __restrict__ doms, c
     const int ci = cl[r];
     const int gx = x0 + tx, gy = y0 + ty + r * BY;
     const R cy = sC[ci], dPo = sP[ci], Kxo = sKx[ci], Kyo = sKy[ci];
+    const bool wx = bcx != BC_PER, wy = bcy != BC_PER;
+    const bool bb[5] = {false, wx && gx == 0, wy && gy == 0, wx && gx == nx - 1, wy && gy == ny - 1};
     R dq[5];
     dq[0] = dPo * R(1.0 / 3.0);
 #pragma unroll
     for (int q = 1; q < 5; ++q) {
-      const int ex = EX5[q], ey = EY5[q];
-      const int sx = gx - ex, sy = gy - ey;
-      const bool wall = ((sx < 0 || sx >= nx) && bcx != BC_PER) || ((sy < 0 || sy >= ny) && bcy != BC_PER);
-      if (wall) {
+      const int ex = EX5(q), ey = EY5(q);
+      if (bb[q]) {
         dq[q] = dPo * R(1.0 / 6.0) - R(0.5) * (R(ex) * Kxo + R(ey) * Kyo);
       } else {
         const int si = ci - ey * CW - ex;
         dq[q] = (sC[si] - cy + sP[si]) * R(1.0 / 6.0) + R(0.5) * (R(ex) * sKx[si] + R(ey) * sKy[si]);
       }
     }
-    const long long o = gy * px + gx;
+    const unsigned o = gy * px + gx;
     R chin = cy + (dq[0] + dq[1] + dq[2] + dq[3] + dq[4]);
     if (D.accum) {
       chin += pv[r];
@@ -618,9 +631,9 @@ __global__ __launch_bounds__(NTHR) void k_scalar(const Dom* __restrict__ doms, c
 // bounce-back of Eq. (33) in pull form with f_L = (1 - phi*)/2, inlet
 // equilibrium at x = 0 and zero-gradient outflow at x = nx - 1 when the x
 // boundary is inlet/outflow.
-__constant__ int EX9[9] = {0, 1, 0, -1, 0, 1, -1, -1, 1};
-__constant__ int EY9[9] = {0, 0, 1, 0, -1, 1, 1, -1, -1};
-__constant__ int OPP9[9] = {0, 3, 4, 1, 2, 7, 8, 5, 6};
+#define EX9(q) ((q) == 1 || (q) == 5 || (q) == 8 ? 1 : (q) == 3 || (q) == 6 || (q) == 7 ? -1 : 0)
+#define EY9(q) ((q) == 2 || (q) == 5 || (q) == 6 ? 1 : (q) == 4 || (q) == 7 || (q) == 8 ? -1 : 0)
+#define OPP9(q) ((q) == 0 ? 0 : (q) <= 4 ? (((q) + 1) & 3) + 1 : (((q) - 3) & 3) + 5)
 
 template <class R>
 __device__ __forceinline__ void flow_eq(R rho, R ux, R uy, R dt, R* feq) {
@@ -630,7 +643,7 @@ __device__ __forceinline__ void flow_eq(R rho, R ux, R uy, R dt, R* feq) {
                   R(1.0 / 36), R(1.0 / 36), R(1.0 / 36), R(1.0 / 36)};
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
-    const R eu = (R(EX9[i]) * ux + R(EY9[i]) * uy) * dt;
+    const R eu = (R(EX9(i)) * ux + R(EY9(i)) * uy) * dt;
     feq[i] = w[i] * rho * (R(1) + R(3) * eu + R(4.5) * eu * eu - R(1.5) * u2);
   }
 }
@@ -655,8 +668,9 @@ __device__ __forceinline__ void flow_collide(R rho, const R* d, R dt, R Fx, R Fy
   md[7] = d[1] - d[2] + d[3] - d[4];
   md[8] = d[5] - d[6] + d[7] - d[8];
   // velocity (Eq. 27) and u / c = u dt
-  const R ux = (c * md[3] + dt * Fx * R(0.5)) / rho;
-  const R uy = (c * md[5] + dt * Fy * R(0.5)) / rho;
+  const R irho = rcp(rho);
+  const R ux = (c * md[3] + dt * Fx * R(0.5)) * irho;
+  const R uy = (c * md[5] + dt * Fy * R(0.5)) * irho;
   const R Ux = ux * dt, Uy = uy * dt, U2 = Ux * Ux + Uy * Uy;
   // m - m^eq (Eq. 29); the conserved rows 0, 3, 5 relax at rate 0
   R neq[9];
@@ -768,7 +782,7 @@ __global__ __launch_bounds__(NTHR) void k_flow(const Dom* __restrict__ doms, con
         const R u = R(D.u_in) * dt;
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
-          const R eu = R(EX9[q]) * u;
+          const R eu = R(EX9(q)) * u;
           dn[q] = w[q] * (R(3) * eu + R(4.5) * eu * eu - R(1.5) * u * u);
         }
       } else {
@@ -776,10 +790,10 @@ __global__ __launch_bounds__(NTHR) void k_flow(const Dom* __restrict__ doms, con
         const R flo = sfl[ci];
 #pragma unroll
         for (int q = 0; q < 9; ++q) {
-          const int ex = EX9[q], ey = EY9[q];
+          const int ex = EX9(q), ey = EY9(q);
           const int sx = gx - ex, sy = gy - ey;
           const bool out = ((sx < 0 || sx >= nx) && fbx != BC_PER) || ((sy < 0 || sy >= ny) && fby != BC_PER);
-          const R bounce = spost[OPP9[q]][ci];
+          const R bounce = spost[OPP9(q)][ci];
           if (q == 0) {
             dn[0] = spost[0][ci];
           } else if (out) {
@@ -795,11 +809,12 @@ __global__ __launch_bounds__(NTHR) void k_flow(const Dom* __restrict__ doms, con
 #pragma unroll
       for (int q = 0; q < 9; ++q) {
         drho += dn[q];
-        jx += R(EX9[q]) * dn[q];
-        jy += R(EY9[q]) * dn[q];
+        jx += R(EX9(q)) * dn[q];
+        jy += R(EY9(q)) * dn[q];
       }
       const R rho = rho_y + drho;
-      const R ux = (c * jx + dt * Fx * R(0.5)) / rho, uy = (c * jy + dt * Fy * R(0.5)) / rho;
+      const R irho = rcp(rho);
+      const R ux = (c * jx + dt * Fx * R(0.5)) * irho, uy = (c * jy + dt * Fy * R(0.5)) * irho;
       const int ncopy = (fbx == BC_INOUT && gx == nx - 2) ? 2 : 1;
       for (int cpy = 0; cpy < ncopy; ++cpy) {
         const long long o = gy * px + gx + cpy;

@@ -173,6 +173,8 @@ std::string validate(const lbm_params& p, int i) {
   if (p.dim != 2) return bad("only dim = 2 is supported");
   if (p.nz != 1) return bad("nz must be 1 in 2D");
   if (p.nx < 3 || p.ny < 3 || p.nx > (1 << 16) || p.ny > (1 << 16)) return bad("grid sides must be in [3, 65536]");
+  // in-plane offsets (up to 8 planes apart) are 32-bit in the kernels
+  if ((long long)((p.nx + 63) / 64 * 64) * p.ny > (1LL << 27)) return bad("more than 2^27 sites in one domain");
   if (p.q_scalar != 5) return bad("scalar lattice must be D2Q5 (q_scalar = 5)");
   if (p.N_phi < 1 || p.N_U < 1 || p.N_T < 1 || p.N_F < 1) return bad("update factors must be >= 1");
   if (!(p.dt_base > 0)) return bad("dt_base must be > 0");
