@@ -33,7 +33,12 @@ notes of the HIP library):
   * several seeds: phi = max over seeds; crystal orientation theta_c rotates
     the normal into the crystal frame for a_s and N and rotates N back;
   * accumulated coupling ("accum"): the phase-change increments are summed
-    and injected right after the field's next transport update.
+    and injected right after the field's next transport update;
+  * pulled temperature (3D directional case, T_mode "pulled"): T is carried
+    by its lattice with the pulling velocity V z^ in its equilibrium, receives
+    no latent heat, and the bottom and top walls hold the moving linear
+    profile T_L + G (z - z_front - V t) by anti-bounce-back; the linear
+    profile is then an exact solution of the T lattice.
 """
 
 from __future__ import annotations
@@ -182,20 +187,38 @@ class Domain:
         self.f_phi = w * self.phi[None]
         self.U = np.full(self.shape, float(d["U0"]))
         self.T = np.full(self.shape, float(d["T0"]))
+        if d.get("T_mode") == "pulled":
+            self.T = self.pulled_T(self.coords()[nd - 1], 0.0)
         if d["has_U"]:
             self.f_U = self.scalar_eq(self.U, P.dt_field(d, "U"))
         if d["has_T"]:
-            self.f_T = self.scalar_eq(self.T, P.dt_field(d, "T"))
+            self.f_T = self.scalar_eq(self.T, P.dt_field(d, "T"), self.velocity_T())
         if d["has_flow"]:
             self.f_F = self.flow_eq(self.rho, self.u, P.dt_field(d, "F"))
         self.P_U = np.zeros(self.shape)
         self.P_T = np.zeros(self.shape)
 
     # ------------------------------------------------------------- equilibria
-    def scalar_eq(self, chi, dt):
-        """Eq. (19): f_i^eq = w_i chi (1 + 3 e_i.u / c) with c = 1/dt."""
+    def scalar_eq(self, chi, dt, u=None):
+        """Eq. (19): f_i^eq = w_i chi (1 + 3 e_i.u / c) with c = 1/dt (the
+        factor 3 is 1/c_s^2 of the scalar lattice)."""
         w = _wq(self.ls, self.dim)
-        return w * chi[None] * (1.0 + self.inv_cs2 * _edot(self.ls, self.u) * dt)
+        u = self.u if u is None else u
+        return w * chi[None] * (1.0 + self.inv_cs2 * _edot(self.ls, u) * dt)
+
+    def velocity_T(self):
+        """Advection velocity of T: the flow velocity, plus the pulling
+        velocity V along the last axis for the pulled temperature."""
+        if self.d.get("T_mode") != "pulled":
+            return self.u
+        u = self.u.copy()
+        u[self.dim - 1] = u[self.dim - 1] + self.d["V_pull"]
+        return u
+
+    def pulled_T(self, z, t):
+        """Moving linear profile T_L + G (z - z_front - V t), T_L = T0."""
+        d = self.d
+        return d["T0"] + d["T_grad"] * (z - d["z_front"] - d["V_pull"] * t)
 
     def flow_eq(self, rho, u, dt):
         """Eq. (28) with c_F = 1/dt_F."""
@@ -256,7 +279,7 @@ class Domain:
                 self.J_U = self.S_phi
             else:
                 self.P_U = self.P_U + dU
-        if d["has_T"] and d.get("T_mode", "transport") == "transport":
+        if d["has_T"] and d.get("T_mode", "transport") != "pulled":
             dT = d["rho_L"] * d["L_h"] * dphi / (2.0 * P.rhoCp_eff(d, phi_new))  # Eq. (38)
             if d["coupling"] == "instant":
                 self.T = self.T + dT
@@ -282,7 +305,8 @@ class Domain:
         else:
             coeff = P.alpha_eff(d, phis)
         tau = self.inv_cs2 * dt * coeff + 0.5                            # Eq. (24)
-        feq = self.scalar_eq(chi, dt)
+        uadv = self.u if which == "U" else self.velocity_T()
+        feq = self.scalar_eq(chi, dt, uadv)
         E = ls.e.astype(np.float64)
         neq = f - feq
         grad_chi = -(self.inv_cs2 / tau)[None] * np.tensordot(E[1:].T, neq[1:], axes=(1, 0))  # Eq. (40)
@@ -296,6 +320,23 @@ class Domain:
         w = _wq(ls, nd)
         post = mrt_collide(ls, f, feq, scalar_relaxation(ls, tau)) + dt * w * Qtr[None]
         f_new = pull(post, ls, self.bc)                                   # Eq. (25)
+        if which == "T" and d.get("T_mode") == "pulled":
+            # anti-bounce-back on the walls of the last axis: populations whose
+            # upstream node lies beyond the wall z_w = -1/2 or nz - 1/2 become
+            # -f^+_ibar(y) + 2 w_i T(z_w) at the middle of the T step
+            ax = nd - 1
+            n = self.shape[0]
+            t_mid = (self.k - 0.5 * d["N_T"]) * d["dt_base"]
+            for i in range(ls.Q):
+                ez = int(ls.e[i, ax])
+                if ez == 0:
+                    continue
+                zw = -0.5 if ez > 0 else n - 0.5
+                src = np.arange(n) - ez
+                m = ((src < 0) | (src >= n)).reshape((n,) + (1,) * (nd - 1))
+                m = np.broadcast_to(m, self.shape)
+                abb = -post[ls.opp[i]] + 2.0 * ls.w[i] * self.pulled_T(zw, t_mid)
+                f_new[i] = np.where(m, abb, f_new[i])
         chi_new = f_new.sum(axis=0)
         if d["coupling"] != "instant":
             Pend = self.P_U if which == "U" else self.P_T
@@ -405,8 +446,7 @@ class Domain:
         if d["has_U"] and k % d["N_U"] == 0:
             self.scalar_step("U")
         if d["has_T"] and k % d["N_T"] == 0:
-            if d.get("T_mode", "transport") == "transport":
-                self.scalar_step("T")
+            self.scalar_step("T")
         if d["has_flow"] and k % d["N_F"] == 0:
             self.flow_step()
 
