@@ -64,10 +64,16 @@ enum {
   LBM_F_PEND_U = 1 << 9, /* pending U increments (accumulated coupling)      */
   LBM_F_PEND_T = 1 << 10,/* pending T increments (accumulated coupling)      */
   LBM_F_SPHI = 1 << 11,  /* stored phase planes s_i = f_i - w_i phi, i>=1 (4) */
-  LBM_F_SF = 1 << 12     /* stored flow planes s_i = f_i - w_i rho, i>=1  (8) */
+  LBM_F_SF = 1 << 12,    /* stored flow planes s_i = f_i - w_i rho, i>=1  (8) */
+  LBM_F_SU = 1 << 13,    /* stored U plane U - U0                 (1 plane)  */
+  LBM_F_ST = 1 << 14     /* stored T plane T - T0                 (1 plane)  */
 };
-/* A checkpoint that restores bit for bit is the set
- * PHI | U | T | RHO | VEL | JU | JT | PEND_U | PEND_T | SPHI | SF
+/* (In 3D the population groups hold 7 and 19 planes and SPHI / SF 6 and 18.)
+ * The U and T planes are kept as the shifts U - U0 and T - T0 from the
+ * initial values, so that FP32 keeps the small far-field increments; U and
+ * T read and write absolute values, SU and ST the stored shifts.
+ * A checkpoint that restores bit for bit is the set
+ * PHI | SU | ST | RHO | VEL | JU | JT | PEND_U | PEND_T | SPHI | SF
  * (the fields a domain carries), read and written back as FP64. */
 
 /* boundary kinds, per axis */
@@ -78,13 +84,17 @@ enum { LBM_STORE_F64 = 0, LBM_STORE_F32 = 1, LBM_STORE_F16 = 2, LBM_STORE_BF16 =
  * variant that sums increments and injects them after the field's next
  * transport update (the ablation of Section 4.4) */
 enum { LBM_COUPLE_INSTANT = 0, LBM_COUPLE_ACCUM = 1 };
+/* temperature field: transported with latent heat (Eq. 10-12, 38), or the
+ * pulled profile of 3D directional solidification: advected at V_pull along
+ * z, no latent heat, z walls held at the moving linear profile */
+enum { LBM_T_TRANSPORT = 0, LBM_T_PULLED = 1 };
 
 /* Parameters of one domain (host memory, FP64, lattice units).  Field
  * names follow the paper's notation. */
 typedef struct {
-  int32_t dim;            /* 2 (3D is reserved)                              */
+  int32_t dim;            /* 2, or 3 (single-domain contexts only)           */
   int32_t nx, ny, nz;     /* grid size; nz = 1 in 2D                         */
-  int32_t q_scalar;       /* scalar lattice: 5 (D2Q5)                        */
+  int32_t q_scalar;       /* scalar lattice: 5 (D2Q5) in 2D, 7 (D3Q7) in 3D  */
   int32_t has_U, has_T, has_flow;
   int32_t N_phi, N_U, N_T, N_F;         /* update factors (Eq. 34), >= 1     */
   double dt_base;                       /* baseline step (Eq. 34)            */
@@ -100,9 +110,14 @@ typedef struct {
   double U0, T0;                        /* initial uniform U and T           */
   int32_t u0_liquid_only;               /* initial u = u_in (1 - phi)/2 x^  */
   int32_t coupling;                     /* LBM_COUPLE_*                      */
+  int32_t T_mode;                       /* LBM_T_TRANSPORT or LBM_T_PULLED   */
+  int32_t pad;
+  double T_grad, V_pull, z_front;       /* pulled temperature (3D):
+                                           T0 + T_grad (z - z_front - V_pull t) */
 } lbm_params;
 
-/* Per-domain diagnostics (FP64 reductions on the device). */
+/* Per-domain diagnostics (FP64 reductions on the device).  In 3D, tip[0]
+ * is the highest and tip[1] the mean phi = 0 crossing height over columns. */
 typedef struct {
   int64_t step;            /* base steps completed                           */
   double solid;            /* sum (1 + phi)/2                                */
@@ -142,6 +157,14 @@ lbm_status lbm_create(const lbm_params* p, int32_t n_domains, int32_t storage,
  * Seeds (<= 4 per domain) are also the origins of the tip diagnostics. */
 lbm_status lbm_init_seeds(lbm_ctx* ctx, int32_t domain, int32_t n_seeds,
                           const double* centres, const double* radii);
+
+/* Initialise a 3D domain with a planar solid layer along z:
+ * phi = tanh[(z_front + xi(x, y) - z)/(sqrt2 W0)] (a random form of the
+ * Section 4.4 initial condition, Eq. 41), U = U0, T = T0 or the pulled
+ * profile, flow at rest, populations at equilibrium.
+ *   xi  host, nx * ny column offsets (x fastest), or NULL for a flat front.
+ * Resets the step counter.  LBM_EINVAL for a 2D domain. */
+lbm_status lbm_init_front(lbm_ctx* ctx, int32_t domain, const double* xi);
 
 /* Advance every domain by n_base_steps base steps of Eq. (34): at base
  * step k a field runs iff k mod N_chi == 0, in the order phase (+ the

@@ -22,13 +22,15 @@ enum Bc { BC_PER = 0, BC_WALL = 1, BC_INOUT = 2 };
 // (pitch px, x fastest).  R = FP64 when the context stores FP64, else FP32;
 // S = the population storage type.
 struct Dom {
-  int nx, ny, px, pad0;
-  long long plane;              // elements per plane
-  int bc[2];                    // scalar boundaries (x, y)
-  int fbc[2];                   // flow boundaries (x, y)
+  int nx, ny, nz, px;           // nz = 1 in 2D
+  long long plane;              // elements per plane (px * ny * nz)
+  int bc[3];                    // scalar boundaries (x, y, z)
+  int fbc[3];                   // flow boundaries (x, y, z)
   int N_phi, N_U, N_T, N_F;
   int has_U, has_T, has_F, accum;
   int T_var;                    // thermal properties vary with phi
+  int T_pulled;                 // 3D pulled temperature (no latent heat, moving walls)
+  int dim;
   int tile0;                    // first tile slot of this domain (partials)
   int ntiles;                   // tiles of this domain
   int nseeds;
@@ -36,22 +38,28 @@ struct Dom {
   double dt_base, W0, tau0, eps, lam, Mc, kc, cth, sth;
   double D_L, D_S, C_inf;
   double kS, kL, rcS, rcL, rho_L, L_h, T_m, m_L, Cp_L;
-  double nu, s_e, s_eps, s_q, u_in, Fx, Fy;
+  double nu, s_e, s_eps, s_q, u_in, Fx, Fy, Fz;
   double U0, T0;
+  double T_grad, V_pull, z_front;
   int u0_liquid;
   int pad1;
+  // base steps to add to a kernel's step argument to get the absolute step:
+  // zero for direct launches, the step at replay start for a captured graph
+  // (whose launches carry the steps of its first cycle)
+  long long koff;
   // state
   void* phi[2];    // R, 1 plane
-  void* sphi[2];   // S, 4 planes: f_i - w_i phi, i = 1..4 (D2Q5)
+  void* sphi[2];   // S, Q-1 planes: f_i - w_i phi, i >= 1 (4 in D2Q5, 6 in D3Q7)
   void* U[2];      // R
-  void* jU[2];     // S, 2 planes: first moment of the U populations
+  void* jU[2];     // S, dim planes: first moment of the U populations
   void* PU;        // R, pending U increments (accumulated coupling)
   void* T[2];      // R
-  void* jT[2];     // S, 2 planes
+  void* jT[2];     // S, dim planes
   void* PT;        // R
   void* rho[2];    // R
-  void* sF[2];     // S, 8 planes: f_i - w_i rho, i = 1..8 (D2Q9)
-  void* vel[2];    // R, 2 planes each (u_x, u_y)
+  void* sF[2];     // S, QF-1 planes: f_i - w_i rho, i >= 1 (8 in D2Q9, 18 in D3Q19)
+  void* vel[2];    // R, dim planes each
+  void* scr;       // R, scratch planes of the two-pass 3D kernels (19)
 };
 
 // Per-tile partial reductions written by the kernels (FP64).
@@ -59,6 +67,7 @@ struct Partial {
   double solid, M_C, enthalpy, mass;
   double S_phi, J_U;            // max |dU_pc| (transfer), max |injected U|
   double nonfinite;
+  double front_max, front_sum;  // 3D: phi = 0 crossing height per column
   double pad;
 };
 

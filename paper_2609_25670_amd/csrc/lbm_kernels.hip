@@ -36,7 +36,30 @@ __device__ __forceinline__ float ld(const __hip_bfloat16* p, long long i) { retu
 __device__ __forceinline__ void st(double* p, long long i, double v) { p[i] = v; }
 __device__ __forceinline__ void st(float* p, long long i, float v) { p[i] = v; }
 __device__ __forceinline__ void st(__half* p, long long i, float v) { p[i] = __float2half(v); }
-__device__ __forceinline__ void st(__hip_bfloat16* p, long long i, float v) { p[i] = __float2bfloat16(v); }
+// BF16 stores round stochastically.  Round-to-nearest gives every stored
+// value the same error for as long as the field is quasi-steady, and those
+// repeated errors in the scalar fluxes add up to a steady drift of the total
+// solute; with the rounding direction drawn with probability proportional to
+// the distance to each neighbour the error has zero mean and does not
+// repeat.  The 16 random bits hash the FP32 value with its element index
+// (Wellons' lowbias32 integer hash), so a store is a pure function of what
+// is stored and where: runs stay bitwise reproducible across tile shapes.
+__device__ __forceinline__ uint32_t mix32(uint32_t x) {
+  x ^= x >> 16;
+  x *= 0x7feb352du;
+  x ^= x >> 15;
+  x *= 0x846ca68bu;
+  x ^= x >> 16;
+  return x;
+}
+__device__ __forceinline__ void st(__hip_bfloat16* p, long long i, float v) {
+  uint32_t u = __float_as_uint(v);
+  if ((u & 0x7f800000u) != 0x7f800000u)   // finite: add 16 random bits below the kept mantissa, truncate
+    u += mix32(u + 0x9e3779b9u * (uint32_t)i) & 0xffffu;
+  else
+    u = __float_as_uint(__bfloat162float(__float2bfloat16(v)));
+  ((uint16_t*)p)[i] = (uint16_t)(u >> 16);
+}
 
 // Reciprocal and inverse square root: the hardware approximations (about
 // 1 ulp) in the FP32 path, exact division and square root in FP64.
@@ -233,8 +256,8 @@ __global__ __launch_bounds__(NTHR) void k_phase(const Dom* __restrict__ doms, co
     sv[r][1] = ld(s_in, o + pl);
     sv[r][2] = ld(s_in, o + 2 * pl);
     sv[r][3] = ld(s_in, o + 3 * pl);
-    Uv[r] = Up ? Up[o] : R(0);
-    Tv[r] = Tp ? Tp[o] : c.theta_off;
+    Uv[r] = Up ? Up[o] + R(D.U0) : R(0);      // planes hold U - U0 and T - T0
+    Tv[r] = Tp ? Tp[o] + R(D.T0) : c.theta_off;
   }
   load_box2<R, BW, BH>(sphi, phi_in, px, x0, y0, nx, ny, bcx, bcy, tx, ty);
   __syncthreads();
@@ -337,6 +360,7 @@ __global__ __launch_bounds__(NTHR) void k_transfer(const Dom* __restrict__ doms,
   R* __restrict__ PU = (R*)D.PU;
   R* __restrict__ PT = (R*)D.PT;
   const R omk = R(1.0 - D.kc), opk = R(1.0 + D.kc);
+  const R Uref = R(D.U0);   // the U plane holds U - U0
   const R cJ = R(D.W0 / (2.0 * 1.4142135623730951));
   const R cT = R(D.rho_L * D.L_h);
   const R rcS = R(D.rcS), rcL = R(D.rcL);
@@ -405,7 +429,7 @@ __global__ __launch_bounds__(NTHR) void k_transfer(const Dom* __restrict__ doms,
     R Jx = R(0), Jy = R(0);
     if (gg >= R(GRAD_EPS2)) {
       const R ig = rsq(gg);
-      const R a = cJ * (R(1) + omk * Us[r]) * (b[0] - pold[r]) * ig;
+      const R a = cJ * (R(1) + omk * (Us[r] + Uref)) * (b[0] - pold[r]) * ig;
       Jx = -a * gxv;
       Jy = -a * gyv;
     }
@@ -428,7 +452,7 @@ __global__ __launch_bounds__(NTHR) void k_transfer(const Dom* __restrict__ doms,
                   (jx[CW + 1] - jx[CW - 1] - jx[-CW - 1] + jx[-CW + 1]) * R(1.0 / 12.0) +
                   (jy[CW] - jy[-CW]) * R(1.0 / 3.0) +
                   (jy[CW + 1] + jy[CW - 1] - jy[-CW - 1] - jy[-CW + 1]) * R(1.0 / 12.0);
-    const R dU = ((R(1) + omk * Us[r]) * dphi - R(2) * div) * rcp(opk - omk * pn);
+    const R dU = ((R(1) + omk * (Us[r] + Uref)) * dphi - R(2) * div) * rcp(opk - omk * pn);
     amax = fmax(amax, fabs(dU));
     if (D.accum)
       PU[o] = PU[o] + dU;
@@ -513,6 +537,7 @@ __global__ __launch_bounds__(NTHR) void k_scalar(const Dom* __restrict__ doms, c
   const R DS = R(D.D_S), DL = R(D.D_L);
   const R kS = R(D.kS), kL = R(D.kL), rcS = R(D.rcS), rcL = R(D.rcL);
   const R itau_const = rcp(R(3) * dt * (kL / rcL) + R(0.5));
+  const R cref = R(FIELD == 0 ? D.U0 : D.T0);
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
 
   int cl[NS], bi[NS];
@@ -550,7 +575,8 @@ __global__ __launch_bounds__(NTHR) void k_scalar(const Dom* __restrict__ doms, c
   for (int r = 0; r < NS; ++r) {
     if (cl[r] < 0) continue;
     const R* b = &sphi[bi[r]];
-    const R jex = chi[r] * uxv[r] * dt, jey = chi[r] * uyv[r] * dt;
+    const R ca = chi[r] + cref;   // the plane holds chi - chi_ref
+    const R jex = ca * uxv[r] * dt, jey = ca * uyv[r] * dt;
     R itau, Q = R(0);
     if (FIELD == 0) {
       const R phi = b[0];
@@ -832,7 +858,10 @@ __global__ __launch_bounds__(NTHR) void k_flow(const Dom* __restrict__ doms, con
 // =================================================================== init
 // phi = max over seeds of tanh[(R - r)/(sqrt2 W0)] (Section 4.1); U = U0,
 // T = T0, rho = 1, u = 0 or u_in (1 - phi)/2 along x; every population at
-// equilibrium with v_n = 0 (Eq. 19, 21, 28).
+// equilibrium with v_n = 0 (Eq. 19, 21, 28).  The U and T planes hold the
+// shifts U - U0 and T - T0: far from the interface the increments are many
+// orders below the initial value, and adding them to U0 or T0 in FP32 would
+// round them away (a systematic solute drift).
 template <class R, class S>
 __global__ void k_init(const Dom* __restrict__ doms, int dom) {
   const Dom& D = doms[dom];
@@ -859,7 +888,7 @@ __global__ void k_init(const Dom* __restrict__ doms, int dom) {
   if (D.has_U) {
     const double dtU = D.N_U * D.dt_base;
     for (int b = 0; b < 2; ++b) {
-      ((R*)D.U[b])[o] = R(D.U0);
+      ((R*)D.U[b])[o] = R(0);    // U - U0
       st((S*)D.jU[b], o, R(D.U0 * ux * dtU));
       st((S*)D.jU[b], o + pl, R(0));
     }
@@ -868,7 +897,7 @@ __global__ void k_init(const Dom* __restrict__ doms, int dom) {
   if (D.has_T) {
     const double dtT = D.N_T * D.dt_base;
     for (int b = 0; b < 2; ++b) {
-      ((R*)D.T[b])[o] = R(D.T0);
+      ((R*)D.T[b])[o] = R(0);    // T - T0
       st((S*)D.jT[b], o, R(D.T0 * ux * dtT));
       st((S*)D.jT[b], o + pl, R(0));
     }
@@ -892,7 +921,8 @@ __global__ void k_init(const Dom* __restrict__ doms, int dom) {
 }
 
 // =================================================================== read / write
-// Plane codes: 0 phi, 1 U, 2 T, 3 rho, 4 ux, 5 uy, 10..14 phase f_0..f_4,
+// Plane codes: 0 phi, 1 U, 2 T, 3 rho, 4 ux, 5 uy, 8 U - U0, 9 T - T0
+// (the stored planes), 10..14 phase f_0..f_4,
 // 20/21 jU, 30/31 jT, 40..48 flow f_0..f_8, 50 pending U, 51 pending T,
 // 60..63 stored phase planes s_1..s_4, 70..77 stored flow planes s_1..s_8.
 template <class R, class S>
@@ -900,8 +930,10 @@ __device__ double read_plane(const Dom& D, long long k, int code, long long o) {
   const long long pl = D.plane;
   switch (code) {
     case 0: return double(((const R*)D.phi[par(n_phi(D, k))])[o]);
-    case 1: return double(((const R*)D.U[par(n_U(D, k))])[o]);
-    case 2: return double(((const R*)D.T[par(n_T(D, k))])[o]);
+    case 1: return double(((const R*)D.U[par(n_U(D, k))])[o]) + D.U0;
+    case 2: return double(((const R*)D.T[par(n_T(D, k))])[o]) + D.T0;
+    case 8: return double(((const R*)D.U[par(n_U(D, k))])[o]);
+    case 9: return double(((const R*)D.T[par(n_T(D, k))])[o]);
     case 3: return double(((const R*)D.rho[par(n_F(D, k))])[o]);
     case 4: return double(((const R*)D.vel[par(n_F(D, k))])[o]);
     case 5: return double(((const R*)D.vel[par(n_F(D, k))])[o + pl]);
@@ -973,8 +1005,10 @@ __global__ void k_write(const Dom* __restrict__ doms, int dom, long long k, cons
     const double v = src[c * n + i];
     switch (code) {
       case 0: ((R*)D.phi[par(n_phi(D, k))])[o] = R(v); break;
-      case 1: ((R*)D.U[par(n_U(D, k))])[o] = R(v); break;
-      case 2: ((R*)D.T[par(n_T(D, k))])[o] = R(v); break;
+      case 1: ((R*)D.U[par(n_U(D, k))])[o] = R(v - D.U0); break;
+      case 2: ((R*)D.T[par(n_T(D, k))])[o] = R(v - D.T0); break;
+      case 8: ((R*)D.U[par(n_U(D, k))])[o] = R(v); break;
+      case 9: ((R*)D.T[par(n_T(D, k))])[o] = R(v); break;
       case 3: ((R*)D.rho[par(n_F(D, k))])[o] = R(v); break;
       case 4: ((R*)D.vel[par(n_F(D, k))])[o] = R(v); break;
       case 5: ((R*)D.vel[par(n_F(D, k))])[o + pl] = R(v); break;
@@ -1047,12 +1081,12 @@ __global__ __launch_bounds__(NTHR) void k_diag_tiles(const Dom* __restrict__ dom
     a[0] += (1.0 + p) * 0.5;
     bool bad = !isfinite(p);
     if (U) {
-      const double u = double(U[o]);
+      const double u = double(U[o]) + D.U0;
       a[1] += D.C_inf * ((1.0 + D.kc) - (1.0 - D.kc) * p) * (1.0 + (1.0 - D.kc) * u) * 0.5;
       bad |= !isfinite(u);
     }
     if (T) {
-      const double tv = double(T[o]);
+      const double tv = double(T[o]) + D.T0;
       a[2] += tv - D.rho_L * D.L_h * p / (2.0 * D.rcL);
       bad |= !isfinite(tv);
     }
@@ -1186,6 +1220,872 @@ __global__ void k_tips(const Dom* __restrict__ doms, long long k, DiagOut* __res
     out[d].tip[s * 4 + ax] = tip;
   }
 }
+
+// =================================================================== 3D
+// Directional solidification in 3D (an extension: the paper's runs are 2D).
+// Scalars on D3Q7 (w_0 = 1/4, w_i = 1/8, c_s^2 = 1/4, so the factor 3 of
+// Eq. (19), (21), (24), (40) becomes 4), flow on D3Q19, isotropic stencils
+// with D3Q19 weights, fourfold-cubic anisotropy a_s = 1 - 3 eps +
+// 4 eps sum_a n_a^4.  Each field update is two passes over the sites: the
+// collision writes its compact result (dP, K) or the nineteen flow
+// deviations to scratch planes, the streaming pass pulls them.  One thread
+// per site, x fastest, so every plane access is coalesced.
+//
+// D3Q7 order: 0, +x, -x, +y, -y, +z, -z.  D3Q19 order: 0, the six axes as
+// above, then (1,1,0), (-1,-1,0), (1,-1,0), (-1,1,0), (1,0,1), (-1,0,-1),
+// (1,0,-1), (-1,0,1), (0,1,1), (0,-1,-1), (0,1,-1), (0,-1,1); the opposite
+// of q >= 1 is q + 1 for odd q and q - 1 for even q.
+__host__ __device__ constexpr int e19(int q, int a) {
+  constexpr int E[19][3] = {{0, 0, 0},  {1, 0, 0},   {-1, 0, 0}, {0, 1, 0},  {0, -1, 0},
+                            {0, 0, 1},  {0, 0, -1},  {1, 1, 0},  {-1, -1, 0}, {1, -1, 0},
+                            {-1, 1, 0}, {1, 0, 1},   {-1, 0, -1}, {1, 0, -1}, {-1, 0, 1},
+                            {0, 1, 1},  {0, -1, -1}, {0, 1, -1}, {0, -1, 1}};
+  return E[q][a];
+}
+__host__ __device__ constexpr int opp19(int q) { return q == 0 ? 0 : (q & 1) ? q + 1 : q - 1; }
+__host__ __device__ constexpr double w19(int q) { return q == 0 ? 1.0 / 3 : q <= 6 ? 1.0 / 18 : 1.0 / 36; }
+
+struct Site3 {
+  int x, y, z;
+  unsigned o;
+};
+
+__device__ __forceinline__ bool site3(const Dom& D, long long i, Site3& s) {
+  const long long n = (long long)D.nx * D.ny * D.nz;
+  if (i >= n) return false;
+  s.x = (int)(i % D.nx);
+  const long long t = i / D.nx;
+  s.y = (int)(t % D.ny);
+  s.z = (int)(t / D.ny);
+  s.o = (unsigned)(((long long)s.z * D.ny + s.y) * D.px + s.x);
+  return true;
+}
+
+// offset of the neighbour (x+dx, y+dy, z+dz) with ghost rules; mirrored
+// reports which axes were clamped at a wall
+__device__ __forceinline__ unsigned nb3(const Dom& D, const Site3& s, int dx, int dy, int dz, const int* bc,
+                                        int* mir = nullptr) {
+  const int gx = ghost(s.x + dx, D.nx, bc[0]);
+  const int gy = ghost(s.y + dy, D.ny, bc[1]);
+  const int gz = ghost(s.z + dz, D.nz, bc[2]);
+  if (mir) {
+    mir[0] = (s.x + dx < 0 || s.x + dx >= D.nx) && bc[0] != BC_PER;
+    mir[1] = (s.y + dy < 0 || s.y + dy >= D.ny) && bc[1] != BC_PER;
+    mir[2] = (s.z + dz < 0 || s.z + dz >= D.nz) && bc[2] != BC_PER;
+  }
+  return (unsigned)(((long long)gz * D.ny + gy) * D.px + gx);
+}
+
+// upstream site y - e, or false when it lies beyond a non-periodic boundary
+__device__ __forceinline__ bool up3(const Dom& D, const Site3& s, int ex, int ey, int ez, const int* bc,
+                                    unsigned& o) {
+  const int gx = resolve(s.x - ex, D.nx, bc[0]);
+  const int gy = resolve(s.y - ey, D.ny, bc[1]);
+  const int gz = resolve(s.z - ez, D.nz, bc[2]);
+  if (gx < 0 || gy < 0 || gz < 0) return false;
+  o = (unsigned)(((long long)gz * D.ny + gy) * D.px + gx);
+  return true;
+}
+
+// isotropic gradient with D3Q19 weights: d_a f = sum_q (3 w_q) e_qa f(x + e_q)
+template <class R>
+__device__ __forceinline__ void grad3(const Dom& D, const Site3& s, const R* __restrict__ f, R* g) {
+  g[0] = g[1] = g[2] = R(0);
+#pragma unroll
+  for (int q = 1; q < 19; ++q) {
+    const R v = f[nb3(D, s, e19(q, 0), e19(q, 1), e19(q, 2), D.bc)];
+    const R c = q <= 6 ? R(1.0 / 6.0) : R(1.0 / 12.0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+      if (e19(q, a) != 0) g[a] += R(e19(q, a)) * c * v;
+  }
+}
+
+// D3Q7 phase collision: (dP, K) and A = a_s^2 from phi, its gradient, j
+template <class R>
+__device__ __forceinline__ void phase_collide3(const Dom& D, R phi, const R* g, const R* j, R Us, R Ts, R& dP,
+                                               R* K, R& A) {
+  const R dt = R(D.N_phi * D.dt_base), W2t = R(D.W0 * D.W0 / D.tau0), eps = R(D.eps);
+  const R gg = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+  R a_s = R(1), N[3] = {R(0), R(0), R(0)};
+  if (gg >= R(GRAD_EPS2)) {
+    const R ig = rsq(gg);
+    const R gn = gg * ig;
+    R n[3], s4 = R(0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      n[a] = -g[a] * ig;
+      s4 += n[a] * n[a] * n[a] * n[a];
+    }
+    a_s = R(1) - R(3) * eps + R(4) * eps * s4;
+    const R f = R(-16) * eps * a_s * gn;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) N[a] = f * n[a] * (n[a] * n[a] - s4);
+  }
+  A = a_s * a_s;
+  const R om = R(1) - rcp(R(4) * dt * A * W2t + R(0.5));   // tau_phi with 1/c_s^2 = 4
+  const R theta = (Ts - R(D.T_m + D.m_L * D.C_inf)) * R(D.Cp_L / D.L_h);
+  const R q = R(1) - phi * phi;
+  const R Q = phi * q - R(D.lam) * (R(D.Mc) * Us + theta) * q * q;
+  dP = dt * Q * R(1.0 / D.tau0);
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const R je = -W2t * N[a] * dt;
+    K[a] = je + om * (j[a] - je);
+  }
+}
+
+template <class R, class S>
+__global__ __launch_bounds__(256) void k3_phase_collide(const Dom* __restrict__ doms, long long k) {
+  const Dom& D = doms[0];
+  Site3 s;
+  if (!site3(D, (long long)blockIdx.x * 256 + threadIdx.x, s) || k % D.N_phi) return;
+  const unsigned pl = (unsigned)D.plane;
+  const int ib = par(n_phi(D, k - 1));
+  const R* phi = (const R*)D.phi[ib];
+  const S* sp = (const S*)D.sphi[ib];
+  const long long nU = (D.accum ? 0 : (k - 1) / D.N_phi) + (k - 1) / D.N_U;
+  // the U and T planes hold U - U0 and T - T0
+  const R Us = D.has_U ? ((const R*)D.U[par(nU)])[s.o] + R(D.U0) : R(0);
+  const R Ts = D.has_T ? ((const R*)D.T[par(n_T(D, k - 1))])[s.o] + R(D.T0) : R(D.T_m + D.m_L * D.C_inf);
+  R g[3];
+  grad3(D, s, phi, g);
+  R sv[6];
+#pragma unroll
+  for (int q = 0; q < 6; ++q) sv[q] = ld(sp, s.o + q * pl);
+  const R j[3] = {sv[0] - sv[1], sv[2] - sv[3], sv[4] - sv[5]};
+  R dP, K[3], A;
+  phase_collide3(D, phi[s.o], g, j, Us, Ts, dP, K, A);
+  R* scr = (R*)D.scr;
+  scr[s.o] = dP;
+  scr[s.o + pl] = K[0];
+  scr[s.o + 2 * pl] = K[1];
+  scr[s.o + 3 * pl] = K[2];
+  scr[s.o + 4 * pl] = A;
+}
+
+// anisotropic pull streaming (Eq. 26) in deviations from w_i phi(y)
+template <class R, class S>
+__global__ __launch_bounds__(256) void k3_phase_stream(const Dom* __restrict__ doms, long long k) {
+  const Dom& D = doms[0];
+  Site3 s;
+  if (!site3(D, (long long)blockIdx.x * 256 + threadIdx.x, s) || k % D.N_phi) return;
+  const unsigned pl = (unsigned)D.plane;
+  const int ib = par(n_phi(D, k - 1)), ob = ib ^ 1;
+  const R* phi = (const R*)D.phi[ib];
+  const S* sp = (const S*)D.sphi[ib];
+  const R* scr = (const R*)D.scr;
+  const R py = phi[s.o];
+  const R dPy = scr[s.o], Ky[3] = {scr[s.o + pl], scr[s.o + 2 * pl], scr[s.o + 3 * pl]};
+  const R A = scr[s.o + 4 * pl], iA = rcp(A), oA = R(1) - A;
+  R sv[6], s0 = R(0);
+#pragma unroll
+  for (int q = 0; q < 6; ++q) {
+    sv[q] = ld(sp, s.o + q * pl);
+    s0 -= sv[q];
+  }
+  R dn[7], sum;
+  dn[0] = (dPy * R(0.25) - oA * s0) * iA;
+  sum = dn[0];
+#pragma unroll
+  for (int q = 1; q < 7; ++q) {
+    const int ex = e19(q, 0), ey = e19(q, 1), ez = e19(q, 2);
+    unsigned o;
+    R dpost;
+    if (up3(D, s, ex, ey, ez, D.bc, o)) {
+      const R Ke = R(ex) * scr[o + pl] + R(ey) * scr[o + 2 * pl] + R(ez) * scr[o + 3 * pl];
+      dpost = (phi[o] - py + scr[o]) * R(0.125) + R(0.5) * Ke;
+    } else {
+      dpost = dPy * R(0.125) - R(0.5) * (R(ex) * Ky[0] + R(ey) * Ky[1] + R(ez) * Ky[2]);
+    }
+    dn[q] = (dpost - oA * sv[q - 1]) * iA;
+    sum += dn[q];
+  }
+  ((R*)D.phi[ob])[s.o] = py + sum;
+  S* so = (S*)D.sphi[ob];
+#pragma unroll
+  for (int q = 1; q < 7; ++q) st(so, s.o + (q - 1) * pl, dn[q] - R(0.125) * sum);
+}
+
+// transfer, pass 1: J = W0/(2 sqrt2) [1 + (1-k) U*] dphi n^{q+1} (Eq. 37)
+template <class R>
+__global__ __launch_bounds__(256) void k3_transfer_J(const Dom* __restrict__ doms, long long k) {
+  const Dom& D = doms[0];
+  Site3 s;
+  if (!site3(D, (long long)blockIdx.x * 256 + threadIdx.x, s) || k % D.N_phi || !D.has_U) return;
+  const unsigned pl = (unsigned)D.plane;
+  const R* pn = (const R*)D.phi[par(n_phi(D, k))];
+  const R* po = (const R*)D.phi[par(n_phi(D, k - 1))];
+  const long long nU = (D.accum ? 0 : (k - 1) / D.N_phi) + (k - 1) / D.N_U;
+  const R* Uin = (const R*)D.U[par(nU)];
+  R g[3];
+  grad3(D, s, pn, g);
+  const R gg = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+  R J[3] = {R(0), R(0), R(0)};
+  if (gg >= R(GRAD_EPS2)) {
+    const R a = R(D.W0 / (2.0 * 1.4142135623730951)) * (R(1) + R(1.0 - D.kc) * (Uin[s.o] + R(D.U0))) *
+                (pn[s.o] - po[s.o]) * rsq(gg);
+#pragma unroll
+    for (int c = 0; c < 3; ++c) J[c] = -a * g[c];
+  }
+  R* scr = (R*)D.scr;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) scr[s.o + c * pl] = J[c];
+}
+
+// transfer, pass 2: compact divergence (ghost J mirrored with the normal
+// component negated), dU and dT of Eq. (38), injection (Eq. 39)
+template <class R>
+__global__ __launch_bounds__(256) void k3_transfer_apply(const Dom* __restrict__ doms, long long k,
+                                                          Partial* __restrict__ part) {
+  __shared__ R red[4];
+  const Dom& D = doms[0];
+  Site3 s;
+  const bool ok = site3(D, (long long)blockIdx.x * 256 + threadIdx.x, s);
+  if (k % D.N_phi) return;
+  const unsigned pl = (unsigned)D.plane;
+  const R* pn = (const R*)D.phi[par(n_phi(D, k))];
+  const R* po = (const R*)D.phi[par(n_phi(D, k - 1))];
+  R amax = R(0);
+  if (ok) {
+    const R p1 = pn[s.o], dphi = p1 - po[s.o];
+    if (D.has_U) {
+      const long long nU = (D.accum ? 0 : (k - 1) / D.N_phi) + (k - 1) / D.N_U;
+      const R* Uin = (const R*)D.U[par(nU)];
+      const R* J = (const R*)D.scr;
+      R div = R(0);
+#pragma unroll
+      for (int q = 1; q < 19; ++q) {
+        int mir[3];
+        const unsigned o = nb3(D, s, e19(q, 0), e19(q, 1), e19(q, 2), D.bc, mir);
+        const R c = q <= 6 ? R(1.0 / 6.0) : R(1.0 / 12.0);
+#pragma unroll
+        for (int a = 0; a < 3; ++a)
+          if (e19(q, a) != 0) {
+            const R v = J[o + a * pl];
+            div += R(e19(q, a)) * c * (mir[a] ? -v : v);
+          }
+      }
+      const R Us = Uin[s.o];   // U - U0
+      const R dU = ((R(1) + R(1.0 - D.kc) * (Us + R(D.U0))) * dphi - R(2) * div) *
+                   rcp(R(1.0 + D.kc) - R(1.0 - D.kc) * p1);
+      amax = fabs(dU);
+      if (D.accum) {
+        R* PU = (R*)D.PU;
+        PU[s.o] = PU[s.o] + dU;
+      } else {
+        ((R*)D.U[par(nU + 1)])[s.o] = Us + dU;
+      }
+    }
+    if (D.has_T && !D.T_pulled) {
+      const R rc = (R(1) + p1) * R(0.5 * D.rcS) + (R(1) - p1) * R(0.5 * D.rcL);
+      const R dT = R(D.rho_L * D.L_h) * dphi * rcp(R(2) * rc);
+      R* Tp = D.accum ? (R*)D.PT : (R*)D.T[par(n_T(D, k - 1))];
+      Tp[s.o] = Tp[s.o] + dT;
+    }
+  }
+  if (part && D.has_U) {
+    for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_down(amax, off, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = amax;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const R m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+      part[blockIdx.x].S_phi = double(m);
+      if (!D.accum) part[blockIdx.x].J_U = double(m);
+    }
+  }
+}
+
+// scalar transport (U: FIELD 0, T: FIELD 1), pass 1: collision to (dP, K)
+template <class R, class S, int FIELD>
+__global__ __launch_bounds__(256) void k3_scalar_collide(const Dom* __restrict__ doms, long long k) {
+  const Dom& D = doms[0];
+  const int N = FIELD == 0 ? D.N_U : D.N_T;
+  Site3 s;
+  if (!site3(D, (long long)blockIdx.x * 256 + threadIdx.x, s) || k % N) return;
+  const unsigned pl = (unsigned)D.plane;
+  const R* cin;
+  const S* jin;
+  if (FIELD == 0) {
+    cin = (const R*)D.U[par((D.accum ? 0 : k / D.N_phi) + (k - 1) / D.N_U)];
+    jin = (const S*)D.jU[par(n_jU(D, k - 1))];
+  } else {
+    cin = (const R*)D.T[par(n_T(D, k - 1))];
+    jin = (const S*)D.jT[par(n_T(D, k - 1))];
+  }
+  const R* phis = (const R*)D.phi[par(n_phi(D, k))];
+  const R dt = R(N * D.dt_base);
+  const R chi = cin[s.o] + R(FIELD == 0 ? D.U0 : D.T0);   // the plane holds chi - chi_ref
+  R u[3] = {R(0), R(0), R(0)};
+  if (D.has_F) {
+    const R* vel = (const R*)D.vel[par(n_F(D, k - 1))];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) u[a] = vel[s.o + a * pl];
+  }
+  if (FIELD == 1 && D.T_pulled) u[2] += R(D.V_pull);
+  R j[3], je[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    j[a] = ld(jin, s.o + a * pl);
+    je[a] = chi * u[a] * dt;
+  }
+  R itau, Q = R(0);
+  const bool var = FIELD == 0 || D.T_var;
+  if (var) {
+    const R phi = phis[s.o];
+    R gp[3];
+    grad3(D, s, phis, gp);
+    R coeff, pre;
+    if (FIELD == 0) {
+      const R ikf = rcp(R(1.0 + D.kc) - R(1.0 - D.kc) * phi);
+      coeff = ((R(1) + phi) * R(D.D_S) + (R(1) - phi) * R(D.D_L)) * ikf;            // Eq. (7)
+      pre = -R(1.0 - D.kc) * coeff * ikf;                                              // Eq. (8), 1st term
+    } else {
+      const R irc = rcp((R(1) + phi) * R(0.5 * D.rcS) + (R(1) - phi) * R(0.5 * D.rcL));
+      coeff = ((R(1) + phi) * R(0.5 * D.kS) + (R(1) - phi) * R(0.5 * D.kL)) * irc;   // Eq. (11)
+      pre = R(D.rcS - D.rcL) * R(0.5) * irc * coeff;                                  // Eq. (12), 1st term
+    }
+    itau = rcp(R(4) * dt * coeff + R(0.5));
+    R gdot = R(0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) gdot += -R(4) * itau * (j[a] - je[a]) * gp[a];     // Eq. (40), D3Q7
+    Q = pre * gdot;
+  } else {
+    itau = rcp(R(4) * dt * R(D.kL / D.rcL) + R(0.5));
+  }
+  const R om = R(1) - itau;
+  R* scr = (R*)D.scr;
+  scr[s.o] = dt * Q;
+#pragma unroll
+  for (int a = 0; a < 3; ++a) scr[s.o + (a + 1) * pl] = je[a] + om * (j[a] - je[a]);
+}
+
+// scalar transport, pass 2: pull streaming (Eq. 25) with bounce-back, or
+// anti-bounce-back to the moving profile on the z walls of the pulled T
+template <class R, class S, int FIELD>
+__global__ __launch_bounds__(256) void k3_scalar_stream(const Dom* __restrict__ doms, long long k,
+                                                         Partial* __restrict__ part) {
+  __shared__ R red[4];
+  const Dom& D = doms[0];
+  const int N = FIELD == 0 ? D.N_U : D.N_T;
+  Site3 s;
+  const bool ok = site3(D, (long long)blockIdx.x * 256 + threadIdx.x, s);
+  if (k % N) return;
+  const unsigned pl = (unsigned)D.plane;
+  const R* cin;
+  R* cout;
+  S* jout;
+  R* pend;
+  if (FIELD == 0) {
+    const long long nU = (D.accum ? 0 : k / D.N_phi) + (k - 1) / D.N_U;
+    cin = (const R*)D.U[par(nU)];
+    cout = (R*)D.U[par(nU + 1)];
+    jout = (S*)D.jU[par(n_jU(D, k))];
+    pend = (R*)D.PU;
+  } else {
+    cin = (const R*)D.T[par(n_T(D, k - 1))];
+    cout = (R*)D.T[par(n_T(D, k))];
+    jout = (S*)D.jT[par(n_T(D, k))];
+    pend = (R*)D.PT;
+  }
+  const R* scr = (const R*)D.scr;
+  R amax = R(0);
+  if (ok) {
+    const R cy = cin[s.o], dPy = scr[s.o];
+    const R Ky[3] = {scr[s.o + pl], scr[s.o + 2 * pl], scr[s.o + 3 * pl]};
+    const bool dir = FIELD == 1 && D.T_pulled;
+    const R tmid = R((double(k + D.koff) - 0.5 * N) * D.dt_base);
+    R dq[7];
+    dq[0] = dPy * R(0.25);
+    R chin = dq[0], j[3] = {R(0), R(0), R(0)};
+#pragma unroll
+    for (int q = 1; q < 7; ++q) {
+      const int ex = e19(q, 0), ey = e19(q, 1), ez = e19(q, 2);
+      unsigned o;
+      if (up3(D, s, ex, ey, ez, D.bc, o)) {
+        const R Ke = R(ex) * scr[o + pl] + R(ey) * scr[o + 2 * pl] + R(ez) * scr[o + 3 * pl];
+        dq[q] = (cin[o] - cy + scr[o]) * R(0.125) + R(0.5) * Ke;
+      } else {
+        const R Ke = R(ex) * Ky[0] + R(ey) * Ky[1] + R(ez) * Ky[2];
+        if (dir && ez != 0) {
+          const R zw = ez > 0 ? R(-0.5) : R(D.nz - 0.5);
+          const R Tw = R(D.T_grad) * (zw - R(D.z_front) - R(D.V_pull) * tmid);   // T_w - T0
+          dq[q] = R(0.125) * (R(2) * Tw - R(2) * cy - dPy) + R(0.5) * Ke;
+        } else {
+          dq[q] = dPy * R(0.125) - R(0.5) * Ke;
+        }
+      }
+      chin += dq[q];
+      j[0] += R(ex) * dq[q];
+      j[1] += R(ey) * dq[q];
+      j[2] += R(ez) * dq[q];
+    }
+    chin += cy;
+    if (D.accum) {
+      const R p = pend[s.o];
+      chin += p;
+      pend[s.o] = R(0);
+      amax = fabs(p);
+    }
+    cout[s.o] = chin;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) st(jout, s.o + a * pl, j[a]);
+  }
+  if (FIELD == 0 && D.accum && part) {
+    for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_down(amax, off, 64));
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = amax;
+    __syncthreads();
+    if (threadIdx.x == 0) part[blockIdx.x].J_U = double(fmax(fmax(red[0], red[1]), fmax(red[2], red[3])));
+  }
+}
+
+// D3Q19 MRT in projector form.  The rates are constant on the moment
+// subspaces (conserved rho, j: 0; energy: s_e; energy squared: s_eps;
+// stress: s_nu; every flux and ghost moment: s_q), so
+// M^-1 S M x = s_q x - s_q P_c x - (s_q - s_e) P_e x - (s_q - s_eps) P_eps x
+//              - (s_q - s_nu) P_nu x
+// with P the orthogonal projectors on the spans of the basis rows
+// {1, e_x, e_y, e_z}, {19|e|^2 - 30}, {(21|e|^4 - 53|e|^2 + 24)/2} and
+// {3e_x^2 - |e|^2, e_y^2 - e_z^2, e_x e_y, e_y e_z, e_x e_z}.
+template <class R>
+__device__ __forceinline__ void mrt19_op(const R* x, R sq, R se, R seps, R snu, R* y) {
+  R c0 = R(0), cx = R(0), cy = R(0), cz = R(0), ce = R(0), cp = R(0), cn[5] = {R(0), R(0), R(0), R(0), R(0)};
+#pragma unroll
+  for (int q = 0; q < 19; ++q) {
+    const int ex = e19(q, 0), ey = e19(q, 1), ez = e19(q, 2), e2 = ex * ex + ey * ey + ez * ez;
+    c0 += x[q];
+    cx += R(ex) * x[q];
+    cy += R(ey) * x[q];
+    cz += R(ez) * x[q];
+    ce += R(19 * e2 - 30) * x[q];
+    cp += R((21 * e2 * e2 - 53 * e2 + 24) / 2) * x[q];
+    cn[0] += R(3 * ex * ex - e2) * x[q];
+    cn[1] += R(ey * ey - ez * ez) * x[q];
+    cn[2] += R(ex * ey) * x[q];
+    cn[3] += R(ey * ez) * x[q];
+    cn[4] += R(ex * ez) * x[q];
+  }
+  c0 *= R(1.0 / 19);
+  cx *= R(0.1);
+  cy *= R(0.1);
+  cz *= R(0.1);
+  ce *= R(1.0 / 2394);
+  cp *= R(1.0 / 252);
+  cn[0] *= R(1.0 / 36);
+  cn[1] *= R(1.0 / 12);
+  cn[2] *= R(0.25);
+  cn[3] *= R(0.25);
+  cn[4] *= R(0.25);
+#pragma unroll
+  for (int q = 0; q < 19; ++q) {
+    const int ex = e19(q, 0), ey = e19(q, 1), ez = e19(q, 2), e2 = ex * ex + ey * ey + ez * ez;
+    const R pc = c0 + cx * R(ex) + cy * R(ey) + cz * R(ez);
+    const R pe = ce * R(19 * e2 - 30);
+    const R pp = cp * R((21 * e2 * e2 - 53 * e2 + 24) / 2);
+    const R pn = cn[0] * R(3 * ex * ex - e2) + cn[1] * R(ey * ey - ez * ez) + cn[2] * R(ex * ey) +
+                 cn[3] * R(ey * ez) + cn[4] * R(ex * ez);
+    y[q] = sq * x[q] - sq * pc - (sq - se) * pe - (sq - seps) * pp - (sq - snu) * pn;
+  }
+}
+
+template <class R, class S>
+__global__ __launch_bounds__(256) void k3_flow_collide(const Dom* __restrict__ doms, long long k) {
+  const Dom& D = doms[0];
+  Site3 s;
+  if (!site3(D, (long long)blockIdx.x * 256 + threadIdx.x, s) || k % D.N_F) return;
+  const unsigned pl = (unsigned)D.plane;
+  const int ib = par(n_F(D, k - 1));
+  const R rho = ((const R*)D.rho[ib])[s.o];
+  const S* sp = (const S*)D.sF[ib];
+  const R dt = R(D.N_F * D.dt_base), c = R(1) / dt;
+  R d[19], j[3] = {R(0), R(0), R(0)};
+  d[0] = R(0);
+#pragma unroll
+  for (int q = 1; q < 19; ++q) {
+    d[q] = ld(sp, s.o + (q - 1) * pl);
+    d[0] -= d[q];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) j[a] += R(e19(q, a)) * d[q];
+  }
+  const R F[3] = {R(D.Fx), R(D.Fy), R(D.Fz)};
+  const R irho = rcp(rho);
+  R u[3], U[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    u[a] = (c * j[a] + dt * F[a] * R(0.5)) * irho;     // Eq. (27)
+    U[a] = u[a] * dt;
+  }
+  const R U2 = U[0] * U[0] + U[1] * U[1] + U[2] * U[2];
+  R x[19], Fi[19];
+  const bool forced = D.Fx != 0.0 || D.Fy != 0.0 || D.Fz != 0.0;
+#pragma unroll
+  for (int q = 0; q < 19; ++q) {
+    const R eU = R(e19(q, 0)) * U[0] + R(e19(q, 1)) * U[1] + R(e19(q, 2)) * U[2];
+    x[q] = d[q] - R(w19(q)) * rho * (R(3) * eU + R(4.5) * eU * eU - R(1.5) * U2);   // f - f^eq
+    if (forced) {
+      const R eF = R(e19(q, 0)) * F[0] + R(e19(q, 1)) * F[1] + R(e19(q, 2)) * F[2];
+      const R uF = (u[0] * F[0] + u[1] * F[1] + u[2] * F[2]) * dt;
+      Fi[q] = R(w19(q)) * (R(3) * (eF - uF) + R(9) * eU * eF) * dt;     // Guo, velocity space
+    }
+  }
+  const R snu = R(1.0 / (3.0 * D.N_F * D.dt_base * D.nu + 0.5));
+  R y[19];
+  mrt19_op(x, R(D.s_q), R(D.s_e), R(D.s_eps), snu, y);
+  R* scr = (R*)D.scr;
+  if (forced) {
+    R yf[19];
+    mrt19_op(Fi, R(D.s_q), R(D.s_e), R(D.s_eps), snu, yf);
+#pragma unroll
+    for (int q = 0; q < 19; ++q) scr[s.o + q * pl] = d[q] - y[q] + Fi[q] - R(0.5) * yf[q];
+  } else {
+#pragma unroll
+    for (int q = 0; q < 19; ++q) scr[s.o + q * pl] = d[q] - y[q];
+  }
+}
+
+// partial bounce-back pull (Eq. 33) in deviations from w_i rho(y)
+template <class R, class S>
+__global__ __launch_bounds__(256) void k3_flow_stream(const Dom* __restrict__ doms, long long k) {
+  const Dom& D = doms[0];
+  Site3 s;
+  if (!site3(D, (long long)blockIdx.x * 256 + threadIdx.x, s) || k % D.N_F) return;
+  const unsigned pl = (unsigned)D.plane;
+  const R* rin = (const R*)D.rho[par(n_F(D, k - 1))];
+  const R* phis = (const R*)D.phi[par(n_phi(D, k))];
+  const R* scr = (const R*)D.scr;
+  const R dt = R(D.N_F * D.dt_base), c = R(1) / dt;
+  const R ry = rin[s.o], fly = (R(1) - phis[s.o]) * R(0.5);
+  R dn[19], drho = R(0), j[3] = {R(0), R(0), R(0)};
+#pragma unroll
+  for (int q = 0; q < 19; ++q) {
+    const int ex = e19(q, 0), ey = e19(q, 1), ez = e19(q, 2);
+    const R bounce = scr[s.o + opp19(q) * pl];
+    unsigned o;
+    if (q == 0) {
+      dn[0] = scr[s.o];
+    } else if (up3(D, s, ex, ey, ez, D.fbc, o)) {
+      const R m = R(0.5) * (fly + (R(1) - phis[o]) * R(0.5));
+      dn[q] = m * (R(w19(q)) * (rin[o] - ry) + scr[o + q * pl]) + (R(1) - m) * bounce;
+    } else {
+      dn[q] = bounce;
+    }
+    drho += dn[q];
+    j[0] += R(ex) * dn[q];
+    j[1] += R(ey) * dn[q];
+    j[2] += R(ez) * dn[q];
+  }
+  const int ob = par(n_F(D, k));
+  const R rho = ry + drho, irho = rcp(rho);
+  ((R*)D.rho[ob])[s.o] = rho;
+  R* vel = (R*)D.vel[ob];
+  const R F[3] = {R(D.Fx), R(D.Fy), R(D.Fz)};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) vel[s.o + a * pl] = (c * j[a] + dt * F[a] * R(0.5)) * irho;
+  S* so = (S*)D.sF[ob];
+#pragma unroll
+  for (int q = 1; q < 19; ++q) st(so, s.o + (q - 1) * pl, dn[q] - R(w19(q)) * drho);
+}
+
+// planar front along z at z_front + xi(x, y) (random form of Eq. 41),
+// U = U0, T = T0 or the pulled profile, flow at rest; equilibrium
+// populations with v_n = 0
+template <class R, class S>
+__global__ void k3_init(const Dom* __restrict__ doms, const double* __restrict__ xi) {
+  const Dom& D = doms[0];
+  Site3 s;
+  if (!site3(D, (long long)blockIdx.x * 256 + threadIdx.x, s)) return;
+  const unsigned pl = (unsigned)D.plane;
+  const double off = xi ? xi[(long long)s.y * D.nx + s.x] : 0.0;
+  const double phi = tanh((D.z_front + off - s.z) / (1.4142135623730951 * D.W0));
+  for (int b = 0; b < 2; ++b) {
+    ((R*)D.phi[b])[s.o] = R(phi);
+    for (int q = 0; q < 6; ++q) st((S*)D.sphi[b], s.o + q * pl, R(0));
+  }
+  if (D.has_U) {
+    for (int b = 0; b < 2; ++b) {
+      ((R*)D.U[b])[s.o] = R(0);   // U - U0
+      for (int a = 0; a < 3; ++a) st((S*)D.jU[b], s.o + a * pl, R(0));
+    }
+    ((R*)D.PU)[s.o] = R(0);
+  }
+  if (D.has_T) {
+    const double dT0 = D.T_pulled ? D.T_grad * (s.z - D.z_front) : 0.0;   // T - T0
+    const double jz = D.T_pulled ? (D.T0 + dT0) * D.V_pull * D.N_T * D.dt_base : 0.0;
+    for (int b = 0; b < 2; ++b) {
+      ((R*)D.T[b])[s.o] = R(dT0);
+      st((S*)D.jT[b], s.o, R(0));
+      st((S*)D.jT[b], s.o + pl, R(0));
+      st((S*)D.jT[b], s.o + 2 * pl, R(jz));
+    }
+    ((R*)D.PT)[s.o] = R(0);
+  }
+  if (D.has_F) {
+    for (int b = 0; b < 2; ++b) {
+      ((R*)D.rho[b])[s.o] = R(1);
+      for (int q = 0; q < 18; ++q) st((S*)D.sF[b], s.o + q * pl, R(0));
+      for (int a = 0; a < 3; ++a) ((R*)D.vel[b])[s.o + a * pl] = R(0);
+    }
+  }
+}
+
+// 3D plane codes follow the 2D ones: 0 phi, 1 U, 2 T, 3 rho, 4/5/6 u,
+// 8 U - U0, 9 T - T0,
+// 10..16 phase f_0..f_6, 20..22 jU, 30..32 jT, 40..58 flow f_0..f_18,
+// 50/51 are not used in 3D (pending planes are 90/91), 60..65 phase s,
+// 70..87 flow s.
+template <class R, class S>
+__device__ double read_plane3(const Dom& D, long long k, int code, unsigned o) {
+  const unsigned pl = (unsigned)D.plane;
+  if (code == 0) return double(((const R*)D.phi[par(n_phi(D, k))])[o]);
+  if (code == 1) return double(((const R*)D.U[par(n_U(D, k))])[o]) + D.U0;
+  if (code == 2) return double(((const R*)D.T[par(n_T(D, k))])[o]) + D.T0;
+  if (code == 8) return double(((const R*)D.U[par(n_U(D, k))])[o]);
+  if (code == 9) return double(((const R*)D.T[par(n_T(D, k))])[o]);
+  if (code == 3) return double(((const R*)D.rho[par(n_F(D, k))])[o]);
+  if (code >= 4 && code <= 6) return double(((const R*)D.vel[par(n_F(D, k))])[o + (code - 4) * pl]);
+  if (code >= 20 && code <= 22) return double(ld((const S*)D.jU[par(n_jU(D, k))], o + (code - 20) * pl));
+  if (code >= 30 && code <= 32) return double(ld((const S*)D.jT[par(n_T(D, k))], o + (code - 30) * pl));
+  if (code == 90) return double(((const R*)D.PU)[o]);
+  if (code == 91) return double(((const R*)D.PT)[o]);
+  if (code >= 60 && code <= 65) return double(ld((const S*)D.sphi[par(n_phi(D, k))], o + (code - 60) * pl));
+  if (code >= 70 && code <= 87) return double(ld((const S*)D.sF[par(n_F(D, k))], o + (code - 70) * pl));
+  if (code >= 10 && code <= 16) {
+    const int b = par(n_phi(D, k));
+    const R phi = ((const R*)D.phi[b])[o];
+    const S* sp = (const S*)D.sphi[b];
+    if (code == 10) {
+      R sum = R(0);
+      for (int q = 0; q < 6; ++q) sum += ld(sp, o + q * pl);
+      return double(phi * R(0.25) - sum);
+    }
+    return double(phi * R(0.125) + ld(sp, o + (code - 11) * pl));
+  }
+  if (code >= 40 && code <= 58) {
+    const int b = par(n_F(D, k));
+    const R rho = ((const R*)D.rho[b])[o];
+    const S* sp = (const S*)D.sF[b];
+    if (code == 40) {
+      R sum = R(0);
+      for (int q = 0; q < 18; ++q) sum += ld(sp, o + q * pl);
+      return double(R(w19(0)) * rho - sum);
+    }
+    const int q = code - 40;
+    return double(R(w19(q)) * rho + ld(sp, o + (q - 1) * pl));
+  }
+  return 0.0;
+}
+
+template <class R, class S>
+__global__ void k3_read(const Dom* __restrict__ doms, long long k, const int* __restrict__ codes, int ncodes,
+                        int out_f64, void* __restrict__ out) {
+  const Dom& D = doms[0];
+  Site3 s;
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  const int c = blockIdx.y;
+  if (c >= ncodes || !site3(D, i, s)) return;
+  const long long n = (long long)D.nx * D.ny * D.nz;
+  const double v = read_plane3<R, S>(D, k, codes[c], s.o);
+  if (out_f64)
+    ((double*)out)[c * n + i] = v;
+  else
+    ((float*)out)[c * n + i] = float(v);
+}
+
+template <class R, class S>
+__global__ void k3_write(const Dom* __restrict__ doms, long long k, const int* __restrict__ codes, int ncodes,
+                         const double* __restrict__ src) {
+  const Dom& D = doms[0];
+  Site3 s;
+  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
+  if (!site3(D, i, s)) return;
+  const long long n = (long long)D.nx * D.ny * D.nz;
+  const unsigned o = s.o, pl = (unsigned)D.plane;
+  int cphi = -1, cflow = -1;
+  for (int c = 0; c < ncodes; ++c) {
+    const int code = codes[c];
+    const double v = src[c * n + i];
+    if (code == 0) ((R*)D.phi[par(n_phi(D, k))])[o] = R(v);
+    else if (code == 1) ((R*)D.U[par(n_U(D, k))])[o] = R(v - D.U0);
+    else if (code == 2) ((R*)D.T[par(n_T(D, k))])[o] = R(v - D.T0);
+    else if (code == 8) ((R*)D.U[par(n_U(D, k))])[o] = R(v);
+    else if (code == 9) ((R*)D.T[par(n_T(D, k))])[o] = R(v);
+    else if (code == 3) ((R*)D.rho[par(n_F(D, k))])[o] = R(v);
+    else if (code >= 4 && code <= 6) ((R*)D.vel[par(n_F(D, k))])[o + (code - 4) * pl] = R(v);
+    else if (code >= 20 && code <= 22) st((S*)D.jU[par(n_jU(D, k))], o + (code - 20) * pl, R(v));
+    else if (code >= 30 && code <= 32) st((S*)D.jT[par(n_T(D, k))], o + (code - 30) * pl, R(v));
+    else if (code == 90) ((R*)D.PU)[o] = R(v);
+    else if (code == 91) ((R*)D.PT)[o] = R(v);
+    else if (code >= 60 && code <= 65) st((S*)D.sphi[par(n_phi(D, k))], o + (code - 60) * pl, R(v));
+    else if (code >= 70 && code <= 87) st((S*)D.sF[par(n_F(D, k))], o + (code - 70) * pl, R(v));
+    else if (code == 10) cphi = c;
+    else if (code == 40) cflow = c;
+  }
+  if (cphi >= 0) {
+    const int b = par(n_phi(D, k));
+    R f[7], phi = R(0);
+    for (int q = 0; q < 7; ++q) {
+      f[q] = R(src[(cphi + q) * n + i]);
+      phi += f[q];
+    }
+    ((R*)D.phi[b])[o] = phi;
+    for (int q = 1; q < 7; ++q) st((S*)D.sphi[b], o + (q - 1) * pl, f[q] - phi * R(0.125));
+  }
+  if (cflow >= 0) {
+    const int b = par(n_F(D, k));
+    R f[19], rho = R(0);
+    for (int q = 0; q < 19; ++q) {
+      f[q] = R(src[(cflow + q) * n + i]);
+      rho += f[q];
+    }
+    ((R*)D.rho[b])[o] = rho;
+    for (int q = 1; q < 19; ++q) st((S*)D.sF[b], o + (q - 1) * pl, f[q] - R(w19(q)) * rho);
+  }
+}
+
+// FP64 partial sums per block of 256 sites (same quantities as in 2D)
+template <class R>
+__global__ __launch_bounds__(256) void k3_diag(const Dom* __restrict__ doms, long long k, Partial* __restrict__ part) {
+  __shared__ double red[5][4];
+  const Dom& D = doms[0];
+  Site3 s;
+  double a[5] = {0, 0, 0, 0, 0};
+  if (site3(D, (long long)blockIdx.x * 256 + threadIdx.x, s)) {
+    const double p = double(((const R*)D.phi[par(n_phi(D, k))])[s.o]);
+    a[0] = (1.0 + p) * 0.5;
+    bool bad = !isfinite(p);
+    if (D.has_U) {
+      const double u = double(((const R*)D.U[par(n_U(D, k))])[s.o]) + D.U0;
+      a[1] = D.C_inf * ((1.0 + D.kc) - (1.0 - D.kc) * p) * (1.0 + (1.0 - D.kc) * u) * 0.5;
+      bad |= !isfinite(u);
+    }
+    if (D.has_T) {
+      const double t = double(((const R*)D.T[par(n_T(D, k))])[s.o]) + D.T0;
+      a[2] = t - D.rho_L * D.L_h * p / (2.0 * D.rcL);
+      bad |= !isfinite(t);
+    }
+    if (D.has_F) {
+      const double r = double(((const R*)D.rho[par(n_F(D, k))])[s.o]);
+      a[3] = r;
+      bad |= !isfinite(r);
+    }
+    a[4] = bad ? 1.0 : 0.0;
+  }
+  for (int jx = 0; jx < 5; ++jx) {
+    double v = a[jx];
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+    if ((threadIdx.x & 63) == 0) red[jx][threadIdx.x >> 6] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    Partial& P = part[blockIdx.x];
+    P.solid = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    P.M_C = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    P.enthalpy = red[2][0] + red[2][1] + red[2][2] + red[2][3];
+    P.mass = red[3][0] + red[3][1] + red[3][2] + red[3][3];
+    P.nonfinite = red[4][0] + red[4][1] + red[4][2] + red[4][3];
+  }
+}
+
+// front height per column: the first phi < 0 marching up z, linearly
+// interpolated; block max and sum into the partials, reduced on the host
+template <class R>
+__global__ void k3_front(const Dom* __restrict__ doms, long long k, double* __restrict__ out) {
+  __shared__ double rm[4], rs[4];
+  const Dom& D = doms[0];
+  const long long col = (long long)blockIdx.x * 256 + threadIdx.x;
+  double h = 0.0;
+  bool has = false;
+  if (col < (long long)D.nx * D.ny) {
+    has = true;
+    const int x = (int)(col % D.nx), y = (int)(col / D.nx);
+    const R* phi = (const R*)D.phi[par(n_phi(D, k))];
+    double prev = double(phi[(long long)y * D.px + x]);
+    h = prev < 0 ? 0.0 : double(D.nz - 1);
+    if (prev >= 0)
+      for (int z = 1; z < D.nz; ++z) {
+        const double cur = double(phi[((long long)z * D.ny + y) * D.px + x]);
+        if (cur < 0) {
+          h = (z - 1) + prev / (prev - cur);
+          break;
+        }
+        prev = cur;
+      }
+  }
+  double m = has ? h : -1e300, sm = has ? h : 0.0;
+  for (int off = 32; off > 0; off >>= 1) {
+    m = fmax(m, __shfl_down(m, off, 64));
+    sm += __shfl_down(sm, off, 64);
+  }
+  if ((threadIdx.x & 63) == 0) {
+    rm[threadIdx.x >> 6] = m;
+    rs[threadIdx.x >> 6] = sm;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    out[2 * blockIdx.x] = fmax(fmax(rm[0], rm[1]), fmax(rm[2], rm[3]));
+    out[2 * blockIdx.x + 1] = rs[0] + rs[1] + rs[2] + rs[3];
+  }
+}
+
+__global__ void k3_set_koff(Dom* __restrict__ doms, long long koff) {
+  if (threadIdx.x == 0) doms[0].koff = koff;
+}
+
+template <class R, class S>
+struct Launch3 {
+  static unsigned blocks(const Dom& h) { return (unsigned)(((long long)h.nx * h.ny * h.nz + 255) / 256); }
+  static void phase(const Dom& h, hipStream_t st, const Dom* d, long long k) {
+    k3_phase_collide<R, S><<<blocks(h), 256, 0, st>>>(d, k);
+    k3_phase_stream<R, S><<<blocks(h), 256, 0, st>>>(d, k);
+  }
+  static void transfer(const Dom& h, hipStream_t st, const Dom* d, long long k, Partial* p) {
+    if (h.has_U) k3_transfer_J<R><<<blocks(h), 256, 0, st>>>(d, k);
+    k3_transfer_apply<R><<<blocks(h), 256, 0, st>>>(d, k, p);
+  }
+  static void scalar(int field, const Dom& h, hipStream_t st, const Dom* d, long long k, Partial* p) {
+    if (field == 0) {
+      k3_scalar_collide<R, S, 0><<<blocks(h), 256, 0, st>>>(d, k);
+      k3_scalar_stream<R, S, 0><<<blocks(h), 256, 0, st>>>(d, k, p);
+    } else {
+      k3_scalar_collide<R, S, 1><<<blocks(h), 256, 0, st>>>(d, k);
+      k3_scalar_stream<R, S, 1><<<blocks(h), 256, 0, st>>>(d, k, p);
+    }
+  }
+  static void flow(const Dom& h, hipStream_t st, const Dom* d, long long k) {
+    k3_flow_collide<R, S><<<blocks(h), 256, 0, st>>>(d, k);
+    k3_flow_stream<R, S><<<blocks(h), 256, 0, st>>>(d, k);
+  }
+  static void step(const Dom& h, hipStream_t st, const Dom* d, long long k, Partial* p) {
+    if (k % h.N_phi == 0) {
+      phase(h, st, d, k);
+      transfer(h, st, d, k, p);
+    }
+    if (h.has_U && k % h.N_U == 0) scalar(0, h, st, d, k, p);
+    if (h.has_T && k % h.N_T == 0) scalar(1, h, st, d, k, p);
+    if (h.has_F && k % h.N_F == 0) flow(h, st, d, k);
+  }
+  static void init(const Dom& h, hipStream_t st, const Dom* d, const double* xi) {
+    k3_init<R, S><<<blocks(h), 256, 0, st>>>(d, xi);
+  }
+  static void set_koff(hipStream_t st, Dom* d, long long koff) { k3_set_koff<<<1, 64, 0, st>>>(d, koff); }
+  static void diag(const Dom& h, hipStream_t st, const Dom* d, long long k, Partial* p, double* front) {
+    k3_diag<R><<<blocks(h), 256, 0, st>>>(d, k, p);
+    k3_front<R><<<(unsigned)(((long long)h.nx * h.ny + 255) / 256), 256, 0, st>>>(d, k, front);
+  }
+  static void read(const Dom& h, hipStream_t st, const Dom* d, long long k, const int* codes, int nc, int f64,
+                   void* out) {
+    k3_read<R, S><<<dim3(blocks(h), nc), 256, 0, st>>>(d, k, codes, nc, f64, out);
+  }
+  static void write(const Dom& h, hipStream_t st, const Dom* d, long long k, const int* codes, int nc,
+                    const double* src) {
+    k3_write<R, S><<<blocks(h), 256, 0, st>>>(d, k, codes, nc, src);
+  }
+};
+
+template struct Launch3<double, double>;
+template struct Launch3<float, float>;
+template struct Launch3<float, __half>;
+template struct Launch3<float, __hip_bfloat16>;
 
 // =================================================================== launchers
 template <class R, class S>

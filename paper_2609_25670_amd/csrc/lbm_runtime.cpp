@@ -41,6 +41,21 @@ struct Launch {
 };
 void diag_final(int ndom, hipStream_t st, const Dom* d, const Partial* p, const int* slot, const int* slot0,
                 DiagOut* o);
+template <class R, class S>
+struct Launch3 {
+  static void phase(const Dom& h, hipStream_t st, const Dom* d, long long k);
+  static void transfer(const Dom& h, hipStream_t st, const Dom* d, long long k, Partial* p);
+  static void scalar(int field, const Dom& h, hipStream_t st, const Dom* d, long long k, Partial* p);
+  static void flow(const Dom& h, hipStream_t st, const Dom* d, long long k);
+  static void step(const Dom& h, hipStream_t st, const Dom* d, long long k, Partial* p);
+  static void init(const Dom& h, hipStream_t st, const Dom* d, const double* xi);
+  static void diag(const Dom& h, hipStream_t st, const Dom* d, long long k, Partial* p, double* front);
+  static void read(const Dom& h, hipStream_t st, const Dom* d, long long k, const int* codes, int nc, int f64,
+                   void* out);
+  static void write(const Dom& h, hipStream_t st, const Dom* d, long long k, const int* codes, int nc,
+                    const double* src);
+  static void set_koff(hipStream_t st, Dom* d, long long koff);
+};
 }  // namespace lbm
 
 using namespace lbm;
@@ -50,7 +65,8 @@ namespace {
 constexpr int kNTY = 4;
 constexpr int kTYs[kNTY] = {4, 8, 16, 32};
 constexpr long long kMaxGraphSteps = 4096;
-constexpr int kMaxCodes = 64;
+constexpr int kMaxCodes = 96;
+constexpr int kStagePlanes = 20;   // host staging planes: holds one D3Q19 population group
 
 std::string g_create_error;
 
@@ -83,6 +99,26 @@ Ops make_ops() {
              Launch<R, S>::write};
 }
 
+struct Ops3 {
+  void (*phase)(const Dom&, hipStream_t, const Dom*, long long);
+  void (*transfer)(const Dom&, hipStream_t, const Dom*, long long, Partial*);
+  void (*scalar)(int, const Dom&, hipStream_t, const Dom*, long long, Partial*);
+  void (*flow)(const Dom&, hipStream_t, const Dom*, long long);
+  void (*step)(const Dom&, hipStream_t, const Dom*, long long, Partial*);
+  void (*init)(const Dom&, hipStream_t, const Dom*, const double*);
+  void (*diag)(const Dom&, hipStream_t, const Dom*, long long, Partial*, double*);
+  void (*read)(const Dom&, hipStream_t, const Dom*, long long, const int*, int, int, void*);
+  void (*write)(const Dom&, hipStream_t, const Dom*, long long, const int*, int, const double*);
+  void (*set_koff)(hipStream_t, Dom*, long long);
+};
+
+template <class R, class S>
+Ops3 make_ops3() {
+  return Ops3{Launch3<R, S>::phase, Launch3<R, S>::transfer, Launch3<R, S>::scalar, Launch3<R, S>::flow,
+              Launch3<R, S>::step,  Launch3<R, S>::init,     Launch3<R, S>::diag,   Launch3<R, S>::read,
+              Launch3<R, S>::write, Launch3<R, S>::set_koff};
+}
+
 size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 long long ipow_lcm(long long a, long long b) { return a / std::gcd(a, b) * b; }
@@ -96,6 +132,12 @@ struct lbm_ctx {
   int storage = LBM_STORE_F32;
   size_t rsz = 4, ssz = 4;
   Ops ops{};
+  Ops3 ops3{};
+  int dim = 2;
+  long long koff = 0;           // value of Dom::koff on the device (3D)
+  double* d_front = nullptr;   // 3D front partials: (max, sum) per column block
+  int nfront = 0;
+  int nblk3 = 0;               // 3D: site blocks of 256
   int ndom = 0;
   std::vector<lbm_params> P;
   std::vector<Dom> H;
@@ -150,13 +192,18 @@ struct Layout {
 
 Layout layout_of(const lbm_params& p) {
   Layout L;
-  L.rplanes = 2;              // phi
-  L.splanes = 8;              // phase s_1..s_4, two buffers
-  if (p.has_U) { L.rplanes += 3; L.splanes += 4; }
-  if (p.has_T) { L.rplanes += 3; L.splanes += 4; }
-  if (p.has_flow) { L.rplanes += 6; L.splanes += 16; }
+  const int d = p.dim;
+  L.rplanes = 2;                           // phi, two buffers
+  L.splanes = 2 * (d == 3 ? 6 : 4);        // phase s_i, two buffers
+  if (p.has_U) { L.rplanes += 3; L.splanes += 2 * d; }
+  if (p.has_T) { L.rplanes += 3; L.splanes += 2 * d; }
+  if (p.has_flow) { L.rplanes += 2 + 2 * d; L.splanes += 2 * (d == 3 ? 18 : 8); }
+  if (d == 3) L.rplanes += p.has_flow ? 19 : 5;   // scratch of the two-pass kernels
   return L;
 }
+
+long long sites_of(const lbm_params& p) { return (long long)p.nx * p.ny * (p.dim == 3 ? p.nz : 1); }
+long long blocks3(const lbm_params& p) { return (sites_of(p) + 255) / 256; }
 
 size_t sizes_of(int storage, size_t& rsz, size_t& ssz) {
   rsz = storage == LBM_STORE_F64 ? 8 : 4;
@@ -170,12 +217,26 @@ std::string validate(const lbm_params& p, int i) {
     snprintf(b, sizeof b, "domain %d: %s", i, m);
     return std::string(b);
   };
-  if (p.dim != 2) return bad("only dim = 2 is supported");
-  if (p.nz != 1) return bad("nz must be 1 in 2D");
+  if (p.dim != 2 && p.dim != 3) return bad("dim must be 2 or 3");
+  if (p.dim == 2 && p.nz != 1) return bad("nz must be 1 in 2D");
   if (p.nx < 3 || p.ny < 3 || p.nx > (1 << 16) || p.ny > (1 << 16)) return bad("grid sides must be in [3, 65536]");
-  // in-plane offsets (up to 8 planes apart) are 32-bit in the kernels
-  if ((long long)((p.nx + 63) / 64 * 64) * p.ny > (1LL << 27)) return bad("more than 2^27 sites in one domain");
-  if (p.q_scalar != 5) return bad("scalar lattice must be D2Q5 (q_scalar = 5)");
+  if (p.dim == 3 && (p.nz < 3 || p.nz > (1 << 16))) return bad("nz must be in [3, 65536]");
+  // in-plane offsets (up to 18 planes apart) are 32-bit unsigned in the kernels
+  if ((long long)((p.nx + 63) / 64 * 64) * p.ny * (p.dim == 3 ? p.nz : 1) > (1LL << 27))
+    return bad("more than 2^27 sites in one domain");
+  if (p.dim == 2 && p.q_scalar != 5) return bad("2D scalar lattice must be D2Q5 (q_scalar = 5)");
+  if (p.dim == 3 && p.q_scalar != 7) return bad("3D scalar lattice must be D3Q7 (q_scalar = 7)");
+  if (p.dim == 3) {
+    for (int a = 0; a < 3; ++a)
+      if (p.flow_bc[a] == LBM_BC_INLET_OUTFLOW) return bad("inlet/outflow is 2D only");
+    if (p.bc[2] != LBM_BC_PERIODIC && p.bc[2] != LBM_BC_WALL) return bad("bad z boundary");
+    if (p.has_flow && p.u0_liquid_only) return bad("3D flow starts at rest (u0_liquid_only is 2D only)");
+  }
+  if (p.T_mode != LBM_T_TRANSPORT && p.T_mode != LBM_T_PULLED) return bad("bad T_mode");
+  if (p.T_mode == LBM_T_PULLED && (p.dim != 3 || p.bc[2] != LBM_BC_WALL))
+    return bad("the pulled temperature needs a 3D domain with z walls");
+  if (p.T_mode == LBM_T_PULLED && (p.kappa_S != p.kappa_L || p.rhoCp_S != p.rhoCp_L))
+    return bad("the pulled temperature needs constant thermal properties");
   if (p.N_phi < 1 || p.N_U < 1 || p.N_T < 1 || p.N_F < 1) return bad("update factors must be >= 1");
   if (!(p.dt_base > 0)) return bad("dt_base must be > 0");
   if (!(p.W0 > 0) || !(p.tau0 > 0)) return bad("W0 and tau0 must be > 0");
@@ -188,14 +249,15 @@ std::string validate(const lbm_params& p, int i) {
   if (p.coupling != LBM_COUPLE_INSTANT && p.coupling != LBM_COUPLE_ACCUM) return bad("bad coupling");
   // relaxation times at phi = +-1 (Eq. 24, 32): every tau must exceed 1/2
   const double amin = 1.0 - 5.0 / 3.0 * p.eps_s;
-  const double tphi = 3.0 * p.N_phi * p.dt_base * amin * amin * p.W0 * p.W0 / p.tau0 + 0.5;
+  const double ics2 = p.dim == 3 ? 4.0 : 3.0;   // 1/c_s^2 of the scalar lattice
+  const double tphi = ics2 * p.N_phi * p.dt_base * amin * amin * p.W0 * p.W0 / p.tau0 + 0.5;
   if (!(tphi > 0.5)) return bad("tau_phi <= 1/2");
   if (p.has_U) {
     for (double ph : {-1.0, 1.0}) {
       const double kf = (1 + p.k) - (1 - p.k) * ph;
       if (!(kf > 0)) return bad("(1+k) - (1-k) phi must be > 0");
       const double De = ((1 + ph) * p.D_S + (1 - ph) * p.D_L) / kf;
-      if (!(3.0 * p.N_U * p.dt_base * De + 0.5 > 0.5)) return bad("tau_U <= 1/2");
+      if (!(ics2 * p.N_U * p.dt_base * De + 0.5 > 0.5)) return bad("tau_U <= 1/2");
     }
   }
   if (p.has_T) {
@@ -203,7 +265,7 @@ std::string validate(const lbm_params& p, int i) {
     for (double ph : {-1.0, 1.0}) {
       const double a = ((1 + ph) / 2 * p.kappa_S + (1 - ph) / 2 * p.kappa_L) /
                        ((1 + ph) / 2 * p.rhoCp_S + (1 - ph) / 2 * p.rhoCp_L);
-      if (!(3.0 * p.N_T * p.dt_base * a + 0.5 > 0.5)) return bad("tau_T <= 1/2");
+      if (!(ics2 * p.N_T * p.dt_base * a + 0.5 > 0.5)) return bad("tau_T <= 1/2");
     }
     if (!(p.L_h != 0) || !(p.Cp_L > 0)) return bad("L_h and Cp_L must be nonzero");
   }
@@ -230,6 +292,10 @@ std::vector<int4> xcd_order(const std::vector<int4>& spatial) {
 
 // ------------------------------------------------------------------ helpers
 static void launch_step(lbm_ctx* c, hipStream_t st, long long k) {
+  if (c->dim == 3) {
+    c->ops3.step(c->H[0], st, c->d_dom, k, c->d_part);
+    return;
+  }
   const int ti = c->ty_index, TY = kTYs[ti];
   for (auto& g : c->g_phi)
     if (k % g.N == 0) {
@@ -304,12 +370,15 @@ size_t lbm_workspace_bytes(const lbm_params* p, int32_t n, int32_t storage) {
   size_t maxsites = 0;
   for (int i = 0; i < n; ++i) {
     if (!validate(p[i], i).empty()) return 0;
-    const size_t plane = (size_t)px_of(p[i].nx) * p[i].ny;
+    if (p[i].dim == 3 && n != 1) return 0;
+    const size_t plane = (size_t)px_of(p[i].nx) * p[i].ny * (p[i].dim == 3 ? p[i].nz : 1);
     const Layout L = layout_of(p[i]);
     total += align256(plane * rsz) * L.rplanes + align256(plane * ssz) * L.splanes;
-    tilesmax += (long long)((p[i].nx + 63) / 64) * ((p[i].ny + kTYs[0] - 1) / kTYs[0]);
-    maxsites = std::max(maxsites, (size_t)p[i].nx * p[i].ny);
+    tilesmax += p[i].dim == 3 ? blocks3(p[i])
+                              : (long long)((p[i].nx + 63) / 64) * ((p[i].ny + kTYs[0] - 1) / kTYs[0]);
+    maxsites = std::max(maxsites, (size_t)sites_of(p[i]));
   }
+  total += align256(sizeof(double) * 2 * (size_t)((p[0].nx * (long long)p[0].ny + 255) / 256 + 1));
   const long long padded = (tilesmax + 7) / 8 * 8;
   total += align256(sizeof(Dom) * n);
   // tile lists per tile height: "all" plus, per field, one list per group of
@@ -319,7 +388,7 @@ size_t lbm_workspace_bytes(const lbm_params* p, int32_t n, int32_t storage) {
   total += align256(sizeof(int) * (size_t)tilesmax) + kNTY * align256(sizeof(int) * (n + 1));
   total += align256(sizeof(DiagOut) * n);
   total += align256(sizeof(int) * kMaxCodes);
-  total += align256(sizeof(double) * maxsites * 16);
+  total += align256(sizeof(double) * maxsites * kStagePlanes);
   return total;
 }
 
@@ -328,6 +397,8 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
   if (!out) return fail(nullptr, LBM_EINVAL, "out is NULL");
   *out = nullptr;
   if (!p || n < 1) return fail(nullptr, LBM_EINVAL, "no domains");
+  for (int i = 0; i < n; ++i)
+    if (p[i].dim == 3 && n != 1) return fail(nullptr, LBM_EINVAL, "3D contexts hold one domain");
   if (storage < 0 || storage > 3) return fail(nullptr, LBM_EINVAL, "bad storage format");
   for (int i = 0; i < n; ++i) {
     const std::string m = validate(p[i], i);
@@ -345,11 +416,12 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
   c->storage = storage;
   sizes_of(storage, c->rsz, c->ssz);
   switch (storage) {
-    case LBM_STORE_F64: c->ops = make_ops<double, double>(); break;
-    case LBM_STORE_F32: c->ops = make_ops<float, float>(); break;
-    case LBM_STORE_F16: c->ops = make_ops<float, __half>(); break;
-    default: c->ops = make_ops<float, __hip_bfloat16>(); break;
+    case LBM_STORE_F64: c->ops = make_ops<double, double>(); c->ops3 = make_ops3<double, double>(); break;
+    case LBM_STORE_F32: c->ops = make_ops<float, float>(); c->ops3 = make_ops3<float, float>(); break;
+    case LBM_STORE_F16: c->ops = make_ops<float, __half>(); c->ops3 = make_ops3<float, __half>(); break;
+    default: c->ops = make_ops<float, __hip_bfloat16>(); c->ops3 = make_ops3<float, __hip_bfloat16>(); break;
   }
+  c->dim = p[0].dim;
   c->ndom = n;
   c->P.assign(p, p + n);
   c->initialised.assign(n, false);
@@ -384,12 +456,19 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
     memset(&D, 0, sizeof D);
     D.nx = q.nx;
     D.ny = q.ny;
+    D.nz = q.dim == 3 ? q.nz : 1;
+    D.dim = q.dim;
     D.px = px_of(q.nx);
-    D.plane = (long long)D.px * q.ny;
-    for (int a = 0; a < 2; ++a) {
+    D.plane = (long long)D.px * q.ny * D.nz;
+    for (int a = 0; a < 3; ++a) {
       D.bc[a] = q.bc[a];
       D.fbc[a] = q.flow_bc[a];
     }
+    D.T_pulled = q.T_mode == LBM_T_PULLED;
+    D.T_grad = q.T_grad;
+    D.V_pull = q.V_pull;
+    D.z_front = q.z_front;
+    D.Fz = q.Fb[2];
     D.N_phi = q.N_phi;
     D.N_U = q.N_U;
     D.N_T = q.N_T;
@@ -431,31 +510,33 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
     D.T0 = q.T0;
     D.u0_liquid = q.u0_liquid_only;
     const size_t pr = D.plane * c->rsz, ps = D.plane * c->ssz;
+    const int d3 = q.dim == 3;
     for (int b = 0; b < 2; ++b) {
       D.phi[b] = take(pr);
-      D.sphi[b] = take(align256(ps) * 4);
+      D.sphi[b] = take(align256(ps) * (d3 ? 6 : 4));
     }
     if (q.has_U) {
       for (int b = 0; b < 2; ++b) {
         D.U[b] = take(pr);
-        D.jU[b] = take(align256(ps) * 2);
+        D.jU[b] = take(align256(ps) * q.dim);
       }
       D.PU = take(pr);
     }
     if (q.has_T) {
       for (int b = 0; b < 2; ++b) {
         D.T[b] = take(pr);
-        D.jT[b] = take(align256(ps) * 2);
+        D.jT[b] = take(align256(ps) * q.dim);
       }
       D.PT = take(pr);
     }
     if (q.has_flow) {
       for (int b = 0; b < 2; ++b) {
         D.rho[b] = take(pr);
-        D.sF[b] = take(align256(ps) * 8);
-        D.vel[b] = take(align256(pr) * 2);
+        D.sF[b] = take(align256(ps) * (d3 ? 18 : 8));
+        D.vel[b] = take(align256(pr) * q.dim);
       }
     }
+    if (d3) D.scr = take(align256(pr) * (q.has_flow ? 19 : 5));
     lcm = ipow_lcm(lcm, q.N_phi);
     if (q.has_U) lcm = ipow_lcm(lcm, q.N_U);
     if (q.has_T) lcm = ipow_lcm(lcm, q.N_T);
@@ -468,8 +549,14 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
   long long tilesmax = 0;
   size_t maxsites = 0;
   for (int i = 0; i < n; ++i) {
-    tilesmax += (long long)((p[i].nx + 63) / 64) * ((p[i].ny + kTYs[0] - 1) / kTYs[0]);
-    maxsites = std::max(maxsites, (size_t)p[i].nx * p[i].ny);
+    tilesmax += p[i].dim == 3 ? blocks3(p[i])
+                              : (long long)((p[i].nx + 63) / 64) * ((p[i].ny + kTYs[0] - 1) / kTYs[0]);
+    maxsites = std::max(maxsites, (size_t)sites_of(p[i]));
+  }
+  if (c->dim == 3) {
+    c->nblk3 = (int)blocks3(p[0]);
+    c->nfront = (int)((p[0].nx * (long long)p[0].ny + 255) / 256);
+    c->d_front = (double*)take(sizeof(double) * 2 * (c->nfront + 1));
   }
   auto build = [&](const std::vector<int>& doms, int ti, TileSet& ts, std::vector<int>* slot0) -> lbm_status {
     const int TY = kTYs[ti];
@@ -495,6 +582,10 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
   std::iota(alld.begin(), alld.end(), 0);
   std::vector<int> slot0[kNTY];
   for (int ti = 0; ti < kNTY; ++ti) {
+    if (c->dim == 3) {
+      slot0[ti] = {0, c->nblk3};   // 3D: one partial slot per block of 256 sites
+      continue;
+    }
     lbm_status s = build(alld, ti, c->all[ti], &slot0[ti]);
     if (s != LBM_OK) {
       lbm_destroy(c);
@@ -514,6 +605,10 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
     for (auto& kv : by) {
       Group g;
       g.N = kv.first;
+      if (c->dim == 3) {   // 3D kernels take the whole domain, no tile lists
+        gs.push_back(g);
+        continue;
+      }
       for (int ti = 0; ti < kNTY; ++ti) {
         if (by.size() == 1 && (int)kv.second.size() == n) {
           g.ts[ti] = c->all[ti];
@@ -540,7 +635,7 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
   for (int ti = 0; ti < kNTY; ++ti) c->d_slot0[ti] = (int*)take(sizeof(int) * (n + 1));
   c->d_diag = (DiagOut*)take(sizeof(DiagOut) * n);
   c->d_codes = (int*)take(sizeof(int) * kMaxCodes);
-  c->stage_elems = maxsites * 16;
+  c->stage_elems = maxsites * kStagePlanes;
   c->d_stage = (double*)take(sizeof(double) * c->stage_elems);
   if ((size_t)(cur - (char*)c->ws) > c->ws_bytes) {
     lbm_destroy(c);
@@ -581,6 +676,7 @@ lbm_status lbm_init_seeds(lbm_ctx* c, int32_t dom, int32_t n_seeds, const double
   if (dom < 0 || dom >= c->ndom) return fail(c, LBM_EINVAL, "bad domain index");
   if (n_seeds < 0 || n_seeds > MAX_SEEDS) return fail(c, LBM_EINVAL, "0..4 seeds per domain");
   if (n_seeds > 0 && (!centres || !radii)) return fail(c, LBM_EINVAL, "NULL seed arrays");
+  if (c->dim == 3) return fail(c, LBM_EINVAL, "3D domains are initialised with lbm_init_front");
   HIPCHK(c, hipSetDevice(c->device));
   Dom& D = c->H[dom];
   D.nseeds = n_seeds;
@@ -593,6 +689,27 @@ lbm_status lbm_init_seeds(lbm_ctx* c, int32_t dom, int32_t n_seeds, const double
   if (st != LBM_OK) return st;
   c->ops.init(c->stream, c->d_dom, dom, (long long)D.nx * D.ny);
   HIPCHK(c, hipGetLastError());
+  c->initialised[dom] = true;
+  c->k = 0;
+  return LBM_OK;
+}
+
+lbm_status lbm_init_front(lbm_ctx* c, int32_t dom, const double* xi) {
+  if (!c) return LBM_EINVAL;
+  if (dom < 0 || dom >= c->ndom) return fail(c, LBM_EINVAL, "bad domain index");
+  if (c->dim != 3) return fail(c, LBM_EINVAL, "lbm_init_front initialises 3D domains");
+  HIPCHK(c, hipSetDevice(c->device));
+  const Dom& D = c->H[dom];
+  const double* dxi = nullptr;
+  if (xi) {
+    HIPCHK(c, hipMemcpyAsync(c->d_stage, xi, sizeof(double) * D.nx * D.ny, hipMemcpyHostToDevice, c->stream));
+    dxi = c->d_stage;
+  }
+  c->ops3.init(D, c->stream, c->d_dom, dxi);
+  c->ops3.set_koff(c->stream, c->d_dom, 0);
+  c->koff = 0;
+  HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipStreamSynchronize(c->stream));
   c->initialised[dom] = true;
   c->k = 0;
   return LBM_OK;
@@ -623,7 +740,7 @@ lbm_status lbm_kernel_times(lbm_ctx* c, int32_t reps, double* ms_out, double* pe
   for (int d = 0; d < c->ndom; ++d)
     if (!c->initialised[d]) return fail(c, LBM_ESTATE, "lbm_init_seeds has not been called for every domain");
   HIPCHK(c, hipSetDevice(c->device));
-  if (c->autotune && !c->tuned) {
+  if (c->autotune && !c->tuned && c->dim == 2) {
     lbm_status s = autotune(c);
     if (s != LBM_OK) return s;
   }
@@ -647,6 +764,15 @@ lbm_status lbm_kernel_times(lbm_ctx* c, int32_t reps, double* ms_out, double* pe
       const long long k = due(g.N);
       const dim3 grid(g.ts[ti].n);
       auto launch = [&]() {
+        if (c->dim == 3) {
+          const Dom& h = c->H[0];
+          if (kind == 0) c->ops3.phase(h, c->stream, c->d_dom, k);
+          if (kind == 1) c->ops3.transfer(h, c->stream, c->d_dom, k, c->d_part);
+          if (kind == 2) c->ops3.scalar(0, h, c->stream, c->d_dom, k, c->d_part);
+          if (kind == 3) c->ops3.scalar(1, h, c->stream, c->d_dom, k, c->d_part);
+          if (kind == 4) c->ops3.flow(h, c->stream, c->d_dom, k);
+          return;
+        }
         if (kind == 0) c->ops.phase(TY, grid, c->stream, c->d_dom, g.ts[ti].d, k);
         if (kind == 1) c->ops.transfer(TY, grid, c->stream, c->d_dom, g.ts[ti].d, k, c->d_part);
         if (kind == 2) c->ops.scalar(0, TY, grid, c->stream, c->d_dom, g.ts[ti].d, k, c->d_part);
@@ -676,13 +802,32 @@ lbm_status lbm_kernel_times(lbm_ctx* c, int32_t reps, double* ms_out, double* pe
 
 static lbm_status run_diag(lbm_ctx* c, lbm_diag* out) {
   const int ti = c->ty_index, TY = kTYs[ti];
-  c->ops.diag_tiles(TY, dim3(c->all[ti].n), c->stream, c->d_dom, c->all[ti].d, c->k, c->d_part);
-  diag_final(c->ndom, c->stream, c->d_dom, c->d_part, c->d_slot, c->d_slot0[ti], c->d_diag);
-  c->ops.tips(c->ndom, c->stream, c->d_dom, c->k, c->d_diag);
+  std::vector<double> front;
+  if (c->dim == 3) {
+    c->ops3.diag(c->H[0], c->stream, c->d_dom, c->k, c->d_part, c->d_front);
+    diag_final(c->ndom, c->stream, c->d_dom, c->d_part, c->d_slot, c->d_slot0[ti], c->d_diag);
+    front.resize(2 * (size_t)c->nfront);
+    HIPCHK(c, hipMemcpyAsync(front.data(), c->d_front, sizeof(double) * front.size(), hipMemcpyDeviceToHost,
+                             c->stream));
+  } else {
+    c->ops.diag_tiles(TY, dim3(c->all[ti].n), c->stream, c->d_dom, c->all[ti].d, c->k, c->d_part);
+    diag_final(c->ndom, c->stream, c->d_dom, c->d_part, c->d_slot, c->d_slot0[ti], c->d_diag);
+    c->ops.tips(c->ndom, c->stream, c->d_dom, c->k, c->d_diag);
+  }
   HIPCHK(c, hipGetLastError());
   std::vector<DiagOut> h(c->ndom);
   HIPCHK(c, hipMemcpyAsync(h.data(), c->d_diag, sizeof(DiagOut) * c->ndom, hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
+  if (c->dim == 3) {
+    double m = -1e300, sm = 0.0;
+    for (int b = 0; b < c->nfront; ++b) {
+      m = std::max(m, front[2 * b]);
+      sm += front[2 * b + 1];
+    }
+    for (int j = 0; j < 16; ++j) h[0].tip[j] = 0.0;
+    h[0].tip[0] = m;
+    h[0].tip[1] = sm / (double(c->H[0].nx) * c->H[0].ny);
+  }
   bool bad = false;
   for (int d = 0; d < c->ndom; ++d) {
     lbm_diag& o = out[d];
@@ -708,7 +853,7 @@ lbm_status lbm_step_multirate(lbm_ctx* c, int64_t n, lbm_diag* diag) {
   for (int d = 0; d < c->ndom; ++d)
     if (!c->initialised[d]) return fail(c, LBM_ESTATE, "lbm_init_seeds has not been called for every domain");
   HIPCHK(c, hipSetDevice(c->device));
-  if (c->autotune && !c->tuned) {
+  if (c->autotune && !c->tuned && c->dim == 2) {
     lbm_status s = autotune(c);
     if (s != LBM_OK) return s;
   }
@@ -730,10 +875,18 @@ lbm_status lbm_step_multirate(lbm_ctx* c, int64_t n, lbm_diag* diag) {
         if (e != hipSuccess) return fail(c, LBM_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(e));
         c->graph_ty = c->ty_index;
       }
+      if (c->dim == 3 && c->koff != c->k) {   // absolute step for the time-dependent 3D walls
+        c->ops3.set_koff(c->stream, c->d_dom, c->k);
+        c->koff = c->k;
+      }
       HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
       c->k += c->cycle;
       left -= c->cycle;
     } else {
+      if (c->dim == 3 && c->koff != 0) {
+        c->ops3.set_koff(c->stream, c->d_dom, 0);
+        c->koff = 0;
+      }
       launch_step(c, c->stream, c->k + 1);
       c->k += 1;
       left -= 1;
@@ -746,6 +899,24 @@ lbm_status lbm_step_multirate(lbm_ctx* c, int64_t n, lbm_diag* diag) {
 
 static int codes_for(const Dom& D, uint32_t mask, int* codes) {
   int n = 0;
+  if (D.dim == 3) {
+    if (mask & LBM_F_PHI) codes[n++] = 0;
+    if (mask & LBM_F_U) codes[n++] = 1;
+    if (mask & LBM_F_T) codes[n++] = 2;
+    if (mask & LBM_F_RHO) codes[n++] = 3;
+    if (mask & LBM_F_VEL) for (int a = 0; a < 3; ++a) codes[n++] = 4 + a;
+    if (mask & LBM_F_POP_PHI) for (int q = 0; q < 7; ++q) codes[n++] = 10 + q;
+    if (mask & LBM_F_JU) for (int a = 0; a < 3; ++a) codes[n++] = 20 + a;
+    if (mask & LBM_F_JT) for (int a = 0; a < 3; ++a) codes[n++] = 30 + a;
+    if (mask & LBM_F_POP_F) for (int q = 0; q < 19; ++q) codes[n++] = 40 + q;
+    if (mask & LBM_F_PEND_U) codes[n++] = 90;
+    if (mask & LBM_F_PEND_T) codes[n++] = 91;
+    if (mask & LBM_F_SPHI) for (int q = 0; q < 6; ++q) codes[n++] = 60 + q;
+    if (mask & LBM_F_SF) for (int q = 0; q < 18; ++q) codes[n++] = 70 + q;
+    if (mask & LBM_F_SU) codes[n++] = 8;
+    if (mask & LBM_F_ST) codes[n++] = 9;
+    return n;
+  }
   if (mask & LBM_F_PHI) codes[n++] = 0;
   if (mask & LBM_F_U) codes[n++] = 1;
   if (mask & LBM_F_T) codes[n++] = 2;
@@ -759,14 +930,16 @@ static int codes_for(const Dom& D, uint32_t mask, int* codes) {
   if (mask & LBM_F_PEND_T) codes[n++] = 51;
   if (mask & LBM_F_SPHI) for (int q = 0; q < 4; ++q) codes[n++] = 60 + q;
   if (mask & LBM_F_SF) for (int q = 0; q < 8; ++q) codes[n++] = 70 + q;
+  if (mask & LBM_F_SU) codes[n++] = 8;
+  if (mask & LBM_F_ST) codes[n++] = 9;
   (void)D;
   return n;
 }
 
 static std::string check_mask(const lbm_params& q, uint32_t mask) {
-  if (mask == 0 || mask >= (1u << 13)) return "empty or unknown field mask";
-  if ((mask & (LBM_F_U | LBM_F_JU | LBM_F_PEND_U)) && !q.has_U) return "domain carries no U field";
-  if ((mask & (LBM_F_T | LBM_F_JT | LBM_F_PEND_T)) && !q.has_T) return "domain carries no T field";
+  if (mask == 0 || mask >= (1u << 15)) return "empty or unknown field mask";
+  if ((mask & (LBM_F_U | LBM_F_JU | LBM_F_PEND_U | LBM_F_SU)) && !q.has_U) return "domain carries no U field";
+  if ((mask & (LBM_F_T | LBM_F_JT | LBM_F_PEND_T | LBM_F_ST)) && !q.has_T) return "domain carries no T field";
   if ((mask & (LBM_F_RHO | LBM_F_VEL | LBM_F_POP_F | LBM_F_SF)) && !q.has_flow) return "domain carries no flow field";
   return "";
 }
@@ -782,18 +955,24 @@ lbm_status lbm_read_fields(lbm_ctx* c, int32_t dom, uint32_t mask, int32_t dst_i
   const Dom& D = c->H[dom];
   int codes[kMaxCodes];
   const int nc = codes_for(D, mask, codes);
-  const long long nsite = (long long)D.nx * D.ny;
+  const long long nsite = (long long)D.nx * D.ny * D.nz;
   HIPCHK(c, hipMemcpyAsync(c->d_codes, codes, sizeof(int) * nc, hipMemcpyHostToDevice, c->stream));
   const size_t esz = dst_fp64 ? 8 : 4;
+  auto rd = [&](const int* cd, int cn, void* out) {
+    if (c->dim == 3)
+      c->ops3.read(D, c->stream, c->d_dom, c->k, cd, cn, dst_fp64, out);
+    else
+      c->ops.read(c->stream, c->d_dom, dom, c->k, cd, cn, dst_fp64, out, nsite);
+  };
   if (dst_is_device) {
-    c->ops.read(c->stream, c->d_dom, dom, c->k, c->d_codes, nc, dst_fp64, dst, nsite);
+    rd(c->d_codes, nc, dst);
     HIPCHK(c, hipGetLastError());
     return LBM_OK;
   }
-  // host destination: stage in chunks of at most 16 planes
-  for (int c0 = 0; c0 < nc; c0 += 16) {
-    const int cn = std::min(16, nc - c0);
-    c->ops.read(c->stream, c->d_dom, dom, c->k, c->d_codes + c0, cn, dst_fp64, c->d_stage, nsite);
+  // host destination: stage in chunks of at most kStagePlanes planes
+  for (int c0 = 0; c0 < nc; c0 += kStagePlanes) {
+    const int cn = std::min(kStagePlanes, nc - c0);
+    rd(c->d_codes + c0, cn, c->d_stage);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipMemcpyAsync((char*)dst + (size_t)c0 * nsite * esz, c->d_stage, (size_t)cn * nsite * esz,
                              hipMemcpyDeviceToHost, c->stream));
@@ -814,32 +993,40 @@ lbm_status lbm_write_fields(lbm_ctx* c, int32_t dom, uint32_t mask, int32_t src_
     return fail(c, LBM_EINVAL, "rho is the sum of the flow populations: pass one of the two");
   if ((mask & LBM_F_POP_PHI) && (mask & LBM_F_SPHI))
     return fail(c, LBM_EINVAL, "pass either the phase populations or the stored phase planes");
+  if (((mask & LBM_F_U) && (mask & LBM_F_SU)) || ((mask & LBM_F_T) && (mask & LBM_F_ST)))
+    return fail(c, LBM_EINVAL, "pass either U (T) or its stored shift, not both");
   HIPCHK(c, hipSetDevice(c->device));
   const Dom& D = c->H[dom];
   int codes[kMaxCodes];
   const int nc = codes_for(D, mask, codes);
-  const long long nsite = (long long)D.nx * D.ny;
+  const long long nsite = (long long)D.nx * D.ny * D.nz;
   HIPCHK(c, hipMemcpyAsync(c->d_codes, codes, sizeof(int) * nc, hipMemcpyHostToDevice, c->stream));
+  auto wr = [&](const int* cd, int cn, const double* from) {
+    if (c->dim == 3)
+      c->ops3.write(D, c->stream, c->d_dom, c->k, cd, cn, from);
+    else
+      c->ops.write(c->stream, c->d_dom, dom, c->k, cd, cn, from, nsite);
+  };
   if (src_is_device) {
-    c->ops.write(c->stream, c->d_dom, dom, c->k, c->d_codes, nc, (const double*)src, nsite);
+    wr(c->d_codes, nc, (const double*)src);
     HIPCHK(c, hipGetLastError());
     return LBM_OK;
   }
-  // host source: stage chunks of at most 16 planes, never splitting the
+  // host source: stage chunks of at most kStagePlanes planes, never splitting the
   // population groups (their planes are re-encoded together)
   const int stage_planes = (int)(c->stage_elems / (size_t)nsite);
   int c0 = 0;
   while (c0 < nc) {
     int c1 = c0;
     while (c1 < nc) {
-      const int unit = (codes[c1] == 10) ? 5 : (codes[c1] == 40) ? 9 : 1;
-      if (c1 + unit - c0 > std::min(16, stage_planes)) break;
+      const int unit = (codes[c1] == 10) ? (c->dim == 3 ? 7 : 5) : (codes[c1] == 40) ? (c->dim == 3 ? 19 : 9) : 1;
+      if (c1 + unit - c0 > std::min(kStagePlanes, stage_planes)) break;
       c1 += unit;
     }
     if (c1 == c0) return fail(c, LBM_EINVAL, "staging buffer too small for one field group");
     HIPCHK(c, hipMemcpyAsync(c->d_stage, (const double*)src + (size_t)c0 * nsite,
                              sizeof(double) * (size_t)(c1 - c0) * nsite, hipMemcpyHostToDevice, c->stream));
-    c->ops.write(c->stream, c->d_dom, dom, c->k, c->d_codes + c0, c1 - c0, c->d_stage, nsite);
+    wr(c->d_codes + c0, c1 - c0, c->d_stage);
     HIPCHK(c, hipGetLastError());
     HIPCHK(c, hipStreamSynchronize(c->stream));
     c0 = c1;

@@ -20,7 +20,7 @@ STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVICE", -4
           -5: "LBM_ESTATE"}
 
 (F_PHI, F_U, F_T, F_RHO, F_VEL, F_POP_PHI, F_JU, F_JT, F_POP_F, F_PEND_U, F_PEND_T, F_SPHI,
- F_SF) = (1 << i for i in range(13))
+ F_SF, F_SU, F_ST) = (1 << i for i in range(15))
 BC = {"periodic": 0, "wall": 1, "inlet_outflow": 2}
 STORAGE = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
 COUPLING = {"instant": 0, "accum": 1}
@@ -28,9 +28,11 @@ COUPLING = {"instant": 0, "accum": 1}
 # names, plane counts per field bit (2D)
 FIELD_BITS = [("phi", F_PHI, 1), ("U", F_U, 1), ("T", F_T, 1), ("rho", F_RHO, 1), ("vel", F_VEL, 2),
               ("f_phi", F_POP_PHI, 5), ("jU", F_JU, 2), ("jT", F_JT, 2), ("f_F", F_POP_F, 9),
-              ("P_U", F_PEND_U, 1), ("P_T", F_PEND_T, 1), ("s_phi", F_SPHI, 4), ("s_F", F_SF, 8)]
+              ("P_U", F_PEND_U, 1), ("P_T", F_PEND_T, 1), ("s_phi", F_SPHI, 4), ("s_F", F_SF, 8),
+              ("s_U", F_SU, 1), ("s_T", F_ST, 1)]
 
-EXPORTS = ["lbm_workspace_bytes", "lbm_create", "lbm_init_seeds", "lbm_step_multirate", "lbm_read_fields",
+EXPORTS = ["lbm_workspace_bytes", "lbm_create", "lbm_init_seeds", "lbm_init_front", "lbm_step_multirate",
+           "lbm_read_fields",
            "lbm_write_fields", "lbm_configure", "lbm_kernel_times", "lbm_steps_done", "lbm_last_error",
            "lbm_destroy"]
 KERNEL_KINDS = ("phase", "transfer", "U", "T", "flow")
@@ -52,7 +54,8 @@ class Params(ctypes.Structure):
         ("s_eps", ctypes.c_double), ("s_q", ctypes.c_double), ("u_in", ctypes.c_double),
         ("Fb", ctypes.c_double * 3), ("bc", ctypes.c_int32 * 3), ("flow_bc", ctypes.c_int32 * 3),
         ("U0", ctypes.c_double), ("T0", ctypes.c_double), ("u0_liquid_only", ctypes.c_int32),
-        ("coupling", ctypes.c_int32),
+        ("coupling", ctypes.c_int32), ("T_mode", ctypes.c_int32), ("pad", ctypes.c_int32),
+        ("T_grad", ctypes.c_double), ("V_pull", ctypes.c_double), ("z_front", ctypes.c_double),
     ]
 
 
@@ -90,6 +93,8 @@ def load() -> ctypes.CDLL:
     lib.lbm_init_seeds.restype = ctypes.c_int
     lib.lbm_init_seeds.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, P(ctypes.c_double),
                                    P(ctypes.c_double)]
+    lib.lbm_init_front.restype = ctypes.c_int
+    lib.lbm_init_front.argtypes = [ctypes.c_void_p, ctypes.c_int32, P(ctypes.c_double)]
     lib.lbm_step_multirate.restype = ctypes.c_int
     lib.lbm_step_multirate.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
     lib.lbm_read_fields.restype = ctypes.c_int
@@ -130,6 +135,10 @@ def to_params(d: dict) -> Params:
         p.flow_bc[a] = BC[d["flow_bc"][a]]
     p.u0_liquid_only = int(bool(d.get("u0_liquid_only", False)))
     p.coupling = COUPLING[d.get("coupling", "instant")]
+    p.T_mode = 1 if d.get("T_mode", "transport") == "pulled" else 0
+    p.T_grad = float(d.get("T_grad", 0.0))
+    p.V_pull = float(d.get("V_pull", 0.0))
+    p.z_front = float(d.get("z_front", 0.0))
     return p
 
 
@@ -179,6 +188,15 @@ class Simulation:
     # ----------------------------------------------------------------- calls
     def init(self):
         for i, d in enumerate(self.domains):
+            if d["dim"] == 3:
+                xi = d.get("perturb")
+                buf = None
+                if xi is not None:
+                    a = np.ascontiguousarray(np.asarray(xi, dtype=np.float64)[: d["ny"], : d["nx"]])
+                    buf = a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+                    self._xi = a
+                _check(self.lib, self.ctx, self.lib.lbm_init_front(self.ctx, i, buf))
+                continue
             seeds = d.get("seeds", [])
             c = (ctypes.c_double * max(1, 2 * len(seeds)))(*[v for s in seeds for v in s[:2]])
             r = (ctypes.c_double * max(1, len(seeds)))(*[s[2] for s in seeds])
@@ -216,31 +234,38 @@ class Simulation:
     def steps_done(self) -> int:
         return int(self.lib.lbm_steps_done(self.ctx))
 
-    def _layout(self, names):
+    def _layout(self, names, domain=0):
+        d = self.domains[domain]
+        dim = d["dim"]
+        cnts = dict(vel=dim, jU=dim, jT=dim, f_phi=d["q_scalar"], s_phi=d["q_scalar"] - 1,
+                    f_F=9 if dim == 2 else 19, s_F=8 if dim == 2 else 18)
         mask = 0
         order = []
         for name, bit, cnt in FIELD_BITS:
             if name in names:
                 mask |= bit
-                order.append((name, cnt))
+                order.append((name, cnts.get(name, cnt)))
         return mask, order
+
+    def _shape(self, domain):
+        d = self.domains[domain]
+        return (d["ny"], d["nx"]) if d["dim"] == 2 else (d["nz"], d["ny"], d["nx"])
 
     def read(self, domain=0, names=("phi",), fp64=True, device=False):
         """Dict name -> array [planes..., ny, nx] (planes squeezed when 1).
         Host numpy arrays by default; torch CUDA tensors with ``device``."""
         import torch
 
-        d = self.domains[domain]
-        nx, ny = d["nx"], d["ny"]
-        mask, order = self._layout(names)
+        shape = self._shape(domain)
+        mask, order = self._layout(names, domain)
         nplanes = sum(c for _, c in order)
         if device:
-            buf = torch.empty((nplanes, ny, nx), dtype=torch.float64 if fp64 else torch.float32,
+            buf = torch.empty((nplanes,) + shape, dtype=torch.float64 if fp64 else torch.float32,
                               device=f"cuda:{self.device}")
             _check(self.lib, self.ctx, self.lib.lbm_read_fields(self.ctx, domain, mask, 1, int(fp64),
                                                                 ctypes.c_void_p(buf.data_ptr())))
         else:
-            buf = np.empty((nplanes, ny, nx), dtype=np.float64 if fp64 else np.float32)
+            buf = np.empty((nplanes,) + shape, dtype=np.float64 if fp64 else np.float32)
             _check(self.lib, self.ctx, self.lib.lbm_read_fields(self.ctx, domain, mask, 0, int(fp64),
                                                                 buf.ctypes.data_as(ctypes.c_void_p)))
         out = {}
@@ -252,11 +277,11 @@ class Simulation:
 
     def write(self, domain, arrays: dict):
         """Overwrite planes from host FP64 arrays (same names as ``read``)."""
-        mask, order = self._layout(list(arrays))
-        d = self.domains[domain]
+        mask, order = self._layout(list(arrays), domain)
+        shape = self._shape(domain)
         parts = []
         for name, cnt in order:
-            a = np.asarray(arrays[name], dtype=np.float64).reshape(cnt, d["ny"], d["nx"])
+            a = np.asarray(arrays[name], dtype=np.float64).reshape((cnt,) + shape)
             parts.append(a)
         buf = np.ascontiguousarray(np.concatenate(parts, axis=0))
         _check(self.lib, self.ctx, self.lib.lbm_write_fields(self.ctx, domain, mask, 0,
@@ -267,9 +292,9 @@ class Simulation:
         d = self.domains[domain]
         names = ["phi", "s_phi"]
         if d["has_U"]:
-            names += ["U", "jU", "P_U"]
+            names += ["s_U", "jU", "P_U"]
         if d["has_T"]:
-            names += ["T", "jT", "P_T"]
+            names += ["s_T", "jT", "P_T"]
         if d["has_flow"]:
             names += ["rho", "vel", "s_F"]
         return tuple(names)

@@ -1,0 +1,196 @@
+"""Parity of the 3D HIP path (D3Q7 scalars, D3Q19 flow) with the FP64 oracle.
+
+FP64 storage/compute against the oracle at 1e-12 relative L2 per field, on
+grids whose site counts leave a ragged last block of 256 sites.  The full
+256 x 256 x 512 directional grid is checked element by element through
+lateral periodicity: with a front offset xi(x, y) that repeats every 16
+sites, the solution repeats with the same period, so every 16 x 16 column
+block of the full run equals the oracle on a 16 x 16 x 512 box.
+"""
+
+import sys
+
+import numpy as np
+import pytest
+
+import lbm_inputs as L
+import oracle
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+ALL3 = ("phi", "U", "T", "rho", "vel", "f_phi", "jU", "jT", "f_F")
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+def _rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 1e-300 else 1.0)
+
+
+def _ref(dom, names):
+    m = dict(phi=dom.phi, U=getattr(dom, "U", None), T=getattr(dom, "T", None), rho=dom.rho, vel=dom.u,
+             f_phi=dom.f_phi, P_U=dom.P_U, P_T=dom.P_T)
+    if "jU" in names:
+        m["jU"] = dom.moments("U")[1]
+    if "jT" in names:
+        m["jT"] = dom.moments("T")[1]
+    if "f_F" in names:
+        m["f_F"] = dom.f_F
+    return {n: m[n] for n in names}
+
+
+def _compare(case, got, ref, tol):
+    for name, r in ref.items():
+        e = _rel(got[name], r)
+        _say(f"  {case}: {name} rel L2 = {e:.3e}")
+        assert e <= tol, (case, name, e)
+
+
+def _run(wl, steps, names, storage="f64", use_graph=True):
+    from paper_2609_25670_amd import simulation_for
+
+    sim = simulation_for(wl, storage=storage)
+    sim.configure(0, use_graph)
+    diag = sim.step(steps, diag=True)
+    got = sim.read(0, names)
+    sim.close()
+    return got, diag[0]
+
+
+def _directional(nx, ny, nz):
+    wl = L.reduced(L.directional_3d(), nx, ny, nz)
+    d = wl["domains"][0]
+    d["Fb"] = (2e-5, 1e-5, 0.0)     # drive the flow so that it advects U and T
+    return wl
+
+
+def test_directional_pulled_fp64():
+    """Directional case (pulled T, N = 1:1:16:4) on 24 x 20 x 33: 80 base
+    steps = two graph replays of 32 plus 16 direct steps, so the moving wall
+    temperature is exercised with a nonzero replay offset."""
+    wl = _directional(24, 20, 33)
+    _say("case 3d directional 24x20x33 fp64 80 steps")
+    got, diag = _run(wl, 80, ALL3)
+    dom = oracle.run(wl["domains"][0], 80)
+    _compare("directional", got, _ref(dom, ALL3), TOL64)
+    t = oracle.diag.totals(dom)
+    assert abs(diag["M_C"] - t["M_C"]) < 1e-11 * t["M_C"]
+    assert abs(diag["solid"] - t["solid"]) < 1e-10 * t["solid"]
+    assert diag["nonfinite"] == 0
+
+
+def test_directional_graph_and_direct_launches_are_bitwise_identical():
+    """Graph replay (with its step offset) and direct launches give the
+    same FP64 state bit for bit."""
+    wl = _directional(24, 20, 33)
+    _say("case 3d determinism graph vs direct")
+    a, _ = _run(wl, 72, ALL3, use_graph=True)
+    b, _ = _run(wl, 72, ALL3, use_graph=False)
+    for n in ALL3:
+        assert np.array_equal(a[n], b[n]), n
+
+
+def test_3d_transport_T_accumulated_walls_fp64():
+    """3D with transported T (latent heat, phi-dependent kappa and rhoCp),
+    accumulated coupling, walls normal to x and z, N = 1:2:4:2."""
+    wl = _directional(20, 18, 26)
+    d = wl["domains"][0]
+    d.update(T_mode="transport", T0=d["T0"] - 0.02, kappa_S=2 * d["kappa_L"], rhoCp_S=1.2 * d["rhoCp_L"],
+             coupling="accum", N_U=2, N_T=4, N_F=2, bc=("wall", "periodic", "wall"),
+             flow_bc=("wall", "periodic", "wall"), D_L=0.05, D_S=5e-4)
+    names = ("phi", "U", "T", "rho", "vel", "jU", "jT", "P_U", "P_T")
+    _say("case 3d transported T, accumulated coupling 20x18x26 fp64 44 steps")
+    got, diag = _run(wl, 44, names)
+    dom = oracle.run(d, 44)
+    _compare("3d accum", got, _ref(dom, names), TOL64)
+    assert abs(diag["enthalpy"] - oracle.diag.totals(dom)["enthalpy"]) < 1e-10 * abs(
+        oracle.diag.totals(dom)["enthalpy"])
+
+
+def test_3d_checkpoint_restore_is_bitwise():
+    """Full 3D state read, written into a fresh context, continued: equal to
+    the uninterrupted run bit for bit."""
+    from paper_2609_25670_amd import simulation_for
+
+    wl = _directional(20, 12, 24)
+    _say("case 3d checkpoint")
+    a = simulation_for(wl, storage="f64")
+    a.step(40)
+    snap = a.read(0, a.state_names())
+    a.step(24)
+    ref = a.read(0, ("phi", "U", "T", "rho", "vel"))
+    a.close()
+    b = simulation_for(wl, storage="f64")
+    b.step(40)
+    b.write(0, snap)
+    b.step(24)
+    got = b.read(0, ("phi", "U", "T", "rho", "vel"))
+    b.close()
+    for n in ref:
+        assert np.array_equal(got[n], ref[n]), n
+
+
+def test_directional_full_size_fp64_by_lateral_periodicity():
+    """256 x 256 x 512 with a 16-periodic front offset, FP64, 32 base steps
+    (one graph replay): every 16 x 16 column block equals the oracle on
+    16 x 16 x 512."""
+    rng = np.random.default_rng(2024)
+    xi16 = rng.uniform(-1.0, 1.0, size=(16, 16))
+    wl = L.directional_3d()
+    d = wl["domains"][0]
+    d["Fb"] = (2e-5, 1e-5, 0.0)
+    d["perturb"] = np.tile(xi16, (16, 16))
+    small = L.reduced(wl, 16, 16, 512)
+    small["domains"][0]["perturb"] = xi16
+    names = ("phi", "U", "T", "vel")
+    _say("case 3d directional full size 256x256x512 fp64 32 steps")
+    got, diag = _run(wl, 32, names)
+    assert diag["nonfinite"] == 0
+    dom = oracle.run(small["domains"][0], 32)
+    ref = _ref(dom, names)
+    for n in names:
+        g = got[n]
+        r = ref[n]
+        worst = 0.0
+        for by in range(16):
+            for bx in range(16):
+                blk = g[..., by * 16:(by + 1) * 16, bx * 16:(bx + 1) * 16]
+                worst = max(worst, _rel(blk, r))
+        _say(f"  full size: {n} worst block rel L2 = {worst:.3e}")
+        assert worst <= TOL64, (n, worst)
+
+
+def test_directional_full_size_bf16_against_fp64():
+    """The workload as configured (random front offset, BF16 population
+    storage) for 320 base steps against the same run in FP64: finite, the
+    relative solute change R_M = (M_C(t) - M_C(0)) / M_C(0) within 1e-6 of
+    the FP64 run's, mean and maximum front heights within 0.01 cell, and the
+    FP64 mean front height within a cell of a planar front in the oracle."""
+    from paper_2609_25670_amd import simulation_for
+
+    wl = L.directional_3d()
+    res = {}
+    for st in ("f64", "bf16"):
+        _say(f"case 3d directional full size {st} 320 steps")
+        sim = simulation_for(wl, storage=st)
+        d0 = sim.step(0, diag=True)[0]
+        d1 = sim.step(320, diag=True)[0]
+        sim.close()
+        assert d1["nonfinite"] == 0
+        res[st] = ((d1["M_C"] - d0["M_C"]) / d0["M_C"], d1["tip"][0], d1["tip"][1])
+        _say(f"  {st}: R_M {res[st][0]:.3e}, max front {res[st][1]:.4f}, mean front {res[st][2]:.4f}")
+    (r64, mx64, mn64), (r16, mx16, mn16) = res["f64"], res["bf16"]
+    assert abs(r16 - r64) <= 1e-6, (r16, r64)
+    assert abs(mx16 - mx64) < 0.01 and abs(mn16 - mn64) < 0.01
+    small = L.reduced(wl, 2, 2, 512)
+    small["domains"][0]["perturb"] = np.zeros((2, 2))
+    dom = oracle.run(small["domains"][0], 320)
+    col = dom.phi[:, 0, 0]
+    z0 = int(np.argmax(col < 0))
+    h_ref = (z0 - 1) + col[z0 - 1] / (col[z0 - 1] - col[z0])
+    assert abs(mn64 - h_ref) < 1.0, (mn64, h_ref)
