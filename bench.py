@@ -40,6 +40,13 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2609_25670_amd", "csrc", f)
                   for f in ("lbm_kernels.hip", "lbm_dev.h")]
 KERNEL_NAMES = {"phase": "k_phase", "transfer": "k_transfer", "U": "k_scalar<..., 0>",
                 "T": "k_scalar<..., 1>", "flow": "k_flow"}
+KERNEL_NAMES_3D = {"phase": "k3_phase_collide + k3_phase_stream", "transfer": "k3_transfer_J + k3_transfer_apply",
+                   "U": "k3_scalar_collide/stream<..., 0>", "T": "k3_scalar_collide/stream<..., 1>",
+                   "flow": "k3_flow_collide + k3_flow_stream"}
+
+
+def sites_of(d: dict) -> int:
+    return d["nx"] * d["ny"] * (d["nz"] if d["dim"] == 3 else 1)
 
 
 def kernel_source_sha() -> str:
@@ -58,17 +65,20 @@ def algorithmic_bytes(kind: str, d: dict, storage: str) -> int:
     r = 8 if storage == "f64" else 4
     U, T, F = int(d["has_U"]), int(d["has_T"]), int(d["has_flow"])
     acc = d.get("coupling", "instant") == "accum"
-    if kind == "phase":      # s_1..s_4 in/out, phi in/out, U*, T*
-        return 8 * s + (2 + U + T) * r
+    dim = d["dim"]
+    qs = 5 if dim == 2 else 7            # scalar lattice
+    qf = 9 if dim == 2 else 19           # flow lattice
+    if kind == "phase":      # s_1..s_{Q-1} in/out, phi in/out, U*, T*
+        return 2 * (qs - 1) * s + (2 + U + T) * r
     if kind == "transfer":   # phi^q, phi^{q+1}; U in/out (or pending), T in place
         return (2 + 2 * U + 2 * T) * r
     if kind == "U":          # U, j_U, phi*, [u]; U, j_U out; [pending]
-        return (3 + 2 * F + 2 * acc) * r + 4 * s
-    if kind == "T":
+        return (3 + dim * F + 2 * acc) * r + 2 * dim * s
+    if kind == "T":          # as U; phi* only with phi-dependent properties
         tvar = d["kappa_S"] != d["kappa_L"] or d["rhoCp_S"] != d["rhoCp_L"]
-        return (2 + int(tvar) + 2 * F + 2 * acc) * r + 4 * s
-    if kind == "flow":       # rho, s_1..s_8, phi* in; rho, s_1..s_8, u out
-        return 5 * r + 16 * s
+        return (2 + int(tvar) + dim * F + 2 * acc) * r + 2 * dim * s
+    if kind == "flow":       # rho, s_1..s_{QF-1}, phi* in; rho, s_1..s_{QF-1}, u out
+        return (3 + dim) * r + 2 * (qf - 1) * s
     raise ValueError(kind)
 
 
@@ -81,10 +91,11 @@ def cycle_of(wl: dict) -> int:
     return L
 
 
-def traffic_from_profiles(workload: str, kind: str, sha: str):
+def traffic_from_profiles(workload: str, kind: str, sha: str, three_d: bool = False):
     """HBM bytes per launch from the committed rocprofv3 counter summary, if
     it was taken on the current kernel source; else None."""
-    path = os.path.join(ROOT, "profiles", f"counters_{KERNEL_NAMES[kind].split('<')[0]}_{workload}.json")
+    name = KERNEL_NAMES[kind].split("<")[0] if not three_d else KERNEL_NAMES_3D[kind].split(" ")[0].split("<")[0]
+    path = os.path.join(ROOT, "profiles", f"counters_{name}_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -109,13 +120,17 @@ def cpu_child(workload: str, steps: int) -> None:
     import oracle
 
     wl = L.workload(workload)
-    sites = sum(d["nx"] * d["ny"] for d in wl["domains"][:1])
-    dom = oracle.Domain(wl["domains"][0])
+    d0 = wl["domains"][0]
+    if d0["dim"] == 3:       # bounded sample: the reduced 3D grid
+        d0 = L.reduced(wl, 64, 64, 128)["domains"][0]
+    sites = sites_of(d0)
+    dom = oracle.Domain(d0)
     t0 = time.perf_counter()
     for _ in range(steps):
         dom.step()
     dt = time.perf_counter() - t0
-    print(json.dumps(dict(seconds=dt, steps=steps, sites=sites, mlups=sites * steps / dt / 1e6)))
+    grid = "x".join(str(d0[k]) for k in (("nx", "ny", "nz") if d0["dim"] == 3 else ("nx", "ny")))
+    print(json.dumps(dict(seconds=dt, steps=steps, sites=sites, grid=grid, mlups=sites * steps / dt / 1e6)))
 
 
 def main() -> int:
@@ -163,7 +178,7 @@ def main() -> int:
     wl = L.workload(args.workload)
     storage = args.storage or wl["storage"]
     cyc = cycle_of(wl)
-    sites = sum(d["nx"] * d["ny"] for d in wl["domains"])
+    sites = sum(sites_of(d) for d in wl["domains"])
     sim = simulation_for(wl, storage=storage)
     if args.tile_rows:
         sim.configure(args.tile_rows, True)
@@ -205,9 +220,10 @@ def main() -> int:
                               alg_GBs=nbytes / (ms * 1e-3) / 1e9 if ms > 0 else None,
                               share_ms_per_base_step=ms * per)
     dom_kind = max(per_kind, key=lambda k: per_kind[k]["share_ms_per_base_step"])
+    knames = KERNEL_NAMES_3D if d0["dim"] == 3 else KERNEL_NAMES
     dk = per_kind[dom_kind]
     sha = kernel_source_sha()
-    traffic = traffic_from_profiles(args.workload, dom_kind, sha)
+    traffic = traffic_from_profiles(args.workload, dom_kind, sha, d0["dim"] == 3)
     achieved = dk["alg_GBs"]
     bytes_per_base_step = sum(algorithmic_bytes(k, d0, storage) * v["launches_per_base_step"]
                               for k, v in per_kind.items())   # per site
@@ -227,7 +243,8 @@ def main() -> int:
         "data": "synthetic",
         "config": {
             "workload": wl["name"],
-            "grid": [d0["nx"], d0["ny"]] if len(wl["domains"]) == 1 else f"{len(wl['domains'])} domains",
+            "grid": ([d0["nx"], d0["ny"]] + ([d0["nz"]] if d0["dim"] == 3 else [])
+                     if len(wl["domains"]) == 1 else f"{len(wl['domains'])} domains"),
             "sites": sites,
             "fields": "+".join(["phi"] + [f for f, k in (("U", "has_U"), ("T", "has_T"), ("flow", "has_flow"))
                                           if d0[k]]),
@@ -238,7 +255,7 @@ def main() -> int:
         },
         "roofline": {
             "bound": "hbm",
-            "kernel": KERNEL_NAMES[dom_kind],
+            "kernel": knames[dom_kind],
             "achieved": round(achieved, 1),
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
@@ -259,7 +276,7 @@ def main() -> int:
             "cores": 1,
             "kind": "oracle",
             "sample": (f"FP64 NumPy oracle, first domain of {wl['name']} "
-                       f"({wl['domains'][0]['nx']}x{wl['domains'][0]['ny']}), {cb['steps']} base steps, "
+                       f"({cb['grid']}), {cb['steps']} base steps, "
                        f"{cb['seconds']:.1f} s on one core of {platform.processor() or platform.machine()}"),
         }
     if rank == 0:

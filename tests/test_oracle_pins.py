@@ -666,3 +666,26 @@ def test_tiny_grid_brute_force(case):
         for key, val in ref.items():
             got = getattr(dom, key)
             assert np.allclose(got, val, atol=1e-14, rtol=0), (case, dom.k, key, np.max(np.abs(got - val)))
+
+
+# --------------------------------------------------------------------- stability margin of Eq. (26)
+def test_anisotropic_streaming_needs_a_relaxation_margin():
+    """Eq. (26) divides the streamed populations by A = a_s^2 and subtracts
+    (1 - A) f: for A < 1 a checkerboard mode that the collision flips with
+    factor (1 - 1/tau_phi) grows unless |1 - 1/tau_phi| + (1 - A) <= A, i.e.
+    tau_phi >= 1/(2A) roughly 0.52 at eps = 0.02.  A circle with pure
+    Allen-Cahn dynamics (lambda = 0) stays within [-1, 1] at tau0 = 100
+    (tau_phi ~ 0.62) and overshoots at tau0 = 1000 (tau_phi ~ 0.512, the
+    Section 4.3 scale, where the thermosolutal case diverges)."""
+    def run(tau0):
+        d = _dom(nx=64, ny=64, W0=2.0, tau0=tau0, eps_s=0.02, lam=0.0, theta_c=0.5,
+                 bc=("periodic",) * 3, seeds=[(31.5, 31.5, 14.0)])
+        dom = oracle.Domain(d)
+        peak = 0.0
+        for _ in range(300):
+            dom.step()
+            peak = max(peak, float(np.max(np.abs(dom.phi))))
+        return peak
+
+    assert run(100.0) <= 1.0 + 1e-6
+    assert run(1000.0) > 1.05
