@@ -28,6 +28,31 @@
 namespace lbm {
 
 // ------------------------------------------------------------------ storage
+// Every plane is device global memory.  The plane pointers live in the
+// domain descriptor, so the compiler sees generic pointers and would emit
+// flat loads and stores (which also wait on the LDS counter); gp() casts
+// them to the global address space so they become global_load/store.
+#define GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ GLOBAL T* gp(const void* p) {
+  return (GLOBAL T*)(T*)p;
+}
+
+__device__ __forceinline__ double ld(const GLOBAL double* p, long long i) { return p[i]; }
+__device__ __forceinline__ float ld(const GLOBAL float* p, long long i) { return p[i]; }
+// (the 16-bit formats move as raw bits: their class types have no
+// address-space-qualified copy constructors)
+__device__ __forceinline__ float ld(const GLOBAL __half* p, long long i) {
+  return __half2float(__ushort_as_half(((const GLOBAL uint16_t*)p)[i]));
+}
+__device__ __forceinline__ float ld(const GLOBAL __hip_bfloat16* p, long long i) {
+  return __uint_as_float((uint32_t)((const GLOBAL uint16_t*)p)[i] << 16);
+}
+__device__ __forceinline__ void st(GLOBAL double* p, long long i, double v) { p[i] = v; }
+__device__ __forceinline__ void st(GLOBAL float* p, long long i, float v) { p[i] = v; }
+__device__ __forceinline__ void st(GLOBAL __half* p, long long i, float v) {
+  ((GLOBAL uint16_t*)p)[i] = __half_as_ushort(__float2half(v));
+}
 __device__ __forceinline__ double ld(const double* p, long long i) { return p[i]; }
 __device__ __forceinline__ float ld(const float* p, long long i) { return p[i]; }
 __device__ __forceinline__ float ld(const __half* p, long long i) { return __half2float(p[i]); }
@@ -52,13 +77,17 @@ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
   x ^= x >> 16;
   return x;
 }
-__device__ __forceinline__ void st(__hip_bfloat16* p, long long i, float v) {
+__device__ __forceinline__ uint16_t bf16_sr(float v, long long i) {
   uint32_t u = __float_as_uint(v);
   if ((u & 0x7f800000u) != 0x7f800000u)   // finite: add 16 random bits below the kept mantissa, truncate
     u += mix32(u + 0x9e3779b9u * (uint32_t)i) & 0xffffu;
   else
     u = __float_as_uint(__bfloat162float(__float2bfloat16(v)));
-  ((uint16_t*)p)[i] = (uint16_t)(u >> 16);
+  return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ void st(__hip_bfloat16* p, long long i, float v) { ((uint16_t*)p)[i] = bf16_sr(v, i); }
+__device__ __forceinline__ void st(GLOBAL __hip_bfloat16* p, long long i, float v) {
+  ((GLOBAL uint16_t*)p)[i] = bf16_sr(v, i);
 }
 
 // Reciprocal and inverse square root: the hardware approximations (about
@@ -172,7 +201,7 @@ __device__ __forceinline__ bool ring_cell(int r, int w, int h, int& lx, int& ly)
 // by BH rows.  Issued before the first barrier together with every other
 // global load of the block, so a block waits for memory once.
 template <class R, int BW, int BH>
-__device__ __forceinline__ void load_box2(R* box, const R* __restrict__ plane, int px, int x0, int y0, int nx,
+__device__ __forceinline__ void load_box2(R* box, const GLOBAL R* __restrict__ plane, int px, int x0, int y0, int nx,
                                           int ny, int bcx, int bcy, int tx, int ty) {
   static_assert(BW == TX + 4, "box width");
   const int gx0 = ghost(x0 - 2 + tx, nx, bcx);
@@ -180,7 +209,7 @@ __device__ __forceinline__ void load_box2(R* box, const R* __restrict__ plane, i
   const int gx1 = two ? ghost(x0 - 2 + tx + TX, nx, bcx) : 0;
 #pragma unroll
   for (int ly = ty; ly < BH; ly += BY) {
-    const R* row = plane + ghost(y0 - 2 + ly, ny, bcy) * px;
+    const GLOBAL R* row = plane + ghost(y0 - 2 + ly, ny, bcy) * px;
     box[ly * BW + tx] = row[gx0];
     if (two) box[ly * BW + tx + TX] = row[gx1];
   }
@@ -207,14 +236,14 @@ __global__ __launch_bounds__(NTHR) void k_phase(const Dom* __restrict__ doms, co
   const int w = min(TX, nx - x0), h = min(TY, ny - y0);
   const int bcx = D.bc[0], bcy = D.bc[1];
   const int ib = par(n_phi(D, k - 1)), ob = ib ^ 1;
-  const R* __restrict__ phi_in = (const R*)D.phi[ib];
-  R* __restrict__ phi_out = (R*)D.phi[ob];
-  const S* __restrict__ s_in = (const S*)D.sphi[ib];
-  S* __restrict__ s_out = (S*)D.sphi[ob];
+  GLOBAL const R* __restrict__ phi_in = gp<const R>(D.phi[ib]);
+  GLOBAL R* __restrict__ phi_out = gp<R>(D.phi[ob]);
+  GLOBAL const S* __restrict__ s_in = gp<const S>(D.sphi[ib]);
+  GLOBAL S* __restrict__ s_out = gp<S>(D.sphi[ob]);
   // latest U and T (before this step's transfer)
   const long long nU = (D.accum ? 0 : (k - 1) / D.N_phi) + (k - 1) / D.N_U;
-  const R* __restrict__ Up = D.has_U ? (const R*)D.U[par(nU)] : nullptr;
-  const R* __restrict__ Tp = D.has_T ? (const R*)D.T[par(n_T(D, k - 1))] : nullptr;
+  GLOBAL const R* __restrict__ Up = D.has_U ? gp<const R>(D.U[par(nU)]) : nullptr;
+  GLOBAL const R* __restrict__ Tp = D.has_T ? gp<const R>(D.T[par(n_T(D, k - 1))]) : nullptr;
 
   PhaseConst<R> c;
   c.dt = R(D.N_phi * D.dt_base);
@@ -351,14 +380,14 @@ __global__ __launch_bounds__(NTHR) void k_transfer(const Dom* __restrict__ doms,
   const int x0 = t.y, y0 = t.z;
   const int w = min(TX, nx - x0), h = min(TY, ny - y0);
   const int bcx = D.bc[0], bcy = D.bc[1];
-  const R* __restrict__ phi_old = (const R*)D.phi[par(n_phi(D, k - 1))];
-  const R* __restrict__ phi_new = (const R*)D.phi[par(n_phi(D, k))];
+  GLOBAL const R* __restrict__ phi_old = gp<const R>(D.phi[par(n_phi(D, k - 1))]);
+  GLOBAL const R* __restrict__ phi_new = gp<const R>(D.phi[par(n_phi(D, k))]);
   const long long nU = (D.accum ? 0 : (k - 1) / D.N_phi) + (k - 1) / D.N_U;
-  const R* __restrict__ Uin = D.has_U ? (const R*)D.U[par(nU)] : nullptr;
-  R* __restrict__ Uout = D.has_U ? (R*)D.U[par(nU + 1)] : nullptr;
-  R* __restrict__ Tcur = D.has_T ? (R*)D.T[par(n_T(D, k - 1))] : nullptr;
-  R* __restrict__ PU = (R*)D.PU;
-  R* __restrict__ PT = (R*)D.PT;
+  GLOBAL const R* __restrict__ Uin = D.has_U ? gp<const R>(D.U[par(nU)]) : nullptr;
+  GLOBAL R* __restrict__ Uout = D.has_U ? gp<R>(D.U[par(nU + 1)]) : nullptr;
+  GLOBAL R* __restrict__ Tcur = D.has_T ? gp<R>(D.T[par(n_T(D, k - 1))]) : nullptr;
+  GLOBAL R* __restrict__ PU = gp<R>(D.PU);
+  GLOBAL R* __restrict__ PT = gp<R>(D.PT);
   const R omk = R(1.0 - D.kc), opk = R(1.0 + D.kc);
   const R Uref = R(D.U0);   // the U plane holds U - U0
   const R cJ = R(D.W0 / (2.0 * 1.4142135623730951));
@@ -509,28 +538,28 @@ __global__ __launch_bounds__(NTHR) void k_scalar(const Dom* __restrict__ doms, c
   const int x0 = t.y, y0 = t.z;
   const int w = min(TX, nx - x0), h = min(TY, ny - y0);
   const int bcx = D.bc[0], bcy = D.bc[1];
-  const R* __restrict__ cin;
-  R* __restrict__ cout;
-  const S* __restrict__ jin;
-  S* __restrict__ jout;
-  R* __restrict__ pend;
+  GLOBAL const R* __restrict__ cin;
+  GLOBAL R* __restrict__ cout;
+  GLOBAL const S* __restrict__ jin;
+  GLOBAL S* __restrict__ jout;
+  GLOBAL R* __restrict__ pend;
   if (FIELD == 0) {
     const long long nU = (D.accum ? 0 : k / D.N_phi) + (k - 1) / D.N_U;
-    cin = (const R*)D.U[par(nU)];
-    cout = (R*)D.U[par(nU + 1)];
-    jin = (const S*)D.jU[par(n_jU(D, k - 1))];
-    jout = (S*)D.jU[par(n_jU(D, k))];
-    pend = (R*)D.PU;
+    cin = gp<const R>(D.U[par(nU)]);
+    cout = gp<R>(D.U[par(nU + 1)]);
+    jin = gp<const S>(D.jU[par(n_jU(D, k - 1))]);
+    jout = gp<S>(D.jU[par(n_jU(D, k))]);
+    pend = gp<R>(D.PU);
   } else {
-    cin = (const R*)D.T[par(n_T(D, k - 1))];
-    cout = (R*)D.T[par(n_T(D, k))];
-    jin = (const S*)D.jT[par(n_T(D, k - 1))];
-    jout = (S*)D.jT[par(n_T(D, k))];
-    pend = (R*)D.PT;
+    cin = gp<const R>(D.T[par(n_T(D, k - 1))]);
+    cout = gp<R>(D.T[par(n_T(D, k))]);
+    jin = gp<const S>(D.jT[par(n_T(D, k - 1))]);
+    jout = gp<S>(D.jT[par(n_T(D, k))]);
+    pend = gp<R>(D.PT);
   }
-  const R* __restrict__ phis = (const R*)D.phi[par(n_phi(D, k))];
+  GLOBAL const R* __restrict__ phis = gp<const R>(D.phi[par(n_phi(D, k))]);
   // velocity of the latest flow update (the flow of step k runs after U, T)
-  const R* __restrict__ vel = D.has_F ? (const R*)D.vel[par(n_F(D, k - 1))] : nullptr;
+  GLOBAL const R* __restrict__ vel = D.has_F ? gp<const R>(D.vel[par(n_F(D, k - 1))]) : nullptr;
   const bool need_phi = FIELD == 0 || D.T_var;
   const R dt = R(N * D.dt_base);
   const R omk = R(1.0 - D.kc), opk = R(1.0 + D.kc);
@@ -751,12 +780,12 @@ __global__ __launch_bounds__(NTHR) void k_flow(const Dom* __restrict__ doms, con
   const int nx = D.nx, ny = D.ny;
   const long long px = D.px, pl = D.plane;
   const int fbx = D.fbc[0], fby = D.fbc[1];
-  const R* __restrict__ rho_in = (const R*)D.rho[par(n_F(D, k - 1))];
-  R* __restrict__ rho_out = (R*)D.rho[par(n_F(D, k))];
-  const S* __restrict__ s_in = (const S*)D.sF[par(n_F(D, k - 1))];
-  S* __restrict__ s_out = (S*)D.sF[par(n_F(D, k))];
-  R* __restrict__ vel = (R*)D.vel[par(n_F(D, k))];
-  const R* __restrict__ phis = (const R*)D.phi[par(n_phi(D, k))];
+  GLOBAL const R* __restrict__ rho_in = gp<const R>(D.rho[par(n_F(D, k - 1))]);
+  GLOBAL R* __restrict__ rho_out = gp<R>(D.rho[par(n_F(D, k))]);
+  GLOBAL const S* __restrict__ s_in = gp<const S>(D.sF[par(n_F(D, k - 1))]);
+  GLOBAL S* __restrict__ s_out = gp<S>(D.sF[par(n_F(D, k))]);
+  GLOBAL R* __restrict__ vel = gp<R>(D.vel[par(n_F(D, k))]);
+  GLOBAL const R* __restrict__ phis = gp<const R>(D.phi[par(n_phi(D, k))]);
   const R dt = R(D.N_F * D.dt_base);
   const R Fx = R(D.Fx), Fy = R(D.Fy);
   const R snu = R(1.0 / (3.0 * D.N_F * D.dt_base * D.nu + 0.5));
@@ -878,30 +907,30 @@ __global__ void k_init(const Dom* __restrict__ doms, int dom) {
     phi = v > phi ? v : phi;
   }
   const R ph = R(phi);
-  ((R*)D.phi[0])[o] = ph;
-  ((R*)D.phi[1])[o] = ph;
+  (gp<R>(D.phi[0]))[o] = ph;
+  (gp<R>(D.phi[1]))[o] = ph;
   for (int q = 0; q < 4; ++q) {
-    st((S*)D.sphi[0], o + q * pl, R(0));
-    st((S*)D.sphi[1], o + q * pl, R(0));
+    st(gp<S>(D.sphi[0]), o + q * pl, R(0));
+    st(gp<S>(D.sphi[1]), o + q * pl, R(0));
   }
   const double ux = (D.has_F && D.u0_liquid) ? D.u_in * (1.0 - double(ph)) * 0.5 : 0.0;
   if (D.has_U) {
     const double dtU = D.N_U * D.dt_base;
     for (int b = 0; b < 2; ++b) {
-      ((R*)D.U[b])[o] = R(0);    // U - U0
-      st((S*)D.jU[b], o, R(D.U0 * ux * dtU));
-      st((S*)D.jU[b], o + pl, R(0));
+      (gp<R>(D.U[b]))[o] = R(0);    // U - U0
+      st(gp<S>(D.jU[b]), o, R(D.U0 * ux * dtU));
+      st(gp<S>(D.jU[b]), o + pl, R(0));
     }
-    ((R*)D.PU)[o] = R(0);
+    (gp<R>(D.PU))[o] = R(0);
   }
   if (D.has_T) {
     const double dtT = D.N_T * D.dt_base;
     for (int b = 0; b < 2; ++b) {
-      ((R*)D.T[b])[o] = R(0);    // T - T0
-      st((S*)D.jT[b], o, R(D.T0 * ux * dtT));
-      st((S*)D.jT[b], o + pl, R(0));
+      (gp<R>(D.T[b]))[o] = R(0);    // T - T0
+      st(gp<S>(D.jT[b]), o, R(D.T0 * ux * dtT));
+      st(gp<S>(D.jT[b]), o + pl, R(0));
     }
-    ((R*)D.PT)[o] = R(0);
+    (gp<R>(D.PT))[o] = R(0);
   }
   if (D.has_F) {
     const double dtF = D.N_F * D.dt_base;
@@ -910,12 +939,12 @@ __global__ void k_init(const Dom* __restrict__ doms, int dom) {
     const R w[9] = {R(4.0 / 9), R(1.0 / 9), R(1.0 / 9), R(1.0 / 9), R(1.0 / 9),
                     R(1.0 / 36), R(1.0 / 36), R(1.0 / 36), R(1.0 / 36)};
     for (int b = 0; b < 2; ++b) {
-      ((R*)D.rho[b])[o] = R(1);
-      for (int q = 1; q < 9; ++q) st((S*)D.sF[b], o + (q - 1) * pl, feq[q] - w[q]);
+      (gp<R>(D.rho[b]))[o] = R(1);
+      for (int q = 1; q < 9; ++q) st(gp<S>(D.sF[b]), o + (q - 1) * pl, feq[q] - w[q]);
     }
     for (int b = 0; b < 2; ++b) {
-      ((R*)D.vel[b])[o] = R(ux);
-      ((R*)D.vel[b])[o + pl] = R(0);
+      (gp<R>(D.vel[b]))[o] = R(ux);
+      (gp<R>(D.vel[b]))[o + pl] = R(0);
     }
   }
 }
@@ -929,26 +958,26 @@ template <class R, class S>
 __device__ double read_plane(const Dom& D, long long k, int code, long long o) {
   const long long pl = D.plane;
   switch (code) {
-    case 0: return double(((const R*)D.phi[par(n_phi(D, k))])[o]);
-    case 1: return double(((const R*)D.U[par(n_U(D, k))])[o]) + D.U0;
-    case 2: return double(((const R*)D.T[par(n_T(D, k))])[o]) + D.T0;
-    case 8: return double(((const R*)D.U[par(n_U(D, k))])[o]);
-    case 9: return double(((const R*)D.T[par(n_T(D, k))])[o]);
-    case 3: return double(((const R*)D.rho[par(n_F(D, k))])[o]);
-    case 4: return double(((const R*)D.vel[par(n_F(D, k))])[o]);
-    case 5: return double(((const R*)D.vel[par(n_F(D, k))])[o + pl]);
-    case 20: case 21: return double(ld((const S*)D.jU[par(n_jU(D, k))], o + (code - 20) * pl));
-    case 30: case 31: return double(ld((const S*)D.jT[par(n_T(D, k))], o + (code - 30) * pl));
-    case 50: return double(((const R*)D.PU)[o]);
-    case 51: return double(((const R*)D.PT)[o]);
+    case 0: return double((gp<const R>(D.phi[par(n_phi(D, k))]))[o]);
+    case 1: return double((gp<const R>(D.U[par(n_U(D, k))]))[o]) + D.U0;
+    case 2: return double((gp<const R>(D.T[par(n_T(D, k))]))[o]) + D.T0;
+    case 8: return double((gp<const R>(D.U[par(n_U(D, k))]))[o]);
+    case 9: return double((gp<const R>(D.T[par(n_T(D, k))]))[o]);
+    case 3: return double((gp<const R>(D.rho[par(n_F(D, k))]))[o]);
+    case 4: return double((gp<const R>(D.vel[par(n_F(D, k))]))[o]);
+    case 5: return double((gp<const R>(D.vel[par(n_F(D, k))]))[o + pl]);
+    case 20: case 21: return double(ld(gp<const S>(D.jU[par(n_jU(D, k))]), o + (code - 20) * pl));
+    case 30: case 31: return double(ld(gp<const S>(D.jT[par(n_T(D, k))]), o + (code - 30) * pl));
+    case 50: return double((gp<const R>(D.PU))[o]);
+    case 51: return double((gp<const R>(D.PT))[o]);
     default: break;
   }
-  if (code >= 60 && code <= 63) return double(ld((const S*)D.sphi[par(n_phi(D, k))], o + (code - 60) * pl));
-  if (code >= 70 && code <= 77) return double(ld((const S*)D.sF[par(n_F(D, k))], o + (code - 70) * pl));
+  if (code >= 60 && code <= 63) return double(ld(gp<const S>(D.sphi[par(n_phi(D, k))]), o + (code - 60) * pl));
+  if (code >= 70 && code <= 77) return double(ld(gp<const S>(D.sF[par(n_F(D, k))]), o + (code - 70) * pl));
   if (code >= 10 && code <= 14) {
     const int b = par(n_phi(D, k));
-    const R* ph = (const R*)D.phi[b];
-    const S* s = (const S*)D.sphi[b];
+    GLOBAL const R* ph = gp<const R>(D.phi[b]);
+    GLOBAL const S* s = gp<const S>(D.sphi[b]);
     const R phi = ph[o];
     const R s1 = ld(s, o), s2 = ld(s, o + pl), s3 = ld(s, o + 2 * pl), s4 = ld(s, o + 3 * pl);
     if (code == 10) return double(phi * R(1.0 / 3.0) - (s1 + s2 + s3 + s4));
@@ -957,8 +986,8 @@ __device__ double read_plane(const Dom& D, long long k, int code, long long o) {
   }
   if (code >= 40 && code <= 48) {
     const int b = par(n_F(D, k));
-    const R rho = ((const R*)D.rho[b])[o];
-    const S* s = (const S*)D.sF[b];
+    const R rho = (gp<const R>(D.rho[b]))[o];
+    GLOBAL const S* s = gp<const S>(D.sF[b]);
     const R w[9] = {R(4.0 / 9), R(1.0 / 9), R(1.0 / 9), R(1.0 / 9), R(1.0 / 9),
                     R(1.0 / 36), R(1.0 / 36), R(1.0 / 36), R(1.0 / 36)};
     if (code == 40) {
@@ -1004,23 +1033,23 @@ __global__ void k_write(const Dom* __restrict__ doms, int dom, long long k, cons
     const int code = codes[c];
     const double v = src[c * n + i];
     switch (code) {
-      case 0: ((R*)D.phi[par(n_phi(D, k))])[o] = R(v); break;
-      case 1: ((R*)D.U[par(n_U(D, k))])[o] = R(v - D.U0); break;
-      case 2: ((R*)D.T[par(n_T(D, k))])[o] = R(v - D.T0); break;
-      case 8: ((R*)D.U[par(n_U(D, k))])[o] = R(v); break;
-      case 9: ((R*)D.T[par(n_T(D, k))])[o] = R(v); break;
-      case 3: ((R*)D.rho[par(n_F(D, k))])[o] = R(v); break;
-      case 4: ((R*)D.vel[par(n_F(D, k))])[o] = R(v); break;
-      case 5: ((R*)D.vel[par(n_F(D, k))])[o + pl] = R(v); break;
-      case 20: case 21: st((S*)D.jU[par(n_jU(D, k))], o + (code - 20) * pl, R(v)); break;
-      case 30: case 31: st((S*)D.jT[par(n_T(D, k))], o + (code - 30) * pl, R(v)); break;
-      case 50: ((R*)D.PU)[o] = R(v); break;
-      case 51: ((R*)D.PT)[o] = R(v); break;
+      case 0: (gp<R>(D.phi[par(n_phi(D, k))]))[o] = R(v); break;
+      case 1: (gp<R>(D.U[par(n_U(D, k))]))[o] = R(v - D.U0); break;
+      case 2: (gp<R>(D.T[par(n_T(D, k))]))[o] = R(v - D.T0); break;
+      case 8: (gp<R>(D.U[par(n_U(D, k))]))[o] = R(v); break;
+      case 9: (gp<R>(D.T[par(n_T(D, k))]))[o] = R(v); break;
+      case 3: (gp<R>(D.rho[par(n_F(D, k))]))[o] = R(v); break;
+      case 4: (gp<R>(D.vel[par(n_F(D, k))]))[o] = R(v); break;
+      case 5: (gp<R>(D.vel[par(n_F(D, k))]))[o + pl] = R(v); break;
+      case 20: case 21: st(gp<S>(D.jU[par(n_jU(D, k))]), o + (code - 20) * pl, R(v)); break;
+      case 30: case 31: st(gp<S>(D.jT[par(n_T(D, k))]), o + (code - 30) * pl, R(v)); break;
+      case 50: (gp<R>(D.PU))[o] = R(v); break;
+      case 51: (gp<R>(D.PT))[o] = R(v); break;
       case 60: case 61: case 62: case 63:
-        st((S*)D.sphi[par(n_phi(D, k))], o + (code - 60) * pl, R(v));
+        st(gp<S>(D.sphi[par(n_phi(D, k))]), o + (code - 60) * pl, R(v));
         break;
       case 70: case 71: case 72: case 73: case 74: case 75: case 76: case 77:
-        st((S*)D.sF[par(n_F(D, k))], o + (code - 70) * pl, R(v));
+        st(gp<S>(D.sF[par(n_F(D, k))]), o + (code - 70) * pl, R(v));
         break;
       default:
         if (code == 10) cphi = c;
@@ -1036,8 +1065,8 @@ __global__ void k_write(const Dom* __restrict__ doms, int dom, long long k, cons
       f[q] = R(src[(cphi + q) * n + i]);
       phi += f[q];
     }
-    ((R*)D.phi[b])[o] = phi;
-    for (int q = 1; q < 5; ++q) st((S*)D.sphi[b], o + (q - 1) * pl, f[q] - phi * R(1.0 / 6.0));
+    (gp<R>(D.phi[b]))[o] = phi;
+    for (int q = 1; q < 5; ++q) st(gp<S>(D.sphi[b]), o + (q - 1) * pl, f[q] - phi * R(1.0 / 6.0));
   }
   if (cflow >= 0) {
     const int b = par(n_F(D, k));
@@ -1049,8 +1078,8 @@ __global__ void k_write(const Dom* __restrict__ doms, int dom, long long k, cons
       f[q] = R(src[(cflow + q) * n + i]);
       rho += f[q];
     }
-    ((R*)D.rho[b])[o] = rho;
-    for (int q = 1; q < 9; ++q) st((S*)D.sF[b], o + (q - 1) * pl, f[q] - w[q] * rho);
+    (gp<R>(D.rho[b]))[o] = rho;
+    for (int q = 1; q < 9; ++q) st(gp<S>(D.sF[b]), o + (q - 1) * pl, f[q] - w[q] * rho);
   }
 }
 
@@ -1067,10 +1096,10 @@ __global__ __launch_bounds__(NTHR) void k_diag_tiles(const Dom* __restrict__ dom
   if (t.x < 0) return;
   const Dom& D = doms[t.x];
   const long long px = D.px;
-  const R* phi = (const R*)D.phi[par(n_phi(D, k))];
-  const R* U = D.has_U ? (const R*)D.U[par(n_U(D, k))] : nullptr;
-  const R* T = D.has_T ? (const R*)D.T[par(n_T(D, k))] : nullptr;
-  const R* rho = D.has_F ? (const R*)D.rho[par(n_F(D, k))] : nullptr;
+  GLOBAL const R* phi = gp<const R>(D.phi[par(n_phi(D, k))]);
+  GLOBAL const R* U = D.has_U ? gp<const R>(D.U[par(n_U(D, k))]) : nullptr;
+  GLOBAL const R* T = D.has_T ? gp<const R>(D.T[par(n_T(D, k))]) : nullptr;
+  GLOBAL const R* rho = D.has_F ? gp<const R>(D.rho[par(n_F(D, k))]) : nullptr;
   const int tx = threadIdx.x, ty = threadIdx.y;
   double a[5] = {0, 0, 0, 0, 0};
   for (int r = 0; r < RPT; ++r) {
@@ -1189,7 +1218,7 @@ __global__ void k_tips(const Dom* __restrict__ doms, long long k, DiagOut* __res
     if (threadIdx.x == 0) out[d].tip[s * 4 + ax] = 0.0;
     return;
   }
-  const R* phi = (const R*)D.phi[par(n_phi(D, k))];
+  GLOBAL const R* phi = gp<const R>(D.phi[par(n_phi(D, k))]);
   const double ang = atan2(D.sth, D.cth) + ax * 1.5707963267948966;
   const double c = cos(ang), sn = sin(ang);
   const double cx = D.seed[s][0], cy = D.seed[s][1];
@@ -1289,7 +1318,7 @@ __device__ __forceinline__ bool up3(const Dom& D, const Site3& s, int ex, int ey
 
 // isotropic gradient with D3Q19 weights: d_a f = sum_q (3 w_q) e_qa f(x + e_q)
 template <class R>
-__device__ __forceinline__ void grad3(const Dom& D, const Site3& s, const R* __restrict__ f, R* g) {
+__device__ __forceinline__ void grad3(const Dom& D, const Site3& s, const GLOBAL R* __restrict__ f, R* g) {
   g[0] = g[1] = g[2] = R(0);
 #pragma unroll
   for (int q = 1; q < 19; ++q) {
@@ -1342,12 +1371,12 @@ __global__ __launch_bounds__(256) void k3_phase_collide(const Dom* __restrict__ 
   if (!site3(D, (long long)blockIdx.x * 256 + threadIdx.x, s) || k % D.N_phi) return;
   const unsigned pl = (unsigned)D.plane;
   const int ib = par(n_phi(D, k - 1));
-  const R* phi = (const R*)D.phi[ib];
-  const S* sp = (const S*)D.sphi[ib];
+  GLOBAL const R* phi = gp<const R>(D.phi[ib]);
+  GLOBAL const S* sp = gp<const S>(D.sphi[ib]);
   const long long nU = (D.accum ? 0 : (k - 1) / D.N_phi) + (k - 1) / D.N_U;
   // the U and T planes hold U - U0 and T - T0
-  const R Us = D.has_U ? ((const R*)D.U[par(nU)])[s.o] + R(D.U0) : R(0);
-  const R Ts = D.has_T ? ((const R*)D.T[par(n_T(D, k - 1))])[s.o] + R(D.T0) : R(D.T_m + D.m_L * D.C_inf);
+  const R Us = D.has_U ? (gp<const R>(D.U[par(nU)]))[s.o] + R(D.U0) : R(0);
+  const R Ts = D.has_T ? (gp<const R>(D.T[par(n_T(D, k - 1))]))[s.o] + R(D.T0) : R(D.T_m + D.m_L * D.C_inf);
   R g[3];
   grad3(D, s, phi, g);
   R sv[6];
@@ -1356,7 +1385,7 @@ __global__ __launch_bounds__(256) void k3_phase_collide(const Dom* __restrict__ 
   const R j[3] = {sv[0] - sv[1], sv[2] - sv[3], sv[4] - sv[5]};
   R dP, K[3], A;
   phase_collide3(D, phi[s.o], g, j, Us, Ts, dP, K, A);
-  R* scr = (R*)D.scr;
+  GLOBAL R* scr = gp<R>(D.scr);
   scr[s.o] = dP;
   scr[s.o + pl] = K[0];
   scr[s.o + 2 * pl] = K[1];
@@ -1372,9 +1401,9 @@ __global__ __launch_bounds__(256) void k3_phase_stream(const Dom* __restrict__ d
   if (!site3(D, (long long)blockIdx.x * 256 + threadIdx.x, s) || k % D.N_phi) return;
   const unsigned pl = (unsigned)D.plane;
   const int ib = par(n_phi(D, k - 1)), ob = ib ^ 1;
-  const R* phi = (const R*)D.phi[ib];
-  const S* sp = (const S*)D.sphi[ib];
-  const R* scr = (const R*)D.scr;
+  GLOBAL const R* phi = gp<const R>(D.phi[ib]);
+  GLOBAL const S* sp = gp<const S>(D.sphi[ib]);
+  GLOBAL const R* scr = gp<const R>(D.scr);
   const R py = phi[s.o];
   const R dPy = scr[s.o], Ky[3] = {scr[s.o + pl], scr[s.o + 2 * pl], scr[s.o + 3 * pl]};
   const R A = scr[s.o + 4 * pl], iA = rcp(A), oA = R(1) - A;
@@ -1401,8 +1430,8 @@ __global__ __launch_bounds__(256) void k3_phase_stream(const Dom* __restrict__ d
     dn[q] = (dpost - oA * sv[q - 1]) * iA;
     sum += dn[q];
   }
-  ((R*)D.phi[ob])[s.o] = py + sum;
-  S* so = (S*)D.sphi[ob];
+  (gp<R>(D.phi[ob]))[s.o] = py + sum;
+  GLOBAL S* so = gp<S>(D.sphi[ob]);
 #pragma unroll
   for (int q = 1; q < 7; ++q) st(so, s.o + (q - 1) * pl, dn[q] - R(0.125) * sum);
 }
@@ -1414,10 +1443,10 @@ __global__ __launch_bounds__(256) void k3_transfer_J(const Dom* __restrict__ dom
   Site3 s;
   if (!site3(D, (long long)blockIdx.x * 256 + threadIdx.x, s) || k % D.N_phi || !D.has_U) return;
   const unsigned pl = (unsigned)D.plane;
-  const R* pn = (const R*)D.phi[par(n_phi(D, k))];
-  const R* po = (const R*)D.phi[par(n_phi(D, k - 1))];
+  GLOBAL const R* pn = gp<const R>(D.phi[par(n_phi(D, k))]);
+  GLOBAL const R* po = gp<const R>(D.phi[par(n_phi(D, k - 1))]);
   const long long nU = (D.accum ? 0 : (k - 1) / D.N_phi) + (k - 1) / D.N_U;
-  const R* Uin = (const R*)D.U[par(nU)];
+  GLOBAL const R* Uin = gp<const R>(D.U[par(nU)]);
   R g[3];
   grad3(D, s, pn, g);
   const R gg = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
@@ -1428,7 +1457,7 @@ __global__ __launch_bounds__(256) void k3_transfer_J(const Dom* __restrict__ dom
 #pragma unroll
     for (int c = 0; c < 3; ++c) J[c] = -a * g[c];
   }
-  R* scr = (R*)D.scr;
+  GLOBAL R* scr = gp<R>(D.scr);
 #pragma unroll
   for (int c = 0; c < 3; ++c) scr[s.o + c * pl] = J[c];
 }
@@ -1444,15 +1473,15 @@ __global__ __launch_bounds__(256) void k3_transfer_apply(const Dom* __restrict__
   const bool ok = site3(D, (long long)blockIdx.x * 256 + threadIdx.x, s);
   if (k % D.N_phi) return;
   const unsigned pl = (unsigned)D.plane;
-  const R* pn = (const R*)D.phi[par(n_phi(D, k))];
-  const R* po = (const R*)D.phi[par(n_phi(D, k - 1))];
+  GLOBAL const R* pn = gp<const R>(D.phi[par(n_phi(D, k))]);
+  GLOBAL const R* po = gp<const R>(D.phi[par(n_phi(D, k - 1))]);
   R amax = R(0);
   if (ok) {
     const R p1 = pn[s.o], dphi = p1 - po[s.o];
     if (D.has_U) {
       const long long nU = (D.accum ? 0 : (k - 1) / D.N_phi) + (k - 1) / D.N_U;
-      const R* Uin = (const R*)D.U[par(nU)];
-      const R* J = (const R*)D.scr;
+      GLOBAL const R* Uin = gp<const R>(D.U[par(nU)]);
+      GLOBAL const R* J = gp<const R>(D.scr);
       R div = R(0);
 #pragma unroll
       for (int q = 1; q < 19; ++q) {
@@ -1471,16 +1500,16 @@ __global__ __launch_bounds__(256) void k3_transfer_apply(const Dom* __restrict__
                    rcp(R(1.0 + D.kc) - R(1.0 - D.kc) * p1);
       amax = fabs(dU);
       if (D.accum) {
-        R* PU = (R*)D.PU;
+        GLOBAL R* PU = gp<R>(D.PU);
         PU[s.o] = PU[s.o] + dU;
       } else {
-        ((R*)D.U[par(nU + 1)])[s.o] = Us + dU;
+        (gp<R>(D.U[par(nU + 1)]))[s.o] = Us + dU;
       }
     }
     if (D.has_T && !D.T_pulled) {
       const R rc = (R(1) + p1) * R(0.5 * D.rcS) + (R(1) - p1) * R(0.5 * D.rcL);
       const R dT = R(D.rho_L * D.L_h) * dphi * rcp(R(2) * rc);
-      R* Tp = D.accum ? (R*)D.PT : (R*)D.T[par(n_T(D, k - 1))];
+      GLOBAL R* Tp = D.accum ? gp<R>(D.PT) : gp<R>(D.T[par(n_T(D, k - 1))]);
       Tp[s.o] = Tp[s.o] + dT;
     }
   }
@@ -1504,21 +1533,21 @@ __global__ __launch_bounds__(256) void k3_scalar_collide(const Dom* __restrict__
   Site3 s;
   if (!site3(D, (long long)blockIdx.x * 256 + threadIdx.x, s) || k % N) return;
   const unsigned pl = (unsigned)D.plane;
-  const R* cin;
-  const S* jin;
+  GLOBAL const R* cin;
+  GLOBAL const S* jin;
   if (FIELD == 0) {
-    cin = (const R*)D.U[par((D.accum ? 0 : k / D.N_phi) + (k - 1) / D.N_U)];
-    jin = (const S*)D.jU[par(n_jU(D, k - 1))];
+    cin = gp<const R>(D.U[par((D.accum ? 0 : k / D.N_phi) + (k - 1) / D.N_U)]);
+    jin = gp<const S>(D.jU[par(n_jU(D, k - 1))]);
   } else {
-    cin = (const R*)D.T[par(n_T(D, k - 1))];
-    jin = (const S*)D.jT[par(n_T(D, k - 1))];
+    cin = gp<const R>(D.T[par(n_T(D, k - 1))]);
+    jin = gp<const S>(D.jT[par(n_T(D, k - 1))]);
   }
-  const R* phis = (const R*)D.phi[par(n_phi(D, k))];
+  GLOBAL const R* phis = gp<const R>(D.phi[par(n_phi(D, k))]);
   const R dt = R(N * D.dt_base);
   const R chi = cin[s.o] + R(FIELD == 0 ? D.U0 : D.T0);   // the plane holds chi - chi_ref
   R u[3] = {R(0), R(0), R(0)};
   if (D.has_F) {
-    const R* vel = (const R*)D.vel[par(n_F(D, k - 1))];
+    GLOBAL const R* vel = gp<const R>(D.vel[par(n_F(D, k - 1))]);
 #pragma unroll
     for (int a = 0; a < 3; ++a) u[a] = vel[s.o + a * pl];
   }
@@ -1554,7 +1583,7 @@ __global__ __launch_bounds__(256) void k3_scalar_collide(const Dom* __restrict__
     itau = rcp(R(4) * dt * R(D.kL / D.rcL) + R(0.5));
   }
   const R om = R(1) - itau;
-  R* scr = (R*)D.scr;
+  GLOBAL R* scr = gp<R>(D.scr);
   scr[s.o] = dt * Q;
 #pragma unroll
   for (int a = 0; a < 3; ++a) scr[s.o + (a + 1) * pl] = je[a] + om * (j[a] - je[a]);
@@ -1572,23 +1601,23 @@ __global__ __launch_bounds__(256) void k3_scalar_stream(const Dom* __restrict__ 
   const bool ok = site3(D, (long long)blockIdx.x * 256 + threadIdx.x, s);
   if (k % N) return;
   const unsigned pl = (unsigned)D.plane;
-  const R* cin;
-  R* cout;
-  S* jout;
-  R* pend;
+  GLOBAL const R* cin;
+  GLOBAL R* cout;
+  GLOBAL S* jout;
+  GLOBAL R* pend;
   if (FIELD == 0) {
     const long long nU = (D.accum ? 0 : k / D.N_phi) + (k - 1) / D.N_U;
-    cin = (const R*)D.U[par(nU)];
-    cout = (R*)D.U[par(nU + 1)];
-    jout = (S*)D.jU[par(n_jU(D, k))];
-    pend = (R*)D.PU;
+    cin = gp<const R>(D.U[par(nU)]);
+    cout = gp<R>(D.U[par(nU + 1)]);
+    jout = gp<S>(D.jU[par(n_jU(D, k))]);
+    pend = gp<R>(D.PU);
   } else {
-    cin = (const R*)D.T[par(n_T(D, k - 1))];
-    cout = (R*)D.T[par(n_T(D, k))];
-    jout = (S*)D.jT[par(n_T(D, k))];
-    pend = (R*)D.PT;
+    cin = gp<const R>(D.T[par(n_T(D, k - 1))]);
+    cout = gp<R>(D.T[par(n_T(D, k))]);
+    jout = gp<S>(D.jT[par(n_T(D, k))]);
+    pend = gp<R>(D.PT);
   }
-  const R* scr = (const R*)D.scr;
+  GLOBAL const R* scr = gp<const R>(D.scr);
   R amax = R(0);
   if (ok) {
     const R cy = cin[s.o], dPy = scr[s.o];
@@ -1695,8 +1724,8 @@ __global__ __launch_bounds__(256) void k3_flow_collide(const Dom* __restrict__ d
   if (!site3(D, (long long)blockIdx.x * 256 + threadIdx.x, s) || k % D.N_F) return;
   const unsigned pl = (unsigned)D.plane;
   const int ib = par(n_F(D, k - 1));
-  const R rho = ((const R*)D.rho[ib])[s.o];
-  const S* sp = (const S*)D.sF[ib];
+  const R rho = (gp<const R>(D.rho[ib]))[s.o];
+  GLOBAL const S* sp = gp<const S>(D.sF[ib]);
   const R dt = R(D.N_F * D.dt_base), c = R(1) / dt;
   R d[19], j[3] = {R(0), R(0), R(0)};
   d[0] = R(0);
@@ -1731,7 +1760,7 @@ __global__ __launch_bounds__(256) void k3_flow_collide(const Dom* __restrict__ d
   const R snu = R(1.0 / (3.0 * D.N_F * D.dt_base * D.nu + 0.5));
   R y[19];
   mrt19_op(x, R(D.s_q), R(D.s_e), R(D.s_eps), snu, y);
-  R* scr = (R*)D.scr;
+  GLOBAL R* scr = gp<R>(D.scr);
   if (forced) {
     R yf[19];
     mrt19_op(Fi, R(D.s_q), R(D.s_e), R(D.s_eps), snu, yf);
@@ -1750,9 +1779,9 @@ __global__ __launch_bounds__(256) void k3_flow_stream(const Dom* __restrict__ do
   Site3 s;
   if (!site3(D, (long long)blockIdx.x * 256 + threadIdx.x, s) || k % D.N_F) return;
   const unsigned pl = (unsigned)D.plane;
-  const R* rin = (const R*)D.rho[par(n_F(D, k - 1))];
-  const R* phis = (const R*)D.phi[par(n_phi(D, k))];
-  const R* scr = (const R*)D.scr;
+  GLOBAL const R* rin = gp<const R>(D.rho[par(n_F(D, k - 1))]);
+  GLOBAL const R* phis = gp<const R>(D.phi[par(n_phi(D, k))]);
+  GLOBAL const R* scr = gp<const R>(D.scr);
   const R dt = R(D.N_F * D.dt_base), c = R(1) / dt;
   const R ry = rin[s.o], fly = (R(1) - phis[s.o]) * R(0.5);
   R dn[19], drho = R(0), j[3] = {R(0), R(0), R(0)};
@@ -1776,12 +1805,12 @@ __global__ __launch_bounds__(256) void k3_flow_stream(const Dom* __restrict__ do
   }
   const int ob = par(n_F(D, k));
   const R rho = ry + drho, irho = rcp(rho);
-  ((R*)D.rho[ob])[s.o] = rho;
-  R* vel = (R*)D.vel[ob];
+  (gp<R>(D.rho[ob]))[s.o] = rho;
+  GLOBAL R* vel = gp<R>(D.vel[ob]);
   const R F[3] = {R(D.Fx), R(D.Fy), R(D.Fz)};
 #pragma unroll
   for (int a = 0; a < 3; ++a) vel[s.o + a * pl] = (c * j[a] + dt * F[a] * R(0.5)) * irho;
-  S* so = (S*)D.sF[ob];
+  GLOBAL S* so = gp<S>(D.sF[ob]);
 #pragma unroll
   for (int q = 1; q < 19; ++q) st(so, s.o + (q - 1) * pl, dn[q] - R(w19(q)) * drho);
 }
@@ -1798,32 +1827,32 @@ __global__ void k3_init(const Dom* __restrict__ doms, const double* __restrict__
   const double off = xi ? xi[(long long)s.y * D.nx + s.x] : 0.0;
   const double phi = tanh((D.z_front + off - s.z) / (1.4142135623730951 * D.W0));
   for (int b = 0; b < 2; ++b) {
-    ((R*)D.phi[b])[s.o] = R(phi);
-    for (int q = 0; q < 6; ++q) st((S*)D.sphi[b], s.o + q * pl, R(0));
+    (gp<R>(D.phi[b]))[s.o] = R(phi);
+    for (int q = 0; q < 6; ++q) st(gp<S>(D.sphi[b]), s.o + q * pl, R(0));
   }
   if (D.has_U) {
     for (int b = 0; b < 2; ++b) {
-      ((R*)D.U[b])[s.o] = R(0);   // U - U0
-      for (int a = 0; a < 3; ++a) st((S*)D.jU[b], s.o + a * pl, R(0));
+      (gp<R>(D.U[b]))[s.o] = R(0);   // U - U0
+      for (int a = 0; a < 3; ++a) st(gp<S>(D.jU[b]), s.o + a * pl, R(0));
     }
-    ((R*)D.PU)[s.o] = R(0);
+    (gp<R>(D.PU))[s.o] = R(0);
   }
   if (D.has_T) {
     const double dT0 = D.T_pulled ? D.T_grad * (s.z - D.z_front) : 0.0;   // T - T0
     const double jz = D.T_pulled ? (D.T0 + dT0) * D.V_pull * D.N_T * D.dt_base : 0.0;
     for (int b = 0; b < 2; ++b) {
-      ((R*)D.T[b])[s.o] = R(dT0);
-      st((S*)D.jT[b], s.o, R(0));
-      st((S*)D.jT[b], s.o + pl, R(0));
-      st((S*)D.jT[b], s.o + 2 * pl, R(jz));
+      (gp<R>(D.T[b]))[s.o] = R(dT0);
+      st(gp<S>(D.jT[b]), s.o, R(0));
+      st(gp<S>(D.jT[b]), s.o + pl, R(0));
+      st(gp<S>(D.jT[b]), s.o + 2 * pl, R(jz));
     }
-    ((R*)D.PT)[s.o] = R(0);
+    (gp<R>(D.PT))[s.o] = R(0);
   }
   if (D.has_F) {
     for (int b = 0; b < 2; ++b) {
-      ((R*)D.rho[b])[s.o] = R(1);
-      for (int q = 0; q < 18; ++q) st((S*)D.sF[b], s.o + q * pl, R(0));
-      for (int a = 0; a < 3; ++a) ((R*)D.vel[b])[s.o + a * pl] = R(0);
+      (gp<R>(D.rho[b]))[s.o] = R(1);
+      for (int q = 0; q < 18; ++q) st(gp<S>(D.sF[b]), s.o + q * pl, R(0));
+      for (int a = 0; a < 3; ++a) (gp<R>(D.vel[b]))[s.o + a * pl] = R(0);
     }
   }
 }
@@ -1836,23 +1865,23 @@ __global__ void k3_init(const Dom* __restrict__ doms, const double* __restrict__
 template <class R, class S>
 __device__ double read_plane3(const Dom& D, long long k, int code, unsigned o) {
   const unsigned pl = (unsigned)D.plane;
-  if (code == 0) return double(((const R*)D.phi[par(n_phi(D, k))])[o]);
-  if (code == 1) return double(((const R*)D.U[par(n_U(D, k))])[o]) + D.U0;
-  if (code == 2) return double(((const R*)D.T[par(n_T(D, k))])[o]) + D.T0;
-  if (code == 8) return double(((const R*)D.U[par(n_U(D, k))])[o]);
-  if (code == 9) return double(((const R*)D.T[par(n_T(D, k))])[o]);
-  if (code == 3) return double(((const R*)D.rho[par(n_F(D, k))])[o]);
-  if (code >= 4 && code <= 6) return double(((const R*)D.vel[par(n_F(D, k))])[o + (code - 4) * pl]);
-  if (code >= 20 && code <= 22) return double(ld((const S*)D.jU[par(n_jU(D, k))], o + (code - 20) * pl));
-  if (code >= 30 && code <= 32) return double(ld((const S*)D.jT[par(n_T(D, k))], o + (code - 30) * pl));
-  if (code == 90) return double(((const R*)D.PU)[o]);
-  if (code == 91) return double(((const R*)D.PT)[o]);
-  if (code >= 60 && code <= 65) return double(ld((const S*)D.sphi[par(n_phi(D, k))], o + (code - 60) * pl));
-  if (code >= 70 && code <= 87) return double(ld((const S*)D.sF[par(n_F(D, k))], o + (code - 70) * pl));
+  if (code == 0) return double((gp<const R>(D.phi[par(n_phi(D, k))]))[o]);
+  if (code == 1) return double((gp<const R>(D.U[par(n_U(D, k))]))[o]) + D.U0;
+  if (code == 2) return double((gp<const R>(D.T[par(n_T(D, k))]))[o]) + D.T0;
+  if (code == 8) return double((gp<const R>(D.U[par(n_U(D, k))]))[o]);
+  if (code == 9) return double((gp<const R>(D.T[par(n_T(D, k))]))[o]);
+  if (code == 3) return double((gp<const R>(D.rho[par(n_F(D, k))]))[o]);
+  if (code >= 4 && code <= 6) return double((gp<const R>(D.vel[par(n_F(D, k))]))[o + (code - 4) * pl]);
+  if (code >= 20 && code <= 22) return double(ld(gp<const S>(D.jU[par(n_jU(D, k))]), o + (code - 20) * pl));
+  if (code >= 30 && code <= 32) return double(ld(gp<const S>(D.jT[par(n_T(D, k))]), o + (code - 30) * pl));
+  if (code == 90) return double((gp<const R>(D.PU))[o]);
+  if (code == 91) return double((gp<const R>(D.PT))[o]);
+  if (code >= 60 && code <= 65) return double(ld(gp<const S>(D.sphi[par(n_phi(D, k))]), o + (code - 60) * pl));
+  if (code >= 70 && code <= 87) return double(ld(gp<const S>(D.sF[par(n_F(D, k))]), o + (code - 70) * pl));
   if (code >= 10 && code <= 16) {
     const int b = par(n_phi(D, k));
-    const R phi = ((const R*)D.phi[b])[o];
-    const S* sp = (const S*)D.sphi[b];
+    const R phi = (gp<const R>(D.phi[b]))[o];
+    GLOBAL const S* sp = gp<const S>(D.sphi[b]);
     if (code == 10) {
       R sum = R(0);
       for (int q = 0; q < 6; ++q) sum += ld(sp, o + q * pl);
@@ -1862,8 +1891,8 @@ __device__ double read_plane3(const Dom& D, long long k, int code, unsigned o) {
   }
   if (code >= 40 && code <= 58) {
     const int b = par(n_F(D, k));
-    const R rho = ((const R*)D.rho[b])[o];
-    const S* sp = (const S*)D.sF[b];
+    const R rho = (gp<const R>(D.rho[b]))[o];
+    GLOBAL const S* sp = gp<const S>(D.sF[b]);
     if (code == 40) {
       R sum = R(0);
       for (int q = 0; q < 18; ++q) sum += ld(sp, o + q * pl);
@@ -1904,19 +1933,19 @@ __global__ void k3_write(const Dom* __restrict__ doms, long long k, const int* _
   for (int c = 0; c < ncodes; ++c) {
     const int code = codes[c];
     const double v = src[c * n + i];
-    if (code == 0) ((R*)D.phi[par(n_phi(D, k))])[o] = R(v);
-    else if (code == 1) ((R*)D.U[par(n_U(D, k))])[o] = R(v - D.U0);
-    else if (code == 2) ((R*)D.T[par(n_T(D, k))])[o] = R(v - D.T0);
-    else if (code == 8) ((R*)D.U[par(n_U(D, k))])[o] = R(v);
-    else if (code == 9) ((R*)D.T[par(n_T(D, k))])[o] = R(v);
-    else if (code == 3) ((R*)D.rho[par(n_F(D, k))])[o] = R(v);
-    else if (code >= 4 && code <= 6) ((R*)D.vel[par(n_F(D, k))])[o + (code - 4) * pl] = R(v);
-    else if (code >= 20 && code <= 22) st((S*)D.jU[par(n_jU(D, k))], o + (code - 20) * pl, R(v));
-    else if (code >= 30 && code <= 32) st((S*)D.jT[par(n_T(D, k))], o + (code - 30) * pl, R(v));
-    else if (code == 90) ((R*)D.PU)[o] = R(v);
-    else if (code == 91) ((R*)D.PT)[o] = R(v);
-    else if (code >= 60 && code <= 65) st((S*)D.sphi[par(n_phi(D, k))], o + (code - 60) * pl, R(v));
-    else if (code >= 70 && code <= 87) st((S*)D.sF[par(n_F(D, k))], o + (code - 70) * pl, R(v));
+    if (code == 0) (gp<R>(D.phi[par(n_phi(D, k))]))[o] = R(v);
+    else if (code == 1) (gp<R>(D.U[par(n_U(D, k))]))[o] = R(v - D.U0);
+    else if (code == 2) (gp<R>(D.T[par(n_T(D, k))]))[o] = R(v - D.T0);
+    else if (code == 8) (gp<R>(D.U[par(n_U(D, k))]))[o] = R(v);
+    else if (code == 9) (gp<R>(D.T[par(n_T(D, k))]))[o] = R(v);
+    else if (code == 3) (gp<R>(D.rho[par(n_F(D, k))]))[o] = R(v);
+    else if (code >= 4 && code <= 6) (gp<R>(D.vel[par(n_F(D, k))]))[o + (code - 4) * pl] = R(v);
+    else if (code >= 20 && code <= 22) st(gp<S>(D.jU[par(n_jU(D, k))]), o + (code - 20) * pl, R(v));
+    else if (code >= 30 && code <= 32) st(gp<S>(D.jT[par(n_T(D, k))]), o + (code - 30) * pl, R(v));
+    else if (code == 90) (gp<R>(D.PU))[o] = R(v);
+    else if (code == 91) (gp<R>(D.PT))[o] = R(v);
+    else if (code >= 60 && code <= 65) st(gp<S>(D.sphi[par(n_phi(D, k))]), o + (code - 60) * pl, R(v));
+    else if (code >= 70 && code <= 87) st(gp<S>(D.sF[par(n_F(D, k))]), o + (code - 70) * pl, R(v));
     else if (code == 10) cphi = c;
     else if (code == 40) cflow = c;
   }
@@ -1927,8 +1956,8 @@ __global__ void k3_write(const Dom* __restrict__ doms, long long k, const int* _
       f[q] = R(src[(cphi + q) * n + i]);
       phi += f[q];
     }
-    ((R*)D.phi[b])[o] = phi;
-    for (int q = 1; q < 7; ++q) st((S*)D.sphi[b], o + (q - 1) * pl, f[q] - phi * R(0.125));
+    (gp<R>(D.phi[b]))[o] = phi;
+    for (int q = 1; q < 7; ++q) st(gp<S>(D.sphi[b]), o + (q - 1) * pl, f[q] - phi * R(0.125));
   }
   if (cflow >= 0) {
     const int b = par(n_F(D, k));
@@ -1937,8 +1966,8 @@ __global__ void k3_write(const Dom* __restrict__ doms, long long k, const int* _
       f[q] = R(src[(cflow + q) * n + i]);
       rho += f[q];
     }
-    ((R*)D.rho[b])[o] = rho;
-    for (int q = 1; q < 19; ++q) st((S*)D.sF[b], o + (q - 1) * pl, f[q] - R(w19(q)) * rho);
+    (gp<R>(D.rho[b]))[o] = rho;
+    for (int q = 1; q < 19; ++q) st(gp<S>(D.sF[b]), o + (q - 1) * pl, f[q] - R(w19(q)) * rho);
   }
 }
 
@@ -1950,21 +1979,21 @@ __global__ __launch_bounds__(256) void k3_diag(const Dom* __restrict__ doms, lon
   Site3 s;
   double a[5] = {0, 0, 0, 0, 0};
   if (site3(D, (long long)blockIdx.x * 256 + threadIdx.x, s)) {
-    const double p = double(((const R*)D.phi[par(n_phi(D, k))])[s.o]);
+    const double p = double((gp<const R>(D.phi[par(n_phi(D, k))]))[s.o]);
     a[0] = (1.0 + p) * 0.5;
     bool bad = !isfinite(p);
     if (D.has_U) {
-      const double u = double(((const R*)D.U[par(n_U(D, k))])[s.o]) + D.U0;
+      const double u = double((gp<const R>(D.U[par(n_U(D, k))]))[s.o]) + D.U0;
       a[1] = D.C_inf * ((1.0 + D.kc) - (1.0 - D.kc) * p) * (1.0 + (1.0 - D.kc) * u) * 0.5;
       bad |= !isfinite(u);
     }
     if (D.has_T) {
-      const double t = double(((const R*)D.T[par(n_T(D, k))])[s.o]) + D.T0;
+      const double t = double((gp<const R>(D.T[par(n_T(D, k))]))[s.o]) + D.T0;
       a[2] = t - D.rho_L * D.L_h * p / (2.0 * D.rcL);
       bad |= !isfinite(t);
     }
     if (D.has_F) {
-      const double r = double(((const R*)D.rho[par(n_F(D, k))])[s.o]);
+      const double r = double((gp<const R>(D.rho[par(n_F(D, k))]))[s.o]);
       a[3] = r;
       bad |= !isfinite(r);
     }
@@ -1998,7 +2027,7 @@ __global__ void k3_front(const Dom* __restrict__ doms, long long k, double* __re
   if (col < (long long)D.nx * D.ny) {
     has = true;
     const int x = (int)(col % D.nx), y = (int)(col / D.nx);
-    const R* phi = (const R*)D.phi[par(n_phi(D, k))];
+    GLOBAL const R* phi = gp<const R>(D.phi[par(n_phi(D, k))]);
     double prev = double(phi[(long long)y * D.px + x]);
     h = prev < 0 ? 0.0 : double(D.nz - 1);
     if (prev >= 0)
