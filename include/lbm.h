@@ -84,10 +84,12 @@ enum { LBM_STORE_F64 = 0, LBM_STORE_F32 = 1, LBM_STORE_F16 = 2, LBM_STORE_BF16 =
  * variant that sums increments and injects them after the field's next
  * transport update (the ablation of Section 4.4) */
 enum { LBM_COUPLE_INSTANT = 0, LBM_COUPLE_ACCUM = 1 };
-/* temperature field: transported with latent heat (Eq. 10-12, 38), or the
- * pulled profile of 3D directional solidification: advected at V_pull along
- * z, no latent heat, z walls held at the moving linear profile */
-enum { LBM_T_TRANSPORT = 0, LBM_T_PULLED = 1 };
+/* temperature field: transported with latent heat (Eq. 10-12, 38); the
+ * pulled profile of 3D directional solidification (advected at V_pull along
+ * z, no latent heat, z walls held at the moving linear profile); or the cold
+ * bottom of Section 4.4 (transported with latent heat, the low wall of the
+ * last axis held at T0; that axis must have walls) */
+enum { LBM_T_TRANSPORT = 0, LBM_T_PULLED = 1, LBM_T_DIRICHLET_LOW = 2 };
 
 /* Parameters of one domain (host memory, FP64, lattice units).  Field
  * names follow the paper's notation. */
@@ -110,10 +112,12 @@ typedef struct {
   double U0, T0;                        /* initial uniform U and T           */
   int32_t u0_liquid_only;               /* initial u = u_in (1 - phi)/2 x^  */
   int32_t coupling;                     /* LBM_COUPLE_*                      */
-  int32_t T_mode;                       /* LBM_T_TRANSPORT or LBM_T_PULLED   */
+  int32_t T_mode;                       /* LBM_T_TRANSPORT, _PULLED, _DIRICHLET_LOW */
   int32_t pad;
   double T_grad, V_pull, z_front;       /* pulled temperature (3D):
-                                           T0 + T_grad (z - z_front - V_pull t) */
+                                           T0 + T_grad (z - z_front - V_pull t);
+                                           z_front: mean height of the front
+                                           set by lbm_init_front */
 } lbm_params;
 
 /* Per-domain diagnostics (FP64 reductions on the device).  In 3D, tip[0]
@@ -158,12 +162,14 @@ lbm_status lbm_create(const lbm_params* p, int32_t n_domains, int32_t storage,
 lbm_status lbm_init_seeds(lbm_ctx* ctx, int32_t domain, int32_t n_seeds,
                           const double* centres, const double* radii);
 
-/* Initialise a 3D domain with a planar solid layer along z:
- * phi = tanh[(z_front + xi(x, y) - z)/(sqrt2 W0)] (a random form of the
- * Section 4.4 initial condition, Eq. 41), U = U0, T = T0 or the pulled
- * profile, flow at rest, populations at equilibrium.
- *   xi  host, nx * ny column offsets (x fastest), or NULL for a flat front.
- * Resets the step counter.  LBM_EINVAL for a 2D domain. */
+/* Initialise a domain with a planar solid layer along its last axis:
+ * phi = tanh[(z_front + xi - z)/(sqrt2 W0)] with z = y in 2D (Eq. 41 with
+ * xi = sin(10 pi x / L)) and z in 3D (a random form of Eq. 41), U = U0,
+ * T = T0 or the pulled profile, flow at rest (3D) or u0 as for seeds (2D),
+ * populations at equilibrium.
+ *   xi  host, column offsets: nx values in 2D, nx * ny (x fastest) in 3D,
+ *       or NULL for a flat front.
+ * Resets the step counter. */
 lbm_status lbm_init_front(lbm_ctx* ctx, int32_t domain, const double* xi);
 
 /* Advance every domain by n_base_steps base steps of Eq. (34): at base

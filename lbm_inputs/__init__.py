@@ -15,5 +15,6 @@ from .configs import (  # noqa: F401
     thermosolutal_flow_1024,
     ensemble_256,
     directional_3d,
+    directional_2d,
     reduced,
 )

@@ -32,7 +32,10 @@ Per-domain keys (all floats unless noted):
   coupling  "instant" (Eq. 39) | "accum" (delayed coarse-step injection)
   T_mode    "transport" | "pulled" (3D: T advected at V_pull along z, no
             latent heat, walls of the last axis held at the moving profile
-            T0 + T_grad (z - z_front - V_pull t))
+            T0 + T_grad (z - z_front - V_pull t)) | "dirichlet_low" (latent
+            heat kept, low wall of the last axis held at T0)
+  perturb   per-column front offset xi (nx values in 2D, ny x nx in 3D):
+            phi = tanh[(z_front + xi - z)/(sqrt2 W0)] along the last axis
 """
 
 from __future__ import annotations
@@ -229,12 +232,42 @@ def directional_3d(nx: int = 256, ny: int = 256, nz: int = 512) -> dict:
                 dtype="f32", storage="bf16")
 
 
+def directional_2d(Le: int = 100, coupling: str = "instant", nx: int = 1000, ny: int = 1000) -> dict:
+    """2D directional saline-water solidification of Section 4.4.
+
+    Table 1 lattice set, W0 = 2, tau0 = 150, D_L = alpha_L / Le with
+    N_U = Le and N_phi = N_T = 1 (Eq. 42), D_S = 1e-2 D_L, U0 = 0.  Eq. (41)
+    front: phi = tanh[(10 + sin(10 pi x / L) - y)/(sqrt2 W0)].  T starts at
+    T_b = -20 and the bottom wall is held there; T_m = 0; no flow.  Periodic
+    in x (the perturbation has five whole wavelengths), zero-flux elsewhere.
+    """
+    t = TABLE1
+    D_L = t["alpha_L"] / Le
+    d = _base_domain()
+    d.update(
+        nx=nx, ny=ny, has_U=True, has_T=True, N_phi=1, N_U=int(Le), N_T=1, dt_base=1.0,
+        W0=t["W0"], tau0=t["tau0"], eps_s=t["eps_s"], lam=t["lam"], Mc=t["Mc"], k=t["k"],
+        D_L=D_L, D_S=1.0e-2 * D_L, C_inf=t["C_inf"],
+        kappa_S=t["kappa_S"], kappa_L=t["kappa_L"],
+        rhoCp_S=t["rho"] * t["Cp_S"], rhoCp_L=t["rho"] * t["Cp_L"],
+        rho_L=t["rho"], L_h=t["L_h"], Cp_L=t["Cp_L"], T_m=0.0, m_L=t["m_L"],
+        U0=0.0, T0=-20.0, bc=("periodic", "wall", "wall"),
+        T_mode="dirichlet_low", z_front=10.0, coupling=coupling,
+    )
+    x = np.arange(nx, dtype=np.float64)
+    d["perturb"] = np.sin(10.0 * math.pi * x / nx)
+    d["Le"] = Le
+    return dict(name=f"directional_2d_Le{Le}_{coupling}", domains=[d], steps=30000, steps_timed=1000,
+                dtype="f64", storage="f64")
+
+
 WORKLOADS = {
     "thermal_128": thermal_128,
     "solutal_512": solutal_512,
     "thermosolutal_flow_1024": thermosolutal_flow_1024,
     "ensemble_256": ensemble_256,
     "directional_3d": directional_3d,
+    "directional_2d": directional_2d,
 }
 
 
@@ -259,7 +292,8 @@ def reduced(wl: dict, nx: int, ny: int, nz: int | None = None, steps: int | None
             seeds.append((cx, cy) + tuple(s[2:]))
         d["seeds"] = seeds
         if "perturb" in d:
-            d["perturb"] = d["perturb"][:ny, :nx]
+            xi = np.asarray(d["perturb"])
+            d["perturb"] = xi[:ny, :nx] if xi.ndim == 2 else xi[:nx]
         d["nx"], d["ny"] = nx, ny
         if nz is not None:
             d["nz"] = nz

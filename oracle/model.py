@@ -38,7 +38,12 @@ notes of the HIP library):
     by its lattice with the pulling velocity V z^ in its equilibrium, receives
     no latent heat, and the bottom and top walls hold the moving linear
     profile T_L + G (z - z_front - V t) by anti-bounce-back; the linear
-    profile is then an exact solution of the T lattice.
+    profile is then an exact solution of the T lattice;
+  * cold bottom (2D directional case of Section 4.4, T_mode "dirichlet_low"):
+    T keeps its latent-heat transfer and the low wall of the last axis is
+    held at T0 by the same anti-bounce-back; the other walls stay zero-flux;
+  * planar fronts (Eq. 41 and its 3D random form): phi = tanh[(z_front +
+    xi - z)/(sqrt2 W0)] along the last axis with a per-column offset xi.
 """
 
 from __future__ import annotations
@@ -161,9 +166,11 @@ class Domain:
         d = self.d
         X = self.coords()
         s2w = math.sqrt(2.0) * d["W0"]
-        if self.dim == 3 and "perturb" in d:
+        if "perturb" in d:
             xi = np.asarray(d["perturb"], dtype=np.float64)
-            return np.tanh((d["z_front"] + xi[None, :, :] - X[2]) / s2w)
+            if self.dim == 3:
+                return np.tanh((d["z_front"] + xi[None, :, :] - X[2]) / s2w)
+            return np.tanh((d["z_front"] + xi[None, :] - X[1]) / s2w)
         phi = np.full(self.shape, -1.0)
         for s in d["seeds"]:
             c = s[: self.dim]
@@ -216,8 +223,11 @@ class Domain:
         return u
 
     def pulled_T(self, z, t):
-        """Moving linear profile T_L + G (z - z_front - V t), T_L = T0."""
+        """Moving linear profile T_L + G (z - z_front - V t), T_L = T0 (the
+        cold bottom is the case G = V = 0)."""
         d = self.d
+        if d.get("T_mode") == "dirichlet_low":
+            return d["T0"] + 0.0 * z
         return d["T0"] + d["T_grad"] * (z - d["z_front"] - d["V_pull"] * t)
 
     def flow_eq(self, rho, u, dt):
@@ -320,16 +330,18 @@ class Domain:
         w = _wq(ls, nd)
         post = mrt_collide(ls, f, feq, scalar_relaxation(ls, tau)) + dt * w * Qtr[None]
         f_new = pull(post, ls, self.bc)                                   # Eq. (25)
-        if which == "T" and d.get("T_mode") == "pulled":
+        if which == "T" and d.get("T_mode") in ("pulled", "dirichlet_low"):
             # anti-bounce-back on the walls of the last axis: populations whose
             # upstream node lies beyond the wall z_w = -1/2 or nz - 1/2 become
-            # -f^+_ibar(y) + 2 w_i T(z_w) at the middle of the T step
+            # -f^+_ibar(y) + 2 w_i T(z_w) at the middle of the T step (the
+            # cold bottom holds T0: only the low wall, G = V = 0)
             ax = nd - 1
             n = self.shape[0]
             t_mid = (self.k - 0.5 * d["N_T"]) * d["dt_base"]
+            low_only = d.get("T_mode") == "dirichlet_low"
             for i in range(ls.Q):
                 ez = int(ls.e[i, ax])
-                if ez == 0:
+                if ez == 0 or (low_only and ez < 0):
                     continue
                 zw = -0.5 if ez > 0 else n - 0.5
                 src = np.arange(n) - ez

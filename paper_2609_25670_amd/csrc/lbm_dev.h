@@ -30,6 +30,7 @@ struct Dom {
   int has_U, has_T, has_F, accum;
   int T_var;                    // thermal properties vary with phi
   int T_pulled;                 // 3D pulled temperature (no latent heat, moving walls)
+  int T_dirlow;                 // low wall of the last axis held at T0 (latent heat kept)
   int dim;
   int tile0;                    // first tile slot of this domain (partials)
   int ntiles;                   // tiles of this domain

@@ -651,7 +651,10 @@ __global__ __launch_bounds__(NTHR) void k_scalar(const Dom* __restrict__ doms, c
 #pragma unroll
     for (int q = 1; q < 5; ++q) {
       const int ex = EX5(q), ey = EY5(q);
-      if (bb[q]) {
+      if (bb[q] && FIELD == 1 && D.T_dirlow && q == 2) {
+        // anti-bounce-back to T0 at the wall y = -1/2 (the plane holds T - T0)
+        dq[q] = -(R(2) * cy + dPo) * R(1.0 / 6.0) + R(0.5) * (R(ex) * Kxo + R(ey) * Kyo);
+      } else if (bb[q]) {
         dq[q] = dPo * R(1.0 / 6.0) - R(0.5) * (R(ex) * Kxo + R(ey) * Kyo);
       } else {
         const int si = ci - ey * CW - ex;
@@ -892,7 +895,7 @@ __global__ __launch_bounds__(NTHR) void k_flow(const Dom* __restrict__ doms, con
 // orders below the initial value, and adding them to U0 or T0 in FP32 would
 // round them away (a systematic solute drift).
 template <class R, class S>
-__global__ void k_init(const Dom* __restrict__ doms, int dom) {
+__global__ void k_init(const Dom* __restrict__ doms, int dom, const double* __restrict__ xi) {
   const Dom& D = doms[dom];
   const long long n = (long long)D.nx * D.ny;
   const long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -901,10 +904,14 @@ __global__ void k_init(const Dom* __restrict__ doms, int dom) {
   const long long o = (long long)y * D.px + x, pl = D.plane;
   const double s2w = 1.4142135623730951 * D.W0;
   double phi = -1.0;
-  for (int s = 0; s < D.nseeds; ++s) {
-    const double dx = x - D.seed[s][0], dy = y - D.seed[s][1];
-    const double v = tanh((D.seed[s][2] - sqrt(dx * dx + dy * dy)) / s2w);
-    phi = v > phi ? v : phi;
+  if (xi) {   // planar front along y (Eq. 41)
+    phi = tanh((D.z_front + xi[x] - y) / s2w);
+  } else {
+    for (int s = 0; s < D.nseeds; ++s) {
+      const double dx = x - D.seed[s][0], dy = y - D.seed[s][1];
+      const double v = tanh((D.seed[s][2] - sqrt(dx * dx + dy * dy)) / s2w);
+      phi = v > phi ? v : phi;
+    }
   }
   const R ph = R(phi);
   (gp<R>(D.phi[0]))[o] = ph;
@@ -1622,7 +1629,7 @@ __global__ __launch_bounds__(256) void k3_scalar_stream(const Dom* __restrict__ 
   if (ok) {
     const R cy = cin[s.o], dPy = scr[s.o];
     const R Ky[3] = {scr[s.o + pl], scr[s.o + 2 * pl], scr[s.o + 3 * pl]};
-    const bool dir = FIELD == 1 && D.T_pulled;
+    const bool dir = FIELD == 1 && (D.T_pulled || D.T_dirlow);
     const R tmid = R((double(k + D.koff) - 0.5 * N) * D.dt_base);
     R dq[7];
     dq[0] = dPy * R(0.25);
@@ -1636,9 +1643,9 @@ __global__ __launch_bounds__(256) void k3_scalar_stream(const Dom* __restrict__ 
         dq[q] = (cin[o] - cy + scr[o]) * R(0.125) + R(0.5) * Ke;
       } else {
         const R Ke = R(ex) * Ky[0] + R(ey) * Ky[1] + R(ez) * Ky[2];
-        if (dir && ez != 0) {
+        if (dir && (ez > 0 || (ez < 0 && D.T_pulled))) {
           const R zw = ez > 0 ? R(-0.5) : R(D.nz - 0.5);
-          const R Tw = R(D.T_grad) * (zw - R(D.z_front) - R(D.V_pull) * tmid);   // T_w - T0
+          const R Tw = D.T_pulled ? R(D.T_grad) * (zw - R(D.z_front) - R(D.V_pull) * tmid) : R(0);   // T_w - T0
           dq[q] = R(0.125) * (R(2) * Tw - R(2) * cy - dPy) + R(0.5) * Ke;
         } else {
           dq[q] = dPy * R(0.125) - R(0.5) * Ke;
@@ -2165,8 +2172,8 @@ struct Launch {
   static void tips(int ndom, hipStream_t st, const Dom* d, long long k, DiagOut* o) {
     k_tips<R><<<dim3(ndom, MAX_SEEDS, 4), 256, 0, st>>>(d, k, o);
   }
-  static void init(hipStream_t st, const Dom* d, int dom, long long n) {
-    k_init<R, S><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(d, dom);
+  static void init(hipStream_t st, const Dom* d, int dom, long long n, const double* xi) {
+    k_init<R, S><<<(unsigned)((n + 255) / 256), 256, 0, st>>>(d, dom, xi);
   }
   static void read(hipStream_t st, const Dom* d, int dom, long long k, const int* codes, int nc, int f64,
                    void* out, long long n) {

@@ -33,7 +33,7 @@ struct Launch {
   static void flow(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k);
   static void diag_tiles(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k, Partial* p);
   static void tips(int ndom, hipStream_t st, const Dom* d, long long k, DiagOut* o);
-  static void init(hipStream_t st, const Dom* d, int dom, long long n);
+  static void init(hipStream_t st, const Dom* d, int dom, long long n, const double* xi);
   static void read(hipStream_t st, const Dom* d, int dom, long long k, const int* codes, int nc, int f64,
                    void* out, long long n);
   static void write(hipStream_t st, const Dom* d, int dom, long long k, const int* codes, int nc,
@@ -87,7 +87,7 @@ struct Ops {
   void (*flow)(int, dim3, hipStream_t, const Dom*, const int4*, long long);
   void (*diag_tiles)(int, dim3, hipStream_t, const Dom*, const int4*, long long, Partial*);
   void (*tips)(int, hipStream_t, const Dom*, long long, DiagOut*);
-  void (*init)(hipStream_t, const Dom*, int, long long);
+  void (*init)(hipStream_t, const Dom*, int, long long, const double*);
   void (*read)(hipStream_t, const Dom*, int, long long, const int*, int, int, void*, long long);
   void (*write)(hipStream_t, const Dom*, int, long long, const int*, int, const double*, long long);
 };
@@ -232,7 +232,10 @@ std::string validate(const lbm_params& p, int i) {
     if (p.bc[2] != LBM_BC_PERIODIC && p.bc[2] != LBM_BC_WALL) return bad("bad z boundary");
     if (p.has_flow && p.u0_liquid_only) return bad("3D flow starts at rest (u0_liquid_only is 2D only)");
   }
-  if (p.T_mode != LBM_T_TRANSPORT && p.T_mode != LBM_T_PULLED) return bad("bad T_mode");
+  if (p.T_mode != LBM_T_TRANSPORT && p.T_mode != LBM_T_PULLED && p.T_mode != LBM_T_DIRICHLET_LOW)
+    return bad("bad T_mode");
+  if (p.T_mode == LBM_T_DIRICHLET_LOW && p.bc[p.dim - 1] != LBM_BC_WALL)
+    return bad("the cold bottom needs walls on the last axis");
   if (p.T_mode == LBM_T_PULLED && (p.dim != 3 || p.bc[2] != LBM_BC_WALL))
     return bad("the pulled temperature needs a 3D domain with z walls");
   if (p.T_mode == LBM_T_PULLED && (p.kappa_S != p.kappa_L || p.rhoCp_S != p.rhoCp_L))
@@ -465,6 +468,7 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
       D.fbc[a] = q.flow_bc[a];
     }
     D.T_pulled = q.T_mode == LBM_T_PULLED;
+    D.T_dirlow = q.T_mode == LBM_T_DIRICHLET_LOW;
     D.T_grad = q.T_grad;
     D.V_pull = q.V_pull;
     D.z_front = q.z_front;
@@ -687,7 +691,7 @@ lbm_status lbm_init_seeds(lbm_ctx* c, int32_t dom, int32_t n_seeds, const double
   }
   lbm_status st = upload_doms(c);
   if (st != LBM_OK) return st;
-  c->ops.init(c->stream, c->d_dom, dom, (long long)D.nx * D.ny);
+  c->ops.init(c->stream, c->d_dom, dom, (long long)D.nx * D.ny, nullptr);
   HIPCHK(c, hipGetLastError());
   c->initialised[dom] = true;
   c->k = 0;
@@ -697,17 +701,24 @@ lbm_status lbm_init_seeds(lbm_ctx* c, int32_t dom, int32_t n_seeds, const double
 lbm_status lbm_init_front(lbm_ctx* c, int32_t dom, const double* xi) {
   if (!c) return LBM_EINVAL;
   if (dom < 0 || dom >= c->ndom) return fail(c, LBM_EINVAL, "bad domain index");
-  if (c->dim != 3) return fail(c, LBM_EINVAL, "lbm_init_front initialises 3D domains");
   HIPCHK(c, hipSetDevice(c->device));
-  const Dom& D = c->H[dom];
+  Dom& D = c->H[dom];
   const double* dxi = nullptr;
+  const size_t ncol = c->dim == 3 ? (size_t)D.nx * D.ny : (size_t)D.nx;
   if (xi) {
-    HIPCHK(c, hipMemcpyAsync(c->d_stage, xi, sizeof(double) * D.nx * D.ny, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipMemcpyAsync(c->d_stage, xi, sizeof(double) * ncol, hipMemcpyHostToDevice, c->stream));
     dxi = c->d_stage;
   }
-  c->ops3.init(D, c->stream, c->d_dom, dxi);
-  c->ops3.set_koff(c->stream, c->d_dom, 0);
-  c->koff = 0;
+  if (c->dim == 3) {
+    c->ops3.init(D, c->stream, c->d_dom, dxi);
+    c->ops3.set_koff(c->stream, c->d_dom, 0);
+    c->koff = 0;
+  } else {
+    D.nseeds = 0;   // no seed tips for a front
+    lbm_status st = upload_doms(c);
+    if (st != LBM_OK) return st;
+    c->ops.init(c->stream, c->d_dom, dom, (long long)D.nx * D.ny, dxi);
+  }
   HIPCHK(c, hipGetLastError());
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->initialised[dom] = true;

@@ -24,6 +24,7 @@ STATUS = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVICE", -4
 BC = {"periodic": 0, "wall": 1, "inlet_outflow": 2}
 STORAGE = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
 COUPLING = {"instant": 0, "accum": 1}
+T_MODE = {"transport": 0, "pulled": 1, "dirichlet_low": 2}
 
 # names, plane counts per field bit (2D)
 FIELD_BITS = [("phi", F_PHI, 1), ("U", F_U, 1), ("T", F_T, 1), ("rho", F_RHO, 1), ("vel", F_VEL, 2),
@@ -135,7 +136,7 @@ def to_params(d: dict) -> Params:
         p.flow_bc[a] = BC[d["flow_bc"][a]]
     p.u0_liquid_only = int(bool(d.get("u0_liquid_only", False)))
     p.coupling = COUPLING[d.get("coupling", "instant")]
-    p.T_mode = 1 if d.get("T_mode", "transport") == "pulled" else 0
+    p.T_mode = T_MODE[d.get("T_mode", "transport")]
     p.T_grad = float(d.get("T_grad", 0.0))
     p.V_pull = float(d.get("V_pull", 0.0))
     p.z_front = float(d.get("z_front", 0.0))
@@ -188,11 +189,12 @@ class Simulation:
     # ----------------------------------------------------------------- calls
     def init(self):
         for i, d in enumerate(self.domains):
-            if d["dim"] == 3:
+            if d["dim"] == 3 or "perturb" in d:
                 xi = d.get("perturb")
                 buf = None
                 if xi is not None:
-                    a = np.ascontiguousarray(np.asarray(xi, dtype=np.float64)[: d["ny"], : d["nx"]])
+                    xi = np.asarray(xi, dtype=np.float64)
+                    a = np.ascontiguousarray(xi[: d["ny"], : d["nx"]] if d["dim"] == 3 else xi[: d["nx"]])
                     buf = a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
                     self._xi = a
                 _check(self.lib, self.ctx, self.lib.lbm_init_front(self.ctx, i, buf))

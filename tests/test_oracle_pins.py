@@ -689,3 +689,44 @@ def test_anisotropic_streaming_needs_a_relaxation_margin():
 
     assert run(100.0) <= 1.0 + 1e-6
     assert run(1000.0) > 1.05
+
+
+# --------------------------------------------------------------------- cold bottom (Section 4.4)
+def test_cold_bottom_follows_the_erf_solution():
+    """T held at T_b on the low wall y = -1/2 by anti-bounce-back, zero flux
+    elsewhere, uniform T_i at t = 0 and no interface: the half-space
+    solution T_b + (T_i - T_b) erf((y + 1/2) / (2 sqrt(alpha t))).  A wall at
+    y = 0 instead of -1/2, or no Dirichlet wall at all, misses by far."""
+    from scipy.special import erf
+
+    alpha, n_steps, Tb = 0.1, 250, -1.0
+    d = _dom(nx=3, ny=80, has_T=True, N_T=1, kappa_S=alpha, kappa_L=alpha, rhoCp_S=1.0, rhoCp_L=1.0,
+             T0=Tb, bc=("periodic", "wall", "wall"), T_mode="dirichlet_low", L_h=1.0, Cp_L=1.0)
+    dom = oracle.Domain(d)
+    dom.T = np.zeros(dom.shape)
+    dom.f_T = dom.scalar_eq(dom.T, 1.0)
+    for _ in range(n_steps):
+        dom.k += 1
+        dom.scalar_step("T")
+    y = np.arange(80, dtype=float)
+    s = 2 * math.sqrt(alpha * n_steps)
+    ref = Tb - Tb * erf((y + 0.5) / s)
+    err = np.max(np.abs(dom.T[:, 1] - ref))
+    assert err < 1e-3, err
+    assert np.max(np.abs(Tb - Tb * erf(y / s) - ref)) > 20 * err
+
+
+def test_eq41_front_initial_condition():
+    """Eq. (41): phi(x, 0) = tanh[(10 + sin(10 pi x / L) - y)/(sqrt2 W0)],
+    mean height 10, amplitude 1, wavelength L/5; T = T_b = -20, U = 0."""
+    wl = L.directional_2d(Le=10, nx=100, ny=40)
+    d = wl["domains"][0]
+    dom = oracle.Domain(d)
+    X, Y = np.meshgrid(np.arange(100.0), np.arange(40.0))
+    ref = np.tanh((10 + np.sin(10 * math.pi * X / 100) - Y) / (math.sqrt(2) * d["W0"]))
+    assert np.allclose(dom.phi, ref, atol=1e-15)
+    assert np.all(dom.T == -20.0) and np.all(dom.U == 0.0)
+    # the liquid concentration relaxation time is the printed 0.578 for every Le (Eq. 42)
+    for Le in (1, 10, 100, 1000):
+        dd = L.directional_2d(Le=Le, nx=8, ny=8)["domains"][0]
+        assert abs(P.tau_U(dd, -1.0) - 0.578) < 1e-12
