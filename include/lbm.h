@@ -196,8 +196,17 @@ lbm_status lbm_write_fields(lbm_ctx* ctx, int32_t domain, uint32_t mask,
                             int32_t src_is_device, const void* src);
 
 /* Tuning: rows per tile of the stencil kernels (4, 8, 16 or 32; 0 = autotune)
- * and whether whole cycles are replayed from a HIP graph. */
-lbm_status lbm_configure(lbm_ctx* ctx, int32_t tile_rows, int32_t use_graph);
+ * and flags:
+ *   LBM_CFG_GRAPH           replay whole multirate cycles from a HIP graph
+ *   LBM_CFG_FUSE_TRANSFER   2D: run the transfer of Eq. (36)-(39) inside the
+ *                           phase kernel, which then recomputes a halo of
+ *                           three sites (domains of at least 8 x 8; results
+ *                           bitwise identical to the separate kernels; slower
+ *                           on MI355X at every size measured, so off by default)
+ * Default after lbm_create: autotune, LBM_CFG_GRAPH.  Unknown flags:
+ * LBM_EINVAL. */
+enum { LBM_CFG_GRAPH = 1, LBM_CFG_FUSE_TRANSFER = 2 };
+lbm_status lbm_configure(lbm_ctx* ctx, int32_t tile_rows, int32_t flags);
 
 /* Average device time, in milliseconds, of one launch of each kernel kind
  * over every domain, measured with HIP events around `reps` back-to-back

@@ -16,5 +16,7 @@ from .configs import (  # noqa: F401
     ensemble_256,
     directional_3d,
     directional_2d,
+    thermal_forced_512,
+    solutal_forced_1000,
     reduced,
 )

@@ -261,6 +261,52 @@ def directional_2d(Le: int = 100, coupling: str = "instant", nx: int = 1000, ny:
                 dtype="f64", storage="f64")
 
 
+def thermal_forced_512(N_T: int = 15) -> dict:
+    """Section 4.1 thermal dendrite under forced convection, 512 x 512.
+
+    W0 = 2.5, tau0 = 125 (dt_phi = 1), alpha = 0.2, nu = 4.62, L_h = 1,
+    eps_s = 0.05, lambda = 0.8839 / 0.1385, theta0 = -0.55, M_c = 0;
+    seed R0 = 10 at the centre; u_in = W0 / tau0 from the left, outflow on the
+    right, periodic top and bottom (flow), zero-flux scalars.  dt_base = 1/15
+    with N_phi = 15, N_F = 1 (tau_F = 1.424) and N_T in {15, 30, 45} (the
+    update-factor study of Fig. 4c).
+    """
+    d = _base_domain()
+    W0, tau0 = 2.5, 125.0
+    d.update(
+        nx=512, ny=512, has_T=True, has_flow=True, N_phi=15, N_T=int(N_T), N_F=1, dt_base=1.0 / 15.0,
+        W0=W0, tau0=tau0, eps_s=0.05, lam=0.8839 / 0.1385, Mc=0.0, k=0.15,
+        kappa_S=0.2, kappa_L=0.2, rhoCp_S=1.0, rhoCp_L=1.0, rho_L=1.0, L_h=1.0, Cp_L=1.0,
+        T_m=0.0, m_L=0.0, T0=-0.55, nu=4.62, u_in=W0 / tau0, u0_liquid_only=True,
+        bc=("wall", "wall", "wall"), flow_bc=("inlet_outflow", "periodic", "periodic"),
+        seeds=[(255.5, 255.5, 10.0)],
+    )
+    return dict(name=f"thermal_forced_512_NT{N_T}", domains=[d], steps=120000, steps_timed=15000,
+                dtype="f32", storage="f32")
+
+
+def solutal_forced_1000(N_U: int = 15) -> dict:
+    """Section 4.2 solutal dendrite under forced convection, 1000 x 1000.
+
+    W0 = 2.5, tau0 = 50 (dt_phi = 1), eps_s = 0.02, lambda = 0.8839 / 0.2762,
+    M_c = 1, k = 0.15, U0 = -0.55, D_L = 0.25, D_S = 1e-2 D_L, u_in = W0/tau0;
+    the viscosity is not given for this case, so the Section 4.1 value
+    nu = 4.62 (tau_F = 1.424 at dt_F = 1/15) is used.  dt_base = 1/15 with
+    N_phi = 15, N_F = 1 and N_U in {15, 30, 45} (Fig. 7c).
+    """
+    d = _base_domain()
+    W0, tau0 = 2.5, 50.0
+    d.update(
+        nx=1000, ny=1000, has_U=True, has_flow=True, N_phi=15, N_U=int(N_U), N_F=1, dt_base=1.0 / 15.0,
+        W0=W0, tau0=tau0, eps_s=0.02, lam=0.8839 / 0.2762, Mc=1.0, k=0.15,
+        D_L=0.25, D_S=2.5e-3, U0=-0.55, nu=4.62, u_in=W0 / tau0, u0_liquid_only=True,
+        bc=("wall", "wall", "wall"), flow_bc=("inlet_outflow", "periodic", "periodic"),
+        seeds=[(499.5, 499.5, 10.0)],
+    )
+    return dict(name=f"solutal_forced_1000_NU{N_U}", domains=[d], steps=450000, steps_timed=15000,
+                dtype="f32", storage="f32")
+
+
 WORKLOADS = {
     "thermal_128": thermal_128,
     "solutal_512": solutal_512,
@@ -268,6 +314,8 @@ WORKLOADS = {
     "ensemble_256": ensemble_256,
     "directional_3d": directional_3d,
     "directional_2d": directional_2d,
+    "thermal_forced_512": thermal_forced_512,
+    "solutal_forced_1000": solutal_forced_1000,
 }
 
 

@@ -88,7 +88,14 @@ __host__ __device__ inline long long n_U(const Dom& d, long long k) {
   return (d.accum ? 0 : k / d.N_phi) + k / d.N_U;
 }
 __host__ __device__ inline long long n_jU(const Dom& d, long long k) { return k / d.N_U; }
-__host__ __device__ inline long long n_T(const Dom& d, long long k) { return k / d.N_T; }
+// T is written, like U, by the transfer of every phase step (latent heat,
+// instantaneous coupling) and by its own transport; its first moment only
+// by the transport
+__host__ __device__ inline long long n_Ttr(const Dom& d, long long k) {
+  return (d.has_T && !d.accum && !d.T_pulled) ? k / d.N_phi : 0;
+}
+__host__ __device__ inline long long n_T(const Dom& d, long long k) { return n_Ttr(d, k) + k / d.N_T; }
+__host__ __device__ inline long long n_jT(const Dom& d, long long k) { return k / d.N_T; }
 __host__ __device__ inline long long n_F(const Dom& d, long long k) { return k / d.N_F; }
 
 }  // namespace lbm

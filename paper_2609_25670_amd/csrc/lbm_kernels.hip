@@ -385,7 +385,8 @@ __global__ __launch_bounds__(NTHR) void k_transfer(const Dom* __restrict__ doms,
   const long long nU = (D.accum ? 0 : (k - 1) / D.N_phi) + (k - 1) / D.N_U;
   GLOBAL const R* __restrict__ Uin = D.has_U ? gp<const R>(D.U[par(nU)]) : nullptr;
   GLOBAL R* __restrict__ Uout = D.has_U ? gp<R>(D.U[par(nU + 1)]) : nullptr;
-  GLOBAL R* __restrict__ Tcur = D.has_T ? gp<R>(D.T[par(n_T(D, k - 1))]) : nullptr;
+  GLOBAL const R* __restrict__ Tin = D.has_T ? gp<const R>(D.T[par(n_T(D, k - 1))]) : nullptr;
+  GLOBAL R* __restrict__ Tout = D.has_T ? gp<R>(D.T[par(n_T(D, k - 1) + 1)]) : nullptr;
   GLOBAL R* __restrict__ PU = gp<R>(D.PU);
   GLOBAL R* __restrict__ PT = gp<R>(D.PT);
   const R omk = R(1.0 - D.kc), opk = R(1.0 + D.kc);
@@ -410,7 +411,7 @@ __global__ __launch_bounds__(NTHR) void k_transfer(const Dom* __restrict__ doms,
       if (D.accum)
         PT[o] = PT[o] + dT;
       else
-        Tcur[o] = Tcur[o] + dT;
+        Tout[o] = Tin[o] + dT;
     }
     return;
   }
@@ -444,7 +445,7 @@ __global__ __launch_bounds__(NTHR) void k_transfer(const Dom* __restrict__ doms,
     const unsigned o = ghost(ry, ny, bcy) * px + ghost(rx, nx, bcx);
     pold[r] = phi_old[o];
     Us[r] = Uin[o];
-    if (r < RPT && D.has_T) Tv[r] = D.accum ? PT[o] : Tcur[o];
+    if (r < RPT && D.has_T) Tv[r] = D.accum ? PT[o] : Tin[o];
   }
   load_box2<R, BW, BH>(sphi, phi_new, px, x0, y0, nx, ny, bcx, bcy, tx, ty);
   __syncthreads();
@@ -493,13 +494,278 @@ __global__ __launch_bounds__(NTHR) void k_transfer(const Dom* __restrict__ doms,
       if (D.accum)
         PT[o] = Tv[r] + dT;
       else
-        Tcur[o] = Tv[r] + dT;
+        Tout[o] = Tv[r] + dT;
     }
   }
   if (part) {
     // block max of |dU| (wavefront reduction, then across the 4 wavefronts)
     for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_down(amax, off, 64));
     if (tx == 0) red[ty] = amax;
+    __syncthreads();
+    if (tid == 0) {
+      R m = red[0];
+      for (int wv = 1; wv < NTHR / 64; ++wv) m = fmax(m, red[wv]);
+      part[t.w].S_phi = double(m);
+      if (!D.accum) part[t.w].J_U = double(m);
+    }
+  }
+}
+
+// =================================================================== fused phase + transfer
+// One phase update and its transfer (Eq. 26, then Eq. 36-39) in a single
+// pass over a 64 x TY tile.  The transfer at a site needs phi^{q+1} two
+// sites away (the anti-trapping current J one site away, its normal from
+// the gradient of phi^{q+1}), so the block streams phi^{q+1} on the tile
+// plus a ring of two, which needs the collisions on the tile plus a ring of
+// three and phi^q on the tile plus four.  The rings are recomputed per
+// block: phi^{q+1} never leaves LDS before the transfer, and the transfer
+// has no launch of its own.  Arithmetic per site is that of k_phase and
+// k_transfer, in the same order, so the results are bitwise identical.
+//
+// Region coordinates: a cell (lx, ly) of a region of ring r maps to the raw
+// position (x0 - r + lx, y0 - r + ly).  On periodic axes that wraps; on
+// wall axes, raw positions beyond the wall take the values of the clamped
+// interior node (the even mirror about the half-way wall that the separate
+// kernels' stencils use), and collisions there are not needed (streaming
+// bounces back from the node itself).
+template <class R, class S, int TY>
+__global__ __launch_bounds__(NTHR) void k_phase_tr(const Dom* __restrict__ doms, const int4* __restrict__ tiles,
+                                                    long long k, Partial* __restrict__ part) {
+  constexpr int W4 = TX + 8, H4 = TY + 8;   // phi^q box
+  constexpr int W3 = TX + 6, H3 = TY + 6;   // collisions
+  constexpr int W2 = TX + 4, H2 = TY + 4;   // streaming, phi^{q+1}
+  constexpr int W1 = TX + 2, H1 = TY + 2;   // J
+  constexpr int N4 = W4 * H4, N3 = W3 * H3, N2 = W2 * H2, N1 = W1 * H1;
+  constexpr int C3 = (N3 + NTHR - 1) / NTHR;   // collision cells per thread
+  __shared__ R sq[N4];
+  __shared__ R cP[N3], cKx[N3], cKy[N3], cA[N3];
+  __shared__ R sn[N2];
+  __shared__ R sJx[N1], sJy[N1];
+  __shared__ R red[NTHR / 64];
+
+  const int4 t = tiles[blockIdx.x];
+  if (t.x < 0) return;
+  const Dom& D = doms[t.x];
+  if (k % D.N_phi) return;
+  const int nx = D.nx, ny = D.ny;
+  const int px = D.px, pl = (int)D.plane;
+  const int x0 = t.y, y0 = t.z;
+  const int w = min(TX, nx - x0), h = min(TY, ny - y0);
+  const int bcx = D.bc[0], bcy = D.bc[1];
+  const bool wx = bcx != BC_PER, wy = bcy != BC_PER;
+  const int ib = par(n_phi(D, k - 1)), ob = ib ^ 1;
+  GLOBAL const R* __restrict__ phi_in = gp<const R>(D.phi[ib]);
+  GLOBAL R* __restrict__ phi_out = gp<R>(D.phi[ob]);
+  GLOBAL const S* __restrict__ s_in = gp<const S>(D.sphi[ib]);
+  GLOBAL S* __restrict__ s_out = gp<S>(D.sphi[ob]);
+  const long long nU = (D.accum ? 0 : (k - 1) / D.N_phi) + (k - 1) / D.N_U;
+  GLOBAL const R* __restrict__ Up = D.has_U ? gp<const R>(D.U[par(nU)]) : nullptr;
+  GLOBAL R* __restrict__ Uout = D.has_U ? gp<R>(D.U[par(nU + 1)]) : nullptr;
+  GLOBAL const R* __restrict__ Tin = D.has_T ? gp<const R>(D.T[par(n_T(D, k - 1))]) : nullptr;
+  GLOBAL R* __restrict__ Tout = D.has_T ? gp<R>(D.T[par(n_T(D, k - 1) + 1)]) : nullptr;
+  GLOBAL R* __restrict__ PU = gp<R>(D.PU);
+  GLOBAL R* __restrict__ PT = gp<R>(D.PT);
+
+  PhaseConst<R> c;
+  c.dt = R(D.N_phi * D.dt_base);
+  c.W2t = R(D.W0 * D.W0 / D.tau0);
+  c.inv_tau0 = R(1.0 / D.tau0);
+  c.eps = R(D.eps);
+  c.lam = R(D.lam);
+  c.Mc = R(D.Mc);
+  c.cth = R(D.cth);
+  c.sth = R(D.sth);
+  c.inv_lhcp = R(D.Cp_L / D.L_h);
+  c.theta_off = R(D.T_m + D.m_L * D.C_inf);
+  const R Uref = R(D.U0), Tref = R(D.T0);
+  const R omk = R(1.0 - D.kc), opk = R(1.0 + D.kc);
+  const R cJ = R(D.W0 / (2.0 * 1.4142135623730951));
+  const R cT = R(D.rho_L * D.L_h);
+  const R rcS = R(D.rcS), rcL = R(D.rcL);
+  const int tid = threadIdx.y * TX + threadIdx.x;
+
+  // raw coordinate -> node whose values it takes (wrap or clamp)
+  auto nodex = [&](int g) { return ghost(g, nx, bcx); };
+  auto nodey = [&](int g) { return ghost(g, ny, bcy); };
+  // raw coordinate -> its position in a region of ring r, after clamping at walls
+  auto posx = [&](int g, int r) { return (wx ? min(max(g, 0), nx - 1) : g) - (x0 - r); };
+  auto posy = [&](int g, int r) { return (wy ? min(max(g, 0), ny - 1) : g) - (y0 - r); };
+
+  // ---- global loads: the collision inputs of this thread's cells, phi^q box
+  R sv[C3][4], Uv[C3], Tv[C3];
+  bool live[C3];
+#pragma unroll
+  for (int j = 0; j < C3; ++j) {
+    const int cidx = tid + j * NTHR;
+    live[j] = false;
+    if (cidx >= N3) continue;
+    const int gx = x0 - 3 + cidx % W3, gy = y0 - 3 + cidx / W3;
+    const int rx = resolve(gx, nx, bcx), ry = resolve(gy, ny, bcy);
+    if (rx < 0 || ry < 0) continue;                    // beyond a wall: never pulled from
+    live[j] = true;
+    const unsigned o = ry * px + rx;
+    sv[j][0] = ld(s_in, o);
+    sv[j][1] = ld(s_in, o + pl);
+    sv[j][2] = ld(s_in, o + 2 * pl);
+    sv[j][3] = ld(s_in, o + 3 * pl);
+    Uv[j] = Up ? Up[o] + Uref : R(0);
+    Tv[j] = Tin ? Tin[o] + Tref : c.theta_off;
+  }
+  for (int cidx = tid; cidx < N4; cidx += NTHR) {
+    const int gx = x0 - 4 + cidx % W4, gy = y0 - 4 + cidx / W4;
+    sq[cidx] = phi_in[nodey(gy) * px + nodex(gx)];
+  }
+  __syncthreads();
+
+  // ---- collisions on the tile + 3 ring
+#pragma unroll
+  for (int j = 0; j < C3; ++j) {
+    if (!live[j]) continue;
+    const int cidx = tid + j * NTHR;
+    const int lx = cidx % W3, ly = cidx / W3;
+    const R* b = &sq[(ly + 1) * W4 + lx + 1];
+    R gxv, gyv;
+    iso_grad(b, W4, gxv, gyv);
+    R dP, Kx, Ky, A;
+    phase_collide(c, b[0], gxv, gyv, sv[j][0] - sv[j][2], sv[j][1] - sv[j][3], Uv[j], Tv[j], dP, Kx, Ky, A);
+    cP[cidx] = dP;
+    cKx[cidx] = Kx;
+    cKy[cidx] = Ky;
+    cA[cidx] = A;
+  }
+  __syncthreads();
+
+  // ---- anisotropic streaming on the tile + 2 ring (deviation form)
+  for (int cidx = tid; cidx < N2; cidx += NTHR) {
+    const int lx = cidx % W2, ly = cidx / W2;
+    const int gx = x0 - 2 + lx, gy = y0 - 2 + ly;
+    const int rx = resolve(gx, nx, bcx), ry = resolve(gy, ny, bcy);
+    if (rx < 0 || ry < 0) continue;                    // filled from the clamped node below
+    const unsigned o = ry * px + rx;
+    const R s1 = ld(s_in, o), s2 = ld(s_in, o + pl), s3 = ld(s_in, o + 2 * pl), s4 = ld(s_in, o + 3 * pl);
+    const int ci = (ly + 1) * W3 + lx + 1;             // this node in the collision region
+    const int bq = (ly + 2) * W4 + lx + 2;             // this node in the phi^q box
+    const R A = cA[ci], iA = rcp(A), oA = R(1) - A;
+    const R phy = sq[bq];
+    const R dPo = cP[ci], Kxo = cKx[ci], Kyo = cKy[ci];
+    const R svq[4] = {s1, s2, s3, s4};
+    const R s0 = -(s1 + s2 + s3 + s4);
+    const bool bb[5] = {false, wx && rx == 0, wy && ry == 0, wx && rx == nx - 1, wy && ry == ny - 1};
+    R dn[5];
+    dn[0] = (dPo * R(1.0 / 3.0) - oA * s0) * iA;
+#pragma unroll
+    for (int q = 1; q < 5; ++q) {
+      const int ex = EX5(q), ey = EY5(q);
+      R dpost;
+      if (bb[q]) {
+        dpost = dPo * R(1.0 / 6.0) - R(0.5) * (R(ex) * Kxo + R(ey) * Kyo);
+      } else {
+        const int si = ci - ey * W3 - ex;
+        const R dphi = sq[bq - ey * W4 - ex] - phy;
+        dpost = (dphi + cP[si]) * R(1.0 / 6.0) + R(0.5) * (R(ex) * cKx[si] + R(ey) * cKy[si]);
+      }
+      dn[q] = (dpost - oA * svq[q - 1]) * iA;
+    }
+    const R dphin = dn[0] + dn[1] + dn[2] + dn[3] + dn[4];
+    const R pn = phy + dphin;
+    sn[cidx] = pn;
+    if (lx >= 2 && ly >= 2 && lx - 2 < w && ly - 2 < h) {   // the tile: write the new state
+      phi_out[o] = pn;
+      const R w6 = dphin * R(1.0 / 6.0);
+      st(s_out, o, dn[1] - w6);
+      st(s_out, o + pl, dn[2] - w6);
+      st(s_out, o + 2 * pl, dn[3] - w6);
+      st(s_out, o + 3 * pl, dn[4] - w6);
+    }
+  }
+  __syncthreads();
+  if (wx || wy) {   // raw positions beyond a wall take phi^{q+1} of the clamped node
+    for (int cidx = tid; cidx < N2; cidx += NTHR) {
+      const int lx = cidx % W2, ly = cidx / W2;
+      const int gx = x0 - 2 + lx, gy = y0 - 2 + ly;
+      if (resolve(gx, nx, bcx) >= 0 && resolve(gy, ny, bcy) >= 0) continue;
+      sn[cidx] = sn[posy(gy, 2) * W2 + posx(gx, 2)];
+    }
+    __syncthreads();
+  }
+
+  if (!D.has_U) {
+    // latent heat only: an own-site update
+    if (!D.has_T) return;
+    for (int cidx = tid; cidx < TX * TY; cidx += NTHR) {
+      const int lx = cidx % TX, ly = cidx / TX;
+      if (lx >= w || ly >= h) continue;
+      const unsigned o = (y0 + ly) * px + x0 + lx;
+      const R pn = sn[(ly + 2) * W2 + lx + 2];
+      const R dphi = pn - sq[(ly + 4) * W4 + lx + 4];
+      const R rc = (R(1) + pn) * R(0.5) * rcS + (R(1) - pn) * R(0.5) * rcL;
+      const R dT = cT * dphi * rcp(R(2) * rc);
+      if (D.accum)
+        PT[o] = PT[o] + dT;
+      else
+        Tout[o] = Tin[o] + dT;
+    }
+    return;
+  }
+
+  // ---- anti-trapping current on the tile + 1 ring (Eq. 37); beyond a wall
+  // the current of the clamped node with its normal component negated
+  for (int cidx = tid; cidx < N1; cidx += NTHR) {
+    const int lx = cidx % W1, ly = cidx / W1;
+    const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
+    const bool mx = wx && (gx < 0 || gx >= nx), my = wy && (gy < 0 || gy >= ny);
+    const int qx = posx(gx, 1), qy = posy(gy, 1);      // node position in the J region
+    const R* b = &sn[(qy + 1) * W2 + qx + 1];
+    R gxv, gyv;
+    iso_grad(b, W2, gxv, gyv);
+    const R gg = gxv * gxv + gyv * gyv;
+    R Jx = R(0), Jy = R(0);
+    if (gg >= R(GRAD_EPS2)) {
+      const unsigned o = nodey(gy) * px + nodex(gx);
+      const R ig = rsq(gg);
+      const R pold = sq[(qy + 3) * W4 + qx + 3];
+      const R a = cJ * (R(1) + omk * (Up[o] + Uref)) * (b[0] - pold) * ig;
+      Jx = -a * gxv;
+      Jy = -a * gyv;
+    }
+    sJx[cidx] = mx ? -Jx : Jx;
+    sJy[cidx] = my ? -Jy : Jy;
+  }
+  __syncthreads();
+
+  // ---- increments of Eq. (38) and the injection of Eq. (39) on the tile
+  R amax = R(0);
+  for (int cidx = tid; cidx < TX * TY; cidx += NTHR) {
+    const int lx = cidx % TX, ly = cidx / TX;
+    if (lx >= w || ly >= h) continue;
+    const unsigned o = (y0 + ly) * px + x0 + lx;
+    const R pn = sn[(ly + 2) * W2 + lx + 2];
+    const R dphi = pn - sq[(ly + 4) * W4 + lx + 4];
+    const R* jx = &sJx[(ly + 1) * W1 + lx + 1];
+    const R* jy = &sJy[(ly + 1) * W1 + lx + 1];
+    const R div = (jx[1] - jx[-1]) * R(1.0 / 3.0) +
+                  (jx[W1 + 1] - jx[W1 - 1] - jx[-W1 - 1] + jx[-W1 + 1]) * R(1.0 / 12.0) +
+                  (jy[W1] - jy[-W1]) * R(1.0 / 3.0) +
+                  (jy[W1 + 1] + jy[W1 - 1] - jy[-W1 - 1] - jy[-W1 + 1]) * R(1.0 / 12.0);
+    const R Us = Up[o];
+    const R dU = ((R(1) + omk * (Us + Uref)) * dphi - R(2) * div) * rcp(opk - omk * pn);
+    amax = fmax(amax, fabs(dU));
+    if (D.accum)
+      PU[o] = PU[o] + dU;
+    else
+      Uout[o] = Us + dU;
+    if (D.has_T) {
+      const R rc = (R(1) + pn) * R(0.5) * rcS + (R(1) - pn) * R(0.5) * rcL;
+      const R dT = cT * dphi * rcp(R(2) * rc);
+      if (D.accum)
+        PT[o] = PT[o] + dT;
+      else
+        Tout[o] = Tin[o] + dT;
+    }
+  }
+  if (part) {
+    for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_down(amax, off, 64));
+    if (threadIdx.x == 0) red[threadIdx.y] = amax;
     __syncthreads();
     if (tid == 0) {
       R m = red[0];
@@ -551,10 +817,10 @@ __global__ __launch_bounds__(NTHR) void k_scalar(const Dom* __restrict__ doms, c
     jout = gp<S>(D.jU[par(n_jU(D, k))]);
     pend = gp<R>(D.PU);
   } else {
-    cin = gp<const R>(D.T[par(n_T(D, k - 1))]);
-    cout = gp<R>(D.T[par(n_T(D, k))]);
-    jin = gp<const S>(D.jT[par(n_T(D, k - 1))]);
-    jout = gp<S>(D.jT[par(n_T(D, k))]);
+    cin = gp<const R>(D.T[par(n_Ttr(D, k) + (k - 1) / D.N_T)]);
+    cout = gp<R>(D.T[par(n_Ttr(D, k) + k / D.N_T)]);
+    jin = gp<const S>(D.jT[par(n_jT(D, k - 1))]);
+    jout = gp<S>(D.jT[par(n_jT(D, k))]);
     pend = gp<R>(D.PT);
   }
   GLOBAL const R* __restrict__ phis = gp<const R>(D.phi[par(n_phi(D, k))]);
@@ -974,7 +1240,7 @@ __device__ double read_plane(const Dom& D, long long k, int code, long long o) {
     case 4: return double((gp<const R>(D.vel[par(n_F(D, k))]))[o]);
     case 5: return double((gp<const R>(D.vel[par(n_F(D, k))]))[o + pl]);
     case 20: case 21: return double(ld(gp<const S>(D.jU[par(n_jU(D, k))]), o + (code - 20) * pl));
-    case 30: case 31: return double(ld(gp<const S>(D.jT[par(n_T(D, k))]), o + (code - 30) * pl));
+    case 30: case 31: return double(ld(gp<const S>(D.jT[par(n_jT(D, k))]), o + (code - 30) * pl));
     case 50: return double((gp<const R>(D.PU))[o]);
     case 51: return double((gp<const R>(D.PT))[o]);
     default: break;
@@ -1049,7 +1315,7 @@ __global__ void k_write(const Dom* __restrict__ doms, int dom, long long k, cons
       case 4: (gp<R>(D.vel[par(n_F(D, k))]))[o] = R(v); break;
       case 5: (gp<R>(D.vel[par(n_F(D, k))]))[o + pl] = R(v); break;
       case 20: case 21: st(gp<S>(D.jU[par(n_jU(D, k))]), o + (code - 20) * pl, R(v)); break;
-      case 30: case 31: st(gp<S>(D.jT[par(n_T(D, k))]), o + (code - 30) * pl, R(v)); break;
+      case 30: case 31: st(gp<S>(D.jT[par(n_jT(D, k))]), o + (code - 30) * pl, R(v)); break;
       case 50: (gp<R>(D.PU))[o] = R(v); break;
       case 51: (gp<R>(D.PT))[o] = R(v); break;
       case 60: case 61: case 62: case 63:
@@ -1516,8 +1782,12 @@ __global__ __launch_bounds__(256) void k3_transfer_apply(const Dom* __restrict__
     if (D.has_T && !D.T_pulled) {
       const R rc = (R(1) + p1) * R(0.5 * D.rcS) + (R(1) - p1) * R(0.5 * D.rcL);
       const R dT = R(D.rho_L * D.L_h) * dphi * rcp(R(2) * rc);
-      GLOBAL R* Tp = D.accum ? gp<R>(D.PT) : gp<R>(D.T[par(n_T(D, k - 1))]);
-      Tp[s.o] = Tp[s.o] + dT;
+      if (D.accum) {
+        GLOBAL R* PT = gp<R>(D.PT);
+        PT[s.o] = PT[s.o] + dT;
+      } else {
+        gp<R>(D.T[par(n_T(D, k - 1) + 1)])[s.o] = gp<const R>(D.T[par(n_T(D, k - 1))])[s.o] + dT;
+      }
     }
   }
   if (part && D.has_U) {
@@ -1546,8 +1816,8 @@ __global__ __launch_bounds__(256) void k3_scalar_collide(const Dom* __restrict__
     cin = gp<const R>(D.U[par((D.accum ? 0 : k / D.N_phi) + (k - 1) / D.N_U)]);
     jin = gp<const S>(D.jU[par(n_jU(D, k - 1))]);
   } else {
-    cin = gp<const R>(D.T[par(n_T(D, k - 1))]);
-    jin = gp<const S>(D.jT[par(n_T(D, k - 1))]);
+    cin = gp<const R>(D.T[par(n_Ttr(D, k) + (k - 1) / D.N_T)]);
+    jin = gp<const S>(D.jT[par(n_jT(D, k - 1))]);
   }
   GLOBAL const R* phis = gp<const R>(D.phi[par(n_phi(D, k))]);
   const R dt = R(N * D.dt_base);
@@ -1619,9 +1889,9 @@ __global__ __launch_bounds__(256) void k3_scalar_stream(const Dom* __restrict__ 
     jout = gp<S>(D.jU[par(n_jU(D, k))]);
     pend = gp<R>(D.PU);
   } else {
-    cin = gp<const R>(D.T[par(n_T(D, k - 1))]);
-    cout = gp<R>(D.T[par(n_T(D, k))]);
-    jout = gp<S>(D.jT[par(n_T(D, k))]);
+    cin = gp<const R>(D.T[par(n_Ttr(D, k) + (k - 1) / D.N_T)]);
+    cout = gp<R>(D.T[par(n_Ttr(D, k) + k / D.N_T)]);
+    jout = gp<S>(D.jT[par(n_jT(D, k))]);
     pend = gp<R>(D.PT);
   }
   GLOBAL const R* scr = gp<const R>(D.scr);
@@ -1880,7 +2150,7 @@ __device__ double read_plane3(const Dom& D, long long k, int code, unsigned o) {
   if (code == 3) return double((gp<const R>(D.rho[par(n_F(D, k))]))[o]);
   if (code >= 4 && code <= 6) return double((gp<const R>(D.vel[par(n_F(D, k))]))[o + (code - 4) * pl]);
   if (code >= 20 && code <= 22) return double(ld(gp<const S>(D.jU[par(n_jU(D, k))]), o + (code - 20) * pl));
-  if (code >= 30 && code <= 32) return double(ld(gp<const S>(D.jT[par(n_T(D, k))]), o + (code - 30) * pl));
+  if (code >= 30 && code <= 32) return double(ld(gp<const S>(D.jT[par(n_jT(D, k))]), o + (code - 30) * pl));
   if (code == 90) return double((gp<const R>(D.PU))[o]);
   if (code == 91) return double((gp<const R>(D.PT))[o]);
   if (code >= 60 && code <= 65) return double(ld(gp<const S>(D.sphi[par(n_phi(D, k))]), o + (code - 60) * pl));
@@ -1948,7 +2218,7 @@ __global__ void k3_write(const Dom* __restrict__ doms, long long k, const int* _
     else if (code == 3) (gp<R>(D.rho[par(n_F(D, k))]))[o] = R(v);
     else if (code >= 4 && code <= 6) (gp<R>(D.vel[par(n_F(D, k))]))[o + (code - 4) * pl] = R(v);
     else if (code >= 20 && code <= 22) st(gp<S>(D.jU[par(n_jU(D, k))]), o + (code - 20) * pl, R(v));
-    else if (code >= 30 && code <= 32) st(gp<S>(D.jT[par(n_T(D, k))]), o + (code - 30) * pl, R(v));
+    else if (code >= 30 && code <= 32) st(gp<S>(D.jT[par(n_jT(D, k))]), o + (code - 30) * pl, R(v));
     else if (code == 90) (gp<R>(D.PU))[o] = R(v);
     else if (code == 91) (gp<R>(D.PT))[o] = R(v);
     else if (code >= 60 && code <= 65) st(gp<S>(D.sphi[par(n_phi(D, k))]), o + (code - 60) * pl, R(v));
@@ -2133,6 +2403,17 @@ struct Launch {
     else if (TY == 8) k_phase<R, S, 8><<<g, b, 0, st>>>(d, t, k);
     else if (TY == 16) k_phase<R, S, 16><<<g, b, 0, st>>>(d, t, k);
     else k_phase<R, S, 32><<<g, b, 0, st>>>(d, t, k);
+  }
+  // phase + transfer in one kernel: 8-row tiles in FP64 (LDS), 8 or 16 otherwise
+  static int phase_tr_rows(int TY) { return sizeof(R) == 8 ? 8 : (TY >= 16 ? 16 : 8); }
+  static void phase_tr(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k, Partial* p) {
+    const dim3 b(TX, BY);
+    if constexpr (sizeof(R) == 8) {
+      k_phase_tr<R, S, 8><<<g, b, 0, st>>>(d, t, k, p);
+    } else {
+      if (TY >= 16) k_phase_tr<R, S, 16><<<g, b, 0, st>>>(d, t, k, p);
+      else k_phase_tr<R, S, 8><<<g, b, 0, st>>>(d, t, k, p);
+    }
   }
   static void transfer(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k, Partial* p) {
     const dim3 b(TX, BY);

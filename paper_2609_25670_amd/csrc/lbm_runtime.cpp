@@ -28,6 +28,8 @@ template <class R, class S>
 struct Launch {
   static void phase(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k);
   static void transfer(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k, Partial* p);
+  static int phase_tr_rows(int TY);
+  static void phase_tr(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k, Partial* p);
   static void scalar(int field, int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k,
                      Partial* p);
   static void flow(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k);
@@ -83,6 +85,8 @@ struct Group {
 struct Ops {
   void (*phase)(int, dim3, hipStream_t, const Dom*, const int4*, long long);
   void (*transfer)(int, dim3, hipStream_t, const Dom*, const int4*, long long, Partial*);
+  void (*phase_tr)(int, dim3, hipStream_t, const Dom*, const int4*, long long, Partial*);
+  int (*phase_tr_rows)(int);
   void (*scalar)(int, int, dim3, hipStream_t, const Dom*, const int4*, long long, Partial*);
   void (*flow)(int, dim3, hipStream_t, const Dom*, const int4*, long long);
   void (*diag_tiles)(int, dim3, hipStream_t, const Dom*, const int4*, long long, Partial*);
@@ -94,7 +98,8 @@ struct Ops {
 
 template <class R, class S>
 Ops make_ops() {
-  return Ops{Launch<R, S>::phase, Launch<R, S>::transfer, Launch<R, S>::scalar, Launch<R, S>::flow,
+  return Ops{Launch<R, S>::phase, Launch<R, S>::transfer, Launch<R, S>::phase_tr, Launch<R, S>::phase_tr_rows,
+             Launch<R, S>::scalar, Launch<R, S>::flow,
              Launch<R, S>::diag_tiles, Launch<R, S>::tips, Launch<R, S>::init, Launch<R, S>::read,
              Launch<R, S>::write};
 }
@@ -158,6 +163,8 @@ struct lbm_ctx {
   bool tuned = false;
   bool autotune = true;
   bool use_graph = true;
+  bool fuse = false;      // phase + transfer in one kernel (2D) when every domain allows it
+  bool fusable = false;   // every domain at least 8 x 8 (the fused kernel's rings wrap once at most)
   hipGraphExec_t gexec = nullptr;
   int graph_ty = -1;
   long long cycle = 1;
@@ -294,16 +301,28 @@ std::vector<int4> xcd_order(const std::vector<int4>& spatial) {
 }  // namespace
 
 // ------------------------------------------------------------------ helpers
+static int ty_slot(int rows) {
+  for (int i = 0; i < kNTY; ++i)
+    if (kTYs[i] == rows) return i;
+  return 0;
+}
+
 static void launch_step(lbm_ctx* c, hipStream_t st, long long k) {
   if (c->dim == 3) {
     c->ops3.step(c->H[0], st, c->d_dom, k, c->d_part);
     return;
   }
   const int ti = c->ty_index, TY = kTYs[ti];
+  const bool fused = c->fuse && c->fusable;
+  const int tf = fused ? ty_slot(c->ops.phase_tr_rows(TY)) : ti;
   for (auto& g : c->g_phi)
     if (k % g.N == 0) {
-      c->ops.phase(TY, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k);
-      c->ops.transfer(TY, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k, c->d_part);
+      if (fused) {
+        c->ops.phase_tr(kTYs[tf], dim3(g.ts[tf].n), st, c->d_dom, g.ts[tf].d, k, c->d_part);
+      } else {
+        c->ops.phase(TY, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k);
+        c->ops.transfer(TY, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k, c->d_part);
+      }
     }
   for (auto& g : c->g_U)
     if (k % g.N == 0) c->ops.scalar(0, TY, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k, c->d_part);
@@ -320,7 +339,9 @@ static lbm_status upload_doms(lbm_ctx* c) {
 }
 
 // Time each tile height on the kernels whose launches are idempotent for a
-// fixed k (they read one buffer and write the other) and keep the fastest.
+// fixed k (they read one buffer and write the other: the phase kernel, or
+// the phase + transfer kernel with instantaneous coupling, and the flow)
+// and keep the fastest.
 static lbm_status autotune(lbm_ctx* c) {
   hipEvent_t e0, e1;
   HIPCHK(c, hipEventCreate(&e0));
@@ -335,11 +356,18 @@ static lbm_status autotune(lbm_ctx* c) {
   for (int ti = 0; ti < kNTY; ++ti) {
     const int TY = kTYs[ti];
     auto run = [&]() {
-      for (auto& g : c->g_phi)
-        c->ops.phase(TY, dim3(g.ts[ti].n), c->stream, c->d_dom, g.ts[ti].d, next_due(g.N));
-      if (!any_accum)
-        for (auto& g : c->g_T)
-          c->ops.scalar(1, TY, dim3(g.ts[ti].n), c->stream, c->d_dom, g.ts[ti].d, next_due(g.N), nullptr);
+      const bool fused = c->fuse && c->fusable && !any_accum;   // accumulated coupling adds in place
+      const int tf = fused ? ty_slot(c->ops.phase_tr_rows(TY)) : ti;
+      for (auto& g : c->g_phi) {
+        if (fused)
+          c->ops.phase_tr(kTYs[tf], dim3(g.ts[tf].n), c->stream, c->d_dom, g.ts[tf].d, next_due(g.N), nullptr);
+        else
+          c->ops.phase(TY, dim3(g.ts[ti].n), c->stream, c->d_dom, g.ts[ti].d, next_due(g.N));
+      }
+      // (the U and T transports are not timed: with instantaneous coupling
+      // the transfer of the same step also writes their planes, so the
+      // transport of the next due step writes the current buffer; with
+      // accumulated coupling it clears the pending planes)
       for (auto& g : c->g_F) c->ops.flow(TY, dim3(g.ts[ti].n), c->stream, c->d_dom, g.ts[ti].d, next_due(g.N));
     };
     run();
@@ -546,6 +574,8 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
     if (q.has_T) lcm = ipow_lcm(lcm, q.N_T);
     if (q.has_flow) lcm = ipow_lcm(lcm, q.N_F);
   }
+  c->fusable = true;
+  for (int i = 0; i < n; ++i) c->fusable &= p[i].dim == 2 && p[i].nx >= 8 && p[i].ny >= 8;
   c->cycle = 2 * lcm;
   c->d_dom = (Dom*)take(sizeof(Dom) * n);
 
@@ -726,7 +756,7 @@ lbm_status lbm_init_front(lbm_ctx* c, int32_t dom, const double* xi) {
   return LBM_OK;
 }
 
-lbm_status lbm_configure(lbm_ctx* c, int32_t tile_rows, int32_t use_graph) {
+lbm_status lbm_configure(lbm_ctx* c, int32_t tile_rows, int32_t flags) {
   if (!c) return LBM_EINVAL;
   if (tile_rows == 0) {
     c->autotune = true;
@@ -740,7 +770,14 @@ lbm_status lbm_configure(lbm_ctx* c, int32_t tile_rows, int32_t use_graph) {
     c->autotune = false;
     c->tuned = true;
   }
-  c->use_graph = use_graph != 0;
+  if (flags & ~3) return fail(c, LBM_EINVAL, "unknown configure flags");
+  c->use_graph = (flags & LBM_CFG_GRAPH) != 0;
+  c->fuse = (flags & LBM_CFG_FUSE_TRANSFER) != 0;
+  if (c->gexec) {   // the captured cycle follows the kernel choice
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+  }
   return LBM_OK;
 }
 
@@ -756,13 +793,14 @@ lbm_status lbm_kernel_times(lbm_ctx* c, int32_t reps, double* ms_out, double* pe
     if (s != LBM_OK) return s;
   }
   const int ti = c->ty_index, TY = kTYs[ti];
+  const bool fused = c->dim == 2 && c->fuse && c->fusable;
   hipEvent_t e0, e1;
   HIPCHK(c, hipEventCreate(&e0));
   HIPCHK(c, hipEventCreate(&e1));
   auto due = [&](int N) { return (c->k / N + 1) * (long long)N; };
   for (int kind = 0; kind < 5; ++kind) {
     const std::vector<Group>& gs = kind <= 1 ? c->g_phi : kind == 2 ? c->g_U : kind == 3 ? c->g_T : c->g_F;
-    if (gs.empty()) {
+    if (gs.empty() || (kind == 1 && fused)) {   // fused: the transfer runs inside the phase kernel
       ms_out[kind] = -1.0;
       if (per_step) per_step[kind] = 0.0;
       continue;
@@ -784,7 +822,11 @@ lbm_status lbm_kernel_times(lbm_ctx* c, int32_t reps, double* ms_out, double* pe
           if (kind == 4) c->ops3.flow(h, c->stream, c->d_dom, k);
           return;
         }
-        if (kind == 0) c->ops.phase(TY, grid, c->stream, c->d_dom, g.ts[ti].d, k);
+        if (kind == 0 && fused) {
+          const int tf = ty_slot(c->ops.phase_tr_rows(TY));
+          c->ops.phase_tr(kTYs[tf], dim3(g.ts[tf].n), c->stream, c->d_dom, g.ts[tf].d, k, c->d_part);
+        }
+        if (kind == 0 && !fused) c->ops.phase(TY, grid, c->stream, c->d_dom, g.ts[ti].d, k);
         if (kind == 1) c->ops.transfer(TY, grid, c->stream, c->d_dom, g.ts[ti].d, k, c->d_part);
         if (kind == 2) c->ops.scalar(0, TY, grid, c->stream, c->d_dom, g.ts[ti].d, k, c->d_part);
         if (kind == 3) c->ops.scalar(1, TY, grid, c->stream, c->d_dom, g.ts[ti].d, k, c->d_part);

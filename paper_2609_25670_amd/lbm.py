@@ -204,8 +204,11 @@ class Simulation:
             r = (ctypes.c_double * max(1, len(seeds)))(*[s[2] for s in seeds])
             _check(self.lib, self.ctx, self.lib.lbm_init_seeds(self.ctx, i, len(seeds), c, r))
 
-    def configure(self, tile_rows=0, use_graph=True):
-        _check(self.lib, self.ctx, self.lib.lbm_configure(self.ctx, int(tile_rows), int(bool(use_graph))))
+    def configure(self, tile_rows=0, use_graph=True, fuse_transfer=False):
+        """Tile height (0 = autotune), HIP-graph replay of whole cycles, and
+        whether the 2D transfer runs inside the phase kernel."""
+        flags = (1 if use_graph else 0) | (2 if fuse_transfer else 0)
+        _check(self.lib, self.ctx, self.lib.lbm_configure(self.ctx, int(tile_rows), flags))
 
     def step(self, n, diag=False):
         """Advance every domain by n base steps.  With ``diag`` returns a list

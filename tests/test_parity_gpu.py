@@ -28,12 +28,12 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / (nb if nb > 1e-300 else 1.0)
 
 
-def _gpu(wl, steps, storage="f64", names=("phi",), tile_rows=None, use_graph=True, domains=None):
+def _gpu(wl, steps, storage="f64", names=("phi",), tile_rows=None, use_graph=True, domains=None, fuse=False):
     from paper_2609_25670_amd import simulation_for
 
     sim = simulation_for(wl, storage=storage)
     if tile_rows is not None:
-        sim.configure(tile_rows, use_graph)
+        sim.configure(tile_rows, use_graph, fuse)
     diag = sim.step(steps, diag=True)
     outs = [sim.read(i, names) for i in (domains if domains is not None else range(sim.n))]
     sim.close()
@@ -149,22 +149,23 @@ def test_batched_uneven_domains_fp64(use_graph):
         _compare(f"domain{i}", gots[i], _oracle_fields(dom, names), TOL64)
 
 
-def test_tile_shapes_and_graph_are_bitwise_identical():
-    """Race detector: every tile height and graph replay versus eager
-    launches give bitwise-identical FP64 state."""
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_tile_shapes_graph_and_fusion_are_bitwise_identical(storage):
+    """Race detector: every tile height, graph replay versus eager launches,
+    and the phase + transfer kernel versus the two separate kernels give
+    bitwise-identical state."""
     wl = L.reduced(L.thermosolutal_flow_1024(), 130, 75)
     wl["domains"][0]["tau0"] = 40.0
     names = ("phi", "U", "T", "rho", "vel", "f_phi", "jU", "jT", "f_F")
     ref = None
-    for rows in (4, 8, 16, 32):
-        for g in (True, False):
-            _say(f"case determinism rows={rows} graph={g}")
-            (got,), _ = _gpu(wl, 64, names=names, tile_rows=rows, use_graph=g)
-            if ref is None:
-                ref = got
-            else:
-                for n in names:
-                    assert np.array_equal(got[n], ref[n]), (rows, g, n)
+    for rows, g, fuse in [(r, g, f) for r in (4, 8, 16, 32) for g in (True, False) for f in (True, False)]:
+        _say(f"case determinism {storage} rows={rows} graph={g} fused={fuse}")
+        (got,), _ = _gpu(wl, 64, storage=storage, names=names, tile_rows=rows, use_graph=g, fuse=fuse)
+        if ref is None:
+            ref = got
+        else:
+            for n in names:
+                assert np.array_equal(got[n], ref[n]), (rows, g, fuse, n)
 
 
 def test_checkpoint_restore_is_bitwise():
