@@ -43,14 +43,14 @@ struct Dom {
   double U0, T0;
   double T_grad, V_pull, z_front;
   int u0_liquid;
-  int pad1;
+  int qs;                       // scalar lattice: 5 (D2Q5), 9 (D2Q9) or 7 (D3Q7)
   // base steps to add to a kernel's step argument to get the absolute step:
   // zero for direct launches, the step at replay start for a captured graph
   // (whose launches carry the steps of its first cycle)
   long long koff;
   // state
   void* phi[2];    // R, 1 plane
-  void* sphi[2];   // S, Q-1 planes: f_i - w_i phi, i >= 1 (4 in D2Q5, 6 in D3Q7)
+  void* sphi[2];   // S, Q-1 planes: f_i - w_i phi, i >= 1 (4 in D2Q5, 8 in D2Q9, 6 in D3Q7)
   void* U[2];      // R
   void* jU[2];     // S, dim planes: first moment of the U populations
   void* PU;        // R, pending U increments (accumulated coupling)

@@ -126,6 +126,29 @@ __device__ __forceinline__ void iso_grad(const R* b, int stride, R& gx, R& gy) {
 // unrolled loops fold them into immediates).
 #define EX5(q) ((q) == 1 ? 1 : (q) == 3 ? -1 : 0)
 #define EY5(q) ((q) == 2 ? 1 : (q) == 4 ? -1 : 0)
+// D2Q9 (Eq. 15): 0, the axes as in D2Q5, then (1,1), (-1,1), (-1,-1), (1,-1)
+#define EX9(q) ((q) == 1 || (q) == 5 || (q) == 8 ? 1 : (q) == 3 || (q) == 6 || (q) == 7 ? -1 : 0)
+#define EY9(q) ((q) == 2 || (q) == 5 || (q) == 6 ? 1 : (q) == 4 || (q) == 7 || (q) == 8 ? -1 : 0)
+
+// Scalar lattices of the phase, U and T fields: D2Q5 (weights 1/3, 1/6) or
+// the paper's D2Q9 (4/9, 1/9, 1/36).  With the relaxation of Eq. (23) every
+// moment but the flux relaxes to equilibrium, so the post-collision
+// populations depend on (chi, j) only:
+//   f_i^+ = w_i (chi + dP) + e_i . [ (3 w_i - c_K) j_eq + c_K K ],
+//   K = j_eq + (1 - 1/tau)(j - j_eq),
+// where c_K = 1 / sum_k e_kx^2 is 1/2 (D2Q5) or 1/6 (D2Q9) (the flux row of
+// the moment basis has that squared norm); in D2Q5 3 w_i = c_K, so only K
+// enters.
+template <int Q>
+struct Lat2 {
+  static constexpr int ex(int q) { return Q == 5 ? EX5(q) : EX9(q); }
+  static constexpr int ey(int q) { return Q == 5 ? EY5(q) : EY9(q); }
+  static constexpr double w(int q) {
+    return Q == 5 ? (q == 0 ? 1.0 / 3 : 1.0 / 6) : (q == 0 ? 4.0 / 9 : q <= 4 ? 1.0 / 9 : 1.0 / 36);
+  }
+  static constexpr double cK = Q == 5 ? 0.5 : 1.0 / 6;
+  static constexpr double cJ(int q) { return 3.0 * w(q) - cK; }   // 0 in D2Q5
+};
 
 // =================================================================== phase
 // Collision of Eq. (14) with the equilibrium of Eq. (21), the relaxation of
@@ -148,7 +171,7 @@ struct PhaseConst {
 
 template <class R>
 __device__ __forceinline__ void phase_collide(const PhaseConst<R>& c, R phi, R gx, R gy, R jx, R jy,
-                                              R Us, R Ts, R& dP, R& Kx, R& Ky, R& A) {
+                                              R Us, R Ts, R& dP, R& Kx, R& Ky, R& A, R* jeq = nullptr) {
   const R gg = gx * gx + gy * gy;
   R a_s = R(1), Nx = R(0), Ny = R(0);
   if (gg >= R(GRAD_EPS2)) {
@@ -178,6 +201,10 @@ __device__ __forceinline__ void phase_collide(const PhaseConst<R>& c, R phi, R g
   dP = c.dt * Q * c.inv_tau0;
   Kx = jex + om * (jx - jex);
   Ky = jey + om * (jy - jey);
+  if (jeq) {
+    jeq[0] = jex;
+    jeq[1] = jey;
+  }
 }
 
 // Ring cell r of the collision box of a w x h tile (box cells (lx, ly) in
@@ -216,15 +243,18 @@ __device__ __forceinline__ void load_box2(R* box, const GLOBAL R* __restrict__ p
 }
 
 // =================================================================== phase kernel
-template <class R, class S, int TY>
+template <class R, class S, int TY, int Q>
 __global__ __launch_bounds__(NTHR) void k_phase(const Dom* __restrict__ doms, const int4* __restrict__ tiles,
                                                  long long k) {
+  using Lq = Lat2<Q>;
   constexpr int RPT = TY / BY;
   constexpr int NS = RPT + 1;  // owned sites + one ring cell per thread
   constexpr int BW = TX + 4, BH = TY + 4;
   constexpr int CW = TX + 2, CH = TY + 2;
+  constexpr int NJ = Q == 9 ? CH * CW : 1;
   __shared__ R sphi[BH * BW];
   __shared__ R sP[CH * CW], sKx[CH * CW], sKy[CH * CW];
+  __shared__ R sJx[NJ], sJy[NJ];   // D2Q9: j_eq of the collision
 
   const int4 t = tiles[blockIdx.x];
   if (t.x < 0) return;
@@ -261,7 +291,7 @@ __global__ __launch_bounds__(NTHR) void k_phase(const Dom* __restrict__ doms, co
   // sites of this thread: RPT owned sites, then at most one ring cell
   int cl[NS];                 // collision-box index (-1: inactive)
   int bi[NS];                 // the same cell in the phi box
-  R sv[NS][4], Uv[NS], Tv[NS];
+  R sv[NS][Q - 1], Uv[NS], Tv[NS];
 #pragma unroll
   for (int r = 0; r < NS; ++r) {
     int lx, ly, gx, gy;
@@ -281,10 +311,8 @@ __global__ __launch_bounds__(NTHR) void k_phase(const Dom* __restrict__ doms, co
     cl[r] = ly * CW + lx;
     bi[r] = (ly + 1) * BW + lx + 1;
     const unsigned o = gy * px + gx;
-    sv[r][0] = ld(s_in, o);
-    sv[r][1] = ld(s_in, o + pl);
-    sv[r][2] = ld(s_in, o + 2 * pl);
-    sv[r][3] = ld(s_in, o + 3 * pl);
+#pragma unroll
+    for (int q = 0; q < Q - 1; ++q) sv[r][q] = ld(s_in, o + q * pl);
     Uv[r] = Up ? Up[o] + R(D.U0) : R(0);      // planes hold U - U0 and T - T0
     Tv[r] = Tp ? Tp[o] + R(D.T0) : c.theta_off;
   }
@@ -298,11 +326,23 @@ __global__ __launch_bounds__(NTHR) void k_phase(const Dom* __restrict__ doms, co
     const R* b = &sphi[bi[r]];
     R gx_, gy_;
     iso_grad(b, BW, gx_, gy_);
-    R dP, Kx, Ky, A;
-    phase_collide(c, b[0], gx_, gy_, sv[r][0] - sv[r][2], sv[r][1] - sv[r][3], Uv[r], Tv[r], dP, Kx, Ky, A);
+    R jx, jy;   // first moment of the deviations (the w_i phi part has none)
+    if constexpr (Q == 5) {
+      jx = sv[r][0] - sv[r][2];
+      jy = sv[r][1] - sv[r][3];
+    } else {
+      jx = sv[r][0] - sv[r][2] + sv[r][4] - sv[r][5] - sv[r][6] + sv[r][7];
+      jy = sv[r][1] - sv[r][3] + sv[r][4] + sv[r][5] - sv[r][6] - sv[r][7];
+    }
+    R dP, Kx, Ky, A, je[2];
+    phase_collide(c, b[0], gx_, gy_, jx, jy, Uv[r], Tv[r], dP, Kx, Ky, A, je);
     sP[cl[r]] = dP;
     sKx[cl[r]] = Kx;
     sKy[cl[r]] = Ky;
+    if constexpr (Q == 9) {
+      sJx[cl[r]] = je[0];
+      sJy[cl[r]] = je[1];
+    }
     if (r < RPT) Aown[r] = A;
   }
   __syncthreads();
@@ -319,34 +359,37 @@ __global__ __launch_bounds__(NTHR) void k_phase(const Dom* __restrict__ doms, co
     const R A = Aown[r], iA = rcp(A), oA = R(1) - A;
     const R phy = sphi[bc];
     const R dPo = sP[ci], Kxo = sKx[ci], Kyo = sKy[ci];
-    const R s0 = -(sv[r][0] + sv[r][1] + sv[r][2] + sv[r][3]);
-    // directions whose upstream node lies beyond a wall (bounce-back)
-    const bool wx = bcx != BC_PER, wy = bcy != BC_PER;
-    const bool bb[5] = {false, wx && gx == 0, wy && gy == 0, wx && gx == nx - 1, wy && gy == ny - 1};
-    R dn[5];
-    dn[0] = (dPo * R(1.0 / 3.0) - oA * s0) * iA;
+    R s0 = R(0);
 #pragma unroll
-    for (int q = 1; q < 5; ++q) {
-      const int ex = EX5(q), ey = EY5(q);
-      const bool wall = bb[q];
+    for (int q = 0; q < Q - 1; ++q) s0 -= sv[r][q];
+    const bool wx = bcx != BC_PER, wy = bcy != BC_PER;
+    R dn[Q];
+    dn[0] = (dPo * R(Lq::w(0)) - oA * s0) * iA;
+#pragma unroll
+    for (int q = 1; q < Q; ++q) {
+      const int ex = Lq::ex(q), ey = Lq::ey(q);
+      // upstream node beyond a wall: half-way bounce-back from this node
+      const int ux = gx - ex, uy = gy - ey;
+      const bool wall = (wx && (ux < 0 || ux >= nx)) || (wy && (uy < 0 || uy >= ny));
       R dpost;
       if (wall) {
-        dpost = dPo * R(1.0 / 6.0) - R(0.5) * (R(ex) * Kxo + R(ey) * Kyo);
+        dpost = dPo * R(Lq::w(q)) - R(Lq::cK) * (R(ex) * Kxo + R(ey) * Kyo);
+        if constexpr (Q == 9) dpost -= R(Lq::cJ(q)) * (R(ex) * sJx[ci] + R(ey) * sJy[ci]);
       } else {
         const int si = ci - ey * CW - ex;
         const R dphi = sphi[bc - ey * BW - ex] - phy;
-        dpost = (dphi + sP[si]) * R(1.0 / 6.0) + R(0.5) * (R(ex) * sKx[si] + R(ey) * sKy[si]);
+        dpost = (dphi + sP[si]) * R(Lq::w(q)) + R(Lq::cK) * (R(ex) * sKx[si] + R(ey) * sKy[si]);
+        if constexpr (Q == 9) dpost += R(Lq::cJ(q)) * (R(ex) * sJx[si] + R(ey) * sJy[si]);
       }
       dn[q] = (dpost - oA * sv[r][q - 1]) * iA;
     }
-    const R dphin = dn[0] + dn[1] + dn[2] + dn[3] + dn[4];
+    R dphin = dn[0];
+#pragma unroll
+    for (int q = 1; q < Q; ++q) dphin += dn[q];
     const unsigned o = gy * px + gx;
     phi_out[o] = phy + dphin;
-    const R w6 = dphin * R(1.0 / 6.0);
-    st(s_out, o, dn[1] - w6);
-    st(s_out, o + pl, dn[2] - w6);
-    st(s_out, o + 2 * pl, dn[3] - w6);
-    st(s_out, o + 3 * pl, dn[4] - w6);
+#pragma unroll
+    for (int q = 1; q < Q; ++q) st(s_out, o + (q - 1) * pl, dn[q] - dphin * R(Lq::w(q)));
   }
 }
 
@@ -355,9 +398,9 @@ __global__ __launch_bounds__(NTHR) void k_phase(const Dom* __restrict__ doms, co
 // dphi n^{q+1}; dU = ([1 + (1-k)U*] dphi - 2 div J) / kfac(phi^{q+1});
 // dT = rho_L L_h dphi / (2 rhoCp_eff(phi^{q+1})).  The compact divergence
 // uses the D2Q9-weighted stencil; ghost J across a wall is the mirror image
-// (normal component negated).  Instantaneous coupling adds dU to U (written
-// to the other U buffer because neighbours' U* are read) and dT to T in
-// place; the accumulated variant adds both to the pending planes.  Because
+// (normal component negated).  Instantaneous coupling adds dU to U and dT to
+// T, each written to the other buffer (neighbours' U* and T* are read); the
+// accumulated variant adds both to the pending planes.  Because
 // the U and T states are stored as (chi, j), adding w_i d to every
 // population is exactly adding d to chi.
 template <class R, int TY>
@@ -783,15 +826,18 @@ __global__ __launch_bounds__(NTHR) void k_phase_tr(const Dom* __restrict__ doms,
 // stencil; then the streaming of Eq. (25) with half-way bounce-back and the
 // reconstruction of chi and j.  The accumulated-coupling variant injects the
 // pending increments right after the transport.
-template <class R, class S, int TY, int FIELD>
+template <class R, class S, int TY, int FIELD, int Q>
 __global__ __launch_bounds__(NTHR) void k_scalar(const Dom* __restrict__ doms, const int4* __restrict__ tiles,
                                                   long long k, Partial* __restrict__ part) {
+  using Lq = Lat2<Q>;
   constexpr int RPT = TY / BY;
   constexpr int NS = RPT + 1;
   constexpr int BW = TX + 4, BH = TY + 4;
   constexpr int CW = TX + 2, CH = TY + 2;
   __shared__ R sphi[BH * BW];
   __shared__ R sC[CH * CW], sP[CH * CW], sKx[CH * CW], sKy[CH * CW];
+  constexpr int NJ = Q == 9 ? CH * CW : 1;
+  __shared__ R sJx[NJ], sJy[NJ];   // D2Q9: j_eq of the collision
   __shared__ R red[NTHR / 64];
 
   const int4 t = tiles[blockIdx.x];
@@ -872,7 +918,7 @@ __global__ __launch_bounds__(NTHR) void k_scalar(const Dom* __restrict__ doms, c
     const R* b = &sphi[bi[r]];
     const R ca = chi[r] + cref;   // the plane holds chi - chi_ref
     const R jex = ca * uxv[r] * dt, jey = ca * uyv[r] * dt;
-    R itau, Q = R(0);
+    R itau, Qs = R(0);
     if (FIELD == 0) {
       const R phi = b[0];
       const R ikf = rcp(opk - omk * phi);
@@ -881,7 +927,7 @@ __global__ __launch_bounds__(NTHR) void k_scalar(const Dom* __restrict__ doms, c
       const R gcx = -R(3) * itau * (jxv[r] - jex), gcy = -R(3) * itau * (jyv[r] - jey);  // Eq. (40)
       R gpx, gpy;
       iso_grad(b, BW, gpx, gpy);
-      Q = -omk * coeff * (gcx * gpx + gcy * gpy) * ikf;                          // Eq. (8), 1st term
+      Qs = -omk * coeff * (gcx * gpx + gcy * gpy) * ikf;                         // Eq. (8), 1st term
     } else if (D.T_var) {
       const R phi = b[0];
       const R irc = rcp((R(1) + phi) * R(0.5) * rcS + (R(1) - phi) * R(0.5) * rcL);
@@ -890,15 +936,19 @@ __global__ __launch_bounds__(NTHR) void k_scalar(const Dom* __restrict__ doms, c
       const R gcx = -R(3) * itau * (jxv[r] - jex), gcy = -R(3) * itau * (jyv[r] - jey);
       R gpx, gpy;
       iso_grad(b, BW, gpx, gpy);
-      Q = (rcS - rcL) * R(0.5) * irc * coeff * (gcx * gpx + gcy * gpy);         // Eq. (12), 1st term
+      Qs = (rcS - rcL) * R(0.5) * irc * coeff * (gcx * gpx + gcy * gpy);        // Eq. (12), 1st term
     } else {
       itau = itau_const;
     }
     const R om = R(1) - itau;
     sC[cl[r]] = chi[r];
-    sP[cl[r]] = dt * Q;
+    sP[cl[r]] = dt * Qs;
     sKx[cl[r]] = jex + om * (jxv[r] - jex);
     sKy[cl[r]] = jey + om * (jyv[r] - jey);
+    if constexpr (Q == 9) {
+      sJx[cl[r]] = jex;
+      sJy[cl[r]] = jey;
+    }
   }
   __syncthreads();
 
@@ -911,32 +961,47 @@ __global__ __launch_bounds__(NTHR) void k_scalar(const Dom* __restrict__ doms, c
     const int gx = x0 + tx, gy = y0 + ty + r * BY;
     const R cy = sC[ci], dPo = sP[ci], Kxo = sKx[ci], Kyo = sKy[ci];
     const bool wx = bcx != BC_PER, wy = bcy != BC_PER;
-    const bool bb[5] = {false, wx && gx == 0, wy && gy == 0, wx && gx == nx - 1, wy && gy == ny - 1};
-    R dq[5];
-    dq[0] = dPo * R(1.0 / 3.0);
+    R dq[Q];
+    dq[0] = dPo * R(Lq::w(0));
 #pragma unroll
-    for (int q = 1; q < 5; ++q) {
-      const int ex = EX5(q), ey = EY5(q);
-      if (bb[q] && FIELD == 1 && D.T_dirlow && q == 2) {
+    for (int q = 1; q < Q; ++q) {
+      const int ex = Lq::ex(q), ey = Lq::ey(q);
+      const int ux = gx - ex, uy = gy - ey;   // upstream node
+      const bool wall = (wx && (ux < 0 || ux >= nx)) || (wy && (uy < 0 || uy >= ny));
+      if (FIELD == 1 && D.T_dirlow && ey > 0 && gy == 0) {
         // anti-bounce-back to T0 at the wall y = -1/2 (the plane holds T - T0)
-        dq[q] = -(R(2) * cy + dPo) * R(1.0 / 6.0) + R(0.5) * (R(ex) * Kxo + R(ey) * Kyo);
-      } else if (bb[q]) {
-        dq[q] = dPo * R(1.0 / 6.0) - R(0.5) * (R(ex) * Kxo + R(ey) * Kyo);
+        dq[q] = -(R(2) * cy + dPo) * R(Lq::w(q)) + R(Lq::cK) * (R(ex) * Kxo + R(ey) * Kyo);
+        if constexpr (Q == 9) dq[q] += R(Lq::cJ(q)) * (R(ex) * sJx[ci] + R(ey) * sJy[ci]);
+      } else if (wall) {
+        dq[q] = dPo * R(Lq::w(q)) - R(Lq::cK) * (R(ex) * Kxo + R(ey) * Kyo);
+        if constexpr (Q == 9) dq[q] -= R(Lq::cJ(q)) * (R(ex) * sJx[ci] + R(ey) * sJy[ci]);
       } else {
         const int si = ci - ey * CW - ex;
-        dq[q] = (sC[si] - cy + sP[si]) * R(1.0 / 6.0) + R(0.5) * (R(ex) * sKx[si] + R(ey) * sKy[si]);
+        dq[q] = (sC[si] - cy + sP[si]) * R(Lq::w(q)) + R(Lq::cK) * (R(ex) * sKx[si] + R(ey) * sKy[si]);
+        if constexpr (Q == 9) dq[q] += R(Lq::cJ(q)) * (R(ex) * sJx[si] + R(ey) * sJy[si]);
       }
     }
     const unsigned o = gy * px + gx;
-    R chin = cy + (dq[0] + dq[1] + dq[2] + dq[3] + dq[4]);
+    R sum = dq[0];
+#pragma unroll
+    for (int q = 1; q < Q; ++q) sum += dq[q];
+    R chin = cy + sum;
     if (D.accum) {
       chin += pv[r];
       pend[o] = R(0);
       amax = fmax(amax, fabs(pv[r]));
     }
     cout[o] = chin;
-    st(jout, o, dq[1] - dq[3]);
-    st(jout, o + pl, dq[2] - dq[4]);
+    R jx = R(0), jy = R(0);
+#pragma unroll
+    for (int q = 1; q < Q; ++q) {
+      if (Lq::ex(q) > 0) jx += dq[q];
+      if (Lq::ex(q) < 0) jx -= dq[q];
+      if (Lq::ey(q) > 0) jy += dq[q];
+      if (Lq::ey(q) < 0) jy -= dq[q];
+    }
+    st(jout, o, jx);
+    st(jout, o + pl, jy);
   }
   if (FIELD == 0 && D.accum && part) {
     for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_down(amax, off, 64));
@@ -955,8 +1020,6 @@ __global__ __launch_bounds__(NTHR) void k_scalar(const Dom* __restrict__ doms, c
 // bounce-back of Eq. (33) in pull form with f_L = (1 - phi*)/2, inlet
 // equilibrium at x = 0 and zero-gradient outflow at x = nx - 1 when the x
 // boundary is inlet/outflow.
-#define EX9(q) ((q) == 1 || (q) == 5 || (q) == 8 ? 1 : (q) == 3 || (q) == 6 || (q) == 7 ? -1 : 0)
-#define EY9(q) ((q) == 2 || (q) == 5 || (q) == 6 ? 1 : (q) == 4 || (q) == 7 || (q) == 8 ? -1 : 0)
 #define OPP9(q) ((q) == 0 ? 0 : (q) <= 4 ? (((q) + 1) & 3) + 1 : (((q) - 3) & 3) + 5)
 
 template <class R>
@@ -1182,7 +1245,7 @@ __global__ void k_init(const Dom* __restrict__ doms, int dom, const double* __re
   const R ph = R(phi);
   (gp<R>(D.phi[0]))[o] = ph;
   (gp<R>(D.phi[1]))[o] = ph;
-  for (int q = 0; q < 4; ++q) {
+  for (int q = 0; q < D.qs - 1; ++q) {
     st(gp<S>(D.sphi[0]), o + q * pl, R(0));
     st(gp<S>(D.sphi[1]), o + q * pl, R(0));
   }
@@ -1224,7 +1287,7 @@ __global__ void k_init(const Dom* __restrict__ doms, int dom, const double* __re
 
 // =================================================================== read / write
 // Plane codes: 0 phi, 1 U, 2 T, 3 rho, 4 ux, 5 uy, 8 U - U0, 9 T - T0
-// (the stored planes), 10..14 phase f_0..f_4,
+// (the stored planes), 10..14 phase f_0..f_4 (10..18 in D2Q9),
 // 20/21 jU, 30/31 jT, 40..48 flow f_0..f_8, 50 pending U, 51 pending T,
 // 60..63 stored phase planes s_1..s_4, 70..77 stored flow planes s_1..s_8.
 template <class R, class S>
@@ -1245,17 +1308,22 @@ __device__ double read_plane(const Dom& D, long long k, int code, long long o) {
     case 51: return double((gp<const R>(D.PT))[o]);
     default: break;
   }
-  if (code >= 60 && code <= 63) return double(ld(gp<const S>(D.sphi[par(n_phi(D, k))]), o + (code - 60) * pl));
+  if (code >= 60 && code < 60 + D.qs - 1)
+    return double(ld(gp<const S>(D.sphi[par(n_phi(D, k))]), o + (code - 60) * pl));
   if (code >= 70 && code <= 77) return double(ld(gp<const S>(D.sF[par(n_F(D, k))]), o + (code - 70) * pl));
-  if (code >= 10 && code <= 14) {
+  if (code >= 10 && code < 10 + D.qs) {
     const int b = par(n_phi(D, k));
     GLOBAL const R* ph = gp<const R>(D.phi[b]);
     GLOBAL const S* s = gp<const S>(D.sphi[b]);
     const R phi = ph[o];
-    const R s1 = ld(s, o), s2 = ld(s, o + pl), s3 = ld(s, o + 2 * pl), s4 = ld(s, o + 3 * pl);
-    if (code == 10) return double(phi * R(1.0 / 3.0) - (s1 + s2 + s3 + s4));
-    const R sv[4] = {s1, s2, s3, s4};
-    return double(phi * R(1.0 / 6.0) + sv[code - 11]);
+    const bool q9 = D.qs == 9;
+    if (code == 10) {
+      R ssum = R(0);
+      for (int q = 0; q < D.qs - 1; ++q) ssum += ld(s, o + q * pl);
+      return double(phi * R(q9 ? 4.0 / 9.0 : 1.0 / 3.0) - ssum);
+    }
+    const int q = code - 10;
+    return double(phi * R(q9 ? (q <= 4 ? 1.0 / 9.0 : 1.0 / 36.0) : 1.0 / 6.0) + ld(s, o + (q - 1) * pl));
   }
   if (code >= 40 && code <= 48) {
     const int b = par(n_F(D, k));
@@ -1318,8 +1386,8 @@ __global__ void k_write(const Dom* __restrict__ doms, int dom, long long k, cons
       case 30: case 31: st(gp<S>(D.jT[par(n_jT(D, k))]), o + (code - 30) * pl, R(v)); break;
       case 50: (gp<R>(D.PU))[o] = R(v); break;
       case 51: (gp<R>(D.PT))[o] = R(v); break;
-      case 60: case 61: case 62: case 63:
-        st(gp<S>(D.sphi[par(n_phi(D, k))]), o + (code - 60) * pl, R(v));
+      case 60: case 61: case 62: case 63: case 64: case 65: case 66: case 67:
+        if (code < 60 + D.qs - 1) st(gp<S>(D.sphi[par(n_phi(D, k))]), o + (code - 60) * pl, R(v));
         break;
       case 70: case 71: case 72: case 73: case 74: case 75: case 76: case 77:
         st(gp<S>(D.sF[par(n_F(D, k))]), o + (code - 70) * pl, R(v));
@@ -1332,14 +1400,16 @@ __global__ void k_write(const Dom* __restrict__ doms, int dom, long long k, cons
   }
   if (cphi >= 0) {
     const int b = par(n_phi(D, k));
-    R f[5];
+    const bool q9 = D.qs == 9;
+    R f[9];
     R phi = R(0);
-    for (int q = 0; q < 5; ++q) {
+    for (int q = 0; q < D.qs; ++q) {
       f[q] = R(src[(cphi + q) * n + i]);
       phi += f[q];
     }
     (gp<R>(D.phi[b]))[o] = phi;
-    for (int q = 1; q < 5; ++q) st(gp<S>(D.sphi[b]), o + (q - 1) * pl, f[q] - phi * R(1.0 / 6.0));
+    for (int q = 1; q < D.qs; ++q)
+      st(gp<S>(D.sphi[b]), o + (q - 1) * pl, f[q] - phi * R(q9 ? (q <= 4 ? 1.0 / 9.0 : 1.0 / 36.0) : 1.0 / 6.0));
   }
   if (cflow >= 0) {
     const int b = par(n_F(D, k));
@@ -1549,17 +1619,30 @@ __host__ __device__ constexpr double w19(int q) { return q == 0 ? 1.0 / 3 : q <=
 
 struct Site3 {
   int x, y, z;
-  unsigned o;
+  unsigned o;        // offset in a plane (pitch px)
+  long long lin;     // x + nx (y + ny z), the packed index of read / write
 };
 
-__device__ __forceinline__ bool site3(const Dom& D, long long i, Site3& s) {
-  const long long n = (long long)D.nx * D.ny * D.nz;
-  if (i >= n) return false;
-  s.x = (int)(i % D.nx);
-  const long long t = i / D.nx;
-  s.y = (int)(t % D.ny);
-  s.z = (int)(t / D.ny);
+// A block of 256 threads covers 64 x 4 sites of one z plane (x fastest, so
+// plane accesses are coalesced rows).  Blocks are dispatched round-robin
+// over the 8 XCDs (block b on XCD b mod 8); the columns of tiles are dealt
+// to the XCDs and the consecutive blocks of one XCD step up in z through
+// the same column, so the z neighbours a block reads were written by the
+// same XCD just before and are still in its L2.  The grid has
+// pad8(ntx nty) nz blocks (Launch3::blocks); padding blocks have no sites.
+__device__ __forceinline__ bool site3(const Dom& D, unsigned b, unsigned t, Site3& s) {
+  const unsigned ntx = (unsigned)(D.nx + 63) >> 6, nty = (unsigned)(D.ny + 3) >> 2;
+  const unsigned r = b >> 3;
+  const unsigned col = (b & 7u) + 8u * (r / (unsigned)D.nz);
+  if (col >= ntx * nty) return false;
+  const int x = (int)(col % ntx) * 64 + (int)(t & 63u);
+  const int y = (int)(col / ntx) * 4 + (int)(t >> 6);
+  if (x >= D.nx || y >= D.ny) return false;
+  s.x = x;
+  s.y = y;
+  s.z = (int)(r % (unsigned)D.nz);
   s.o = (unsigned)(((long long)s.z * D.ny + s.y) * D.px + s.x);
+  s.lin = ((long long)s.z * D.ny + s.y) * D.nx + s.x;
   return true;
 }
 
@@ -1641,7 +1724,7 @@ template <class R, class S>
 __global__ __launch_bounds__(256) void k3_phase_collide(const Dom* __restrict__ doms, long long k) {
   const Dom& D = doms[0];
   Site3 s;
-  if (!site3(D, (long long)blockIdx.x * 256 + threadIdx.x, s) || k % D.N_phi) return;
+  if (!site3(D, blockIdx.x, threadIdx.x, s) || k % D.N_phi) return;
   const unsigned pl = (unsigned)D.plane;
   const int ib = par(n_phi(D, k - 1));
   GLOBAL const R* phi = gp<const R>(D.phi[ib]);
@@ -1671,7 +1754,7 @@ template <class R, class S>
 __global__ __launch_bounds__(256) void k3_phase_stream(const Dom* __restrict__ doms, long long k) {
   const Dom& D = doms[0];
   Site3 s;
-  if (!site3(D, (long long)blockIdx.x * 256 + threadIdx.x, s) || k % D.N_phi) return;
+  if (!site3(D, blockIdx.x, threadIdx.x, s) || k % D.N_phi) return;
   const unsigned pl = (unsigned)D.plane;
   const int ib = par(n_phi(D, k - 1)), ob = ib ^ 1;
   GLOBAL const R* phi = gp<const R>(D.phi[ib]);
@@ -1714,7 +1797,7 @@ template <class R>
 __global__ __launch_bounds__(256) void k3_transfer_J(const Dom* __restrict__ doms, long long k) {
   const Dom& D = doms[0];
   Site3 s;
-  if (!site3(D, (long long)blockIdx.x * 256 + threadIdx.x, s) || k % D.N_phi || !D.has_U) return;
+  if (!site3(D, blockIdx.x, threadIdx.x, s) || k % D.N_phi || !D.has_U) return;
   const unsigned pl = (unsigned)D.plane;
   GLOBAL const R* pn = gp<const R>(D.phi[par(n_phi(D, k))]);
   GLOBAL const R* po = gp<const R>(D.phi[par(n_phi(D, k - 1))]);
@@ -1743,7 +1826,7 @@ __global__ __launch_bounds__(256) void k3_transfer_apply(const Dom* __restrict__
   __shared__ R red[4];
   const Dom& D = doms[0];
   Site3 s;
-  const bool ok = site3(D, (long long)blockIdx.x * 256 + threadIdx.x, s);
+  const bool ok = site3(D, blockIdx.x, threadIdx.x, s);
   if (k % D.N_phi) return;
   const unsigned pl = (unsigned)D.plane;
   GLOBAL const R* pn = gp<const R>(D.phi[par(n_phi(D, k))]);
@@ -1808,7 +1891,7 @@ __global__ __launch_bounds__(256) void k3_scalar_collide(const Dom* __restrict__
   const Dom& D = doms[0];
   const int N = FIELD == 0 ? D.N_U : D.N_T;
   Site3 s;
-  if (!site3(D, (long long)blockIdx.x * 256 + threadIdx.x, s) || k % N) return;
+  if (!site3(D, blockIdx.x, threadIdx.x, s) || k % N) return;
   const unsigned pl = (unsigned)D.plane;
   GLOBAL const R* cin;
   GLOBAL const S* jin;
@@ -1875,7 +1958,7 @@ __global__ __launch_bounds__(256) void k3_scalar_stream(const Dom* __restrict__ 
   const Dom& D = doms[0];
   const int N = FIELD == 0 ? D.N_U : D.N_T;
   Site3 s;
-  const bool ok = site3(D, (long long)blockIdx.x * 256 + threadIdx.x, s);
+  const bool ok = site3(D, blockIdx.x, threadIdx.x, s);
   if (k % N) return;
   const unsigned pl = (unsigned)D.plane;
   GLOBAL const R* cin;
@@ -1998,7 +2081,7 @@ template <class R, class S>
 __global__ __launch_bounds__(256) void k3_flow_collide(const Dom* __restrict__ doms, long long k) {
   const Dom& D = doms[0];
   Site3 s;
-  if (!site3(D, (long long)blockIdx.x * 256 + threadIdx.x, s) || k % D.N_F) return;
+  if (!site3(D, blockIdx.x, threadIdx.x, s) || k % D.N_F) return;
   const unsigned pl = (unsigned)D.plane;
   const int ib = par(n_F(D, k - 1));
   const R rho = (gp<const R>(D.rho[ib]))[s.o];
@@ -2054,7 +2137,7 @@ template <class R, class S>
 __global__ __launch_bounds__(256) void k3_flow_stream(const Dom* __restrict__ doms, long long k) {
   const Dom& D = doms[0];
   Site3 s;
-  if (!site3(D, (long long)blockIdx.x * 256 + threadIdx.x, s) || k % D.N_F) return;
+  if (!site3(D, blockIdx.x, threadIdx.x, s) || k % D.N_F) return;
   const unsigned pl = (unsigned)D.plane;
   GLOBAL const R* rin = gp<const R>(D.rho[par(n_F(D, k - 1))]);
   GLOBAL const R* phis = gp<const R>(D.phi[par(n_phi(D, k))]);
@@ -2099,7 +2182,7 @@ template <class R, class S>
 __global__ void k3_init(const Dom* __restrict__ doms, const double* __restrict__ xi) {
   const Dom& D = doms[0];
   Site3 s;
-  if (!site3(D, (long long)blockIdx.x * 256 + threadIdx.x, s)) return;
+  if (!site3(D, blockIdx.x, threadIdx.x, s)) return;
   const unsigned pl = (unsigned)D.plane;
   const double off = xi ? xi[(long long)s.y * D.nx + s.x] : 0.0;
   const double phi = tanh((D.z_front + off - s.z) / (1.4142135623730951 * D.W0));
@@ -2186,10 +2269,9 @@ __global__ void k3_read(const Dom* __restrict__ doms, long long k, const int* __
                         int out_f64, void* __restrict__ out) {
   const Dom& D = doms[0];
   Site3 s;
-  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
   const int c = blockIdx.y;
-  if (c >= ncodes || !site3(D, i, s)) return;
-  const long long n = (long long)D.nx * D.ny * D.nz;
+  if (c >= ncodes || !site3(D, blockIdx.x, threadIdx.x, s)) return;
+  const long long n = (long long)D.nx * D.ny * D.nz, i = s.lin;
   const double v = read_plane3<R, S>(D, k, codes[c], s.o);
   if (out_f64)
     ((double*)out)[c * n + i] = v;
@@ -2202,9 +2284,8 @@ __global__ void k3_write(const Dom* __restrict__ doms, long long k, const int* _
                          const double* __restrict__ src) {
   const Dom& D = doms[0];
   Site3 s;
-  const long long i = (long long)blockIdx.x * 256 + threadIdx.x;
-  if (!site3(D, i, s)) return;
-  const long long n = (long long)D.nx * D.ny * D.nz;
+  if (!site3(D, blockIdx.x, threadIdx.x, s)) return;
+  const long long n = (long long)D.nx * D.ny * D.nz, i = s.lin;
   const unsigned o = s.o, pl = (unsigned)D.plane;
   int cphi = -1, cflow = -1;
   for (int c = 0; c < ncodes; ++c) {
@@ -2255,7 +2336,7 @@ __global__ __launch_bounds__(256) void k3_diag(const Dom* __restrict__ doms, lon
   const Dom& D = doms[0];
   Site3 s;
   double a[5] = {0, 0, 0, 0, 0};
-  if (site3(D, (long long)blockIdx.x * 256 + threadIdx.x, s)) {
+  if (site3(D, blockIdx.x, threadIdx.x, s)) {
     const double p = double((gp<const R>(D.phi[par(n_phi(D, k))]))[s.o]);
     a[0] = (1.0 + p) * 0.5;
     bool bad = !isfinite(p);
@@ -2339,7 +2420,10 @@ __global__ void k3_set_koff(Dom* __restrict__ doms, long long koff) {
 
 template <class R, class S>
 struct Launch3 {
-  static unsigned blocks(const Dom& h) { return (unsigned)(((long long)h.nx * h.ny * h.nz + 255) / 256); }
+  static unsigned blocks(const Dom& h) {
+    const long long cols = (long long)((h.nx + 63) / 64) * ((h.ny + 3) / 4);
+    return (unsigned)((cols + 7) / 8 * 8 * h.nz);
+  }
   static void phase(const Dom& h, hipStream_t st, const Dom* d, long long k) {
     k3_phase_collide<R, S><<<blocks(h), 256, 0, st>>>(d, k);
     k3_phase_stream<R, S><<<blocks(h), 256, 0, st>>>(d, k);
@@ -2397,12 +2481,20 @@ template struct Launch3<float, __hip_bfloat16>;
 template <class R, class S>
 struct Launch {
   // TY selects the tile height: 4, 8, 16 or 32 rows
-  static void phase(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k) {
+  // Q: scalar lattice, 5 (D2Q5) or 9 (D2Q9)
+  static void phase(int TY, int Q, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k) {
     const dim3 b(TX, BY);
-    if (TY == 4) k_phase<R, S, 4><<<g, b, 0, st>>>(d, t, k);
-    else if (TY == 8) k_phase<R, S, 8><<<g, b, 0, st>>>(d, t, k);
-    else if (TY == 16) k_phase<R, S, 16><<<g, b, 0, st>>>(d, t, k);
-    else k_phase<R, S, 32><<<g, b, 0, st>>>(d, t, k);
+    if (Q == 9) {
+      if (TY == 4) k_phase<R, S, 4, 9><<<g, b, 0, st>>>(d, t, k);
+      else if (TY == 8) k_phase<R, S, 8, 9><<<g, b, 0, st>>>(d, t, k);
+      else if (TY == 16) k_phase<R, S, 16, 9><<<g, b, 0, st>>>(d, t, k);
+      else k_phase<R, S, 32, 9><<<g, b, 0, st>>>(d, t, k);
+      return;
+    }
+    if (TY == 4) k_phase<R, S, 4, 5><<<g, b, 0, st>>>(d, t, k);
+    else if (TY == 8) k_phase<R, S, 8, 5><<<g, b, 0, st>>>(d, t, k);
+    else if (TY == 16) k_phase<R, S, 16, 5><<<g, b, 0, st>>>(d, t, k);
+    else k_phase<R, S, 32, 5><<<g, b, 0, st>>>(d, t, k);
   }
   // phase + transfer in one kernel: 8-row tiles in FP64 (LDS), 8 or 16 otherwise
   static int phase_tr_rows(int TY) { return sizeof(R) == 8 ? 8 : (TY >= 16 ? 16 : 8); }
@@ -2423,17 +2515,25 @@ struct Launch {
     else k_transfer<R, 32><<<g, b, 0, st>>>(d, t, k, p);
   }
   template <int F>
-  static void scalar_f(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k, Partial* p) {
+  static void scalar_f(int TY, int Q, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k,
+                       Partial* p) {
     const dim3 b(TX, BY);
-    if (TY == 4) k_scalar<R, S, 4, F><<<g, b, 0, st>>>(d, t, k, p);
-    else if (TY == 8) k_scalar<R, S, 8, F><<<g, b, 0, st>>>(d, t, k, p);
-    else if (TY == 16) k_scalar<R, S, 16, F><<<g, b, 0, st>>>(d, t, k, p);
-    else k_scalar<R, S, 32, F><<<g, b, 0, st>>>(d, t, k, p);
+    if (Q == 9) {
+      if (TY == 4) k_scalar<R, S, 4, F, 9><<<g, b, 0, st>>>(d, t, k, p);
+      else if (TY == 8) k_scalar<R, S, 8, F, 9><<<g, b, 0, st>>>(d, t, k, p);
+      else if (TY == 16) k_scalar<R, S, 16, F, 9><<<g, b, 0, st>>>(d, t, k, p);
+      else k_scalar<R, S, 32, F, 9><<<g, b, 0, st>>>(d, t, k, p);
+      return;
+    }
+    if (TY == 4) k_scalar<R, S, 4, F, 5><<<g, b, 0, st>>>(d, t, k, p);
+    else if (TY == 8) k_scalar<R, S, 8, F, 5><<<g, b, 0, st>>>(d, t, k, p);
+    else if (TY == 16) k_scalar<R, S, 16, F, 5><<<g, b, 0, st>>>(d, t, k, p);
+    else k_scalar<R, S, 32, F, 5><<<g, b, 0, st>>>(d, t, k, p);
   }
-  static void scalar(int field, int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k,
+  static void scalar(int field, int TY, int Q, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k,
                      Partial* p) {
-    if (field == 0) scalar_f<0>(TY, g, st, d, t, k, p);
-    else scalar_f<1>(TY, g, st, d, t, k, p);
+    if (field == 0) scalar_f<0>(TY, Q, g, st, d, t, k, p);
+    else scalar_f<1>(TY, Q, g, st, d, t, k, p);
   }
   static void flow(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k) {
     constexpr int SUB = sizeof(R) == 8 ? 8 : 16;

@@ -26,11 +26,11 @@
 namespace lbm {
 template <class R, class S>
 struct Launch {
-  static void phase(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k);
+  static void phase(int TY, int Q, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k);
   static void transfer(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k, Partial* p);
   static int phase_tr_rows(int TY);
   static void phase_tr(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k, Partial* p);
-  static void scalar(int field, int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k,
+  static void scalar(int field, int TY, int Q, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k,
                      Partial* p);
   static void flow(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k);
   static void diag_tiles(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k, Partial* p);
@@ -83,11 +83,11 @@ struct Group {
 };
 
 struct Ops {
-  void (*phase)(int, dim3, hipStream_t, const Dom*, const int4*, long long);
+  void (*phase)(int, int, dim3, hipStream_t, const Dom*, const int4*, long long);
   void (*transfer)(int, dim3, hipStream_t, const Dom*, const int4*, long long, Partial*);
   void (*phase_tr)(int, dim3, hipStream_t, const Dom*, const int4*, long long, Partial*);
   int (*phase_tr_rows)(int);
-  void (*scalar)(int, int, dim3, hipStream_t, const Dom*, const int4*, long long, Partial*);
+  void (*scalar)(int, int, int, dim3, hipStream_t, const Dom*, const int4*, long long, Partial*);
   void (*flow)(int, dim3, hipStream_t, const Dom*, const int4*, long long);
   void (*diag_tiles)(int, dim3, hipStream_t, const Dom*, const int4*, long long, Partial*);
   void (*tips)(int, hipStream_t, const Dom*, long long, DiagOut*);
@@ -164,7 +164,8 @@ struct lbm_ctx {
   bool autotune = true;
   bool use_graph = true;
   bool fuse = false;      // phase + transfer in one kernel (2D) when every domain allows it
-  bool fusable = false;   // every domain at least 8 x 8 (the fused kernel's rings wrap once at most)
+  bool fusable = false;   // every domain at least 8 x 8 (the fused kernel's rings wrap once at most), D2Q5
+  int qs = 5;             // scalar lattice of the (2D) context: 5 or 9
   hipGraphExec_t gexec = nullptr;
   int graph_ty = -1;
   long long cycle = 1;
@@ -201,7 +202,7 @@ Layout layout_of(const lbm_params& p) {
   Layout L;
   const int d = p.dim;
   L.rplanes = 2;                           // phi, two buffers
-  L.splanes = 2 * (d == 3 ? 6 : 4);        // phase s_i, two buffers
+  L.splanes = 2 * (p.q_scalar - 1);        // phase s_i, two buffers
   if (p.has_U) { L.rplanes += 3; L.splanes += 2 * d; }
   if (p.has_T) { L.rplanes += 3; L.splanes += 2 * d; }
   if (p.has_flow) { L.rplanes += 2 + 2 * d; L.splanes += 2 * (d == 3 ? 18 : 8); }
@@ -210,7 +211,12 @@ Layout layout_of(const lbm_params& p) {
 }
 
 long long sites_of(const lbm_params& p) { return (long long)p.nx * p.ny * (p.dim == 3 ? p.nz : 1); }
-long long blocks3(const lbm_params& p) { return (sites_of(p) + 255) / 256; }
+// 3D grid: one block per 64 x 4 tile of a z plane, tile columns padded to a
+// multiple of the 8 XCDs (the mapping of the 3D kernels)
+long long blocks3(const lbm_params& p) {
+  const long long cols = (long long)((p.nx + 63) / 64) * ((p.ny + 3) / 4);
+  return (cols + 7) / 8 * 8 * p.nz;
+}
 
 size_t sizes_of(int storage, size_t& rsz, size_t& ssz) {
   rsz = storage == LBM_STORE_F64 ? 8 : 4;
@@ -231,7 +237,8 @@ std::string validate(const lbm_params& p, int i) {
   // in-plane offsets (up to 18 planes apart) are 32-bit unsigned in the kernels
   if ((long long)((p.nx + 63) / 64 * 64) * p.ny * (p.dim == 3 ? p.nz : 1) > (1LL << 27))
     return bad("more than 2^27 sites in one domain");
-  if (p.dim == 2 && p.q_scalar != 5) return bad("2D scalar lattice must be D2Q5 (q_scalar = 5)");
+  if (p.dim == 2 && p.q_scalar != 5 && p.q_scalar != 9)
+    return bad("2D scalar lattice must be D2Q5 or D2Q9 (q_scalar = 5 or 9)");
   if (p.dim == 3 && p.q_scalar != 7) return bad("3D scalar lattice must be D3Q7 (q_scalar = 7)");
   if (p.dim == 3) {
     for (int a = 0; a < 3; ++a)
@@ -320,14 +327,14 @@ static void launch_step(lbm_ctx* c, hipStream_t st, long long k) {
       if (fused) {
         c->ops.phase_tr(kTYs[tf], dim3(g.ts[tf].n), st, c->d_dom, g.ts[tf].d, k, c->d_part);
       } else {
-        c->ops.phase(TY, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k);
+        c->ops.phase(TY, c->qs, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k);
         c->ops.transfer(TY, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k, c->d_part);
       }
     }
   for (auto& g : c->g_U)
-    if (k % g.N == 0) c->ops.scalar(0, TY, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k, c->d_part);
+    if (k % g.N == 0) c->ops.scalar(0, TY, c->qs, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k, c->d_part);
   for (auto& g : c->g_T)
-    if (k % g.N == 0) c->ops.scalar(1, TY, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k, c->d_part);
+    if (k % g.N == 0) c->ops.scalar(1, TY, c->qs, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k, c->d_part);
   for (auto& g : c->g_F)
     if (k % g.N == 0) c->ops.flow(TY, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k);
 }
@@ -362,7 +369,7 @@ static lbm_status autotune(lbm_ctx* c) {
         if (fused)
           c->ops.phase_tr(kTYs[tf], dim3(g.ts[tf].n), c->stream, c->d_dom, g.ts[tf].d, next_due(g.N), nullptr);
         else
-          c->ops.phase(TY, dim3(g.ts[ti].n), c->stream, c->d_dom, g.ts[ti].d, next_due(g.N));
+          c->ops.phase(TY, c->qs, dim3(g.ts[ti].n), c->stream, c->d_dom, g.ts[ti].d, next_due(g.N));
       }
       // (the U and T transports are not timed: with instantaneous coupling
       // the transfer of the same step also writes their planes, so the
@@ -401,7 +408,7 @@ size_t lbm_workspace_bytes(const lbm_params* p, int32_t n, int32_t storage) {
   size_t maxsites = 0;
   for (int i = 0; i < n; ++i) {
     if (!validate(p[i], i).empty()) return 0;
-    if (p[i].dim == 3 && n != 1) return 0;
+    if ((p[i].dim == 3 && n != 1) || p[i].q_scalar != p[0].q_scalar) return 0;
     const size_t plane = (size_t)px_of(p[i].nx) * p[i].ny * (p[i].dim == 3 ? p[i].nz : 1);
     const Layout L = layout_of(p[i]);
     total += align256(plane * rsz) * L.rplanes + align256(plane * ssz) * L.splanes;
@@ -428,8 +435,10 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
   if (!out) return fail(nullptr, LBM_EINVAL, "out is NULL");
   *out = nullptr;
   if (!p || n < 1) return fail(nullptr, LBM_EINVAL, "no domains");
-  for (int i = 0; i < n; ++i)
+  for (int i = 0; i < n; ++i) {
     if (p[i].dim == 3 && n != 1) return fail(nullptr, LBM_EINVAL, "3D contexts hold one domain");
+    if (p[i].q_scalar != p[0].q_scalar) return fail(nullptr, LBM_EINVAL, "the domains of a context share one scalar lattice");
+  }
   if (storage < 0 || storage > 3) return fail(nullptr, LBM_EINVAL, "bad storage format");
   for (int i = 0; i < n; ++i) {
     const std::string m = validate(p[i], i);
@@ -541,11 +550,12 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
     D.U0 = q.U0;
     D.T0 = q.T0;
     D.u0_liquid = q.u0_liquid_only;
+    D.qs = q.q_scalar;
     const size_t pr = D.plane * c->rsz, ps = D.plane * c->ssz;
     const int d3 = q.dim == 3;
     for (int b = 0; b < 2; ++b) {
       D.phi[b] = take(pr);
-      D.sphi[b] = take(align256(ps) * (d3 ? 6 : 4));
+      D.sphi[b] = take(align256(ps) * (q.q_scalar - 1));
     }
     if (q.has_U) {
       for (int b = 0; b < 2; ++b) {
@@ -574,8 +584,9 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
     if (q.has_T) lcm = ipow_lcm(lcm, q.N_T);
     if (q.has_flow) lcm = ipow_lcm(lcm, q.N_F);
   }
+  c->qs = p[0].q_scalar;
   c->fusable = true;
-  for (int i = 0; i < n; ++i) c->fusable &= p[i].dim == 2 && p[i].nx >= 8 && p[i].ny >= 8;
+  for (int i = 0; i < n; ++i) c->fusable &= p[i].dim == 2 && p[i].q_scalar == 5 && p[i].nx >= 8 && p[i].ny >= 8;
   c->cycle = 2 * lcm;
   c->d_dom = (Dom*)take(sizeof(Dom) * n);
 
@@ -826,10 +837,10 @@ lbm_status lbm_kernel_times(lbm_ctx* c, int32_t reps, double* ms_out, double* pe
           const int tf = ty_slot(c->ops.phase_tr_rows(TY));
           c->ops.phase_tr(kTYs[tf], dim3(g.ts[tf].n), c->stream, c->d_dom, g.ts[tf].d, k, c->d_part);
         }
-        if (kind == 0 && !fused) c->ops.phase(TY, grid, c->stream, c->d_dom, g.ts[ti].d, k);
+        if (kind == 0 && !fused) c->ops.phase(TY, c->qs, grid, c->stream, c->d_dom, g.ts[ti].d, k);
         if (kind == 1) c->ops.transfer(TY, grid, c->stream, c->d_dom, g.ts[ti].d, k, c->d_part);
-        if (kind == 2) c->ops.scalar(0, TY, grid, c->stream, c->d_dom, g.ts[ti].d, k, c->d_part);
-        if (kind == 3) c->ops.scalar(1, TY, grid, c->stream, c->d_dom, g.ts[ti].d, k, c->d_part);
+        if (kind == 2) c->ops.scalar(0, TY, c->qs, grid, c->stream, c->d_dom, g.ts[ti].d, k, c->d_part);
+        if (kind == 3) c->ops.scalar(1, TY, c->qs, grid, c->stream, c->d_dom, g.ts[ti].d, k, c->d_part);
         if (kind == 4) c->ops.flow(TY, grid, c->stream, c->d_dom, g.ts[ti].d, k);
       };
       launch();
@@ -975,17 +986,16 @@ static int codes_for(const Dom& D, uint32_t mask, int* codes) {
   if (mask & LBM_F_T) codes[n++] = 2;
   if (mask & LBM_F_RHO) codes[n++] = 3;
   if (mask & LBM_F_VEL) { codes[n++] = 4; codes[n++] = 5; }
-  if (mask & LBM_F_POP_PHI) for (int q = 0; q < 5; ++q) codes[n++] = 10 + q;
+  if (mask & LBM_F_POP_PHI) for (int q = 0; q < D.qs; ++q) codes[n++] = 10 + q;
   if (mask & LBM_F_JU) { codes[n++] = 20; codes[n++] = 21; }
   if (mask & LBM_F_JT) { codes[n++] = 30; codes[n++] = 31; }
   if (mask & LBM_F_POP_F) for (int q = 0; q < 9; ++q) codes[n++] = 40 + q;
   if (mask & LBM_F_PEND_U) codes[n++] = 50;
   if (mask & LBM_F_PEND_T) codes[n++] = 51;
-  if (mask & LBM_F_SPHI) for (int q = 0; q < 4; ++q) codes[n++] = 60 + q;
+  if (mask & LBM_F_SPHI) for (int q = 0; q < D.qs - 1; ++q) codes[n++] = 60 + q;
   if (mask & LBM_F_SF) for (int q = 0; q < 8; ++q) codes[n++] = 70 + q;
   if (mask & LBM_F_SU) codes[n++] = 8;
   if (mask & LBM_F_ST) codes[n++] = 9;
-  (void)D;
   return n;
 }
 
@@ -1072,7 +1082,7 @@ lbm_status lbm_write_fields(lbm_ctx* c, int32_t dom, uint32_t mask, int32_t src_
   while (c0 < nc) {
     int c1 = c0;
     while (c1 < nc) {
-      const int unit = (codes[c1] == 10) ? (c->dim == 3 ? 7 : 5) : (codes[c1] == 40) ? (c->dim == 3 ? 19 : 9) : 1;
+      const int unit = (codes[c1] == 10) ? D.qs : (codes[c1] == 40) ? (c->dim == 3 ? 19 : 9) : 1;
       if (c1 + unit - c0 > std::min(kStagePlanes, stage_planes)) break;
       c1 += unit;
     }

@@ -66,9 +66,15 @@ def test_workspace_size_and_validation():
     bad = dict(d, N_U=0)
     arr = (lbm.Params * 1)(lbm.to_params(bad))
     assert lib.lbm_workspace_bytes(arr, 1, 1) == 0
-    bad = dict(d, q_scalar=9)
+    bad = dict(d, q_scalar=7)                  # D3Q7 in a 2D domain
     arr = (lbm.Params * 1)(lbm.to_params(bad))
     assert lib.lbm_workspace_bytes(arr, 1, 1) == 0
+    # D2Q9 scalars: eight stored phase planes instead of four
+    q9 = (lbm.Params * 1)(lbm.to_params(dict(d, q_scalar=9)))
+    assert lib.lbm_workspace_bytes(q9, 1, 1) >= n32 + 2 * 4 * 512 * 512 * 4
+    # the domains of one context share their scalar lattice
+    mixed = (lbm.Params * 2)(lbm.to_params(d), lbm.to_params(dict(d, q_scalar=9)))
+    assert lib.lbm_workspace_bytes(mixed, 2, 1) == 0
 
 
 def test_create_rejects_invalid_parameters_before_touching_the_device():
