@@ -18,6 +18,15 @@ constexpr double GRAD_EPS2 = 1e-16;
 
 enum Bc { BC_PER = 0, BC_WALL = 1, BC_INOUT = 2 };
 
+// Derived per-domain constants of the 2D kernels, evaluated once on the host
+// in FP64 (kd) and rounded to FP32 (kf), so no kernel spends FP64 divisions
+// or conversions on them.
+enum Kc {
+  K_DTPHI, K_W2T, K_INVTAU0, K_EPS, K_LAM, K_MC, K_CTH, K_STH, K_INVLHCP, K_THOFF,
+  K_OMK, K_OPK, K_CJ, K_CT, K_RCS, K_RCL, K_HRCS, K_HRCL, K_HKS, K_HKL, K_DTU, K_DTT,
+  K_DS, K_DL, K_U0, K_T0, K_ALPHAL, K_N
+};
+
 // Per-domain device descriptor.  Pointers address planes of px*ny elements
 // (pitch px, x fastest).  R = FP64 when the context stores FP64, else FP32;
 // S = the population storage type.
@@ -48,6 +57,8 @@ struct Dom {
   // zero for direct launches, the step at replay start for a captured graph
   // (whose launches carry the steps of its first cycle)
   long long koff;
+  double kd[K_N];
+  float kf[K_N];
   // state
   void* phi[2];    // R, 1 plane
   void* sphi[2];   // S, Q-1 planes: f_i - w_i phi, i >= 1 (4 in D2Q5, 8 in D2Q9, 6 in D3Q7)
@@ -62,6 +73,13 @@ struct Dom {
   void* vel[2];    // R, dim planes each
   void* scr;       // R, scratch planes of the two-pass 3D kernels (19)
 };
+
+template <class R>
+__device__ __forceinline__ R kc(const Dom& d, int i);
+template <>
+__device__ __forceinline__ double kc<double>(const Dom& d, int i) { return d.kd[i]; }
+template <>
+__device__ __forceinline__ float kc<float>(const Dom& d, int i) { return d.kf[i]; }
 
 // Per-tile partial reductions written by the kernels (FP64).
 struct Partial {

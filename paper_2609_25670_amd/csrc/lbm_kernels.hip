@@ -23,6 +23,8 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "lbm_dev.h"
 
 namespace lbm {
@@ -170,6 +172,22 @@ struct PhaseConst {
 };
 
 template <class R>
+__device__ __forceinline__ PhaseConst<R> phase_const(const Dom& D) {
+  PhaseConst<R> c;
+  c.dt = kc<R>(D, K_DTPHI);
+  c.W2t = kc<R>(D, K_W2T);
+  c.inv_tau0 = kc<R>(D, K_INVTAU0);
+  c.eps = kc<R>(D, K_EPS);
+  c.lam = kc<R>(D, K_LAM);
+  c.Mc = kc<R>(D, K_MC);
+  c.cth = kc<R>(D, K_CTH);
+  c.sth = kc<R>(D, K_STH);
+  c.inv_lhcp = kc<R>(D, K_INVLHCP);
+  c.theta_off = kc<R>(D, K_THOFF);
+  return c;
+}
+
+template <class R>
 __device__ __forceinline__ void phase_collide(const PhaseConst<R>& c, R phi, R gx, R gy, R jx, R jy,
                                               R Us, R Ts, R& dP, R& Kx, R& Ky, R& A, R* jeq = nullptr) {
   const R gg = gx * gx + gy * gy;
@@ -275,17 +293,7 @@ __global__ __launch_bounds__(NTHR) void k_phase(const Dom* __restrict__ doms, co
   GLOBAL const R* __restrict__ Up = D.has_U ? gp<const R>(D.U[par(nU)]) : nullptr;
   GLOBAL const R* __restrict__ Tp = D.has_T ? gp<const R>(D.T[par(n_T(D, k - 1))]) : nullptr;
 
-  PhaseConst<R> c;
-  c.dt = R(D.N_phi * D.dt_base);
-  c.W2t = R(D.W0 * D.W0 / D.tau0);
-  c.inv_tau0 = R(1.0 / D.tau0);
-  c.eps = R(D.eps);
-  c.lam = R(D.lam);
-  c.Mc = R(D.Mc);
-  c.cth = R(D.cth);
-  c.sth = R(D.sth);
-  c.inv_lhcp = R(D.Cp_L / D.L_h);
-  c.theta_off = R(D.T_m + D.m_L * D.C_inf);
+  const PhaseConst<R> c = phase_const<R>(D);
 
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
   // sites of this thread: RPT owned sites, then at most one ring cell
@@ -313,8 +321,8 @@ __global__ __launch_bounds__(NTHR) void k_phase(const Dom* __restrict__ doms, co
     const unsigned o = gy * px + gx;
 #pragma unroll
     for (int q = 0; q < Q - 1; ++q) sv[r][q] = ld(s_in, o + q * pl);
-    Uv[r] = Up ? Up[o] + R(D.U0) : R(0);      // planes hold U - U0 and T - T0
-    Tv[r] = Tp ? Tp[o] + R(D.T0) : c.theta_off;
+    Uv[r] = Up ? Up[o] + kc<R>(D, K_U0) : R(0);      // planes hold U - U0 and T - T0
+    Tv[r] = Tp ? Tp[o] + kc<R>(D, K_T0) : c.theta_off;
   }
   load_box2<R, BW, BH>(sphi, phi_in, px, x0, y0, nx, ny, bcx, bcy, tx, ty);
   __syncthreads();
@@ -350,47 +358,56 @@ __global__ __launch_bounds__(NTHR) void k_phase(const Dom* __restrict__ doms, co
   // anisotropic pull streaming (Eq. 26) into owned sites, in deviations
   // d_i = f_i - w_i phi(y) of the destination y:
   //   A d_i^new = [f_i^+(y - e_i) - w_i phi(y)] - (1 - A) d_i
+  // Only tiles on a wall test the upstream node of each direction (a test
+  // uniform over the block).
+  const bool wx = bcx != BC_PER, wy = bcy != BC_PER;
+  const bool edge = (wx && (x0 == 0 || x0 + w >= nx)) || (wy && (y0 == 0 || y0 + h >= ny));
+  auto stream = [&](auto edge_c) {
+    constexpr bool EDGE = decltype(edge_c)::value;
 #pragma unroll
-  for (int r = 0; r < RPT; ++r) {
-    if (cl[r] < 0) continue;
-    const int ci = cl[r];
-    const int bc = bi[r];
-    const int gx = x0 + tx, gy = y0 + ty + r * BY;
-    const R A = Aown[r], iA = rcp(A), oA = R(1) - A;
-    const R phy = sphi[bc];
-    const R dPo = sP[ci], Kxo = sKx[ci], Kyo = sKy[ci];
-    R s0 = R(0);
+    for (int r = 0; r < RPT; ++r) {
+      if (cl[r] < 0) continue;
+      const int ci = cl[r];
+      const int bc = bi[r];
+      const int gx = x0 + tx, gy = y0 + ty + r * BY;
+      const R A = Aown[r], iA = rcp(A), oA = R(1) - A;
+      const R phy = sphi[bc];
+      const R dPo = sP[ci];
+      R s0 = R(0);
 #pragma unroll
-    for (int q = 0; q < Q - 1; ++q) s0 -= sv[r][q];
-    const bool wx = bcx != BC_PER, wy = bcy != BC_PER;
-    R dn[Q];
-    dn[0] = (dPo * R(Lq::w(0)) - oA * s0) * iA;
+      for (int q = 0; q < Q - 1; ++q) s0 -= sv[r][q];
+      R dn[Q];
+      dn[0] = (dPo * R(Lq::w(0)) - oA * s0) * iA;
 #pragma unroll
-    for (int q = 1; q < Q; ++q) {
-      const int ex = Lq::ex(q), ey = Lq::ey(q);
-      // upstream node beyond a wall: half-way bounce-back from this node
-      const int ux = gx - ex, uy = gy - ey;
-      const bool wall = (wx && (ux < 0 || ux >= nx)) || (wy && (uy < 0 || uy >= ny));
-      R dpost;
-      if (wall) {
-        dpost = dPo * R(Lq::w(q)) - R(Lq::cK) * (R(ex) * Kxo + R(ey) * Kyo);
-        if constexpr (Q == 9) dpost -= R(Lq::cJ(q)) * (R(ex) * sJx[ci] + R(ey) * sJy[ci]);
-      } else {
-        const int si = ci - ey * CW - ex;
-        const R dphi = sphi[bc - ey * BW - ex] - phy;
-        dpost = (dphi + sP[si]) * R(Lq::w(q)) + R(Lq::cK) * (R(ex) * sKx[si] + R(ey) * sKy[si]);
-        if constexpr (Q == 9) dpost += R(Lq::cJ(q)) * (R(ex) * sJx[si] + R(ey) * sJy[si]);
+      for (int q = 1; q < Q; ++q) {
+        const int ex = Lq::ex(q), ey = Lq::ey(q);
+        // upstream node gx - ex, gy - ey beyond a wall: half-way bounce-back
+        // from this node
+        const bool wall = EDGE && ((wx && ((ex > 0 && gx == 0) || (ex < 0 && gx == nx - 1))) ||
+                                   (wy && ((ey > 0 && gy == 0) || (ey < 0 && gy == ny - 1))));
+        R dpost;
+        if (wall) {
+          dpost = dPo * R(Lq::w(q)) - R(Lq::cK) * (R(ex) * sKx[ci] + R(ey) * sKy[ci]);
+          if constexpr (Q == 9) dpost -= R(Lq::cJ(q)) * (R(ex) * sJx[ci] + R(ey) * sJy[ci]);
+        } else {
+          const int si = ci - ey * CW - ex;
+          const R dphi = sphi[bc - ey * BW - ex] - phy;
+          dpost = (dphi + sP[si]) * R(Lq::w(q)) + R(Lq::cK) * (R(ex) * sKx[si] + R(ey) * sKy[si]);
+          if constexpr (Q == 9) dpost += R(Lq::cJ(q)) * (R(ex) * sJx[si] + R(ey) * sJy[si]);
+        }
+        dn[q] = (dpost - oA * sv[r][q - 1]) * iA;
       }
-      dn[q] = (dpost - oA * sv[r][q - 1]) * iA;
+      R dphin = dn[0];
+#pragma unroll
+      for (int q = 1; q < Q; ++q) dphin += dn[q];
+      const unsigned o = gy * px + gx;
+      phi_out[o] = phy + dphin;
+#pragma unroll
+      for (int q = 1; q < Q; ++q) st(s_out, o + (q - 1) * pl, dn[q] - dphin * R(Lq::w(q)));
     }
-    R dphin = dn[0];
-#pragma unroll
-    for (int q = 1; q < Q; ++q) dphin += dn[q];
-    const unsigned o = gy * px + gx;
-    phi_out[o] = phy + dphin;
-#pragma unroll
-    for (int q = 1; q < Q; ++q) st(s_out, o + (q - 1) * pl, dn[q] - dphin * R(Lq::w(q)));
-  }
+  };
+  if (edge) stream(std::true_type{});
+  else stream(std::false_type{});
 }
 
 // =================================================================== transfer
@@ -432,11 +449,11 @@ __global__ __launch_bounds__(NTHR) void k_transfer(const Dom* __restrict__ doms,
   GLOBAL R* __restrict__ Tout = D.has_T ? gp<R>(D.T[par(n_T(D, k - 1) + 1)]) : nullptr;
   GLOBAL R* __restrict__ PU = gp<R>(D.PU);
   GLOBAL R* __restrict__ PT = gp<R>(D.PT);
-  const R omk = R(1.0 - D.kc), opk = R(1.0 + D.kc);
-  const R Uref = R(D.U0);   // the U plane holds U - U0
-  const R cJ = R(D.W0 / (2.0 * 1.4142135623730951));
-  const R cT = R(D.rho_L * D.L_h);
-  const R rcS = R(D.rcS), rcL = R(D.rcL);
+  const R omk = kc<R>(D, K_OMK), opk = kc<R>(D, K_OPK);
+  const R Uref = kc<R>(D, K_U0);   // the U plane holds U - U0
+  const R cJ = kc<R>(D, K_CJ);
+  const R cT = kc<R>(D, K_CT);
+  const R rcS = kc<R>(D, K_RCS), rcL = kc<R>(D, K_RCL);
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
 
   if (!D.has_U) {
@@ -609,22 +626,12 @@ __global__ __launch_bounds__(NTHR) void k_phase_tr(const Dom* __restrict__ doms,
   GLOBAL R* __restrict__ PU = gp<R>(D.PU);
   GLOBAL R* __restrict__ PT = gp<R>(D.PT);
 
-  PhaseConst<R> c;
-  c.dt = R(D.N_phi * D.dt_base);
-  c.W2t = R(D.W0 * D.W0 / D.tau0);
-  c.inv_tau0 = R(1.0 / D.tau0);
-  c.eps = R(D.eps);
-  c.lam = R(D.lam);
-  c.Mc = R(D.Mc);
-  c.cth = R(D.cth);
-  c.sth = R(D.sth);
-  c.inv_lhcp = R(D.Cp_L / D.L_h);
-  c.theta_off = R(D.T_m + D.m_L * D.C_inf);
-  const R Uref = R(D.U0), Tref = R(D.T0);
-  const R omk = R(1.0 - D.kc), opk = R(1.0 + D.kc);
-  const R cJ = R(D.W0 / (2.0 * 1.4142135623730951));
-  const R cT = R(D.rho_L * D.L_h);
-  const R rcS = R(D.rcS), rcL = R(D.rcL);
+  const PhaseConst<R> c = phase_const<R>(D);
+  const R Uref = kc<R>(D, K_U0), Tref = kc<R>(D, K_T0);
+  const R omk = kc<R>(D, K_OMK), opk = kc<R>(D, K_OPK);
+  const R cJ = kc<R>(D, K_CJ);
+  const R cT = kc<R>(D, K_CT);
+  const R rcS = kc<R>(D, K_RCS), rcL = kc<R>(D, K_RCL);
   const int tid = threadIdx.y * TX + threadIdx.x;
 
   // raw coordinate -> node whose values it takes (wrap or clamp)
@@ -714,11 +721,10 @@ __global__ __launch_bounds__(NTHR) void k_phase_tr(const Dom* __restrict__ doms,
     sn[cidx] = pn;
     if (lx >= 2 && ly >= 2 && lx - 2 < w && ly - 2 < h) {   // the tile: write the new state
       phi_out[o] = pn;
-      const R w6 = dphin * R(1.0 / 6.0);
-      st(s_out, o, dn[1] - w6);
-      st(s_out, o + pl, dn[2] - w6);
-      st(s_out, o + 2 * pl, dn[3] - w6);
-      st(s_out, o + 3 * pl, dn[4] - w6);
+      st(s_out, o, dn[1] - dphin * R(1.0 / 6.0));
+      st(s_out, o + pl, dn[2] - dphin * R(1.0 / 6.0));
+      st(s_out, o + 2 * pl, dn[3] - dphin * R(1.0 / 6.0));
+      st(s_out, o + 3 * pl, dn[4] - dphin * R(1.0 / 6.0));
     }
   }
   __syncthreads();
@@ -873,12 +879,13 @@ __global__ __launch_bounds__(NTHR) void k_scalar(const Dom* __restrict__ doms, c
   // velocity of the latest flow update (the flow of step k runs after U, T)
   GLOBAL const R* __restrict__ vel = D.has_F ? gp<const R>(D.vel[par(n_F(D, k - 1))]) : nullptr;
   const bool need_phi = FIELD == 0 || D.T_var;
-  const R dt = R(N * D.dt_base);
-  const R omk = R(1.0 - D.kc), opk = R(1.0 + D.kc);
-  const R DS = R(D.D_S), DL = R(D.D_L);
-  const R kS = R(D.kS), kL = R(D.kL), rcS = R(D.rcS), rcL = R(D.rcL);
-  const R itau_const = rcp(R(3) * dt * (kL / rcL) + R(0.5));
-  const R cref = R(FIELD == 0 ? D.U0 : D.T0);
+  const R dt = kc<R>(D, FIELD == 0 ? K_DTU : K_DTT);
+  const R omk = kc<R>(D, K_OMK), opk = kc<R>(D, K_OPK);
+  const R DS = kc<R>(D, K_DS), DL = kc<R>(D, K_DL);
+  const R hkS = kc<R>(D, K_HKS), hkL = kc<R>(D, K_HKL), hrcS = kc<R>(D, K_HRCS), hrcL = kc<R>(D, K_HRCL);
+  const R rcS = kc<R>(D, K_RCS), rcL = kc<R>(D, K_RCL);
+  const R itau_const = rcp(R(3) * dt * kc<R>(D, K_ALPHAL) + R(0.5));
+  const R cref = kc<R>(D, FIELD == 0 ? K_U0 : K_T0);
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
 
   int cl[NS], bi[NS];
@@ -930,13 +937,13 @@ __global__ __launch_bounds__(NTHR) void k_scalar(const Dom* __restrict__ doms, c
       Qs = -omk * coeff * (gcx * gpx + gcy * gpy) * ikf;                         // Eq. (8), 1st term
     } else if (D.T_var) {
       const R phi = b[0];
-      const R irc = rcp((R(1) + phi) * R(0.5) * rcS + (R(1) - phi) * R(0.5) * rcL);
-      const R coeff = ((R(1) + phi) * R(0.5) * kS + (R(1) - phi) * R(0.5) * kL) * irc;  // Eq. (11)
+      const R irc = rcp((R(1) + phi) * hrcS + (R(1) - phi) * hrcL);
+      const R coeff = ((R(1) + phi) * hkS + (R(1) - phi) * hkL) * irc;          // Eq. (11)
       itau = rcp(R(3) * dt * coeff + R(0.5));
       const R gcx = -R(3) * itau * (jxv[r] - jex), gcy = -R(3) * itau * (jyv[r] - jey);
       R gpx, gpy;
       iso_grad(b, BW, gpx, gpy);
-      Qs = (rcS - rcL) * R(0.5) * irc * coeff * (gcx * gpx + gcy * gpy);        // Eq. (12), 1st term
+      Qs = (hrcS - hrcL) * irc * coeff * (gcx * gpx + gcy * gpy);               // Eq. (12), 1st term
     } else {
       itau = itau_const;
     }
@@ -952,57 +959,66 @@ __global__ __launch_bounds__(NTHR) void k_scalar(const Dom* __restrict__ doms, c
   }
   __syncthreads();
 
-  // pull streaming (Eq. 25) in deviations d_i = f_i - w_i chi(y)
+  // pull streaming (Eq. 25) in deviations d_i = f_i - w_i chi(y).  Only
+  // tiles on a wall test the upstream node of each direction; the test is
+  // uniform over the block, so interior tiles run without those branches.
   R amax = R(0);
+  const bool wx = bcx != BC_PER, wy = bcy != BC_PER;
+  const bool edge = (wx && (x0 == 0 || x0 + w >= nx)) || (wy && (y0 == 0 || y0 + h >= ny));
+  auto stream = [&](auto edge_c) {
+    constexpr bool EDGE = decltype(edge_c)::value;
 #pragma unroll
-  for (int r = 0; r < RPT; ++r) {
-    if (cl[r] < 0) continue;
-    const int ci = cl[r];
-    const int gx = x0 + tx, gy = y0 + ty + r * BY;
-    const R cy = sC[ci], dPo = sP[ci], Kxo = sKx[ci], Kyo = sKy[ci];
-    const bool wx = bcx != BC_PER, wy = bcy != BC_PER;
-    R dq[Q];
-    dq[0] = dPo * R(Lq::w(0));
+    for (int r = 0; r < RPT; ++r) {
+      if (cl[r] < 0) continue;
+      const int ci = cl[r];
+      const int gx = x0 + tx, gy = y0 + ty + r * BY;
+      const R cy = sC[ci], dPo = sP[ci];
+      R dq[Q];
+      dq[0] = dPo * R(Lq::w(0));
 #pragma unroll
-    for (int q = 1; q < Q; ++q) {
-      const int ex = Lq::ex(q), ey = Lq::ey(q);
-      const int ux = gx - ex, uy = gy - ey;   // upstream node
-      const bool wall = (wx && (ux < 0 || ux >= nx)) || (wy && (uy < 0 || uy >= ny));
-      if (FIELD == 1 && D.T_dirlow && ey > 0 && gy == 0) {
-        // anti-bounce-back to T0 at the wall y = -1/2 (the plane holds T - T0)
-        dq[q] = -(R(2) * cy + dPo) * R(Lq::w(q)) + R(Lq::cK) * (R(ex) * Kxo + R(ey) * Kyo);
-        if constexpr (Q == 9) dq[q] += R(Lq::cJ(q)) * (R(ex) * sJx[ci] + R(ey) * sJy[ci]);
-      } else if (wall) {
-        dq[q] = dPo * R(Lq::w(q)) - R(Lq::cK) * (R(ex) * Kxo + R(ey) * Kyo);
-        if constexpr (Q == 9) dq[q] -= R(Lq::cJ(q)) * (R(ex) * sJx[ci] + R(ey) * sJy[ci]);
-      } else {
-        const int si = ci - ey * CW - ex;
-        dq[q] = (sC[si] - cy + sP[si]) * R(Lq::w(q)) + R(Lq::cK) * (R(ex) * sKx[si] + R(ey) * sKy[si]);
-        if constexpr (Q == 9) dq[q] += R(Lq::cJ(q)) * (R(ex) * sJx[si] + R(ey) * sJy[si]);
+      for (int q = 1; q < Q; ++q) {
+        const int ex = Lq::ex(q), ey = Lq::ey(q);
+        // the upstream node gx - ex, gy - ey lies beyond a wall
+        const bool wall = EDGE && ((wx && ((ex > 0 && gx == 0) || (ex < 0 && gx == nx - 1))) ||
+                                   (wy && ((ey > 0 && gy == 0) || (ey < 0 && gy == ny - 1))));
+        if (EDGE && FIELD == 1 && D.T_dirlow && ey > 0 && gy == 0) {
+          // anti-bounce-back to T0 at the wall y = -1/2 (the plane holds T - T0)
+          dq[q] = -(R(2) * cy + dPo) * R(Lq::w(q)) + R(Lq::cK) * (R(ex) * sKx[ci] + R(ey) * sKy[ci]);
+          if constexpr (Q == 9) dq[q] += R(Lq::cJ(q)) * (R(ex) * sJx[ci] + R(ey) * sJy[ci]);
+        } else if (wall) {
+          dq[q] = dPo * R(Lq::w(q)) - R(Lq::cK) * (R(ex) * sKx[ci] + R(ey) * sKy[ci]);
+          if constexpr (Q == 9) dq[q] -= R(Lq::cJ(q)) * (R(ex) * sJx[ci] + R(ey) * sJy[ci]);
+        } else {
+          const int si = ci - ey * CW - ex;
+          dq[q] = (sC[si] - cy + sP[si]) * R(Lq::w(q)) + R(Lq::cK) * (R(ex) * sKx[si] + R(ey) * sKy[si]);
+          if constexpr (Q == 9) dq[q] += R(Lq::cJ(q)) * (R(ex) * sJx[si] + R(ey) * sJy[si]);
+        }
       }
-    }
-    const unsigned o = gy * px + gx;
-    R sum = dq[0];
+      const unsigned o = gy * px + gx;
+      R sum = dq[0];
 #pragma unroll
-    for (int q = 1; q < Q; ++q) sum += dq[q];
-    R chin = cy + sum;
-    if (D.accum) {
-      chin += pv[r];
-      pend[o] = R(0);
-      amax = fmax(amax, fabs(pv[r]));
-    }
-    cout[o] = chin;
-    R jx = R(0), jy = R(0);
+      for (int q = 1; q < Q; ++q) sum += dq[q];
+      R chin = cy + sum;
+      if (D.accum) {
+        chin += pv[r];
+        pend[o] = R(0);
+        amax = fmax(amax, fabs(pv[r]));
+      }
+      cout[o] = chin;
+      R jx = R(0), jy = R(0);
 #pragma unroll
-    for (int q = 1; q < Q; ++q) {
-      if (Lq::ex(q) > 0) jx += dq[q];
-      if (Lq::ex(q) < 0) jx -= dq[q];
-      if (Lq::ey(q) > 0) jy += dq[q];
-      if (Lq::ey(q) < 0) jy -= dq[q];
+      for (int q = 1; q < Q; ++q) {
+        if (Lq::ex(q) > 0) jx += dq[q];
+        if (Lq::ex(q) < 0) jx -= dq[q];
+        if (Lq::ey(q) > 0) jy += dq[q];
+        if (Lq::ey(q) < 0) jy -= dq[q];
+      }
+      st(jout, o, jx);
+      st(jout, o + pl, jy);
     }
-    st(jout, o, jx);
-    st(jout, o + pl, jy);
-  }
+  };
+  if (edge) stream(std::true_type{});
+  else stream(std::false_type{});
   if (FIELD == 0 && D.accum && part) {
     for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_down(amax, off, 64));
     if (tx == 0) red[ty] = amax;

@@ -551,6 +551,37 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
     D.T0 = q.T0;
     D.u0_liquid = q.u0_liquid_only;
     D.qs = q.q_scalar;
+    {
+      double* K = D.kd;
+      K[K_DTPHI] = q.N_phi * q.dt_base;
+      K[K_W2T] = q.W0 * q.W0 / q.tau0;
+      K[K_INVTAU0] = 1.0 / q.tau0;
+      K[K_EPS] = q.eps_s;
+      K[K_LAM] = q.lam;
+      K[K_MC] = q.Mc;
+      K[K_CTH] = cos(q.theta_c);
+      K[K_STH] = sin(q.theta_c);
+      K[K_INVLHCP] = q.Cp_L / q.L_h;
+      K[K_THOFF] = q.T_m + q.m_L * q.C_inf;
+      K[K_OMK] = 1.0 - q.k;
+      K[K_OPK] = 1.0 + q.k;
+      K[K_CJ] = q.W0 / (2.0 * 1.4142135623730951);
+      K[K_CT] = q.rho_L * q.L_h;
+      K[K_RCS] = q.rhoCp_S;
+      K[K_RCL] = q.rhoCp_L;
+      K[K_HRCS] = 0.5 * q.rhoCp_S;
+      K[K_HRCL] = 0.5 * q.rhoCp_L;
+      K[K_HKS] = 0.5 * q.kappa_S;
+      K[K_HKL] = 0.5 * q.kappa_L;
+      K[K_DTU] = q.N_U * q.dt_base;
+      K[K_DTT] = q.N_T * q.dt_base;
+      K[K_DS] = q.D_S;
+      K[K_DL] = q.D_L;
+      K[K_U0] = q.U0;
+      K[K_T0] = q.T0;
+      K[K_ALPHAL] = q.kappa_L / q.rhoCp_L;
+      for (int j = 0; j < K_N; ++j) D.kf[j] = (float)K[j];
+    }
     const size_t pr = D.plane * c->rsz, ps = D.plane * c->ssz;
     const int d3 = q.dim == 3;
     for (int b = 0; b < 2; ++b) {
