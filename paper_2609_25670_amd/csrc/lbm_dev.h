@@ -100,20 +100,31 @@ struct DiagOut {
 // Buffer index holding a field's latest values after `n` writes.
 __host__ __device__ inline int par(long long n) { return (int)(n & 1); }
 
-// Writes of each double-buffered plane after completing base step k.
-__host__ __device__ inline long long n_phi(const Dom& d, long long k) { return k / d.N_phi; }
-__host__ __device__ inline long long n_U(const Dom& d, long long k) {
-  return (d.accum ? 0 : k / d.N_phi) + k / d.N_U;
+// Writes of each double-buffered plane after completing base step k.  The
+// step kernels take k as a 32-bit unsigned step within the cycle of
+// 2 lcm(N_chi) base steps (every quotient's parity and every k mod N is
+// periodic with it), so their divisions are 32-bit; the host and the
+// read-out kernels use the absolute 64-bit step.
+template <class I>
+__host__ __device__ inline I n_phi(const Dom& d, I k) { return k / (I)d.N_phi; }
+template <class I>
+__host__ __device__ inline I n_U(const Dom& d, I k) {
+  return (d.accum ? I(0) : k / (I)d.N_phi) + k / (I)d.N_U;
 }
-__host__ __device__ inline long long n_jU(const Dom& d, long long k) { return k / d.N_U; }
+template <class I>
+__host__ __device__ inline I n_jU(const Dom& d, I k) { return k / (I)d.N_U; }
 // T is written, like U, by the transfer of every phase step (latent heat,
 // instantaneous coupling) and by its own transport; its first moment only
 // by the transport
-__host__ __device__ inline long long n_Ttr(const Dom& d, long long k) {
-  return (d.has_T && !d.accum && !d.T_pulled) ? k / d.N_phi : 0;
+template <class I>
+__host__ __device__ inline I n_Ttr(const Dom& d, I k) {
+  return (d.has_T && !d.accum && !d.T_pulled) ? k / (I)d.N_phi : I(0);
 }
-__host__ __device__ inline long long n_T(const Dom& d, long long k) { return n_Ttr(d, k) + k / d.N_T; }
-__host__ __device__ inline long long n_jT(const Dom& d, long long k) { return k / d.N_T; }
-__host__ __device__ inline long long n_F(const Dom& d, long long k) { return k / d.N_F; }
+template <class I>
+__host__ __device__ inline I n_T(const Dom& d, I k) { return n_Ttr(d, k) + k / (I)d.N_T; }
+template <class I>
+__host__ __device__ inline I n_jT(const Dom& d, I k) { return k / (I)d.N_T; }
+template <class I>
+__host__ __device__ inline I n_F(const Dom& d, I k) { return k / (I)d.N_F; }
 
 }  // namespace lbm

@@ -92,6 +92,48 @@ __device__ __forceinline__ void st(GLOBAL __hip_bfloat16* p, long long i, float 
   ((GLOBAL uint16_t*)p)[i] = bf16_sr(v, i);
 }
 
+// Element i of a plane addressed through a 32-bit byte offset.  The plane
+// base is uniform and stays in scalar registers, and one vector register
+// holding the offset serves every plane of a site, so each access is one
+// global load or store in base + offset form with no 64-bit address
+// arithmetic per lane.  Every 2D plane is smaller than 4 GiB (lbm_create
+// rejects larger ones).
+template <class T>
+__device__ __forceinline__ const GLOBAL T* at(const GLOBAL T* p, unsigned i) {
+  return (const GLOBAL T*)((const GLOBAL char*)p + i * (unsigned)sizeof(T));
+}
+template <class T>
+__device__ __forceinline__ GLOBAL T* at(GLOBAL T* p, unsigned i) {
+  return (GLOBAL T*)((GLOBAL char*)p + i * (unsigned)sizeof(T));
+}
+// The plane at element offset off of a group of planes.  The optimiser
+// would otherwise fold the per-lane offset of a site into one 64-bit vector
+// address and add each plane's stride to it per lane; the empty asm
+// statement (it emits no instruction) keeps every plane base a separate
+// scalar value, so all the planes of a site share the one offset register.
+template <class T>
+__device__ __forceinline__ T* plane(T* p, long long off) {
+  T* r = p + off;
+  asm("" : "+s"(r));
+  return r;
+}
+__device__ __forceinline__ double ldo(const GLOBAL double* p, unsigned i) { return *at(p, i); }
+__device__ __forceinline__ float ldo(const GLOBAL float* p, unsigned i) { return *at(p, i); }
+__device__ __forceinline__ float ldo(const GLOBAL __half* p, unsigned i) {
+  return __half2float(__ushort_as_half(*at((const GLOBAL uint16_t*)p, i)));
+}
+__device__ __forceinline__ float ldo(const GLOBAL __hip_bfloat16* p, unsigned i) {
+  return __uint_as_float((uint32_t)*at((const GLOBAL uint16_t*)p, i) << 16);
+}
+__device__ __forceinline__ void sto(GLOBAL double* p, unsigned i, double v) { *at(p, i) = v; }
+__device__ __forceinline__ void sto(GLOBAL float* p, unsigned i, float v) { *at(p, i) = v; }
+__device__ __forceinline__ void sto(GLOBAL __half* p, unsigned i, float v) {
+  *at((GLOBAL uint16_t*)p, i) = __half_as_ushort(__float2half(v));
+}
+__device__ __forceinline__ void sto(GLOBAL __hip_bfloat16* p, unsigned i, float v) {
+  *at((GLOBAL uint16_t*)p, i) = bf16_sr(v, i);
+}
+
 // Reciprocal and inverse square root: the hardware approximations (about
 // 1 ulp) in the FP32 path, exact division and square root in FP64.
 __device__ __forceinline__ float rcp(float x) { return __builtin_amdgcn_rcpf(x); }
@@ -246,7 +288,7 @@ __device__ __forceinline__ bool ring_cell(int r, int w, int h, int& lx, int& ly)
 // by BH rows.  Issued before the first barrier together with every other
 // global load of the block, so a block waits for memory once.
 template <class R, int BW, int BH>
-__device__ __forceinline__ void load_box2(R* box, const GLOBAL R* __restrict__ plane, int px, int x0, int y0, int nx,
+__device__ __forceinline__ void load_box2(R* box, const GLOBAL R* __restrict__ src, int px, int x0, int y0, int nx,
                                           int ny, int bcx, int bcy, int tx, int ty) {
   static_assert(BW == TX + 4, "box width");
   const int gx0 = ghost(x0 - 2 + tx, nx, bcx);
@@ -254,16 +296,16 @@ __device__ __forceinline__ void load_box2(R* box, const GLOBAL R* __restrict__ p
   const int gx1 = two ? ghost(x0 - 2 + tx + TX, nx, bcx) : 0;
 #pragma unroll
   for (int ly = ty; ly < BH; ly += BY) {
-    const GLOBAL R* row = plane + ghost(y0 - 2 + ly, ny, bcy) * px;
-    box[ly * BW + tx] = row[gx0];
-    if (two) box[ly * BW + tx + TX] = row[gx1];
+    const unsigned row = (unsigned)(ghost(y0 - 2 + ly, ny, bcy) * px);
+    box[ly * BW + tx] = ldo(src, row + gx0);
+    if (two) box[ly * BW + tx + TX] = ldo(src, row + gx1);
   }
 }
 
 // =================================================================== phase kernel
 template <class R, class S, int TY, int Q>
 __global__ __launch_bounds__(NTHR) void k_phase(const Dom* __restrict__ doms, const int4* __restrict__ tiles,
-                                                 long long k) {
+                                                 unsigned k) {
   using Lq = Lat2<Q>;
   constexpr int RPT = TY / BY;
   constexpr int NS = RPT + 1;  // owned sites + one ring cell per thread
@@ -289,7 +331,7 @@ __global__ __launch_bounds__(NTHR) void k_phase(const Dom* __restrict__ doms, co
   GLOBAL const S* __restrict__ s_in = gp<const S>(D.sphi[ib]);
   GLOBAL S* __restrict__ s_out = gp<S>(D.sphi[ob]);
   // latest U and T (before this step's transfer)
-  const long long nU = (D.accum ? 0 : (k - 1) / D.N_phi) + (k - 1) / D.N_U;
+  const unsigned nU = (D.accum ? 0u : (k - 1) / D.N_phi) + (k - 1) / D.N_U;
   GLOBAL const R* __restrict__ Up = D.has_U ? gp<const R>(D.U[par(nU)]) : nullptr;
   GLOBAL const R* __restrict__ Tp = D.has_T ? gp<const R>(D.T[par(n_T(D, k - 1))]) : nullptr;
 
@@ -320,9 +362,9 @@ __global__ __launch_bounds__(NTHR) void k_phase(const Dom* __restrict__ doms, co
     bi[r] = (ly + 1) * BW + lx + 1;
     const unsigned o = gy * px + gx;
 #pragma unroll
-    for (int q = 0; q < Q - 1; ++q) sv[r][q] = ld(s_in, o + q * pl);
-    Uv[r] = Up ? Up[o] + kc<R>(D, K_U0) : R(0);      // planes hold U - U0 and T - T0
-    Tv[r] = Tp ? Tp[o] + kc<R>(D, K_T0) : c.theta_off;
+    for (int q = 0; q < Q - 1; ++q) sv[r][q] = ldo(plane(s_in, q * pl), o);
+    Uv[r] = Up ? ldo(Up, o) + kc<R>(D, K_U0) : R(0);      // planes hold U - U0 and T - T0
+    Tv[r] = Tp ? ldo(Tp, o) + kc<R>(D, K_T0) : c.theta_off;
   }
   load_box2<R, BW, BH>(sphi, phi_in, px, x0, y0, nx, ny, bcx, bcy, tx, ty);
   __syncthreads();
@@ -401,9 +443,9 @@ __global__ __launch_bounds__(NTHR) void k_phase(const Dom* __restrict__ doms, co
 #pragma unroll
       for (int q = 1; q < Q; ++q) dphin += dn[q];
       const unsigned o = gy * px + gx;
-      phi_out[o] = phy + dphin;
+      sto(phi_out, o, phy + dphin);
 #pragma unroll
-      for (int q = 1; q < Q; ++q) st(s_out, o + (q - 1) * pl, dn[q] - dphin * R(Lq::w(q)));
+      for (int q = 1; q < Q; ++q) sto(plane(s_out, (q - 1) * pl), o, dn[q] - dphin * R(Lq::w(q)));
     }
   };
   if (edge) stream(std::true_type{});
@@ -422,7 +464,7 @@ __global__ __launch_bounds__(NTHR) void k_phase(const Dom* __restrict__ doms, co
 // population is exactly adding d to chi.
 template <class R, int TY>
 __global__ __launch_bounds__(NTHR) void k_transfer(const Dom* __restrict__ doms, const int4* __restrict__ tiles,
-                                                    long long k, Partial* __restrict__ part) {
+                                                    unsigned k, Partial* __restrict__ part) {
   constexpr int RPT = TY / BY;
   constexpr int NS = RPT + 1;
   constexpr int BW = TX + 4, BH = TY + 4;
@@ -442,7 +484,7 @@ __global__ __launch_bounds__(NTHR) void k_transfer(const Dom* __restrict__ doms,
   const int bcx = D.bc[0], bcy = D.bc[1];
   GLOBAL const R* __restrict__ phi_old = gp<const R>(D.phi[par(n_phi(D, k - 1))]);
   GLOBAL const R* __restrict__ phi_new = gp<const R>(D.phi[par(n_phi(D, k))]);
-  const long long nU = (D.accum ? 0 : (k - 1) / D.N_phi) + (k - 1) / D.N_U;
+  const unsigned nU = (D.accum ? 0u : (k - 1) / D.N_phi) + (k - 1) / D.N_U;
   GLOBAL const R* __restrict__ Uin = D.has_U ? gp<const R>(D.U[par(nU)]) : nullptr;
   GLOBAL R* __restrict__ Uout = D.has_U ? gp<R>(D.U[par(nU + 1)]) : nullptr;
   GLOBAL const R* __restrict__ Tin = D.has_T ? gp<const R>(D.T[par(n_T(D, k - 1))]) : nullptr;
@@ -464,14 +506,14 @@ __global__ __launch_bounds__(NTHR) void k_transfer(const Dom* __restrict__ doms,
       const int gx = x0 + tx, gy = y0 + ty + r * BY;
       if (tx >= w || ty + r * BY >= h) continue;
       const unsigned o = gy * px + gx;
-      const R pn = phi_new[o];
-      const R dphi = pn - phi_old[o];
+      const R pn = ldo(phi_new, o);
+      const R dphi = pn - ldo(phi_old, o);
       const R rc = (R(1) + pn) * R(0.5) * rcS + (R(1) - pn) * R(0.5) * rcL;
       const R dT = cT * dphi * rcp(R(2) * rc);
       if (D.accum)
-        PT[o] = PT[o] + dT;
+        sto(PT, o, ldo(PT, o) + dT);
       else
-        Tout[o] = Tin[o] + dT;
+        sto(Tout, o, ldo(Tin, o) + dT);
     }
     return;
   }
@@ -503,9 +545,9 @@ __global__ __launch_bounds__(NTHR) void k_transfer(const Dom* __restrict__ doms,
     mxs[r] = mx;
     mys[r] = my;
     const unsigned o = ghost(ry, ny, bcy) * px + ghost(rx, nx, bcx);
-    pold[r] = phi_old[o];
-    Us[r] = Uin[o];
-    if (r < RPT && D.has_T) Tv[r] = D.accum ? PT[o] : Tin[o];
+    pold[r] = ldo(phi_old, o);
+    Us[r] = ldo(Uin, o);
+    if (r < RPT && D.has_T) Tv[r] = D.accum ? ldo(PT, o) : ldo(Tin, o);
   }
   load_box2<R, BW, BH>(sphi, phi_new, px, x0, y0, nx, ny, bcx, bcy, tx, ty);
   __syncthreads();
@@ -545,16 +587,16 @@ __global__ __launch_bounds__(NTHR) void k_transfer(const Dom* __restrict__ doms,
     const R dU = ((R(1) + omk * (Us[r] + Uref)) * dphi - R(2) * div) * rcp(opk - omk * pn);
     amax = fmax(amax, fabs(dU));
     if (D.accum)
-      PU[o] = PU[o] + dU;
+      sto(PU, o, ldo(PU, o) + dU);
     else
-      Uout[o] = Us[r] + dU;
+      sto(Uout, o, Us[r] + dU);
     if (D.has_T) {
       const R rc = (R(1) + pn) * R(0.5) * rcS + (R(1) - pn) * R(0.5) * rcL;
       const R dT = cT * dphi * rcp(R(2) * rc);
       if (D.accum)
-        PT[o] = Tv[r] + dT;
+        sto(PT, o, Tv[r] + dT);
       else
-        Tout[o] = Tv[r] + dT;
+        sto(Tout, o, Tv[r] + dT);
     }
   }
   if (part) {
@@ -590,7 +632,7 @@ __global__ __launch_bounds__(NTHR) void k_transfer(const Dom* __restrict__ doms,
 // bounces back from the node itself).
 template <class R, class S, int TY>
 __global__ __launch_bounds__(NTHR) void k_phase_tr(const Dom* __restrict__ doms, const int4* __restrict__ tiles,
-                                                    long long k, Partial* __restrict__ part) {
+                                                    unsigned k, Partial* __restrict__ part) {
   constexpr int W4 = TX + 8, H4 = TY + 8;   // phi^q box
   constexpr int W3 = TX + 6, H3 = TY + 6;   // collisions
   constexpr int W2 = TX + 4, H2 = TY + 4;   // streaming, phi^{q+1}
@@ -618,7 +660,7 @@ __global__ __launch_bounds__(NTHR) void k_phase_tr(const Dom* __restrict__ doms,
   GLOBAL R* __restrict__ phi_out = gp<R>(D.phi[ob]);
   GLOBAL const S* __restrict__ s_in = gp<const S>(D.sphi[ib]);
   GLOBAL S* __restrict__ s_out = gp<S>(D.sphi[ob]);
-  const long long nU = (D.accum ? 0 : (k - 1) / D.N_phi) + (k - 1) / D.N_U;
+  const unsigned nU = (D.accum ? 0u : (k - 1) / D.N_phi) + (k - 1) / D.N_U;
   GLOBAL const R* __restrict__ Up = D.has_U ? gp<const R>(D.U[par(nU)]) : nullptr;
   GLOBAL R* __restrict__ Uout = D.has_U ? gp<R>(D.U[par(nU + 1)]) : nullptr;
   GLOBAL const R* __restrict__ Tin = D.has_T ? gp<const R>(D.T[par(n_T(D, k - 1))]) : nullptr;
@@ -654,12 +696,12 @@ __global__ __launch_bounds__(NTHR) void k_phase_tr(const Dom* __restrict__ doms,
     if (rx < 0 || ry < 0) continue;                    // beyond a wall: never pulled from
     live[j] = true;
     const unsigned o = ry * px + rx;
-    sv[j][0] = ld(s_in, o);
-    sv[j][1] = ld(s_in, o + pl);
-    sv[j][2] = ld(s_in, o + 2 * pl);
-    sv[j][3] = ld(s_in, o + 3 * pl);
-    Uv[j] = Up ? Up[o] + Uref : R(0);
-    Tv[j] = Tin ? Tin[o] + Tref : c.theta_off;
+    sv[j][0] = ldo(s_in, o);
+    sv[j][1] = ldo(plane(s_in, pl), o);
+    sv[j][2] = ldo(plane(s_in, 2 * pl), o);
+    sv[j][3] = ldo(plane(s_in, 3 * pl), o);
+    Uv[j] = Up ? ldo(Up, o) + Uref : R(0);
+    Tv[j] = Tin ? ldo(Tin, o) + Tref : c.theta_off;
   }
   for (int cidx = tid; cidx < N4; cidx += NTHR) {
     const int gx = x0 - 4 + cidx % W4, gy = y0 - 4 + cidx / W4;
@@ -692,7 +734,7 @@ __global__ __launch_bounds__(NTHR) void k_phase_tr(const Dom* __restrict__ doms,
     const int rx = resolve(gx, nx, bcx), ry = resolve(gy, ny, bcy);
     if (rx < 0 || ry < 0) continue;                    // filled from the clamped node below
     const unsigned o = ry * px + rx;
-    const R s1 = ld(s_in, o), s2 = ld(s_in, o + pl), s3 = ld(s_in, o + 2 * pl), s4 = ld(s_in, o + 3 * pl);
+    const R s1 = ldo(s_in, o), s2 = ldo(plane(s_in, pl), o), s3 = ldo(plane(s_in, 2 * pl), o), s4 = ldo(plane(s_in, 3 * pl), o);
     const int ci = (ly + 1) * W3 + lx + 1;             // this node in the collision region
     const int bq = (ly + 2) * W4 + lx + 2;             // this node in the phi^q box
     const R A = cA[ci], iA = rcp(A), oA = R(1) - A;
@@ -720,11 +762,11 @@ __global__ __launch_bounds__(NTHR) void k_phase_tr(const Dom* __restrict__ doms,
     const R pn = phy + dphin;
     sn[cidx] = pn;
     if (lx >= 2 && ly >= 2 && lx - 2 < w && ly - 2 < h) {   // the tile: write the new state
-      phi_out[o] = pn;
-      st(s_out, o, dn[1] - dphin * R(1.0 / 6.0));
-      st(s_out, o + pl, dn[2] - dphin * R(1.0 / 6.0));
-      st(s_out, o + 2 * pl, dn[3] - dphin * R(1.0 / 6.0));
-      st(s_out, o + 3 * pl, dn[4] - dphin * R(1.0 / 6.0));
+      sto(phi_out, o, pn);
+      sto(s_out, o, dn[1] - dphin * R(1.0 / 6.0));
+      sto(plane(s_out, pl), o, dn[2] - dphin * R(1.0 / 6.0));
+      sto(plane(s_out, 2 * pl), o, dn[3] - dphin * R(1.0 / 6.0));
+      sto(plane(s_out, 3 * pl), o, dn[4] - dphin * R(1.0 / 6.0));
     }
   }
   __syncthreads();
@@ -750,9 +792,9 @@ __global__ __launch_bounds__(NTHR) void k_phase_tr(const Dom* __restrict__ doms,
       const R rc = (R(1) + pn) * R(0.5) * rcS + (R(1) - pn) * R(0.5) * rcL;
       const R dT = cT * dphi * rcp(R(2) * rc);
       if (D.accum)
-        PT[o] = PT[o] + dT;
+        sto(PT, o, ldo(PT, o) + dT);
       else
-        Tout[o] = Tin[o] + dT;
+        sto(Tout, o, ldo(Tin, o) + dT);
     }
     return;
   }
@@ -773,7 +815,7 @@ __global__ __launch_bounds__(NTHR) void k_phase_tr(const Dom* __restrict__ doms,
       const unsigned o = nodey(gy) * px + nodex(gx);
       const R ig = rsq(gg);
       const R pold = sq[(qy + 3) * W4 + qx + 3];
-      const R a = cJ * (R(1) + omk * (Up[o] + Uref)) * (b[0] - pold) * ig;
+      const R a = cJ * (R(1) + omk * (ldo(Up, o) + Uref)) * (b[0] - pold) * ig;
       Jx = -a * gxv;
       Jy = -a * gyv;
     }
@@ -796,20 +838,20 @@ __global__ __launch_bounds__(NTHR) void k_phase_tr(const Dom* __restrict__ doms,
                   (jx[W1 + 1] - jx[W1 - 1] - jx[-W1 - 1] + jx[-W1 + 1]) * R(1.0 / 12.0) +
                   (jy[W1] - jy[-W1]) * R(1.0 / 3.0) +
                   (jy[W1 + 1] + jy[W1 - 1] - jy[-W1 - 1] - jy[-W1 + 1]) * R(1.0 / 12.0);
-    const R Us = Up[o];
+    const R Us = ldo(Up, o);
     const R dU = ((R(1) + omk * (Us + Uref)) * dphi - R(2) * div) * rcp(opk - omk * pn);
     amax = fmax(amax, fabs(dU));
     if (D.accum)
-      PU[o] = PU[o] + dU;
+      sto(PU, o, ldo(PU, o) + dU);
     else
-      Uout[o] = Us + dU;
+      sto(Uout, o, Us + dU);
     if (D.has_T) {
       const R rc = (R(1) + pn) * R(0.5) * rcS + (R(1) - pn) * R(0.5) * rcL;
       const R dT = cT * dphi * rcp(R(2) * rc);
       if (D.accum)
-        PT[o] = PT[o] + dT;
+        sto(PT, o, ldo(PT, o) + dT);
       else
-        Tout[o] = Tin[o] + dT;
+        sto(Tout, o, ldo(Tin, o) + dT);
     }
   }
   if (part) {
@@ -834,7 +876,7 @@ __global__ __launch_bounds__(NTHR) void k_phase_tr(const Dom* __restrict__ doms,
 // pending increments right after the transport.
 template <class R, class S, int TY, int FIELD, int Q>
 __global__ __launch_bounds__(NTHR) void k_scalar(const Dom* __restrict__ doms, const int4* __restrict__ tiles,
-                                                  long long k, Partial* __restrict__ part) {
+                                                  unsigned k, Partial* __restrict__ part) {
   using Lq = Lat2<Q>;
   constexpr int RPT = TY / BY;
   constexpr int NS = RPT + 1;
@@ -862,7 +904,7 @@ __global__ __launch_bounds__(NTHR) void k_scalar(const Dom* __restrict__ doms, c
   GLOBAL S* __restrict__ jout;
   GLOBAL R* __restrict__ pend;
   if (FIELD == 0) {
-    const long long nU = (D.accum ? 0 : k / D.N_phi) + (k - 1) / D.N_U;
+    const unsigned nU = (D.accum ? 0u : k / D.N_phi) + (k - 1) / D.N_U;
     cin = gp<const R>(D.U[par(nU)]);
     cout = gp<R>(D.U[par(nU + 1)]);
     jin = gp<const S>(D.jU[par(n_jU(D, k - 1))]);
@@ -909,12 +951,12 @@ __global__ __launch_bounds__(NTHR) void k_scalar(const Dom* __restrict__ doms, c
     cl[r] = ly * CW + lx;
     bi[r] = (ly + 1) * BW + lx + 1;
     const unsigned o = gy * px + gx;
-    chi[r] = cin[o];
-    jxv[r] = ld(jin, o);
-    jyv[r] = ld(jin, o + pl);
-    uxv[r] = vel ? vel[o] : R(0);
-    uyv[r] = vel ? vel[o + pl] : R(0);
-    if (r < RPT && D.accum) pv[r] = pend[o];
+    chi[r] = ldo(cin, o);
+    jxv[r] = ldo(jin, o);
+    jyv[r] = ldo(plane(jin, pl), o);
+    uxv[r] = vel ? ldo(vel, o) : R(0);
+    uyv[r] = vel ? ldo(plane(vel, pl), o) : R(0);
+    if (r < RPT && D.accum) pv[r] = ldo(pend, o);
   }
   if (need_phi) load_box2<R, BW, BH>(sphi, phis, px, x0, y0, nx, ny, bcx, bcy, tx, ty);
   __syncthreads();
@@ -1001,10 +1043,10 @@ __global__ __launch_bounds__(NTHR) void k_scalar(const Dom* __restrict__ doms, c
       R chin = cy + sum;
       if (D.accum) {
         chin += pv[r];
-        pend[o] = R(0);
+        sto(pend, o, R(0));
         amax = fmax(amax, fabs(pv[r]));
       }
-      cout[o] = chin;
+      sto(cout, o, chin);
       R jx = R(0), jy = R(0);
 #pragma unroll
       for (int q = 1; q < Q; ++q) {
@@ -1013,8 +1055,8 @@ __global__ __launch_bounds__(NTHR) void k_scalar(const Dom* __restrict__ doms, c
         if (Lq::ey(q) > 0) jy += dq[q];
         if (Lq::ey(q) < 0) jy -= dq[q];
       }
-      st(jout, o, jx);
-      st(jout, o + pl, jy);
+      sto(jout, o, jx);
+      sto(plane(jout, pl), o, jy);
     }
   };
   if (edge) stream(std::true_type{});
@@ -1113,7 +1155,7 @@ __device__ __forceinline__ void flow_collide(R rho, const R* d, R dt, R Fx, R Fy
 // processed in sub-tiles of SUB rows (8 in FP64, 16 in FP32) that reuse it.
 template <class R, class S, int TY, int SUB>
 __global__ __launch_bounds__(NTHR) void k_flow(const Dom* __restrict__ doms, const int4* __restrict__ tiles,
-                                                long long k) {
+                                                unsigned k) {
   constexpr int RPT = SUB / BY;
   constexpr int CW = TX + 2, CH = SUB + 2;
   static_assert(TY % SUB == 0, "tile height must be a multiple of the sub-tile height");
@@ -1126,7 +1168,8 @@ __global__ __launch_bounds__(NTHR) void k_flow(const Dom* __restrict__ doms, con
   const Dom& D = doms[t.x];
   if (k % D.N_F) return;
   const int nx = D.nx, ny = D.ny;
-  const long long px = D.px, pl = D.plane;
+  const int px = D.px;
+  const long long pl = D.plane;
   const int fbx = D.fbc[0], fby = D.fbc[1];
   GLOBAL const R* __restrict__ rho_in = gp<const R>(D.rho[par(n_F(D, k - 1))]);
   GLOBAL R* __restrict__ rho_out = gp<R>(D.rho[par(n_F(D, k))]);
@@ -1149,16 +1192,16 @@ __global__ __launch_bounds__(NTHR) void k_flow(const Dom* __restrict__ doms, con
     for (int i = tid; i < CW * CH; i += NTHR) {
       const int lx = i % CW, ly = i / CW;
       const int rx = x0 - 1 + lx, ry = y0 - 1 + ly;
-      sfl[i] = (R(1) - phis[ghost(ry, ny, fbyw) * px + ghost(rx, nx, fbxw)]) * R(0.5);
+      sfl[i] = (R(1) - ldo(phis, (unsigned)(ghost(ry, ny, fbyw) * px + ghost(rx, nx, fbxw)))) * R(0.5);
       const int gx = resolve(rx, nx, fbxw), gy = resolve(ry, ny, fbyw);
       if (gx < 0 || gy < 0) continue;
-      const long long o = gy * px + gx;
-      const R rho = rho_in[o];
+      const unsigned o = gy * px + gx;
+      const R rho = ldo(rho_in, o);
       R d[9];
       R ssum = R(0);
 #pragma unroll
       for (int q = 1; q < 9; ++q) {
-        d[q] = ld(s_in, o + (q - 1) * pl);
+        d[q] = ldo(plane(s_in, (q - 1) * pl), o);
         ssum += d[q];
       }
       d[0] = -ssum;
@@ -1220,12 +1263,12 @@ __global__ __launch_bounds__(NTHR) void k_flow(const Dom* __restrict__ doms, con
       const R ux = (c * jx + dt * Fx * R(0.5)) * irho, uy = (c * jy + dt * Fy * R(0.5)) * irho;
       const int ncopy = (fbx == BC_INOUT && gx == nx - 2) ? 2 : 1;
       for (int cpy = 0; cpy < ncopy; ++cpy) {
-        const long long o = gy * px + gx + cpy;
-        rho_out[o] = rho;
-        vel[o] = ux;
-        vel[o + pl] = uy;
+        const unsigned o = gy * px + gx + cpy;
+        sto(rho_out, o, rho);
+        sto(vel, o, ux);
+        sto(plane(vel, pl), o, uy);
 #pragma unroll
-        for (int q = 1; q < 9; ++q) st(s_out, o + (q - 1) * pl, dn[q] - w[q] * drho);
+        for (int q = 1; q < 9; ++q) sto(plane(s_out, (q - 1) * pl), o, dn[q] - w[q] * drho);
       }
     }
     __syncthreads();
@@ -1737,7 +1780,7 @@ __device__ __forceinline__ void phase_collide3(const Dom& D, R phi, const R* g, 
 }
 
 template <class R, class S>
-__global__ __launch_bounds__(256) void k3_phase_collide(const Dom* __restrict__ doms, long long k) {
+__global__ __launch_bounds__(256) void k3_phase_collide(const Dom* __restrict__ doms, unsigned k) {
   const Dom& D = doms[0];
   Site3 s;
   if (!site3(D, blockIdx.x, threadIdx.x, s) || k % D.N_phi) return;
@@ -1745,7 +1788,7 @@ __global__ __launch_bounds__(256) void k3_phase_collide(const Dom* __restrict__ 
   const int ib = par(n_phi(D, k - 1));
   GLOBAL const R* phi = gp<const R>(D.phi[ib]);
   GLOBAL const S* sp = gp<const S>(D.sphi[ib]);
-  const long long nU = (D.accum ? 0 : (k - 1) / D.N_phi) + (k - 1) / D.N_U;
+  const unsigned nU = (D.accum ? 0u : (k - 1) / D.N_phi) + (k - 1) / D.N_U;
   // the U and T planes hold U - U0 and T - T0
   const R Us = D.has_U ? (gp<const R>(D.U[par(nU)]))[s.o] + R(D.U0) : R(0);
   const R Ts = D.has_T ? (gp<const R>(D.T[par(n_T(D, k - 1))]))[s.o] + R(D.T0) : R(D.T_m + D.m_L * D.C_inf);
@@ -1767,7 +1810,7 @@ __global__ __launch_bounds__(256) void k3_phase_collide(const Dom* __restrict__ 
 
 // anisotropic pull streaming (Eq. 26) in deviations from w_i phi(y)
 template <class R, class S>
-__global__ __launch_bounds__(256) void k3_phase_stream(const Dom* __restrict__ doms, long long k) {
+__global__ __launch_bounds__(256) void k3_phase_stream(const Dom* __restrict__ doms, unsigned k) {
   const Dom& D = doms[0];
   Site3 s;
   if (!site3(D, blockIdx.x, threadIdx.x, s) || k % D.N_phi) return;
@@ -1810,14 +1853,14 @@ __global__ __launch_bounds__(256) void k3_phase_stream(const Dom* __restrict__ d
 
 // transfer, pass 1: J = W0/(2 sqrt2) [1 + (1-k) U*] dphi n^{q+1} (Eq. 37)
 template <class R>
-__global__ __launch_bounds__(256) void k3_transfer_J(const Dom* __restrict__ doms, long long k) {
+__global__ __launch_bounds__(256) void k3_transfer_J(const Dom* __restrict__ doms, unsigned k) {
   const Dom& D = doms[0];
   Site3 s;
   if (!site3(D, blockIdx.x, threadIdx.x, s) || k % D.N_phi || !D.has_U) return;
   const unsigned pl = (unsigned)D.plane;
   GLOBAL const R* pn = gp<const R>(D.phi[par(n_phi(D, k))]);
   GLOBAL const R* po = gp<const R>(D.phi[par(n_phi(D, k - 1))]);
-  const long long nU = (D.accum ? 0 : (k - 1) / D.N_phi) + (k - 1) / D.N_U;
+  const unsigned nU = (D.accum ? 0u : (k - 1) / D.N_phi) + (k - 1) / D.N_U;
   GLOBAL const R* Uin = gp<const R>(D.U[par(nU)]);
   R g[3];
   grad3(D, s, pn, g);
@@ -1837,7 +1880,7 @@ __global__ __launch_bounds__(256) void k3_transfer_J(const Dom* __restrict__ dom
 // transfer, pass 2: compact divergence (ghost J mirrored with the normal
 // component negated), dU and dT of Eq. (38), injection (Eq. 39)
 template <class R>
-__global__ __launch_bounds__(256) void k3_transfer_apply(const Dom* __restrict__ doms, long long k,
+__global__ __launch_bounds__(256) void k3_transfer_apply(const Dom* __restrict__ doms, unsigned k,
                                                           Partial* __restrict__ part) {
   __shared__ R red[4];
   const Dom& D = doms[0];
@@ -1851,7 +1894,7 @@ __global__ __launch_bounds__(256) void k3_transfer_apply(const Dom* __restrict__
   if (ok) {
     const R p1 = pn[s.o], dphi = p1 - po[s.o];
     if (D.has_U) {
-      const long long nU = (D.accum ? 0 : (k - 1) / D.N_phi) + (k - 1) / D.N_U;
+      const unsigned nU = (D.accum ? 0u : (k - 1) / D.N_phi) + (k - 1) / D.N_U;
       GLOBAL const R* Uin = gp<const R>(D.U[par(nU)]);
       GLOBAL const R* J = gp<const R>(D.scr);
       R div = R(0);
@@ -1903,7 +1946,7 @@ __global__ __launch_bounds__(256) void k3_transfer_apply(const Dom* __restrict__
 
 // scalar transport (U: FIELD 0, T: FIELD 1), pass 1: collision to (dP, K)
 template <class R, class S, int FIELD>
-__global__ __launch_bounds__(256) void k3_scalar_collide(const Dom* __restrict__ doms, long long k) {
+__global__ __launch_bounds__(256) void k3_scalar_collide(const Dom* __restrict__ doms, unsigned k) {
   const Dom& D = doms[0];
   const int N = FIELD == 0 ? D.N_U : D.N_T;
   Site3 s;
@@ -1968,7 +2011,7 @@ __global__ __launch_bounds__(256) void k3_scalar_collide(const Dom* __restrict__
 // scalar transport, pass 2: pull streaming (Eq. 25) with bounce-back, or
 // anti-bounce-back to the moving profile on the z walls of the pulled T
 template <class R, class S, int FIELD>
-__global__ __launch_bounds__(256) void k3_scalar_stream(const Dom* __restrict__ doms, long long k,
+__global__ __launch_bounds__(256) void k3_scalar_stream(const Dom* __restrict__ doms, unsigned k,
                                                          Partial* __restrict__ part) {
   __shared__ R red[4];
   const Dom& D = doms[0];
@@ -1982,7 +2025,7 @@ __global__ __launch_bounds__(256) void k3_scalar_stream(const Dom* __restrict__ 
   GLOBAL S* jout;
   GLOBAL R* pend;
   if (FIELD == 0) {
-    const long long nU = (D.accum ? 0 : k / D.N_phi) + (k - 1) / D.N_U;
+    const unsigned nU = (D.accum ? 0u : k / D.N_phi) + (k - 1) / D.N_U;
     cin = gp<const R>(D.U[par(nU)]);
     cout = gp<R>(D.U[par(nU + 1)]);
     jout = gp<S>(D.jU[par(n_jU(D, k))]);
@@ -2094,7 +2137,7 @@ __device__ __forceinline__ void mrt19_op(const R* x, R sq, R se, R seps, R snu, 
 }
 
 template <class R, class S>
-__global__ __launch_bounds__(256) void k3_flow_collide(const Dom* __restrict__ doms, long long k) {
+__global__ __launch_bounds__(256) void k3_flow_collide(const Dom* __restrict__ doms, unsigned k) {
   const Dom& D = doms[0];
   Site3 s;
   if (!site3(D, blockIdx.x, threadIdx.x, s) || k % D.N_F) return;
@@ -2150,7 +2193,7 @@ __global__ __launch_bounds__(256) void k3_flow_collide(const Dom* __restrict__ d
 
 // partial bounce-back pull (Eq. 33) in deviations from w_i rho(y)
 template <class R, class S>
-__global__ __launch_bounds__(256) void k3_flow_stream(const Dom* __restrict__ doms, long long k) {
+__global__ __launch_bounds__(256) void k3_flow_stream(const Dom* __restrict__ doms, unsigned k) {
   const Dom& D = doms[0];
   Site3 s;
   if (!site3(D, blockIdx.x, threadIdx.x, s) || k % D.N_F) return;
@@ -2440,15 +2483,15 @@ struct Launch3 {
     const long long cols = (long long)((h.nx + 63) / 64) * ((h.ny + 3) / 4);
     return (unsigned)((cols + 7) / 8 * 8 * h.nz);
   }
-  static void phase(const Dom& h, hipStream_t st, const Dom* d, long long k) {
+  static void phase(const Dom& h, hipStream_t st, const Dom* d, unsigned k) {
     k3_phase_collide<R, S><<<blocks(h), 256, 0, st>>>(d, k);
     k3_phase_stream<R, S><<<blocks(h), 256, 0, st>>>(d, k);
   }
-  static void transfer(const Dom& h, hipStream_t st, const Dom* d, long long k, Partial* p) {
+  static void transfer(const Dom& h, hipStream_t st, const Dom* d, unsigned k, Partial* p) {
     if (h.has_U) k3_transfer_J<R><<<blocks(h), 256, 0, st>>>(d, k);
     k3_transfer_apply<R><<<blocks(h), 256, 0, st>>>(d, k, p);
   }
-  static void scalar(int field, const Dom& h, hipStream_t st, const Dom* d, long long k, Partial* p) {
+  static void scalar(int field, const Dom& h, hipStream_t st, const Dom* d, unsigned k, Partial* p) {
     if (field == 0) {
       k3_scalar_collide<R, S, 0><<<blocks(h), 256, 0, st>>>(d, k);
       k3_scalar_stream<R, S, 0><<<blocks(h), 256, 0, st>>>(d, k, p);
@@ -2457,11 +2500,11 @@ struct Launch3 {
       k3_scalar_stream<R, S, 1><<<blocks(h), 256, 0, st>>>(d, k, p);
     }
   }
-  static void flow(const Dom& h, hipStream_t st, const Dom* d, long long k) {
+  static void flow(const Dom& h, hipStream_t st, const Dom* d, unsigned k) {
     k3_flow_collide<R, S><<<blocks(h), 256, 0, st>>>(d, k);
     k3_flow_stream<R, S><<<blocks(h), 256, 0, st>>>(d, k);
   }
-  static void step(const Dom& h, hipStream_t st, const Dom* d, long long k, Partial* p) {
+  static void step(const Dom& h, hipStream_t st, const Dom* d, unsigned k, Partial* p) {
     if (k % h.N_phi == 0) {
       phase(h, st, d, k);
       transfer(h, st, d, k, p);
@@ -2498,7 +2541,7 @@ template <class R, class S>
 struct Launch {
   // TY selects the tile height: 4, 8, 16 or 32 rows
   // Q: scalar lattice, 5 (D2Q5) or 9 (D2Q9)
-  static void phase(int TY, int Q, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k) {
+  static void phase(int TY, int Q, dim3 g, hipStream_t st, const Dom* d, const int4* t, unsigned k) {
     const dim3 b(TX, BY);
     if (Q == 9) {
       if (TY == 4) k_phase<R, S, 4, 9><<<g, b, 0, st>>>(d, t, k);
@@ -2514,7 +2557,7 @@ struct Launch {
   }
   // phase + transfer in one kernel: 8-row tiles in FP64 (LDS), 8 or 16 otherwise
   static int phase_tr_rows(int TY) { return sizeof(R) == 8 ? 8 : (TY >= 16 ? 16 : 8); }
-  static void phase_tr(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k, Partial* p) {
+  static void phase_tr(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, unsigned k, Partial* p) {
     const dim3 b(TX, BY);
     if constexpr (sizeof(R) == 8) {
       k_phase_tr<R, S, 8><<<g, b, 0, st>>>(d, t, k, p);
@@ -2523,7 +2566,7 @@ struct Launch {
       else k_phase_tr<R, S, 8><<<g, b, 0, st>>>(d, t, k, p);
     }
   }
-  static void transfer(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k, Partial* p) {
+  static void transfer(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, unsigned k, Partial* p) {
     const dim3 b(TX, BY);
     if (TY == 4) k_transfer<R, 4><<<g, b, 0, st>>>(d, t, k, p);
     else if (TY == 8) k_transfer<R, 8><<<g, b, 0, st>>>(d, t, k, p);
@@ -2531,7 +2574,7 @@ struct Launch {
     else k_transfer<R, 32><<<g, b, 0, st>>>(d, t, k, p);
   }
   template <int F>
-  static void scalar_f(int TY, int Q, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k,
+  static void scalar_f(int TY, int Q, dim3 g, hipStream_t st, const Dom* d, const int4* t, unsigned k,
                        Partial* p) {
     const dim3 b(TX, BY);
     if (Q == 9) {
@@ -2546,12 +2589,12 @@ struct Launch {
     else if (TY == 16) k_scalar<R, S, 16, F, 5><<<g, b, 0, st>>>(d, t, k, p);
     else k_scalar<R, S, 32, F, 5><<<g, b, 0, st>>>(d, t, k, p);
   }
-  static void scalar(int field, int TY, int Q, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k,
+  static void scalar(int field, int TY, int Q, dim3 g, hipStream_t st, const Dom* d, const int4* t, unsigned k,
                      Partial* p) {
     if (field == 0) scalar_f<0>(TY, Q, g, st, d, t, k, p);
     else scalar_f<1>(TY, Q, g, st, d, t, k, p);
   }
-  static void flow(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k) {
+  static void flow(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, unsigned k) {
     constexpr int SUB = sizeof(R) == 8 ? 8 : 16;
     const dim3 b(TX, BY);
     if (TY == 4) k_flow<R, S, 4, 4><<<g, b, 0, st>>>(d, t, k);

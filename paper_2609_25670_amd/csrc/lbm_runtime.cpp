@@ -26,13 +26,13 @@
 namespace lbm {
 template <class R, class S>
 struct Launch {
-  static void phase(int TY, int Q, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k);
-  static void transfer(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k, Partial* p);
+  static void phase(int TY, int Q, dim3 g, hipStream_t st, const Dom* d, const int4* t, unsigned k);
+  static void transfer(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, unsigned k, Partial* p);
   static int phase_tr_rows(int TY);
-  static void phase_tr(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k, Partial* p);
-  static void scalar(int field, int TY, int Q, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k,
+  static void phase_tr(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, unsigned k, Partial* p);
+  static void scalar(int field, int TY, int Q, dim3 g, hipStream_t st, const Dom* d, const int4* t, unsigned k,
                      Partial* p);
-  static void flow(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k);
+  static void flow(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, unsigned k);
   static void diag_tiles(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, long long k, Partial* p);
   static void tips(int ndom, hipStream_t st, const Dom* d, long long k, DiagOut* o);
   static void init(hipStream_t st, const Dom* d, int dom, long long n, const double* xi);
@@ -45,11 +45,11 @@ void diag_final(int ndom, hipStream_t st, const Dom* d, const Partial* p, const 
                 DiagOut* o);
 template <class R, class S>
 struct Launch3 {
-  static void phase(const Dom& h, hipStream_t st, const Dom* d, long long k);
-  static void transfer(const Dom& h, hipStream_t st, const Dom* d, long long k, Partial* p);
-  static void scalar(int field, const Dom& h, hipStream_t st, const Dom* d, long long k, Partial* p);
-  static void flow(const Dom& h, hipStream_t st, const Dom* d, long long k);
-  static void step(const Dom& h, hipStream_t st, const Dom* d, long long k, Partial* p);
+  static void phase(const Dom& h, hipStream_t st, const Dom* d, unsigned k);
+  static void transfer(const Dom& h, hipStream_t st, const Dom* d, unsigned k, Partial* p);
+  static void scalar(int field, const Dom& h, hipStream_t st, const Dom* d, unsigned k, Partial* p);
+  static void flow(const Dom& h, hipStream_t st, const Dom* d, unsigned k);
+  static void step(const Dom& h, hipStream_t st, const Dom* d, unsigned k, Partial* p);
   static void init(const Dom& h, hipStream_t st, const Dom* d, const double* xi);
   static void diag(const Dom& h, hipStream_t st, const Dom* d, long long k, Partial* p, double* front);
   static void read(const Dom& h, hipStream_t st, const Dom* d, long long k, const int* codes, int nc, int f64,
@@ -83,12 +83,12 @@ struct Group {
 };
 
 struct Ops {
-  void (*phase)(int, int, dim3, hipStream_t, const Dom*, const int4*, long long);
-  void (*transfer)(int, dim3, hipStream_t, const Dom*, const int4*, long long, Partial*);
-  void (*phase_tr)(int, dim3, hipStream_t, const Dom*, const int4*, long long, Partial*);
+  void (*phase)(int, int, dim3, hipStream_t, const Dom*, const int4*, unsigned);
+  void (*transfer)(int, dim3, hipStream_t, const Dom*, const int4*, unsigned, Partial*);
+  void (*phase_tr)(int, dim3, hipStream_t, const Dom*, const int4*, unsigned, Partial*);
   int (*phase_tr_rows)(int);
-  void (*scalar)(int, int, int, dim3, hipStream_t, const Dom*, const int4*, long long, Partial*);
-  void (*flow)(int, dim3, hipStream_t, const Dom*, const int4*, long long);
+  void (*scalar)(int, int, int, dim3, hipStream_t, const Dom*, const int4*, unsigned, Partial*);
+  void (*flow)(int, dim3, hipStream_t, const Dom*, const int4*, unsigned);
   void (*diag_tiles)(int, dim3, hipStream_t, const Dom*, const int4*, long long, Partial*);
   void (*tips)(int, hipStream_t, const Dom*, long long, DiagOut*);
   void (*init)(hipStream_t, const Dom*, int, long long, const double*);
@@ -105,11 +105,11 @@ Ops make_ops() {
 }
 
 struct Ops3 {
-  void (*phase)(const Dom&, hipStream_t, const Dom*, long long);
-  void (*transfer)(const Dom&, hipStream_t, const Dom*, long long, Partial*);
-  void (*scalar)(int, const Dom&, hipStream_t, const Dom*, long long, Partial*);
-  void (*flow)(const Dom&, hipStream_t, const Dom*, long long);
-  void (*step)(const Dom&, hipStream_t, const Dom*, long long, Partial*);
+  void (*phase)(const Dom&, hipStream_t, const Dom*, unsigned);
+  void (*transfer)(const Dom&, hipStream_t, const Dom*, unsigned, Partial*);
+  void (*scalar)(int, const Dom&, hipStream_t, const Dom*, unsigned, Partial*);
+  void (*flow)(const Dom&, hipStream_t, const Dom*, unsigned);
+  void (*step)(const Dom&, hipStream_t, const Dom*, unsigned, Partial*);
   void (*init)(const Dom&, hipStream_t, const Dom*, const double*);
   void (*diag)(const Dom&, hipStream_t, const Dom*, long long, Partial*, double*);
   void (*read)(const Dom&, hipStream_t, const Dom*, long long, const int*, int, int, void*);
@@ -314,7 +314,14 @@ static int ty_slot(int rows) {
   return 0;
 }
 
-static void launch_step(lbm_ctx* c, hipStream_t st, long long k) {
+// The step kernels take the base step within the cycle: absolute step k >= 1
+// maps to 1 + (k - 1) mod cycle, which keeps every k mod N_chi and the
+// parity of every buffer count, so their index arithmetic stays 32-bit.  The
+// time-dependent 3D walls add Dom::koff, the absolute step at the start of
+// the cycle.
+static unsigned cycle_step(const lbm_ctx* c, long long k) { return (unsigned)((k - 1) % c->cycle + 1); }
+
+static void launch_step(lbm_ctx* c, hipStream_t st, unsigned k) {
   if (c->dim == 3) {
     c->ops3.step(c->H[0], st, c->d_dom, k, c->d_part);
     return;
@@ -359,7 +366,7 @@ static lbm_status autotune(lbm_ctx* c) {
   for (auto& D : c->H) any_accum |= D.accum != 0;
   // the next due step of a group: its kernels read the current buffers and
   // write only the other ones, so repeating them leaves the state unchanged
-  auto next_due = [&](int N) { return (c->k / N + 1) * (long long)N; };
+  auto next_due = [&](int N) { return cycle_step(c, (c->k / N + 1) * (long long)N); };
   for (int ti = 0; ti < kNTY; ++ti) {
     const int TY = kTYs[ti];
     auto run = [&]() {
@@ -443,6 +450,21 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
   for (int i = 0; i < n; ++i) {
     const std::string m = validate(p[i], i);
     if (!m.empty()) return fail(nullptr, LBM_EINVAL, m);
+  }
+  {
+    // the step kernels index the cycle of 2 lcm(N_chi) base steps and a
+    // plane's elements in 32 bits
+    long long lcm = 1;
+    for (int i = 0; i < n; ++i) {
+      for (int N : {p[i].N_phi, p[i].N_U, p[i].N_T, p[i].N_F}) {
+        lcm = ipow_lcm(lcm, N);
+        if (lcm > (1LL << 29)) return fail(nullptr, LBM_EINVAL, "the update factors' lcm exceeds 2^29");
+      }
+      const int esz = storage == LBM_STORE_F64 ? 8 : 4;
+      const long long nz = p[i].dim == 3 ? p[i].nz : 1;
+      if ((long long)px_of(p[i].nx) * p[i].ny * nz * esz >= (1LL << 32))
+        return fail(nullptr, LBM_EINVAL, "domain " + std::to_string(i) + ": one field plane exceeds 4 GiB");
+    }
   }
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || device < 0 || device >= ndev)
@@ -852,7 +874,7 @@ lbm_status lbm_kernel_times(lbm_ctx* c, int32_t reps, double* ms_out, double* pe
     // spent per base step (groups weighted by how often they are due)
     double all = 0.0, weighted = 0.0;
     for (auto& g : gs) {
-      const long long k = due(g.N);
+      const unsigned k = cycle_step(c, due(g.N));
       const dim3 grid(g.ts[ti].n);
       auto launch = [&]() {
         if (c->dim == 3) {
@@ -963,7 +985,7 @@ lbm_status lbm_step_multirate(lbm_ctx* c, int64_t n, lbm_diag* diag) {
         }
         hipGraph_t g;
         HIPCHK(c, hipStreamBeginCapture(c->cap_stream, hipStreamCaptureModeThreadLocal));
-        for (long long j = 1; j <= c->cycle; ++j) launch_step(c, c->cap_stream, j);
+        for (long long j = 1; j <= c->cycle; ++j) launch_step(c, c->cap_stream, (unsigned)j);
         HIPCHK(c, hipStreamEndCapture(c->cap_stream, &g));
         hipError_t e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
         (void)hipGraphDestroy(g);
@@ -978,11 +1000,12 @@ lbm_status lbm_step_multirate(lbm_ctx* c, int64_t n, lbm_diag* diag) {
       c->k += c->cycle;
       left -= c->cycle;
     } else {
-      if (c->dim == 3 && c->koff != 0) {
-        c->ops3.set_koff(c->stream, c->d_dom, 0);
-        c->koff = 0;
+      const long long base = c->k - c->k % c->cycle;
+      if (c->dim == 3 && c->koff != base) {
+        c->ops3.set_koff(c->stream, c->d_dom, base);
+        c->koff = base;
       }
-      launch_step(c, c->stream, c->k + 1);
+      launch_step(c, c->stream, cycle_step(c, c->k + 1));
       c->k += 1;
       left -= 1;
     }
