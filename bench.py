@@ -14,7 +14,10 @@ Prints one JSON line.  ``value`` is coupled-field MLUPS
 largest share of device time per base step: its algorithmic bytes per launch
 divided by its average launch time, measured with HIP events on the stream
 the library issues its work on.  ``cpu_baseline`` times the FP64 oracle on
-a bounded sample of the same workload on one host core.
+a bounded sample of the same workload on one host core.  The default
+workload's state is cache-resident, so the line also carries
+``hbm_bound_workload``: the same measurement (two cycles) on the 256-domain
+ensemble, whose 2 GB state streams from HBM.
 """
 
 from __future__ import annotations
@@ -35,6 +38,8 @@ if ROOT not in sys.path:
 
 METRIC = ("coupled-field MLUPS + % HBM peak; FP32/FP16-store vs FP64 at stated tip-velocity error")
 HBM_PEAK_GBS = 8000.0
+DEFAULT_WORKLOAD = "solutal_512"
+HBM_WORKLOAD = "ensemble_256"
 STORAGE_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2609_25670_amd", "csrc", f)
                   for f in ("lbm_kernels.hip", "lbm_dev.h")]
@@ -66,7 +71,7 @@ def algorithmic_bytes(kind: str, d: dict, storage: str) -> int:
     U, T, F = int(d["has_U"]), int(d["has_T"]), int(d["has_flow"])
     acc = d.get("coupling", "instant") == "accum"
     dim = d["dim"]
-    qs = 5 if dim == 2 else 7            # scalar lattice
+    qs = d.get("q_scalar", 5) if dim == 2 else 7   # scalar lattice
     qf = 9 if dim == 2 else 19           # flow lattice
     if kind == "phase":      # s_1..s_{Q-1} in/out, phi in/out, U*, T*
         return 2 * (qs - 1) * s + (2 + U + T) * r
@@ -136,12 +141,55 @@ def cpu_child(workload: str, steps: int) -> None:
     print(json.dumps(dict(seconds=dt, steps=steps, sites=sites, grid=grid, mlups=sites * steps / dt / 1e6)))
 
 
+def measure(sim, wl: dict, storage: str, steps: int, warmup: int) -> dict:
+    """Time ``steps`` multirate cycles after ``warmup`` cycles (wall clock
+    between device synchronisations, and HIP events), then time each kernel
+    kind with HIP events on the library's stream.  Closes ``sim``."""
+    import torch
+
+    cyc = cycle_of(wl)
+    sites = sum(sites_of(d) for d in wl["domains"])
+    # warm-up: autotune, graph capture, clocks
+    sim.step(warmup * cyc)
+    torch.cuda.synchronize()
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    sim.step(steps * cyc)
+    ev1.record()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    diag = sim.step(0, diag=True)
+    finite = all(dd["nonfinite"] == 0 for dd in diag)
+    mlups = sites * steps * cyc / wall / 1e6
+
+    # per-kernel launch times (HIP events on the library's stream)
+    kt = sim.kernel_times(reps=200)
+    sim.close()
+    d0 = wl["domains"][0]
+    if d0["dim"] == 2 and "phase" in kt and "transfer" not in kt:   # the transfer runs inside the phase kernel
+        kt = {("phase_tr" if k == "phase" else k): v for k, v in kt.items()}
+    per_kind = {}
+    for kind, (ms, per) in kt.items():
+        nbytes = algorithmic_bytes(kind, d0, storage) * sites
+        per_kind[kind] = dict(ms_per_launch=ms, launches_per_base_step=per,
+                              alg_bytes_per_launch=nbytes,
+                              alg_GBs=nbytes / (ms * 1e-3) / 1e9 if ms > 0 else None,
+                              share_ms_per_base_step=ms * per)
+    dom_kind = max(per_kind, key=lambda k: per_kind[k]["share_ms_per_base_step"])
+    return dict(mlups=mlups, wall=wall, event_ms=ev0.elapsed_time(ev1), finite=finite, kernels=per_kind,
+                dominant=dom_kind)
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5000)
     ap.add_argument("--warmup", type=int, default=250)
-    ap.add_argument("--workload", default="solutal_512")
+    ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
+    ap.add_argument("--no-hbm-line", action="store_true",
+                    help="skip the measurement of the HBM-bound ensemble beside the default workload")
     ap.add_argument("--storage", default=None, help="override the workload's population storage")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-steps", type=int, default=384)
@@ -193,38 +241,10 @@ def main() -> int:
         sim.close()
         print(json.dumps(dict(profile_steps=args.profile_steps, workload=wl["name"], storage=storage)), flush=True)
         return 0
-    # warm-up: autotune, graph capture, clocks
-    sim.step(args.warmup * cyc)
-    torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record()
-    sim.step(args.steps * cyc)
-    ev1.record()
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    wall = t1 - t0
-    ev_ms = ev0.elapsed_time(ev1)
-    diag = sim.step(0, diag=True)
-    finite = all(dd["nonfinite"] == 0 for dd in diag)
-    base_steps = args.steps * cyc
-    mlups = sites * base_steps / wall / 1e6
-
-    # per-kernel launch times (HIP events on the library's stream)
-    kt = sim.kernel_times(reps=200)
-    sim.close()
+    m = measure(sim, wl, storage, args.steps, args.warmup)
+    mlups, wall, ev_ms, finite = m["mlups"], m["wall"], m["event_ms"], m["finite"]
+    per_kind, dom_kind = m["kernels"], m["dominant"]
     d0 = wl["domains"][0]
-    if d0["dim"] == 2 and "phase" in kt and "transfer" not in kt:   # the transfer runs inside the phase kernel
-        kt = {("phase_tr" if k == "phase" else k): v for k, v in kt.items()}
-    per_kind = {}
-    for kind, (ms, per) in kt.items():
-        nbytes = algorithmic_bytes(kind, d0, storage) * sites
-        per_kind[kind] = dict(ms_per_launch=ms, launches_per_base_step=per,
-                              alg_bytes_per_launch=nbytes,
-                              alg_GBs=nbytes / (ms * 1e-3) / 1e9 if ms > 0 else None,
-                              share_ms_per_base_step=ms * per)
-    dom_kind = max(per_kind, key=lambda k: per_kind[k]["share_ms_per_base_step"])
     knames = KERNEL_NAMES_3D if d0["dim"] == 3 else KERNEL_NAMES
     dk = per_kind[dom_kind]
     sha = kernel_source_sha()
@@ -273,6 +293,35 @@ def main() -> int:
         "event_ms_timed_region": ev_ms,
         "finite": finite,
     }
+    if args.workload == DEFAULT_WORKLOAD and not args.no_hbm_line:
+        # The default workload's state (25 MB) is cache-resident; the same
+        # measurement on the HBM-bound batched ensemble (about 2 GB) sits beside it.
+        hw = L.workload(HBM_WORKLOAD)
+        hsim = simulation_for(hw, storage=hw["storage"])
+        hm = measure(hsim, hw, hw["storage"], 2, 1)
+        finite = finite and hm["finite"]
+        hk = hm["kernels"][hm["dominant"]]
+        result["hbm_bound_workload"] = {
+            "workload": hw["name"],
+            "sites": sum(sites_of(d) for d in hw["domains"]),
+            "storage": hw["storage"],
+            "value": round(hm["mlups"], 2),
+            "unit": "MLUPS",
+            "steps": 2,
+            "base_steps_per_step": cycle_of(hw),
+            "roofline": {
+                "bound": "hbm",
+                "kernel": KERNEL_NAMES[hm["dominant"]],
+                "achieved": round(hk["alg_GBs"], 1),
+                "peak": HBM_PEAK_GBS,
+                "unit": "GB/s",
+                "frac": round(hk["alg_GBs"] / HBM_PEAK_GBS, 4),
+                "traffic": traffic_from_profiles(HBM_WORKLOAD, hm["dominant"], sha),
+            },
+            "kernels": {k: {kk: (round(vv, 6) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                        for k, v in hm["kernels"].items()},
+        }
+        result["finite"] = finite
     if rank == 0 and not args.no_cpu_baseline:
         cb = cpu_baseline(args.workload, args.cpu_steps)
         result["cpu_baseline"] = {
