@@ -24,7 +24,7 @@ enum Bc { BC_PER = 0, BC_WALL = 1, BC_INOUT = 2 };
 enum Kc {
   K_DTPHI, K_W2T, K_INVTAU0, K_EPS, K_LAM, K_MC, K_CTH, K_STH, K_INVLHCP, K_THOFF,
   K_OMK, K_OPK, K_CJ, K_CT, K_RCS, K_RCL, K_HRCS, K_HRCL, K_HKS, K_HKL, K_DTU, K_DTT,
-  K_DS, K_DL, K_U0, K_T0, K_ALPHAL, K_N
+  K_DS, K_DL, K_U0, K_T0, K_ALPHAL, K_HDRC, K_DTF, K_N
 };
 
 // Per-domain device descriptor.  Pointers address planes of px*ny elements

@@ -23,6 +23,7 @@
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <type_traits>
 
 #include "lbm_dev.h"
@@ -133,6 +134,17 @@ __device__ __forceinline__ void sto(GLOBAL __half* p, unsigned i, float v) {
 __device__ __forceinline__ void sto(GLOBAL __hip_bfloat16* p, unsigned i, float v) {
   *at((GLOBAL uint16_t*)p, i) = bf16_sr(v, i);
 }
+
+// Raw storage bits of a population plane (16-bit formats as their bit
+// patterns), so that prefetched loads are not consumed by a conversion
+// before they are needed; cvt_raw converts at the point of use.
+template <class S> struct RawT { using type = S; };
+template <> struct RawT<__half> { using type = uint16_t; };
+template <> struct RawT<__hip_bfloat16> { using type = uint16_t; };
+__device__ __forceinline__ double cvt_raw(double v, double*) { return v; }
+__device__ __forceinline__ float cvt_raw(float v, float*) { return v; }
+__device__ __forceinline__ float cvt_raw(uint16_t v, __half*) { return __half2float(__ushort_as_half(v)); }
+__device__ __forceinline__ float cvt_raw(uint16_t v, __hip_bfloat16*) { return __uint_as_float((uint32_t)v << 16); }
 
 // Reciprocal and inverse square root: the hardware approximations (about
 // 1 ulp) in the FP32 path, exact division and square root in FP64.
@@ -1657,10 +1669,11 @@ __global__ void k_tips(const Dom* __restrict__ doms, long long k, DiagOut* __res
 // Scalars on D3Q7 (w_0 = 1/4, w_i = 1/8, c_s^2 = 1/4, so the factor 3 of
 // Eq. (19), (21), (24), (40) becomes 4), flow on D3Q19, isotropic stencils
 // with D3Q19 weights, fourfold-cubic anisotropy a_s = 1 - 3 eps +
-// 4 eps sum_a n_a^4.  Each field update is two passes over the sites: the
-// collision writes its compact result (dP, K) or the nineteen flow
-// deviations to scratch planes, the streaming pass pulls them.  One thread
-// per site, x fastest, so every plane access is coalesced.
+// 4 eps sum_a n_a^4.  The phase field, the scalars and the transfer march
+// up through z in one pass with their collisions held in LDS (below).  The
+// flow is two passes over the sites: the collision writes the nineteen
+// post-collision deviations to scratch planes, the streaming pass pulls
+// them.  x is the fastest index, so every plane access is coalesced.
 //
 // D3Q7 order: 0, +x, -x, +y, -y, +z, -z.  D3Q19 order: 0, the six axes as
 // above, then (1,1,0), (-1,-1,0), (1,-1,0), (-1,1,0), (1,0,1), (-1,0,-1),
@@ -1705,21 +1718,6 @@ __device__ __forceinline__ bool site3(const Dom& D, unsigned b, unsigned t, Site
   return true;
 }
 
-// offset of the neighbour (x+dx, y+dy, z+dz) with ghost rules; mirrored
-// reports which axes were clamped at a wall
-__device__ __forceinline__ unsigned nb3(const Dom& D, const Site3& s, int dx, int dy, int dz, const int* bc,
-                                        int* mir = nullptr) {
-  const int gx = ghost(s.x + dx, D.nx, bc[0]);
-  const int gy = ghost(s.y + dy, D.ny, bc[1]);
-  const int gz = ghost(s.z + dz, D.nz, bc[2]);
-  if (mir) {
-    mir[0] = (s.x + dx < 0 || s.x + dx >= D.nx) && bc[0] != BC_PER;
-    mir[1] = (s.y + dy < 0 || s.y + dy >= D.ny) && bc[1] != BC_PER;
-    mir[2] = (s.z + dz < 0 || s.z + dz >= D.nz) && bc[2] != BC_PER;
-  }
-  return (unsigned)(((long long)gz * D.ny + gy) * D.px + gx);
-}
-
 // upstream site y - e, or false when it lies beyond a non-periodic boundary
 __device__ __forceinline__ bool up3(const Dom& D, const Site3& s, int ex, int ey, int ez, const int* bc,
                                     unsigned& o) {
@@ -1731,25 +1729,12 @@ __device__ __forceinline__ bool up3(const Dom& D, const Site3& s, int ex, int ey
   return true;
 }
 
-// isotropic gradient with D3Q19 weights: d_a f = sum_q (3 w_q) e_qa f(x + e_q)
-template <class R>
-__device__ __forceinline__ void grad3(const Dom& D, const Site3& s, const GLOBAL R* __restrict__ f, R* g) {
-  g[0] = g[1] = g[2] = R(0);
-#pragma unroll
-  for (int q = 1; q < 19; ++q) {
-    const R v = f[nb3(D, s, e19(q, 0), e19(q, 1), e19(q, 2), D.bc)];
-    const R c = q <= 6 ? R(1.0 / 6.0) : R(1.0 / 12.0);
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-      if (e19(q, a) != 0) g[a] += R(e19(q, a)) * c * v;
-  }
-}
-
 // D3Q7 phase collision: (dP, K) and A = a_s^2 from phi, its gradient, j
+// (the domain's constants in c, evaluated once on the host)
 template <class R>
-__device__ __forceinline__ void phase_collide3(const Dom& D, R phi, const R* g, const R* j, R Us, R Ts, R& dP,
-                                               R* K, R& A) {
-  const R dt = R(D.N_phi * D.dt_base), W2t = R(D.W0 * D.W0 / D.tau0), eps = R(D.eps);
+__device__ __forceinline__ void phase_collide3(const PhaseConst<R>& c, R phi, const R* g, const R* j, R Us, R Ts,
+                                               R& dP, R* K, R& A) {
+  const R dt = c.dt, W2t = c.W2t, eps = c.eps;
   const R gg = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
   R a_s = R(1), N[3] = {R(0), R(0), R(0)};
   if (gg >= R(GRAD_EPS2)) {
@@ -1768,10 +1753,10 @@ __device__ __forceinline__ void phase_collide3(const Dom& D, R phi, const R* g, 
   }
   A = a_s * a_s;
   const R om = R(1) - rcp(R(4) * dt * A * W2t + R(0.5));   // tau_phi with 1/c_s^2 = 4
-  const R theta = (Ts - R(D.T_m + D.m_L * D.C_inf)) * R(D.Cp_L / D.L_h);
+  const R theta = (Ts - c.theta_off) * c.inv_lhcp;
   const R q = R(1) - phi * phi;
-  const R Q = phi * q - R(D.lam) * (R(D.Mc) * Us + theta) * q * q;
-  dP = dt * Q * R(1.0 / D.tau0);
+  const R Q = phi * q - c.lam * (c.Mc * Us + theta) * q * q;
+  dP = dt * Q * c.inv_tau0;
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
     const R je = -W2t * N[a] * dt;
@@ -1779,311 +1764,713 @@ __device__ __forceinline__ void phase_collide3(const Dom& D, R phi, const R* g, 
   }
 }
 
-template <class R, class S>
-__global__ __launch_bounds__(256) void k3_phase_collide(const Dom* __restrict__ doms, unsigned k) {
-  const Dom& D = doms[0];
-  Site3 s;
-  if (!site3(D, blockIdx.x, threadIdx.x, s) || k % D.N_phi) return;
-  const unsigned pl = (unsigned)D.plane;
-  const int ib = par(n_phi(D, k - 1));
-  GLOBAL const R* phi = gp<const R>(D.phi[ib]);
-  GLOBAL const S* sp = gp<const S>(D.sphi[ib]);
-  const unsigned nU = (D.accum ? 0u : (k - 1) / D.N_phi) + (k - 1) / D.N_U;
-  // the U and T planes hold U - U0 and T - T0
-  const R Us = D.has_U ? (gp<const R>(D.U[par(nU)]))[s.o] + R(D.U0) : R(0);
-  const R Ts = D.has_T ? (gp<const R>(D.T[par(n_T(D, k - 1))]))[s.o] + R(D.T0) : R(D.T_m + D.m_L * D.C_inf);
-  R g[3];
-  grad3(D, s, phi, g);
-  R sv[6];
-#pragma unroll
-  for (int q = 0; q < 6; ++q) sv[q] = ld(sp, s.o + q * pl);
-  const R j[3] = {sv[0] - sv[1], sv[2] - sv[3], sv[4] - sv[5]};
-  R dP, K[3], A;
-  phase_collide3(D, phi[s.o], g, j, Us, Ts, dP, K, A);
-  GLOBAL R* scr = gp<R>(D.scr);
-  scr[s.o] = dP;
-  scr[s.o + pl] = K[0];
-  scr[s.o + 2 * pl] = K[1];
-  scr[s.o + 3 * pl] = K[2];
-  scr[s.o + 4 * pl] = A;
+// ------------------------------------------------------------ 3D single pass (z-marching)
+// One block owns a 64 x 4 column of sites over a run of z planes and walks
+// up through it plane by plane.  Per plane it puts the phase field two
+// planes ahead into a four-plane LDS window (the tile plus two rings),
+// collides the next plane on the tile plus one ring into a three-plane LDS
+// window of (dP, K), and streams the current plane from the planes below,
+// at and above.  The collisions stay in LDS instead of a scratch round trip
+// through HBM, and the loads for the next plane are issued before the
+// current plane is computed.  The arithmetic is that of the two-pass
+// kernels, term for term.
+constexpr int ZTX = 64, ZTY = 4;                  // tile: one site per thread and plane
+constexpr int ZRW = ZTX + 2, ZRH = ZTY + 2;       // collision region (ring 1)
+constexpr int ZBW = ZTX + 4, ZBH = ZTY + 4;       // phase window (ring 2)
+constexpr int ZNR = ZRW * ZRH, ZNB = ZBW * ZBH;
+constexpr int ZNBL = (ZNB + 255) / 256;           // window cells per thread
+
+__device__ __forceinline__ int zslot4(int z) { return (z + 8) & 3; }
+__device__ __forceinline__ int zslot3(int z) { return (z + 9) % 3; }
+
+// Domain geometry held in registers for the whole march (the descriptor
+// would otherwise be re-read after every store, which may alias it).
+struct ZGeo {
+  int nx, ny, nz, px, bcx, bcy, bcz;
+};
+__device__ __forceinline__ ZGeo zgeo(const Dom& D) {
+  return ZGeo{D.nx, D.ny, D.nz, D.px, D.bc[0], D.bc[1], D.bc[2]};
+}
+__device__ __forceinline__ unsigned zoff(const ZGeo& G, int x, int y, int z) {
+  return ((unsigned)z * (unsigned)G.ny + (unsigned)y) * (unsigned)G.px + (unsigned)x;
 }
 
-// anisotropic pull streaming (Eq. 26) in deviations from w_i phi(y)
+// Block -> (tile column, run of z planes).  The (run, column) pairs are
+// numbered column fastest and dealt to the 8 XCDs in contiguous ranges
+// (block b runs on XCD b mod 8), so neighbouring columns at the same height
+// share an XCD and its L2.  The grid has 8 ceil(ncol nrun / 8) blocks.
+struct ZCol {
+  int x0, y0, w, h, za, zb;
+};
+__device__ __forceinline__ bool zcol(const ZGeo& G, unsigned b, int zrun, ZCol& c) {
+  const int ntx = (G.nx + ZTX - 1) / ZTX, nty = (G.ny + ZTY - 1) / ZTY;
+  const int ncol = ntx * nty, nrun = (G.nz + zrun - 1) / zrun;
+  const int per = (ncol * nrun + 7) / 8;
+  const int i = (int)(b >> 3), L = (int)(b & 7u) * per + i;
+  if (i >= per || L >= ncol * nrun) return false;
+  const int col = L % ncol, run = L / ncol;
+  c.x0 = (col % ntx) * ZTX;
+  c.y0 = (col / ntx) * ZTY;
+  c.w = min(ZTX, G.nx - c.x0);
+  c.h = min(ZTY, G.ny - c.y0);
+  c.za = run * zrun;
+  c.zb = min(G.nz, c.za + zrun);
+  return true;
+}
+
+// region cell i of a thread (0: its own site, 1: a ring cell), in region
+// coordinates (the tile is 1..w x 1..h)
+__device__ __forceinline__ bool zcell(int i, int tid, const ZCol& c, int& lx, int& ly) {
+  if (i == 0) {
+    lx = (tid & 63) + 1;
+    ly = (tid >> 6) + 1;
+    return (tid & 63) < c.w && (tid >> 6) < c.h;
+  }
+  return ring_cell(tid, c.w, c.h, lx, ly);
+}
+
+// isotropic gradient with D3Q19 weights, d_a f = sum_q (3 w_q) e_qa f(x + e_q),
+// from the window planes z - 1, z, z + 1 around window cell cb
+template <class R>
+__device__ __forceinline__ void zgrad(const R* p0, const R* p1, const R* p2, int cb, R* g) {
+  g[0] = g[1] = g[2] = R(0);
+#pragma unroll
+  for (int q = 1; q < 19; ++q) {
+    const int ex = e19(q, 0), ey = e19(q, 1), ez = e19(q, 2);
+    const R* p = ez < 0 ? p0 : ez > 0 ? p2 : p1;
+    const R v = p[cb + ey * ZBW + ex];
+    const R cq = q <= 6 ? R(1.0 / 6.0) : R(1.0 / 12.0);
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+      if (e19(q, a) != 0) g[a] += R(e19(q, a)) * cq * v;
+  }
+}
+
+// window cells of a thread: the in-plane offset of the ghosted site (walls
+// clamp to the boundary node, periodic axes wrap)
+struct ZWinMap {
+  unsigned o[ZNBL];    // in-plane offset of the ghosted site
+};
+__device__ __forceinline__ void zwin_map(const ZGeo& G, const ZCol& c, int tid, ZWinMap& m) {
+#pragma unroll
+  for (int i = 0; i < ZNBL; ++i) {
+    const int cc = min(tid + 256 * i, ZNB - 1);
+    const int gx = ghost(c.x0 - 2 + cc % ZBW, G.nx, G.bcx), gy = ghost(c.y0 - 2 + cc / ZBW, G.ny, G.bcy);
+    m.o[i] = (unsigned)gy * (unsigned)G.px + (unsigned)gx;
+  }
+}
+template <class R>
+struct ZWin {
+  R v[ZNBL];
+};
+template <class R>
+__device__ __forceinline__ void zload_win(const ZGeo& G, const ZWinMap& m, int zw, int tid, GLOBAL const R* f,
+                                          ZWin<R>& w) {
+  const unsigned pz = (unsigned)ghost(zw, G.nz, G.bcz) * (unsigned)G.ny * (unsigned)G.px;
+#pragma unroll
+  for (int i = 0; i < ZNBL; ++i)
+    if (tid + 256 * i < ZNB) w.v[i] = ldo(f, pz + m.o[i]);
+}
+template <class R>
+__device__ __forceinline__ void zput_win(R* dst, const ZWin<R>& w, int tid) {
+#pragma unroll
+  for (int i = 0; i < ZNBL; ++i)
+    if (tid + 256 * i < ZNB) dst[tid + 256 * i] = w.v[i];
+}
+
+// region cells of a thread: region index and in-plane offset (-1: none,
+// or beyond a wall)
+struct ZRegMap {
+  int cr[2];
+  unsigned o[2];
+};
+__device__ __forceinline__ void zreg_map(const ZGeo& G, const ZCol& c, int tid, ZRegMap& m) {
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    int lx, ly;
+    m.cr[i] = -1;
+    if (!zcell(i, tid, c, lx, ly)) continue;
+    const int gx = resolve(c.x0 - 1 + lx, G.nx, G.bcx), gy = resolve(c.y0 - 1 + ly, G.ny, G.bcy);
+    if (gx < 0 || gy < 0) continue;
+    m.cr[i] = ly * ZRW + lx;
+    m.o[i] = (unsigned)gy * (unsigned)G.px + (unsigned)gx;
+  }
+}
+__device__ __forceinline__ int zbox(int cr) { return (cr / ZRW + 1) * ZBW + cr % ZRW + 1; }
+
+// raw loads of the phase collision inputs of a plane's region cells
 template <class R, class S>
-__global__ __launch_bounds__(256) void k3_phase_stream(const Dom* __restrict__ doms, unsigned k) {
+struct ZPhaseIn {
+  typename RawT<S>::type s[2][6];
+  R U[2], T[2];
+};
+template <class R, class S>
+__device__ __forceinline__ void zload_phase(const ZGeo& G, const ZRegMap& m, int zc, long long pl,
+                                            GLOBAL const typename RawT<S>::type* sp, GLOBAL const R* Up,
+                                            GLOBAL const R* Tp, ZPhaseIn<R, S>& in) {
+  const int gz = resolve(zc, G.nz, G.bcz);
+  if (gz < 0) return;
+  const unsigned pz = (unsigned)gz * (unsigned)G.ny * (unsigned)G.px;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    if (m.cr[i] < 0) continue;
+    const unsigned o = pz + m.o[i];
+#pragma unroll
+    for (int q = 0; q < 6; ++q) in.s[i][q] = *at(plane(sp, q * pl), o);
+    if (Up) in.U[i] = ldo(Up, o);
+    if (Tp) in.T[i] = ldo(Tp, o);
+  }
+}
+
+template <class R, class S>
+__global__ __launch_bounds__(256) void k3z_phase(const Dom* __restrict__ doms, unsigned k, int zrun) {
+  using SR = typename RawT<S>::type;
+  __shared__ R wphi[4][ZNB];
+  __shared__ R wcol[3][4][ZNR];   // dP, Kx, Ky, Kz per region cell
   const Dom& D = doms[0];
-  Site3 s;
-  if (!site3(D, blockIdx.x, threadIdx.x, s) || k % D.N_phi) return;
-  const unsigned pl = (unsigned)D.plane;
+  const ZGeo G = zgeo(D);
+  ZCol c;
+  if (!zcol(G, blockIdx.x, zrun, c) || k % D.N_phi) return;
+  const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
+  const long long pl = D.plane;
   const int ib = par(n_phi(D, k - 1)), ob = ib ^ 1;
   GLOBAL const R* phi = gp<const R>(D.phi[ib]);
-  GLOBAL const S* sp = gp<const S>(D.sphi[ib]);
-  GLOBAL const R* scr = gp<const R>(D.scr);
-  const R py = phi[s.o];
-  const R dPy = scr[s.o], Ky[3] = {scr[s.o + pl], scr[s.o + 2 * pl], scr[s.o + 3 * pl]};
-  const R A = scr[s.o + 4 * pl], iA = rcp(A), oA = R(1) - A;
-  R sv[6], s0 = R(0);
-#pragma unroll
-  for (int q = 0; q < 6; ++q) {
-    sv[q] = ld(sp, s.o + q * pl);
-    s0 -= sv[q];
-  }
-  R dn[7], sum;
-  dn[0] = (dPy * R(0.25) - oA * s0) * iA;
-  sum = dn[0];
-#pragma unroll
-  for (int q = 1; q < 7; ++q) {
-    const int ex = e19(q, 0), ey = e19(q, 1), ez = e19(q, 2);
-    unsigned o;
-    R dpost;
-    if (up3(D, s, ex, ey, ez, D.bc, o)) {
-      const R Ke = R(ex) * scr[o + pl] + R(ey) * scr[o + 2 * pl] + R(ez) * scr[o + 3 * pl];
-      dpost = (phi[o] - py + scr[o]) * R(0.125) + R(0.5) * Ke;
-    } else {
-      dpost = dPy * R(0.125) - R(0.5) * (R(ex) * Ky[0] + R(ey) * Ky[1] + R(ez) * Ky[2]);
-    }
-    dn[q] = (dpost - oA * sv[q - 1]) * iA;
-    sum += dn[q];
-  }
-  (gp<R>(D.phi[ob]))[s.o] = py + sum;
-  GLOBAL S* so = gp<S>(D.sphi[ob]);
-#pragma unroll
-  for (int q = 1; q < 7; ++q) st(so, s.o + (q - 1) * pl, dn[q] - R(0.125) * sum);
-}
-
-// transfer, pass 1: J = W0/(2 sqrt2) [1 + (1-k) U*] dphi n^{q+1} (Eq. 37)
-template <class R>
-__global__ __launch_bounds__(256) void k3_transfer_J(const Dom* __restrict__ doms, unsigned k) {
-  const Dom& D = doms[0];
-  Site3 s;
-  if (!site3(D, blockIdx.x, threadIdx.x, s) || k % D.N_phi || !D.has_U) return;
-  const unsigned pl = (unsigned)D.plane;
-  GLOBAL const R* pn = gp<const R>(D.phi[par(n_phi(D, k))]);
-  GLOBAL const R* po = gp<const R>(D.phi[par(n_phi(D, k - 1))]);
+  GLOBAL const SR* sp = gp<const SR>(D.sphi[ib]);
+  GLOBAL R* phi_out = gp<R>(D.phi[ob]);
+  GLOBAL S* s_out = gp<S>(D.sphi[ob]);
   const unsigned nU = (D.accum ? 0u : (k - 1) / D.N_phi) + (k - 1) / D.N_U;
-  GLOBAL const R* Uin = gp<const R>(D.U[par(nU)]);
-  R g[3];
-  grad3(D, s, pn, g);
-  const R gg = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
-  R J[3] = {R(0), R(0), R(0)};
-  if (gg >= R(GRAD_EPS2)) {
-    const R a = R(D.W0 / (2.0 * 1.4142135623730951)) * (R(1) + R(1.0 - D.kc) * (Uin[s.o] + R(D.U0))) *
-                (pn[s.o] - po[s.o]) * rsq(gg);
-#pragma unroll
-    for (int c = 0; c < 3; ++c) J[c] = -a * g[c];
-  }
-  GLOBAL R* scr = gp<R>(D.scr);
-#pragma unroll
-  for (int c = 0; c < 3; ++c) scr[s.o + c * pl] = J[c];
-}
+  GLOBAL const R* Up = D.has_U ? gp<const R>(D.U[par(nU)]) : nullptr;
+  GLOBAL const R* Tp = D.has_T ? gp<const R>(D.T[par(n_T(D, k - 1))]) : nullptr;
+  const PhaseConst<R> pc = phase_const<R>(D);
+  const R U0 = kc<R>(D, K_U0), T0 = kc<R>(D, K_T0);
+  const bool own = tx < c.w && ty < c.h;
+  const int gx = c.x0 + tx, gy = c.y0 + ty;
+  ZWinMap wm;
+  zwin_map(G, c, tid, wm);
+  ZRegMap rm;
+  zreg_map(G, c, tid, rm);
+  // upstream neighbours of the own site in x and y (false: beyond a wall)
+  const bool upx[2] = {resolve(gx - 1, G.nx, G.bcx) >= 0, resolve(gx + 1, G.nx, G.bcx) >= 0};
+  const bool upy[2] = {resolve(gy - 1, G.ny, G.bcy) >= 0, resolve(gy + 1, G.ny, G.bcy) >= 0};
 
-// transfer, pass 2: compact divergence (ghost J mirrored with the normal
-// component negated), dU and dT of Eq. (38), injection (Eq. 39)
-template <class R>
-__global__ __launch_bounds__(256) void k3_transfer_apply(const Dom* __restrict__ doms, unsigned k,
-                                                          Partial* __restrict__ part) {
-  __shared__ R red[4];
-  const Dom& D = doms[0];
-  Site3 s;
-  const bool ok = site3(D, blockIdx.x, threadIdx.x, s);
-  if (k % D.N_phi) return;
-  const unsigned pl = (unsigned)D.plane;
-  GLOBAL const R* pn = gp<const R>(D.phi[par(n_phi(D, k))]);
-  GLOBAL const R* po = gp<const R>(D.phi[par(n_phi(D, k - 1))]);
-  R amax = R(0);
-  if (ok) {
-    const R p1 = pn[s.o], dphi = p1 - po[s.o];
-    if (D.has_U) {
-      const unsigned nU = (D.accum ? 0u : (k - 1) / D.N_phi) + (k - 1) / D.N_U;
-      GLOBAL const R* Uin = gp<const R>(D.U[par(nU)]);
-      GLOBAL const R* J = gp<const R>(D.scr);
-      R div = R(0);
+  // collide plane zc on the region from its loaded inputs and the window
+  // planes zc - 1, zc, zc + 1; the own site's A and deviations are returned
+  auto collide = [&](const ZPhaseIn<R, S>& in, int zc, R& Aown, R* svown) {
+    if (resolve(zc, G.nz, G.bcz) < 0) return;   // beyond a wall: never pulled from
+    const R* p0 = wphi[zslot4(zc - 1)];
+    const R* p1 = wphi[zslot4(zc)];
+    const R* p2 = wphi[zslot4(zc + 1)];
+    R* out = &wcol[zslot3(zc)][0][0];
 #pragma unroll
-      for (int q = 1; q < 19; ++q) {
-        int mir[3];
-        const unsigned o = nb3(D, s, e19(q, 0), e19(q, 1), e19(q, 2), D.bc, mir);
-        const R c = q <= 6 ? R(1.0 / 6.0) : R(1.0 / 12.0);
+    for (int i = 0; i < 2; ++i) {
+      if (rm.cr[i] < 0) continue;
+      const int cr = rm.cr[i], cb = zbox(cr);
+      R g[3];
+      zgrad(p0, p1, p2, cb, g);
+      R sv[6];
 #pragma unroll
-        for (int a = 0; a < 3; ++a)
-          if (e19(q, a) != 0) {
-            const R v = J[o + a * pl];
-            div += R(e19(q, a)) * c * (mir[a] ? -v : v);
-          }
-      }
-      const R Us = Uin[s.o];   // U - U0
-      const R dU = ((R(1) + R(1.0 - D.kc) * (Us + R(D.U0))) * dphi - R(2) * div) *
-                   rcp(R(1.0 + D.kc) - R(1.0 - D.kc) * p1);
-      amax = fabs(dU);
-      if (D.accum) {
-        GLOBAL R* PU = gp<R>(D.PU);
-        PU[s.o] = PU[s.o] + dU;
-      } else {
-        (gp<R>(D.U[par(nU + 1)]))[s.o] = Us + dU;
+      for (int q = 0; q < 6; ++q) sv[q] = cvt_raw(in.s[i][q], (S*)nullptr);
+      const R j[3] = {sv[0] - sv[1], sv[2] - sv[3], sv[4] - sv[5]};
+      const R Us = Up ? in.U[i] + U0 : R(0);
+      const R Ts = Tp ? in.T[i] + T0 : pc.theta_off;
+      R dP, K[3], A;
+      phase_collide3(pc, p1[cb], g, j, Us, Ts, dP, K, A);
+      out[cr] = dP;
+      out[ZNR + cr] = K[0];
+      out[2 * ZNR + cr] = K[1];
+      out[3 * ZNR + cr] = K[2];
+      if (i == 0) {
+        Aown = A;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) svown[q] = sv[q];
       }
     }
-    if (D.has_T && !D.T_pulled) {
-      const R rc = (R(1) + p1) * R(0.5 * D.rcS) + (R(1) - p1) * R(0.5 * D.rcL);
-      const R dT = R(D.rho_L * D.L_h) * dphi * rcp(R(2) * rc);
-      if (D.accum) {
-        GLOBAL R* PT = gp<R>(D.PT);
-        PT[s.o] = PT[s.o] + dT;
-      } else {
-        gp<R>(D.T[par(n_T(D, k - 1) + 1)])[s.o] = gp<const R>(D.T[par(n_T(D, k - 1))])[s.o] + dT;
-      }
-    }
+  };
+
+  // prologue: window planes za - 2 .. za + 1, collisions of za - 1 and za
+  R Acur = R(1), Anext = R(1), svcur[6], svnext[6];
+  ZPhaseIn<R, S> in0, in1;
+  {
+    ZWin<R> w0, w1, w2, w3;
+    zload_win(G, wm, c.za - 2, tid, phi, w0);
+    zload_win(G, wm, c.za - 1, tid, phi, w1);
+    zload_win(G, wm, c.za, tid, phi, w2);
+    zload_win(G, wm, c.za + 1, tid, phi, w3);
+    zload_phase(G, rm, c.za - 1, pl, sp, Up, Tp, in0);
+    zload_phase(G, rm, c.za, pl, sp, Up, Tp, in1);
+    zput_win(wphi[zslot4(c.za - 2)], w0, tid);
+    zput_win(wphi[zslot4(c.za - 1)], w1, tid);
+    zput_win(wphi[zslot4(c.za)], w2, tid);
+    zput_win(wphi[zslot4(c.za + 1)], w3, tid);
   }
-  if (part && D.has_U) {
-    for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_down(amax, off, 64));
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = amax;
+  __syncthreads();
+  collide(in0, c.za - 1, Anext, svnext);
+  collide(in1, c.za, Acur, svcur);
+  ZWin<R> wn;
+  zload_win(G, wm, c.za + 2, tid, phi, wn);
+  zload_phase(G, rm, c.za + 1, pl, sp, Up, Tp, in0);
+  __syncthreads();
+
+  for (int z = c.za; z < c.zb; ++z) {
+    zput_win(wphi[zslot4(z + 2)], wn, tid);
+    const ZPhaseIn<R, S> cur = in0;
+    if (z + 1 < c.zb) {   // prefetch for the next plane
+      zload_win(G, wm, z + 3, tid, phi, wn);
+      zload_phase(G, rm, z + 2, pl, sp, Up, Tp, in0);
+    }
     __syncthreads();
-    if (threadIdx.x == 0) {
-      const R m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
-      part[blockIdx.x].S_phi = double(m);
-      if (!D.accum) part[blockIdx.x].J_U = double(m);
+    collide(cur, z + 1, Anext, svnext);   // the plane above: its halo for this plane
+    __syncthreads();
+    if (own) {
+      // anisotropic pull streaming (Eq. 26) in deviations from w_i phi(y)
+      const int cr = (ty + 1) * ZRW + tx + 1, cb = (ty + 2) * ZBW + tx + 2;
+      const R* c1 = &wcol[zslot3(z)][0][0];
+      const R py = wphi[zslot4(z)][cb];
+      const R dPy = c1[cr], Ky[3] = {c1[ZNR + cr], c1[2 * ZNR + cr], c1[3 * ZNR + cr]};
+      const R A = Acur, iA = rcp(A), oA = R(1) - A;
+      const bool upz[2] = {resolve(z - 1, G.nz, G.bcz) >= 0, resolve(z + 1, G.nz, G.bcz) >= 0};
+      R s0 = R(0);
+#pragma unroll
+      for (int q = 0; q < 6; ++q) s0 -= svcur[q];
+      R dn[7], sum;
+      dn[0] = (dPy * R(0.25) - oA * s0) * iA;
+      sum = dn[0];
+#pragma unroll
+      for (int q = 1; q < 7; ++q) {
+        const int ex = e19(q, 0), ey = e19(q, 1), ez = e19(q, 2);
+        const bool up = ex > 0 ? upx[0] : ex < 0 ? upx[1] : ey > 0 ? upy[0] : ey < 0 ? upy[1] : ez > 0 ? upz[0] : upz[1];
+        R dpost;
+        if (up) {
+          const R* cu = &wcol[zslot3(z - ez)][0][0];
+          const int ur = cr - ey * ZRW - ex;
+          const R Ke = R(ex) * cu[ZNR + ur] + R(ey) * cu[2 * ZNR + ur] + R(ez) * cu[3 * ZNR + ur];
+          dpost = (wphi[zslot4(z - ez)][cb - ey * ZBW - ex] - py + cu[ur]) * R(0.125) + R(0.5) * Ke;
+        } else {
+          dpost = dPy * R(0.125) - R(0.5) * (R(ex) * Ky[0] + R(ey) * Ky[1] + R(ez) * Ky[2]);
+        }
+        dn[q] = (dpost - oA * svcur[q - 1]) * iA;
+        sum += dn[q];
+      }
+      const unsigned o = zoff(G, gx, gy, z);
+      sto(phi_out, o, py + sum);
+#pragma unroll
+      for (int q = 1; q < 7; ++q) sto(plane(s_out, (q - 1) * pl), o, dn[q] - R(0.125) * sum);
+    }
+    Acur = Anext;
+#pragma unroll
+    for (int q = 0; q < 6; ++q) svcur[q] = svnext[q];
+    __syncthreads();
+  }
+}
+
+// raw loads of the scalar collision inputs of a plane's region cells
+template <class R, class S>
+struct ZScalIn {
+  R chi[2];
+  typename RawT<S>::type j[2][3];
+  R u[2][3];
+};
+template <class R, class S>
+__device__ __forceinline__ void zload_scal(const ZGeo& G, const ZRegMap& m, int zc, long long pl, GLOBAL const R* cin,
+                                           GLOBAL const typename RawT<S>::type* jin, GLOBAL const R* vel,
+                                           ZScalIn<R, S>& in) {
+  const int gz = resolve(zc, G.nz, G.bcz);
+  if (gz < 0) return;
+  const unsigned pz = (unsigned)gz * (unsigned)G.ny * (unsigned)G.px;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    if (m.cr[i] < 0) continue;
+    const unsigned o = pz + m.o[i];
+    in.chi[i] = ldo(cin, o);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) in.j[i][a] = *at(plane(jin, a * pl), o);
+    if (vel) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) in.u[i][a] = ldo(plane(vel, a * pl), o);
     }
   }
 }
 
-// scalar transport (U: FIELD 0, T: FIELD 1), pass 1: collision to (dP, K)
+// scalar transport (U: FIELD 0, T: FIELD 1) in one pass: collision to
+// (dP, K) on the region of the plane above, pull streaming (Eq. 25) of the
+// current plane with bounce-back, or anti-bounce-back to the moving
+// profile on the z walls of the pulled T
 template <class R, class S, int FIELD>
-__global__ __launch_bounds__(256) void k3_scalar_collide(const Dom* __restrict__ doms, unsigned k) {
-  const Dom& D = doms[0];
-  const int N = FIELD == 0 ? D.N_U : D.N_T;
-  Site3 s;
-  if (!site3(D, blockIdx.x, threadIdx.x, s) || k % N) return;
-  const unsigned pl = (unsigned)D.plane;
-  GLOBAL const R* cin;
-  GLOBAL const S* jin;
-  if (FIELD == 0) {
-    cin = gp<const R>(D.U[par((D.accum ? 0 : k / D.N_phi) + (k - 1) / D.N_U)]);
-    jin = gp<const S>(D.jU[par(n_jU(D, k - 1))]);
-  } else {
-    cin = gp<const R>(D.T[par(n_Ttr(D, k) + (k - 1) / D.N_T)]);
-    jin = gp<const S>(D.jT[par(n_jT(D, k - 1))]);
-  }
-  GLOBAL const R* phis = gp<const R>(D.phi[par(n_phi(D, k))]);
-  const R dt = R(N * D.dt_base);
-  const R chi = cin[s.o] + R(FIELD == 0 ? D.U0 : D.T0);   // the plane holds chi - chi_ref
-  R u[3] = {R(0), R(0), R(0)};
-  if (D.has_F) {
-    GLOBAL const R* vel = gp<const R>(D.vel[par(n_F(D, k - 1))]);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) u[a] = vel[s.o + a * pl];
-  }
-  if (FIELD == 1 && D.T_pulled) u[2] += R(D.V_pull);
-  R j[3], je[3];
-#pragma unroll
-  for (int a = 0; a < 3; ++a) {
-    j[a] = ld(jin, s.o + a * pl);
-    je[a] = chi * u[a] * dt;
-  }
-  R itau, Q = R(0);
-  const bool var = FIELD == 0 || D.T_var;
-  if (var) {
-    const R phi = phis[s.o];
-    R gp[3];
-    grad3(D, s, phis, gp);
-    R coeff, pre;
-    if (FIELD == 0) {
-      const R ikf = rcp(R(1.0 + D.kc) - R(1.0 - D.kc) * phi);
-      coeff = ((R(1) + phi) * R(D.D_S) + (R(1) - phi) * R(D.D_L)) * ikf;            // Eq. (7)
-      pre = -R(1.0 - D.kc) * coeff * ikf;                                              // Eq. (8), 1st term
-    } else {
-      const R irc = rcp((R(1) + phi) * R(0.5 * D.rcS) + (R(1) - phi) * R(0.5 * D.rcL));
-      coeff = ((R(1) + phi) * R(0.5 * D.kS) + (R(1) - phi) * R(0.5 * D.kL)) * irc;   // Eq. (11)
-      pre = R(D.rcS - D.rcL) * R(0.5) * irc * coeff;                                  // Eq. (12), 1st term
-    }
-    itau = rcp(R(4) * dt * coeff + R(0.5));
-    R gdot = R(0);
-#pragma unroll
-    for (int a = 0; a < 3; ++a) gdot += -R(4) * itau * (j[a] - je[a]) * gp[a];     // Eq. (40), D3Q7
-    Q = pre * gdot;
-  } else {
-    itau = rcp(R(4) * dt * R(D.kL / D.rcL) + R(0.5));
-  }
-  const R om = R(1) - itau;
-  GLOBAL R* scr = gp<R>(D.scr);
-  scr[s.o] = dt * Q;
-#pragma unroll
-  for (int a = 0; a < 3; ++a) scr[s.o + (a + 1) * pl] = je[a] + om * (j[a] - je[a]);
-}
-
-// scalar transport, pass 2: pull streaming (Eq. 25) with bounce-back, or
-// anti-bounce-back to the moving profile on the z walls of the pulled T
-template <class R, class S, int FIELD>
-__global__ __launch_bounds__(256) void k3_scalar_stream(const Dom* __restrict__ doms, unsigned k,
-                                                         Partial* __restrict__ part) {
+__global__ __launch_bounds__(256) void k3z_scalar(const Dom* __restrict__ doms, unsigned k, int zrun,
+                                                  Partial* __restrict__ part) {
+  using SR = typename RawT<S>::type;
+  __shared__ R wphi[4][ZNB];
+  __shared__ R wchi[3][ZNR];
+  __shared__ R wcol[3][4][ZNR];   // dP, Kx, Ky, Kz per region cell
   __shared__ R red[4];
   const Dom& D = doms[0];
+  const ZGeo G = zgeo(D);
   const int N = FIELD == 0 ? D.N_U : D.N_T;
-  Site3 s;
-  const bool ok = site3(D, blockIdx.x, threadIdx.x, s);
-  if (k % N) return;
-  const unsigned pl = (unsigned)D.plane;
+  ZCol c;
+  if (!zcol(G, blockIdx.x, zrun, c) || k % N) return;
+  const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
+  const long long pl = D.plane;
   GLOBAL const R* cin;
   GLOBAL R* cout;
+  GLOBAL const SR* jin;
   GLOBAL S* jout;
   GLOBAL R* pend;
   if (FIELD == 0) {
     const unsigned nU = (D.accum ? 0u : k / D.N_phi) + (k - 1) / D.N_U;
     cin = gp<const R>(D.U[par(nU)]);
     cout = gp<R>(D.U[par(nU + 1)]);
+    jin = gp<const SR>(D.jU[par(n_jU(D, k - 1))]);
     jout = gp<S>(D.jU[par(n_jU(D, k))]);
     pend = gp<R>(D.PU);
   } else {
     cin = gp<const R>(D.T[par(n_Ttr(D, k) + (k - 1) / D.N_T)]);
     cout = gp<R>(D.T[par(n_Ttr(D, k) + k / D.N_T)]);
+    jin = gp<const SR>(D.jT[par(n_jT(D, k - 1))]);
     jout = gp<S>(D.jT[par(n_jT(D, k))]);
     pend = gp<R>(D.PT);
   }
-  GLOBAL const R* scr = gp<const R>(D.scr);
-  R amax = R(0);
-  if (ok) {
-    const R cy = cin[s.o], dPy = scr[s.o];
-    const R Ky[3] = {scr[s.o + pl], scr[s.o + 2 * pl], scr[s.o + 3 * pl]};
-    const bool dir = FIELD == 1 && (D.T_pulled || D.T_dirlow);
-    const R tmid = R((double(k + D.koff) - 0.5 * N) * D.dt_base);
-    R dq[7];
-    dq[0] = dPy * R(0.25);
-    R chin = dq[0], j[3] = {R(0), R(0), R(0)};
+  GLOBAL const R* phis = gp<const R>(D.phi[par(n_phi(D, k))]);
+  GLOBAL const R* vel = D.has_F ? gp<const R>(D.vel[par(n_F(D, k - 1))]) : nullptr;
+  const bool var = FIELD == 0 || D.T_var;
+  const bool accum = D.accum;
+  const R dt = kc<R>(D, FIELD == 0 ? K_DTU : K_DTT);
+  const R cref = kc<R>(D, FIELD == 0 ? K_U0 : K_T0);
+  const R omk = kc<R>(D, K_OMK), opk = kc<R>(D, K_OPK), DS = kc<R>(D, K_DS), DL = kc<R>(D, K_DL);
+  const R hrcS = kc<R>(D, K_HRCS), hrcL = kc<R>(D, K_HRCL), hkS = kc<R>(D, K_HKS), hkL = kc<R>(D, K_HKL);
+  const R hdrc = kc<R>(D, K_HDRC);
+  const R itau_const = rcp(R(4) * dt * kc<R>(D, K_ALPHAL) + R(0.5));
+  const R vpull = FIELD == 1 && D.T_pulled ? R(D.V_pull) : R(0);
+  // the walls of the pulled T and of the cold bottom (anti-bounce-back)
+  const bool dir = FIELD == 1 && (D.T_pulled || D.T_dirlow), pulled = FIELD == 1 && D.T_pulled;
+  const R tmid = R((double(k + D.koff) - 0.5 * N) * D.dt_base);
+  const R Tw_lo = pulled ? R(D.T_grad) * (R(-0.5) - R(D.z_front) - R(D.V_pull) * tmid) : R(0);   // T_w - T0
+  const R Tw_hi = pulled ? R(D.T_grad) * (R(G.nz - 0.5) - R(D.z_front) - R(D.V_pull) * tmid) : R(0);
+  const bool own = tx < c.w && ty < c.h;
+  const int gx = c.x0 + tx, gy = c.y0 + ty;
+  ZWinMap wm;
+  zwin_map(G, c, tid, wm);
+  ZRegMap rm;
+  zreg_map(G, c, tid, rm);
+  const bool upx[2] = {resolve(gx - 1, G.nx, G.bcx) >= 0, resolve(gx + 1, G.nx, G.bcx) >= 0};
+  const bool upy[2] = {resolve(gy - 1, G.ny, G.bcy) >= 0, resolve(gy + 1, G.ny, G.bcy) >= 0};
+
+  auto collide = [&](const ZScalIn<R, S>& in, int zc) {
+    if (resolve(zc, G.nz, G.bcz) < 0) return;   // beyond a wall: never pulled from
+    const R* p0 = wphi[zslot4(zc - 1)];
+    const R* p1 = wphi[zslot4(zc)];
+    const R* p2 = wphi[zslot4(zc + 1)];
+    R* out = &wcol[zslot3(zc)][0][0];
+    R* cw = wchi[zslot3(zc)];
 #pragma unroll
-    for (int q = 1; q < 7; ++q) {
-      const int ex = e19(q, 0), ey = e19(q, 1), ez = e19(q, 2);
-      unsigned o;
-      if (up3(D, s, ex, ey, ez, D.bc, o)) {
-        const R Ke = R(ex) * scr[o + pl] + R(ey) * scr[o + 2 * pl] + R(ez) * scr[o + 3 * pl];
-        dq[q] = (cin[o] - cy + scr[o]) * R(0.125) + R(0.5) * Ke;
-      } else {
-        const R Ke = R(ex) * Ky[0] + R(ey) * Ky[1] + R(ez) * Ky[2];
-        if (dir && (ez > 0 || (ez < 0 && D.T_pulled))) {
-          const R zw = ez > 0 ? R(-0.5) : R(D.nz - 0.5);
-          const R Tw = D.T_pulled ? R(D.T_grad) * (zw - R(D.z_front) - R(D.V_pull) * tmid) : R(0);   // T_w - T0
-          dq[q] = R(0.125) * (R(2) * Tw - R(2) * cy - dPy) + R(0.5) * Ke;
-        } else {
-          dq[q] = dPy * R(0.125) - R(0.5) * Ke;
-        }
+    for (int i = 0; i < 2; ++i) {
+      if (rm.cr[i] < 0) continue;
+      const int cr = rm.cr[i];
+      const R chi = in.chi[i] + cref;   // the plane holds chi - chi_ref
+      R u[3] = {R(0), R(0), R(0)};
+      if (vel) {
+#pragma unroll
+        for (int a = 0; a < 3; ++a) u[a] = in.u[i][a];
       }
-      chin += dq[q];
-      j[0] += R(ex) * dq[q];
-      j[1] += R(ey) * dq[q];
-      j[2] += R(ez) * dq[q];
-    }
-    chin += cy;
-    if (D.accum) {
-      const R p = pend[s.o];
-      chin += p;
-      pend[s.o] = R(0);
-      amax = fabs(p);
-    }
-    cout[s.o] = chin;
+      if (FIELD == 1 && pulled) u[2] += vpull;
+      R j[3], je[3];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) st(jout, s.o + a * pl, j[a]);
+      for (int a = 0; a < 3; ++a) {
+        j[a] = cvt_raw(in.j[i][a], (S*)nullptr);
+        je[a] = chi * u[a] * dt;
+      }
+      R itau, Q = R(0);
+      if (var) {
+        const int cb = zbox(cr);
+        const R phi = p1[cb];
+        R g[3];
+        zgrad(p0, p1, p2, cb, g);
+        R coeff, pre;
+        if (FIELD == 0) {
+          const R ikf = rcp(opk - omk * phi);
+          coeff = ((R(1) + phi) * DS + (R(1) - phi) * DL) * ikf;            // Eq. (7)
+          pre = -omk * coeff * ikf;                                          // Eq. (8), 1st term
+        } else {
+          const R irc = rcp((R(1) + phi) * hrcS + (R(1) - phi) * hrcL);
+          coeff = ((R(1) + phi) * hkS + (R(1) - phi) * hkL) * irc;          // Eq. (11)
+          pre = hdrc * irc * coeff;                                          // Eq. (12), 1st term
+        }
+        itau = rcp(R(4) * dt * coeff + R(0.5));
+        R gdot = R(0);
+#pragma unroll
+        for (int a = 0; a < 3; ++a) gdot += -R(4) * itau * (j[a] - je[a]) * g[a];   // Eq. (40), D3Q7
+        Q = pre * gdot;
+      } else {
+        itau = itau_const;
+      }
+      const R om = R(1) - itau;
+      cw[cr] = in.chi[i];
+      out[cr] = dt * Q;
+#pragma unroll
+      for (int a = 0; a < 3; ++a) out[(a + 1) * ZNR + cr] = je[a] + om * (j[a] - je[a]);
+    }
+  };
+
+  R amax = R(0);
+  ZScalIn<R, S> in0, in1;
+  {
+    ZWin<R> w0, w1, w2, w3;
+    if (var) {
+      zload_win(G, wm, c.za - 2, tid, phis, w0);
+      zload_win(G, wm, c.za - 1, tid, phis, w1);
+      zload_win(G, wm, c.za, tid, phis, w2);
+      zload_win(G, wm, c.za + 1, tid, phis, w3);
+    }
+    zload_scal(G, rm, c.za - 1, pl, cin, jin, vel, in0);
+    zload_scal(G, rm, c.za, pl, cin, jin, vel, in1);
+    if (var) {
+      zput_win(wphi[zslot4(c.za - 2)], w0, tid);
+      zput_win(wphi[zslot4(c.za - 1)], w1, tid);
+      zput_win(wphi[zslot4(c.za)], w2, tid);
+      zput_win(wphi[zslot4(c.za + 1)], w3, tid);
+    }
   }
-  if (FIELD == 0 && D.accum && part) {
-    for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_down(amax, off, 64));
-    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = amax;
+  __syncthreads();
+  collide(in0, c.za - 1);
+  collide(in1, c.za);
+  ZWin<R> wn;
+  if (var) zload_win(G, wm, c.za + 2, tid, phis, wn);
+  zload_scal(G, rm, c.za + 1, pl, cin, jin, vel, in0);
+  __syncthreads();
+
+  for (int z = c.za; z < c.zb; ++z) {
+    if (var) zput_win(wphi[zslot4(z + 2)], wn, tid);
+    const ZScalIn<R, S> cur = in0;
+    if (z + 1 < c.zb) {   // prefetch for the next plane
+      if (var) zload_win(G, wm, z + 3, tid, phis, wn);
+      zload_scal(G, rm, z + 2, pl, cin, jin, vel, in0);
+    }
     __syncthreads();
-    if (threadIdx.x == 0) part[blockIdx.x].J_U = double(fmax(fmax(red[0], red[1]), fmax(red[2], red[3])));
+    collide(cur, z + 1);
+    __syncthreads();
+    if (own) {
+      const int cr = (ty + 1) * ZRW + tx + 1;
+      const R* c1 = &wcol[zslot3(z)][0][0];
+      const R cy = wchi[zslot3(z)][cr], dPy = c1[cr];
+      const R Ky[3] = {c1[ZNR + cr], c1[2 * ZNR + cr], c1[3 * ZNR + cr]};
+      const bool upz[2] = {resolve(z - 1, G.nz, G.bcz) >= 0, resolve(z + 1, G.nz, G.bcz) >= 0};
+      R dq[7];
+      dq[0] = dPy * R(0.25);
+      R chin = dq[0], j[3] = {R(0), R(0), R(0)};
+#pragma unroll
+      for (int q = 1; q < 7; ++q) {
+        const int ex = e19(q, 0), ey = e19(q, 1), ez = e19(q, 2);
+        const bool up = ex > 0 ? upx[0] : ex < 0 ? upx[1] : ey > 0 ? upy[0] : ey < 0 ? upy[1] : ez > 0 ? upz[0] : upz[1];
+        if (up) {
+          const R* cu = &wcol[zslot3(z - ez)][0][0];
+          const int ur = cr - ey * ZRW - ex;
+          const R Ke = R(ex) * cu[ZNR + ur] + R(ey) * cu[2 * ZNR + ur] + R(ez) * cu[3 * ZNR + ur];
+          dq[q] = (wchi[zslot3(z - ez)][ur] - cy + cu[ur]) * R(0.125) + R(0.5) * Ke;
+        } else {
+          const R Ke = R(ex) * Ky[0] + R(ey) * Ky[1] + R(ez) * Ky[2];
+          if (dir && (ez > 0 || (ez < 0 && pulled))) {
+            const R Tw = ez > 0 ? Tw_lo : Tw_hi;
+            dq[q] = R(0.125) * (R(2) * Tw - R(2) * cy - dPy) + R(0.5) * Ke;
+          } else {
+            dq[q] = dPy * R(0.125) - R(0.5) * Ke;
+          }
+        }
+        chin += dq[q];
+        j[0] += R(ex) * dq[q];
+        j[1] += R(ey) * dq[q];
+        j[2] += R(ez) * dq[q];
+      }
+      chin += cy;
+      const unsigned o = zoff(G, gx, gy, z);
+      if (accum) {
+        const R p = ldo(pend, o);
+        chin += p;
+        sto(pend, o, R(0));
+        amax = fmax(amax, fabs(p));
+      }
+      sto(cout, o, chin);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) sto(plane(jout, a * pl), o, j[a]);
+    }
+    __syncthreads();
+  }
+  if (FIELD == 0 && accum && part) {
+    for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_down(amax, off, 64));
+    if ((tid & 63) == 0) red[tid >> 6] = amax;
+    __syncthreads();
+    if (tid == 0) part[blockIdx.x].J_U = double(fmax(fmax(red[0], red[1]), fmax(red[2], red[3])));
+  }
+}
+
+// raw loads of the transfer inputs of a plane's region cells
+template <class R>
+struct ZTrIn {
+  R po[2], U[2], T;
+};
+template <class R>
+__device__ __forceinline__ void zload_tr(const ZGeo& G, const ZRegMap& m, int zc, GLOBAL const R* po,
+                                         GLOBAL const R* Uin, GLOBAL const R* Tin, bool own, ZTrIn<R>& in) {
+  const int gz = resolve(zc, G.nz, G.bcz);
+  if (gz < 0) return;
+  const unsigned pz = (unsigned)gz * (unsigned)G.ny * (unsigned)G.px;
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    if (m.cr[i] < 0) continue;
+    const unsigned o = pz + m.o[i];
+    in.po[i] = ldo(po, o);
+    if (Uin) in.U[i] = ldo(Uin, o);
+  }
+  if (own && Tin) in.T = ldo(Tin, pz + m.o[0]);
+}
+
+// phase-step transfer (Eq. 36-39) in one pass: J = W0/(2 sqrt2) [1 + (1-k)
+// U*] dphi n^{q+1} on the region of the plane above, then the compact
+// divergence (a neighbour beyond a wall is the boundary node, its J
+// mirrored with the normal component negated), dU and dT of Eq. (38) and
+// the injection (Eq. 39) on the current plane
+template <class R>
+__global__ __launch_bounds__(256) void k3z_transfer(const Dom* __restrict__ doms, unsigned k, int zrun,
+                                                    Partial* __restrict__ part) {
+  __shared__ R wpn[4][ZNB];
+  __shared__ R wJ[3][3][ZNR];
+  __shared__ R red[4];
+  const Dom& D = doms[0];
+  const ZGeo G = zgeo(D);
+  ZCol c;
+  if (!zcol(G, blockIdx.x, zrun, c) || k % D.N_phi) return;
+  const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
+  GLOBAL const R* pn = gp<const R>(D.phi[par(n_phi(D, k))]);
+  GLOBAL const R* po = gp<const R>(D.phi[par(n_phi(D, k - 1))]);
+  const bool hasU = D.has_U, hasT = D.has_T && !D.T_pulled, accum = D.accum;
+  const unsigned nU = (D.accum ? 0u : (k - 1) / D.N_phi) + (k - 1) / D.N_U;
+  GLOBAL const R* Uin = hasU ? gp<const R>(D.U[par(nU)]) : nullptr;
+  GLOBAL R* Uout = hasU ? gp<R>(D.U[par(nU + 1)]) : nullptr;
+  GLOBAL const R* Tin = hasT ? gp<const R>(D.T[par(n_T(D, k - 1))]) : nullptr;
+  GLOBAL R* Tout = hasT ? gp<R>(D.T[par(n_T(D, k - 1) + 1)]) : nullptr;
+  GLOBAL R* PU = gp<R>(D.PU);
+  GLOBAL R* PT = gp<R>(D.PT);
+  const R cJ = kc<R>(D, K_CJ), omk = kc<R>(D, K_OMK), opk = kc<R>(D, K_OPK), U0 = kc<R>(D, K_U0);
+  const R hrcS = kc<R>(D, K_HRCS), hrcL = kc<R>(D, K_HRCL), cT = kc<R>(D, K_CT);
+  const bool own = tx < c.w && ty < c.h;
+  const int gx = c.x0 + tx, gy = c.y0 + ty;
+  ZWinMap wm;
+  zwin_map(G, c, tid, wm);
+  ZRegMap rm;
+  zreg_map(G, c, tid, rm);
+  // mirror flags of the own site's neighbours in x and y (beyond a wall)
+  const bool mxl = gx - 1 < 0 && G.bcx != BC_PER, mxh = gx + 1 >= G.nx && G.bcx != BC_PER;
+  const bool myl = gy - 1 < 0 && G.bcy != BC_PER, myh = gy + 1 >= G.ny && G.bcy != BC_PER;
+
+  // J on the region of plane zc from the window planes zc - 1 .. zc + 1
+  auto flux = [&](const ZTrIn<R>& in, int zc) {
+    if (resolve(zc, G.nz, G.bcz) < 0) return;   // beyond a wall: the boundary node's J is used
+    const R* p0 = wpn[zslot4(zc - 1)];
+    const R* p1 = wpn[zslot4(zc)];
+    const R* p2 = wpn[zslot4(zc + 1)];
+    R* out = &wJ[zslot3(zc)][0][0];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      if (rm.cr[i] < 0) continue;
+      const int cr = rm.cr[i], cb = zbox(cr);
+      R g[3];
+      zgrad(p0, p1, p2, cb, g);
+      const R gg = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+      R J[3] = {R(0), R(0), R(0)};
+      if (gg >= R(GRAD_EPS2)) {
+        const R a = cJ * (R(1) + omk * (in.U[i] + U0)) * (p1[cb] - in.po[i]) * rsq(gg);
+#pragma unroll
+        for (int q = 0; q < 3; ++q) J[q] = -a * g[q];
+      }
+#pragma unroll
+      for (int q = 0; q < 3; ++q) out[q * ZNR + cr] = J[q];
+    }
+  };
+
+  R amax = R(0);
+  ZTrIn<R> in0, in1;
+  if (hasU) {
+    ZWin<R> w0, w1, w2, w3;
+    zload_win(G, wm, c.za - 2, tid, pn, w0);
+    zload_win(G, wm, c.za - 1, tid, pn, w1);
+    zload_win(G, wm, c.za, tid, pn, w2);
+    zload_win(G, wm, c.za + 1, tid, pn, w3);
+    zload_tr(G, rm, c.za - 1, po, Uin, Tin, false, in0);
+    zload_tr(G, rm, c.za, po, Uin, Tin, own, in1);
+    zput_win(wpn[zslot4(c.za - 2)], w0, tid);
+    zput_win(wpn[zslot4(c.za - 1)], w1, tid);
+    zput_win(wpn[zslot4(c.za)], w2, tid);
+    zput_win(wpn[zslot4(c.za + 1)], w3, tid);
+    __syncthreads();
+    flux(in0, c.za - 1);
+    flux(in1, c.za);
+  } else {
+    zload_tr(G, rm, c.za, po, Uin, Tin, own, in1);
+  }
+  ZTrIn<R> cur = in1;   // inputs of the plane being applied (own cell)
+  ZWin<R> wn;
+  if (hasU) zload_win(G, wm, c.za + 2, tid, pn, wn);
+  zload_tr(G, rm, c.za + 1, po, Uin, Tin, own, in0);
+  __syncthreads();
+
+  for (int z = c.za; z < c.zb; ++z) {
+    if (hasU) zput_win(wpn[zslot4(z + 2)], wn, tid);
+    const ZTrIn<R> nxt = in0;   // inputs of the plane above
+    if (z + 1 < c.zb) {         // prefetch for the next plane
+      if (hasU) zload_win(G, wm, z + 3, tid, pn, wn);
+      zload_tr(G, rm, z + 2, po, Uin, Tin, own, in0);
+    }
+    __syncthreads();
+    if (hasU) flux(nxt, z + 1);
+    __syncthreads();
+    if (own) {
+      const unsigned o = zoff(G, gx, gy, z);
+      const int cr = (ty + 1) * ZRW + tx + 1, cb = (ty + 2) * ZBW + tx + 2;
+      const R p1 = hasU ? wpn[zslot4(z)][cb] : ldo(pn, o);
+      const R dphi = p1 - cur.po[0];
+      if (hasU) {
+        const bool mzl = z - 1 < 0 && G.bcz != BC_PER, mzh = z + 1 >= G.nz && G.bcz != BC_PER;
+        R div = R(0);
+#pragma unroll
+        for (int q = 1; q < 19; ++q) {
+          const int ex = e19(q, 0), ey = e19(q, 1), ez = e19(q, 2);
+          const bool mir[3] = {ex < 0 ? mxl : ex > 0 ? mxh : false, ey < 0 ? myl : ey > 0 ? myh : false,
+                               ez < 0 ? mzl : ez > 0 ? mzh : false};
+          // a neighbour beyond a wall is the boundary node itself (ghost)
+          const int dx = mir[0] ? 0 : ex, dy = mir[1] ? 0 : ey, dz = mir[2] ? 0 : ez;
+          const R* Jq = &wJ[zslot3(z + dz)][0][0];
+          const int nr = cr + dy * ZRW + dx;
+          const R cq = q <= 6 ? R(1.0 / 6.0) : R(1.0 / 12.0);
+#pragma unroll
+          for (int a = 0; a < 3; ++a)
+            if (e19(q, a) != 0) {
+              const R v = Jq[a * ZNR + nr];
+              div += R(e19(q, a)) * cq * (mir[a] ? -v : v);
+            }
+        }
+        const R Us = cur.U[0];   // U - U0
+        const R dU = ((R(1) + omk * (Us + U0)) * dphi - R(2) * div) * rcp(opk - omk * p1);
+        amax = fmax(amax, fabs(dU));
+        if (accum) sto(PU, o, ldo(PU, o) + dU);
+        else sto(Uout, o, Us + dU);
+      }
+      if (hasT) {
+        const R rc = (R(1) + p1) * hrcS + (R(1) - p1) * hrcL;
+        const R dT = cT * dphi * rcp(R(2) * rc);
+        if (accum) sto(PT, o, ldo(PT, o) + dT);
+        else sto(Tout, o, cur.T + dT);
+      }
+    }
+    cur = nxt;
+    __syncthreads();
+  }
+  if (part && hasU) {
+    for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_down(amax, off, 64));
+    if ((tid & 63) == 0) red[tid >> 6] = amax;
+    __syncthreads();
+    if (tid == 0) {
+      const R m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+      part[blockIdx.x].S_phi = double(m);
+      if (!accum) part[blockIdx.x].J_U = double(m);
+    }
   }
 }
 
@@ -2483,22 +2870,28 @@ struct Launch3 {
     const long long cols = (long long)((h.nx + 63) / 64) * ((h.ny + 3) / 4);
     return (unsigned)((cols + 7) / 8 * 8 * h.nz);
   }
+  // z-marching launches: runs of zrun planes, enough (column, run) pairs
+  // for about 2048 blocks
+  static int zrun(const Dom& h) {
+    const int ncol = ((h.nx + ZTX - 1) / ZTX) * ((h.ny + ZTY - 1) / ZTY);
+    const int nrun = std::max(1, std::min((2048 + ncol - 1) / ncol, (h.nz + 7) / 8));
+    return (h.nz + nrun - 1) / nrun;
+  }
+  static unsigned zblocks(const Dom& h) {
+    const long long ncol = (long long)((h.nx + ZTX - 1) / ZTX) * ((h.ny + ZTY - 1) / ZTY);
+    const int zr = zrun(h);
+    const long long n = ncol * ((h.nz + zr - 1) / zr);
+    return (unsigned)((n + 7) / 8 * 8);
+  }
   static void phase(const Dom& h, hipStream_t st, const Dom* d, unsigned k) {
-    k3_phase_collide<R, S><<<blocks(h), 256, 0, st>>>(d, k);
-    k3_phase_stream<R, S><<<blocks(h), 256, 0, st>>>(d, k);
+    k3z_phase<R, S><<<zblocks(h), 256, 0, st>>>(d, k, zrun(h));
   }
   static void transfer(const Dom& h, hipStream_t st, const Dom* d, unsigned k, Partial* p) {
-    if (h.has_U) k3_transfer_J<R><<<blocks(h), 256, 0, st>>>(d, k);
-    k3_transfer_apply<R><<<blocks(h), 256, 0, st>>>(d, k, p);
+    k3z_transfer<R><<<zblocks(h), 256, 0, st>>>(d, k, zrun(h), p);
   }
   static void scalar(int field, const Dom& h, hipStream_t st, const Dom* d, unsigned k, Partial* p) {
-    if (field == 0) {
-      k3_scalar_collide<R, S, 0><<<blocks(h), 256, 0, st>>>(d, k);
-      k3_scalar_stream<R, S, 0><<<blocks(h), 256, 0, st>>>(d, k, p);
-    } else {
-      k3_scalar_collide<R, S, 1><<<blocks(h), 256, 0, st>>>(d, k);
-      k3_scalar_stream<R, S, 1><<<blocks(h), 256, 0, st>>>(d, k, p);
-    }
+    if (field == 0) k3z_scalar<R, S, 0><<<zblocks(h), 256, 0, st>>>(d, k, zrun(h), p);
+    else k3z_scalar<R, S, 1><<<zblocks(h), 256, 0, st>>>(d, k, zrun(h), p);
   }
   static void flow(const Dom& h, hipStream_t st, const Dom* d, unsigned k) {
     k3_flow_collide<R, S><<<blocks(h), 256, 0, st>>>(d, k);

@@ -206,7 +206,7 @@ Layout layout_of(const lbm_params& p) {
   if (p.has_U) { L.rplanes += 3; L.splanes += 2 * d; }
   if (p.has_T) { L.rplanes += 3; L.splanes += 2 * d; }
   if (p.has_flow) { L.rplanes += 2 + 2 * d; L.splanes += 2 * (d == 3 ? 18 : 8); }
-  if (d == 3) L.rplanes += p.has_flow ? 19 : 5;   // scratch of the two-pass kernels
+  if (d == 3 && p.has_flow) L.rplanes += 19;   // scratch of the two-pass flow kernels
   return L;
 }
 
@@ -602,6 +602,8 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
       K[K_U0] = q.U0;
       K[K_T0] = q.T0;
       K[K_ALPHAL] = q.kappa_L / q.rhoCp_L;
+      K[K_HDRC] = 0.5 * (q.rhoCp_S - q.rhoCp_L);
+      K[K_DTF] = q.N_F * q.dt_base;
       for (int j = 0; j < K_N; ++j) D.kf[j] = (float)K[j];
     }
     const size_t pr = D.plane * c->rsz, ps = D.plane * c->ssz;
@@ -631,7 +633,7 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
         D.vel[b] = take(align256(pr) * q.dim);
       }
     }
-    if (d3) D.scr = take(align256(pr) * (q.has_flow ? 19 : 5));
+    if (d3 && q.has_flow) D.scr = take(align256(pr) * 19);
     lcm = ipow_lcm(lcm, q.N_phi);
     if (q.has_U) lcm = ipow_lcm(lcm, q.N_U);
     if (q.has_T) lcm = ipow_lcm(lcm, q.N_T);
