@@ -45,9 +45,8 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2609_25670_amd", "csrc", f)
                   for f in ("lbm_kernels.hip", "lbm_dev.h")]
 KERNEL_NAMES = {"phase": "k_phase", "phase_tr": "k_phase_tr", "transfer": "k_transfer", "U": "k_scalar<..., 0>",
                 "T": "k_scalar<..., 1>", "flow": "k_flow"}
-KERNEL_NAMES_3D = {"phase": "k3_phase_collide + k3_phase_stream", "transfer": "k3_transfer_J + k3_transfer_apply",
-                   "U": "k3_scalar_collide/stream<..., 0>", "T": "k3_scalar_collide/stream<..., 1>",
-                   "flow": "k3_flow_collide + k3_flow_stream"}
+KERNEL_NAMES_3D = {"phase": "k3z_phase", "transfer": "k3z_transfer", "U": "k3z_scalar<..., 0>",
+                   "T": "k3z_scalar<..., 1>", "flow": "k3z_flow"}
 
 
 def sites_of(d: dict) -> int:

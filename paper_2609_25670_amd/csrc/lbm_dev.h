@@ -71,7 +71,6 @@ struct Dom {
   void* rho[2];    // R
   void* sF[2];     // S, QF-1 planes: f_i - w_i rho, i >= 1 (8 in D2Q9, 18 in D3Q19)
   void* vel[2];    // R, dim planes each
-  void* scr;       // R, scratch planes of the two-pass 3D kernels (19)
 };
 
 template <class R>

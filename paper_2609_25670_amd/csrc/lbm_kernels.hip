@@ -1669,11 +1669,9 @@ __global__ void k_tips(const Dom* __restrict__ doms, long long k, DiagOut* __res
 // Scalars on D3Q7 (w_0 = 1/4, w_i = 1/8, c_s^2 = 1/4, so the factor 3 of
 // Eq. (19), (21), (24), (40) becomes 4), flow on D3Q19, isotropic stencils
 // with D3Q19 weights, fourfold-cubic anisotropy a_s = 1 - 3 eps +
-// 4 eps sum_a n_a^4.  The phase field, the scalars and the transfer march
-// up through z in one pass with their collisions held in LDS (below).  The
-// flow is two passes over the sites: the collision writes the nineteen
-// post-collision deviations to scratch planes, the streaming pass pulls
-// them.  x is the fastest index, so every plane access is coalesced.
+// 4 eps sum_a n_a^4.  Every field update marches up through z in one pass
+// with its collisions held in LDS (below); x is the fastest index, so every
+// plane access is coalesced.
 //
 // D3Q7 order: 0, +x, -x, +y, -y, +z, -z.  D3Q19 order: 0, the six axes as
 // above, then (1,1,0), (-1,-1,0), (1,-1,0), (-1,1,0), (1,0,1), (-1,0,-1),
@@ -1718,16 +1716,6 @@ __device__ __forceinline__ bool site3(const Dom& D, unsigned b, unsigned t, Site
   return true;
 }
 
-// upstream site y - e, or false when it lies beyond a non-periodic boundary
-__device__ __forceinline__ bool up3(const Dom& D, const Site3& s, int ex, int ey, int ez, const int* bc,
-                                    unsigned& o) {
-  const int gx = resolve(s.x - ex, D.nx, bc[0]);
-  const int gy = resolve(s.y - ey, D.ny, bc[1]);
-  const int gz = resolve(s.z - ez, D.nz, bc[2]);
-  if (gx < 0 || gy < 0 || gz < 0) return false;
-  o = (unsigned)(((long long)gz * D.ny + gy) * D.px + gx);
-  return true;
-}
 
 // D3Q7 phase collision: (dP, K) and A = a_s^2 from phi, its gradient, j
 // (the domain's constants in c, evaluated once on the host)
@@ -1770,10 +1758,10 @@ __device__ __forceinline__ void phase_collide3(const PhaseConst<R>& c, R phi, co
 // planes ahead into a four-plane LDS window (the tile plus two rings),
 // collides the next plane on the tile plus one ring into a three-plane LDS
 // window of (dP, K), and streams the current plane from the planes below,
-// at and above.  The collisions stay in LDS instead of a scratch round trip
+// at and above.  The collisions stay in LDS (the tile's ring of collisions
+// is recomputed by each neighbouring block) instead of making a round trip
 // through HBM, and the loads for the next plane are issued before the
-// current plane is computed.  The arithmetic is that of the two-pass
-// kernels, term for term.
+// current plane is computed.
 constexpr int ZTX = 64, ZTY = 4;                  // tile: one site per thread and plane
 constexpr int ZRW = ZTX + 2, ZRH = ZTY + 2;       // collision region (ring 1)
 constexpr int ZBW = ZTX + 4, ZBH = ZTY + 4;       // phase window (ring 2)
@@ -2523,26 +2511,20 @@ __device__ __forceinline__ void mrt19_op(const R* x, R sq, R se, R seps, R snu, 
   }
 }
 
-template <class R, class S>
-__global__ __launch_bounds__(256) void k3_flow_collide(const Dom* __restrict__ doms, unsigned k) {
-  const Dom& D = doms[0];
-  Site3 s;
-  if (!site3(D, blockIdx.x, threadIdx.x, s) || k % D.N_F) return;
-  const unsigned pl = (unsigned)D.plane;
-  const int ib = par(n_F(D, k - 1));
-  const R rho = (gp<const R>(D.rho[ib]))[s.o];
-  GLOBAL const S* sp = gp<const S>(D.sF[ib]);
-  const R dt = R(D.N_F * D.dt_base), c = R(1) / dt;
-  R d[19], j[3] = {R(0), R(0), R(0)};
+// D3Q19 MRT collision of one site (Eq. 27-31 in 3D): the post-collision
+// deviations p_q = f_q^+ - w_q rho from rho and the stored deviations d
+// (d_0 = -sum of the others)
+template <class R>
+__device__ __forceinline__ void flow_collide3(R rho, R* d, R dt, R c, const R* F, bool forced, R sq, R se, R seps,
+                                             R snu, R* p) {
+  R j[3] = {R(0), R(0), R(0)};
   d[0] = R(0);
 #pragma unroll
   for (int q = 1; q < 19; ++q) {
-    d[q] = ld(sp, s.o + (q - 1) * pl);
     d[0] -= d[q];
 #pragma unroll
     for (int a = 0; a < 3; ++a) j[a] += R(e19(q, a)) * d[q];
   }
-  const R F[3] = {R(D.Fx), R(D.Fy), R(D.Fz)};
   const R irho = rcp(rho);
   R u[3], U[3];
 #pragma unroll
@@ -2552,7 +2534,6 @@ __global__ __launch_bounds__(256) void k3_flow_collide(const Dom* __restrict__ d
   }
   const R U2 = U[0] * U[0] + U[1] * U[1] + U[2] * U[2];
   R x[19], Fi[19];
-  const bool forced = D.Fx != 0.0 || D.Fy != 0.0 || D.Fz != 0.0;
 #pragma unroll
   for (int q = 0; q < 19; ++q) {
     const R eU = R(e19(q, 0)) * U[0] + R(e19(q, 1)) * U[1] + R(e19(q, 2)) * U[2];
@@ -2563,62 +2544,182 @@ __global__ __launch_bounds__(256) void k3_flow_collide(const Dom* __restrict__ d
       Fi[q] = R(w19(q)) * (R(3) * (eF - uF) + R(9) * eU * eF) * dt;     // Guo, velocity space
     }
   }
-  const R snu = R(1.0 / (3.0 * D.N_F * D.dt_base * D.nu + 0.5));
   R y[19];
-  mrt19_op(x, R(D.s_q), R(D.s_e), R(D.s_eps), snu, y);
-  GLOBAL R* scr = gp<R>(D.scr);
+  mrt19_op(x, sq, se, seps, snu, y);
   if (forced) {
     R yf[19];
-    mrt19_op(Fi, R(D.s_q), R(D.s_e), R(D.s_eps), snu, yf);
+    mrt19_op(Fi, sq, se, seps, snu, yf);
 #pragma unroll
-    for (int q = 0; q < 19; ++q) scr[s.o + q * pl] = d[q] - y[q] + Fi[q] - R(0.5) * yf[q];
+    for (int q = 0; q < 19; ++q) p[q] = d[q] - y[q] + Fi[q] - R(0.5) * yf[q];
   } else {
 #pragma unroll
-    for (int q = 0; q < 19; ++q) scr[s.o + q * pl] = d[q] - y[q];
+    for (int q = 0; q < 19; ++q) p[q] = d[q] - y[q];
   }
 }
 
-// partial bounce-back pull (Eq. 33) in deviations from w_i rho(y)
+// D3Q19 direction groups by z component: the components a plane streams to
+// the plane above (ez = +1), within itself (ez = 0, q >= 1) and below
+__host__ __device__ constexpr int zgroup(int q) { return e19(q, 2) > 0 ? 0 : e19(q, 2) == 0 ? 1 : 2; }
+__host__ __device__ constexpr int zindex(int q) {   // index of q within its group
+  int n = 0;
+  for (int r = 1; r < q; ++r) n += zgroup(r) == zgroup(q);
+  return n;
+}
+
+// raw loads of the flow collision inputs of a plane's region cells
 template <class R, class S>
-__global__ __launch_bounds__(256) void k3_flow_stream(const Dom* __restrict__ doms, unsigned k) {
-  const Dom& D = doms[0];
-  Site3 s;
-  if (!site3(D, blockIdx.x, threadIdx.x, s) || k % D.N_F) return;
-  const unsigned pl = (unsigned)D.plane;
-  GLOBAL const R* rin = gp<const R>(D.rho[par(n_F(D, k - 1))]);
-  GLOBAL const R* phis = gp<const R>(D.phi[par(n_phi(D, k))]);
-  GLOBAL const R* scr = gp<const R>(D.scr);
-  const R dt = R(D.N_F * D.dt_base), c = R(1) / dt;
-  const R ry = rin[s.o], fly = (R(1) - phis[s.o]) * R(0.5);
-  R dn[19], drho = R(0), j[3] = {R(0), R(0), R(0)};
+struct ZFlowIn {
+  R rho[2], phi[2];
+  typename RawT<S>::type s[2][18];
+};
+template <class R, class S>
+__device__ __forceinline__ void zload_flow(const ZGeo& G, const ZRegMap& m, int zc, long long pl, GLOBAL const R* rin,
+                                           GLOBAL const R* phis, GLOBAL const typename RawT<S>::type* sp,
+                                           ZFlowIn<R, S>& in) {
+  const int gz = resolve(zc, G.nz, G.bcz);
+  if (gz < 0) return;
+  const unsigned pz = (unsigned)gz * (unsigned)G.ny * (unsigned)G.px;
 #pragma unroll
-  for (int q = 0; q < 19; ++q) {
-    const int ex = e19(q, 0), ey = e19(q, 1), ez = e19(q, 2);
-    const R bounce = scr[s.o + opp19(q) * pl];
-    unsigned o;
-    if (q == 0) {
-      dn[0] = scr[s.o];
-    } else if (up3(D, s, ex, ey, ez, D.fbc, o)) {
-      const R m = R(0.5) * (fly + (R(1) - phis[o]) * R(0.5));
-      dn[q] = m * (R(w19(q)) * (rin[o] - ry) + scr[o + q * pl]) + (R(1) - m) * bounce;
-    } else {
-      dn[q] = bounce;
-    }
-    drho += dn[q];
-    j[0] += R(ex) * dn[q];
-    j[1] += R(ey) * dn[q];
-    j[2] += R(ez) * dn[q];
+  for (int i = 0; i < 2; ++i) {
+    if (m.cr[i] < 0) continue;
+    const unsigned o = pz + m.o[i];
+    in.rho[i] = ldo(rin, o);
+    in.phi[i] = ldo(phis, o);
+#pragma unroll
+    for (int q = 0; q < 18; ++q) in.s[i][q] = *at(plane(sp, q * pl), o);
   }
-  const int ob = par(n_F(D, k));
-  const R rho = ry + drho, irho = rcp(rho);
-  (gp<R>(D.rho[ob]))[s.o] = rho;
+}
+
+// flow in one pass: MRT collision (Eq. 27-32 in 3D) of the plane above on
+// the region, then the partial bounce-back pull (Eq. 33) of the current
+// plane in deviations from w_i rho(y).  Components streaming up (ez = +1)
+// are kept for two planes, in-plane ones for one, downward ones only for
+// the plane being streamed; the own site's nineteen post-collision values
+// stay in registers for the bounce-back.
+template <class R, class S>
+__global__ __launch_bounds__(256) void k3z_flow(const Dom* __restrict__ doms, unsigned k, int zrun) {
+  using SR = typename RawT<S>::type;
+  __shared__ R wup[3][5][ZNR];     // ez = +1 components, planes z - 1 .. z + 1
+  __shared__ R win[2][8][ZNR];     // ez = 0 components, planes z, z + 1
+  __shared__ R wdn[5][ZNR];        // ez = -1 components of plane z + 1
+  __shared__ R wrho[3][ZNR], wfl[3][ZNR];
+  const Dom& D = doms[0];
+  const ZGeo G{D.nx, D.ny, D.nz, D.px, D.fbc[0], D.fbc[1], D.fbc[2]};
+  ZCol c;
+  if (!zcol(G, blockIdx.x, zrun, c) || k % D.N_F) return;
+  const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
+  const long long pl = D.plane;
+  const int ib = par(n_F(D, k - 1)), ob = par(n_F(D, k));
+  GLOBAL const R* rin = gp<const R>(D.rho[ib]);
+  GLOBAL const SR* sp = gp<const SR>(D.sF[ib]);
+  GLOBAL const R* phis = gp<const R>(D.phi[par(n_phi(D, k))]);
+  GLOBAL R* rho_out = gp<R>(D.rho[ob]);
   GLOBAL R* vel = gp<R>(D.vel[ob]);
+  GLOBAL S* s_out = gp<S>(D.sF[ob]);
+  const R dt = R(D.N_F * D.dt_base), cdt = R(1) / dt;
   const R F[3] = {R(D.Fx), R(D.Fy), R(D.Fz)};
+  const bool forced = D.Fx != 0.0 || D.Fy != 0.0 || D.Fz != 0.0;
+  const R snu = R(1.0 / (3.0 * D.N_F * D.dt_base * D.nu + 0.5));
+  const R sq = R(D.s_q), se = R(D.s_e), seps = R(D.s_eps);
+  const bool own = tx < c.w && ty < c.h;
+  const int gx = c.x0 + tx, gy = c.y0 + ty;
+  ZRegMap rm;
+  zreg_map(G, c, tid, rm);
+  const bool upx[2] = {resolve(gx - 1, G.nx, G.bcx) >= 0, resolve(gx + 1, G.nx, G.bcx) >= 0};
+  const bool upy[2] = {resolve(gy - 1, G.ny, G.bcy) >= 0, resolve(gy + 1, G.ny, G.bcy) >= 0};
+
+  // collide plane zc on the region; the own site's values are returned
+  auto collide = [&](const ZFlowIn<R, S>& in, int zc, R* pown, R& rown, R& flown) {
+    if (resolve(zc, G.nz, G.bcz) < 0) return;   // beyond a wall: never pulled from
+    const int su = zslot3(zc), si = zc & 1, s3 = zslot3(zc);
 #pragma unroll
-  for (int a = 0; a < 3; ++a) vel[s.o + a * pl] = (c * j[a] + dt * F[a] * R(0.5)) * irho;
-  GLOBAL S* so = gp<S>(D.sF[ob]);
+    for (int i = 0; i < 2; ++i) {
+      if (rm.cr[i] < 0) continue;
+      const int cr = rm.cr[i];
+      R d[19], p[19];
 #pragma unroll
-  for (int q = 1; q < 19; ++q) st(so, s.o + (q - 1) * pl, dn[q] - R(w19(q)) * drho);
+      for (int q = 1; q < 19; ++q) d[q] = cvt_raw(in.s[i][q - 1], (S*)nullptr);
+      const R rho = in.rho[i];
+      flow_collide3(rho, d, dt, cdt, F, forced, sq, se, seps, snu, p);
+      const R fl = (R(1) - in.phi[i]) * R(0.5);
+#pragma unroll
+      for (int q = 1; q < 19; ++q) {
+        if (zgroup(q) == 0) wup[su][zindex(q)][cr] = p[q];
+        else if (zgroup(q) == 1) win[si][zindex(q)][cr] = p[q];
+        else wdn[zindex(q)][cr] = p[q];
+      }
+      wrho[s3][cr] = rho;
+      wfl[s3][cr] = fl;
+      if (i == 0) {
+#pragma unroll
+        for (int q = 0; q < 19; ++q) pown[q] = p[q];
+        rown = rho;
+        flown = fl;
+      }
+    }
+  };
+
+  R pcur[19], pnext[19], rcur = R(1), rnext = R(1), fcur = R(0), fnext = R(0);
+  ZFlowIn<R, S> in0;
+  {
+    ZFlowIn<R, S> a, b;
+    zload_flow(G, rm, c.za - 1, pl, rin, phis, sp, a);
+    zload_flow(G, rm, c.za, pl, rin, phis, sp, b);
+    collide(a, c.za - 1, pnext, rnext, fnext);
+    __syncthreads();   // the in-plane and downward components of za - 1 are not needed
+    collide(b, c.za, pcur, rcur, fcur);
+  }
+  zload_flow(G, rm, c.za + 1, pl, rin, phis, sp, in0);
+  __syncthreads();
+
+  for (int z = c.za; z < c.zb; ++z) {
+    const ZFlowIn<R, S> cur = in0;
+    if (z + 1 < c.zb) zload_flow(G, rm, z + 2, pl, rin, phis, sp, in0);   // prefetch
+    collide(cur, z + 1, pnext, rnext, fnext);
+    __syncthreads();
+    if (own) {
+      const int cr = (ty + 1) * ZRW + tx + 1;
+      const bool upz[2] = {resolve(z - 1, G.nz, G.bcz) >= 0, resolve(z + 1, G.nz, G.bcz) >= 0};
+      const R ry = rcur, fly = fcur;
+      R dn[19], drho = R(0), j[3] = {R(0), R(0), R(0)};
+#pragma unroll
+      for (int q = 0; q < 19; ++q) {
+        const int ex = e19(q, 0), ey = e19(q, 1), ez = e19(q, 2);
+        const R bounce = pcur[opp19(q)];
+        if (q == 0) {
+          dn[0] = pcur[0];
+        } else {
+          const bool up = (ex == 0 || upx[ex > 0 ? 0 : 1]) && (ey == 0 || upy[ey > 0 ? 0 : 1]) &&
+                          (ez == 0 || upz[ez > 0 ? 0 : 1]);
+          if (up) {
+            const int ur = cr - ey * ZRW - ex, s3 = zslot3(z - ez);
+            const R pu = zgroup(q) == 0 ? wup[zslot3(z - 1)][zindex(q)][ur]
+                                        : zgroup(q) == 1 ? win[z & 1][zindex(q)][ur] : wdn[zindex(q)][ur];
+            const R m = R(0.5) * (fly + wfl[s3][ur]);
+            dn[q] = m * (R(w19(q)) * (wrho[s3][ur] - ry) + pu) + (R(1) - m) * bounce;
+          } else {
+            dn[q] = bounce;
+          }
+        }
+        drho += dn[q];
+        j[0] += R(ex) * dn[q];
+        j[1] += R(ey) * dn[q];
+        j[2] += R(ez) * dn[q];
+      }
+      const R rho = ry + drho, irho = rcp(rho);
+      const unsigned o = zoff(G, gx, gy, z);
+      sto(rho_out, o, rho);
+#pragma unroll
+      for (int a = 0; a < 3; ++a) sto(plane(vel, a * pl), o, (cdt * j[a] + dt * F[a] * R(0.5)) * irho);
+#pragma unroll
+      for (int q = 1; q < 19; ++q) sto(plane(s_out, (q - 1) * pl), o, dn[q] - R(w19(q)) * drho);
+    }
+#pragma unroll
+    for (int q = 0; q < 19; ++q) pcur[q] = pnext[q];
+    rcur = rnext;
+    fcur = fnext;
+    __syncthreads();
+  }
 }
 
 // planar front along z at z_front + xi(x, y) (random form of Eq. 41),
@@ -2894,8 +2995,7 @@ struct Launch3 {
     else k3z_scalar<R, S, 1><<<zblocks(h), 256, 0, st>>>(d, k, zrun(h), p);
   }
   static void flow(const Dom& h, hipStream_t st, const Dom* d, unsigned k) {
-    k3_flow_collide<R, S><<<blocks(h), 256, 0, st>>>(d, k);
-    k3_flow_stream<R, S><<<blocks(h), 256, 0, st>>>(d, k);
+    k3z_flow<R, S><<<zblocks(h), 256, 0, st>>>(d, k, zrun(h));
   }
   static void step(const Dom& h, hipStream_t st, const Dom* d, unsigned k, Partial* p) {
     if (k % h.N_phi == 0) {

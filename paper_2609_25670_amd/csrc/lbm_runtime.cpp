@@ -206,7 +206,6 @@ Layout layout_of(const lbm_params& p) {
   if (p.has_U) { L.rplanes += 3; L.splanes += 2 * d; }
   if (p.has_T) { L.rplanes += 3; L.splanes += 2 * d; }
   if (p.has_flow) { L.rplanes += 2 + 2 * d; L.splanes += 2 * (d == 3 ? 18 : 8); }
-  if (d == 3 && p.has_flow) L.rplanes += 19;   // scratch of the two-pass flow kernels
   return L;
 }
 
@@ -633,7 +632,6 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
         D.vel[b] = take(align256(pr) * q.dim);
       }
     }
-    if (d3 && q.has_flow) D.scr = take(align256(pr) * 19);
     lcm = ipow_lcm(lcm, q.N_phi);
     if (q.has_U) lcm = ipow_lcm(lcm, q.N_U);
     if (q.has_T) lcm = ipow_lcm(lcm, q.N_T);

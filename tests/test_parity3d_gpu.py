@@ -112,6 +112,23 @@ def test_3d_transport_T_accumulated_walls_fp64():
         oracle.diag.totals(dom)["enthalpy"])
 
 
+def test_3d_periodic_z_ragged_tiles_fp64():
+    """Periodic in all three directions, transported T with phi-dependent
+    properties, on 70 x 9 x 21: ragged tiles in x (70 = 64 + 6) and y
+    (9 = 2 x 4 + 1), and z runs that wrap around the periodic boundary."""
+    wl = _directional(70, 9, 21)
+    d = wl["domains"][0]
+    d.update(T_mode="transport", T0=d["T0"] - 0.02, kappa_S=2 * d["kappa_L"], rhoCp_S=1.2 * d["rhoCp_L"],
+             N_U=1, N_T=2, N_F=2, bc=("periodic", "periodic", "periodic"),
+             flow_bc=("periodic", "periodic", "periodic"), D_L=0.05, D_S=5e-4)
+    names = ("phi", "U", "T", "rho", "vel", "jU", "jT", "f_phi")
+    _say("case 3d periodic xyz ragged 70x9x21 fp64 36 steps")
+    got, diag = _run(wl, 36, names)
+    dom = oracle.run(d, 36)
+    _compare("3d periodic", got, _ref(dom, names), TOL64)
+    assert diag["nonfinite"] == 0
+
+
 def test_3d_checkpoint_restore_is_bitwise():
     """Full 3D state read, written into a fresh context, continued: equal to
     the uninterrupted run bit for bit."""
