@@ -464,6 +464,232 @@ __global__ __launch_bounds__(NTHR) void k_phase(const Dom* __restrict__ doms, co
   else stream(std::false_type{});
 }
 
+// =================================================================== 2D marching in y
+// For large domains: one block owns a 64-wide column over a run of rows
+// (the host lists the runs) and walks up through it four rows at a time (one row per
+// wavefront).  The phase field is kept in an eight-row LDS ring (the
+// column plus two cells on each side), the collisions of the four rows
+// ahead go into an eight-row LDS ring (the column plus one ring cell on
+// each side), and the four current rows are streamed from the rows below,
+// at and above.  Ring collisions are recomputed only in x (3% at 64
+// columns instead of 16% for a 64 x 16 tile), and the loads of the next
+// four rows are issued before the current rows are computed.  The
+// arithmetic is the tile kernels', expression for expression.
+constexpr int YCW = TX + 2, YBW = TX + 4;
+
+// isotropic gradient with D2Q9 weights from three rows (below, at, above)
+template <class R>
+__device__ __forceinline__ void iso_grad_rows(const R* rm, const R* r0, const R* rp, int c, R& gx, R& gy) {
+  const R E = r0[c + 1], W = r0[c - 1], N = rp[c], S = rm[c];
+  const R NE = rp[c + 1], NW = rp[c - 1], SE = rm[c + 1], SW = rm[c - 1];
+  gx = (E - W) * R(1.0 / 3.0) + (NE - NW - SW + SE) * R(1.0 / 12.0);
+  gy = (N - S) * R(1.0 / 3.0) + (NE + NW - SW - SE) * R(1.0 / 12.0);
+}
+
+// collision cells of a thread for the four rows r0 .. r0 + 3: its column
+// cell of row r0 + ty, and for threads 0..7 one of the eight ring cells
+__device__ __forceinline__ bool ym_cell(int i, int tx, int ty, int tid, int w, int r0, int& col, int& row) {
+  if (i == 0) {
+    col = tx + 1;
+    row = r0 + ty;
+    return tx < w;
+  }
+  if (tid >= 8) return false;
+  col = (tid & 1) ? w + 1 : 0;
+  row = r0 + (tid >> 1);
+  return true;
+}
+
+template <class R, class S, int Q>
+struct YPhaseIn {
+  typename RawT<S>::type s[2][Q - 1];
+  R U[2], T[2];
+  R phi[2];   // two phase-field window cells
+};
+
+template <class R, class S, int Q>
+__device__ __forceinline__ void ym_load_phase(int nx, int ny, int px, int bcx, int bcy, int x0, int w, int r0,
+                                              long long pl, int tx, int ty, int tid,
+                                              GLOBAL const R* phi, GLOBAL const typename RawT<S>::type* sp,
+                                              GLOBAL const R* Up, GLOBAL const R* Tp, YPhaseIn<R, S, Q>& in,
+                                              bool inputs = true) {
+  // collision inputs of rows r0 .. r0 + 3
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    if (!inputs) break;
+    int col, row;
+    if (!ym_cell(i, tx, ty, tid, w, r0, col, row)) continue;
+    const int gx = resolve(x0 - 1 + col, nx, bcx), gy = resolve(row, ny, bcy);
+    if (gx < 0 || gy < 0) continue;
+    const unsigned o = (unsigned)gy * (unsigned)px + (unsigned)gx;
+#pragma unroll
+    for (int q = 0; q < Q - 1; ++q) in.s[i][q] = *at(plane(sp, q * pl), o);
+    if (Up) in.U[i] = ldo(Up, o);
+    if (Tp) in.T[i] = ldo(Tp, o);
+  }
+  // phase-field rows r0 + 1 .. r0 + 4 (68 cells each, ghosted)
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int cc = tid + 256 * i;
+    if (cc < 4 * YBW) {
+      const int gx = ghost(x0 - 2 + cc % YBW, nx, bcx), gy = ghost(r0 + 1 + cc / YBW, ny, bcy);
+      in.phi[i] = ldo(phi, (unsigned)gy * (unsigned)px + (unsigned)gx);
+    }
+  }
+}
+
+template <class R, class S, int Q>
+__global__ __launch_bounds__(NTHR) void k_phase_ym(const Dom* __restrict__ doms, const int4* __restrict__ runs,
+                                                    unsigned k) {
+  using Lq = Lat2<Q>;
+  using SR = typename RawT<S>::type;
+  constexpr int NV = Q == 9 ? 5 : 3;   // dP, Kx, Ky (and j_eq in D2Q9)
+  __shared__ R wphi[8][YBW];
+  __shared__ R wc[8][NV][YCW];
+  __shared__ R wA[8][TX];
+  __shared__ R wsv[8][Q - 1][TX];
+
+  const int4 t = runs[blockIdx.x];
+  if (t.x < 0) return;
+  const Dom& D = doms[t.x];
+  if (k % D.N_phi) return;
+  const int nx = D.nx, ny = D.ny, px = D.px, bcx = D.bc[0], bcy = D.bc[1];
+  const long long pl = D.plane;
+  const int x0 = t.y, ya = t.z, yb = t.w;
+  const int w = min(TX, nx - x0);
+  const int ib = par(n_phi(D, k - 1)), ob = ib ^ 1;
+  GLOBAL const R* __restrict__ phi_in = gp<const R>(D.phi[ib]);
+  GLOBAL R* __restrict__ phi_out = gp<R>(D.phi[ob]);
+  GLOBAL const SR* __restrict__ s_in = gp<const SR>(D.sphi[ib]);
+  GLOBAL S* __restrict__ s_out = gp<S>(D.sphi[ob]);
+  const unsigned nU = (D.accum ? 0u : (k - 1) / D.N_phi) + (k - 1) / D.N_U;
+  GLOBAL const R* __restrict__ Up = D.has_U ? gp<const R>(D.U[par(nU)]) : nullptr;
+  GLOBAL const R* __restrict__ Tp = D.has_T ? gp<const R>(D.T[par(n_T(D, k - 1))]) : nullptr;
+  const PhaseConst<R> c = phase_const<R>(D);
+  const R U0 = kc<R>(D, K_U0), T0 = kc<R>(D, K_T0);
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
+  const bool wx = bcx != BC_PER, wy = bcy != BC_PER;
+
+  auto put_phi = [&](const YPhaseIn<R, S, Q>& in, int r0) {   // rows r0 + 1 .. r0 + 4
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int cc = tid + 256 * i;
+      if (cc < 4 * YBW) wphi[(r0 + 1 + cc / YBW) & 7][cc % YBW] = in.phi[i];
+    }
+  };
+  // collide rows r0 .. r0 + 3 (phase-field rows r0 - 1 .. r0 + 4 in LDS)
+  auto collide = [&](const YPhaseIn<R, S, Q>& in, int r0) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      int col, row;
+      if (!ym_cell(i, tx, ty, tid, w, r0, col, row)) continue;
+      if (resolve(x0 - 1 + col, nx, bcx) < 0 || resolve(row, ny, bcy) < 0) continue;   // beyond a wall
+      const R* rm = wphi[(row - 1) & 7];
+      const R* r0p = wphi[row & 7];
+      const R* rp = wphi[(row + 1) & 7];
+      R gx_, gy_;
+      iso_grad_rows(rm, r0p, rp, col + 1, gx_, gy_);
+      R sv[Q - 1];
+#pragma unroll
+      for (int q = 0; q < Q - 1; ++q) sv[q] = cvt_raw(in.s[i][q], (S*)nullptr);
+      R jx, jy;
+      if constexpr (Q == 5) {
+        jx = sv[0] - sv[2];
+        jy = sv[1] - sv[3];
+      } else {
+        jx = sv[0] - sv[2] + sv[4] - sv[5] - sv[6] + sv[7];
+        jy = sv[1] - sv[3] + sv[4] + sv[5] - sv[6] - sv[7];
+      }
+      const R Uv = Up ? in.U[i] + U0 : R(0);
+      const R Tv = Tp ? in.T[i] + T0 : c.theta_off;
+      R dP, Kx, Ky, A, je[2];
+      phase_collide(c, r0p[col + 1], gx_, gy_, jx, jy, Uv, Tv, dP, Kx, Ky, A, je);
+      R(*cr)[YCW] = wc[row & 7];
+      cr[0][col] = dP;
+      cr[1][col] = Kx;
+      cr[2][col] = Ky;
+      if constexpr (Q == 9) {
+        cr[3][col] = je[0];
+        cr[4][col] = je[1];
+      }
+      if (i == 0) {
+        wA[row & 7][tx] = A;
+#pragma unroll
+        for (int q = 0; q < Q - 1; ++q) wsv[row & 7][q][tx] = sv[q];
+      }
+    }
+  };
+
+  // prologue: phase-field rows ya - 4 .. ya + 1, collisions of ya - 3 .. ya
+  YPhaseIn<R, S, Q> in0, in1;
+  {
+    YPhaseIn<R, S, Q> lo;
+    ym_load_phase<R, S, Q>(nx, ny, px, bcx, bcy, x0, w, ya - 7, pl, tx, ty, tid, phi_in, s_in, Up, Tp, lo, false);
+    ym_load_phase<R, S, Q>(nx, ny, px, bcx, bcy, x0, w, ya - 3, pl, tx, ty, tid, phi_in, s_in, Up, Tp, in1);
+    put_phi(lo, ya - 7);   // rows ya - 6 .. ya - 3 (ya - 4 and ya - 3 are used)
+    put_phi(in1, ya - 3);  // rows ya - 2 .. ya + 1
+  }
+  __syncthreads();
+  collide(in1, ya - 3);
+  ym_load_phase<R, S, Q>(nx, ny, px, bcx, bcy, x0, w, ya + 1, pl, tx, ty, tid, phi_in, s_in, Up, Tp, in0);
+  __syncthreads();
+
+  for (int y = ya; y < yb; y += 4) {
+    // in0: collision inputs of rows y + 1 .. y + 4 and phase-field rows y + 2 .. y + 5
+    put_phi(in0, y + 1);
+    const YPhaseIn<R, S, Q> cur = in0;
+    if (y + 4 < yb)
+      ym_load_phase<R, S, Q>(nx, ny, px, bcx, bcy, x0, w, y + 5, pl, tx, ty, tid, phi_in, s_in, Up, Tp, in0);
+    __syncthreads();
+    collide(cur, y + 1);
+    __syncthreads();
+    const int gy = y + ty;
+    if (tx < w && gy < yb) {
+      // anisotropic pull streaming (Eq. 26) into the own site, in deviations
+      const int gx = x0 + tx, lx = tx + 1;
+      const bool edge = (wx && (x0 == 0 || x0 + w >= nx)) || (wy && (y == 0 || y + 4 >= ny));
+      const R A = wA[gy & 7][tx], iA = rcp(A), oA = R(1) - A;
+      const R phy = wphi[gy & 7][lx + 1];
+      const R(*co)[YCW] = wc[gy & 7];
+      const R dPo = co[0][lx];
+      R sv[Q - 1];
+#pragma unroll
+      for (int q = 0; q < Q - 1; ++q) sv[q] = wsv[gy & 7][q][tx];
+      R s0 = R(0);
+#pragma unroll
+      for (int q = 0; q < Q - 1; ++q) s0 -= sv[q];
+      R dn[Q];
+      dn[0] = (dPo * R(Lq::w(0)) - oA * s0) * iA;
+#pragma unroll
+      for (int q = 1; q < Q; ++q) {
+        const int ex = Lq::ex(q), ey = Lq::ey(q);
+        const bool wall = edge && ((wx && ((ex > 0 && gx == 0) || (ex < 0 && gx == nx - 1))) ||
+                                   (wy && ((ey > 0 && gy == 0) || (ey < 0 && gy == ny - 1))));
+        R dpost;
+        if (wall) {
+          dpost = dPo * R(Lq::w(q)) - R(Lq::cK) * (R(ex) * co[1][lx] + R(ey) * co[2][lx]);
+          if constexpr (Q == 9) dpost -= R(Lq::cJ(q)) * (R(ex) * co[3][lx] + R(ey) * co[4][lx]);
+        } else {
+          const R(*cu)[YCW] = wc[(gy - ey) & 7];
+          const int ux = lx - ex;
+          const R dphi = wphi[(gy - ey) & 7][ux + 1] - phy;
+          dpost = (dphi + cu[0][ux]) * R(Lq::w(q)) + R(Lq::cK) * (R(ex) * cu[1][ux] + R(ey) * cu[2][ux]);
+          if constexpr (Q == 9) dpost += R(Lq::cJ(q)) * (R(ex) * cu[3][ux] + R(ey) * cu[4][ux]);
+        }
+        dn[q] = (dpost - oA * sv[q - 1]) * iA;
+      }
+      R dphin = dn[0];
+#pragma unroll
+      for (int q = 1; q < Q; ++q) dphin += dn[q];
+      const unsigned o = (unsigned)gy * (unsigned)px + (unsigned)gx;
+      sto(phi_out, o, phy + dphin);
+#pragma unroll
+      for (int q = 1; q < Q; ++q) sto(plane(s_out, (q - 1) * pl), o, dn[q] - dphin * R(Lq::w(q)));
+    }
+    __syncthreads();
+  }
+}
+
 // =================================================================== transfer
 // Eq. (36)-(39): dphi = phi^{q+1} - phi^q; J = W0/(2 sqrt2) [1 + (1-k) U*]
 // dphi n^{q+1}; dU = ([1 + (1-k)U*] dphi - 2 div J) / kfac(phi^{q+1});
@@ -3047,6 +3273,12 @@ struct Launch {
     else if (TY == 8) k_phase<R, S, 8, 5><<<g, b, 0, st>>>(d, t, k);
     else if (TY == 16) k_phase<R, S, 16, 5><<<g, b, 0, st>>>(d, t, k);
     else k_phase<R, S, 32, 5><<<g, b, 0, st>>>(d, t, k);
+  }
+  // y-marching phase kernel over a list of column runs
+  static void phase_ym(int Q, dim3 g, hipStream_t st, const Dom* d, const int4* runs, unsigned k) {
+    const dim3 b(TX, BY);
+    if (Q == 9) k_phase_ym<R, S, 9><<<g, b, 0, st>>>(d, runs, k);
+    else k_phase_ym<R, S, 5><<<g, b, 0, st>>>(d, runs, k);
   }
   // phase + transfer in one kernel: 8-row tiles in FP64 (LDS), 8 or 16 otherwise
   static int phase_tr_rows(int TY) { return sizeof(R) == 8 ? 8 : (TY >= 16 ? 16 : 8); }

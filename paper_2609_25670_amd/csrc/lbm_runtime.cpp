@@ -30,6 +30,7 @@ struct Launch {
   static void transfer(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, unsigned k, Partial* p);
   static int phase_tr_rows(int TY);
   static void phase_tr(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, unsigned k, Partial* p);
+  static void phase_ym(int Q, dim3 g, hipStream_t st, const Dom* d, const int4* runs, unsigned k);
   static void scalar(int field, int TY, int Q, dim3 g, hipStream_t st, const Dom* d, const int4* t, unsigned k,
                      Partial* p);
   static void flow(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, unsigned k);
@@ -68,6 +69,7 @@ constexpr int kNTY = 4;
 constexpr int kTYs[kNTY] = {4, 8, 16, 32};
 constexpr long long kMaxGraphSteps = 4096;
 constexpr int kMaxCodes = 96;
+constexpr int kYRun = 64;          // rows per run of the 2D marching kernels (a multiple of every tile height)
 constexpr int kStagePlanes = 20;   // host staging planes: holds one D3Q19 population group
 
 std::string g_create_error;
@@ -80,6 +82,7 @@ struct TileSet {
 struct Group {
   int N;              // update factor shared by the domains of the group
   TileSet ts[kNTY];   // per tile height
+  TileSet runs;       // 64-wide column runs of kYRun rows (2D marching kernels)
 };
 
 struct Ops {
@@ -87,6 +90,7 @@ struct Ops {
   void (*transfer)(int, dim3, hipStream_t, const Dom*, const int4*, unsigned, Partial*);
   void (*phase_tr)(int, dim3, hipStream_t, const Dom*, const int4*, unsigned, Partial*);
   int (*phase_tr_rows)(int);
+  void (*phase_ym)(int, dim3, hipStream_t, const Dom*, const int4*, unsigned);
   void (*scalar)(int, int, int, dim3, hipStream_t, const Dom*, const int4*, unsigned, Partial*);
   void (*flow)(int, dim3, hipStream_t, const Dom*, const int4*, unsigned);
   void (*diag_tiles)(int, dim3, hipStream_t, const Dom*, const int4*, long long, Partial*);
@@ -99,7 +103,7 @@ struct Ops {
 template <class R, class S>
 Ops make_ops() {
   return Ops{Launch<R, S>::phase, Launch<R, S>::transfer, Launch<R, S>::phase_tr, Launch<R, S>::phase_tr_rows,
-             Launch<R, S>::scalar, Launch<R, S>::flow,
+             Launch<R, S>::phase_ym, Launch<R, S>::scalar, Launch<R, S>::flow,
              Launch<R, S>::diag_tiles, Launch<R, S>::tips, Launch<R, S>::init, Launch<R, S>::read,
              Launch<R, S>::write};
 }
@@ -165,6 +169,9 @@ struct lbm_ctx {
   bool use_graph = true;
   bool fuse = false;      // phase + transfer in one kernel (2D) when every domain allows it
   bool fusable = false;   // every domain at least 8 x 8 (the fused kernel's rings wrap once at most), D2Q5
+  int march = 0;          // 2D marching phase kernel: 0 by size, 1 always, -1 never
+  bool march_big = false; // the phase groups hold enough column runs to fill the chip
+  bool marchable = false; // every domain 2D and at least 16 x 16 (the marching windows wrap once at most)
   int qs = 5;             // scalar lattice of the (2D) context: 5 or 9
   hipGraphExec_t gexec = nullptr;
   int graph_ty = -1;
@@ -320,6 +327,11 @@ static int ty_slot(int rows) {
 // the cycle.
 static unsigned cycle_step(const lbm_ctx* c, long long k) { return (unsigned)((k - 1) % c->cycle + 1); }
 
+// whether the phase field runs on the marching kernel
+static bool use_march(const lbm_ctx* c) {
+  return c->marchable && (c->march > 0 || (c->march == 0 && c->march_big));
+}
+
 static void launch_step(lbm_ctx* c, hipStream_t st, unsigned k) {
   if (c->dim == 3) {
     c->ops3.step(c->H[0], st, c->d_dom, k, c->d_part);
@@ -333,7 +345,10 @@ static void launch_step(lbm_ctx* c, hipStream_t st, unsigned k) {
       if (fused) {
         c->ops.phase_tr(kTYs[tf], dim3(g.ts[tf].n), st, c->d_dom, g.ts[tf].d, k, c->d_part);
       } else {
-        c->ops.phase(TY, c->qs, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k);
+        if (use_march(c))
+          c->ops.phase_ym(c->qs, dim3(g.runs.n), st, c->d_dom, g.runs.d, k);
+        else
+          c->ops.phase(TY, c->qs, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k);
         c->ops.transfer(TY, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k, c->d_part);
       }
     }
@@ -354,7 +369,9 @@ static lbm_status upload_doms(lbm_ctx* c) {
 // Time each tile height on the kernels whose launches are idempotent for a
 // fixed k (they read one buffer and write the other: the phase kernel, or
 // the phase + transfer kernel with instantaneous coupling, and the flow)
-// and keep the fastest.
+// and keep the fastest.  The tiled phase kernel is timed also when the
+// phase field marches: it then stands in for the tiled transfer and
+// transports, which share its tile shape and access pattern.
 static lbm_status autotune(lbm_ctx* c) {
   hipEvent_t e0, e1;
   HIPCHK(c, hipEventCreate(&e0));
@@ -411,9 +428,11 @@ size_t lbm_workspace_bytes(const lbm_params* p, int32_t n, int32_t storage) {
   sizes_of(storage, rsz, ssz);
   size_t total = 0;
   long long tilesmax = 0;   // tiles at the smallest tile height
+  long long runs = 0;       // column runs of the 2D marching kernels
   size_t maxsites = 0;
   for (int i = 0; i < n; ++i) {
     if (!validate(p[i], i).empty()) return 0;
+    if (p[i].dim == 2) runs += (long long)((p[i].nx + 63) / 64) * ((p[i].ny + kYRun - 1) / kYRun);
     if ((p[i].dim == 3 && n != 1) || p[i].q_scalar != p[0].q_scalar) return 0;
     const size_t plane = (size_t)px_of(p[i].nx) * p[i].ny * (p[i].dim == 3 ? p[i].nz : 1);
     const Layout L = layout_of(p[i]);
@@ -428,6 +447,8 @@ size_t lbm_workspace_bytes(const lbm_params* p, int32_t n, int32_t storage) {
   // tile lists per tile height: "all" plus, per field, one list per group of
   // domains sharing an update factor (at most 8 groups, each padded by < 8)
   total += kNTY * (5 * (sizeof(int4) * (size_t)(padded + 64)) + 40 * 256);
+  // run lists: per field, one list per group (at most 8 groups, each padded by < 8)
+  total += 4 * (sizeof(int4) * (size_t)(runs + 64) + 8 * 256);
   total += align256(sizeof(Partial) * (size_t)tilesmax);
   total += align256(sizeof(int) * (size_t)tilesmax) + kNTY * align256(sizeof(int) * (n + 1));
   total += align256(sizeof(DiagOut) * n);
@@ -640,6 +661,13 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
   c->qs = p[0].q_scalar;
   c->fusable = true;
   for (int i = 0; i < n; ++i) c->fusable &= p[i].dim == 2 && p[i].q_scalar == 5 && p[i].nx >= 8 && p[i].ny >= 8;
+  c->marchable = true;
+  for (int i = 0; i < n; ++i) c->marchable &= p[i].dim == 2 && p[i].nx >= 16 && p[i].ny >= 16;
+  {
+    long long runs = 0;   // a column run is one block: marching pays when they are many
+    for (int i = 0; i < n; ++i) runs += (long long)((p[i].nx + 63) / 64) * ((p[i].ny + kYRun - 1) / kYRun);
+    c->march_big = runs >= 4 * 256;
+  }
   c->cycle = 2 * lcm;
   c->d_dom = (Dom*)take(sizeof(Dom) * n);
 
@@ -714,6 +742,16 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
           lbm_status s = build(kv.second, ti, g.ts[ti], nullptr);
           if (s != LBM_OK) return s;
         }
+      }
+      {
+        std::vector<int4> sp;
+        for (int d : kv.second)
+          for (int y0 = 0; y0 < p[d].ny; y0 += kYRun)
+            for (int x0 = 0; x0 < p[d].nx; x0 += 64) sp.push_back(make_int4(d, x0, y0, std::min(p[d].ny, y0 + kYRun)));
+        std::vector<int4> o = xcd_order(sp);
+        g.runs.d = (int4*)take(sizeof(int4) * o.size());
+        g.runs.n = (int)o.size();
+        HIPCHK(c, hipMemcpy(g.runs.d, o.data(), sizeof(int4) * o.size(), hipMemcpyHostToDevice));
       }
       gs.push_back(g);
     }
@@ -834,9 +872,12 @@ lbm_status lbm_configure(lbm_ctx* c, int32_t tile_rows, int32_t flags) {
     c->autotune = false;
     c->tuned = true;
   }
-  if (flags & ~3) return fail(c, LBM_EINVAL, "unknown configure flags");
+  if (flags & ~15) return fail(c, LBM_EINVAL, "unknown configure flags");
+  if ((flags & LBM_CFG_MARCH) && (flags & LBM_CFG_TILES))
+    return fail(c, LBM_EINVAL, "LBM_CFG_MARCH and LBM_CFG_TILES exclude each other");
   c->use_graph = (flags & LBM_CFG_GRAPH) != 0;
   c->fuse = (flags & LBM_CFG_FUSE_TRANSFER) != 0;
+  c->march = (flags & LBM_CFG_MARCH) ? 1 : (flags & LBM_CFG_TILES) ? -1 : 0;
   if (c->gexec) {   // the captured cycle follows the kernel choice
     HIPCHK(c, hipStreamSynchronize(c->stream));
     (void)hipGraphExecDestroy(c->gexec);
@@ -890,7 +931,10 @@ lbm_status lbm_kernel_times(lbm_ctx* c, int32_t reps, double* ms_out, double* pe
           const int tf = ty_slot(c->ops.phase_tr_rows(TY));
           c->ops.phase_tr(kTYs[tf], dim3(g.ts[tf].n), c->stream, c->d_dom, g.ts[tf].d, k, c->d_part);
         }
-        if (kind == 0 && !fused) c->ops.phase(TY, c->qs, grid, c->stream, c->d_dom, g.ts[ti].d, k);
+        if (kind == 0 && !fused && use_march(c))
+          c->ops.phase_ym(c->qs, dim3(g.runs.n), c->stream, c->d_dom, g.runs.d, k);
+        else if (kind == 0 && !fused)
+          c->ops.phase(TY, c->qs, grid, c->stream, c->d_dom, g.ts[ti].d, k);
         if (kind == 1) c->ops.transfer(TY, grid, c->stream, c->d_dom, g.ts[ti].d, k, c->d_part);
         if (kind == 2) c->ops.scalar(0, TY, c->qs, grid, c->stream, c->d_dom, g.ts[ti].d, k, c->d_part);
         if (kind == 3) c->ops.scalar(1, TY, c->qs, grid, c->stream, c->d_dom, g.ts[ti].d, k, c->d_part);

@@ -28,12 +28,13 @@ def _rel(a, b):
     return np.linalg.norm(a - b) / (nb if nb > 1e-300 else 1.0)
 
 
-def _gpu(wl, steps, storage="f64", names=("phi",), tile_rows=None, use_graph=True, domains=None, fuse=False):
+def _gpu(wl, steps, storage="f64", names=("phi",), tile_rows=None, use_graph=True, domains=None, fuse=False,
+         march=None):
     from paper_2609_25670_amd import simulation_for
 
     sim = simulation_for(wl, storage=storage)
     if tile_rows is not None:
-        sim.configure(tile_rows, use_graph, fuse)
+        sim.configure(tile_rows, use_graph, fuse, march)
     diag = sim.step(steps, diag=True)
     outs = [sim.read(i, names) for i in (domains if domains is not None else range(sim.n))]
     sim.close()
@@ -152,20 +153,37 @@ def test_batched_uneven_domains_fp64(use_graph):
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 def test_tile_shapes_graph_and_fusion_are_bitwise_identical(storage):
     """Race detector: every tile height, graph replay versus eager launches,
-    and the phase + transfer kernel versus the two separate kernels give
-    bitwise-identical state."""
+    the phase + transfer kernel versus the two separate kernels, and the
+    marching phase kernel versus the tiled one give bitwise-identical
+    state."""
     wl = L.reduced(L.thermosolutal_flow_1024(), 130, 75)
     wl["domains"][0]["tau0"] = 40.0
     names = ("phi", "U", "T", "rho", "vel", "f_phi", "jU", "jT", "f_F")
     ref = None
-    for rows, g, fuse in [(r, g, f) for r in (4, 8, 16, 32) for g in (True, False) for f in (True, False)]:
-        _say(f"case determinism {storage} rows={rows} graph={g} fused={fuse}")
-        (got,), _ = _gpu(wl, 64, storage=storage, names=names, tile_rows=rows, use_graph=g, fuse=fuse)
+    runs = [(r, g, f, False) for r in (4, 8, 16, 32) for g in (True, False) for f in (True, False)]
+    runs += [(r, g, False, True) for r in (4, 32) for g in (True, False)]
+    for rows, g, fuse, march in runs:
+        _say(f"case determinism {storage} rows={rows} graph={g} fused={fuse} march={march}")
+        (got,), _ = _gpu(wl, 64, storage=storage, names=names, tile_rows=rows, use_graph=g, fuse=fuse, march=march)
         if ref is None:
             ref = got
         else:
             for n in names:
-                assert np.array_equal(got[n], ref[n]), (rows, g, fuse, n)
+                assert np.array_equal(got[n], ref[n]), (rows, g, fuse, march, n)
+
+
+@pytest.mark.parametrize("q", [5, 9])
+def test_marching_phase_kernel_fp64(q):
+    """The marching phase kernel on the walled solutal case (70 rows: a
+    second run of 6 rows, 150 = 2 x 64 + 22 columns) and the D2Q9 lattice:
+    FP64 parity with the oracle."""
+    wl = L.reduced(L.solutal_512(), 150, 70)
+    wl["domains"][0]["q_scalar"] = q
+    names = ("phi", "U", "f_phi", "jU")
+    _say(f"case marching phase kernel D2Q{q} fp64 150x70 120 steps")
+    (got,), diag = _gpu(wl, 120, names=names, tile_rows=8, march=True)
+    dom = oracle.run(wl["domains"][0], 120)
+    _compare(f"marching D2Q{q}", got, _oracle_fields(dom, names), TOL64)
 
 
 def test_checkpoint_restore_is_bitwise():
