@@ -203,14 +203,15 @@ lbm_status lbm_write_fields(lbm_ctx* ctx, int32_t domain, uint32_t mask,
  *                           three sites (domains of at least 8 x 8; results
  *                           bitwise identical to the separate kernels; slower
  *                           on MI355X at every size measured, so off by default)
- *   LBM_CFG_MARCH           2D: the phase kernel always walks 64-wide columns
- *                           up in runs of 64 rows instead of tiling them
- *                           (domains of at least 16 x 16; results bitwise
- *                           identical to the tiles)
- *   LBM_CFG_TILES           2D: the phase kernel always tiles
- * With neither of the last two, the phase kernel marches when every domain
- * is at least 16 x 16 and the context holds at least 1024 column runs
- * (enough blocks to fill the chip), and tiles otherwise.
+ *   LBM_CFG_MARCH           2D: the phase, transfer and T-transport kernels
+ *                           always walk 64-wide columns up in runs of 64
+ *                           rows instead of tiling them (domains of at least
+ *                           16 x 16; results bitwise identical to the tiles;
+ *                           the U transport stays tiled)
+ *   LBM_CFG_TILES           2D: every kernel tiles
+ * With neither of the last two, the kernels march when every domain is at
+ * least 16 x 16 and the context holds at least 1024 column runs (enough
+ * blocks to fill the chip), and tile otherwise.
  * Default after lbm_create: autotune, LBM_CFG_GRAPH.  Unknown flags, or
  * LBM_CFG_MARCH with LBM_CFG_TILES: LBM_EINVAL. */
 enum { LBM_CFG_GRAPH = 1, LBM_CFG_FUSE_TRANSFER = 2, LBM_CFG_MARCH = 4, LBM_CFG_TILES = 8 };

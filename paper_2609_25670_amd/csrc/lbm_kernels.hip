@@ -851,6 +851,208 @@ __global__ __launch_bounds__(NTHR) void k_transfer(const Dom* __restrict__ doms,
   }
 }
 
+// raw loads of the marching transfer: J inputs of rows r0 .. r0 + 3 (phi^q
+// and U* at the column and ring cells, ghosted: beyond a wall, the
+// boundary node) and phi^{q+1} rows r0 + 1 .. r0 + 4
+template <class R>
+struct YTrIn {
+  R po[2], U[2];
+  R phi[2];
+};
+template <class R>
+__device__ __forceinline__ void ym_load_tr(int nx, int ny, int px, int bcx, int bcy, int x0, int w, int r0, int tx,
+                                           int ty, int tid, GLOBAL const R* pn, GLOBAL const R* po,
+                                           GLOBAL const R* Uin, YTrIn<R>& in, bool inputs = true) {
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    if (!inputs) break;
+    int col, row;
+    if (!ym_cell(i, tx, ty, tid, w, r0, col, row)) continue;
+    const unsigned o = (unsigned)ghost(row, ny, bcy) * (unsigned)px + (unsigned)ghost(x0 - 1 + col, nx, bcx);
+    in.po[i] = ldo(po, o);
+    in.U[i] = ldo(Uin, o);
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int cc = tid + 256 * i;
+    if (cc < 4 * YBW) {
+      const int gx = ghost(x0 - 2 + cc % YBW, nx, bcx), gy = ghost(r0 + 1 + cc / YBW, ny, bcy);
+      in.phi[i] = ldo(pn, (unsigned)gy * (unsigned)px + (unsigned)gx);
+    }
+  }
+}
+// the own site of a row: phi^q, U*, T before the injection (or its pending
+// plane), and phi^{q+1} when there is no U (and so no window)
+template <class R>
+struct YTrOwn {
+  R po, U, T, pn;
+};
+template <class R>
+__device__ __forceinline__ void ym_load_own(int ny, int px, int x0, int w, int row, int tx, bool hasU,
+                                            GLOBAL const R* pn, GLOBAL const R* po, GLOBAL const R* Uin,
+                                            GLOBAL const R* Tsrc, YTrOwn<R>& m) {
+  if (tx >= w || row < 0 || row >= ny) return;
+  const unsigned o = (unsigned)row * (unsigned)px + (unsigned)(x0 + tx);
+  m.po = ldo(po, o);
+  if (hasU) m.U = ldo(Uin, o);
+  else m.pn = ldo(pn, o);
+  if (Tsrc) m.T = ldo(Tsrc, o);
+}
+
+// phase-step transfer (Eq. 36-39) marching up a column: J on the rows
+// ahead (column plus ring; beyond a wall, the boundary node's J with the
+// normal component negated), then the compact divergence, dU, dT and the
+// injection on the current rows.  The largest |dU| of the run goes to the
+// partial slot of its first tile at the tile height in use (the run's
+// other tiles' slots are cleared), where the diagnostics reduce it.
+template <class R>
+__global__ __launch_bounds__(NTHR) void k_transfer_ym(const Dom* __restrict__ doms, const int4* __restrict__ runs,
+                                                       unsigned k, Partial* __restrict__ part,
+                                                       const int* __restrict__ slot0, int TY) {
+  __shared__ R wphi[8][YBW];
+  __shared__ R wJx[8][YCW], wJy[8][YCW];
+  __shared__ R red[NTHR / 64];
+
+  const int4 t = runs[blockIdx.x];
+  if (t.x < 0) return;
+  const Dom& D = doms[t.x];
+  if (k % D.N_phi) return;
+  const int nx = D.nx, ny = D.ny, px = D.px, bcx = D.bc[0], bcy = D.bc[1];
+  const int x0 = t.y, ya = t.z, yb = t.w;
+  const int w = min(TX, nx - x0);
+  GLOBAL const R* __restrict__ phi_old = gp<const R>(D.phi[par(n_phi(D, k - 1))]);
+  GLOBAL const R* __restrict__ phi_new = gp<const R>(D.phi[par(n_phi(D, k))]);
+  const unsigned nU = (D.accum ? 0u : (k - 1) / D.N_phi) + (k - 1) / D.N_U;
+  const bool hasU = D.has_U, hasT = D.has_T, accum = D.accum;
+  GLOBAL const R* __restrict__ Uin = hasU ? gp<const R>(D.U[par(nU)]) : nullptr;
+  GLOBAL R* __restrict__ Uout = hasU ? gp<R>(D.U[par(nU + 1)]) : nullptr;
+  GLOBAL R* __restrict__ Tout = hasT ? gp<R>(D.T[par(n_T(D, k - 1) + 1)]) : nullptr;
+  GLOBAL R* __restrict__ PU = gp<R>(D.PU);
+  GLOBAL R* __restrict__ PT = gp<R>(D.PT);
+  // T before the injection: the pending plane (accumulated coupling) or T
+  GLOBAL const R* __restrict__ Tsrc = hasT ? (accum ? (GLOBAL const R*)PT : gp<const R>(D.T[par(n_T(D, k - 1))]))
+                                           : nullptr;
+  const R omk = kc<R>(D, K_OMK), opk = kc<R>(D, K_OPK);
+  const R Uref = kc<R>(D, K_U0);   // the U plane holds U - U0
+  const R cJ = kc<R>(D, K_CJ);
+  const R cT = kc<R>(D, K_CT);
+  const R rcS = kc<R>(D, K_RCS), rcL = kc<R>(D, K_RCL);
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
+
+  auto put_phi = [&](const YTrIn<R>& in, int r0) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int cc = tid + 256 * i;
+      if (cc < 4 * YBW) wphi[(r0 + 1 + cc / YBW) & 7][cc % YBW] = in.phi[i];
+    }
+  };
+  // J of rows r0 .. r0 + 3 (phi^{q+1} rows r0 - 1 .. r0 + 4 in LDS)
+  auto flux = [&](const YTrIn<R>& in, int r0) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      int col, row;
+      if (!ym_cell(i, tx, ty, tid, w, r0, col, row)) continue;
+      int rx = x0 - 1 + col, ry = row;
+      bool mx = false, my = false;
+      if (rx < 0 && bcx != BC_PER) { rx = 0; mx = true; }
+      if (rx >= nx && bcx != BC_PER) { rx = nx - 1; mx = true; }
+      if (ry < 0 && bcy != BC_PER) { ry = 0; my = true; }
+      if (ry >= ny && bcy != BC_PER) { ry = ny - 1; my = true; }
+      const int bcol = rx - (x0 - 2);   // window column of the (boundary) node
+      R gxv, gyv;
+      iso_grad_rows(wphi[(ry - 1) & 7], wphi[ry & 7], wphi[(ry + 1) & 7], bcol, gxv, gyv);
+      const R gg = gxv * gxv + gyv * gyv;
+      R Jx = R(0), Jy = R(0);
+      if (gg >= R(GRAD_EPS2)) {
+        const R ig = rsq(gg);
+        const R a = cJ * (R(1) + omk * (in.U[i] + Uref)) * (wphi[ry & 7][bcol] - in.po[i]) * ig;
+        Jx = -a * gxv;
+        Jy = -a * gyv;
+      }
+      wJx[row & 7][col] = mx ? -Jx : Jx;
+      wJy[row & 7][col] = my ? -Jy : Jy;
+    }
+  };
+
+  R amax = R(0);
+  YTrIn<R> in0;
+  YTrOwn<R> own;
+  // own sites of rows ya .. ya + 3; with U, phi^{q+1} rows ya - 6 .. ya + 1
+  // and J of rows ya - 3 .. ya
+  ym_load_own(ny, px, x0, w, ya + ty, tx, hasU, phi_new, phi_old, Uin, Tsrc, own);
+  if (hasU) {
+    YTrIn<R> lo, mid;
+    ym_load_tr(nx, ny, px, bcx, bcy, x0, w, ya - 7, tx, ty, tid, phi_new, phi_old, Uin, lo, false);
+    ym_load_tr(nx, ny, px, bcx, bcy, x0, w, ya - 3, tx, ty, tid, phi_new, phi_old, Uin, mid);
+    put_phi(lo, ya - 7);
+    put_phi(mid, ya - 3);
+    __syncthreads();
+    flux(mid, ya - 3);
+    ym_load_tr(nx, ny, px, bcx, bcy, x0, w, ya + 1, tx, ty, tid, phi_new, phi_old, Uin, in0);
+  }
+  __syncthreads();
+
+  for (int y = ya; y < yb; y += 4) {
+    // in0: J inputs of rows y + 1 .. y + 4, phi^{q+1} rows y + 2 .. y + 5;
+    // own: the own site of row y + ty
+    if (hasU) put_phi(in0, y + 1);
+    const YTrIn<R> cur = in0;
+    const YTrOwn<R> me = own;
+    if (y + 4 < yb) {   // prefetch for the next rows
+      if (hasU) ym_load_tr(nx, ny, px, bcx, bcy, x0, w, y + 5, tx, ty, tid, phi_new, phi_old, Uin, in0);
+      ym_load_own(ny, px, x0, w, y + 4 + ty, tx, hasU, phi_new, phi_old, Uin, Tsrc, own);
+    }
+    __syncthreads();
+    if (hasU) flux(cur, y + 1);
+    __syncthreads();
+    const int gy = y + ty;
+    if (tx < w && gy < yb) {
+      const int gx = x0 + tx, lx = tx + 1;
+      const unsigned o = (unsigned)gy * (unsigned)px + (unsigned)gx;
+      const R pn = hasU ? wphi[gy & 7][lx + 1] : me.pn;
+      const R dphi = pn - me.po;
+      if (hasU) {
+        const int rm = (gy - 1) & 7, r0 = gy & 7, rp = (gy + 1) & 7;
+        const R div = (wJx[r0][lx + 1] - wJx[r0][lx - 1]) * R(1.0 / 3.0) +
+                      (wJx[rp][lx + 1] - wJx[rp][lx - 1] - wJx[rm][lx - 1] + wJx[rm][lx + 1]) * R(1.0 / 12.0) +
+                      (wJy[rp][lx] - wJy[rm][lx]) * R(1.0 / 3.0) +
+                      (wJy[rp][lx + 1] + wJy[rp][lx - 1] - wJy[rm][lx - 1] - wJy[rm][lx + 1]) * R(1.0 / 12.0);
+        const R Us = me.U;
+        const R dU = ((R(1) + omk * (Us + Uref)) * dphi - R(2) * div) * rcp(opk - omk * pn);
+        amax = fmax(amax, fabs(dU));
+        if (accum)
+          sto(PU, o, ldo(PU, o) + dU);
+        else
+          sto(Uout, o, Us + dU);
+      }
+      if (hasT) {
+        const R rc = (R(1) + pn) * R(0.5) * rcS + (R(1) - pn) * R(0.5) * rcL;
+        const R dT = cT * dphi * rcp(R(2) * rc);
+        if (accum)
+          sto(PT, o, me.T + dT);
+        else
+          sto(Tout, o, me.T + dT);
+      }
+    }
+    __syncthreads();
+  }
+  if (part && hasU) {
+    for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_down(amax, off, 64));
+    if (tx == 0) red[ty] = amax;
+    __syncthreads();
+    if (tid == 0) {
+      R m = red[0];
+      for (int wv = 1; wv < NTHR / 64; ++wv) m = fmax(m, red[wv]);
+      const int ntx = (nx + 63) / 64, tcol = x0 / 64;
+      for (int r = ya / TY; r * TY < yb; ++r) {
+        Partial& P = part[slot0[t.x] + r * ntx + tcol];
+        P.S_phi = r == ya / TY ? double(m) : 0.0;
+        if (!accum) P.J_U = r == ya / TY ? double(m) : 0.0;
+      }
+    }
+  }
+}
+
 // =================================================================== fused phase + transfer
 // One phase update and its transfer (Eq. 26, then Eq. 36-39) in a single
 // pass over a 64 x TY tile.  The transfer at a site needs phi^{q+1} two
@@ -1310,6 +1512,262 @@ __global__ __launch_bounds__(NTHR) void k_scalar(const Dom* __restrict__ doms, c
     }
   }
 }
+
+// raw loads of the marching scalar transport for the rows r0 .. r0 + 3:
+// chi, j and the velocity at the column and ring cells (beyond a wall: no
+// cell), the phase field rows r0 + 1 .. r0 + 4, and the own pending
+// increment of row r0 - 1 + ty (the row streamed while these are collided)
+template <class R, class S>
+struct YScIn {
+  R chi[2], u[2][2];
+  typename RawT<S>::type j[2][2];
+  R phi[2];
+  R pend;
+};
+template <class R, class S>
+__device__ __forceinline__ void ym_load_sc(int nx, int ny, int px, int bcx, int bcy, int x0, int w, int r0, int tx,
+                                           int ty, int tid, long long pl, bool need_phi, GLOBAL const R* phis,
+                                           GLOBAL const R* cin, GLOBAL const typename RawT<S>::type* jin,
+                                           GLOBAL const R* vel, GLOBAL const R* pend, YScIn<R, S>& in,
+                                           bool inputs = true) {
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    if (!inputs) break;
+    int col, row;
+    if (!ym_cell(i, tx, ty, tid, w, r0, col, row)) continue;
+    const int gx = resolve(x0 - 1 + col, nx, bcx), gy = resolve(row, ny, bcy);
+    if (gx < 0 || gy < 0) continue;
+    const unsigned o = (unsigned)gy * (unsigned)px + (unsigned)gx;
+    in.chi[i] = ldo(cin, o);
+    in.j[i][0] = *at(jin, o);
+    in.j[i][1] = *at(plane(jin, pl), o);
+    if (vel) {
+      in.u[i][0] = ldo(vel, o);
+      in.u[i][1] = ldo(plane(vel, pl), o);
+    }
+  }
+  if (need_phi) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int cc = tid + 256 * i;
+      if (cc < 4 * YBW) {
+        const int gx = ghost(x0 - 2 + cc % YBW, nx, bcx), gy = ghost(r0 + 1 + cc / YBW, ny, bcy);
+        in.phi[i] = ldo(phis, (unsigned)gy * (unsigned)px + (unsigned)gx);
+      }
+    }
+  }
+  const int oy = r0 - 1 + ty;
+  if (pend && inputs && tx < w && oy >= 0 && oy < ny) in.pend = ldo(pend, (unsigned)oy * (unsigned)px + (unsigned)(x0 + tx));
+}
+
+// scalar transport (U: FIELD 0, T: FIELD 1) marching up a column: the
+// collision of Eq. (14) with the equilibrium of Eq. (19)-(20), tau of Eq.
+// (7) or (11) and the source of Eq. (8) or (12) with grad chi from Eq. (40)
+// on the rows ahead, then the pull streaming of Eq. (25) on the current
+// rows.  With accumulated coupling the largest pending |dU| of the run goes
+// to the partial slot of its first tile at the tile height in use.
+template <class R, class S, int FIELD, int Q>
+__global__ __launch_bounds__(NTHR) void k_scalar_ym(const Dom* __restrict__ doms, const int4* __restrict__ runs,
+                                                     unsigned k, Partial* __restrict__ part,
+                                                     const int* __restrict__ slot0, int TY) {
+  using Lq = Lat2<Q>;
+  using SR = typename RawT<S>::type;
+  constexpr int NV = Q == 9 ? 6 : 4;   // chi, dt Q, Kx, Ky (and j_eq in D2Q9)
+  __shared__ R wphi[8][YBW];
+  __shared__ R wc[8][NV][YCW];
+  __shared__ R red[NTHR / 64];
+
+  const int4 t = runs[blockIdx.x];
+  if (t.x < 0) return;
+  const Dom& D = doms[t.x];
+  const int N = FIELD == 0 ? D.N_U : D.N_T;
+  if (k % N) return;
+  const int nx = D.nx, ny = D.ny, px = D.px, bcx = D.bc[0], bcy = D.bc[1];
+  const long long pl = D.plane;
+  const int x0 = t.y, ya = t.z, yb = t.w;
+  const int w = min(TX, nx - x0);
+  GLOBAL const R* __restrict__ cin;
+  GLOBAL R* __restrict__ cout;
+  GLOBAL const SR* __restrict__ jin;
+  GLOBAL S* __restrict__ jout;
+  GLOBAL R* __restrict__ pend;
+  if (FIELD == 0) {
+    const unsigned nU = (D.accum ? 0u : k / D.N_phi) + (k - 1) / D.N_U;
+    cin = gp<const R>(D.U[par(nU)]);
+    cout = gp<R>(D.U[par(nU + 1)]);
+    jin = gp<const SR>(D.jU[par(n_jU(D, k - 1))]);
+    jout = gp<S>(D.jU[par(n_jU(D, k))]);
+    pend = gp<R>(D.PU);
+  } else {
+    cin = gp<const R>(D.T[par(n_Ttr(D, k) + (k - 1) / D.N_T)]);
+    cout = gp<R>(D.T[par(n_Ttr(D, k) + k / D.N_T)]);
+    jin = gp<const SR>(D.jT[par(n_jT(D, k - 1))]);
+    jout = gp<S>(D.jT[par(n_jT(D, k))]);
+    pend = gp<R>(D.PT);
+  }
+  GLOBAL const R* __restrict__ phis = gp<const R>(D.phi[par(n_phi(D, k))]);
+  GLOBAL const R* __restrict__ vel = D.has_F ? gp<const R>(D.vel[par(n_F(D, k - 1))]) : nullptr;
+  const bool need_phi = FIELD == 0 || D.T_var;
+  const bool accum = D.accum;
+  GLOBAL const R* __restrict__ pend_in = accum ? (GLOBAL const R*)pend : nullptr;
+  const R dt = kc<R>(D, FIELD == 0 ? K_DTU : K_DTT);
+  const R omk = kc<R>(D, K_OMK), opk = kc<R>(D, K_OPK);
+  const R DS = kc<R>(D, K_DS), DL = kc<R>(D, K_DL);
+  const R hkS = kc<R>(D, K_HKS), hkL = kc<R>(D, K_HKL), hrcS = kc<R>(D, K_HRCS), hrcL = kc<R>(D, K_HRCL);
+  const R itau_const = rcp(R(3) * dt * kc<R>(D, K_ALPHAL) + R(0.5));
+  const R cref = kc<R>(D, FIELD == 0 ? K_U0 : K_T0);
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
+  const bool wx = bcx != BC_PER, wy = bcy != BC_PER;
+
+  auto put_phi = [&](const YScIn<R, S>& in, int r0) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int cc = tid + 256 * i;
+      if (cc < 4 * YBW) wphi[(r0 + 1 + cc / YBW) & 7][cc % YBW] = in.phi[i];
+    }
+  };
+  auto collide = [&](const YScIn<R, S>& in, int r0) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      int col, row;
+      if (!ym_cell(i, tx, ty, tid, w, r0, col, row)) continue;
+      if (resolve(x0 - 1 + col, nx, bcx) < 0 || resolve(row, ny, bcy) < 0) continue;   // beyond a wall
+      const R chi = in.chi[i];
+      const R ca = chi + cref;   // the plane holds chi - chi_ref
+      const R uxv = vel ? in.u[i][0] : R(0), uyv = vel ? in.u[i][1] : R(0);
+      const R jxv = cvt_raw(in.j[i][0], (S*)nullptr), jyv = cvt_raw(in.j[i][1], (S*)nullptr);
+      const R jex = ca * uxv * dt, jey = ca * uyv * dt;
+      R itau, Qs = R(0);
+      if (FIELD == 0) {
+        const R* r0p = wphi[row & 7];
+        const R phi = r0p[col + 1];
+        const R ikf = rcp(opk - omk * phi);
+        const R coeff = ((R(1) + phi) * DS + (R(1) - phi) * DL) * ikf;            // Eq. (7)
+        itau = rcp(R(3) * dt * coeff + R(0.5));
+        const R gcx = -R(3) * itau * (jxv - jex), gcy = -R(3) * itau * (jyv - jey);  // Eq. (40)
+        R gpx, gpy;
+        iso_grad_rows(wphi[(row - 1) & 7], r0p, wphi[(row + 1) & 7], col + 1, gpx, gpy);
+        Qs = -omk * coeff * (gcx * gpx + gcy * gpy) * ikf;                         // Eq. (8), 1st term
+      } else if (need_phi) {
+        const R* r0p = wphi[row & 7];
+        const R phi = r0p[col + 1];
+        const R irc = rcp((R(1) + phi) * hrcS + (R(1) - phi) * hrcL);
+        const R coeff = ((R(1) + phi) * hkS + (R(1) - phi) * hkL) * irc;          // Eq. (11)
+        itau = rcp(R(3) * dt * coeff + R(0.5));
+        const R gcx = -R(3) * itau * (jxv - jex), gcy = -R(3) * itau * (jyv - jey);
+        R gpx, gpy;
+        iso_grad_rows(wphi[(row - 1) & 7], r0p, wphi[(row + 1) & 7], col + 1, gpx, gpy);
+        Qs = (hrcS - hrcL) * irc * coeff * (gcx * gpx + gcy * gpy);               // Eq. (12), 1st term
+      } else {
+        itau = itau_const;
+      }
+      const R om = R(1) - itau;
+      R(*cr)[YCW] = wc[row & 7];
+      cr[0][col] = chi;
+      cr[1][col] = dt * Qs;
+      cr[2][col] = jex + om * (jxv - jex);
+      cr[3][col] = jey + om * (jyv - jey);
+      if constexpr (Q == 9) {
+        cr[4][col] = jex;
+        cr[5][col] = jey;
+      }
+    }
+  };
+
+  R amax = R(0);
+  YScIn<R, S> in0;
+  {
+    YScIn<R, S> lo, mid;
+    if (need_phi) {
+      ym_load_sc<R, S>(nx, ny, px, bcx, bcy, x0, w, ya - 7, tx, ty, tid, pl, true, phis, cin, jin, vel, nullptr, lo,
+                       false);
+      put_phi(lo, ya - 7);
+    }
+    ym_load_sc<R, S>(nx, ny, px, bcx, bcy, x0, w, ya - 3, tx, ty, tid, pl, need_phi, phis, cin, jin, vel, nullptr, mid);
+    if (need_phi) put_phi(mid, ya - 3);
+    __syncthreads();
+    collide(mid, ya - 3);
+    ym_load_sc<R, S>(nx, ny, px, bcx, bcy, x0, w, ya + 1, tx, ty, tid, pl, need_phi, phis, cin, jin, vel, pend_in,
+                     in0);
+  }
+  __syncthreads();
+
+  for (int y = ya; y < yb; y += 4) {
+    // in0: inputs of rows y + 1 .. y + 4, phase field rows y + 2 .. y + 5,
+    // own pending increment of row y + ty (in pcur)
+    if (need_phi) put_phi(in0, y + 1);
+    const YScIn<R, S> cur = in0;
+    if (y + 4 < yb)
+      ym_load_sc<R, S>(nx, ny, px, bcx, bcy, x0, w, y + 5, tx, ty, tid, pl, need_phi, phis, cin, jin, vel, pend_in,
+                       in0);
+    __syncthreads();
+    collide(cur, y + 1);
+    __syncthreads();
+    const int gy = y + ty;
+    if (tx < w && gy < yb) {
+      // pull streaming (Eq. 25) in deviations d_i = f_i - w_i chi(y)
+      const int gx = x0 + tx, lx = tx + 1;
+      const bool edge = (wx && (x0 == 0 || x0 + w >= nx)) || (wy && (y == 0 || y + 4 >= ny));
+      const R(*co)[YCW] = wc[gy & 7];
+      const R cy = co[0][lx], dPo = co[1][lx];
+      R dq[Q];
+      dq[0] = dPo * R(Lq::w(0));
+#pragma unroll
+      for (int q = 1; q < Q; ++q) {
+        const int ex = Lq::ex(q), ey = Lq::ey(q);
+        const bool wall = edge && ((wx && ((ex > 0 && gx == 0) || (ex < 0 && gx == nx - 1))) ||
+                                   (wy && ((ey > 0 && gy == 0) || (ey < 0 && gy == ny - 1))));
+        if (edge && FIELD == 1 && D.T_dirlow && ey > 0 && gy == 0) {
+          // anti-bounce-back to T0 at the wall y = -1/2 (the plane holds T - T0)
+          dq[q] = -(R(2) * cy + dPo) * R(Lq::w(q)) + R(Lq::cK) * (R(ex) * co[2][lx] + R(ey) * co[3][lx]);
+          if constexpr (Q == 9) dq[q] += R(Lq::cJ(q)) * (R(ex) * co[4][lx] + R(ey) * co[5][lx]);
+        } else if (wall) {
+          dq[q] = dPo * R(Lq::w(q)) - R(Lq::cK) * (R(ex) * co[2][lx] + R(ey) * co[3][lx]);
+          if constexpr (Q == 9) dq[q] -= R(Lq::cJ(q)) * (R(ex) * co[4][lx] + R(ey) * co[5][lx]);
+        } else {
+          const R(*cu)[YCW] = wc[(gy - ey) & 7];
+          const int ux = lx - ex;
+          dq[q] = (cu[0][ux] - cy + cu[1][ux]) * R(Lq::w(q)) + R(Lq::cK) * (R(ex) * cu[2][ux] + R(ey) * cu[3][ux]);
+          if constexpr (Q == 9) dq[q] += R(Lq::cJ(q)) * (R(ex) * cu[4][ux] + R(ey) * cu[5][ux]);
+        }
+      }
+      const unsigned o = (unsigned)gy * (unsigned)px + (unsigned)gx;
+      R sum = dq[0];
+#pragma unroll
+      for (int q = 1; q < Q; ++q) sum += dq[q];
+      R chin = cy + sum;
+      if (accum) {
+        chin += cur.pend;
+        sto(pend, o, R(0));
+        amax = fmax(amax, fabs(cur.pend));
+      }
+      sto(cout, o, chin);
+      R jx = R(0), jy = R(0);
+#pragma unroll
+      for (int q = 1; q < Q; ++q) {
+        if (Lq::ex(q) > 0) jx += dq[q];
+        if (Lq::ex(q) < 0) jx -= dq[q];
+        if (Lq::ey(q) > 0) jy += dq[q];
+        if (Lq::ey(q) < 0) jy -= dq[q];
+      }
+      sto(jout, o, jx);
+      sto(plane(jout, pl), o, jy);
+    }
+    __syncthreads();
+  }
+  if (FIELD == 0 && accum && part) {
+    for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_down(amax, off, 64));
+    if (tx == 0) red[ty] = amax;
+    __syncthreads();
+    if (tid == 0) {
+      R m = red[0];
+      for (int wv = 1; wv < NTHR / 64; ++wv) m = fmax(m, red[wv]);
+      const int ntx = (nx + 63) / 64, tcol = x0 / 64;
+      for (int r = ya / TY; r * TY < yb; ++r) part[slot0[t.x] + r * ntx + tcol].J_U = r == ya / TY ? double(m) : 0.0;
+    }
+  }
+}
+
 
 // =================================================================== flow
 // D2Q9 MRT (Eq. 27-32) with Guo forcing (Eq. 30), then the weighted partial
@@ -3273,6 +3731,24 @@ struct Launch {
     else if (TY == 8) k_phase<R, S, 8, 5><<<g, b, 0, st>>>(d, t, k);
     else if (TY == 16) k_phase<R, S, 16, 5><<<g, b, 0, st>>>(d, t, k);
     else k_phase<R, S, 32, 5><<<g, b, 0, st>>>(d, t, k);
+  }
+  // y-marching scalar transport over a list of column runs
+  static void scalar_ym(int field, int Q, dim3 g, hipStream_t st, const Dom* d, const int4* runs, unsigned k,
+                        Partial* p, const int* slot0, int TY) {
+    const dim3 b(TX, BY);
+    if (field == 0) {
+      if (Q == 9) k_scalar_ym<R, S, 0, 9><<<g, b, 0, st>>>(d, runs, k, p, slot0, TY);
+      else k_scalar_ym<R, S, 0, 5><<<g, b, 0, st>>>(d, runs, k, p, slot0, TY);
+    } else {
+      if (Q == 9) k_scalar_ym<R, S, 1, 9><<<g, b, 0, st>>>(d, runs, k, p, slot0, TY);
+      else k_scalar_ym<R, S, 1, 5><<<g, b, 0, st>>>(d, runs, k, p, slot0, TY);
+    }
+  }
+  // y-marching transfer over a list of column runs; slot0: partial slots of
+  // the tile height TY in use
+  static void transfer_ym(dim3 g, hipStream_t st, const Dom* d, const int4* runs, unsigned k, Partial* p,
+                          const int* slot0, int TY) {
+    k_transfer_ym<R><<<g, dim3(TX, BY), 0, st>>>(d, runs, k, p, slot0, TY);
   }
   // y-marching phase kernel over a list of column runs
   static void phase_ym(int Q, dim3 g, hipStream_t st, const Dom* d, const int4* runs, unsigned k) {

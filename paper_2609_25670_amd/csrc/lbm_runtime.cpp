@@ -31,6 +31,10 @@ struct Launch {
   static int phase_tr_rows(int TY);
   static void phase_tr(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, unsigned k, Partial* p);
   static void phase_ym(int Q, dim3 g, hipStream_t st, const Dom* d, const int4* runs, unsigned k);
+  static void transfer_ym(dim3 g, hipStream_t st, const Dom* d, const int4* runs, unsigned k, Partial* p,
+                          const int* slot0, int TY);
+  static void scalar_ym(int field, int Q, dim3 g, hipStream_t st, const Dom* d, const int4* runs, unsigned k,
+                        Partial* p, const int* slot0, int TY);
   static void scalar(int field, int TY, int Q, dim3 g, hipStream_t st, const Dom* d, const int4* t, unsigned k,
                      Partial* p);
   static void flow(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, unsigned k);
@@ -91,6 +95,8 @@ struct Ops {
   void (*phase_tr)(int, dim3, hipStream_t, const Dom*, const int4*, unsigned, Partial*);
   int (*phase_tr_rows)(int);
   void (*phase_ym)(int, dim3, hipStream_t, const Dom*, const int4*, unsigned);
+  void (*transfer_ym)(dim3, hipStream_t, const Dom*, const int4*, unsigned, Partial*, const int*, int);
+  void (*scalar_ym)(int, int, dim3, hipStream_t, const Dom*, const int4*, unsigned, Partial*, const int*, int);
   void (*scalar)(int, int, int, dim3, hipStream_t, const Dom*, const int4*, unsigned, Partial*);
   void (*flow)(int, dim3, hipStream_t, const Dom*, const int4*, unsigned);
   void (*diag_tiles)(int, dim3, hipStream_t, const Dom*, const int4*, long long, Partial*);
@@ -103,7 +109,7 @@ struct Ops {
 template <class R, class S>
 Ops make_ops() {
   return Ops{Launch<R, S>::phase, Launch<R, S>::transfer, Launch<R, S>::phase_tr, Launch<R, S>::phase_tr_rows,
-             Launch<R, S>::phase_ym, Launch<R, S>::scalar, Launch<R, S>::flow,
+             Launch<R, S>::phase_ym, Launch<R, S>::transfer_ym, Launch<R, S>::scalar_ym, Launch<R, S>::scalar, Launch<R, S>::flow,
              Launch<R, S>::diag_tiles, Launch<R, S>::tips, Launch<R, S>::init, Launch<R, S>::read,
              Launch<R, S>::write};
 }
@@ -345,17 +351,25 @@ static void launch_step(lbm_ctx* c, hipStream_t st, unsigned k) {
       if (fused) {
         c->ops.phase_tr(kTYs[tf], dim3(g.ts[tf].n), st, c->d_dom, g.ts[tf].d, k, c->d_part);
       } else {
-        if (use_march(c))
+        if (use_march(c)) {
           c->ops.phase_ym(c->qs, dim3(g.runs.n), st, c->d_dom, g.runs.d, k);
-        else
+          c->ops.transfer_ym(dim3(g.runs.n), st, c->d_dom, g.runs.d, k, c->d_part, c->d_slot0[ti], TY);
+        } else {
           c->ops.phase(TY, c->qs, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k);
-        c->ops.transfer(TY, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k, c->d_part);
+          c->ops.transfer(TY, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k, c->d_part);
+        }
       }
     }
+  const bool march = use_march(c);
+  // (the U transport stays tiled: marching it measured slower on the
+  // batched ensemble, 248 against 236 us per launch)
   for (auto& g : c->g_U)
     if (k % g.N == 0) c->ops.scalar(0, TY, c->qs, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k, c->d_part);
   for (auto& g : c->g_T)
-    if (k % g.N == 0) c->ops.scalar(1, TY, c->qs, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k, c->d_part);
+    if (k % g.N == 0) {
+      if (march) c->ops.scalar_ym(1, c->qs, dim3(g.runs.n), st, c->d_dom, g.runs.d, k, c->d_part, c->d_slot0[ti], TY);
+      else c->ops.scalar(1, TY, c->qs, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k, c->d_part);
+    }
   for (auto& g : c->g_F)
     if (k % g.N == 0) c->ops.flow(TY, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k);
 }
@@ -935,9 +949,15 @@ lbm_status lbm_kernel_times(lbm_ctx* c, int32_t reps, double* ms_out, double* pe
           c->ops.phase_ym(c->qs, dim3(g.runs.n), c->stream, c->d_dom, g.runs.d, k);
         else if (kind == 0 && !fused)
           c->ops.phase(TY, c->qs, grid, c->stream, c->d_dom, g.ts[ti].d, k);
-        if (kind == 1) c->ops.transfer(TY, grid, c->stream, c->d_dom, g.ts[ti].d, k, c->d_part);
-        if (kind == 2) c->ops.scalar(0, TY, c->qs, grid, c->stream, c->d_dom, g.ts[ti].d, k, c->d_part);
-        if (kind == 3) c->ops.scalar(1, TY, c->qs, grid, c->stream, c->d_dom, g.ts[ti].d, k, c->d_part);
+        if (kind == 1 && use_march(c))
+          c->ops.transfer_ym(dim3(g.runs.n), c->stream, c->d_dom, g.runs.d, k, c->d_part, c->d_slot0[ti], TY);
+        else if (kind == 1)
+          c->ops.transfer(TY, grid, c->stream, c->d_dom, g.ts[ti].d, k, c->d_part);
+        if (kind == 3 && use_march(c))
+          c->ops.scalar_ym(kind - 2, c->qs, dim3(g.runs.n), c->stream, c->d_dom, g.runs.d, k, c->d_part,
+                           c->d_slot0[ti], TY);
+        else if (kind == 2 || kind == 3)
+          c->ops.scalar(kind - 2, TY, c->qs, grid, c->stream, c->d_dom, g.ts[ti].d, k, c->d_part);
         if (kind == 4) c->ops.flow(TY, grid, c->stream, c->d_dom, g.ts[ti].d, k);
       };
       launch();

@@ -207,8 +207,8 @@ class Simulation:
     def configure(self, tile_rows=0, use_graph=True, fuse_transfer=False, march=None):
         """Tile height (0 = autotune), HIP-graph replay of whole cycles,
         whether the 2D transfer runs inside the phase kernel, and whether
-        the 2D phase kernel marches up 64-wide columns (True), tiles (False)
-        or chooses by size (None)."""
+        the 2D phase, transfer and T-transport kernels march up 64-wide
+        columns (True), tile (False) or choose by size (None)."""
         flags = (1 if use_graph else 0) | (2 if fuse_transfer else 0)
         flags |= {None: 0, True: 4, False: 8}[march]
         _check(self.lib, self.ctx, self.lib.lbm_configure(self.ctx, int(tile_rows), flags))

@@ -173,15 +173,19 @@ def test_tile_shapes_graph_and_fusion_are_bitwise_identical(storage):
 
 
 @pytest.mark.parametrize("q", [5, 9])
-def test_marching_phase_kernel_fp64(q):
-    """The marching phase kernel on the walled solutal case (70 rows: a
-    second run of 6 rows, 150 = 2 x 64 + 22 columns) and the D2Q9 lattice:
-    FP64 parity with the oracle."""
-    wl = L.reduced(L.solutal_512(), 150, 70)
+def test_marching_kernels_fp64(q):
+    """The marching phase, transfer and T-transport kernels on the 2D
+    directional case (cold bottom, walls, Le = 10) on 150 x 70 (a second
+    run of 6 rows, 150 = 2 x 64 + 22 columns), in D2Q5 and D2Q9: FP64
+    parity with the oracle, and the same S_phi and J_U diagnostics as the
+    tiled kernels."""
+    wl = L.directional_2d(Le=10, coupling="instant", nx=150, ny=70)
     wl["domains"][0]["q_scalar"] = q
-    names = ("phi", "U", "f_phi", "jU")
-    _say(f"case marching phase kernel D2Q{q} fp64 150x70 120 steps")
+    names = ("phi", "U", "T", "f_phi", "jU", "jT")
+    _say(f"case marching kernels D2Q{q} fp64 150x70 120 steps")
     (got,), diag = _gpu(wl, 120, names=names, tile_rows=8, march=True)
+    _, diag_t = _gpu(wl, 120, names=names, tile_rows=8, march=False)
+    assert diag[0]["S_phi"] == diag_t[0]["S_phi"] and diag[0]["J_U"] == diag_t[0]["J_U"]
     dom = oracle.run(wl["domains"][0], 120)
     _compare(f"marching D2Q{q}", got, _oracle_fields(dom, names), TOL64)
 
