@@ -45,6 +45,7 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2609_25670_amd", "csrc", f)
                   for f in ("lbm_kernels.hip", "lbm_dev.h")]
 KERNEL_NAMES = {"phase": "k_phase", "phase_tr": "k_phase_tr", "transfer": "k_transfer", "U": "k_scalar<..., 0>",
                 "T": "k_scalar<..., 1>", "flow": "k_flow"}
+KERNEL_NAMES_MARCH = dict(KERNEL_NAMES, phase="k_phase_ym", transfer="k_transfer_ym", T="k_scalar_ym<..., 1>")
 KERNEL_NAMES_3D = {"phase": "k3z_phase", "transfer": "k3z_transfer", "U": "k3z_scalar<..., 0>",
                    "T": "k3z_scalar<..., 1>", "flow": "k3z_flow"}
 
@@ -98,10 +99,10 @@ def cycle_of(wl: dict) -> int:
     return L
 
 
-def traffic_from_profiles(workload: str, kind: str, sha: str, three_d: bool = False):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, if
-    it was taken on the current kernel source; else None."""
-    name = KERNEL_NAMES[kind].split("<")[0] if not three_d else KERNEL_NAMES_3D[kind].split(" ")[0].split("<")[0]
+def traffic_from_profiles(workload: str, kernel: str, sha: str):
+    """HBM bytes per launch of a kernel from the committed rocprofv3 counter
+    summary, if it was taken on the current kernel source; else None."""
+    name = kernel.split("<")[0]
     path = os.path.join(ROOT, "profiles", f"counters_{name}_{workload}.json")
     if not os.path.exists(path):
         return None
@@ -164,6 +165,7 @@ def measure(sim, wl: dict, storage: str, steps: int, warmup: int) -> dict:
     mlups = sites * steps * cyc / wall / 1e6
 
     # per-kernel launch times (HIP events on the library's stream)
+    marching = sim.marching
     kt = sim.kernel_times(reps=200)
     sim.close()
     d0 = wl["domains"][0]
@@ -177,8 +179,10 @@ def measure(sim, wl: dict, storage: str, steps: int, warmup: int) -> dict:
                               alg_GBs=nbytes / (ms * 1e-3) / 1e9 if ms > 0 else None,
                               share_ms_per_base_step=ms * per)
     dom_kind = max(per_kind, key=lambda k: per_kind[k]["share_ms_per_base_step"])
+    d0 = wl["domains"][0]
+    names = KERNEL_NAMES_3D if d0["dim"] == 3 else KERNEL_NAMES_MARCH if marching else KERNEL_NAMES
     return dict(mlups=mlups, wall=wall, event_ms=ev0.elapsed_time(ev1), finite=finite, kernels=per_kind,
-                dominant=dom_kind)
+                dominant=dom_kind, names=names)
 
 
 def main() -> int:
@@ -212,7 +216,15 @@ def main() -> int:
         for _ in range(3):
             b.copy_(a)
         torch.cuda.synchronize()
-        print(json.dumps(dict(copy_probe_bytes=n * 4, reps=3)), flush=True)
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(10):
+            b.copy_(a)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / 10
+        print(json.dumps(dict(copy_probe_bytes=n * 4, reps=13, ms_per_copy=ms,
+                              read_plus_write_GBs=2 * n * 4 / (ms * 1e-3) / 1e9)), flush=True)
         return 0
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); "
@@ -244,10 +256,10 @@ def main() -> int:
     mlups, wall, ev_ms, finite = m["mlups"], m["wall"], m["event_ms"], m["finite"]
     per_kind, dom_kind = m["kernels"], m["dominant"]
     d0 = wl["domains"][0]
-    knames = KERNEL_NAMES_3D if d0["dim"] == 3 else KERNEL_NAMES
+    knames = m["names"]
     dk = per_kind[dom_kind]
     sha = kernel_source_sha()
-    traffic = traffic_from_profiles(args.workload, dom_kind, sha, d0["dim"] == 3)
+    traffic = traffic_from_profiles(args.workload, knames[dom_kind], sha)
     achieved = dk["alg_GBs"]
     bytes_per_base_step = sum(algorithmic_bytes(k, d0, storage) * v["launches_per_base_step"]
                               for k, v in per_kind.items())   # per site
@@ -310,12 +322,12 @@ def main() -> int:
             "base_steps_per_step": cycle_of(hw),
             "roofline": {
                 "bound": "hbm",
-                "kernel": KERNEL_NAMES[hm["dominant"]],
+                "kernel": hm["names"][hm["dominant"]],
                 "achieved": round(hk["alg_GBs"], 1),
                 "peak": HBM_PEAK_GBS,
                 "unit": "GB/s",
                 "frac": round(hk["alg_GBs"] / HBM_PEAK_GBS, 4),
-                "traffic": traffic_from_profiles(HBM_WORKLOAD, hm["dominant"], sha),
+                "traffic": traffic_from_profiles(HBM_WORKLOAD, hm["names"][hm["dominant"]], sha),
             },
             "kernels": {k: {kk: (round(vv, 6) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                         for k, v in hm["kernels"].items()},

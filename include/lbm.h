@@ -232,6 +232,11 @@ lbm_status lbm_kernel_times(lbm_ctx* ctx, int32_t reps, double* ms_out, double* 
 /* Base steps completed since the last lbm_init_seeds. */
 int64_t lbm_steps_done(const lbm_ctx* ctx);
 
+/* 1 when the context's 2D phase, transfer and T-transport kernels march up
+ * column runs (see lbm_configure), 0 when they tile or the context is 3D,
+ * -1 for ctx NULL. */
+int32_t lbm_marching(const lbm_ctx* ctx);
+
 /* Text of the last error of ctx (or of the last failed lbm_create when ctx
  * is NULL).  Owned by the library. */
 const char* lbm_last_error(const lbm_ctx* ctx);

@@ -34,8 +34,8 @@ FIELD_BITS = [("phi", F_PHI, 1), ("U", F_U, 1), ("T", F_T, 1), ("rho", F_RHO, 1)
 
 EXPORTS = ["lbm_workspace_bytes", "lbm_create", "lbm_init_seeds", "lbm_init_front", "lbm_step_multirate",
            "lbm_read_fields",
-           "lbm_write_fields", "lbm_configure", "lbm_kernel_times", "lbm_steps_done", "lbm_last_error",
-           "lbm_destroy"]
+           "lbm_write_fields", "lbm_configure", "lbm_kernel_times", "lbm_steps_done", "lbm_marching",
+           "lbm_last_error", "lbm_destroy"]
 KERNEL_KINDS = ("phase", "transfer", "U", "T", "flow")
 
 
@@ -110,6 +110,8 @@ def load() -> ctypes.CDLL:
     lib.lbm_kernel_times.argtypes = [ctypes.c_void_p, ctypes.c_int32, P(ctypes.c_double), P(ctypes.c_double)]
     lib.lbm_steps_done.restype = ctypes.c_int64
     lib.lbm_steps_done.argtypes = [ctypes.c_void_p]
+    lib.lbm_marching.restype = ctypes.c_int32
+    lib.lbm_marching.argtypes = [ctypes.c_void_p]
     lib.lbm_last_error.restype = ctypes.c_char_p
     lib.lbm_last_error.argtypes = [ctypes.c_void_p]
     lib.lbm_destroy.restype = None
@@ -241,6 +243,11 @@ class Simulation:
     @property
     def steps_done(self) -> int:
         return int(self.lib.lbm_steps_done(self.ctx))
+
+    @property
+    def marching(self) -> bool:
+        """Whether the 2D phase, transfer and T-transport kernels march."""
+        return self.lib.lbm_marching(self.ctx) == 1
 
     def _layout(self, names, domain=0):
         d = self.domains[domain]
