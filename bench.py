@@ -78,8 +78,9 @@ def algorithmic_bytes(kind: str, d: dict, storage: str) -> int:
     if kind == "phase_tr":   # phase with its transfer in one kernel: the phase
         # kernel's bytes plus the new U and T planes (or the pending planes)
         return 2 * (qs - 1) * s + (2 + U + T) * r + (2 if acc else 1) * (U + T) * r
-    if kind == "transfer":   # phi^q, phi^{q+1}; U in, U out (or pending), T in, T out
-        return (2 + 2 * U + 2 * T) * r
+    if kind == "transfer":   # phi^q, phi^{q+1}; U in, U out (or pending), T in, T out (not a pulled T)
+        Tl = T if d.get("T_mode", "transport") != "pulled" else 0
+        return (2 + 2 * U + 2 * Tl) * r
     if kind == "U":          # U, j_U, phi*, [u]; U, j_U out; [pending]
         return (3 + dim * F + 2 * acc) * r + 2 * dim * s
     if kind == "T":          # as U; phi* only with phi-dependent properties
