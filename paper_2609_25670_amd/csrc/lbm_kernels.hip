@@ -1053,6 +1053,229 @@ __global__ __launch_bounds__(NTHR) void k_transfer_ym(const Dom* __restrict__ do
   }
 }
 
+// =================================================================== deferred transfer + phase
+// The transfer of phase step k - 1 fused into the phase kernel of step k,
+// for steps with no transport in between.  The transfer needs phi^{k-1} two
+// sites away (J at a site takes the gradient of phi^{k-1}, the divergence
+// at a collision cell the J of its neighbours), so the block reads phi^{k-1}
+// on the tile plus three rings, computes J on the tile plus two rings and
+// U*, T* = the transferred U, T on the tile plus one ring, where the phase
+// collision uses them, and writes them on the tile.  Only loads and the
+// cheap transfer arithmetic are repeated on the rings, no collisions, and
+// the transfer's own launch disappears.  D2Q5, instantaneous coupling.
+// Bitwise identical to the two separate kernels.
+template <class R, class S, int TY>
+__global__ __launch_bounds__(NTHR) void k_dtr_phase(const Dom* __restrict__ doms, const int4* __restrict__ tiles,
+                                                     unsigned k, Partial* __restrict__ part) {
+  constexpr int W3 = TX + 6, H3 = TY + 6;   // phi^{k-1} box
+  constexpr int W2 = TX + 4, H2 = TY + 4;   // J
+  constexpr int W1 = TX + 2, H1 = TY + 2;   // transferred U, T and the collisions
+  constexpr int N3 = W3 * H3, N2 = W2 * H2, N1 = W1 * H1;
+  constexpr int C2 = (N2 + NTHR - 1) / NTHR, C1 = (N1 + NTHR - 1) / NTHR;
+  constexpr int RPT = TY / BY;
+  __shared__ R sq[N3];
+  __shared__ R sJx[N2], sJy[N2];
+  __shared__ R cP[N1], cKx[N1], cKy[N1];
+  __shared__ R red[NTHR / 64];
+
+  const int4 t = tiles[blockIdx.x];
+  if (t.x < 0) return;
+  const Dom& D = doms[t.x];
+  if (k % D.N_phi) return;
+  const int nx = D.nx, ny = D.ny;
+  const int px = D.px, pl = (int)D.plane;
+  const int x0 = t.y, y0 = t.z;
+  const int w = min(TX, nx - x0), h = min(TY, ny - y0);
+  const int bcx = D.bc[0], bcy = D.bc[1];
+  const bool wx = bcx != BC_PER, wy = bcy != BC_PER;
+  const unsigned kt = k - 1;   // the transfer's step
+  // transfer of step kt: phi^{kt-1} -> phi^{kt}; U, T of before -> after
+  GLOBAL const R* __restrict__ phi_old = gp<const R>(D.phi[par(n_phi(D, kt - 1))]);
+  const int ib = par(n_phi(D, kt)), ob = ib ^ 1;
+  GLOBAL const R* __restrict__ phi_in = gp<const R>(D.phi[ib]);   // phi^{kt}: the transfer's new, the phase's input
+  GLOBAL R* __restrict__ phi_out = gp<R>(D.phi[ob]);
+  GLOBAL const S* __restrict__ s_in = gp<const S>(D.sphi[ib]);
+  GLOBAL S* __restrict__ s_out = gp<S>(D.sphi[ob]);
+  const unsigned nU = (kt - 1) / D.N_phi + (kt - 1) / D.N_U;
+  GLOBAL const R* __restrict__ Uin = D.has_U ? gp<const R>(D.U[par(nU)]) : nullptr;
+  GLOBAL R* __restrict__ Uout = D.has_U ? gp<R>(D.U[par(nU + 1)]) : nullptr;
+  GLOBAL const R* __restrict__ Tin = D.has_T ? gp<const R>(D.T[par(n_T(D, kt - 1))]) : nullptr;
+  GLOBAL R* __restrict__ Tout = D.has_T ? gp<R>(D.T[par(n_T(D, kt - 1) + 1)]) : nullptr;
+  const PhaseConst<R> c = phase_const<R>(D);
+  const R Uref = kc<R>(D, K_U0), Tref = kc<R>(D, K_T0);
+  const R omk = kc<R>(D, K_OMK), opk = kc<R>(D, K_OPK);
+  const R cJ = kc<R>(D, K_CJ), cT = kc<R>(D, K_CT);
+  const R rcS = kc<R>(D, K_RCS), rcL = kc<R>(D, K_RCL);
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
+  // raw coordinate -> position of the node whose values it takes in a
+  // region of ring r (walls clamp, periodic axes keep the raw position)
+  auto posx = [&](int g, int r) { return (wx ? min(max(g, 0), nx - 1) : g) - (x0 - r); };
+  auto posy = [&](int g, int r) { return (wy ? min(max(g, 0), ny - 1) : g) - (y0 - r); };
+
+  // ---- loads: phi^{kt} box; J inputs on ring 2; transfer and collision inputs on ring 1
+  for (int i = tid; i < N3; i += NTHR)
+    sq[i] = ldo(phi_in, (unsigned)(ghost(y0 - 3 + i / W3, ny, bcy) * px + ghost(x0 - 3 + i % W3, nx, bcx)));
+  R jpo[C2], jU[C2];
+#pragma unroll
+  for (int j = 0; j < C2; ++j) {
+    const int i = tid + j * NTHR;
+    if (i >= N2) continue;
+    const unsigned o = (unsigned)(ghost(y0 - 2 + i / W2, ny, bcy) * px + ghost(x0 - 2 + i % W2, nx, bcx));
+    jpo[j] = ldo(phi_old, o);
+    if (Uin) jU[j] = ldo(Uin, o);
+  }
+  R sv[C1][4], cpo[C1], cU[C1], cT_[C1];
+  bool live[C1];
+#pragma unroll
+  for (int j = 0; j < C1; ++j) {
+    const int i = tid + j * NTHR;
+    live[j] = false;
+    if (i >= N1) continue;
+    const int rx = resolve(x0 - 1 + i % W1, nx, bcx), ry = resolve(y0 - 1 + i / W1, ny, bcy);
+    if (rx < 0 || ry < 0) continue;   // beyond a wall: never pulled from
+    live[j] = true;
+    const unsigned o = (unsigned)(ry * px + rx);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sv[j][q] = ldo(plane(s_in, q * pl), o);
+    cpo[j] = ldo(phi_old, o);
+    if (Uin) cU[j] = ldo(Uin, o);
+    if (Tin) cT_[j] = ldo(Tin, o);
+  }
+  __syncthreads();
+
+  // ---- J of step kt on ring 2 (beyond a wall: the clamped node's J with
+  // its normal component negated), as the transfer kernel computes it
+  if (Uin) {
+#pragma unroll
+    for (int j = 0; j < C2; ++j) {
+      const int i = tid + j * NTHR;
+      if (i >= N2) continue;
+      const int gx = x0 - 2 + i % W2, gy = y0 - 2 + i / W2;
+      const bool mx = wx && (gx < 0 || gx >= nx), my = wy && (gy < 0 || gy >= ny);
+      const R* b = &sq[(posy(gy, 3)) * W3 + posx(gx, 3)];
+      R gxv, gyv;
+      iso_grad(b, W3, gxv, gyv);
+      const R gg = gxv * gxv + gyv * gyv;
+      R Jx = R(0), Jy = R(0);
+      if (gg >= R(GRAD_EPS2)) {
+        const R ig = rsq(gg);
+        const R a = cJ * (R(1) + omk * (jU[j] + Uref)) * (b[0] - jpo[j]) * ig;
+        Jx = -a * gxv;
+        Jy = -a * gyv;
+      }
+      sJx[i] = mx ? -Jx : Jx;
+      sJy[i] = my ? -Jy : Jy;
+    }
+  }
+  __syncthreads();
+
+  // ---- transferred U and T on ring 1, then the phase collision there
+  R amax = R(0), Aown[C1];
+#pragma unroll
+  for (int j = 0; j < C1; ++j) {
+    if (!live[j]) continue;
+    const int i = tid + j * NTHR;
+    const int lx = i % W1, ly = i / W1;
+    const bool own = lx >= 1 && ly >= 1 && lx <= w && ly <= h;
+    const unsigned o = (unsigned)((y0 - 1 + ly) * px + (x0 - 1 + lx));   // a live cell is inside the domain
+    const R* b = &sq[(ly + 2) * W3 + lx + 2];
+    const R pn = b[0];
+    const R dphi = pn - cpo[j];
+    R Ust = R(0), Tst = R(0);
+    if (Uin) {
+      const R* jx = &sJx[(ly + 1) * W2 + lx + 1];
+      const R* jy = &sJy[(ly + 1) * W2 + lx + 1];
+      const R div = (jx[1] - jx[-1]) * R(1.0 / 3.0) +
+                    (jx[W2 + 1] - jx[W2 - 1] - jx[-W2 - 1] + jx[-W2 + 1]) * R(1.0 / 12.0) +
+                    (jy[W2] - jy[-W2]) * R(1.0 / 3.0) +
+                    (jy[W2 + 1] + jy[W2 - 1] - jy[-W2 - 1] - jy[-W2 + 1]) * R(1.0 / 12.0);
+      const R dU = ((R(1) + omk * (cU[j] + Uref)) * dphi - R(2) * div) * rcp(opk - omk * pn);
+      Ust = cU[j] + dU;
+      if (own) {
+        amax = fmax(amax, fabs(dU));
+        sto(Uout, o, Ust);
+      }
+    }
+    if (Tin) {
+      const R rc = (R(1) + pn) * R(0.5) * rcS + (R(1) - pn) * R(0.5) * rcL;
+      const R dT = cT * dphi * rcp(R(2) * rc);
+      Tst = cT_[j] + dT;
+      if (own) sto(Tout, o, Tst);
+    }
+    // the phase collision of step k with the transferred U and T
+    R gxv, gyv;
+    iso_grad(b, W3, gxv, gyv);
+    const R Uv = Uin ? Ust + Uref : R(0);
+    const R Tv = Tin ? Tst + Tref : c.theta_off;
+    R dP, Kx, Ky, A;
+    phase_collide(c, pn, gxv, gyv, sv[j][0] - sv[j][2], sv[j][1] - sv[j][3], Uv, Tv, dP, Kx, Ky, A);
+    cP[i] = dP;
+    cKx[i] = Kx;
+    cKy[i] = Ky;
+    Aown[j] = A;
+  }
+  __syncthreads();
+
+  // ---- anisotropic pull streaming (Eq. 26) of the tile, in deviations
+  const bool edge = (wx && (x0 == 0 || x0 + w >= nx)) || (wy && (y0 == 0 || y0 + h >= ny));
+  auto stream = [&](auto edge_c) {
+    constexpr bool EDGE = decltype(edge_c)::value;
+#pragma unroll
+    for (int j = 0; j < C1; ++j) {
+      if (!live[j]) continue;
+      const int i = tid + j * NTHR;
+      const int lx = i % W1, ly = i / W1;
+      if (!(lx >= 1 && ly >= 1 && lx <= w && ly <= h)) continue;
+      const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
+      const R A = Aown[j], iA = rcp(A), oA = R(1) - A;
+      const int bq = (ly + 2) * W3 + lx + 2;
+      const R phy = sq[bq];
+      const R dPo = cP[i];
+      R s0 = R(0);
+#pragma unroll
+      for (int q = 0; q < 4; ++q) s0 -= sv[j][q];
+      R dn[5];
+      dn[0] = (dPo * R(1.0 / 3.0) - oA * s0) * iA;
+#pragma unroll
+      for (int q = 1; q < 5; ++q) {
+        const int ex = EX5(q), ey = EY5(q);
+        const bool wall = EDGE && ((wx && ((ex > 0 && gx == 0) || (ex < 0 && gx == nx - 1))) ||
+                                   (wy && ((ey > 0 && gy == 0) || (ey < 0 && gy == ny - 1))));
+        R dpost;
+        if (wall) {
+          dpost = dPo * R(1.0 / 6.0) - R(0.5) * (R(ex) * cKx[i] + R(ey) * cKy[i]);
+        } else {
+          const int si = i - ey * W1 - ex;
+          const R dphi = sq[bq - ey * W3 - ex] - phy;
+          dpost = (dphi + cP[si]) * R(1.0 / 6.0) + R(0.5) * (R(ex) * cKx[si] + R(ey) * cKy[si]);
+        }
+        dn[q] = (dpost - oA * sv[j][q - 1]) * iA;
+      }
+      R dphin = dn[0];
+#pragma unroll
+      for (int q = 1; q < 5; ++q) dphin += dn[q];
+      const unsigned o = (unsigned)(gy * px + gx);
+      sto(phi_out, o, phy + dphin);
+#pragma unroll
+      for (int q = 1; q < 5; ++q) sto(plane(s_out, (q - 1) * pl), o, dn[q] - dphin * R(1.0 / 6.0));
+    }
+  };
+  if (edge) stream(std::true_type{});
+  else stream(std::false_type{});
+
+  if (part && Uin) {
+    for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_down(amax, off, 64));
+    if (tx == 0) red[ty] = amax;
+    __syncthreads();
+    if (tid == 0) {
+      R m = red[0];
+      for (int wv = 1; wv < NTHR / 64; ++wv) m = fmax(m, red[wv]);
+      part[t.w].S_phi = double(m);
+      part[t.w].J_U = double(m);
+    }
+  }
+}
+
 // =================================================================== fused phase + transfer
 // One phase update and its transfer (Eq. 26, then Eq. 36-39) in a single
 // pass over a 64 x TY tile.  The transfer at a site needs phi^{q+1} two
@@ -3731,6 +3954,14 @@ struct Launch {
     else if (TY == 8) k_phase<R, S, 8, 5><<<g, b, 0, st>>>(d, t, k);
     else if (TY == 16) k_phase<R, S, 16, 5><<<g, b, 0, st>>>(d, t, k);
     else k_phase<R, S, 32, 5><<<g, b, 0, st>>>(d, t, k);
+  }
+  // transfer of step k - 1 fused into the phase kernel of step k (D2Q5)
+  static void dtr_phase(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, unsigned k, Partial* p) {
+    const dim3 b(TX, BY);
+    if (TY == 4) k_dtr_phase<R, S, 4><<<g, b, 0, st>>>(d, t, k, p);
+    else if (TY == 8) k_dtr_phase<R, S, 8><<<g, b, 0, st>>>(d, t, k, p);
+    else if (TY == 16) k_dtr_phase<R, S, 16><<<g, b, 0, st>>>(d, t, k, p);
+    else k_dtr_phase<R, S, 32><<<g, b, 0, st>>>(d, t, k, p);
   }
   // y-marching scalar transport over a list of column runs
   static void scalar_ym(int field, int Q, dim3 g, hipStream_t st, const Dom* d, const int4* runs, unsigned k,

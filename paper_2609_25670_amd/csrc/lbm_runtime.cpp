@@ -31,6 +31,7 @@ struct Launch {
   static int phase_tr_rows(int TY);
   static void phase_tr(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, unsigned k, Partial* p);
   static void phase_ym(int Q, dim3 g, hipStream_t st, const Dom* d, const int4* runs, unsigned k);
+  static void dtr_phase(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, unsigned k, Partial* p);
   static void transfer_ym(dim3 g, hipStream_t st, const Dom* d, const int4* runs, unsigned k, Partial* p,
                           const int* slot0, int TY);
   static void scalar_ym(int field, int Q, dim3 g, hipStream_t st, const Dom* d, const int4* runs, unsigned k,
@@ -95,6 +96,7 @@ struct Ops {
   void (*phase_tr)(int, dim3, hipStream_t, const Dom*, const int4*, unsigned, Partial*);
   int (*phase_tr_rows)(int);
   void (*phase_ym)(int, dim3, hipStream_t, const Dom*, const int4*, unsigned);
+  void (*dtr_phase)(int, dim3, hipStream_t, const Dom*, const int4*, unsigned, Partial*);
   void (*transfer_ym)(dim3, hipStream_t, const Dom*, const int4*, unsigned, Partial*, const int*, int);
   void (*scalar_ym)(int, int, dim3, hipStream_t, const Dom*, const int4*, unsigned, Partial*, const int*, int);
   void (*scalar)(int, int, int, dim3, hipStream_t, const Dom*, const int4*, unsigned, Partial*);
@@ -109,7 +111,7 @@ struct Ops {
 template <class R, class S>
 Ops make_ops() {
   return Ops{Launch<R, S>::phase, Launch<R, S>::transfer, Launch<R, S>::phase_tr, Launch<R, S>::phase_tr_rows,
-             Launch<R, S>::phase_ym, Launch<R, S>::transfer_ym, Launch<R, S>::scalar_ym, Launch<R, S>::scalar, Launch<R, S>::flow,
+             Launch<R, S>::phase_ym, Launch<R, S>::dtr_phase, Launch<R, S>::transfer_ym, Launch<R, S>::scalar_ym, Launch<R, S>::scalar, Launch<R, S>::flow,
              Launch<R, S>::diag_tiles, Launch<R, S>::tips, Launch<R, S>::init, Launch<R, S>::read,
              Launch<R, S>::write};
 }
@@ -176,6 +178,9 @@ struct lbm_ctx {
   bool fuse = false;      // phase + transfer in one kernel (2D) when every domain allows it
   bool fusable = false;   // every domain at least 8 x 8 (the fused kernel's rings wrap once at most), D2Q5
   int march = 0;          // 2D marching phase kernel: 0 by size, 1 always, -1 never
+  bool defer = true;      // defer a phase step's transfer into the next phase kernel where allowed
+  bool deferrable = false;// D2Q5, one phase group with N_phi = 1, instantaneous coupling, domains >= 8 x 8
+  bool pending = false;   // the last launched step's transfer is deferred
   bool march_big = false; // the phase groups hold enough column runs to fill the chip
   bool marchable = false; // every domain 2D and at least 16 x 16 (the marching windows wrap once at most)
   int qs = 5;             // scalar lattice of the (2D) context: 5 or 9
@@ -338,7 +343,18 @@ static bool use_march(const lbm_ctx* c) {
   return c->marchable && (c->march > 0 || (c->march == 0 && c->march_big));
 }
 
-static void launch_step(lbm_ctx* c, hipStream_t st, unsigned k) {
+// Whether the transfer of phase step k (within the cycle) waits for the
+// phase kernel of step k + 1: no transport runs at step k, k is not the
+// cycle's last step, and the context allows it.
+static bool defers(const lbm_ctx* c, unsigned k) {
+  if (!(c->defer && c->deferrable && !c->fuse && !use_march(c)) || (long long)k >= c->cycle) return false;
+  for (auto* gs : {&c->g_U, &c->g_T, &c->g_F})
+    for (auto& g : *gs)
+      if (k % g.N == 0) return false;
+  return true;
+}
+
+static void launch_step(lbm_ctx* c, hipStream_t st, unsigned k, bool last = false) {
   if (c->dim == 3) {
     c->ops3.step(c->H[0], st, c->d_dom, k, c->d_part);
     return;
@@ -355,8 +371,12 @@ static void launch_step(lbm_ctx* c, hipStream_t st, unsigned k) {
           c->ops.phase_ym(c->qs, dim3(g.runs.n), st, c->d_dom, g.runs.d, k);
           c->ops.transfer_ym(dim3(g.runs.n), st, c->d_dom, g.runs.d, k, c->d_part, c->d_slot0[ti], TY);
         } else {
-          c->ops.phase(TY, c->qs, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k);
-          c->ops.transfer(TY, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k, c->d_part);
+          if (c->pending)   // the previous step's transfer runs inside this phase kernel
+            c->ops.dtr_phase(TY, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k, c->d_part);
+          else
+            c->ops.phase(TY, c->qs, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k);
+          c->pending = !last && defers(c, k);
+          if (!c->pending) c->ops.transfer(TY, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k, c->d_part);
         }
       }
     }
@@ -675,6 +695,9 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
   c->qs = p[0].q_scalar;
   c->fusable = true;
   for (int i = 0; i < n; ++i) c->fusable &= p[i].dim == 2 && p[i].q_scalar == 5 && p[i].nx >= 8 && p[i].ny >= 8;
+  c->deferrable = p[0].dim == 2 && p[0].q_scalar == 5;
+  for (int i = 0; i < n; ++i)
+    c->deferrable &= p[i].N_phi == 1 && p[i].coupling == LBM_COUPLE_INSTANT && p[i].nx >= 8 && p[i].ny >= 8;
   c->marchable = true;
   for (int i = 0; i < n; ++i) c->marchable &= p[i].dim == 2 && p[i].nx >= 16 && p[i].ny >= 16;
   {
@@ -886,12 +909,13 @@ lbm_status lbm_configure(lbm_ctx* c, int32_t tile_rows, int32_t flags) {
     c->autotune = false;
     c->tuned = true;
   }
-  if (flags & ~15) return fail(c, LBM_EINVAL, "unknown configure flags");
+  if (flags & ~31) return fail(c, LBM_EINVAL, "unknown configure flags");
   if ((flags & LBM_CFG_MARCH) && (flags & LBM_CFG_TILES))
     return fail(c, LBM_EINVAL, "LBM_CFG_MARCH and LBM_CFG_TILES exclude each other");
   c->use_graph = (flags & LBM_CFG_GRAPH) != 0;
   c->fuse = (flags & LBM_CFG_FUSE_TRANSFER) != 0;
   c->march = (flags & LBM_CFG_MARCH) ? 1 : (flags & LBM_CFG_TILES) ? -1 : 0;
+  c->defer = (flags & LBM_CFG_NO_DEFER) == 0;
   if (c->gexec) {   // the captured cycle follows the kernel choice
     HIPCHK(c, hipStreamSynchronize(c->stream));
     (void)hipGraphExecDestroy(c->gexec);
@@ -975,6 +999,32 @@ lbm_status lbm_kernel_times(lbm_ctx* c, int32_t reps, double* ms_out, double* pe
     }
     ms_out[kind] = all;
     if (per_step) per_step[kind] = weighted / all;
+  }
+  // deferred transfers: the phase kernel with the previous step's transfer
+  // runs instead of the plain one on the steps after a deferral
+  ms_out[5] = -1.0;
+  if (per_step) per_step[5] = 0.0;
+  if (c->dim == 2 && !fused) {
+    long long ndef = 0;
+    for (long long kk = 1; kk < c->cycle; ++kk) ndef += defers(c, (unsigned)kk);
+    if (ndef > 0) {
+      const double fdef = double(ndef) / double(c->cycle);
+      if (per_step) {
+        per_step[0] *= 1.0 - fdef;
+        per_step[1] *= 1.0 - fdef;
+        per_step[5] = fdef;
+      }
+      const Group& g = c->g_phi[0];
+      auto launch = [&]() { c->ops.dtr_phase(TY, dim3(g.ts[ti].n), c->stream, c->d_dom, g.ts[ti].d, 2u, c->d_part); };
+      launch();
+      HIPCHK(c, hipEventRecord(e0, c->stream));
+      for (int r = 0; r < reps; ++r) launch();
+      HIPCHK(c, hipEventRecord(e1, c->stream));
+      HIPCHK(c, hipEventSynchronize(e1));
+      float ms = 0;
+      HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+      ms_out[5] = double(ms) / reps;
+    }
   }
   HIPCHK(c, hipEventDestroy(e0));
   HIPCHK(c, hipEventDestroy(e1));
@@ -1071,7 +1121,7 @@ lbm_status lbm_step_multirate(lbm_ctx* c, int64_t n, lbm_diag* diag) {
         c->ops3.set_koff(c->stream, c->d_dom, base);
         c->koff = base;
       }
-      launch_step(c, c->stream, cycle_step(c, c->k + 1));
+      launch_step(c, c->stream, cycle_step(c, c->k + 1), left == 1);
       c->k += 1;
       left -= 1;
     }

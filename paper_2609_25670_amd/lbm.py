@@ -36,7 +36,7 @@ EXPORTS = ["lbm_workspace_bytes", "lbm_create", "lbm_init_seeds", "lbm_init_fron
            "lbm_read_fields",
            "lbm_write_fields", "lbm_configure", "lbm_kernel_times", "lbm_steps_done", "lbm_marching",
            "lbm_last_error", "lbm_destroy"]
-KERNEL_KINDS = ("phase", "transfer", "U", "T", "flow")
+KERNEL_KINDS = ("phase", "transfer", "U", "T", "flow", "phase_dtr")
 
 
 class Params(ctypes.Structure):
@@ -206,12 +206,13 @@ class Simulation:
             r = (ctypes.c_double * max(1, len(seeds)))(*[s[2] for s in seeds])
             _check(self.lib, self.ctx, self.lib.lbm_init_seeds(self.ctx, i, len(seeds), c, r))
 
-    def configure(self, tile_rows=0, use_graph=True, fuse_transfer=False, march=None):
+    def configure(self, tile_rows=0, use_graph=True, fuse_transfer=False, march=None, defer=True):
         """Tile height (0 = autotune), HIP-graph replay of whole cycles,
-        whether the 2D transfer runs inside the phase kernel, and whether
-        the 2D phase, transfer and T-transport kernels march up 64-wide
-        columns (True), tile (False) or choose by size (None)."""
-        flags = (1 if use_graph else 0) | (2 if fuse_transfer else 0)
+        whether the 2D transfer runs inside the phase kernel, whether the 2D
+        phase, transfer and T-transport kernels march up 64-wide columns
+        (True), tile (False) or choose by size (None), and whether a
+        transfer may be deferred into the next phase kernel."""
+        flags = (1 if use_graph else 0) | (2 if fuse_transfer else 0) | (0 if defer else 16)
         flags |= {None: 0, True: 4, False: 8}[march]
         _check(self.lib, self.ctx, self.lib.lbm_configure(self.ctx, int(tile_rows), flags))
 
@@ -235,8 +236,8 @@ class Simulation:
     def kernel_times(self, reps=200):
         """Per-kind average launch time (ms) and launches per base step.
         Leaves the state undefined (call ``init`` before stepping again)."""
-        ms = (ctypes.c_double * 5)()
-        per = (ctypes.c_double * 5)()
+        ms = (ctypes.c_double * 6)()
+        per = (ctypes.c_double * 6)()
         _check(self.lib, self.ctx, self.lib.lbm_kernel_times(self.ctx, int(reps), ms, per))
         return {k: (ms[i], per[i]) for i, k in enumerate(KERNEL_KINDS) if ms[i] >= 0}
 

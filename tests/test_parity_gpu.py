@@ -90,7 +90,9 @@ def test_thermal_128_full_run_fp64():
 
 
 def test_solutal_reduced_fp64_ragged_tiles():
-    """2D solutal dendrite (N_U = 4, zero-flux) on 150 x 70."""
+    """2D solutal dendrite (N_U = 4, zero-flux) on 150 x 70, with the
+    default configuration (3 of every 4 transfers deferred into the next
+    phase kernel)."""
     wl = L.reduced(L.solutal_512(), 150, 70)
     names = ("phi", "U", "f_phi", "jU")
     _say("case solutal 150x70 fp64 600 steps")
@@ -170,6 +172,35 @@ def test_tile_shapes_graph_and_fusion_are_bitwise_identical(storage):
         else:
             for n in names:
                 assert np.array_equal(got[n], ref[n]), (rows, g, fuse, march, n)
+
+
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_deferred_transfer_is_bitwise_identical(storage):
+    """The transfer of a phase step with no transport after it (3 of 4 in
+    the solutal case, N_U = 4) runs inside the next phase kernel.  Against
+    the separate kernels: the same state bit for bit and the same S_phi and
+    J_U, over tile heights, graph replay or direct launches, and calls that
+    end inside a multirate cycle (5 + 3 + 59 steps)."""
+    from paper_2609_25670_amd import simulation_for
+
+    wl = L.reduced(L.solutal_512(), 130, 75)
+    names = ("phi", "U", "f_phi", "jU")
+    ref = None
+    for rows, g, defer in [(r, g, d) for r in (4, 16) for g in (True, False) for d in (False, True)]:
+        _say(f"case deferred transfer {storage} rows={rows} graph={g} defer={defer}")
+        sim = simulation_for(wl, storage=storage)
+        sim.configure(rows, g, False, False, defer)
+        sim.step(5)
+        sim.step(3)
+        diag = sim.step(59, diag=True)[0]
+        got = sim.read(0, names)
+        sim.close()
+        if ref is None:
+            ref = (got, diag)
+        else:
+            for n in names:
+                assert np.array_equal(got[n], ref[0][n]), (rows, g, defer, n)
+            assert diag["S_phi"] == ref[1]["S_phi"] and diag["J_U"] == ref[1]["J_U"]
 
 
 @pytest.mark.parametrize("q", [5, 9])
