@@ -83,3 +83,48 @@ def test_mixed_precision_storage(case):
         sys.stdout.flush()
         assert tip_err <= 0.01, (case, st, tip_err)
         assert max(l2.values()) < L2_BAR[st], (case, st, l2)
+
+
+def test_batched_ensemble_fp16_storage():
+    """The batched form: twelve domains of the ensemble workload (every
+    Lewis number, sides 128-512, 1-4 seeds) in one context with FP16
+    population storage, against the same batch in FP64.  Per domain: tip
+    velocity of the first seed within 1 % where the tip advances at least
+    a cell over the measured window, and total-solute drift within 1e-6."""
+    from paper_2609_25670_amd import simulation_for
+
+    wl = L.ensemble_256()
+    doms = wl["domains"]
+    pick = []
+    for le in (1, 10, 100, 1000):   # three domains of every Lewis number
+        pick += [i for i, d in enumerate(doms) if d["Le"] == le][:3]
+    sub = dict(wl, domains=[doms[i] for i in pick])
+    steps, every = 3000, 100
+    res = {}
+    for st in ("f64", "f16"):
+        print(f"case batched ensemble subset ({len(pick)} domains) {st} {steps} steps", flush=True)
+        sim = simulation_for(sub, storage=st)
+        d0 = sim.step(0, diag=True)
+        hist = []
+        for _ in range(steps // every):
+            dd = sim.step(every, diag=True)
+            hist.append([(x["step"], float(np.mean(x["tip"][:4])), x["M_C"]) for x in dd])
+        sim.close()
+        res[st] = (d0, hist)
+    checked = 0
+    for j, i in enumerate(pick):
+        h64 = [h[j] for h in res["f64"][1]]
+        h16 = [h[j] for h in res["f16"][1]]
+        a = int(len(h64) * 0.8)
+        adv = h64[-1][1] - h64[a][1]
+        v64, v16 = _tip_velocity(h64), _tip_velocity(h16)
+        m64, m16 = res["f64"][0][j]["M_C"], res["f16"][0][j]["M_C"]
+        drift = abs((h16[-1][2] - m16) / m16 - (h64[-1][2] - m64) / m64)
+        err = abs(v16 - v64) / abs(v64) if v64 != 0 else float("inf")
+        print(f"  domain {i} (side {doms[i]['nx']}, Le {doms[i]['Le']}): tip advance {adv:.2f}, "
+              f"tip velocity rel err {err:.2e}, solute drift {drift:.2e}", flush=True)
+        assert drift <= 1e-6, (i, drift)
+        if adv >= 1.0:
+            assert err <= 0.01, (i, err)
+            checked += 1
+    assert checked >= 6, checked
