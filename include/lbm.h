@@ -134,7 +134,7 @@ typedef struct {
   int64_t nonfinite;       /* count of non-finite phi/U/T/rho values         */
 } lbm_diag;
 
-/* Device bytes a context needs for these domains (states, double buffers,
+/* Device bytes a context needs for these domains (states with their buffers,
  * descriptors, tile lists, reduction partials).  0 on invalid input. */
 size_t lbm_workspace_bytes(const lbm_params* p, int32_t n_domains, int32_t storage);
 

@@ -337,9 +337,10 @@ __global__ __launch_bounds__(NTHR) void k_phase(const Dom* __restrict__ doms, co
   const int x0 = t.y, y0 = t.z;
   const int w = min(TX, nx - x0), h = min(TY, ny - y0);
   const int bcx = D.bc[0], bcy = D.bc[1];
-  const int ib = par(n_phi(D, k - 1)), ob = ib ^ 1;
-  GLOBAL const R* __restrict__ phi_in = gp<const R>(D.phi[ib]);
-  GLOBAL R* __restrict__ phi_out = gp<R>(D.phi[ob]);
+  const unsigned np = n_phi(D, k - 1);
+  const int ib = par(np), ob = ib ^ 1;
+  GLOBAL const R* __restrict__ phi_in = gp<const R>(D.phi[tri(np)]);
+  GLOBAL R* __restrict__ phi_out = gp<R>(D.phi[tri(np + 1)]);
   GLOBAL const S* __restrict__ s_in = gp<const S>(D.sphi[ib]);
   GLOBAL S* __restrict__ s_out = gp<S>(D.sphi[ob]);
   // latest U and T (before this step's transfer)
@@ -557,9 +558,10 @@ __global__ __launch_bounds__(NTHR) void k_phase_ym(const Dom* __restrict__ doms,
   const long long pl = D.plane;
   const int x0 = t.y, ya = t.z, yb = t.w;
   const int w = min(TX, nx - x0);
-  const int ib = par(n_phi(D, k - 1)), ob = ib ^ 1;
-  GLOBAL const R* __restrict__ phi_in = gp<const R>(D.phi[ib]);
-  GLOBAL R* __restrict__ phi_out = gp<R>(D.phi[ob]);
+  const unsigned np = n_phi(D, k - 1);
+  const int ib = par(np), ob = ib ^ 1;
+  GLOBAL const R* __restrict__ phi_in = gp<const R>(D.phi[tri(np)]);
+  GLOBAL R* __restrict__ phi_out = gp<R>(D.phi[tri(np + 1)]);
   GLOBAL const SR* __restrict__ s_in = gp<const SR>(D.sphi[ib]);
   GLOBAL S* __restrict__ s_out = gp<S>(D.sphi[ob]);
   const unsigned nU = (D.accum ? 0u : (k - 1) / D.N_phi) + (k - 1) / D.N_U;
@@ -720,8 +722,8 @@ __global__ __launch_bounds__(NTHR) void k_transfer(const Dom* __restrict__ doms,
   const int x0 = t.y, y0 = t.z;
   const int w = min(TX, nx - x0), h = min(TY, ny - y0);
   const int bcx = D.bc[0], bcy = D.bc[1];
-  GLOBAL const R* __restrict__ phi_old = gp<const R>(D.phi[par(n_phi(D, k - 1))]);
-  GLOBAL const R* __restrict__ phi_new = gp<const R>(D.phi[par(n_phi(D, k))]);
+  GLOBAL const R* __restrict__ phi_old = gp<const R>(D.phi[tri(n_phi(D, k - 1))]);
+  GLOBAL const R* __restrict__ phi_new = gp<const R>(D.phi[tri(n_phi(D, k))]);
   const unsigned nU = (D.accum ? 0u : (k - 1) / D.N_phi) + (k - 1) / D.N_U;
   GLOBAL const R* __restrict__ Uin = D.has_U ? gp<const R>(D.U[par(nU)]) : nullptr;
   GLOBAL R* __restrict__ Uout = D.has_U ? gp<R>(D.U[par(nU + 1)]) : nullptr;
@@ -920,8 +922,8 @@ __global__ __launch_bounds__(NTHR) void k_transfer_ym(const Dom* __restrict__ do
   const int nx = D.nx, ny = D.ny, px = D.px, bcx = D.bc[0], bcy = D.bc[1];
   const int x0 = t.y, ya = t.z, yb = t.w;
   const int w = min(TX, nx - x0);
-  GLOBAL const R* __restrict__ phi_old = gp<const R>(D.phi[par(n_phi(D, k - 1))]);
-  GLOBAL const R* __restrict__ phi_new = gp<const R>(D.phi[par(n_phi(D, k))]);
+  GLOBAL const R* __restrict__ phi_old = gp<const R>(D.phi[tri(n_phi(D, k - 1))]);
+  GLOBAL const R* __restrict__ phi_new = gp<const R>(D.phi[tri(n_phi(D, k))]);
   const unsigned nU = (D.accum ? 0u : (k - 1) / D.N_phi) + (k - 1) / D.N_U;
   const bool hasU = D.has_U, hasT = D.has_T, accum = D.accum;
   GLOBAL const R* __restrict__ Uin = hasU ? gp<const R>(D.U[par(nU)]) : nullptr;
@@ -1063,7 +1065,10 @@ __global__ __launch_bounds__(NTHR) void k_transfer_ym(const Dom* __restrict__ do
 // collision uses them, and writes them on the tile.  Only loads and the
 // cheap transfer arithmetic are repeated on the rings, no collisions, and
 // the transfer's own launch disappears.  D2Q5, instantaneous coupling.
-// Bitwise identical to the two separate kernels.
+// The transfer's old phase field phi^{k-2}, read on two rings, sits in the
+// buffer that this step's output does not use (three phase buffers), so
+// neighbouring blocks never overwrite it.  Bitwise identical to the two
+// separate kernels.
 template <class R, class S, int TY>
 __global__ __launch_bounds__(NTHR) void k_dtr_phase(const Dom* __restrict__ doms, const int4* __restrict__ tiles,
                                                      unsigned k, Partial* __restrict__ part) {
@@ -1090,10 +1095,11 @@ __global__ __launch_bounds__(NTHR) void k_dtr_phase(const Dom* __restrict__ doms
   const bool wx = bcx != BC_PER, wy = bcy != BC_PER;
   const unsigned kt = k - 1;   // the transfer's step
   // transfer of step kt: phi^{kt-1} -> phi^{kt}; U, T of before -> after
-  GLOBAL const R* __restrict__ phi_old = gp<const R>(D.phi[par(n_phi(D, kt - 1))]);
-  const int ib = par(n_phi(D, kt)), ob = ib ^ 1;
-  GLOBAL const R* __restrict__ phi_in = gp<const R>(D.phi[ib]);   // phi^{kt}: the transfer's new, the phase's input
-  GLOBAL R* __restrict__ phi_out = gp<R>(D.phi[ob]);
+  GLOBAL const R* __restrict__ phi_old = gp<const R>(D.phi[tri(n_phi(D, kt - 1))]);
+  const unsigned np = n_phi(D, kt);
+  const int ib = par(np), ob = ib ^ 1;
+  GLOBAL const R* __restrict__ phi_in = gp<const R>(D.phi[tri(np)]);   // phi^{kt}: the transfer's new, the phase's input
+  GLOBAL R* __restrict__ phi_out = gp<R>(D.phi[tri(np + 1)]);
   GLOBAL const S* __restrict__ s_in = gp<const S>(D.sphi[ib]);
   GLOBAL S* __restrict__ s_out = gp<S>(D.sphi[ob]);
   const unsigned nU = (kt - 1) / D.N_phi + (kt - 1) / D.N_U;
@@ -1318,9 +1324,10 @@ __global__ __launch_bounds__(NTHR) void k_phase_tr(const Dom* __restrict__ doms,
   const int w = min(TX, nx - x0), h = min(TY, ny - y0);
   const int bcx = D.bc[0], bcy = D.bc[1];
   const bool wx = bcx != BC_PER, wy = bcy != BC_PER;
-  const int ib = par(n_phi(D, k - 1)), ob = ib ^ 1;
-  GLOBAL const R* __restrict__ phi_in = gp<const R>(D.phi[ib]);
-  GLOBAL R* __restrict__ phi_out = gp<R>(D.phi[ob]);
+  const unsigned np = n_phi(D, k - 1);
+  const int ib = par(np), ob = ib ^ 1;
+  GLOBAL const R* __restrict__ phi_in = gp<const R>(D.phi[tri(np)]);
+  GLOBAL R* __restrict__ phi_out = gp<R>(D.phi[tri(np + 1)]);
   GLOBAL const S* __restrict__ s_in = gp<const S>(D.sphi[ib]);
   GLOBAL S* __restrict__ s_out = gp<S>(D.sphi[ob]);
   const unsigned nU = (D.accum ? 0u : (k - 1) / D.N_phi) + (k - 1) / D.N_U;
@@ -1580,7 +1587,7 @@ __global__ __launch_bounds__(NTHR) void k_scalar(const Dom* __restrict__ doms, c
     jout = gp<S>(D.jT[par(n_jT(D, k))]);
     pend = gp<R>(D.PT);
   }
-  GLOBAL const R* __restrict__ phis = gp<const R>(D.phi[par(n_phi(D, k))]);
+  GLOBAL const R* __restrict__ phis = gp<const R>(D.phi[tri(n_phi(D, k))]);
   // velocity of the latest flow update (the flow of step k runs after U, T)
   GLOBAL const R* __restrict__ vel = D.has_F ? gp<const R>(D.vel[par(n_F(D, k - 1))]) : nullptr;
   const bool need_phi = FIELD == 0 || D.T_var;
@@ -1828,7 +1835,7 @@ __global__ __launch_bounds__(NTHR) void k_scalar_ym(const Dom* __restrict__ doms
     jout = gp<S>(D.jT[par(n_jT(D, k))]);
     pend = gp<R>(D.PT);
   }
-  GLOBAL const R* __restrict__ phis = gp<const R>(D.phi[par(n_phi(D, k))]);
+  GLOBAL const R* __restrict__ phis = gp<const R>(D.phi[tri(n_phi(D, k))]);
   GLOBAL const R* __restrict__ vel = D.has_F ? gp<const R>(D.vel[par(n_F(D, k - 1))]) : nullptr;
   const bool need_phi = FIELD == 0 || D.T_var;
   const bool accum = D.accum;
@@ -2095,7 +2102,7 @@ __global__ __launch_bounds__(NTHR) void k_flow(const Dom* __restrict__ doms, con
   GLOBAL const S* __restrict__ s_in = gp<const S>(D.sF[par(n_F(D, k - 1))]);
   GLOBAL S* __restrict__ s_out = gp<S>(D.sF[par(n_F(D, k))]);
   GLOBAL R* __restrict__ vel = gp<R>(D.vel[par(n_F(D, k))]);
-  GLOBAL const R* __restrict__ phis = gp<const R>(D.phi[par(n_phi(D, k))]);
+  GLOBAL const R* __restrict__ phis = gp<const R>(D.phi[tri(n_phi(D, k))]);
   const R dt = R(D.N_F * D.dt_base);
   const R Fx = R(D.Fx), Fy = R(D.Fy);
   const R snu = R(1.0 / (3.0 * D.N_F * D.dt_base * D.nu + 0.5));
@@ -2221,8 +2228,7 @@ __global__ void k_init(const Dom* __restrict__ doms, int dom, const double* __re
     }
   }
   const R ph = R(phi);
-  (gp<R>(D.phi[0]))[o] = ph;
-  (gp<R>(D.phi[1]))[o] = ph;
+  for (int b = 0; b < 3; ++b) (gp<R>(D.phi[b]))[o] = ph;
   for (int q = 0; q < D.qs - 1; ++q) {
     st(gp<S>(D.sphi[0]), o + q * pl, R(0));
     st(gp<S>(D.sphi[1]), o + q * pl, R(0));
@@ -2272,7 +2278,7 @@ template <class R, class S>
 __device__ double read_plane(const Dom& D, long long k, int code, long long o) {
   const long long pl = D.plane;
   switch (code) {
-    case 0: return double((gp<const R>(D.phi[par(n_phi(D, k))]))[o]);
+    case 0: return double((gp<const R>(D.phi[tri(n_phi(D, k))]))[o]);
     case 1: return double((gp<const R>(D.U[par(n_U(D, k))]))[o]) + D.U0;
     case 2: return double((gp<const R>(D.T[par(n_T(D, k))]))[o]) + D.T0;
     case 8: return double((gp<const R>(D.U[par(n_U(D, k))]))[o]);
@@ -2291,7 +2297,7 @@ __device__ double read_plane(const Dom& D, long long k, int code, long long o) {
   if (code >= 70 && code <= 77) return double(ld(gp<const S>(D.sF[par(n_F(D, k))]), o + (code - 70) * pl));
   if (code >= 10 && code < 10 + D.qs) {
     const int b = par(n_phi(D, k));
-    GLOBAL const R* ph = gp<const R>(D.phi[b]);
+    GLOBAL const R* ph = gp<const R>(D.phi[tri(n_phi(D, k))]);
     GLOBAL const S* s = gp<const S>(D.sphi[b]);
     const R phi = ph[o];
     const bool q9 = D.qs == 9;
@@ -2352,7 +2358,7 @@ __global__ void k_write(const Dom* __restrict__ doms, int dom, long long k, cons
     const int code = codes[c];
     const double v = src[c * n + i];
     switch (code) {
-      case 0: (gp<R>(D.phi[par(n_phi(D, k))]))[o] = R(v); break;
+      case 0: (gp<R>(D.phi[tri(n_phi(D, k))]))[o] = R(v); break;
       case 1: (gp<R>(D.U[par(n_U(D, k))]))[o] = R(v - D.U0); break;
       case 2: (gp<R>(D.T[par(n_T(D, k))]))[o] = R(v - D.T0); break;
       case 8: (gp<R>(D.U[par(n_U(D, k))]))[o] = R(v); break;
@@ -2385,7 +2391,7 @@ __global__ void k_write(const Dom* __restrict__ doms, int dom, long long k, cons
       f[q] = R(src[(cphi + q) * n + i]);
       phi += f[q];
     }
-    (gp<R>(D.phi[b]))[o] = phi;
+    (gp<R>(D.phi[tri(n_phi(D, k))]))[o] = phi;
     for (int q = 1; q < D.qs; ++q)
       st(gp<S>(D.sphi[b]), o + (q - 1) * pl, f[q] - phi * R(q9 ? (q <= 4 ? 1.0 / 9.0 : 1.0 / 36.0) : 1.0 / 6.0));
   }
@@ -2417,7 +2423,7 @@ __global__ __launch_bounds__(NTHR) void k_diag_tiles(const Dom* __restrict__ dom
   if (t.x < 0) return;
   const Dom& D = doms[t.x];
   const long long px = D.px;
-  GLOBAL const R* phi = gp<const R>(D.phi[par(n_phi(D, k))]);
+  GLOBAL const R* phi = gp<const R>(D.phi[tri(n_phi(D, k))]);
   GLOBAL const R* U = D.has_U ? gp<const R>(D.U[par(n_U(D, k))]) : nullptr;
   GLOBAL const R* T = D.has_T ? gp<const R>(D.T[par(n_T(D, k))]) : nullptr;
   GLOBAL const R* rho = D.has_F ? gp<const R>(D.rho[par(n_F(D, k))]) : nullptr;
@@ -2539,7 +2545,7 @@ __global__ void k_tips(const Dom* __restrict__ doms, long long k, DiagOut* __res
     if (threadIdx.x == 0) out[d].tip[s * 4 + ax] = 0.0;
     return;
   }
-  GLOBAL const R* phi = gp<const R>(D.phi[par(n_phi(D, k))]);
+  GLOBAL const R* phi = gp<const R>(D.phi[tri(n_phi(D, k))]);
   const double ang = atan2(D.sth, D.cth) + ax * 1.5707963267948966;
   const double c = cos(ang), sn = sin(ang);
   const double cx = D.seed[s][0], cy = D.seed[s][1];
@@ -2828,10 +2834,11 @@ __global__ __launch_bounds__(256) void k3z_phase(const Dom* __restrict__ doms, u
   if (!zcol(G, blockIdx.x, zrun, c) || k % D.N_phi) return;
   const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
   const long long pl = D.plane;
-  const int ib = par(n_phi(D, k - 1)), ob = ib ^ 1;
-  GLOBAL const R* phi = gp<const R>(D.phi[ib]);
+  const unsigned np = n_phi(D, k - 1);
+  const int ib = par(np), ob = ib ^ 1;
+  GLOBAL const R* phi = gp<const R>(D.phi[tri(np)]);
   GLOBAL const SR* sp = gp<const SR>(D.sphi[ib]);
-  GLOBAL R* phi_out = gp<R>(D.phi[ob]);
+  GLOBAL R* phi_out = gp<R>(D.phi[tri(np + 1)]);
   GLOBAL S* s_out = gp<S>(D.sphi[ob]);
   const unsigned nU = (D.accum ? 0u : (k - 1) / D.N_phi) + (k - 1) / D.N_U;
   GLOBAL const R* Up = D.has_U ? gp<const R>(D.U[par(nU)]) : nullptr;
@@ -3024,7 +3031,7 @@ __global__ __launch_bounds__(256) void k3z_scalar(const Dom* __restrict__ doms, 
     jout = gp<S>(D.jT[par(n_jT(D, k))]);
     pend = gp<R>(D.PT);
   }
-  GLOBAL const R* phis = gp<const R>(D.phi[par(n_phi(D, k))]);
+  GLOBAL const R* phis = gp<const R>(D.phi[tri(n_phi(D, k))]);
   GLOBAL const R* vel = D.has_F ? gp<const R>(D.vel[par(n_F(D, k - 1))]) : nullptr;
   const bool var = FIELD == 0 || D.T_var;
   const bool accum = D.accum;
@@ -3233,8 +3240,8 @@ __global__ __launch_bounds__(256) void k3z_transfer(const Dom* __restrict__ doms
   ZCol c;
   if (!zcol(G, blockIdx.x, zrun, c) || k % D.N_phi) return;
   const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
-  GLOBAL const R* pn = gp<const R>(D.phi[par(n_phi(D, k))]);
-  GLOBAL const R* po = gp<const R>(D.phi[par(n_phi(D, k - 1))]);
+  GLOBAL const R* pn = gp<const R>(D.phi[tri(n_phi(D, k))]);
+  GLOBAL const R* po = gp<const R>(D.phi[tri(n_phi(D, k - 1))]);
   const bool hasU = D.has_U, hasT = D.has_T && !D.T_pulled, accum = D.accum;
   const unsigned nU = (D.accum ? 0u : (k - 1) / D.N_phi) + (k - 1) / D.N_U;
   GLOBAL const R* Uin = hasU ? gp<const R>(D.U[par(nU)]) : nullptr;
@@ -3519,7 +3526,7 @@ __global__ __launch_bounds__(256) void k3z_flow(const Dom* __restrict__ doms, un
   const int ib = par(n_F(D, k - 1)), ob = par(n_F(D, k));
   GLOBAL const R* rin = gp<const R>(D.rho[ib]);
   GLOBAL const SR* sp = gp<const SR>(D.sF[ib]);
-  GLOBAL const R* phis = gp<const R>(D.phi[par(n_phi(D, k))]);
+  GLOBAL const R* phis = gp<const R>(D.phi[tri(n_phi(D, k))]);
   GLOBAL R* rho_out = gp<R>(D.rho[ob]);
   GLOBAL R* vel = gp<R>(D.vel[ob]);
   GLOBAL S* s_out = gp<S>(D.sF[ob]);
@@ -3640,10 +3647,9 @@ __global__ void k3_init(const Dom* __restrict__ doms, const double* __restrict__
   const unsigned pl = (unsigned)D.plane;
   const double off = xi ? xi[(long long)s.y * D.nx + s.x] : 0.0;
   const double phi = tanh((D.z_front + off - s.z) / (1.4142135623730951 * D.W0));
-  for (int b = 0; b < 2; ++b) {
-    (gp<R>(D.phi[b]))[s.o] = R(phi);
+  for (int b = 0; b < 3; ++b) (gp<R>(D.phi[b]))[s.o] = R(phi);
+  for (int b = 0; b < 2; ++b)
     for (int q = 0; q < 6; ++q) st(gp<S>(D.sphi[b]), s.o + q * pl, R(0));
-  }
   if (D.has_U) {
     for (int b = 0; b < 2; ++b) {
       (gp<R>(D.U[b]))[s.o] = R(0);   // U - U0
@@ -3679,7 +3685,7 @@ __global__ void k3_init(const Dom* __restrict__ doms, const double* __restrict__
 template <class R, class S>
 __device__ double read_plane3(const Dom& D, long long k, int code, unsigned o) {
   const unsigned pl = (unsigned)D.plane;
-  if (code == 0) return double((gp<const R>(D.phi[par(n_phi(D, k))]))[o]);
+  if (code == 0) return double((gp<const R>(D.phi[tri(n_phi(D, k))]))[o]);
   if (code == 1) return double((gp<const R>(D.U[par(n_U(D, k))]))[o]) + D.U0;
   if (code == 2) return double((gp<const R>(D.T[par(n_T(D, k))]))[o]) + D.T0;
   if (code == 8) return double((gp<const R>(D.U[par(n_U(D, k))]))[o]);
@@ -3694,7 +3700,7 @@ __device__ double read_plane3(const Dom& D, long long k, int code, unsigned o) {
   if (code >= 70 && code <= 87) return double(ld(gp<const S>(D.sF[par(n_F(D, k))]), o + (code - 70) * pl));
   if (code >= 10 && code <= 16) {
     const int b = par(n_phi(D, k));
-    const R phi = (gp<const R>(D.phi[b]))[o];
+    const R phi = (gp<const R>(D.phi[tri(n_phi(D, k))]))[o];
     GLOBAL const S* sp = gp<const S>(D.sphi[b]);
     if (code == 10) {
       R sum = R(0);
@@ -3745,7 +3751,7 @@ __global__ void k3_write(const Dom* __restrict__ doms, long long k, const int* _
   for (int c = 0; c < ncodes; ++c) {
     const int code = codes[c];
     const double v = src[c * n + i];
-    if (code == 0) (gp<R>(D.phi[par(n_phi(D, k))]))[o] = R(v);
+    if (code == 0) (gp<R>(D.phi[tri(n_phi(D, k))]))[o] = R(v);
     else if (code == 1) (gp<R>(D.U[par(n_U(D, k))]))[o] = R(v - D.U0);
     else if (code == 2) (gp<R>(D.T[par(n_T(D, k))]))[o] = R(v - D.T0);
     else if (code == 8) (gp<R>(D.U[par(n_U(D, k))]))[o] = R(v);
@@ -3768,7 +3774,7 @@ __global__ void k3_write(const Dom* __restrict__ doms, long long k, const int* _
       f[q] = R(src[(cphi + q) * n + i]);
       phi += f[q];
     }
-    (gp<R>(D.phi[b]))[o] = phi;
+    (gp<R>(D.phi[tri(n_phi(D, k))]))[o] = phi;
     for (int q = 1; q < 7; ++q) st(gp<S>(D.sphi[b]), o + (q - 1) * pl, f[q] - phi * R(0.125));
   }
   if (cflow >= 0) {
@@ -3791,7 +3797,7 @@ __global__ __launch_bounds__(256) void k3_diag(const Dom* __restrict__ doms, lon
   Site3 s;
   double a[5] = {0, 0, 0, 0, 0};
   if (site3(D, blockIdx.x, threadIdx.x, s)) {
-    const double p = double((gp<const R>(D.phi[par(n_phi(D, k))]))[s.o]);
+    const double p = double((gp<const R>(D.phi[tri(n_phi(D, k))]))[s.o]);
     a[0] = (1.0 + p) * 0.5;
     bool bad = !isfinite(p);
     if (D.has_U) {
@@ -3839,7 +3845,7 @@ __global__ void k3_front(const Dom* __restrict__ doms, long long k, double* __re
   if (col < (long long)D.nx * D.ny) {
     has = true;
     const int x = (int)(col % D.nx), y = (int)(col / D.nx);
-    GLOBAL const R* phi = gp<const R>(D.phi[par(n_phi(D, k))]);
+    GLOBAL const R* phi = gp<const R>(D.phi[tri(n_phi(D, k))]);
     double prev = double(phi[(long long)y * D.px + x]);
     h = prev < 0 ? 0.0 : double(D.nz - 1);
     if (prev >= 0)

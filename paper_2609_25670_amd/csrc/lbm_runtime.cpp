@@ -4,9 +4,10 @@
 // the per-domain state planes, the device descriptors, the tile lists and the
 // reduction buffers.  Stepping issues, per base step k, the kernels whose
 // field is due (k mod N_chi == 0, Eq. 34) in the order phase, transfer, U, T,
-// flow; whole cycles of 2 * lcm(N_chi) base steps (the period after which
-// every double-buffer parity repeats) are captured once into a HIP graph and
-// replayed.
+// flow; whole cycles of 2 * lcm(N_chi) base steps, or three times that
+// (the period after which every buffer index repeats: parities of the
+// double-buffered planes, write counts mod 3 of the phase field), are
+// captured once into a HIP graph and replayed.
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
@@ -219,7 +220,7 @@ struct Layout {
 Layout layout_of(const lbm_params& p) {
   Layout L;
   const int d = p.dim;
-  L.rplanes = 2;                           // phi, two buffers
+  L.rplanes = 3;                           // phi, three buffers
   L.splanes = 2 * (p.q_scalar - 1);        // phase s_i, two buffers
   if (p.has_U) { L.rplanes += 3; L.splanes += 2 * d; }
   if (p.has_T) { L.rplanes += 3; L.splanes += 2 * d; }
@@ -332,8 +333,8 @@ static int ty_slot(int rows) {
 }
 
 // The step kernels take the base step within the cycle: absolute step k >= 1
-// maps to 1 + (k - 1) mod cycle, which keeps every k mod N_chi and the
-// parity of every buffer count, so their index arithmetic stays 32-bit.  The
+// maps to 1 + (k - 1) mod cycle, which keeps every k mod N_chi and every
+// buffer index, so their index arithmetic stays 32-bit.  The
 // time-dependent 3D walls add Dom::koff, the absolute step at the start of
 // the cycle.
 static unsigned cycle_step(const lbm_ctx* c, long long k) { return (unsigned)((k - 1) % c->cycle + 1); }
@@ -506,8 +507,8 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
     if (!m.empty()) return fail(nullptr, LBM_EINVAL, m);
   }
   {
-    // the step kernels index the cycle of 2 lcm(N_chi) base steps and a
-    // plane's elements in 32 bits
+    // the step kernels index the cycle of (up to) 6 lcm(N_chi) base steps
+    // and a plane's elements in 32 bits
     long long lcm = 1;
     for (int i = 0; i < n; ++i) {
       for (int N : {p[i].N_phi, p[i].N_U, p[i].N_T, p[i].N_F}) {
@@ -662,10 +663,8 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
     }
     const size_t pr = D.plane * c->rsz, ps = D.plane * c->ssz;
     const int d3 = q.dim == 3;
-    for (int b = 0; b < 2; ++b) {
-      D.phi[b] = take(pr);
-      D.sphi[b] = take(align256(ps) * (q.q_scalar - 1));
-    }
+    for (int b = 0; b < 3; ++b) D.phi[b] = take(pr);
+    for (int b = 0; b < 2; ++b) D.sphi[b] = take(align256(ps) * (q.q_scalar - 1));
     if (q.has_U) {
       for (int b = 0; b < 2; ++b) {
         D.U[b] = take(pr);
@@ -705,7 +704,10 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
     for (int i = 0; i < n; ++i) runs += (long long)((p[i].nx + 63) / 64) * ((p[i].ny + kYRun - 1) / kYRun);
     c->march_big = runs >= 4 * 256;
   }
+  // the phase field's buffer index (its write count mod 3) repeats too
   c->cycle = 2 * lcm;
+  for (int i = 0; i < n; ++i)
+    if ((c->cycle / p[i].N_phi) % 3 != 0) c->cycle *= 3;
   c->d_dom = (Dom*)take(sizeof(Dom) * n);
 
   // tile lists (three tile heights), groups by update factor

@@ -209,6 +209,41 @@ def test_deferred_transfer_is_bitwise_identical(storage, case):
             assert diag["S_phi"] == ref[1]["S_phi"] and diag["J_U"] == ref[1]["J_U"]
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32"])
+def test_deferred_transfer_more_blocks_than_fit_on_the_chip(storage):
+    """The deferred transfer reads the transfer's old phase field on rings
+    that neighbouring blocks own, while those blocks write the next phase
+    field.  On 1024 x 1024 with four seeds (long interfaces across many
+    tile edges) and 64 x 4 tiles, 4096 blocks, more than are resident at
+    once, so late blocks run after their neighbours have finished: the
+    state equals that of the separate kernels bit for bit, and FP64 equals
+    the oracle."""
+    from paper_2609_25670_amd import simulation_for
+
+    wl = L.reduced(L.solutal_512(), 1024, 1024)
+    d = wl["domains"][0]
+    d["seeds"] = [(300.5, 300.5, 120.0), (720.5, 310.5, 110.0), (310.5, 730.5, 100.0), (715.5, 715.5, 130.0)]
+    names = ("phi", "U", "f_phi", "jU")
+    steps = 27
+    res = {}
+    for defer in (False, True):
+        _say(f"case deferred transfer 1024x1024 {storage} rows=4 defer={defer}")
+        sim = simulation_for(wl, storage=storage)
+        sim.configure(4, True, False, False, defer)
+        diag = sim.step(steps, diag=True)[0]
+        res[defer] = sim.read(0, names)
+        sim.close()
+        assert diag["nonfinite"] == 0
+    for n in names:
+        assert np.array_equal(res[True][n], res[False][n]), n
+    if storage == "f64":
+        dom = oracle.run(d, steps)
+        for n, ref in (("phi", dom.phi), ("U", dom.U)):
+            e = _rel(res[True][n], ref)
+            _say(f"  deferred 1024x1024: {n} rel L2 = {e:.3e}")
+            assert e <= TOL64, (n, e)
+
+
 @pytest.mark.parametrize("q", [5, 9])
 def test_marching_kernels_fp64(q):
     """The marching phase, transfer and T-transport kernels on the 2D
