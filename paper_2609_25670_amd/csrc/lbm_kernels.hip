@@ -1076,8 +1076,8 @@ __global__ __launch_bounds__(NTHR) void k_dtr_phase(const Dom* __restrict__ doms
   constexpr int W2 = TX + 4, H2 = TY + 4;   // J
   constexpr int W1 = TX + 2, H1 = TY + 2;   // transferred U, T and the collisions
   constexpr int N3 = W3 * H3, N2 = W2 * H2, N1 = W1 * H1;
-  constexpr int C2 = (N2 + NTHR - 1) / NTHR, C1 = (N1 + NTHR - 1) / NTHR;
-  constexpr int RPT = TY / BY;
+  constexpr int C2 = (N2 + NTHR - 1) / NTHR;
+  constexpr int RPT = TY / BY, NS = RPT + 1;
   __shared__ R sq[N3];
   __shared__ R sJx[N2], sJy[N2];
   __shared__ R cP[N1], cKx[N1], cKy[N1];
@@ -1130,22 +1130,38 @@ __global__ __launch_bounds__(NTHR) void k_dtr_phase(const Dom* __restrict__ doms
     jpo[j] = ldo(phi_old, o);
     if (Uin) jU[j] = ldo(Uin, o);
   }
-  R sv[C1][4], cpo[C1], cU[C1], cT_[C1];
-  bool live[C1];
+  // cells of this thread in the collision box (tile plus one ring): RPT
+  // owned sites, then at most one ring cell (beyond a wall: none, never
+  // pulled from), so the streaming below runs on every lane
+  int cl[NS], bq[NS], ji[NS];   // collision-box, phi-box and J-box indices
+  unsigned oc[NS];
+  R sv[NS][4], cpo[NS], cU[NS], cT_[NS];
 #pragma unroll
-  for (int j = 0; j < C1; ++j) {
-    const int i = tid + j * NTHR;
-    live[j] = false;
-    if (i >= N1) continue;
-    const int rx = resolve(x0 - 1 + i % W1, nx, bcx), ry = resolve(y0 - 1 + i / W1, ny, bcy);
-    if (rx < 0 || ry < 0) continue;   // beyond a wall: never pulled from
-    live[j] = true;
-    const unsigned o = (unsigned)(ry * px + rx);
+  for (int r = 0; r < NS; ++r) {
+    int lx, ly, gx, gy;
+    cl[r] = -1;
+    if (r < RPT) {
+      lx = tx + 1;
+      ly = ty + r * BY + 1;
+      if (tx >= w || ly > h) continue;
+      gx = x0 + tx;
+      gy = y0 + ly - 1;
+    } else {
+      if (!ring_cell(tid, w, h, lx, ly)) continue;
+      gx = resolve(x0 - 1 + lx, nx, bcx);
+      gy = resolve(y0 - 1 + ly, ny, bcy);
+      if (gx < 0 || gy < 0) continue;
+    }
+    cl[r] = ly * W1 + lx;
+    bq[r] = (ly + 2) * W3 + lx + 2;
+    ji[r] = (ly + 1) * W2 + lx + 1;
+    const unsigned o = (unsigned)(gy * px + gx);
+    oc[r] = o;
 #pragma unroll
-    for (int q = 0; q < 4; ++q) sv[j][q] = ldo(plane(s_in, q * pl), o);
-    cpo[j] = ldo(phi_old, o);
-    if (Uin) cU[j] = ldo(Uin, o);
-    if (Tin) cT_[j] = ldo(Tin, o);
+    for (int q = 0; q < 4; ++q) sv[r][q] = ldo(plane(s_in, q * pl), o);
+    cpo[r] = ldo(phi_old, o);
+    if (Uin) cU[r] = ldo(Uin, o);
+    if (Tin) cT_[r] = ldo(Tin, o);
   }
   __syncthreads();
 
@@ -1175,38 +1191,36 @@ __global__ __launch_bounds__(NTHR) void k_dtr_phase(const Dom* __restrict__ doms
   }
   __syncthreads();
 
-  // ---- transferred U and T on ring 1, then the phase collision there
-  R amax = R(0), Aown[C1];
+  // ---- transferred U and T at the collision cells (stored on the owned
+  // sites), then the phase collision there
+  R amax = R(0), Aown[RPT];
 #pragma unroll
-  for (int j = 0; j < C1; ++j) {
-    if (!live[j]) continue;
-    const int i = tid + j * NTHR;
-    const int lx = i % W1, ly = i / W1;
-    const bool own = lx >= 1 && ly >= 1 && lx <= w && ly <= h;
-    const unsigned o = (unsigned)((y0 - 1 + ly) * px + (x0 - 1 + lx));   // a live cell is inside the domain
-    const R* b = &sq[(ly + 2) * W3 + lx + 2];
+  for (int r = 0; r < NS; ++r) {
+    if (cl[r] < 0) continue;
+    const bool own = r < RPT;
+    const R* b = &sq[bq[r]];
     const R pn = b[0];
-    const R dphi = pn - cpo[j];
+    const R dphi = pn - cpo[r];
     R Ust = R(0), Tst = R(0);
     if (Uin) {
-      const R* jx = &sJx[(ly + 1) * W2 + lx + 1];
-      const R* jy = &sJy[(ly + 1) * W2 + lx + 1];
+      const R* jx = &sJx[ji[r]];
+      const R* jy = &sJy[ji[r]];
       const R div = (jx[1] - jx[-1]) * R(1.0 / 3.0) +
                     (jx[W2 + 1] - jx[W2 - 1] - jx[-W2 - 1] + jx[-W2 + 1]) * R(1.0 / 12.0) +
                     (jy[W2] - jy[-W2]) * R(1.0 / 3.0) +
                     (jy[W2 + 1] + jy[W2 - 1] - jy[-W2 - 1] - jy[-W2 + 1]) * R(1.0 / 12.0);
-      const R dU = ((R(1) + omk * (cU[j] + Uref)) * dphi - R(2) * div) * rcp(opk - omk * pn);
-      Ust = cU[j] + dU;
+      const R dU = ((R(1) + omk * (cU[r] + Uref)) * dphi - R(2) * div) * rcp(opk - omk * pn);
+      Ust = cU[r] + dU;
       if (own) {
         amax = fmax(amax, fabs(dU));
-        sto(Uout, o, Ust);
+        sto(Uout, oc[r], Ust);
       }
     }
     if (Tin) {
       const R rc = (R(1) + pn) * R(0.5) * rcS + (R(1) - pn) * R(0.5) * rcL;
       const R dT = cT * dphi * rcp(R(2) * rc);
-      Tst = cT_[j] + dT;
-      if (own) sto(Tout, o, Tst);
+      Tst = cT_[r] + dT;
+      if (own) sto(Tout, oc[r], Tst);
     }
     // the phase collision of step k with the transferred U and T
     R gxv, gyv;
@@ -1214,11 +1228,11 @@ __global__ __launch_bounds__(NTHR) void k_dtr_phase(const Dom* __restrict__ doms
     const R Uv = Uin ? Ust + Uref : R(0);
     const R Tv = Tin ? Tst + Tref : c.theta_off;
     R dP, Kx, Ky, A;
-    phase_collide(c, pn, gxv, gyv, sv[j][0] - sv[j][2], sv[j][1] - sv[j][3], Uv, Tv, dP, Kx, Ky, A);
-    cP[i] = dP;
-    cKx[i] = Kx;
-    cKy[i] = Ky;
-    Aown[j] = A;
+    phase_collide(c, pn, gxv, gyv, sv[r][0] - sv[r][2], sv[r][1] - sv[r][3], Uv, Tv, dP, Kx, Ky, A);
+    cP[cl[r]] = dP;
+    cKx[cl[r]] = Kx;
+    cKy[cl[r]] = Ky;
+    if (own) Aown[r] = A;
   }
   __syncthreads();
 
@@ -1227,19 +1241,17 @@ __global__ __launch_bounds__(NTHR) void k_dtr_phase(const Dom* __restrict__ doms
   auto stream = [&](auto edge_c) {
     constexpr bool EDGE = decltype(edge_c)::value;
 #pragma unroll
-    for (int j = 0; j < C1; ++j) {
-      if (!live[j]) continue;
-      const int i = tid + j * NTHR;
-      const int lx = i % W1, ly = i / W1;
-      if (!(lx >= 1 && ly >= 1 && lx <= w && ly <= h)) continue;
-      const int gx = x0 - 1 + lx, gy = y0 - 1 + ly;
-      const R A = Aown[j], iA = rcp(A), oA = R(1) - A;
-      const int bq = (ly + 2) * W3 + lx + 2;
-      const R phy = sq[bq];
+    for (int r = 0; r < RPT; ++r) {
+      if (cl[r] < 0) continue;
+      const int i = cl[r];
+      const int gx = x0 + tx, gy = y0 + ty + r * BY;
+      const R A = Aown[r], iA = rcp(A), oA = R(1) - A;
+      const int bc = bq[r];
+      const R phy = sq[bc];
       const R dPo = cP[i];
       R s0 = R(0);
 #pragma unroll
-      for (int q = 0; q < 4; ++q) s0 -= sv[j][q];
+      for (int q = 0; q < 4; ++q) s0 -= sv[r][q];
       R dn[5];
       dn[0] = (dPo * R(1.0 / 3.0) - oA * s0) * iA;
 #pragma unroll
@@ -1252,15 +1264,15 @@ __global__ __launch_bounds__(NTHR) void k_dtr_phase(const Dom* __restrict__ doms
           dpost = dPo * R(1.0 / 6.0) - R(0.5) * (R(ex) * cKx[i] + R(ey) * cKy[i]);
         } else {
           const int si = i - ey * W1 - ex;
-          const R dphi = sq[bq - ey * W3 - ex] - phy;
+          const R dphi = sq[bc - ey * W3 - ex] - phy;
           dpost = (dphi + cP[si]) * R(1.0 / 6.0) + R(0.5) * (R(ex) * cKx[si] + R(ey) * cKy[si]);
         }
-        dn[q] = (dpost - oA * sv[j][q - 1]) * iA;
+        dn[q] = (dpost - oA * sv[r][q - 1]) * iA;
       }
       R dphin = dn[0];
 #pragma unroll
       for (int q = 1; q < 5; ++q) dphin += dn[q];
-      const unsigned o = (unsigned)(gy * px + gx);
+      const unsigned o = oc[r];
       sto(phi_out, o, phy + dphin);
 #pragma unroll
       for (int q = 1; q < 5; ++q) sto(plane(s_out, (q - 1) * pl), o, dn[q] - dphin * R(1.0 / 6.0));
