@@ -218,7 +218,10 @@ lbm_status lbm_write_fields(lbm_ctx* ctx, int32_t domain, uint32_t mask,
  *                           transfer of a phase step at which no transport
  *                           runs (and which is not the last step of a call
  *                           or of a graph cycle) runs inside the next phase
- *                           kernel; results bitwise identical.
+ *                           kernel, and where every domain has U in one
+ *                           update group, the transfer of a step at which U
+ *                           is due runs inside that U transport; results
+ *                           bitwise identical.
  * Default after lbm_create: autotune, LBM_CFG_GRAPH.  Unknown flags, or
  * LBM_CFG_MARCH with LBM_CFG_TILES: LBM_EINVAL. */
 enum { LBM_CFG_GRAPH = 1, LBM_CFG_FUSE_TRANSFER = 2, LBM_CFG_MARCH = 4, LBM_CFG_TILES = 8, LBM_CFG_NO_DEFER = 16 };
@@ -228,13 +231,13 @@ lbm_status lbm_configure(lbm_ctx* ctx, int32_t tile_rows, int32_t flags);
  * over every domain, measured with HIP events around `reps` back-to-back
  * launches on the context stream: ms_out[0] phase, [1] transfer, [2] U
  * transport, [3] T transport, [4] flow, [5] the phase kernel carrying the
- * previous step's deferred transfer (-1 where the context has no such
- * kernel); the arrays hold 6 values.  per_step_out[0..5] (may be NULL)
- * receives the fraction of that time spent per base step (each group of
- * domains sharing an update factor N contributes 1/N of its own launch
- * time; with deferred transfers the plain phase and transfer kernels run on
- * the other steps), so ms_out * per_step_out is the device time per base
- * step.  The timing launches overwrite the state:
+ * previous step's deferred transfer, [6] the U transport carrying its
+ * step's transfer (-1 where the context has no such kernel); the arrays
+ * hold 7 values.  per_step_out[0..6] (may be NULL) receives the fraction of
+ * that time spent per base step (each group of domains sharing an update
+ * factor N contributes 1/N of its own launch time; with deferred transfers
+ * the plain phase, transfer and U kernels run on the other steps), so
+ * ms_out * per_step_out is the device time per base step.  The timing launches overwrite the state:
  * every domain must be re-initialised with lbm_init_seeds before the next
  * lbm_step_multirate. */
 lbm_status lbm_kernel_times(lbm_ctx* ctx, int32_t reps, double* ms_out, double* per_step_out);

@@ -60,9 +60,9 @@ struct Dom {
   double kd[K_N];
   float kf[K_N];
   // state
-  void* phi[3];    // R, 1 plane, three buffers (see tri())
+  void* phi[4];    // R, 1 plane, four buffers (see qb())
   void* sphi[2];   // S, Q-1 planes: f_i - w_i phi, i >= 1 (4 in D2Q5, 8 in D2Q9, 6 in D3Q7)
-  void* U[2];      // R
+  void* U[4];      // R, four buffers
   void* jU[2];     // S, dim planes: first moment of the U populations
   void* PU;        // R, pending U increments (accumulated coupling)
   void* T[2];      // R
@@ -99,19 +99,20 @@ struct DiagOut {
 // Buffer index holding a field's latest values after `n` writes.
 __host__ __device__ inline int par(long long n) { return (int)(n & 1); }
 
-// Buffer index of the phase field after n writes.  It has three buffers, so
-// that a kernel writing phi^{n+1} may still read phi^{n-1} at sites of other
-// blocks: the phase kernel that carries the previous step's transfer reads
-// phi^{n-1} on its rings while neighbouring blocks write phi^{n+1}.
+// Buffer index of the phase field and of U after n writes.  Both have four
+// buffers, so that a kernel writing the next value may still read the value
+// two writes back at sites of other blocks: the kernels that carry a
+// deferred transfer read phi^{n-1} (and U before the transfer) on their
+// rings while neighbouring blocks write phi^{n+1} (the transported U).
 template <class I>
-__host__ __device__ inline int tri(I n) { return (int)(n % (I)3); }
+__host__ __device__ inline int qb(I n) { return (int)(n & (I)3); }
 
 // Writes of each buffered plane after completing base step k.  The
 // step kernels take k as a 32-bit unsigned step within the cycle of
-// 2 lcm(N_chi) base steps, tripled where the phase field's write count over
-// it is not a multiple of 3 (every quotient's parity, every phase buffer
-// index and every k mod N is periodic with it), so their divisions are
-// 32-bit; the host and the read-out kernels use the absolute 64-bit step.
+// 2 lcm(N_chi) base steps, doubled where the write count of phi or U over
+// it is not a multiple of 4 (every buffer index and every k mod N is
+// periodic with it), so their divisions are 32-bit; the host and the
+// read-out kernels use the absolute 64-bit step.
 template <class I>
 __host__ __device__ inline I n_phi(const Dom& d, I k) { return k / (I)d.N_phi; }
 template <class I>

@@ -339,13 +339,13 @@ __global__ __launch_bounds__(NTHR) void k_phase(const Dom* __restrict__ doms, co
   const int bcx = D.bc[0], bcy = D.bc[1];
   const unsigned np = n_phi(D, k - 1);
   const int ib = par(np), ob = ib ^ 1;
-  GLOBAL const R* __restrict__ phi_in = gp<const R>(D.phi[tri(np)]);
-  GLOBAL R* __restrict__ phi_out = gp<R>(D.phi[tri(np + 1)]);
+  GLOBAL const R* __restrict__ phi_in = gp<const R>(D.phi[qb(np)]);
+  GLOBAL R* __restrict__ phi_out = gp<R>(D.phi[qb(np + 1)]);
   GLOBAL const S* __restrict__ s_in = gp<const S>(D.sphi[ib]);
   GLOBAL S* __restrict__ s_out = gp<S>(D.sphi[ob]);
   // latest U and T (before this step's transfer)
   const unsigned nU = (D.accum ? 0u : (k - 1) / D.N_phi) + (k - 1) / D.N_U;
-  GLOBAL const R* __restrict__ Up = D.has_U ? gp<const R>(D.U[par(nU)]) : nullptr;
+  GLOBAL const R* __restrict__ Up = D.has_U ? gp<const R>(D.U[qb(nU)]) : nullptr;
   GLOBAL const R* __restrict__ Tp = D.has_T ? gp<const R>(D.T[par(n_T(D, k - 1))]) : nullptr;
 
   const PhaseConst<R> c = phase_const<R>(D);
@@ -560,12 +560,12 @@ __global__ __launch_bounds__(NTHR) void k_phase_ym(const Dom* __restrict__ doms,
   const int w = min(TX, nx - x0);
   const unsigned np = n_phi(D, k - 1);
   const int ib = par(np), ob = ib ^ 1;
-  GLOBAL const R* __restrict__ phi_in = gp<const R>(D.phi[tri(np)]);
-  GLOBAL R* __restrict__ phi_out = gp<R>(D.phi[tri(np + 1)]);
+  GLOBAL const R* __restrict__ phi_in = gp<const R>(D.phi[qb(np)]);
+  GLOBAL R* __restrict__ phi_out = gp<R>(D.phi[qb(np + 1)]);
   GLOBAL const SR* __restrict__ s_in = gp<const SR>(D.sphi[ib]);
   GLOBAL S* __restrict__ s_out = gp<S>(D.sphi[ob]);
   const unsigned nU = (D.accum ? 0u : (k - 1) / D.N_phi) + (k - 1) / D.N_U;
-  GLOBAL const R* __restrict__ Up = D.has_U ? gp<const R>(D.U[par(nU)]) : nullptr;
+  GLOBAL const R* __restrict__ Up = D.has_U ? gp<const R>(D.U[qb(nU)]) : nullptr;
   GLOBAL const R* __restrict__ Tp = D.has_T ? gp<const R>(D.T[par(n_T(D, k - 1))]) : nullptr;
   const PhaseConst<R> c = phase_const<R>(D);
   const R U0 = kc<R>(D, K_U0), T0 = kc<R>(D, K_T0);
@@ -722,11 +722,11 @@ __global__ __launch_bounds__(NTHR) void k_transfer(const Dom* __restrict__ doms,
   const int x0 = t.y, y0 = t.z;
   const int w = min(TX, nx - x0), h = min(TY, ny - y0);
   const int bcx = D.bc[0], bcy = D.bc[1];
-  GLOBAL const R* __restrict__ phi_old = gp<const R>(D.phi[tri(n_phi(D, k - 1))]);
-  GLOBAL const R* __restrict__ phi_new = gp<const R>(D.phi[tri(n_phi(D, k))]);
+  GLOBAL const R* __restrict__ phi_old = gp<const R>(D.phi[qb(n_phi(D, k - 1))]);
+  GLOBAL const R* __restrict__ phi_new = gp<const R>(D.phi[qb(n_phi(D, k))]);
   const unsigned nU = (D.accum ? 0u : (k - 1) / D.N_phi) + (k - 1) / D.N_U;
-  GLOBAL const R* __restrict__ Uin = D.has_U ? gp<const R>(D.U[par(nU)]) : nullptr;
-  GLOBAL R* __restrict__ Uout = D.has_U ? gp<R>(D.U[par(nU + 1)]) : nullptr;
+  GLOBAL const R* __restrict__ Uin = D.has_U ? gp<const R>(D.U[qb(nU)]) : nullptr;
+  GLOBAL R* __restrict__ Uout = D.has_U ? gp<R>(D.U[qb(nU + 1)]) : nullptr;
   GLOBAL const R* __restrict__ Tin = D.has_T ? gp<const R>(D.T[par(n_T(D, k - 1))]) : nullptr;
   GLOBAL R* __restrict__ Tout = D.has_T ? gp<R>(D.T[par(n_T(D, k - 1) + 1)]) : nullptr;
   GLOBAL R* __restrict__ PU = gp<R>(D.PU);
@@ -922,12 +922,12 @@ __global__ __launch_bounds__(NTHR) void k_transfer_ym(const Dom* __restrict__ do
   const int nx = D.nx, ny = D.ny, px = D.px, bcx = D.bc[0], bcy = D.bc[1];
   const int x0 = t.y, ya = t.z, yb = t.w;
   const int w = min(TX, nx - x0);
-  GLOBAL const R* __restrict__ phi_old = gp<const R>(D.phi[tri(n_phi(D, k - 1))]);
-  GLOBAL const R* __restrict__ phi_new = gp<const R>(D.phi[tri(n_phi(D, k))]);
+  GLOBAL const R* __restrict__ phi_old = gp<const R>(D.phi[qb(n_phi(D, k - 1))]);
+  GLOBAL const R* __restrict__ phi_new = gp<const R>(D.phi[qb(n_phi(D, k))]);
   const unsigned nU = (D.accum ? 0u : (k - 1) / D.N_phi) + (k - 1) / D.N_U;
   const bool hasU = D.has_U, hasT = D.has_T, accum = D.accum;
-  GLOBAL const R* __restrict__ Uin = hasU ? gp<const R>(D.U[par(nU)]) : nullptr;
-  GLOBAL R* __restrict__ Uout = hasU ? gp<R>(D.U[par(nU + 1)]) : nullptr;
+  GLOBAL const R* __restrict__ Uin = hasU ? gp<const R>(D.U[qb(nU)]) : nullptr;
+  GLOBAL R* __restrict__ Uout = hasU ? gp<R>(D.U[qb(nU + 1)]) : nullptr;
   GLOBAL R* __restrict__ Tout = hasT ? gp<R>(D.T[par(n_T(D, k - 1) + 1)]) : nullptr;
   GLOBAL R* __restrict__ PU = gp<R>(D.PU);
   GLOBAL R* __restrict__ PT = gp<R>(D.PT);
@@ -1065,8 +1065,8 @@ __global__ __launch_bounds__(NTHR) void k_transfer_ym(const Dom* __restrict__ do
 // collision uses them, and writes them on the tile.  Only loads and the
 // cheap transfer arithmetic are repeated on the rings, no collisions, and
 // the transfer's own launch disappears.  D2Q5, instantaneous coupling.
-// The transfer's old phase field phi^{k-2}, read on two rings, sits in the
-// buffer that this step's output does not use (three phase buffers), so
+// The transfer's old phase field phi^{k-2}, read on two rings, sits in a
+// buffer that this step's output does not use (four phase buffers), so
 // neighbouring blocks never overwrite it.  Bitwise identical to the two
 // separate kernels.
 template <class R, class S, int TY>
@@ -1095,16 +1095,16 @@ __global__ __launch_bounds__(NTHR) void k_dtr_phase(const Dom* __restrict__ doms
   const bool wx = bcx != BC_PER, wy = bcy != BC_PER;
   const unsigned kt = k - 1;   // the transfer's step
   // transfer of step kt: phi^{kt-1} -> phi^{kt}; U, T of before -> after
-  GLOBAL const R* __restrict__ phi_old = gp<const R>(D.phi[tri(n_phi(D, kt - 1))]);
+  GLOBAL const R* __restrict__ phi_old = gp<const R>(D.phi[qb(n_phi(D, kt - 1))]);
   const unsigned np = n_phi(D, kt);
   const int ib = par(np), ob = ib ^ 1;
-  GLOBAL const R* __restrict__ phi_in = gp<const R>(D.phi[tri(np)]);   // phi^{kt}: the transfer's new, the phase's input
-  GLOBAL R* __restrict__ phi_out = gp<R>(D.phi[tri(np + 1)]);
+  GLOBAL const R* __restrict__ phi_in = gp<const R>(D.phi[qb(np)]);   // phi^{kt}: the transfer's new, the phase's input
+  GLOBAL R* __restrict__ phi_out = gp<R>(D.phi[qb(np + 1)]);
   GLOBAL const S* __restrict__ s_in = gp<const S>(D.sphi[ib]);
   GLOBAL S* __restrict__ s_out = gp<S>(D.sphi[ob]);
   const unsigned nU = (kt - 1) / D.N_phi + (kt - 1) / D.N_U;
-  GLOBAL const R* __restrict__ Uin = D.has_U ? gp<const R>(D.U[par(nU)]) : nullptr;
-  GLOBAL R* __restrict__ Uout = D.has_U ? gp<R>(D.U[par(nU + 1)]) : nullptr;
+  GLOBAL const R* __restrict__ Uin = D.has_U ? gp<const R>(D.U[qb(nU)]) : nullptr;
+  GLOBAL R* __restrict__ Uout = D.has_U ? gp<R>(D.U[qb(nU + 1)]) : nullptr;
   GLOBAL const R* __restrict__ Tin = D.has_T ? gp<const R>(D.T[par(n_T(D, kt - 1))]) : nullptr;
   GLOBAL R* __restrict__ Tout = D.has_T ? gp<R>(D.T[par(n_T(D, kt - 1) + 1)]) : nullptr;
   const PhaseConst<R> c = phase_const<R>(D);
@@ -1338,13 +1338,13 @@ __global__ __launch_bounds__(NTHR) void k_phase_tr(const Dom* __restrict__ doms,
   const bool wx = bcx != BC_PER, wy = bcy != BC_PER;
   const unsigned np = n_phi(D, k - 1);
   const int ib = par(np), ob = ib ^ 1;
-  GLOBAL const R* __restrict__ phi_in = gp<const R>(D.phi[tri(np)]);
-  GLOBAL R* __restrict__ phi_out = gp<R>(D.phi[tri(np + 1)]);
+  GLOBAL const R* __restrict__ phi_in = gp<const R>(D.phi[qb(np)]);
+  GLOBAL R* __restrict__ phi_out = gp<R>(D.phi[qb(np + 1)]);
   GLOBAL const S* __restrict__ s_in = gp<const S>(D.sphi[ib]);
   GLOBAL S* __restrict__ s_out = gp<S>(D.sphi[ob]);
   const unsigned nU = (D.accum ? 0u : (k - 1) / D.N_phi) + (k - 1) / D.N_U;
-  GLOBAL const R* __restrict__ Up = D.has_U ? gp<const R>(D.U[par(nU)]) : nullptr;
-  GLOBAL R* __restrict__ Uout = D.has_U ? gp<R>(D.U[par(nU + 1)]) : nullptr;
+  GLOBAL const R* __restrict__ Up = D.has_U ? gp<const R>(D.U[qb(nU)]) : nullptr;
+  GLOBAL R* __restrict__ Uout = D.has_U ? gp<R>(D.U[qb(nU + 1)]) : nullptr;
   GLOBAL const R* __restrict__ Tin = D.has_T ? gp<const R>(D.T[par(n_T(D, k - 1))]) : nullptr;
   GLOBAL R* __restrict__ Tout = D.has_T ? gp<R>(D.T[par(n_T(D, k - 1) + 1)]) : nullptr;
   GLOBAL R* __restrict__ PU = gp<R>(D.PU);
@@ -1587,8 +1587,8 @@ __global__ __launch_bounds__(NTHR) void k_scalar(const Dom* __restrict__ doms, c
   GLOBAL R* __restrict__ pend;
   if (FIELD == 0) {
     const unsigned nU = (D.accum ? 0u : k / D.N_phi) + (k - 1) / D.N_U;
-    cin = gp<const R>(D.U[par(nU)]);
-    cout = gp<R>(D.U[par(nU + 1)]);
+    cin = gp<const R>(D.U[qb(nU)]);
+    cout = gp<R>(D.U[qb(nU + 1)]);
     jin = gp<const S>(D.jU[par(n_jU(D, k - 1))]);
     jout = gp<S>(D.jU[par(n_jU(D, k))]);
     pend = gp<R>(D.PU);
@@ -1599,7 +1599,7 @@ __global__ __launch_bounds__(NTHR) void k_scalar(const Dom* __restrict__ doms, c
     jout = gp<S>(D.jT[par(n_jT(D, k))]);
     pend = gp<R>(D.PT);
   }
-  GLOBAL const R* __restrict__ phis = gp<const R>(D.phi[tri(n_phi(D, k))]);
+  GLOBAL const R* __restrict__ phis = gp<const R>(D.phi[qb(n_phi(D, k))]);
   // velocity of the latest flow update (the flow of step k runs after U, T)
   GLOBAL const R* __restrict__ vel = D.has_F ? gp<const R>(D.vel[par(n_F(D, k - 1))]) : nullptr;
   const bool need_phi = FIELD == 0 || D.T_var;
@@ -1755,6 +1755,239 @@ __global__ __launch_bounds__(NTHR) void k_scalar(const Dom* __restrict__ doms, c
   }
 }
 
+// =================================================================== transfer + U transport
+// The transfer of phase step k fused into the U transport of the same step
+// (the U update is due at k): the transport's collisions need the
+// transferred U* on the tile plus one ring, so, as in the deferred-transfer
+// phase kernel, the block reads phi^k on the tile plus three rings and
+// phi^{k-1}, U on two rings, computes J on two rings and U* (and T* on the
+// owned sites) itself, then collides and streams U.  U* is not written: its
+// only reader is this transport, and the transported U goes to the buffer
+// after it.  The U planes have four buffers, so the U before the transfer,
+// read on the rings, is never the buffer neighbouring blocks write.  D2Q5,
+// instantaneous coupling.  Bitwise identical to the two separate kernels.
+template <class R, class S, int TY>
+__global__ __launch_bounds__(NTHR) void k_dtr_scalar(const Dom* __restrict__ doms, const int4* __restrict__ tiles,
+                                                      unsigned k, Partial* __restrict__ part) {
+  using Lq = Lat2<5>;
+  constexpr int W3 = TX + 6, H3 = TY + 6;   // phi^k box
+  constexpr int W2 = TX + 4, H2 = TY + 4;   // J
+  constexpr int W1 = TX + 2, H1 = TY + 2;   // U* and the transport collisions
+  constexpr int N3 = W3 * H3, N2 = W2 * H2, N1 = W1 * H1;
+  constexpr int C2 = (N2 + NTHR - 1) / NTHR;
+  constexpr int RPT = TY / BY, NS = RPT + 1;
+  __shared__ R sq[N3];
+  __shared__ R sJx[N2], sJy[N2];
+  __shared__ R sC[N1], sP[N1], sKx[N1], sKy[N1];
+  __shared__ R red[NTHR / 64];
+
+  const int4 t = tiles[blockIdx.x];
+  if (t.x < 0) return;
+  const Dom& D = doms[t.x];
+  if (k % D.N_U) return;
+  const int nx = D.nx, ny = D.ny;
+  const int px = D.px, pl = (int)D.plane;
+  const int x0 = t.y, y0 = t.z;
+  const int w = min(TX, nx - x0), h = min(TY, ny - y0);
+  const int bcx = D.bc[0], bcy = D.bc[1];
+  const bool wx = bcx != BC_PER, wy = bcy != BC_PER;
+  // transfer of step k: phi^{k-1} -> phi^k, U -> U*; then U* -> the transported U
+  GLOBAL const R* __restrict__ phi_old = gp<const R>(D.phi[qb(n_phi(D, k - 1))]);
+  GLOBAL const R* __restrict__ phi_new = gp<const R>(D.phi[qb(n_phi(D, k))]);
+  const unsigned nU = (k - 1) / D.N_phi + (k - 1) / D.N_U;
+  GLOBAL const R* __restrict__ Uin = gp<const R>(D.U[qb(nU)]);
+  GLOBAL R* __restrict__ Uout = gp<R>(D.U[qb(nU + 2)]);
+  GLOBAL const R* __restrict__ Tin = D.has_T ? gp<const R>(D.T[par(n_T(D, k - 1))]) : nullptr;
+  GLOBAL R* __restrict__ Tout = D.has_T ? gp<R>(D.T[par(n_T(D, k - 1) + 1)]) : nullptr;
+  GLOBAL const S* __restrict__ jin = gp<const S>(D.jU[par(n_jU(D, k - 1))]);
+  GLOBAL S* __restrict__ jout = gp<S>(D.jU[par(n_jU(D, k))]);
+  GLOBAL const R* __restrict__ vel = D.has_F ? gp<const R>(D.vel[par(n_F(D, k - 1))]) : nullptr;
+  const R Uref = kc<R>(D, K_U0);
+  const R omk = kc<R>(D, K_OMK), opk = kc<R>(D, K_OPK);
+  const R cJ = kc<R>(D, K_CJ), cT = kc<R>(D, K_CT);
+  const R rcS = kc<R>(D, K_RCS), rcL = kc<R>(D, K_RCL);
+  const R dt = kc<R>(D, K_DTU);
+  const R DS = kc<R>(D, K_DS), DL = kc<R>(D, K_DL);
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
+  // raw coordinate -> position of the node whose values it takes in a
+  // region of ring r (walls clamp, periodic axes keep the raw position)
+  auto posx = [&](int g, int r) { return (wx ? min(max(g, 0), nx - 1) : g) - (x0 - r); };
+  auto posy = [&](int g, int r) { return (wy ? min(max(g, 0), ny - 1) : g) - (y0 - r); };
+
+  // ---- loads: phi^k box; J inputs on ring 2; transfer and transport inputs
+  // at the collision cells (RPT owned sites, then at most one ring cell)
+  for (int i = tid; i < N3; i += NTHR)
+    sq[i] = ldo(phi_new, (unsigned)(ghost(y0 - 3 + i / W3, ny, bcy) * px + ghost(x0 - 3 + i % W3, nx, bcx)));
+  R jpo[C2], jU[C2];
+#pragma unroll
+  for (int j = 0; j < C2; ++j) {
+    const int i = tid + j * NTHR;
+    if (i >= N2) continue;
+    const unsigned o = (unsigned)(ghost(y0 - 2 + i / W2, ny, bcy) * px + ghost(x0 - 2 + i % W2, nx, bcx));
+    jpo[j] = ldo(phi_old, o);
+    jU[j] = ldo(Uin, o);
+  }
+  int cl[NS], bq[NS], ji[NS];
+  unsigned oc[NS];
+  R cpo[NS], cU[NS], jxv[NS], jyv[NS], uxv[NS], uyv[NS], cT_[RPT];
+#pragma unroll
+  for (int r = 0; r < NS; ++r) {
+    int lx, ly, gx, gy;
+    cl[r] = -1;
+    if (r < RPT) {
+      lx = tx + 1;
+      ly = ty + r * BY + 1;
+      if (tx >= w || ly > h) continue;
+      gx = x0 + tx;
+      gy = y0 + ly - 1;
+    } else {
+      if (!ring_cell(tid, w, h, lx, ly)) continue;
+      gx = resolve(x0 - 1 + lx, nx, bcx);
+      gy = resolve(y0 - 1 + ly, ny, bcy);
+      if (gx < 0 || gy < 0) continue;   // beyond a wall: never pulled from
+    }
+    cl[r] = ly * W1 + lx;
+    bq[r] = (ly + 2) * W3 + lx + 2;
+    ji[r] = (ly + 1) * W2 + lx + 1;
+    const unsigned o = (unsigned)(gy * px + gx);
+    oc[r] = o;
+    cpo[r] = ldo(phi_old, o);
+    cU[r] = ldo(Uin, o);
+    jxv[r] = ldo(jin, o);
+    jyv[r] = ldo(plane(jin, pl), o);
+    uxv[r] = vel ? ldo(vel, o) : R(0);
+    uyv[r] = vel ? ldo(plane(vel, pl), o) : R(0);
+    if (r < RPT && Tin) cT_[r] = ldo(Tin, o);
+  }
+  __syncthreads();
+
+  // ---- J of step k on ring 2 (beyond a wall: the clamped node's J with its
+  // normal component negated), as the transfer kernel computes it
+#pragma unroll
+  for (int j = 0; j < C2; ++j) {
+    const int i = tid + j * NTHR;
+    if (i >= N2) continue;
+    const int gx = x0 - 2 + i % W2, gy = y0 - 2 + i / W2;
+    const bool mx = wx && (gx < 0 || gx >= nx), my = wy && (gy < 0 || gy >= ny);
+    const R* b = &sq[(posy(gy, 3)) * W3 + posx(gx, 3)];
+    R gxv, gyv;
+    iso_grad(b, W3, gxv, gyv);
+    const R gg = gxv * gxv + gyv * gyv;
+    R Jx = R(0), Jy = R(0);
+    if (gg >= R(GRAD_EPS2)) {
+      const R ig = rsq(gg);
+      const R a = cJ * (R(1) + omk * (jU[j] + Uref)) * (b[0] - jpo[j]) * ig;
+      Jx = -a * gxv;
+      Jy = -a * gyv;
+    }
+    sJx[i] = mx ? -Jx : Jx;
+    sJy[i] = my ? -Jy : Jy;
+  }
+  __syncthreads();
+
+  // ---- U* at the collision cells (T* on the owned sites), then the U
+  // collision of Eq. (14) with the transport source, as the transport
+  // kernel computes them
+  R amax = R(0);
+#pragma unroll
+  for (int r = 0; r < NS; ++r) {
+    if (cl[r] < 0) continue;
+    const bool own = r < RPT;
+    const R* b = &sq[bq[r]];
+    const R pn = b[0];
+    const R dphi = pn - cpo[r];
+    const R* jx = &sJx[ji[r]];
+    const R* jy = &sJy[ji[r]];
+    const R div = (jx[1] - jx[-1]) * R(1.0 / 3.0) +
+                  (jx[W2 + 1] - jx[W2 - 1] - jx[-W2 - 1] + jx[-W2 + 1]) * R(1.0 / 12.0) +
+                  (jy[W2] - jy[-W2]) * R(1.0 / 3.0) +
+                  (jy[W2 + 1] + jy[W2 - 1] - jy[-W2 - 1] - jy[-W2 + 1]) * R(1.0 / 12.0);
+    const R dU = ((R(1) + omk * (cU[r] + Uref)) * dphi - R(2) * div) * rcp(opk - omk * pn);
+    const R chi = cU[r] + dU;
+    if (own) {
+      amax = fmax(amax, fabs(dU));
+      if (Tin) {
+        const R rc = (R(1) + pn) * R(0.5) * rcS + (R(1) - pn) * R(0.5) * rcL;
+        const R dT = cT * dphi * rcp(R(2) * rc);
+        sto(Tout, oc[r], cT_[r] + dT);
+      }
+    }
+    const R ca = chi + Uref;
+    const R jex = ca * uxv[r] * dt, jey = ca * uyv[r] * dt;
+    const R phi = pn;
+    const R ikf = rcp(opk - omk * phi);
+    const R coeff = ((R(1) + phi) * DS + (R(1) - phi) * DL) * ikf;
+    const R itau = rcp(R(3) * dt * coeff + R(0.5));
+    const R gcx = -R(3) * itau * (jxv[r] - jex), gcy = -R(3) * itau * (jyv[r] - jey);
+    R gpx, gpy;
+    iso_grad(b, W3, gpx, gpy);
+    const R Qs = -omk * coeff * (gcx * gpx + gcy * gpy) * ikf;
+    const R om = R(1) - itau;
+    sC[cl[r]] = chi;
+    sP[cl[r]] = dt * Qs;
+    sKx[cl[r]] = jex + om * (jxv[r] - jex);
+    sKy[cl[r]] = jey + om * (jyv[r] - jey);
+  }
+  __syncthreads();
+
+  // ---- pull streaming (Eq. 25) of the tile in deviations
+  const bool edge = (wx && (x0 == 0 || x0 + w >= nx)) || (wy && (y0 == 0 || y0 + h >= ny));
+  auto stream = [&](auto edge_c) {
+    constexpr bool EDGE = decltype(edge_c)::value;
+#pragma unroll
+    for (int r = 0; r < RPT; ++r) {
+      if (cl[r] < 0) continue;
+      const int ci = cl[r];
+      const int gx = x0 + tx, gy = y0 + ty + r * BY;
+      const R cy = sC[ci], dPo = sP[ci];
+      R dq[5];
+      dq[0] = dPo * R(Lq::w(0));
+#pragma unroll
+      for (int q = 1; q < 5; ++q) {
+        const int ex = Lq::ex(q), ey = Lq::ey(q);
+        const bool wall = EDGE && ((wx && ((ex > 0 && gx == 0) || (ex < 0 && gx == nx - 1))) ||
+                                   (wy && ((ey > 0 && gy == 0) || (ey < 0 && gy == ny - 1))));
+        if (wall) {
+          dq[q] = dPo * R(Lq::w(q)) - R(Lq::cK) * (R(ex) * sKx[ci] + R(ey) * sKy[ci]);
+        } else {
+          const int si = ci - ey * W1 - ex;
+          dq[q] = (sC[si] - cy + sP[si]) * R(Lq::w(q)) + R(Lq::cK) * (R(ex) * sKx[si] + R(ey) * sKy[si]);
+        }
+      }
+      const unsigned o = oc[r];
+      R sum = dq[0];
+#pragma unroll
+      for (int q = 1; q < 5; ++q) sum += dq[q];
+      const R chin = cy + sum;
+      sto(Uout, o, chin);
+      R jx = R(0), jy = R(0);
+#pragma unroll
+      for (int q = 1; q < 5; ++q) {
+        if (Lq::ex(q) > 0) jx += dq[q];
+        if (Lq::ex(q) < 0) jx -= dq[q];
+        if (Lq::ey(q) > 0) jy += dq[q];
+        if (Lq::ey(q) < 0) jy -= dq[q];
+      }
+      sto(jout, o, jx);
+      sto(plane(jout, pl), o, jy);
+    }
+  };
+  if (edge) stream(std::true_type{});
+  else stream(std::false_type{});
+
+  if (part) {
+    for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_down(amax, off, 64));
+    if (tx == 0) red[ty] = amax;
+    __syncthreads();
+    if (tid == 0) {
+      R m = red[0];
+      for (int wv = 1; wv < NTHR / 64; ++wv) m = fmax(m, red[wv]);
+      part[t.w].S_phi = double(m);
+      part[t.w].J_U = double(m);
+    }
+  }
+}
+
 // raw loads of the marching scalar transport for the rows r0 .. r0 + 3:
 // chi, j and the velocity at the column and ring cells (beyond a wall: no
 // cell), the phase field rows r0 + 1 .. r0 + 4, and the own pending
@@ -1835,8 +2068,8 @@ __global__ __launch_bounds__(NTHR) void k_scalar_ym(const Dom* __restrict__ doms
   GLOBAL R* __restrict__ pend;
   if (FIELD == 0) {
     const unsigned nU = (D.accum ? 0u : k / D.N_phi) + (k - 1) / D.N_U;
-    cin = gp<const R>(D.U[par(nU)]);
-    cout = gp<R>(D.U[par(nU + 1)]);
+    cin = gp<const R>(D.U[qb(nU)]);
+    cout = gp<R>(D.U[qb(nU + 1)]);
     jin = gp<const SR>(D.jU[par(n_jU(D, k - 1))]);
     jout = gp<S>(D.jU[par(n_jU(D, k))]);
     pend = gp<R>(D.PU);
@@ -1847,7 +2080,7 @@ __global__ __launch_bounds__(NTHR) void k_scalar_ym(const Dom* __restrict__ doms
     jout = gp<S>(D.jT[par(n_jT(D, k))]);
     pend = gp<R>(D.PT);
   }
-  GLOBAL const R* __restrict__ phis = gp<const R>(D.phi[tri(n_phi(D, k))]);
+  GLOBAL const R* __restrict__ phis = gp<const R>(D.phi[qb(n_phi(D, k))]);
   GLOBAL const R* __restrict__ vel = D.has_F ? gp<const R>(D.vel[par(n_F(D, k - 1))]) : nullptr;
   const bool need_phi = FIELD == 0 || D.T_var;
   const bool accum = D.accum;
@@ -2114,7 +2347,7 @@ __global__ __launch_bounds__(NTHR) void k_flow(const Dom* __restrict__ doms, con
   GLOBAL const S* __restrict__ s_in = gp<const S>(D.sF[par(n_F(D, k - 1))]);
   GLOBAL S* __restrict__ s_out = gp<S>(D.sF[par(n_F(D, k))]);
   GLOBAL R* __restrict__ vel = gp<R>(D.vel[par(n_F(D, k))]);
-  GLOBAL const R* __restrict__ phis = gp<const R>(D.phi[tri(n_phi(D, k))]);
+  GLOBAL const R* __restrict__ phis = gp<const R>(D.phi[qb(n_phi(D, k))]);
   const R dt = R(D.N_F * D.dt_base);
   const R Fx = R(D.Fx), Fy = R(D.Fy);
   const R snu = R(1.0 / (3.0 * D.N_F * D.dt_base * D.nu + 0.5));
@@ -2240,7 +2473,7 @@ __global__ void k_init(const Dom* __restrict__ doms, int dom, const double* __re
     }
   }
   const R ph = R(phi);
-  for (int b = 0; b < 3; ++b) (gp<R>(D.phi[b]))[o] = ph;
+  for (int b = 0; b < 4; ++b) (gp<R>(D.phi[b]))[o] = ph;
   for (int q = 0; q < D.qs - 1; ++q) {
     st(gp<S>(D.sphi[0]), o + q * pl, R(0));
     st(gp<S>(D.sphi[1]), o + q * pl, R(0));
@@ -2248,8 +2481,8 @@ __global__ void k_init(const Dom* __restrict__ doms, int dom, const double* __re
   const double ux = (D.has_F && D.u0_liquid) ? D.u_in * (1.0 - double(ph)) * 0.5 : 0.0;
   if (D.has_U) {
     const double dtU = D.N_U * D.dt_base;
+    for (int b = 0; b < 4; ++b) (gp<R>(D.U[b]))[o] = R(0);    // U - U0
     for (int b = 0; b < 2; ++b) {
-      (gp<R>(D.U[b]))[o] = R(0);    // U - U0
       st(gp<S>(D.jU[b]), o, R(D.U0 * ux * dtU));
       st(gp<S>(D.jU[b]), o + pl, R(0));
     }
@@ -2290,10 +2523,10 @@ template <class R, class S>
 __device__ double read_plane(const Dom& D, long long k, int code, long long o) {
   const long long pl = D.plane;
   switch (code) {
-    case 0: return double((gp<const R>(D.phi[tri(n_phi(D, k))]))[o]);
-    case 1: return double((gp<const R>(D.U[par(n_U(D, k))]))[o]) + D.U0;
+    case 0: return double((gp<const R>(D.phi[qb(n_phi(D, k))]))[o]);
+    case 1: return double((gp<const R>(D.U[qb(n_U(D, k))]))[o]) + D.U0;
     case 2: return double((gp<const R>(D.T[par(n_T(D, k))]))[o]) + D.T0;
-    case 8: return double((gp<const R>(D.U[par(n_U(D, k))]))[o]);
+    case 8: return double((gp<const R>(D.U[qb(n_U(D, k))]))[o]);
     case 9: return double((gp<const R>(D.T[par(n_T(D, k))]))[o]);
     case 3: return double((gp<const R>(D.rho[par(n_F(D, k))]))[o]);
     case 4: return double((gp<const R>(D.vel[par(n_F(D, k))]))[o]);
@@ -2309,7 +2542,7 @@ __device__ double read_plane(const Dom& D, long long k, int code, long long o) {
   if (code >= 70 && code <= 77) return double(ld(gp<const S>(D.sF[par(n_F(D, k))]), o + (code - 70) * pl));
   if (code >= 10 && code < 10 + D.qs) {
     const int b = par(n_phi(D, k));
-    GLOBAL const R* ph = gp<const R>(D.phi[tri(n_phi(D, k))]);
+    GLOBAL const R* ph = gp<const R>(D.phi[qb(n_phi(D, k))]);
     GLOBAL const S* s = gp<const S>(D.sphi[b]);
     const R phi = ph[o];
     const bool q9 = D.qs == 9;
@@ -2370,10 +2603,10 @@ __global__ void k_write(const Dom* __restrict__ doms, int dom, long long k, cons
     const int code = codes[c];
     const double v = src[c * n + i];
     switch (code) {
-      case 0: (gp<R>(D.phi[tri(n_phi(D, k))]))[o] = R(v); break;
-      case 1: (gp<R>(D.U[par(n_U(D, k))]))[o] = R(v - D.U0); break;
+      case 0: (gp<R>(D.phi[qb(n_phi(D, k))]))[o] = R(v); break;
+      case 1: (gp<R>(D.U[qb(n_U(D, k))]))[o] = R(v - D.U0); break;
       case 2: (gp<R>(D.T[par(n_T(D, k))]))[o] = R(v - D.T0); break;
-      case 8: (gp<R>(D.U[par(n_U(D, k))]))[o] = R(v); break;
+      case 8: (gp<R>(D.U[qb(n_U(D, k))]))[o] = R(v); break;
       case 9: (gp<R>(D.T[par(n_T(D, k))]))[o] = R(v); break;
       case 3: (gp<R>(D.rho[par(n_F(D, k))]))[o] = R(v); break;
       case 4: (gp<R>(D.vel[par(n_F(D, k))]))[o] = R(v); break;
@@ -2403,7 +2636,7 @@ __global__ void k_write(const Dom* __restrict__ doms, int dom, long long k, cons
       f[q] = R(src[(cphi + q) * n + i]);
       phi += f[q];
     }
-    (gp<R>(D.phi[tri(n_phi(D, k))]))[o] = phi;
+    (gp<R>(D.phi[qb(n_phi(D, k))]))[o] = phi;
     for (int q = 1; q < D.qs; ++q)
       st(gp<S>(D.sphi[b]), o + (q - 1) * pl, f[q] - phi * R(q9 ? (q <= 4 ? 1.0 / 9.0 : 1.0 / 36.0) : 1.0 / 6.0));
   }
@@ -2435,8 +2668,8 @@ __global__ __launch_bounds__(NTHR) void k_diag_tiles(const Dom* __restrict__ dom
   if (t.x < 0) return;
   const Dom& D = doms[t.x];
   const long long px = D.px;
-  GLOBAL const R* phi = gp<const R>(D.phi[tri(n_phi(D, k))]);
-  GLOBAL const R* U = D.has_U ? gp<const R>(D.U[par(n_U(D, k))]) : nullptr;
+  GLOBAL const R* phi = gp<const R>(D.phi[qb(n_phi(D, k))]);
+  GLOBAL const R* U = D.has_U ? gp<const R>(D.U[qb(n_U(D, k))]) : nullptr;
   GLOBAL const R* T = D.has_T ? gp<const R>(D.T[par(n_T(D, k))]) : nullptr;
   GLOBAL const R* rho = D.has_F ? gp<const R>(D.rho[par(n_F(D, k))]) : nullptr;
   const int tx = threadIdx.x, ty = threadIdx.y;
@@ -2557,7 +2790,7 @@ __global__ void k_tips(const Dom* __restrict__ doms, long long k, DiagOut* __res
     if (threadIdx.x == 0) out[d].tip[s * 4 + ax] = 0.0;
     return;
   }
-  GLOBAL const R* phi = gp<const R>(D.phi[tri(n_phi(D, k))]);
+  GLOBAL const R* phi = gp<const R>(D.phi[qb(n_phi(D, k))]);
   const double ang = atan2(D.sth, D.cth) + ax * 1.5707963267948966;
   const double c = cos(ang), sn = sin(ang);
   const double cx = D.seed[s][0], cy = D.seed[s][1];
@@ -2848,12 +3081,12 @@ __global__ __launch_bounds__(256) void k3z_phase(const Dom* __restrict__ doms, u
   const long long pl = D.plane;
   const unsigned np = n_phi(D, k - 1);
   const int ib = par(np), ob = ib ^ 1;
-  GLOBAL const R* phi = gp<const R>(D.phi[tri(np)]);
+  GLOBAL const R* phi = gp<const R>(D.phi[qb(np)]);
   GLOBAL const SR* sp = gp<const SR>(D.sphi[ib]);
-  GLOBAL R* phi_out = gp<R>(D.phi[tri(np + 1)]);
+  GLOBAL R* phi_out = gp<R>(D.phi[qb(np + 1)]);
   GLOBAL S* s_out = gp<S>(D.sphi[ob]);
   const unsigned nU = (D.accum ? 0u : (k - 1) / D.N_phi) + (k - 1) / D.N_U;
-  GLOBAL const R* Up = D.has_U ? gp<const R>(D.U[par(nU)]) : nullptr;
+  GLOBAL const R* Up = D.has_U ? gp<const R>(D.U[qb(nU)]) : nullptr;
   GLOBAL const R* Tp = D.has_T ? gp<const R>(D.T[par(n_T(D, k - 1))]) : nullptr;
   const PhaseConst<R> pc = phase_const<R>(D);
   const R U0 = kc<R>(D, K_U0), T0 = kc<R>(D, K_T0);
@@ -3031,8 +3264,8 @@ __global__ __launch_bounds__(256) void k3z_scalar(const Dom* __restrict__ doms, 
   GLOBAL R* pend;
   if (FIELD == 0) {
     const unsigned nU = (D.accum ? 0u : k / D.N_phi) + (k - 1) / D.N_U;
-    cin = gp<const R>(D.U[par(nU)]);
-    cout = gp<R>(D.U[par(nU + 1)]);
+    cin = gp<const R>(D.U[qb(nU)]);
+    cout = gp<R>(D.U[qb(nU + 1)]);
     jin = gp<const SR>(D.jU[par(n_jU(D, k - 1))]);
     jout = gp<S>(D.jU[par(n_jU(D, k))]);
     pend = gp<R>(D.PU);
@@ -3043,7 +3276,7 @@ __global__ __launch_bounds__(256) void k3z_scalar(const Dom* __restrict__ doms, 
     jout = gp<S>(D.jT[par(n_jT(D, k))]);
     pend = gp<R>(D.PT);
   }
-  GLOBAL const R* phis = gp<const R>(D.phi[tri(n_phi(D, k))]);
+  GLOBAL const R* phis = gp<const R>(D.phi[qb(n_phi(D, k))]);
   GLOBAL const R* vel = D.has_F ? gp<const R>(D.vel[par(n_F(D, k - 1))]) : nullptr;
   const bool var = FIELD == 0 || D.T_var;
   const bool accum = D.accum;
@@ -3252,12 +3485,12 @@ __global__ __launch_bounds__(256) void k3z_transfer(const Dom* __restrict__ doms
   ZCol c;
   if (!zcol(G, blockIdx.x, zrun, c) || k % D.N_phi) return;
   const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
-  GLOBAL const R* pn = gp<const R>(D.phi[tri(n_phi(D, k))]);
-  GLOBAL const R* po = gp<const R>(D.phi[tri(n_phi(D, k - 1))]);
+  GLOBAL const R* pn = gp<const R>(D.phi[qb(n_phi(D, k))]);
+  GLOBAL const R* po = gp<const R>(D.phi[qb(n_phi(D, k - 1))]);
   const bool hasU = D.has_U, hasT = D.has_T && !D.T_pulled, accum = D.accum;
   const unsigned nU = (D.accum ? 0u : (k - 1) / D.N_phi) + (k - 1) / D.N_U;
-  GLOBAL const R* Uin = hasU ? gp<const R>(D.U[par(nU)]) : nullptr;
-  GLOBAL R* Uout = hasU ? gp<R>(D.U[par(nU + 1)]) : nullptr;
+  GLOBAL const R* Uin = hasU ? gp<const R>(D.U[qb(nU)]) : nullptr;
+  GLOBAL R* Uout = hasU ? gp<R>(D.U[qb(nU + 1)]) : nullptr;
   GLOBAL const R* Tin = hasT ? gp<const R>(D.T[par(n_T(D, k - 1))]) : nullptr;
   GLOBAL R* Tout = hasT ? gp<R>(D.T[par(n_T(D, k - 1) + 1)]) : nullptr;
   GLOBAL R* PU = gp<R>(D.PU);
@@ -3538,7 +3771,7 @@ __global__ __launch_bounds__(256) void k3z_flow(const Dom* __restrict__ doms, un
   const int ib = par(n_F(D, k - 1)), ob = par(n_F(D, k));
   GLOBAL const R* rin = gp<const R>(D.rho[ib]);
   GLOBAL const SR* sp = gp<const SR>(D.sF[ib]);
-  GLOBAL const R* phis = gp<const R>(D.phi[tri(n_phi(D, k))]);
+  GLOBAL const R* phis = gp<const R>(D.phi[qb(n_phi(D, k))]);
   GLOBAL R* rho_out = gp<R>(D.rho[ob]);
   GLOBAL R* vel = gp<R>(D.vel[ob]);
   GLOBAL S* s_out = gp<S>(D.sF[ob]);
@@ -3659,14 +3892,13 @@ __global__ void k3_init(const Dom* __restrict__ doms, const double* __restrict__
   const unsigned pl = (unsigned)D.plane;
   const double off = xi ? xi[(long long)s.y * D.nx + s.x] : 0.0;
   const double phi = tanh((D.z_front + off - s.z) / (1.4142135623730951 * D.W0));
-  for (int b = 0; b < 3; ++b) (gp<R>(D.phi[b]))[s.o] = R(phi);
+  for (int b = 0; b < 4; ++b) (gp<R>(D.phi[b]))[s.o] = R(phi);
   for (int b = 0; b < 2; ++b)
     for (int q = 0; q < 6; ++q) st(gp<S>(D.sphi[b]), s.o + q * pl, R(0));
   if (D.has_U) {
-    for (int b = 0; b < 2; ++b) {
-      (gp<R>(D.U[b]))[s.o] = R(0);   // U - U0
+    for (int b = 0; b < 4; ++b) (gp<R>(D.U[b]))[s.o] = R(0);   // U - U0
+    for (int b = 0; b < 2; ++b)
       for (int a = 0; a < 3; ++a) st(gp<S>(D.jU[b]), s.o + a * pl, R(0));
-    }
     (gp<R>(D.PU))[s.o] = R(0);
   }
   if (D.has_T) {
@@ -3697,10 +3929,10 @@ __global__ void k3_init(const Dom* __restrict__ doms, const double* __restrict__
 template <class R, class S>
 __device__ double read_plane3(const Dom& D, long long k, int code, unsigned o) {
   const unsigned pl = (unsigned)D.plane;
-  if (code == 0) return double((gp<const R>(D.phi[tri(n_phi(D, k))]))[o]);
-  if (code == 1) return double((gp<const R>(D.U[par(n_U(D, k))]))[o]) + D.U0;
+  if (code == 0) return double((gp<const R>(D.phi[qb(n_phi(D, k))]))[o]);
+  if (code == 1) return double((gp<const R>(D.U[qb(n_U(D, k))]))[o]) + D.U0;
   if (code == 2) return double((gp<const R>(D.T[par(n_T(D, k))]))[o]) + D.T0;
-  if (code == 8) return double((gp<const R>(D.U[par(n_U(D, k))]))[o]);
+  if (code == 8) return double((gp<const R>(D.U[qb(n_U(D, k))]))[o]);
   if (code == 9) return double((gp<const R>(D.T[par(n_T(D, k))]))[o]);
   if (code == 3) return double((gp<const R>(D.rho[par(n_F(D, k))]))[o]);
   if (code >= 4 && code <= 6) return double((gp<const R>(D.vel[par(n_F(D, k))]))[o + (code - 4) * pl]);
@@ -3712,7 +3944,7 @@ __device__ double read_plane3(const Dom& D, long long k, int code, unsigned o) {
   if (code >= 70 && code <= 87) return double(ld(gp<const S>(D.sF[par(n_F(D, k))]), o + (code - 70) * pl));
   if (code >= 10 && code <= 16) {
     const int b = par(n_phi(D, k));
-    const R phi = (gp<const R>(D.phi[tri(n_phi(D, k))]))[o];
+    const R phi = (gp<const R>(D.phi[qb(n_phi(D, k))]))[o];
     GLOBAL const S* sp = gp<const S>(D.sphi[b]);
     if (code == 10) {
       R sum = R(0);
@@ -3763,10 +3995,10 @@ __global__ void k3_write(const Dom* __restrict__ doms, long long k, const int* _
   for (int c = 0; c < ncodes; ++c) {
     const int code = codes[c];
     const double v = src[c * n + i];
-    if (code == 0) (gp<R>(D.phi[tri(n_phi(D, k))]))[o] = R(v);
-    else if (code == 1) (gp<R>(D.U[par(n_U(D, k))]))[o] = R(v - D.U0);
+    if (code == 0) (gp<R>(D.phi[qb(n_phi(D, k))]))[o] = R(v);
+    else if (code == 1) (gp<R>(D.U[qb(n_U(D, k))]))[o] = R(v - D.U0);
     else if (code == 2) (gp<R>(D.T[par(n_T(D, k))]))[o] = R(v - D.T0);
-    else if (code == 8) (gp<R>(D.U[par(n_U(D, k))]))[o] = R(v);
+    else if (code == 8) (gp<R>(D.U[qb(n_U(D, k))]))[o] = R(v);
     else if (code == 9) (gp<R>(D.T[par(n_T(D, k))]))[o] = R(v);
     else if (code == 3) (gp<R>(D.rho[par(n_F(D, k))]))[o] = R(v);
     else if (code >= 4 && code <= 6) (gp<R>(D.vel[par(n_F(D, k))]))[o + (code - 4) * pl] = R(v);
@@ -3786,7 +4018,7 @@ __global__ void k3_write(const Dom* __restrict__ doms, long long k, const int* _
       f[q] = R(src[(cphi + q) * n + i]);
       phi += f[q];
     }
-    (gp<R>(D.phi[tri(n_phi(D, k))]))[o] = phi;
+    (gp<R>(D.phi[qb(n_phi(D, k))]))[o] = phi;
     for (int q = 1; q < 7; ++q) st(gp<S>(D.sphi[b]), o + (q - 1) * pl, f[q] - phi * R(0.125));
   }
   if (cflow >= 0) {
@@ -3809,11 +4041,11 @@ __global__ __launch_bounds__(256) void k3_diag(const Dom* __restrict__ doms, lon
   Site3 s;
   double a[5] = {0, 0, 0, 0, 0};
   if (site3(D, blockIdx.x, threadIdx.x, s)) {
-    const double p = double((gp<const R>(D.phi[tri(n_phi(D, k))]))[s.o]);
+    const double p = double((gp<const R>(D.phi[qb(n_phi(D, k))]))[s.o]);
     a[0] = (1.0 + p) * 0.5;
     bool bad = !isfinite(p);
     if (D.has_U) {
-      const double u = double((gp<const R>(D.U[par(n_U(D, k))]))[s.o]) + D.U0;
+      const double u = double((gp<const R>(D.U[qb(n_U(D, k))]))[s.o]) + D.U0;
       a[1] = D.C_inf * ((1.0 + D.kc) - (1.0 - D.kc) * p) * (1.0 + (1.0 - D.kc) * u) * 0.5;
       bad |= !isfinite(u);
     }
@@ -3857,7 +4089,7 @@ __global__ void k3_front(const Dom* __restrict__ doms, long long k, double* __re
   if (col < (long long)D.nx * D.ny) {
     has = true;
     const int x = (int)(col % D.nx), y = (int)(col / D.nx);
-    GLOBAL const R* phi = gp<const R>(D.phi[tri(n_phi(D, k))]);
+    GLOBAL const R* phi = gp<const R>(D.phi[qb(n_phi(D, k))]);
     double prev = double(phi[(long long)y * D.px + x]);
     h = prev < 0 ? 0.0 : double(D.nz - 1);
     if (prev >= 0)
@@ -3980,6 +4212,14 @@ struct Launch {
     else if (TY == 8) k_dtr_phase<R, S, 8><<<g, b, 0, st>>>(d, t, k, p);
     else if (TY == 16) k_dtr_phase<R, S, 16><<<g, b, 0, st>>>(d, t, k, p);
     else k_dtr_phase<R, S, 32><<<g, b, 0, st>>>(d, t, k, p);
+  }
+  // transfer of step k fused into the U transport of step k (D2Q5)
+  static void dtr_scalar(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, unsigned k, Partial* p) {
+    const dim3 b(TX, BY);
+    if (TY == 4) k_dtr_scalar<R, S, 4><<<g, b, 0, st>>>(d, t, k, p);
+    else if (TY == 8) k_dtr_scalar<R, S, 8><<<g, b, 0, st>>>(d, t, k, p);
+    else if (TY == 16) k_dtr_scalar<R, S, 16><<<g, b, 0, st>>>(d, t, k, p);
+    else k_dtr_scalar<R, S, 32><<<g, b, 0, st>>>(d, t, k, p);
   }
   // y-marching scalar transport over a list of column runs
   static void scalar_ym(int field, int Q, dim3 g, hipStream_t st, const Dom* d, const int4* runs, unsigned k,

@@ -4,10 +4,10 @@
 // the per-domain state planes, the device descriptors, the tile lists and the
 // reduction buffers.  Stepping issues, per base step k, the kernels whose
 // field is due (k mod N_chi == 0, Eq. 34) in the order phase, transfer, U, T,
-// flow; whole cycles of 2 * lcm(N_chi) base steps, or three times that
-// (the period after which every buffer index repeats: parities of the
-// double-buffered planes, write counts mod 3 of the phase field), are
-// captured once into a HIP graph and replayed.
+// flow; whole cycles of 2 * lcm(N_chi) base steps, or twice that (the
+// period after which every buffer index repeats: parities of the
+// double-buffered planes, write counts mod 4 of phi and U), are captured
+// once into a HIP graph and replayed.
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
 #include <hip/hip_runtime.h>
@@ -33,6 +33,7 @@ struct Launch {
   static void phase_tr(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, unsigned k, Partial* p);
   static void phase_ym(int Q, dim3 g, hipStream_t st, const Dom* d, const int4* runs, unsigned k);
   static void dtr_phase(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, unsigned k, Partial* p);
+  static void dtr_scalar(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, unsigned k, Partial* p);
   static void transfer_ym(dim3 g, hipStream_t st, const Dom* d, const int4* runs, unsigned k, Partial* p,
                           const int* slot0, int TY);
   static void scalar_ym(int field, int Q, dim3 g, hipStream_t st, const Dom* d, const int4* runs, unsigned k,
@@ -98,6 +99,7 @@ struct Ops {
   int (*phase_tr_rows)(int);
   void (*phase_ym)(int, dim3, hipStream_t, const Dom*, const int4*, unsigned);
   void (*dtr_phase)(int, dim3, hipStream_t, const Dom*, const int4*, unsigned, Partial*);
+  void (*dtr_scalar)(int, dim3, hipStream_t, const Dom*, const int4*, unsigned, Partial*);
   void (*transfer_ym)(dim3, hipStream_t, const Dom*, const int4*, unsigned, Partial*, const int*, int);
   void (*scalar_ym)(int, int, dim3, hipStream_t, const Dom*, const int4*, unsigned, Partial*, const int*, int);
   void (*scalar)(int, int, int, dim3, hipStream_t, const Dom*, const int4*, unsigned, Partial*);
@@ -112,7 +114,7 @@ struct Ops {
 template <class R, class S>
 Ops make_ops() {
   return Ops{Launch<R, S>::phase, Launch<R, S>::transfer, Launch<R, S>::phase_tr, Launch<R, S>::phase_tr_rows,
-             Launch<R, S>::phase_ym, Launch<R, S>::dtr_phase, Launch<R, S>::transfer_ym, Launch<R, S>::scalar_ym, Launch<R, S>::scalar, Launch<R, S>::flow,
+             Launch<R, S>::phase_ym, Launch<R, S>::dtr_phase, Launch<R, S>::dtr_scalar, Launch<R, S>::transfer_ym, Launch<R, S>::scalar_ym, Launch<R, S>::scalar, Launch<R, S>::flow,
              Launch<R, S>::diag_tiles, Launch<R, S>::tips, Launch<R, S>::init, Launch<R, S>::read,
              Launch<R, S>::write};
 }
@@ -182,6 +184,7 @@ struct lbm_ctx {
   bool defer = true;      // defer a phase step's transfer into the next phase kernel where allowed
   bool deferrable = false;// D2Q5, one phase group with N_phi = 1, instantaneous coupling, domains >= 8 x 8
   bool pending = false;   // the last launched step's transfer is deferred
+  bool one_U = false;     // every domain has U, all in one update group
   bool march_big = false; // the phase groups hold enough column runs to fill the chip
   bool marchable = false; // every domain 2D and at least 16 x 16 (the marching windows wrap once at most)
   int qs = 5;             // scalar lattice of the (2D) context: 5 or 9
@@ -220,9 +223,9 @@ struct Layout {
 Layout layout_of(const lbm_params& p) {
   Layout L;
   const int d = p.dim;
-  L.rplanes = 3;                           // phi, three buffers
+  L.rplanes = 4;                           // phi, four buffers
   L.splanes = 2 * (p.q_scalar - 1);        // phase s_i, two buffers
-  if (p.has_U) { L.rplanes += 3; L.splanes += 2 * d; }
+  if (p.has_U) { L.rplanes += 5; L.splanes += 2 * d; }   // U (four buffers), pending U
   if (p.has_T) { L.rplanes += 3; L.splanes += 2 * d; }
   if (p.has_flow) { L.rplanes += 2 + 2 * d; L.splanes += 2 * (d == 3 ? 18 : 8); }
   return L;
@@ -355,6 +358,14 @@ static bool defers(const lbm_ctx* c, unsigned k) {
   return true;
 }
 
+// Whether the transfer of phase step k runs inside the U transport of step
+// k: the U update is due at k, every domain has U in one update group, and
+// the context allows deferred transfers.
+static bool fuses_U(const lbm_ctx* c, unsigned k) {
+  if (!(c->defer && c->deferrable && c->one_U && !c->fuse && !use_march(c))) return false;
+  return k % c->g_U[0].N == 0;
+}
+
 static void launch_step(lbm_ctx* c, hipStream_t st, unsigned k, bool last = false) {
   if (c->dim == 3) {
     c->ops3.step(c->H[0], st, c->d_dom, k, c->d_part);
@@ -377,7 +388,8 @@ static void launch_step(lbm_ctx* c, hipStream_t st, unsigned k, bool last = fals
           else
             c->ops.phase(TY, c->qs, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k);
           c->pending = !last && defers(c, k);
-          if (!c->pending) c->ops.transfer(TY, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k, c->d_part);
+          if (!c->pending && !fuses_U(c, k))   // else in the phase kernel of step k + 1 or the U transport
+            c->ops.transfer(TY, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k, c->d_part);
         }
       }
     }
@@ -385,7 +397,12 @@ static void launch_step(lbm_ctx* c, hipStream_t st, unsigned k, bool last = fals
   // (the U transport stays tiled: marching it measured slower on the
   // batched ensemble, 248 against 236 us per launch)
   for (auto& g : c->g_U)
-    if (k % g.N == 0) c->ops.scalar(0, TY, c->qs, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k, c->d_part);
+    if (k % g.N == 0) {
+      if (fuses_U(c, k))   // carrying this step's transfer
+        c->ops.dtr_scalar(TY, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k, c->d_part);
+      else
+        c->ops.scalar(0, TY, c->qs, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k, c->d_part);
+    }
   for (auto& g : c->g_T)
     if (k % g.N == 0) {
       if (march) c->ops.scalar_ym(1, c->qs, dim3(g.runs.n), st, c->d_dom, g.runs.d, k, c->d_part, c->d_slot0[ti], TY);
@@ -507,7 +524,7 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
     if (!m.empty()) return fail(nullptr, LBM_EINVAL, m);
   }
   {
-    // the step kernels index the cycle of (up to) 6 lcm(N_chi) base steps
+    // the step kernels index the cycle of (up to) 4 lcm(N_chi) base steps
     // and a plane's elements in 32 bits
     long long lcm = 1;
     for (int i = 0; i < n; ++i) {
@@ -663,13 +680,11 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
     }
     const size_t pr = D.plane * c->rsz, ps = D.plane * c->ssz;
     const int d3 = q.dim == 3;
-    for (int b = 0; b < 3; ++b) D.phi[b] = take(pr);
+    for (int b = 0; b < 4; ++b) D.phi[b] = take(pr);
     for (int b = 0; b < 2; ++b) D.sphi[b] = take(align256(ps) * (q.q_scalar - 1));
     if (q.has_U) {
-      for (int b = 0; b < 2; ++b) {
-        D.U[b] = take(pr);
-        D.jU[b] = take(align256(ps) * q.dim);
-      }
+      for (int b = 0; b < 4; ++b) D.U[b] = take(pr);
+      for (int b = 0; b < 2; ++b) D.jU[b] = take(align256(ps) * q.dim);
       D.PU = take(pr);
     }
     if (q.has_T) {
@@ -704,10 +719,17 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
     for (int i = 0; i < n; ++i) runs += (long long)((p[i].nx + 63) / 64) * ((p[i].ny + kYRun - 1) / kYRun);
     c->march_big = runs >= 4 * 256;
   }
-  // the phase field's buffer index (its write count mod 3) repeats too
+  // the buffer indices of phi and U (write counts mod 4) repeat too; both
+  // counts are even over 2 lcm, so doubling once makes them multiples of 4
   c->cycle = 2 * lcm;
-  for (int i = 0; i < n; ++i)
-    if ((c->cycle / p[i].N_phi) % 3 != 0) c->cycle *= 3;
+  for (int i = 0; i < n; ++i) {
+    const long long wphi = c->cycle / p[i].N_phi;
+    const long long wU = p[i].has_U ? (p[i].coupling == LBM_COUPLE_INSTANT ? wphi : 0) + c->cycle / p[i].N_U : 0;
+    if (wphi % 4 != 0 || wU % 4 != 0) {
+      c->cycle *= 2;
+      break;
+    }
+  }
   c->d_dom = (Dom*)take(sizeof(Dom) * n);
 
   // tile lists (three tile heights), groups by update factor
@@ -805,6 +827,8 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
       return fail(nullptr, LBM_EINVAL, "too many distinct update factors for one field (max 8)");
     }
   }
+  c->one_U = c->g_U.size() == 1;
+  for (int i = 0; i < n; ++i) c->one_U &= p[i].has_U != 0;
   c->d_part = (Partial*)take(sizeof(Partial) * (size_t)tilesmax);
   c->d_slot = (int*)take(sizeof(int) * (size_t)tilesmax);
   for (int ti = 0; ti < kNTY; ++ti) c->d_slot0[ti] = (int*)take(sizeof(int) * (n + 1));
@@ -1003,12 +1027,27 @@ lbm_status lbm_kernel_times(lbm_ctx* c, int32_t reps, double* ms_out, double* pe
     if (per_step) per_step[kind] = weighted / all;
   }
   // deferred transfers: the phase kernel with the previous step's transfer
-  // runs instead of the plain one on the steps after a deferral
-  ms_out[5] = -1.0;
-  if (per_step) per_step[5] = 0.0;
+  // runs instead of the plain one on the steps after a deferral, and the U
+  // transport with its step's transfer instead of the plain one
+  auto time_launch = [&](auto launch, double& out) -> lbm_status {
+    launch();
+    HIPCHK(c, hipEventRecord(e0, c->stream));
+    for (int r = 0; r < reps; ++r) launch();
+    HIPCHK(c, hipEventRecord(e1, c->stream));
+    HIPCHK(c, hipEventSynchronize(e1));
+    float ms = 0;
+    HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
+    out = double(ms) / reps;
+    return LBM_OK;
+  };
+  ms_out[5] = ms_out[6] = -1.0;
+  if (per_step) per_step[5] = per_step[6] = 0.0;
   if (c->dim == 2 && !fused) {
-    long long ndef = 0;
-    for (long long kk = 1; kk < c->cycle; ++kk) ndef += defers(c, (unsigned)kk);
+    long long ndef = 0, nfu = 0;
+    for (long long kk = 1; kk <= c->cycle; ++kk) {
+      ndef += kk < c->cycle && defers(c, (unsigned)kk);
+      nfu += fuses_U(c, (unsigned)kk);
+    }
     if (ndef > 0) {
       const double fdef = double(ndef) / double(c->cycle);
       if (per_step) {
@@ -1017,15 +1056,23 @@ lbm_status lbm_kernel_times(lbm_ctx* c, int32_t reps, double* ms_out, double* pe
         per_step[5] = fdef;
       }
       const Group& g = c->g_phi[0];
-      auto launch = [&]() { c->ops.dtr_phase(TY, dim3(g.ts[ti].n), c->stream, c->d_dom, g.ts[ti].d, 2u, c->d_part); };
-      launch();
-      HIPCHK(c, hipEventRecord(e0, c->stream));
-      for (int r = 0; r < reps; ++r) launch();
-      HIPCHK(c, hipEventRecord(e1, c->stream));
-      HIPCHK(c, hipEventSynchronize(e1));
-      float ms = 0;
-      HIPCHK(c, hipEventElapsedTime(&ms, e0, e1));
-      ms_out[5] = double(ms) / reps;
+      lbm_status s = time_launch(
+          [&]() { c->ops.dtr_phase(TY, dim3(g.ts[ti].n), c->stream, c->d_dom, g.ts[ti].d, 2u, c->d_part); },
+          ms_out[5]);
+      if (s != LBM_OK) return s;
+    }
+    if (nfu > 0) {   // (every phase step is due: N_phi = 1)
+      if (per_step) {
+        per_step[1] -= double(nfu) / double(c->cycle);
+        per_step[2] = 0.0;
+        per_step[6] = double(nfu) / double(c->cycle);
+      }
+      const Group& g = c->g_U[0];
+      const unsigned k = cycle_step(c, due(g.N));
+      lbm_status s = time_launch(
+          [&]() { c->ops.dtr_scalar(TY, dim3(g.ts[ti].n), c->stream, c->d_dom, g.ts[ti].d, k, c->d_part); },
+          ms_out[6]);
+      if (s != LBM_OK) return s;
     }
   }
   HIPCHK(c, hipEventDestroy(e0));

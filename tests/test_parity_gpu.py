@@ -174,11 +174,14 @@ def test_tile_shapes_graph_and_fusion_are_bitwise_identical(storage):
                 assert np.array_equal(got[n], ref[n]), (rows, g, fuse, march, n)
 
 
-@pytest.mark.parametrize("storage,case", [("f64", "solutal"), ("f32", "solutal"), ("f64", "thermosolutal")])
+@pytest.mark.parametrize("storage,case", [("f64", "solutal"), ("f32", "solutal"), ("f64", "thermosolutal"),
+                                          ("f32", "flow")])
 def test_deferred_transfer_is_bitwise_identical(storage, case):
     """The transfer of a phase step with no transport after it (3 of 4 in
     the solutal case, N_U = 4; 2 of 3 with U and T at N = 3 and latent
-    heat) runs inside the next phase kernel.  Against the separate kernels:
+    heat) runs inside the next phase kernel, and the transfer of a step at
+    which U is due inside that U transport (every step with flow, N_U = 1,
+    where the transport takes the velocity).  Against the separate kernels:
     the same state bit for bit and the same S_phi and J_U, over tile
     heights, graph replay or direct launches, and calls that end inside a
     multirate cycle (5 + 3 + 59 steps)."""
@@ -187,10 +190,14 @@ def test_deferred_transfer_is_bitwise_identical(storage, case):
     if case == "solutal":
         wl = L.reduced(L.solutal_512(), 130, 75)
         names = ("phi", "U", "f_phi", "jU")
-    else:
+    elif case == "thermosolutal":
         wl = L.reduced(L.thermosolutal_flow_1024(), 130, 75)
         wl["domains"][0].update(has_flow=False, N_U=3, N_T=3, tau0=40.0)
         names = ("phi", "U", "T", "f_phi", "jU", "jT")
+    else:
+        wl = L.reduced(L.thermosolutal_flow_1024(), 130, 75)
+        wl["domains"][0].update(tau0=40.0)
+        names = ("phi", "U", "T", "vel", "f_phi", "jU", "jT")
     ref = None
     for rows, g, defer in [(r, g, d) for r in (4, 16) for g in (True, False) for d in (False, True)]:
         _say(f"case deferred transfer {storage} rows={rows} graph={g} defer={defer}")
