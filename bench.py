@@ -175,6 +175,7 @@ def measure(sim, wl: dict, storage: str, steps: int, warmup: int) -> dict:
     # per-kernel launch times (HIP events on the library's stream)
     marching = sim.marching
     kt = sim.kernel_times(reps=200)
+    rows = sim.tile_rows
     sim.close()
     d0 = wl["domains"][0]
     if d0["dim"] == 2 and "phase" in kt and "transfer" not in kt:   # the transfer runs inside the phase kernel
@@ -190,7 +191,7 @@ def measure(sim, wl: dict, storage: str, steps: int, warmup: int) -> dict:
     d0 = wl["domains"][0]
     names = KERNEL_NAMES_3D if d0["dim"] == 3 else KERNEL_NAMES_MARCH if marching else KERNEL_NAMES
     return dict(mlups=mlups, wall=wall, event_ms=ev0.elapsed_time(ev1), finite=finite, kernels=per_kind,
-                dominant=dom_kind, names=names)
+                dominant=dom_kind, names=names, tile_rows=rows)
 
 
 def main() -> int:
@@ -295,6 +296,7 @@ def main() -> int:
             "update_factors": {k: d0[k] for k in ("N_phi", "N_U", "N_T", "N_F")},
             "storage": storage,
             "base_steps_per_step": cyc,
+            "tile_rows": m["tile_rows"],
             "parallelism": "single_gpu",
         },
         "roofline": {
@@ -328,6 +330,7 @@ def main() -> int:
             "unit": "MLUPS",
             "steps": 2,
             "base_steps_per_step": cycle_of(hw),
+            "tile_rows": hm["tile_rows"],
             "roofline": {
                 "bound": "hbm",
                 "kernel": hm["names"][hm["dominant"]],

@@ -250,6 +250,12 @@ int64_t lbm_steps_done(const lbm_ctx* ctx);
  * -1 for ctx NULL. */
 int32_t lbm_marching(const lbm_ctx* ctx);
 
+/* Tile height of the 2D tiled kernels in use: the one fixed by
+ * lbm_configure, else the autotuner's pick once it has run (at the first
+ * lbm_step_multirate or lbm_kernel_times), else 0; 0 for a 3D context, -1
+ * for ctx NULL. */
+int32_t lbm_tile_rows(const lbm_ctx* ctx);
+
 /* Text of the last error of ctx (or of the last failed lbm_create when ctx
  * is NULL).  Owned by the library. */
 const char* lbm_last_error(const lbm_ctx* ctx);

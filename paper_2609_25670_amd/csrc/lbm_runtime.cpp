@@ -954,6 +954,12 @@ int64_t lbm_steps_done(const lbm_ctx* c) { return c ? c->k : -1; }
 
 int32_t lbm_marching(const lbm_ctx* c) { return c ? (use_march(c) ? 1 : 0) : -1; }
 
+int32_t lbm_tile_rows(const lbm_ctx* c) {
+  if (!c) return -1;
+  if (c->dim == 3 || (c->autotune && !c->tuned)) return 0;
+  return kTYs[c->ty_index];
+}
+
 lbm_status lbm_kernel_times(lbm_ctx* c, int32_t reps, double* ms_out, double* per_step) {
   if (!c || !ms_out || reps < 1) return c ? fail(c, LBM_EINVAL, "bad arguments") : LBM_EINVAL;
   for (int d = 0; d < c->ndom; ++d)

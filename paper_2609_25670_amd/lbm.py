@@ -35,7 +35,7 @@ FIELD_BITS = [("phi", F_PHI, 1), ("U", F_U, 1), ("T", F_T, 1), ("rho", F_RHO, 1)
 EXPORTS = ["lbm_workspace_bytes", "lbm_create", "lbm_init_seeds", "lbm_init_front", "lbm_step_multirate",
            "lbm_read_fields",
            "lbm_write_fields", "lbm_configure", "lbm_kernel_times", "lbm_steps_done", "lbm_marching",
-           "lbm_last_error", "lbm_destroy"]
+           "lbm_tile_rows", "lbm_last_error", "lbm_destroy"]
 KERNEL_KINDS = ("phase", "transfer", "U", "T", "flow", "phase_dtr", "U_dtr")
 
 
@@ -112,6 +112,8 @@ def load() -> ctypes.CDLL:
     lib.lbm_steps_done.argtypes = [ctypes.c_void_p]
     lib.lbm_marching.restype = ctypes.c_int32
     lib.lbm_marching.argtypes = [ctypes.c_void_p]
+    lib.lbm_tile_rows.restype = ctypes.c_int32
+    lib.lbm_tile_rows.argtypes = [ctypes.c_void_p]
     lib.lbm_last_error.restype = ctypes.c_char_p
     lib.lbm_last_error.argtypes = [ctypes.c_void_p]
     lib.lbm_destroy.restype = None
@@ -249,6 +251,12 @@ class Simulation:
     def marching(self) -> bool:
         """Whether the 2D phase, transfer and T-transport kernels march."""
         return self.lib.lbm_marching(self.ctx) == 1
+
+    @property
+    def tile_rows(self) -> int:
+        """Tile height of the 2D tiled kernels in use (0 before the
+        autotuner has run, and in 3D)."""
+        return int(self.lib.lbm_tile_rows(self.ctx))
 
     def _layout(self, names, domain=0):
         d = self.domains[domain]
