@@ -84,7 +84,7 @@ def algorithmic_bytes(kind: str, d: dict, storage: str) -> int:
     if kind == "U_dtr":      # U transport carrying its step's transfer: phi^q, phi^{q+1}, U, j_U, [u],
         # T in; U, j_U, T out (the transferred U stays on chip)
         Tl = T if d.get("T_mode", "transport") != "pulled" else 0
-        return (3 + dim * F + 2 * Tl) * r + 2 * dim * s
+        return (4 + dim * F + 2 * Tl) * r + 2 * dim * s
     if kind == "transfer":   # phi^q, phi^{q+1}; U in, U out (or pending), T in, T out (not a pulled T)
         Tl = T if d.get("T_mode", "transport") != "pulled" else 0
         return (2 + 2 * U + 2 * Tl) * r
