@@ -45,7 +45,8 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2609_25670_amd", "csrc", f)
                   for f in ("lbm_kernels.hip", "lbm_dev.h")]
 KERNEL_NAMES = {"phase": "k_phase", "phase_tr": "k_phase_tr", "transfer": "k_transfer", "U": "k_scalar<..., 0>",
                 "T": "k_scalar<..., 1>", "flow": "k_flow", "phase_dtr": "k_dtr_phase", "U_dtr": "k_dtr_scalar"}
-KERNEL_NAMES_MARCH = dict(KERNEL_NAMES, phase="k_phase_ym", transfer="k_transfer_ym", T="k_scalar_ym<..., 1>")
+KERNEL_NAMES_MARCH = dict(KERNEL_NAMES, phase="k_phase_ym", transfer="k_transfer_ym", T="k_scalar_ym<..., 1>",
+                          T_tr="k_tr_scalar_ym")
 KERNEL_NAMES_3D = {"phase": "k3z_phase", "transfer": "k3z_transfer", "U": "k3z_scalar<..., 0>",
                    "T": "k3z_scalar<..., 1>", "flow": "k3z_flow"}
 
@@ -85,6 +86,9 @@ def algorithmic_bytes(kind: str, d: dict, storage: str) -> int:
         # T in; U, j_U, T out (the transferred U stays on chip)
         Tl = T if d.get("T_mode", "transport") != "pulled" else 0
         return (4 + dim * F + 2 * Tl) * r + 2 * dim * s
+    if kind == "T_tr":       # T transport carrying its step's transfer: phi^q, phi^{q+1}, U, T, j_T, [u] in;
+        # U*, T, j_T out (the transferred T stays on chip)
+        return (4 + 2 * U + dim * F) * r + 2 * dim * s
     if kind == "transfer":   # phi^q, phi^{q+1}; U in, U out (or pending), T in, T out (not a pulled T)
         Tl = T if d.get("T_mode", "transport") != "pulled" else 0
         return (2 + 2 * U + 2 * Tl) * r

@@ -220,7 +220,11 @@ lbm_status lbm_write_fields(lbm_ctx* ctx, int32_t domain, uint32_t mask,
  *                           or of a graph cycle) runs inside the next phase
  *                           kernel, and where every domain has U in one
  *                           update group, the transfer of a step at which U
- *                           is due runs inside that U transport; results
+ *                           is due runs inside that U transport.  In a
+ *                           marching context whose domains all have a
+ *                           transported T (instantaneous coupling, one
+ *                           update group), the transfer of a step at which
+ *                           T is due runs inside that T transport.  Results
  *                           bitwise identical.
  * Default after lbm_create: autotune, LBM_CFG_GRAPH.  Unknown flags, or
  * LBM_CFG_MARCH with LBM_CFG_TILES: LBM_EINVAL. */
@@ -232,11 +236,12 @@ lbm_status lbm_configure(lbm_ctx* ctx, int32_t tile_rows, int32_t flags);
  * launches on the context stream: ms_out[0] phase, [1] transfer, [2] U
  * transport, [3] T transport, [4] flow, [5] the phase kernel carrying the
  * previous step's deferred transfer, [6] the U transport carrying its
- * step's transfer (-1 where the context has no such kernel); the arrays
- * hold 7 values.  per_step_out[0..6] (may be NULL) receives the fraction of
- * that time spent per base step (each group of domains sharing an update
- * factor N contributes 1/N of its own launch time; with deferred transfers
- * the plain phase, transfer and U kernels run on the other steps), so
+ * step's transfer, [7] the marching T transport carrying its step's
+ * transfer (-1 where the context has no such kernel); the arrays hold 8
+ * values.  per_step_out[0..7] (may be NULL) receives the fraction of that
+ * time spent per base step (each group of domains sharing an update factor
+ * N contributes 1/N of its own launch time; with deferred transfers the
+ * plain phase, transfer, U and T kernels run on the other steps), so
  * ms_out * per_step_out is the device time per base step.  The timing launches overwrite the state:
  * every domain must be re-initialised with lbm_init_seeds before the next
  * lbm_step_multirate. */

@@ -65,7 +65,7 @@ struct Dom {
   void* U[4];      // R, four buffers
   void* jU[2];     // S, dim planes: first moment of the U populations
   void* PU;        // R, pending U increments (accumulated coupling)
-  void* T[2];      // R
+  void* T[4];      // R, four buffers
   void* jT[2];     // S, dim planes
   void* PT;        // R
   void* rho[2];    // R
@@ -99,18 +99,18 @@ struct DiagOut {
 // Buffer index holding a field's latest values after `n` writes.
 __host__ __device__ inline int par(long long n) { return (int)(n & 1); }
 
-// Buffer index of the phase field and of U after n writes.  Both have four
+// Buffer index of the phase field, U and T after n writes.  They have four
 // buffers, so that a kernel writing the next value may still read the value
 // two writes back at sites of other blocks: the kernels that carry a
-// deferred transfer read phi^{n-1} (and U before the transfer) on their
-// rings while neighbouring blocks write phi^{n+1} (the transported U).
+// deferred transfer read phi^{n-1} (U or T before the transfer) on their
+// rings while neighbouring blocks write phi^{n+1} (the transported U or T).
 template <class I>
 __host__ __device__ inline int qb(I n) { return (int)(n & (I)3); }
 
 // Writes of each buffered plane after completing base step k.  The
 // step kernels take k as a 32-bit unsigned step within the cycle of
-// 2 lcm(N_chi) base steps, doubled where the write count of phi or U over
-// it is not a multiple of 4 (every buffer index and every k mod N is
+// 2 lcm(N_chi) base steps, doubled where the write count of phi, U or T
+// over it is not a multiple of 4 (every buffer index and every k mod N is
 // periodic with it), so their divisions are 32-bit; the host and the
 // read-out kernels use the absolute 64-bit step.
 template <class I>

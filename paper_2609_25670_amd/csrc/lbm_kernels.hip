@@ -346,7 +346,7 @@ __global__ __launch_bounds__(NTHR) void k_phase(const Dom* __restrict__ doms, co
   // latest U and T (before this step's transfer)
   const unsigned nU = (D.accum ? 0u : (k - 1) / D.N_phi) + (k - 1) / D.N_U;
   GLOBAL const R* __restrict__ Up = D.has_U ? gp<const R>(D.U[qb(nU)]) : nullptr;
-  GLOBAL const R* __restrict__ Tp = D.has_T ? gp<const R>(D.T[par(n_T(D, k - 1))]) : nullptr;
+  GLOBAL const R* __restrict__ Tp = D.has_T ? gp<const R>(D.T[qb(n_T(D, k - 1))]) : nullptr;
 
   const PhaseConst<R> c = phase_const<R>(D);
 
@@ -566,7 +566,7 @@ __global__ __launch_bounds__(NTHR) void k_phase_ym(const Dom* __restrict__ doms,
   GLOBAL S* __restrict__ s_out = gp<S>(D.sphi[ob]);
   const unsigned nU = (D.accum ? 0u : (k - 1) / D.N_phi) + (k - 1) / D.N_U;
   GLOBAL const R* __restrict__ Up = D.has_U ? gp<const R>(D.U[qb(nU)]) : nullptr;
-  GLOBAL const R* __restrict__ Tp = D.has_T ? gp<const R>(D.T[par(n_T(D, k - 1))]) : nullptr;
+  GLOBAL const R* __restrict__ Tp = D.has_T ? gp<const R>(D.T[qb(n_T(D, k - 1))]) : nullptr;
   const PhaseConst<R> c = phase_const<R>(D);
   const R U0 = kc<R>(D, K_U0), T0 = kc<R>(D, K_T0);
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
@@ -727,8 +727,8 @@ __global__ __launch_bounds__(NTHR) void k_transfer(const Dom* __restrict__ doms,
   const unsigned nU = (D.accum ? 0u : (k - 1) / D.N_phi) + (k - 1) / D.N_U;
   GLOBAL const R* __restrict__ Uin = D.has_U ? gp<const R>(D.U[qb(nU)]) : nullptr;
   GLOBAL R* __restrict__ Uout = D.has_U ? gp<R>(D.U[qb(nU + 1)]) : nullptr;
-  GLOBAL const R* __restrict__ Tin = D.has_T ? gp<const R>(D.T[par(n_T(D, k - 1))]) : nullptr;
-  GLOBAL R* __restrict__ Tout = D.has_T ? gp<R>(D.T[par(n_T(D, k - 1) + 1)]) : nullptr;
+  GLOBAL const R* __restrict__ Tin = D.has_T ? gp<const R>(D.T[qb(n_T(D, k - 1))]) : nullptr;
+  GLOBAL R* __restrict__ Tout = D.has_T ? gp<R>(D.T[qb(n_T(D, k - 1) + 1)]) : nullptr;
   GLOBAL R* __restrict__ PU = gp<R>(D.PU);
   GLOBAL R* __restrict__ PT = gp<R>(D.PT);
   const R omk = kc<R>(D, K_OMK), opk = kc<R>(D, K_OPK);
@@ -928,11 +928,11 @@ __global__ __launch_bounds__(NTHR) void k_transfer_ym(const Dom* __restrict__ do
   const bool hasU = D.has_U, hasT = D.has_T, accum = D.accum;
   GLOBAL const R* __restrict__ Uin = hasU ? gp<const R>(D.U[qb(nU)]) : nullptr;
   GLOBAL R* __restrict__ Uout = hasU ? gp<R>(D.U[qb(nU + 1)]) : nullptr;
-  GLOBAL R* __restrict__ Tout = hasT ? gp<R>(D.T[par(n_T(D, k - 1) + 1)]) : nullptr;
+  GLOBAL R* __restrict__ Tout = hasT ? gp<R>(D.T[qb(n_T(D, k - 1) + 1)]) : nullptr;
   GLOBAL R* __restrict__ PU = gp<R>(D.PU);
   GLOBAL R* __restrict__ PT = gp<R>(D.PT);
   // T before the injection: the pending plane (accumulated coupling) or T
-  GLOBAL const R* __restrict__ Tsrc = hasT ? (accum ? (GLOBAL const R*)PT : gp<const R>(D.T[par(n_T(D, k - 1))]))
+  GLOBAL const R* __restrict__ Tsrc = hasT ? (accum ? (GLOBAL const R*)PT : gp<const R>(D.T[qb(n_T(D, k - 1))]))
                                            : nullptr;
   const R omk = kc<R>(D, K_OMK), opk = kc<R>(D, K_OPK);
   const R Uref = kc<R>(D, K_U0);   // the U plane holds U - U0
@@ -1105,8 +1105,8 @@ __global__ __launch_bounds__(NTHR) void k_dtr_phase(const Dom* __restrict__ doms
   const unsigned nU = (kt - 1) / D.N_phi + (kt - 1) / D.N_U;
   GLOBAL const R* __restrict__ Uin = D.has_U ? gp<const R>(D.U[qb(nU)]) : nullptr;
   GLOBAL R* __restrict__ Uout = D.has_U ? gp<R>(D.U[qb(nU + 1)]) : nullptr;
-  GLOBAL const R* __restrict__ Tin = D.has_T ? gp<const R>(D.T[par(n_T(D, kt - 1))]) : nullptr;
-  GLOBAL R* __restrict__ Tout = D.has_T ? gp<R>(D.T[par(n_T(D, kt - 1) + 1)]) : nullptr;
+  GLOBAL const R* __restrict__ Tin = D.has_T ? gp<const R>(D.T[qb(n_T(D, kt - 1))]) : nullptr;
+  GLOBAL R* __restrict__ Tout = D.has_T ? gp<R>(D.T[qb(n_T(D, kt - 1) + 1)]) : nullptr;
   const PhaseConst<R> c = phase_const<R>(D);
   const R Uref = kc<R>(D, K_U0), Tref = kc<R>(D, K_T0);
   const R omk = kc<R>(D, K_OMK), opk = kc<R>(D, K_OPK);
@@ -1345,8 +1345,8 @@ __global__ __launch_bounds__(NTHR) void k_phase_tr(const Dom* __restrict__ doms,
   const unsigned nU = (D.accum ? 0u : (k - 1) / D.N_phi) + (k - 1) / D.N_U;
   GLOBAL const R* __restrict__ Up = D.has_U ? gp<const R>(D.U[qb(nU)]) : nullptr;
   GLOBAL R* __restrict__ Uout = D.has_U ? gp<R>(D.U[qb(nU + 1)]) : nullptr;
-  GLOBAL const R* __restrict__ Tin = D.has_T ? gp<const R>(D.T[par(n_T(D, k - 1))]) : nullptr;
-  GLOBAL R* __restrict__ Tout = D.has_T ? gp<R>(D.T[par(n_T(D, k - 1) + 1)]) : nullptr;
+  GLOBAL const R* __restrict__ Tin = D.has_T ? gp<const R>(D.T[qb(n_T(D, k - 1))]) : nullptr;
+  GLOBAL R* __restrict__ Tout = D.has_T ? gp<R>(D.T[qb(n_T(D, k - 1) + 1)]) : nullptr;
   GLOBAL R* __restrict__ PU = gp<R>(D.PU);
   GLOBAL R* __restrict__ PT = gp<R>(D.PT);
 
@@ -1593,8 +1593,8 @@ __global__ __launch_bounds__(NTHR) void k_scalar(const Dom* __restrict__ doms, c
     jout = gp<S>(D.jU[par(n_jU(D, k))]);
     pend = gp<R>(D.PU);
   } else {
-    cin = gp<const R>(D.T[par(n_Ttr(D, k) + (k - 1) / D.N_T)]);
-    cout = gp<R>(D.T[par(n_Ttr(D, k) + k / D.N_T)]);
+    cin = gp<const R>(D.T[qb(n_Ttr(D, k) + (k - 1) / D.N_T)]);
+    cout = gp<R>(D.T[qb(n_Ttr(D, k) + k / D.N_T)]);
     jin = gp<const S>(D.jT[par(n_jT(D, k - 1))]);
     jout = gp<S>(D.jT[par(n_jT(D, k))]);
     pend = gp<R>(D.PT);
@@ -1797,8 +1797,8 @@ __global__ __launch_bounds__(NTHR) void k_dtr_scalar(const Dom* __restrict__ dom
   const unsigned nU = (k - 1) / D.N_phi + (k - 1) / D.N_U;
   GLOBAL const R* __restrict__ Uin = gp<const R>(D.U[qb(nU)]);
   GLOBAL R* __restrict__ Uout = gp<R>(D.U[qb(nU + 2)]);
-  GLOBAL const R* __restrict__ Tin = D.has_T ? gp<const R>(D.T[par(n_T(D, k - 1))]) : nullptr;
-  GLOBAL R* __restrict__ Tout = D.has_T ? gp<R>(D.T[par(n_T(D, k - 1) + 1)]) : nullptr;
+  GLOBAL const R* __restrict__ Tin = D.has_T ? gp<const R>(D.T[qb(n_T(D, k - 1))]) : nullptr;
+  GLOBAL R* __restrict__ Tout = D.has_T ? gp<R>(D.T[qb(n_T(D, k - 1) + 1)]) : nullptr;
   GLOBAL const S* __restrict__ jin = gp<const S>(D.jU[par(n_jU(D, k - 1))]);
   GLOBAL S* __restrict__ jout = gp<S>(D.jU[par(n_jU(D, k))]);
   GLOBAL const R* __restrict__ vel = D.has_F ? gp<const R>(D.vel[par(n_F(D, k - 1))]) : nullptr;
@@ -2074,8 +2074,8 @@ __global__ __launch_bounds__(NTHR) void k_scalar_ym(const Dom* __restrict__ doms
     jout = gp<S>(D.jU[par(n_jU(D, k))]);
     pend = gp<R>(D.PU);
   } else {
-    cin = gp<const R>(D.T[par(n_Ttr(D, k) + (k - 1) / D.N_T)]);
-    cout = gp<R>(D.T[par(n_Ttr(D, k) + k / D.N_T)]);
+    cin = gp<const R>(D.T[qb(n_Ttr(D, k) + (k - 1) / D.N_T)]);
+    cout = gp<R>(D.T[qb(n_Ttr(D, k) + k / D.N_T)]);
     jin = gp<const SR>(D.jT[par(n_jT(D, k - 1))]);
     jout = gp<S>(D.jT[par(n_jT(D, k))]);
     pend = gp<R>(D.PT);
@@ -2243,6 +2243,300 @@ __global__ __launch_bounds__(NTHR) void k_scalar_ym(const Dom* __restrict__ doms
   }
 }
 
+
+// =================================================================== transfer + T transport, marching
+// raw loads of the marching transfer + T transport for the rows r0 .. r0 + 3:
+// the J inputs phi^q and U at the column and ring cells (ghosted: beyond a
+// wall, the boundary node), and where the cell is a collision cell (not
+// beyond a wall) T before the transfer, j_T and the velocity; then phi^{q+1}
+// rows r0 + 1 .. r0 + 4
+template <class R, class S>
+struct YTsIn {
+  R po[2], U[2], T[2], u[2][2];
+  typename RawT<S>::type j[2][2];
+  R phi[2];
+};
+template <class R, class S>
+__device__ __forceinline__ void ym_load_ts(int nx, int ny, int px, int bcx, int bcy, int x0, int w, int r0, int tx,
+                                           int ty, int tid, long long pl, GLOBAL const R* pn, GLOBAL const R* po,
+                                           GLOBAL const R* Uin, GLOBAL const R* Tin,
+                                           GLOBAL const typename RawT<S>::type* jin, GLOBAL const R* vel,
+                                           YTsIn<R, S>& in, bool inputs = true) {
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    if (!inputs) break;
+    int col, row;
+    if (!ym_cell(i, tx, ty, tid, w, r0, col, row)) continue;
+    const int rx = x0 - 1 + col;
+    // inside the domain and across periodic edges the ghost and the
+    // resolved node coincide
+    const unsigned o = (unsigned)ghost(row, ny, bcy) * (unsigned)px + (unsigned)ghost(rx, nx, bcx);
+    in.po[i] = ldo(po, o);
+    if (Uin) in.U[i] = ldo(Uin, o);
+    if (resolve(rx, nx, bcx) < 0 || resolve(row, ny, bcy) < 0) continue;
+    in.T[i] = ldo(Tin, o);
+    in.j[i][0] = *at(jin, o);
+    in.j[i][1] = *at(plane(jin, pl), o);
+    if (vel) {
+      in.u[i][0] = ldo(vel, o);
+      in.u[i][1] = ldo(plane(vel, pl), o);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i) {
+    const int cc = tid + 256 * i;
+    if (cc < 4 * YBW) {
+      const int gx = ghost(x0 - 2 + cc % YBW, nx, bcx), gy = ghost(r0 + 1 + cc / YBW, ny, bcy);
+      in.phi[i] = ldo(pn, (unsigned)gy * (unsigned)px + (unsigned)gx);
+    }
+  }
+}
+
+// The transfer of phase step k fused into the T transport of the same step,
+// marching up a column (a step at which both are due, instantaneous
+// coupling).  On the rows ahead: J (as the marching transfer), and at the
+// collision cells T* = T + dT of the transfer and the T collision with it;
+// on the current rows: U* = U + dU (written) and the T streaming.  T* is
+// not written: its only reader is this transport, and the transported T
+// goes to the buffer after it.  The T planes have four buffers, so the T
+// before the transfer, read on the rings, is never the buffer neighbouring
+// blocks write.  The U transport of the step runs after this kernel.
+// Bitwise identical to the two separate kernels.
+template <class R, class S, int Q>
+__global__ __launch_bounds__(NTHR) void k_tr_scalar_ym(const Dom* __restrict__ doms, const int4* __restrict__ runs,
+                                                        unsigned k, Partial* __restrict__ part,
+                                                        const int* __restrict__ slot0, int TY) {
+  using Lq = Lat2<Q>;
+  using SR = typename RawT<S>::type;
+  constexpr int NV = Q == 9 ? 6 : 4;   // chi, dt Q, Kx, Ky (and j_eq in D2Q9)
+  __shared__ R wphi[8][YBW];
+  __shared__ R wJx[8][YCW], wJy[8][YCW];
+  __shared__ R wc[8][NV][YCW];
+  __shared__ R red[NTHR / 64];
+
+  const int4 t = runs[blockIdx.x];
+  if (t.x < 0) return;
+  const Dom& D = doms[t.x];
+  if (k % D.N_phi || k % D.N_T) return;
+  const int nx = D.nx, ny = D.ny, px = D.px, bcx = D.bc[0], bcy = D.bc[1];
+  const long long pl = D.plane;
+  const int x0 = t.y, ya = t.z, yb = t.w;
+  const int w = min(TX, nx - x0);
+  GLOBAL const R* __restrict__ phi_old = gp<const R>(D.phi[qb(n_phi(D, k - 1))]);
+  GLOBAL const R* __restrict__ phi_new = gp<const R>(D.phi[qb(n_phi(D, k))]);
+  const bool hasU = D.has_U;
+  const unsigned nU = (k - 1) / D.N_phi + (k - 1) / D.N_U;
+  GLOBAL const R* __restrict__ Uin = hasU ? gp<const R>(D.U[qb(nU)]) : nullptr;
+  GLOBAL R* __restrict__ Uout = hasU ? gp<R>(D.U[qb(nU + 1)]) : nullptr;
+  const unsigned nT = n_T(D, k - 1);
+  GLOBAL const R* __restrict__ Tin = gp<const R>(D.T[qb(nT)]);
+  GLOBAL R* __restrict__ cout = gp<R>(D.T[qb(nT + 2)]);
+  GLOBAL const SR* __restrict__ jin = gp<const SR>(D.jT[par(n_jT(D, k - 1))]);
+  GLOBAL S* __restrict__ jout = gp<S>(D.jT[par(n_jT(D, k))]);
+  GLOBAL const R* __restrict__ vel = D.has_F ? gp<const R>(D.vel[par(n_F(D, k - 1))]) : nullptr;
+  const bool need_phi = D.T_var;
+  const R omk = kc<R>(D, K_OMK), opk = kc<R>(D, K_OPK);
+  const R Uref = kc<R>(D, K_U0);   // the U plane holds U - U0
+  const R cJ = kc<R>(D, K_CJ);
+  const R cT = kc<R>(D, K_CT);
+  const R rcS = kc<R>(D, K_RCS), rcL = kc<R>(D, K_RCL);
+  const R dt = kc<R>(D, K_DTT);
+  const R hkS = kc<R>(D, K_HKS), hkL = kc<R>(D, K_HKL), hrcS = kc<R>(D, K_HRCS), hrcL = kc<R>(D, K_HRCL);
+  const R itau_const = rcp(R(3) * dt * kc<R>(D, K_ALPHAL) + R(0.5));
+  const R cref = kc<R>(D, K_T0);
+  const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
+  const bool wx = bcx != BC_PER, wy = bcy != BC_PER;
+
+  auto put_phi = [&](const YTsIn<R, S>& in, int r0) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      const int cc = tid + 256 * i;
+      if (cc < 4 * YBW) wphi[(r0 + 1 + cc / YBW) & 7][cc % YBW] = in.phi[i];
+    }
+  };
+  // J of rows r0 .. r0 + 3 (phi^{q+1} rows r0 - 1 .. r0 + 4 in LDS), as the
+  // marching transfer computes it
+  auto flux = [&](const YTsIn<R, S>& in, int r0) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      int col, row;
+      if (!ym_cell(i, tx, ty, tid, w, r0, col, row)) continue;
+      int rx = x0 - 1 + col, ry = row;
+      bool mx = false, my = false;
+      if (rx < 0 && bcx != BC_PER) { rx = 0; mx = true; }
+      if (rx >= nx && bcx != BC_PER) { rx = nx - 1; mx = true; }
+      if (ry < 0 && bcy != BC_PER) { ry = 0; my = true; }
+      if (ry >= ny && bcy != BC_PER) { ry = ny - 1; my = true; }
+      const int bcol = rx - (x0 - 2);   // window column of the (boundary) node
+      R gxv, gyv;
+      iso_grad_rows(wphi[(ry - 1) & 7], wphi[ry & 7], wphi[(ry + 1) & 7], bcol, gxv, gyv);
+      const R gg = gxv * gxv + gyv * gyv;
+      R Jx = R(0), Jy = R(0);
+      if (gg >= R(GRAD_EPS2)) {
+        const R ig = rsq(gg);
+        const R a = cJ * (R(1) + omk * (in.U[i] + Uref)) * (wphi[ry & 7][bcol] - in.po[i]) * ig;
+        Jx = -a * gxv;
+        Jy = -a * gyv;
+      }
+      wJx[row & 7][col] = mx ? -Jx : Jx;
+      wJy[row & 7][col] = my ? -Jy : Jy;
+    }
+  };
+  // T* and the T collision at the collision cells of rows r0 .. r0 + 3, as
+  // the transfer and the marching transport compute them
+  auto collide = [&](const YTsIn<R, S>& in, int r0) {
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+      int col, row;
+      if (!ym_cell(i, tx, ty, tid, w, r0, col, row)) continue;
+      if (resolve(x0 - 1 + col, nx, bcx) < 0 || resolve(row, ny, bcy) < 0) continue;   // beyond a wall
+      const R* r0p = wphi[row & 7];
+      const R pn = r0p[col + 1];
+      const R dphi = pn - in.po[i];
+      const R rc = (R(1) + pn) * R(0.5) * rcS + (R(1) - pn) * R(0.5) * rcL;
+      const R dT = cT * dphi * rcp(R(2) * rc);
+      const R chi = in.T[i] + dT;
+      const R ca = chi + cref;   // the plane holds T - T0
+      const R uxv = vel ? in.u[i][0] : R(0), uyv = vel ? in.u[i][1] : R(0);
+      const R jxv = cvt_raw(in.j[i][0], (S*)nullptr), jyv = cvt_raw(in.j[i][1], (S*)nullptr);
+      const R jex = ca * uxv * dt, jey = ca * uyv * dt;
+      R itau, Qs = R(0);
+      if (need_phi) {
+        const R phi = r0p[col + 1];
+        const R irc = rcp((R(1) + phi) * hrcS + (R(1) - phi) * hrcL);
+        const R coeff = ((R(1) + phi) * hkS + (R(1) - phi) * hkL) * irc;          // Eq. (11)
+        itau = rcp(R(3) * dt * coeff + R(0.5));
+        const R gcx = -R(3) * itau * (jxv - jex), gcy = -R(3) * itau * (jyv - jey);
+        R gpx, gpy;
+        iso_grad_rows(wphi[(row - 1) & 7], r0p, wphi[(row + 1) & 7], col + 1, gpx, gpy);
+        Qs = (hrcS - hrcL) * irc * coeff * (gcx * gpx + gcy * gpy);               // Eq. (12), 1st term
+      } else {
+        itau = itau_const;
+      }
+      const R om = R(1) - itau;
+      R(*cr)[YCW] = wc[row & 7];
+      cr[0][col] = chi;
+      cr[1][col] = dt * Qs;
+      cr[2][col] = jex + om * (jxv - jex);
+      cr[3][col] = jey + om * (jyv - jey);
+      if constexpr (Q == 9) {
+        cr[4][col] = jex;
+        cr[5][col] = jey;
+      }
+    }
+  };
+
+  R amax = R(0);
+  YTsIn<R, S> in0;
+  YTrOwn<R> own;
+  // own sites of rows ya .. ya + 3; phi^{q+1} rows ya - 6 .. ya + 1, J and
+  // the collisions of rows ya - 3 .. ya
+  ym_load_own<R>(ny, px, x0, w, ya + ty, tx, hasU, phi_new, phi_old, Uin, nullptr, own);
+  {
+    YTsIn<R, S> lo, mid;
+    ym_load_ts<R, S>(nx, ny, px, bcx, bcy, x0, w, ya - 7, tx, ty, tid, pl, phi_new, phi_old, Uin, Tin, jin, vel, lo,
+                     false);
+    ym_load_ts<R, S>(nx, ny, px, bcx, bcy, x0, w, ya - 3, tx, ty, tid, pl, phi_new, phi_old, Uin, Tin, jin, vel, mid);
+    put_phi(lo, ya - 7);
+    put_phi(mid, ya - 3);
+    __syncthreads();
+    if (hasU) flux(mid, ya - 3);
+    collide(mid, ya - 3);
+    ym_load_ts<R, S>(nx, ny, px, bcx, bcy, x0, w, ya + 1, tx, ty, tid, pl, phi_new, phi_old, Uin, Tin, jin, vel, in0);
+  }
+  __syncthreads();
+
+  for (int y = ya; y < yb; y += 4) {
+    // in0: inputs of rows y + 1 .. y + 4, phi^{q+1} rows y + 2 .. y + 5;
+    // own: the own site of row y + ty
+    put_phi(in0, y + 1);
+    const YTsIn<R, S> cur = in0;
+    const YTrOwn<R> me = own;
+    if (y + 4 < yb) {   // prefetch for the next rows
+      ym_load_ts<R, S>(nx, ny, px, bcx, bcy, x0, w, y + 5, tx, ty, tid, pl, phi_new, phi_old, Uin, Tin, jin, vel,
+                       in0);
+      ym_load_own<R>(ny, px, x0, w, y + 4 + ty, tx, hasU, phi_new, phi_old, Uin, nullptr, own);
+    }
+    __syncthreads();
+    if (hasU) flux(cur, y + 1);
+    collide(cur, y + 1);
+    __syncthreads();
+    const int gy = y + ty;
+    if (tx < w && gy < yb) {
+      const int gx = x0 + tx, lx = tx + 1;
+      const unsigned o = (unsigned)gy * (unsigned)px + (unsigned)gx;
+      if (hasU) {   // U* of the transfer
+        const R pn = wphi[gy & 7][lx + 1];
+        const R dphi = pn - me.po;
+        const int rm = (gy - 1) & 7, r0 = gy & 7, rp = (gy + 1) & 7;
+        const R div = (wJx[r0][lx + 1] - wJx[r0][lx - 1]) * R(1.0 / 3.0) +
+                      (wJx[rp][lx + 1] - wJx[rp][lx - 1] - wJx[rm][lx - 1] + wJx[rm][lx + 1]) * R(1.0 / 12.0) +
+                      (wJy[rp][lx] - wJy[rm][lx]) * R(1.0 / 3.0) +
+                      (wJy[rp][lx + 1] + wJy[rp][lx - 1] - wJy[rm][lx - 1] - wJy[rm][lx + 1]) * R(1.0 / 12.0);
+        const R Us = me.U;
+        const R dU = ((R(1) + omk * (Us + Uref)) * dphi - R(2) * div) * rcp(opk - omk * pn);
+        amax = fmax(amax, fabs(dU));
+        sto(Uout, o, Us + dU);
+      }
+      // pull streaming (Eq. 25) of T in deviations d_i = f_i - w_i chi(y)
+      const bool edge = (wx && (x0 == 0 || x0 + w >= nx)) || (wy && (y == 0 || y + 4 >= ny));
+      const R(*co)[YCW] = wc[gy & 7];
+      const R cy = co[0][lx], dPo = co[1][lx];
+      R dq[Q];
+      dq[0] = dPo * R(Lq::w(0));
+#pragma unroll
+      for (int q = 1; q < Q; ++q) {
+        const int ex = Lq::ex(q), ey = Lq::ey(q);
+        const bool wall = edge && ((wx && ((ex > 0 && gx == 0) || (ex < 0 && gx == nx - 1))) ||
+                                   (wy && ((ey > 0 && gy == 0) || (ey < 0 && gy == ny - 1))));
+        if (edge && D.T_dirlow && ey > 0 && gy == 0) {
+          // anti-bounce-back to T0 at the wall y = -1/2 (the plane holds T - T0)
+          dq[q] = -(R(2) * cy + dPo) * R(Lq::w(q)) + R(Lq::cK) * (R(ex) * co[2][lx] + R(ey) * co[3][lx]);
+          if constexpr (Q == 9) dq[q] += R(Lq::cJ(q)) * (R(ex) * co[4][lx] + R(ey) * co[5][lx]);
+        } else if (wall) {
+          dq[q] = dPo * R(Lq::w(q)) - R(Lq::cK) * (R(ex) * co[2][lx] + R(ey) * co[3][lx]);
+          if constexpr (Q == 9) dq[q] -= R(Lq::cJ(q)) * (R(ex) * co[4][lx] + R(ey) * co[5][lx]);
+        } else {
+          const R(*cu)[YCW] = wc[(gy - ey) & 7];
+          const int ux = lx - ex;
+          dq[q] = (cu[0][ux] - cy + cu[1][ux]) * R(Lq::w(q)) + R(Lq::cK) * (R(ex) * cu[2][ux] + R(ey) * cu[3][ux]);
+          if constexpr (Q == 9) dq[q] += R(Lq::cJ(q)) * (R(ex) * cu[4][ux] + R(ey) * cu[5][ux]);
+        }
+      }
+      R sum = dq[0];
+#pragma unroll
+      for (int q = 1; q < Q; ++q) sum += dq[q];
+      const R chin = cy + sum;
+      sto(cout, o, chin);
+      R jx = R(0), jy = R(0);
+#pragma unroll
+      for (int q = 1; q < Q; ++q) {
+        if (Lq::ex(q) > 0) jx += dq[q];
+        if (Lq::ex(q) < 0) jx -= dq[q];
+        if (Lq::ey(q) > 0) jy += dq[q];
+        if (Lq::ey(q) < 0) jy -= dq[q];
+      }
+      sto(jout, o, jx);
+      sto(plane(jout, pl), o, jy);
+    }
+    __syncthreads();
+  }
+  if (part && hasU) {
+    for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_down(amax, off, 64));
+    if (tx == 0) red[ty] = amax;
+    __syncthreads();
+    if (tid == 0) {
+      R m = red[0];
+      for (int wv = 1; wv < NTHR / 64; ++wv) m = fmax(m, red[wv]);
+      const int ntx = (nx + 63) / 64, tcol = x0 / 64;
+      for (int r = ya / TY; r * TY < yb; ++r) {
+        Partial& P = part[slot0[t.x] + r * ntx + tcol];
+        P.S_phi = r == ya / TY ? double(m) : 0.0;
+        P.J_U = r == ya / TY ? double(m) : 0.0;
+      }
+    }
+  }
+}
 
 // =================================================================== flow
 // D2Q9 MRT (Eq. 27-32) with Guo forcing (Eq. 30), then the weighted partial
@@ -2490,8 +2784,8 @@ __global__ void k_init(const Dom* __restrict__ doms, int dom, const double* __re
   }
   if (D.has_T) {
     const double dtT = D.N_T * D.dt_base;
+    for (int b = 0; b < 4; ++b) (gp<R>(D.T[b]))[o] = R(0);    // T - T0
     for (int b = 0; b < 2; ++b) {
-      (gp<R>(D.T[b]))[o] = R(0);    // T - T0
       st(gp<S>(D.jT[b]), o, R(D.T0 * ux * dtT));
       st(gp<S>(D.jT[b]), o + pl, R(0));
     }
@@ -2525,9 +2819,9 @@ __device__ double read_plane(const Dom& D, long long k, int code, long long o) {
   switch (code) {
     case 0: return double((gp<const R>(D.phi[qb(n_phi(D, k))]))[o]);
     case 1: return double((gp<const R>(D.U[qb(n_U(D, k))]))[o]) + D.U0;
-    case 2: return double((gp<const R>(D.T[par(n_T(D, k))]))[o]) + D.T0;
+    case 2: return double((gp<const R>(D.T[qb(n_T(D, k))]))[o]) + D.T0;
     case 8: return double((gp<const R>(D.U[qb(n_U(D, k))]))[o]);
-    case 9: return double((gp<const R>(D.T[par(n_T(D, k))]))[o]);
+    case 9: return double((gp<const R>(D.T[qb(n_T(D, k))]))[o]);
     case 3: return double((gp<const R>(D.rho[par(n_F(D, k))]))[o]);
     case 4: return double((gp<const R>(D.vel[par(n_F(D, k))]))[o]);
     case 5: return double((gp<const R>(D.vel[par(n_F(D, k))]))[o + pl]);
@@ -2605,9 +2899,9 @@ __global__ void k_write(const Dom* __restrict__ doms, int dom, long long k, cons
     switch (code) {
       case 0: (gp<R>(D.phi[qb(n_phi(D, k))]))[o] = R(v); break;
       case 1: (gp<R>(D.U[qb(n_U(D, k))]))[o] = R(v - D.U0); break;
-      case 2: (gp<R>(D.T[par(n_T(D, k))]))[o] = R(v - D.T0); break;
+      case 2: (gp<R>(D.T[qb(n_T(D, k))]))[o] = R(v - D.T0); break;
       case 8: (gp<R>(D.U[qb(n_U(D, k))]))[o] = R(v); break;
-      case 9: (gp<R>(D.T[par(n_T(D, k))]))[o] = R(v); break;
+      case 9: (gp<R>(D.T[qb(n_T(D, k))]))[o] = R(v); break;
       case 3: (gp<R>(D.rho[par(n_F(D, k))]))[o] = R(v); break;
       case 4: (gp<R>(D.vel[par(n_F(D, k))]))[o] = R(v); break;
       case 5: (gp<R>(D.vel[par(n_F(D, k))]))[o + pl] = R(v); break;
@@ -2670,7 +2964,7 @@ __global__ __launch_bounds__(NTHR) void k_diag_tiles(const Dom* __restrict__ dom
   const long long px = D.px;
   GLOBAL const R* phi = gp<const R>(D.phi[qb(n_phi(D, k))]);
   GLOBAL const R* U = D.has_U ? gp<const R>(D.U[qb(n_U(D, k))]) : nullptr;
-  GLOBAL const R* T = D.has_T ? gp<const R>(D.T[par(n_T(D, k))]) : nullptr;
+  GLOBAL const R* T = D.has_T ? gp<const R>(D.T[qb(n_T(D, k))]) : nullptr;
   GLOBAL const R* rho = D.has_F ? gp<const R>(D.rho[par(n_F(D, k))]) : nullptr;
   const int tx = threadIdx.x, ty = threadIdx.y;
   double a[5] = {0, 0, 0, 0, 0};
@@ -3087,7 +3381,7 @@ __global__ __launch_bounds__(256) void k3z_phase(const Dom* __restrict__ doms, u
   GLOBAL S* s_out = gp<S>(D.sphi[ob]);
   const unsigned nU = (D.accum ? 0u : (k - 1) / D.N_phi) + (k - 1) / D.N_U;
   GLOBAL const R* Up = D.has_U ? gp<const R>(D.U[qb(nU)]) : nullptr;
-  GLOBAL const R* Tp = D.has_T ? gp<const R>(D.T[par(n_T(D, k - 1))]) : nullptr;
+  GLOBAL const R* Tp = D.has_T ? gp<const R>(D.T[qb(n_T(D, k - 1))]) : nullptr;
   const PhaseConst<R> pc = phase_const<R>(D);
   const R U0 = kc<R>(D, K_U0), T0 = kc<R>(D, K_T0);
   const bool own = tx < c.w && ty < c.h;
@@ -3270,8 +3564,8 @@ __global__ __launch_bounds__(256) void k3z_scalar(const Dom* __restrict__ doms, 
     jout = gp<S>(D.jU[par(n_jU(D, k))]);
     pend = gp<R>(D.PU);
   } else {
-    cin = gp<const R>(D.T[par(n_Ttr(D, k) + (k - 1) / D.N_T)]);
-    cout = gp<R>(D.T[par(n_Ttr(D, k) + k / D.N_T)]);
+    cin = gp<const R>(D.T[qb(n_Ttr(D, k) + (k - 1) / D.N_T)]);
+    cout = gp<R>(D.T[qb(n_Ttr(D, k) + k / D.N_T)]);
     jin = gp<const SR>(D.jT[par(n_jT(D, k - 1))]);
     jout = gp<S>(D.jT[par(n_jT(D, k))]);
     pend = gp<R>(D.PT);
@@ -3491,8 +3785,8 @@ __global__ __launch_bounds__(256) void k3z_transfer(const Dom* __restrict__ doms
   const unsigned nU = (D.accum ? 0u : (k - 1) / D.N_phi) + (k - 1) / D.N_U;
   GLOBAL const R* Uin = hasU ? gp<const R>(D.U[qb(nU)]) : nullptr;
   GLOBAL R* Uout = hasU ? gp<R>(D.U[qb(nU + 1)]) : nullptr;
-  GLOBAL const R* Tin = hasT ? gp<const R>(D.T[par(n_T(D, k - 1))]) : nullptr;
-  GLOBAL R* Tout = hasT ? gp<R>(D.T[par(n_T(D, k - 1) + 1)]) : nullptr;
+  GLOBAL const R* Tin = hasT ? gp<const R>(D.T[qb(n_T(D, k - 1))]) : nullptr;
+  GLOBAL R* Tout = hasT ? gp<R>(D.T[qb(n_T(D, k - 1) + 1)]) : nullptr;
   GLOBAL R* PU = gp<R>(D.PU);
   GLOBAL R* PT = gp<R>(D.PT);
   const R cJ = kc<R>(D, K_CJ), omk = kc<R>(D, K_OMK), opk = kc<R>(D, K_OPK), U0 = kc<R>(D, K_U0);
@@ -3904,8 +4198,8 @@ __global__ void k3_init(const Dom* __restrict__ doms, const double* __restrict__
   if (D.has_T) {
     const double dT0 = D.T_pulled ? D.T_grad * (s.z - D.z_front) : 0.0;   // T - T0
     const double jz = D.T_pulled ? (D.T0 + dT0) * D.V_pull * D.N_T * D.dt_base : 0.0;
+    for (int b = 0; b < 4; ++b) (gp<R>(D.T[b]))[s.o] = R(dT0);
     for (int b = 0; b < 2; ++b) {
-      (gp<R>(D.T[b]))[s.o] = R(dT0);
       st(gp<S>(D.jT[b]), s.o, R(0));
       st(gp<S>(D.jT[b]), s.o + pl, R(0));
       st(gp<S>(D.jT[b]), s.o + 2 * pl, R(jz));
@@ -3931,9 +4225,9 @@ __device__ double read_plane3(const Dom& D, long long k, int code, unsigned o) {
   const unsigned pl = (unsigned)D.plane;
   if (code == 0) return double((gp<const R>(D.phi[qb(n_phi(D, k))]))[o]);
   if (code == 1) return double((gp<const R>(D.U[qb(n_U(D, k))]))[o]) + D.U0;
-  if (code == 2) return double((gp<const R>(D.T[par(n_T(D, k))]))[o]) + D.T0;
+  if (code == 2) return double((gp<const R>(D.T[qb(n_T(D, k))]))[o]) + D.T0;
   if (code == 8) return double((gp<const R>(D.U[qb(n_U(D, k))]))[o]);
-  if (code == 9) return double((gp<const R>(D.T[par(n_T(D, k))]))[o]);
+  if (code == 9) return double((gp<const R>(D.T[qb(n_T(D, k))]))[o]);
   if (code == 3) return double((gp<const R>(D.rho[par(n_F(D, k))]))[o]);
   if (code >= 4 && code <= 6) return double((gp<const R>(D.vel[par(n_F(D, k))]))[o + (code - 4) * pl]);
   if (code >= 20 && code <= 22) return double(ld(gp<const S>(D.jU[par(n_jU(D, k))]), o + (code - 20) * pl));
@@ -3997,9 +4291,9 @@ __global__ void k3_write(const Dom* __restrict__ doms, long long k, const int* _
     const double v = src[c * n + i];
     if (code == 0) (gp<R>(D.phi[qb(n_phi(D, k))]))[o] = R(v);
     else if (code == 1) (gp<R>(D.U[qb(n_U(D, k))]))[o] = R(v - D.U0);
-    else if (code == 2) (gp<R>(D.T[par(n_T(D, k))]))[o] = R(v - D.T0);
+    else if (code == 2) (gp<R>(D.T[qb(n_T(D, k))]))[o] = R(v - D.T0);
     else if (code == 8) (gp<R>(D.U[qb(n_U(D, k))]))[o] = R(v);
-    else if (code == 9) (gp<R>(D.T[par(n_T(D, k))]))[o] = R(v);
+    else if (code == 9) (gp<R>(D.T[qb(n_T(D, k))]))[o] = R(v);
     else if (code == 3) (gp<R>(D.rho[par(n_F(D, k))]))[o] = R(v);
     else if (code >= 4 && code <= 6) (gp<R>(D.vel[par(n_F(D, k))]))[o + (code - 4) * pl] = R(v);
     else if (code >= 20 && code <= 22) st(gp<S>(D.jU[par(n_jU(D, k))]), o + (code - 20) * pl, R(v));
@@ -4050,7 +4344,7 @@ __global__ __launch_bounds__(256) void k3_diag(const Dom* __restrict__ doms, lon
       bad |= !isfinite(u);
     }
     if (D.has_T) {
-      const double t = double((gp<const R>(D.T[par(n_T(D, k))]))[s.o]) + D.T0;
+      const double t = double((gp<const R>(D.T[qb(n_T(D, k))]))[s.o]) + D.T0;
       a[2] = t - D.rho_L * D.L_h * p / (2.0 * D.rcL);
       bad |= !isfinite(t);
     }
@@ -4232,6 +4526,13 @@ struct Launch {
       if (Q == 9) k_scalar_ym<R, S, 1, 9><<<g, b, 0, st>>>(d, runs, k, p, slot0, TY);
       else k_scalar_ym<R, S, 1, 5><<<g, b, 0, st>>>(d, runs, k, p, slot0, TY);
     }
+  }
+  // y-marching transfer fused into the T transport of the same step
+  static void tr_scalar_ym(int Q, dim3 g, hipStream_t st, const Dom* d, const int4* runs, unsigned k, Partial* p,
+                           const int* slot0, int TY) {
+    const dim3 b(TX, BY);
+    if (Q == 9) k_tr_scalar_ym<R, S, 9><<<g, b, 0, st>>>(d, runs, k, p, slot0, TY);
+    else k_tr_scalar_ym<R, S, 5><<<g, b, 0, st>>>(d, runs, k, p, slot0, TY);
   }
   // y-marching transfer over a list of column runs; slot0: partial slots of
   // the tile height TY in use

@@ -36,6 +36,8 @@ struct Launch {
   static void dtr_scalar(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, unsigned k, Partial* p);
   static void transfer_ym(dim3 g, hipStream_t st, const Dom* d, const int4* runs, unsigned k, Partial* p,
                           const int* slot0, int TY);
+  static void tr_scalar_ym(int Q, dim3 g, hipStream_t st, const Dom* d, const int4* runs, unsigned k, Partial* p,
+                           const int* slot0, int TY);
   static void scalar_ym(int field, int Q, dim3 g, hipStream_t st, const Dom* d, const int4* runs, unsigned k,
                         Partial* p, const int* slot0, int TY);
   static void scalar(int field, int TY, int Q, dim3 g, hipStream_t st, const Dom* d, const int4* t, unsigned k,
@@ -101,6 +103,7 @@ struct Ops {
   void (*dtr_phase)(int, dim3, hipStream_t, const Dom*, const int4*, unsigned, Partial*);
   void (*dtr_scalar)(int, dim3, hipStream_t, const Dom*, const int4*, unsigned, Partial*);
   void (*transfer_ym)(dim3, hipStream_t, const Dom*, const int4*, unsigned, Partial*, const int*, int);
+  void (*tr_scalar_ym)(int, dim3, hipStream_t, const Dom*, const int4*, unsigned, Partial*, const int*, int);
   void (*scalar_ym)(int, int, dim3, hipStream_t, const Dom*, const int4*, unsigned, Partial*, const int*, int);
   void (*scalar)(int, int, int, dim3, hipStream_t, const Dom*, const int4*, unsigned, Partial*);
   void (*flow)(int, dim3, hipStream_t, const Dom*, const int4*, unsigned);
@@ -114,7 +117,7 @@ struct Ops {
 template <class R, class S>
 Ops make_ops() {
   return Ops{Launch<R, S>::phase, Launch<R, S>::transfer, Launch<R, S>::phase_tr, Launch<R, S>::phase_tr_rows,
-             Launch<R, S>::phase_ym, Launch<R, S>::dtr_phase, Launch<R, S>::dtr_scalar, Launch<R, S>::transfer_ym, Launch<R, S>::scalar_ym, Launch<R, S>::scalar, Launch<R, S>::flow,
+             Launch<R, S>::phase_ym, Launch<R, S>::dtr_phase, Launch<R, S>::dtr_scalar, Launch<R, S>::transfer_ym, Launch<R, S>::tr_scalar_ym, Launch<R, S>::scalar_ym, Launch<R, S>::scalar, Launch<R, S>::flow,
              Launch<R, S>::diag_tiles, Launch<R, S>::tips, Launch<R, S>::init, Launch<R, S>::read,
              Launch<R, S>::write};
 }
@@ -185,6 +188,7 @@ struct lbm_ctx {
   bool deferrable = false;// D2Q5, one phase group with N_phi = 1, instantaneous coupling, domains >= 8 x 8
   bool pending = false;   // the last launched step's transfer is deferred
   bool one_U = false;     // every domain has U, all in one update group
+  bool one_T = false;     // one phase group; every domain has a transported T, all in one update group
   bool march_big = false; // the phase groups hold enough column runs to fill the chip
   bool marchable = false; // every domain 2D and at least 16 x 16 (the marching windows wrap once at most)
   int qs = 5;             // scalar lattice of the (2D) context: 5 or 9
@@ -226,7 +230,7 @@ Layout layout_of(const lbm_params& p) {
   L.rplanes = 4;                           // phi, four buffers
   L.splanes = 2 * (p.q_scalar - 1);        // phase s_i, two buffers
   if (p.has_U) { L.rplanes += 5; L.splanes += 2 * d; }   // U (four buffers), pending U
-  if (p.has_T) { L.rplanes += 3; L.splanes += 2 * d; }
+  if (p.has_T) { L.rplanes += 5; L.splanes += 2 * d; }   // T (four buffers), pending T
   if (p.has_flow) { L.rplanes += 2 + 2 * d; L.splanes += 2 * (d == 3 ? 18 : 8); }
   return L;
 }
@@ -366,6 +370,15 @@ static bool fuses_U(const lbm_ctx* c, unsigned k) {
   return k % c->g_U[0].N == 0;
 }
 
+// Whether the marching transfer of phase step k runs inside the T
+// transport of step k: both are due at k, every domain has a transported
+// T with instantaneous coupling in one update group, and the context
+// allows deferred transfers.
+static bool fuses_T(const lbm_ctx* c, unsigned k) {
+  if (!(c->defer && c->one_T && !c->fuse && use_march(c))) return false;
+  return k % c->g_T[0].N == 0 && k % c->g_phi[0].N == 0;
+}
+
 static void launch_step(lbm_ctx* c, hipStream_t st, unsigned k, bool last = false) {
   if (c->dim == 3) {
     c->ops3.step(c->H[0], st, c->d_dom, k, c->d_part);
@@ -381,7 +394,8 @@ static void launch_step(lbm_ctx* c, hipStream_t st, unsigned k, bool last = fals
       } else {
         if (use_march(c)) {
           c->ops.phase_ym(c->qs, dim3(g.runs.n), st, c->d_dom, g.runs.d, k);
-          c->ops.transfer_ym(dim3(g.runs.n), st, c->d_dom, g.runs.d, k, c->d_part, c->d_slot0[ti], TY);
+          if (!fuses_T(c, k))   // else inside the T transport, launched first below
+            c->ops.transfer_ym(dim3(g.runs.n), st, c->d_dom, g.runs.d, k, c->d_part, c->d_slot0[ti], TY);
         } else {
           if (c->pending)   // the previous step's transfer runs inside this phase kernel
             c->ops.dtr_phase(TY, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k, c->d_part);
@@ -394,6 +408,12 @@ static void launch_step(lbm_ctx* c, hipStream_t st, unsigned k, bool last = fals
       }
     }
   const bool march = use_march(c);
+  // the transfer fused into the T transport precedes the U transport, which
+  // reads the transferred U (the two transports are independent)
+  const bool trT = fuses_T(c, k);
+  if (trT)
+    for (auto& g : c->g_T)
+      c->ops.tr_scalar_ym(c->qs, dim3(g.runs.n), st, c->d_dom, g.runs.d, k, c->d_part, c->d_slot0[ti], TY);
   // (the U transport stays tiled: marching it measured slower on the
   // batched ensemble, 248 against 236 us per launch)
   for (auto& g : c->g_U)
@@ -404,7 +424,7 @@ static void launch_step(lbm_ctx* c, hipStream_t st, unsigned k, bool last = fals
         c->ops.scalar(0, TY, c->qs, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k, c->d_part);
     }
   for (auto& g : c->g_T)
-    if (k % g.N == 0) {
+    if (k % g.N == 0 && !trT) {
       if (march) c->ops.scalar_ym(1, c->qs, dim3(g.runs.n), st, c->d_dom, g.runs.d, k, c->d_part, c->d_slot0[ti], TY);
       else c->ops.scalar(1, TY, c->qs, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k, c->d_part);
     }
@@ -688,10 +708,8 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
       D.PU = take(pr);
     }
     if (q.has_T) {
-      for (int b = 0; b < 2; ++b) {
-        D.T[b] = take(pr);
-        D.jT[b] = take(align256(ps) * q.dim);
-      }
+      for (int b = 0; b < 4; ++b) D.T[b] = take(pr);
+      for (int b = 0; b < 2; ++b) D.jT[b] = take(align256(ps) * q.dim);
       D.PT = take(pr);
     }
     if (q.has_flow) {
@@ -719,13 +737,15 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
     for (int i = 0; i < n; ++i) runs += (long long)((p[i].nx + 63) / 64) * ((p[i].ny + kYRun - 1) / kYRun);
     c->march_big = runs >= 4 * 256;
   }
-  // the buffer indices of phi and U (write counts mod 4) repeat too; both
-  // counts are even over 2 lcm, so doubling once makes them multiples of 4
+  // the buffer indices of phi, U and T (write counts mod 4) repeat too;
+  // the counts are even over 2 lcm, so doubling once makes them multiples of 4
   c->cycle = 2 * lcm;
   for (int i = 0; i < n; ++i) {
+    const bool inst = p[i].coupling == LBM_COUPLE_INSTANT;
     const long long wphi = c->cycle / p[i].N_phi;
-    const long long wU = p[i].has_U ? (p[i].coupling == LBM_COUPLE_INSTANT ? wphi : 0) + c->cycle / p[i].N_U : 0;
-    if (wphi % 4 != 0 || wU % 4 != 0) {
+    const long long wU = p[i].has_U ? (inst ? wphi : 0) + c->cycle / p[i].N_U : 0;
+    const long long wT = p[i].has_T ? (inst && p[i].T_mode != LBM_T_PULLED ? wphi : 0) + c->cycle / p[i].N_T : 0;
+    if (wphi % 4 != 0 || wU % 4 != 0 || wT % 4 != 0) {
       c->cycle *= 2;
       break;
     }
@@ -828,7 +848,11 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
     }
   }
   c->one_U = c->g_U.size() == 1;
-  for (int i = 0; i < n; ++i) c->one_U &= p[i].has_U != 0;
+  c->one_T = c->g_T.size() == 1 && c->g_phi.size() == 1;
+  for (int i = 0; i < n; ++i) {
+    c->one_U &= p[i].has_U != 0;
+    c->one_T &= p[i].has_T != 0 && p[i].T_mode != LBM_T_PULLED && p[i].coupling == LBM_COUPLE_INSTANT;
+  }
   c->d_part = (Partial*)take(sizeof(Partial) * (size_t)tilesmax);
   c->d_slot = (int*)take(sizeof(int) * (size_t)tilesmax);
   for (int ti = 0; ti < kNTY; ++ti) c->d_slot0[ti] = (int*)take(sizeof(int) * (n + 1));
@@ -1046,8 +1070,8 @@ lbm_status lbm_kernel_times(lbm_ctx* c, int32_t reps, double* ms_out, double* pe
     out = double(ms) / reps;
     return LBM_OK;
   };
-  ms_out[5] = ms_out[6] = -1.0;
-  if (per_step) per_step[5] = per_step[6] = 0.0;
+  ms_out[5] = ms_out[6] = ms_out[7] = -1.0;
+  if (per_step) per_step[5] = per_step[6] = per_step[7] = 0.0;
   if (c->dim == 2 && !fused) {
     long long ndef = 0, nfu = 0;
     for (long long kk = 1; kk <= c->cycle; ++kk) {
@@ -1078,6 +1102,25 @@ lbm_status lbm_kernel_times(lbm_ctx* c, int32_t reps, double* ms_out, double* pe
       lbm_status s = time_launch(
           [&]() { c->ops.dtr_scalar(TY, dim3(g.ts[ti].n), c->stream, c->d_dom, g.ts[ti].d, k, c->d_part); },
           ms_out[6]);
+      if (s != LBM_OK) return s;
+    }
+    long long ntr = 0;
+    for (long long kk = 1; kk <= c->cycle; ++kk) ntr += fuses_T(c, (unsigned)kk);
+    if (ntr > 0) {   // the marching transfer inside the T transport
+      const double f = double(ntr) / double(c->cycle);
+      if (per_step) {
+        per_step[1] -= f;
+        per_step[3] -= f;
+        per_step[7] = f;
+      }
+      const Group& g = c->g_T[0];
+      const unsigned k = cycle_step(c, due(std::lcm(g.N, c->g_phi[0].N)));
+      lbm_status s = time_launch(
+          [&]() {
+            c->ops.tr_scalar_ym(c->qs, dim3(g.runs.n), c->stream, c->d_dom, g.runs.d, k, c->d_part,
+                                c->d_slot0[ti], TY);
+          },
+          ms_out[7]);
       if (s != LBM_OK) return s;
     }
   }

@@ -36,7 +36,7 @@ EXPORTS = ["lbm_workspace_bytes", "lbm_create", "lbm_init_seeds", "lbm_init_fron
            "lbm_read_fields",
            "lbm_write_fields", "lbm_configure", "lbm_kernel_times", "lbm_steps_done", "lbm_marching",
            "lbm_tile_rows", "lbm_last_error", "lbm_destroy"]
-KERNEL_KINDS = ("phase", "transfer", "U", "T", "flow", "phase_dtr", "U_dtr")
+KERNEL_KINDS = ("phase", "transfer", "U", "T", "flow", "phase_dtr", "U_dtr", "T_tr")
 
 
 class Params(ctypes.Structure):
@@ -238,8 +238,8 @@ class Simulation:
     def kernel_times(self, reps=200):
         """Per-kind average launch time (ms) and launches per base step.
         Leaves the state undefined (call ``init`` before stepping again)."""
-        ms = (ctypes.c_double * 7)()
-        per = (ctypes.c_double * 7)()
+        ms = (ctypes.c_double * 8)()
+        per = (ctypes.c_double * 8)()
         _check(self.lib, self.ctx, self.lib.lbm_kernel_times(self.ctx, int(reps), ms, per))
         return {k: (ms[i], per[i]) for i, k in enumerate(KERNEL_KINDS) if ms[i] >= 0}
 

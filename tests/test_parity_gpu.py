@@ -269,6 +269,42 @@ def test_marching_kernels_fp64(q):
     _compare(f"marching D2Q{q}", got, _oracle_fields(dom, names), TOL64)
 
 
+@pytest.mark.parametrize("storage,case", [("f64", "directional"), ("f16", "directional"), ("f32", "flow")])
+def test_marching_transfer_in_T_transport_is_bitwise_identical(storage, case):
+    """On the marching path the transfer of a step at which T is due runs
+    inside the T transport (every step in the directional case, N_T = 1;
+    every fourth with flow, N_T = 4, where the transport takes the
+    velocity).  Against the separate marching kernels: the same state bit
+    for bit and the same S_phi and J_U, over tile heights (partial slots),
+    graph replay or direct launches and calls that end inside a cycle."""
+    from paper_2609_25670_amd import simulation_for
+
+    if case == "directional":
+        wl = L.directional_2d(Le=10, coupling="instant", nx=150, ny=70)
+        names = ("phi", "U", "T", "f_phi", "jU", "jT")
+    else:
+        wl = L.reduced(L.thermosolutal_flow_1024(), 130, 75)
+        wl["domains"][0].update(tau0=40.0)
+        names = ("phi", "U", "T", "vel", "f_phi", "jU", "jT")
+    ref = None
+    for rows, g, defer in [(r, g, d) for r in (4, 16) for g in (True, False) for d in (False, True)]:
+        _say(f"case marching transfer in T {case} {storage} rows={rows} graph={g} defer={defer}")
+        sim = simulation_for(wl, storage=storage)
+        sim.configure(rows, g, False, True, defer)
+        sim.step(5)
+        sim.step(3)
+        diag = sim.step(41, diag=True)[0]
+        got = sim.read(0, names)
+        sim.close()
+        assert diag["nonfinite"] == 0
+        if ref is None:
+            ref = (got, diag)
+        else:
+            for n in names:
+                assert np.array_equal(got[n], ref[0][n]), (rows, g, defer, n)
+            assert diag["S_phi"] == ref[1]["S_phi"] and diag["J_U"] == ref[1]["J_U"]
+
+
 def test_checkpoint_restore_is_bitwise():
     """Read the full state, write it into a fresh context, continue: equal
     to the uninterrupted run, bit for bit."""
