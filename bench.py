@@ -143,6 +143,8 @@ def cpu_child(workload: str, steps: int) -> None:
     d0 = wl["domains"][0]
     if d0["dim"] == 3:       # bounded sample: the reduced 3D grid
         d0 = L.reduced(wl, 64, 64, 128)["domains"][0]
+    elif d0["nx"] * d0["ny"] > 512 * 512:   # bounded sample: a 512 x 512 grid
+        d0 = L.reduced(wl, 512, 512)["domains"][0]
     sites = sites_of(d0)
     dom = oracle.Domain(d0)
     t0 = time.perf_counter()

@@ -13,6 +13,7 @@ from .configs import (  # noqa: F401
     thermal_128,
     solutal_512,
     thermosolutal_flow_1024,
+    thermosolutal_flow_4096,
     ensemble_256,
     directional_3d,
     directional_2d,

@@ -138,6 +138,20 @@ def thermosolutal_flow_1024() -> dict:
                 steps_timed=2000, dtype="f32", storage="f16")
 
 
+def thermosolutal_flow_4096() -> dict:
+    """The forced-convection case enlarged to 4096 x 4096 (16.8 M sites, past
+    the 256 MB last-level cache in every storage format), for the HBM-bound
+    measurement of the four-field step.  The seed keeps its radius at the
+    centre.  tau0 = 100, D_L = 0.04, D_S = 4e-4 (tau_phi ~ 0.62), where the
+    scheme is stable: at the Section 4.3 scale it diverges within about 170
+    steps on any grid.  The kernels and bytes per site are those of the
+    1024 x 1024 case."""
+    wl = thermosolutal_flow_1024()
+    d = wl["domains"][0]
+    d.update(nx=4096, ny=4096, seeds=[(2047.5, 2047.5, 30.0)], tau0=100.0, D_L=0.04, D_S=4.0e-4)
+    return dict(wl, name="thermosolutal_flow_4096", domains=[d])
+
+
 # Table 1 lattice values (saline water, Section 4.4)
 TABLE1 = dict(
     L_h=133.6, Cp_L=1.676, Cp_S=0.836, kappa_L=0.0437, kappa_S=0.178,
@@ -311,6 +325,7 @@ WORKLOADS = {
     "thermal_128": thermal_128,
     "solutal_512": solutal_512,
     "thermosolutal_flow_1024": thermosolutal_flow_1024,
+    "thermosolutal_flow_4096": thermosolutal_flow_4096,
     "ensemble_256": ensemble_256,
     "directional_3d": directional_3d,
     "directional_2d": directional_2d,
