@@ -178,6 +178,26 @@ __device__ __forceinline__ void iso_grad(const R* b, int stride, R& gx, R& gy) {
   gy = (N - S) * R(1.0 / 3.0) + (NE + NW - SW - SE) * R(1.0 / 12.0);
 }
 
+// e . (a, b) and e . (a, b, c) for a lattice direction e.  The components
+// are compile-time constants once the direction loops are unrolled, so the
+// zero ones are dropped here: the compiler keeps a multiply by zero (0 * x
+// is not 0 for every x in IEEE arithmetic) and with it the load of x.  The
+// result equals the full sum for every finite input.
+template <class R>
+__device__ __forceinline__ R edot2(int ex, int ey, R a, R b) {
+  if (ex == 0) return ey == 0 ? R(0) : R(ey) * b;
+  if (ey == 0) return R(ex) * a;
+  return R(ex) * a + R(ey) * b;
+}
+template <class R>
+__device__ __forceinline__ R edot3(int ex, int ey, int ez, R a, R b, R c) {
+  if (ex == 0) return edot2(ey, ez, b, c);
+  if (ey == 0 && ez == 0) return R(ex) * a;
+  if (ey == 0) return R(ex) * a + R(ez) * c;
+  if (ez == 0) return R(ex) * a + R(ey) * b;
+  return R(ex) * a + R(ey) * b + R(ez) * c;
+}
+
 // D2Q5: e_1 = +x, e_2 = +y, e_3 = -x, e_4 = -y (compile-time tables so that
 // unrolled loops fold them into immediates).
 #define EX5(q) ((q) == 1 ? 1 : (q) == 3 ? -1 : 0)
@@ -442,13 +462,13 @@ __global__ __launch_bounds__(NTHR) void k_phase(const Dom* __restrict__ doms, co
                                    (wy && ((ey > 0 && gy == 0) || (ey < 0 && gy == ny - 1))));
         R dpost;
         if (wall) {
-          dpost = dPo * R(Lq::w(q)) - R(Lq::cK) * (R(ex) * sKx[ci] + R(ey) * sKy[ci]);
-          if constexpr (Q == 9) dpost -= R(Lq::cJ(q)) * (R(ex) * sJx[ci] + R(ey) * sJy[ci]);
+          dpost = dPo * R(Lq::w(q)) - R(Lq::cK) * edot2(ex, ey, sKx[ci], sKy[ci]);
+          if constexpr (Q == 9) dpost -= R(Lq::cJ(q)) * edot2(ex, ey, sJx[ci], sJy[ci]);
         } else {
           const int si = ci - ey * CW - ex;
           const R dphi = sphi[bc - ey * BW - ex] - phy;
-          dpost = (dphi + sP[si]) * R(Lq::w(q)) + R(Lq::cK) * (R(ex) * sKx[si] + R(ey) * sKy[si]);
-          if constexpr (Q == 9) dpost += R(Lq::cJ(q)) * (R(ex) * sJx[si] + R(ey) * sJy[si]);
+          dpost = (dphi + sP[si]) * R(Lq::w(q)) + R(Lq::cK) * edot2(ex, ey, sKx[si], sKy[si]);
+          if constexpr (Q == 9) dpost += R(Lq::cJ(q)) * edot2(ex, ey, sJx[si], sJy[si]);
         }
         dn[q] = (dpost - oA * sv[r][q - 1]) * iA;
       }
@@ -669,14 +689,14 @@ __global__ __launch_bounds__(NTHR) void k_phase_ym(const Dom* __restrict__ doms,
                                    (wy && ((ey > 0 && gy == 0) || (ey < 0 && gy == ny - 1))));
         R dpost;
         if (wall) {
-          dpost = dPo * R(Lq::w(q)) - R(Lq::cK) * (R(ex) * co[1][lx] + R(ey) * co[2][lx]);
-          if constexpr (Q == 9) dpost -= R(Lq::cJ(q)) * (R(ex) * co[3][lx] + R(ey) * co[4][lx]);
+          dpost = dPo * R(Lq::w(q)) - R(Lq::cK) * edot2(ex, ey, co[1][lx], co[2][lx]);
+          if constexpr (Q == 9) dpost -= R(Lq::cJ(q)) * edot2(ex, ey, co[3][lx], co[4][lx]);
         } else {
           const R(*cu)[YCW] = wc[(gy - ey) & 7];
           const int ux = lx - ex;
           const R dphi = wphi[(gy - ey) & 7][ux + 1] - phy;
-          dpost = (dphi + cu[0][ux]) * R(Lq::w(q)) + R(Lq::cK) * (R(ex) * cu[1][ux] + R(ey) * cu[2][ux]);
-          if constexpr (Q == 9) dpost += R(Lq::cJ(q)) * (R(ex) * cu[3][ux] + R(ey) * cu[4][ux]);
+          dpost = (dphi + cu[0][ux]) * R(Lq::w(q)) + R(Lq::cK) * edot2(ex, ey, cu[1][ux], cu[2][ux]);
+          if constexpr (Q == 9) dpost += R(Lq::cJ(q)) * edot2(ex, ey, cu[3][ux], cu[4][ux]);
         }
         dn[q] = (dpost - oA * sv[q - 1]) * iA;
       }
@@ -1261,11 +1281,11 @@ __global__ __launch_bounds__(NTHR) void k_dtr_phase(const Dom* __restrict__ doms
                                    (wy && ((ey > 0 && gy == 0) || (ey < 0 && gy == ny - 1))));
         R dpost;
         if (wall) {
-          dpost = dPo * R(1.0 / 6.0) - R(0.5) * (R(ex) * cKx[i] + R(ey) * cKy[i]);
+          dpost = dPo * R(1.0 / 6.0) - R(0.5) * edot2(ex, ey, cKx[i], cKy[i]);
         } else {
           const int si = i - ey * W1 - ex;
           const R dphi = sq[bc - ey * W3 - ex] - phy;
-          dpost = (dphi + cP[si]) * R(1.0 / 6.0) + R(0.5) * (R(ex) * cKx[si] + R(ey) * cKy[si]);
+          dpost = (dphi + cP[si]) * R(1.0 / 6.0) + R(0.5) * edot2(ex, ey, cKx[si], cKy[si]);
         }
         dn[q] = (dpost - oA * sv[r][q - 1]) * iA;
       }
@@ -1432,11 +1452,11 @@ __global__ __launch_bounds__(NTHR) void k_phase_tr(const Dom* __restrict__ doms,
       const int ex = EX5(q), ey = EY5(q);
       R dpost;
       if (bb[q]) {
-        dpost = dPo * R(1.0 / 6.0) - R(0.5) * (R(ex) * Kxo + R(ey) * Kyo);
+        dpost = dPo * R(1.0 / 6.0) - R(0.5) * edot2(ex, ey, Kxo, Kyo);
       } else {
         const int si = ci - ey * W3 - ex;
         const R dphi = sq[bq - ey * W4 - ex] - phy;
-        dpost = (dphi + cP[si]) * R(1.0 / 6.0) + R(0.5) * (R(ex) * cKx[si] + R(ey) * cKy[si]);
+        dpost = (dphi + cP[si]) * R(1.0 / 6.0) + R(0.5) * edot2(ex, ey, cKx[si], cKy[si]);
       }
       dn[q] = (dpost - oA * svq[q - 1]) * iA;
     }
@@ -1707,15 +1727,15 @@ __global__ __launch_bounds__(NTHR) void k_scalar(const Dom* __restrict__ doms, c
                                    (wy && ((ey > 0 && gy == 0) || (ey < 0 && gy == ny - 1))));
         if (EDGE && FIELD == 1 && D.T_dirlow && ey > 0 && gy == 0) {
           // anti-bounce-back to T0 at the wall y = -1/2 (the plane holds T - T0)
-          dq[q] = -(R(2) * cy + dPo) * R(Lq::w(q)) + R(Lq::cK) * (R(ex) * sKx[ci] + R(ey) * sKy[ci]);
-          if constexpr (Q == 9) dq[q] += R(Lq::cJ(q)) * (R(ex) * sJx[ci] + R(ey) * sJy[ci]);
+          dq[q] = -(R(2) * cy + dPo) * R(Lq::w(q)) + R(Lq::cK) * edot2(ex, ey, sKx[ci], sKy[ci]);
+          if constexpr (Q == 9) dq[q] += R(Lq::cJ(q)) * edot2(ex, ey, sJx[ci], sJy[ci]);
         } else if (wall) {
-          dq[q] = dPo * R(Lq::w(q)) - R(Lq::cK) * (R(ex) * sKx[ci] + R(ey) * sKy[ci]);
-          if constexpr (Q == 9) dq[q] -= R(Lq::cJ(q)) * (R(ex) * sJx[ci] + R(ey) * sJy[ci]);
+          dq[q] = dPo * R(Lq::w(q)) - R(Lq::cK) * edot2(ex, ey, sKx[ci], sKy[ci]);
+          if constexpr (Q == 9) dq[q] -= R(Lq::cJ(q)) * edot2(ex, ey, sJx[ci], sJy[ci]);
         } else {
           const int si = ci - ey * CW - ex;
-          dq[q] = (sC[si] - cy + sP[si]) * R(Lq::w(q)) + R(Lq::cK) * (R(ex) * sKx[si] + R(ey) * sKy[si]);
-          if constexpr (Q == 9) dq[q] += R(Lq::cJ(q)) * (R(ex) * sJx[si] + R(ey) * sJy[si]);
+          dq[q] = (sC[si] - cy + sP[si]) * R(Lq::w(q)) + R(Lq::cK) * edot2(ex, ey, sKx[si], sKy[si]);
+          if constexpr (Q == 9) dq[q] += R(Lq::cJ(q)) * edot2(ex, ey, sJx[si], sJy[si]);
         }
       }
       const unsigned o = gy * px + gx;
@@ -1948,10 +1968,10 @@ __global__ __launch_bounds__(NTHR) void k_dtr_scalar(const Dom* __restrict__ dom
         const bool wall = EDGE && ((wx && ((ex > 0 && gx == 0) || (ex < 0 && gx == nx - 1))) ||
                                    (wy && ((ey > 0 && gy == 0) || (ey < 0 && gy == ny - 1))));
         if (wall) {
-          dq[q] = dPo * R(Lq::w(q)) - R(Lq::cK) * (R(ex) * sKx[ci] + R(ey) * sKy[ci]);
+          dq[q] = dPo * R(Lq::w(q)) - R(Lq::cK) * edot2(ex, ey, sKx[ci], sKy[ci]);
         } else {
           const int si = ci - ey * W1 - ex;
-          dq[q] = (sC[si] - cy + sP[si]) * R(Lq::w(q)) + R(Lq::cK) * (R(ex) * sKx[si] + R(ey) * sKy[si]);
+          dq[q] = (sC[si] - cy + sP[si]) * R(Lq::w(q)) + R(Lq::cK) * edot2(ex, ey, sKx[si], sKy[si]);
         }
       }
       const unsigned o = oc[r];
@@ -2194,16 +2214,16 @@ __global__ __launch_bounds__(NTHR) void k_scalar_ym(const Dom* __restrict__ doms
                                    (wy && ((ey > 0 && gy == 0) || (ey < 0 && gy == ny - 1))));
         if (edge && FIELD == 1 && D.T_dirlow && ey > 0 && gy == 0) {
           // anti-bounce-back to T0 at the wall y = -1/2 (the plane holds T - T0)
-          dq[q] = -(R(2) * cy + dPo) * R(Lq::w(q)) + R(Lq::cK) * (R(ex) * co[2][lx] + R(ey) * co[3][lx]);
-          if constexpr (Q == 9) dq[q] += R(Lq::cJ(q)) * (R(ex) * co[4][lx] + R(ey) * co[5][lx]);
+          dq[q] = -(R(2) * cy + dPo) * R(Lq::w(q)) + R(Lq::cK) * edot2(ex, ey, co[2][lx], co[3][lx]);
+          if constexpr (Q == 9) dq[q] += R(Lq::cJ(q)) * edot2(ex, ey, co[4][lx], co[5][lx]);
         } else if (wall) {
-          dq[q] = dPo * R(Lq::w(q)) - R(Lq::cK) * (R(ex) * co[2][lx] + R(ey) * co[3][lx]);
-          if constexpr (Q == 9) dq[q] -= R(Lq::cJ(q)) * (R(ex) * co[4][lx] + R(ey) * co[5][lx]);
+          dq[q] = dPo * R(Lq::w(q)) - R(Lq::cK) * edot2(ex, ey, co[2][lx], co[3][lx]);
+          if constexpr (Q == 9) dq[q] -= R(Lq::cJ(q)) * edot2(ex, ey, co[4][lx], co[5][lx]);
         } else {
           const R(*cu)[YCW] = wc[(gy - ey) & 7];
           const int ux = lx - ex;
-          dq[q] = (cu[0][ux] - cy + cu[1][ux]) * R(Lq::w(q)) + R(Lq::cK) * (R(ex) * cu[2][ux] + R(ey) * cu[3][ux]);
-          if constexpr (Q == 9) dq[q] += R(Lq::cJ(q)) * (R(ex) * cu[4][ux] + R(ey) * cu[5][ux]);
+          dq[q] = (cu[0][ux] - cy + cu[1][ux]) * R(Lq::w(q)) + R(Lq::cK) * edot2(ex, ey, cu[2][ux], cu[3][ux]);
+          if constexpr (Q == 9) dq[q] += R(Lq::cJ(q)) * edot2(ex, ey, cu[4][ux], cu[5][ux]);
         }
       }
       const unsigned o = (unsigned)gy * (unsigned)px + (unsigned)gx;
@@ -2491,16 +2511,16 @@ __global__ __launch_bounds__(NTHR) void k_tr_scalar_ym(const Dom* __restrict__ d
                                    (wy && ((ey > 0 && gy == 0) || (ey < 0 && gy == ny - 1))));
         if (edge && D.T_dirlow && ey > 0 && gy == 0) {
           // anti-bounce-back to T0 at the wall y = -1/2 (the plane holds T - T0)
-          dq[q] = -(R(2) * cy + dPo) * R(Lq::w(q)) + R(Lq::cK) * (R(ex) * co[2][lx] + R(ey) * co[3][lx]);
-          if constexpr (Q == 9) dq[q] += R(Lq::cJ(q)) * (R(ex) * co[4][lx] + R(ey) * co[5][lx]);
+          dq[q] = -(R(2) * cy + dPo) * R(Lq::w(q)) + R(Lq::cK) * edot2(ex, ey, co[2][lx], co[3][lx]);
+          if constexpr (Q == 9) dq[q] += R(Lq::cJ(q)) * edot2(ex, ey, co[4][lx], co[5][lx]);
         } else if (wall) {
-          dq[q] = dPo * R(Lq::w(q)) - R(Lq::cK) * (R(ex) * co[2][lx] + R(ey) * co[3][lx]);
-          if constexpr (Q == 9) dq[q] -= R(Lq::cJ(q)) * (R(ex) * co[4][lx] + R(ey) * co[5][lx]);
+          dq[q] = dPo * R(Lq::w(q)) - R(Lq::cK) * edot2(ex, ey, co[2][lx], co[3][lx]);
+          if constexpr (Q == 9) dq[q] -= R(Lq::cJ(q)) * edot2(ex, ey, co[4][lx], co[5][lx]);
         } else {
           const R(*cu)[YCW] = wc[(gy - ey) & 7];
           const int ux = lx - ex;
-          dq[q] = (cu[0][ux] - cy + cu[1][ux]) * R(Lq::w(q)) + R(Lq::cK) * (R(ex) * cu[2][ux] + R(ey) * cu[3][ux]);
-          if constexpr (Q == 9) dq[q] += R(Lq::cJ(q)) * (R(ex) * cu[4][ux] + R(ey) * cu[5][ux]);
+          dq[q] = (cu[0][ux] - cy + cu[1][ux]) * R(Lq::w(q)) + R(Lq::cK) * edot2(ex, ey, cu[2][ux], cu[3][ux]);
+          if constexpr (Q == 9) dq[q] += R(Lq::cJ(q)) * edot2(ex, ey, cu[4][ux], cu[5][ux]);
         }
       }
       R sum = dq[0];
@@ -2553,7 +2573,7 @@ __device__ __forceinline__ void flow_eq(R rho, R ux, R uy, R dt, R* feq) {
                   R(1.0 / 36), R(1.0 / 36), R(1.0 / 36), R(1.0 / 36)};
 #pragma unroll
   for (int i = 0; i < 9; ++i) {
-    const R eu = (R(EX9(i)) * ux + R(EY9(i)) * uy) * dt;
+    const R eu = edot2(EX9(i), EY9(i), ux, uy) * dt;
     feq[i] = w[i] * rho * (R(1) + R(3) * eu + R(4.5) * eu * eu - R(1.5) * u2);
   }
 }
@@ -2600,7 +2620,8 @@ __device__ __forceinline__ void flow_collide(R rho, const R* d, R dt, R Fx, R Fy
   const R sr[9] = {R(0), s_e, s_eps, R(0), s_q, R(0), s_q, s_nu, s_nu};
   R dm[9];
 #pragma unroll
-  for (int i = 0; i < 9; ++i) dm[i] = -sr[i] * neq[i] + (R(1) - R(0.5) * sr[i]) * G[i];
+  for (int i = 0; i < 9; ++i)   // (the conserved rows relax at rate 0: no multiply by zero issued)
+    dm[i] = (i == 0 || i == 3 || i == 5) ? G[i] : -sr[i] * neq[i] + (R(1) - R(0.5) * sr[i]) * G[i];
   // f^+ - f = M^-1 dm, M^-1 = M^T diag(1/9, 1/36, 1/36, 1/6, 1/12, 1/6, 1/12, 1/4, 1/4)
   const R a0 = dm[0] * R(1.0 / 9), a1 = dm[1] * R(1.0 / 36), a2 = dm[2] * R(1.0 / 36);
   const R a3 = dm[3] * R(1.0 / 6), a4 = dm[4] * R(1.0 / 12), a5 = dm[5] * R(1.0 / 6), a6 = dm[6] * R(1.0 / 12);
@@ -2720,8 +2741,8 @@ __global__ __launch_bounds__(NTHR) void k_flow(const Dom* __restrict__ doms, con
 #pragma unroll
       for (int q = 0; q < 9; ++q) {
         drho += dn[q];
-        jx += R(EX9(q)) * dn[q];
-        jy += R(EY9(q)) * dn[q];
+        if (EX9(q) != 0) jx += R(EX9(q)) * dn[q];
+        if (EY9(q) != 0) jy += R(EY9(q)) * dn[q];
       }
       const R rho = rho_y + drho;
       const R irho = rcp(rho);
@@ -3484,10 +3505,10 @@ __global__ __launch_bounds__(256) void k3z_phase(const Dom* __restrict__ doms, u
         if (up) {
           const R* cu = &wcol[zslot3(z - ez)][0][0];
           const int ur = cr - ey * ZRW - ex;
-          const R Ke = R(ex) * cu[ZNR + ur] + R(ey) * cu[2 * ZNR + ur] + R(ez) * cu[3 * ZNR + ur];
+          const R Ke = edot3(ex, ey, ez, cu[ZNR + ur], cu[2 * ZNR + ur], cu[3 * ZNR + ur]);
           dpost = (wphi[zslot4(z - ez)][cb - ey * ZBW - ex] - py + cu[ur]) * R(0.125) + R(0.5) * Ke;
         } else {
-          dpost = dPy * R(0.125) - R(0.5) * (R(ex) * Ky[0] + R(ey) * Ky[1] + R(ez) * Ky[2]);
+          dpost = dPy * R(0.125) - R(0.5) * edot3(ex, ey, ez, Ky[0], Ky[1], Ky[2]);
         }
         dn[q] = (dpost - oA * svcur[q - 1]) * iA;
         sum += dn[q];
@@ -3704,10 +3725,10 @@ __global__ __launch_bounds__(256) void k3z_scalar(const Dom* __restrict__ doms, 
         if (up) {
           const R* cu = &wcol[zslot3(z - ez)][0][0];
           const int ur = cr - ey * ZRW - ex;
-          const R Ke = R(ex) * cu[ZNR + ur] + R(ey) * cu[2 * ZNR + ur] + R(ez) * cu[3 * ZNR + ur];
+          const R Ke = edot3(ex, ey, ez, cu[ZNR + ur], cu[2 * ZNR + ur], cu[3 * ZNR + ur]);
           dq[q] = (wchi[zslot3(z - ez)][ur] - cy + cu[ur]) * R(0.125) + R(0.5) * Ke;
         } else {
-          const R Ke = R(ex) * Ky[0] + R(ey) * Ky[1] + R(ez) * Ky[2];
+          const R Ke = edot3(ex, ey, ez, Ky[0], Ky[1], Ky[2]);
           if (dir && (ez > 0 || (ez < 0 && pulled))) {
             const R Tw = ez > 0 ? Tw_lo : Tw_hi;
             dq[q] = R(0.125) * (R(2) * Tw - R(2) * cy - dPy) + R(0.5) * Ke;
@@ -3716,9 +3737,9 @@ __global__ __launch_bounds__(256) void k3z_scalar(const Dom* __restrict__ doms, 
           }
         }
         chin += dq[q];
-        j[0] += R(ex) * dq[q];
-        j[1] += R(ey) * dq[q];
-        j[2] += R(ez) * dq[q];
+        if (ex != 0) j[0] += R(ex) * dq[q];
+        if (ey != 0) j[1] += R(ey) * dq[q];
+        if (ez != 0) j[2] += R(ez) * dq[q];
       }
       chin += cy;
       const unsigned o = zoff(G, gx, gy, z);
@@ -3925,21 +3946,22 @@ __global__ __launch_bounds__(256) void k3z_transfer(const Dom* __restrict__ doms
 // {3e_x^2 - |e|^2, e_y^2 - e_z^2, e_x e_y, e_y e_z, e_x e_z}.
 template <class R>
 __device__ __forceinline__ void mrt19_op(const R* x, R sq, R se, R seps, R snu, R* y) {
+  // (the basis entries are compile-time constants once the loops are
+  // unrolled; the zero ones are skipped, see edot2)
   R c0 = R(0), cx = R(0), cy = R(0), cz = R(0), ce = R(0), cp = R(0), cn[5] = {R(0), R(0), R(0), R(0), R(0)};
 #pragma unroll
   for (int q = 0; q < 19; ++q) {
     const int ex = e19(q, 0), ey = e19(q, 1), ez = e19(q, 2), e2 = ex * ex + ey * ey + ez * ez;
+    const int kn[5] = {3 * ex * ex - e2, ey * ey - ez * ez, ex * ey, ey * ez, ex * ez};
     c0 += x[q];
-    cx += R(ex) * x[q];
-    cy += R(ey) * x[q];
-    cz += R(ez) * x[q];
+    if (ex != 0) cx += R(ex) * x[q];
+    if (ey != 0) cy += R(ey) * x[q];
+    if (ez != 0) cz += R(ez) * x[q];
     ce += R(19 * e2 - 30) * x[q];
     cp += R((21 * e2 * e2 - 53 * e2 + 24) / 2) * x[q];
-    cn[0] += R(3 * ex * ex - e2) * x[q];
-    cn[1] += R(ey * ey - ez * ez) * x[q];
-    cn[2] += R(ex * ey) * x[q];
-    cn[3] += R(ey * ez) * x[q];
-    cn[4] += R(ex * ez) * x[q];
+#pragma unroll
+    for (int i = 0; i < 5; ++i)
+      if (kn[i] != 0) cn[i] += R(kn[i]) * x[q];
   }
   c0 *= R(1.0 / 19);
   cx *= R(0.1);
@@ -3955,12 +3977,20 @@ __device__ __forceinline__ void mrt19_op(const R* x, R sq, R se, R seps, R snu, 
 #pragma unroll
   for (int q = 0; q < 19; ++q) {
     const int ex = e19(q, 0), ey = e19(q, 1), ez = e19(q, 2), e2 = ex * ex + ey * ey + ez * ez;
-    const R pc = c0 + cx * R(ex) + cy * R(ey) + cz * R(ez);
+    const int kn[5] = {3 * ex * ex - e2, ey * ey - ez * ez, ex * ey, ey * ez, ex * ez};
+    const R pc = c0 + edot3(ex, ey, ez, cx, cy, cz);
     const R pe = ce * R(19 * e2 - 30);
     const R pp = cp * R((21 * e2 * e2 - 53 * e2 + 24) / 2);
-    const R pn = cn[0] * R(3 * ex * ex - e2) + cn[1] * R(ey * ey - ez * ez) + cn[2] * R(ex * ey) +
-                 cn[3] * R(ey * ez) + cn[4] * R(ex * ez);
-    y[q] = sq * x[q] - sq * pc - (sq - se) * pe - (sq - seps) * pp - (sq - snu) * pn;
+    R pn = R(0);
+    bool nz = false;
+#pragma unroll
+    for (int i = 0; i < 5; ++i)
+      if (kn[i] != 0) {
+        pn = nz ? pn + cn[i] * R(kn[i]) : cn[i] * R(kn[i]);
+        nz = true;
+      }
+    y[q] = sq * x[q] - sq * pc - (sq - se) * pe - (sq - seps) * pp;
+    if (nz) y[q] -= (sq - snu) * pn;
   }
 }
 
@@ -3976,7 +4006,8 @@ __device__ __forceinline__ void flow_collide3(R rho, R* d, R dt, R c, const R* F
   for (int q = 1; q < 19; ++q) {
     d[0] -= d[q];
 #pragma unroll
-    for (int a = 0; a < 3; ++a) j[a] += R(e19(q, a)) * d[q];
+    for (int a = 0; a < 3; ++a)
+      if (e19(q, a) != 0) j[a] += R(e19(q, a)) * d[q];
   }
   const R irho = rcp(rho);
   R u[3], U[3];
@@ -3989,10 +4020,10 @@ __device__ __forceinline__ void flow_collide3(R rho, R* d, R dt, R c, const R* F
   R x[19], Fi[19];
 #pragma unroll
   for (int q = 0; q < 19; ++q) {
-    const R eU = R(e19(q, 0)) * U[0] + R(e19(q, 1)) * U[1] + R(e19(q, 2)) * U[2];
+    const R eU = edot3(e19(q, 0), e19(q, 1), e19(q, 2), U[0], U[1], U[2]);
     x[q] = d[q] - R(w19(q)) * rho * (R(3) * eU + R(4.5) * eU * eU - R(1.5) * U2);   // f - f^eq
     if (forced) {
-      const R eF = R(e19(q, 0)) * F[0] + R(e19(q, 1)) * F[1] + R(e19(q, 2)) * F[2];
+      const R eF = edot3(e19(q, 0), e19(q, 1), e19(q, 2), F[0], F[1], F[2]);
       const R uF = (u[0] * F[0] + u[1] * F[1] + u[2] * F[2]) * dt;
       Fi[q] = R(w19(q)) * (R(3) * (eF - uF) + R(9) * eU * eF) * dt;     // Guo, velocity space
     }
@@ -4155,9 +4186,9 @@ __global__ __launch_bounds__(256) void k3z_flow(const Dom* __restrict__ doms, un
           }
         }
         drho += dn[q];
-        j[0] += R(ex) * dn[q];
-        j[1] += R(ey) * dn[q];
-        j[2] += R(ez) * dn[q];
+        if (ex != 0) j[0] += R(ex) * dn[q];
+        if (ey != 0) j[1] += R(ey) * dn[q];
+        if (ez != 0) j[2] += R(ez) * dn[q];
       }
       const R rho = ry + drho, irho = rcp(rho);
       const unsigned o = zoff(G, gx, gy, z);
