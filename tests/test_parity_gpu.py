@@ -350,16 +350,20 @@ def test_nonfinite_state_is_reported():
     sim.close()
 
 
-def test_solutal_full_size_bench_configuration_fp32():
+@pytest.mark.parametrize("steps,tol", [(8, 1e-7), (40, 1e-7)])
+def test_solutal_full_size_bench_configuration_fp32(steps, tol):
     """512 x 512 solutal case exactly as the benchmark launches it (FP32,
-    autotuned tiles, graph replay) for two whole cycles against the oracle
-    on the full grid, at the FP32 tolerance."""
+    autotuned tiles, deferred transfers, graph replay of the 16-step cycle)
+    against the oracle on the full grid: 8 steps (direct launches) and 40
+    (two graph replays, then 8 direct steps).  FP32 arithmetic and storage
+    (unit roundoff 6e-8) keep the relative L2 near 1e-8 over these windows
+    (3e-9 and 9e-9 measured for phi); the bar leaves a tenfold margin."""
     wl = L.solutal_512()
     names = ("phi", "U")
-    _say("case solutal_512 full size fp32 8 steps")
-    (got,), _ = _gpu(wl, 8, storage="f32", names=names)
-    dom = oracle.run(wl["domains"][0], 8)
+    _say(f"case solutal_512 full size fp32 {steps} steps")
+    (got,), _ = _gpu(wl, steps, storage="f32", names=names)
+    dom = oracle.run(wl["domains"][0], steps)
     for n in names:
         e = _rel(got[n], getattr(dom, n))
         _say(f"  solutal_512: {n} rel L2 = {e:.3e}")
-        assert e < 2e-6, (n, e)
+        assert e < tol, (n, e)
