@@ -718,7 +718,7 @@ __global__ __launch_bounds__(NTHR) void k_phase_ym(const Dom* __restrict__ doms,
 // dT = rho_L L_h dphi / (2 rhoCp_eff(phi^{q+1})).  The compact divergence
 // uses the D2Q9-weighted stencil; ghost J across a wall is the mirror image
 // (normal component negated).  Instantaneous coupling adds dU to U and dT to
-// T, each written to the other buffer (neighbours' U* and T* are read); the
+// T, each written to the next buffer (neighbours' U* and T* are read); the
 // accumulated variant adds both to the pending planes.  Because
 // the U and T states are stored as (chi, j), adding w_i d to every
 // population is exactly adding d to chi.

@@ -6,7 +6,7 @@
 // field is due (k mod N_chi == 0, Eq. 34) in the order phase, transfer, U, T,
 // flow; whole cycles of 2 * lcm(N_chi) base steps, or twice that (the
 // period after which every buffer index repeats: parities of the
-// double-buffered planes, write counts mod 4 of phi and U), are captured
+// double-buffered planes, write counts mod 4 of phi, U and T), are captured
 // once into a HIP graph and replayed.
 #include <hip/hip_bf16.h>
 #include <hip/hip_fp16.h>
