@@ -666,48 +666,55 @@ __global__ __launch_bounds__(NTHR) void k_phase_ym(const Dom* __restrict__ doms,
     collide(cur, y + 1);
     __syncthreads();
     const int gy = y + ty;
-    if (tx < w && gy < yb) {
-      // anisotropic pull streaming (Eq. 26) into the own site, in deviations
-      const int gx = x0 + tx, lx = tx + 1;
-      const bool edge = (wx && (x0 == 0 || x0 + w >= nx)) || (wy && (y == 0 || y + 4 >= ny));
-      const R A = wA[gy & 7][tx], iA = rcp(A), oA = R(1) - A;
-      const R phy = wphi[gy & 7][lx + 1];
-      const R(*co)[YCW] = wc[gy & 7];
-      const R dPo = co[0][lx];
-      R sv[Q - 1];
+    // walls tested only on iterations whose rows or column touch one (the
+    // test is uniform over the block)
+    const bool edge = (wx && (x0 == 0 || x0 + w >= nx)) || (wy && (y == 0 || y + 4 >= ny));
+    auto stream_rows = [&](auto edge_c) {
+      constexpr bool EDGE = decltype(edge_c)::value;
+      if (tx < w && gy < yb) {
+        // anisotropic pull streaming (Eq. 26) into the own site, in deviations
+        const int gx = x0 + tx, lx = tx + 1;
+        const R A = wA[gy & 7][tx], iA = rcp(A), oA = R(1) - A;
+        const R phy = wphi[gy & 7][lx + 1];
+        const R(*co)[YCW] = wc[gy & 7];
+        const R dPo = co[0][lx];
+        R sv[Q - 1];
 #pragma unroll
-      for (int q = 0; q < Q - 1; ++q) sv[q] = wsv[gy & 7][q][tx];
-      R s0 = R(0);
+        for (int q = 0; q < Q - 1; ++q) sv[q] = wsv[gy & 7][q][tx];
+        R s0 = R(0);
 #pragma unroll
-      for (int q = 0; q < Q - 1; ++q) s0 -= sv[q];
-      R dn[Q];
-      dn[0] = (dPo * R(Lq::w(0)) - oA * s0) * iA;
+        for (int q = 0; q < Q - 1; ++q) s0 -= sv[q];
+        R dn[Q];
+        dn[0] = (dPo * R(Lq::w(0)) - oA * s0) * iA;
 #pragma unroll
-      for (int q = 1; q < Q; ++q) {
-        const int ex = Lq::ex(q), ey = Lq::ey(q);
-        const bool wall = edge && ((wx && ((ex > 0 && gx == 0) || (ex < 0 && gx == nx - 1))) ||
-                                   (wy && ((ey > 0 && gy == 0) || (ey < 0 && gy == ny - 1))));
-        R dpost;
-        if (wall) {
-          dpost = dPo * R(Lq::w(q)) - R(Lq::cK) * edot2(ex, ey, co[1][lx], co[2][lx]);
-          if constexpr (Q == 9) dpost -= R(Lq::cJ(q)) * edot2(ex, ey, co[3][lx], co[4][lx]);
-        } else {
-          const R(*cu)[YCW] = wc[(gy - ey) & 7];
-          const int ux = lx - ex;
-          const R dphi = wphi[(gy - ey) & 7][ux + 1] - phy;
-          dpost = (dphi + cu[0][ux]) * R(Lq::w(q)) + R(Lq::cK) * edot2(ex, ey, cu[1][ux], cu[2][ux]);
-          if constexpr (Q == 9) dpost += R(Lq::cJ(q)) * edot2(ex, ey, cu[3][ux], cu[4][ux]);
+        for (int q = 1; q < Q; ++q) {
+          const int ex = Lq::ex(q), ey = Lq::ey(q);
+          const bool wall = EDGE && ((wx && ((ex > 0 && gx == 0) || (ex < 0 && gx == nx - 1))) ||
+                                     (wy && ((ey > 0 && gy == 0) || (ey < 0 && gy == ny - 1))));
+          R dpost;
+          if (wall) {
+            dpost = dPo * R(Lq::w(q)) - R(Lq::cK) * edot2(ex, ey, co[1][lx], co[2][lx]);
+            if constexpr (Q == 9) dpost -= R(Lq::cJ(q)) * edot2(ex, ey, co[3][lx], co[4][lx]);
+          } else {
+            const R(*cu)[YCW] = wc[(gy - ey) & 7];
+            const int ux = lx - ex;
+            const R dphi = wphi[(gy - ey) & 7][ux + 1] - phy;
+            dpost = (dphi + cu[0][ux]) * R(Lq::w(q)) + R(Lq::cK) * edot2(ex, ey, cu[1][ux], cu[2][ux]);
+            if constexpr (Q == 9) dpost += R(Lq::cJ(q)) * edot2(ex, ey, cu[3][ux], cu[4][ux]);
+          }
+          dn[q] = (dpost - oA * sv[q - 1]) * iA;
         }
-        dn[q] = (dpost - oA * sv[q - 1]) * iA;
+        R dphin = dn[0];
+#pragma unroll
+        for (int q = 1; q < Q; ++q) dphin += dn[q];
+        const unsigned o = (unsigned)gy * (unsigned)px + (unsigned)gx;
+        sto(phi_out, o, phy + dphin);
+#pragma unroll
+        for (int q = 1; q < Q; ++q) sto(plane(s_out, (q - 1) * pl), o, dn[q] - dphin * R(Lq::w(q)));
       }
-      R dphin = dn[0];
-#pragma unroll
-      for (int q = 1; q < Q; ++q) dphin += dn[q];
-      const unsigned o = (unsigned)gy * (unsigned)px + (unsigned)gx;
-      sto(phi_out, o, phy + dphin);
-#pragma unroll
-      for (int q = 1; q < Q; ++q) sto(plane(s_out, (q - 1) * pl), o, dn[q] - dphin * R(Lq::w(q)));
-    }
+    };
+    if (edge) stream_rows(std::true_type{});
+    else stream_rows(std::false_type{});
     __syncthreads();
   }
 }
@@ -2199,55 +2206,62 @@ __global__ __launch_bounds__(NTHR) void k_scalar_ym(const Dom* __restrict__ doms
     collide(cur, y + 1);
     __syncthreads();
     const int gy = y + ty;
-    if (tx < w && gy < yb) {
-      // pull streaming (Eq. 25) in deviations d_i = f_i - w_i chi(y)
-      const int gx = x0 + tx, lx = tx + 1;
-      const bool edge = (wx && (x0 == 0 || x0 + w >= nx)) || (wy && (y == 0 || y + 4 >= ny));
-      const R(*co)[YCW] = wc[gy & 7];
-      const R cy = co[0][lx], dPo = co[1][lx];
-      R dq[Q];
-      dq[0] = dPo * R(Lq::w(0));
+    // walls tested only on iterations whose rows or column touch one (the
+    // test is uniform over the block)
+    const bool edge = (wx && (x0 == 0 || x0 + w >= nx)) || (wy && (y == 0 || y + 4 >= ny));
+    auto stream_rows = [&](auto edge_c) {
+      constexpr bool EDGE = decltype(edge_c)::value;
+      if (tx < w && gy < yb) {
+        // pull streaming (Eq. 25) in deviations d_i = f_i - w_i chi(y)
+        const int gx = x0 + tx, lx = tx + 1;
+        const R(*co)[YCW] = wc[gy & 7];
+        const R cy = co[0][lx], dPo = co[1][lx];
+        R dq[Q];
+        dq[0] = dPo * R(Lq::w(0));
 #pragma unroll
-      for (int q = 1; q < Q; ++q) {
-        const int ex = Lq::ex(q), ey = Lq::ey(q);
-        const bool wall = edge && ((wx && ((ex > 0 && gx == 0) || (ex < 0 && gx == nx - 1))) ||
-                                   (wy && ((ey > 0 && gy == 0) || (ey < 0 && gy == ny - 1))));
-        if (edge && FIELD == 1 && D.T_dirlow && ey > 0 && gy == 0) {
-          // anti-bounce-back to T0 at the wall y = -1/2 (the plane holds T - T0)
-          dq[q] = -(R(2) * cy + dPo) * R(Lq::w(q)) + R(Lq::cK) * edot2(ex, ey, co[2][lx], co[3][lx]);
-          if constexpr (Q == 9) dq[q] += R(Lq::cJ(q)) * edot2(ex, ey, co[4][lx], co[5][lx]);
-        } else if (wall) {
-          dq[q] = dPo * R(Lq::w(q)) - R(Lq::cK) * edot2(ex, ey, co[2][lx], co[3][lx]);
-          if constexpr (Q == 9) dq[q] -= R(Lq::cJ(q)) * edot2(ex, ey, co[4][lx], co[5][lx]);
-        } else {
-          const R(*cu)[YCW] = wc[(gy - ey) & 7];
-          const int ux = lx - ex;
-          dq[q] = (cu[0][ux] - cy + cu[1][ux]) * R(Lq::w(q)) + R(Lq::cK) * edot2(ex, ey, cu[2][ux], cu[3][ux]);
-          if constexpr (Q == 9) dq[q] += R(Lq::cJ(q)) * edot2(ex, ey, cu[4][ux], cu[5][ux]);
+        for (int q = 1; q < Q; ++q) {
+          const int ex = Lq::ex(q), ey = Lq::ey(q);
+          const bool wall = EDGE && ((wx && ((ex > 0 && gx == 0) || (ex < 0 && gx == nx - 1))) ||
+                                     (wy && ((ey > 0 && gy == 0) || (ey < 0 && gy == ny - 1))));
+          if (EDGE && FIELD == 1 && D.T_dirlow && ey > 0 && gy == 0) {
+            // anti-bounce-back to T0 at the wall y = -1/2 (the plane holds T - T0)
+            dq[q] = -(R(2) * cy + dPo) * R(Lq::w(q)) + R(Lq::cK) * edot2(ex, ey, co[2][lx], co[3][lx]);
+            if constexpr (Q == 9) dq[q] += R(Lq::cJ(q)) * edot2(ex, ey, co[4][lx], co[5][lx]);
+          } else if (wall) {
+            dq[q] = dPo * R(Lq::w(q)) - R(Lq::cK) * edot2(ex, ey, co[2][lx], co[3][lx]);
+            if constexpr (Q == 9) dq[q] -= R(Lq::cJ(q)) * edot2(ex, ey, co[4][lx], co[5][lx]);
+          } else {
+            const R(*cu)[YCW] = wc[(gy - ey) & 7];
+            const int ux = lx - ex;
+            dq[q] = (cu[0][ux] - cy + cu[1][ux]) * R(Lq::w(q)) + R(Lq::cK) * edot2(ex, ey, cu[2][ux], cu[3][ux]);
+            if constexpr (Q == 9) dq[q] += R(Lq::cJ(q)) * edot2(ex, ey, cu[4][ux], cu[5][ux]);
+          }
         }
-      }
-      const unsigned o = (unsigned)gy * (unsigned)px + (unsigned)gx;
-      R sum = dq[0];
+        const unsigned o = (unsigned)gy * (unsigned)px + (unsigned)gx;
+        R sum = dq[0];
 #pragma unroll
-      for (int q = 1; q < Q; ++q) sum += dq[q];
-      R chin = cy + sum;
-      if (accum) {
-        chin += cur.pend;
-        sto(pend, o, R(0));
-        amax = fmax(amax, fabs(cur.pend));
-      }
-      sto(cout, o, chin);
-      R jx = R(0), jy = R(0);
+        for (int q = 1; q < Q; ++q) sum += dq[q];
+        R chin = cy + sum;
+        if (accum) {
+          chin += cur.pend;
+          sto(pend, o, R(0));
+          amax = fmax(amax, fabs(cur.pend));
+        }
+        sto(cout, o, chin);
+        R jx = R(0), jy = R(0);
 #pragma unroll
-      for (int q = 1; q < Q; ++q) {
-        if (Lq::ex(q) > 0) jx += dq[q];
-        if (Lq::ex(q) < 0) jx -= dq[q];
-        if (Lq::ey(q) > 0) jy += dq[q];
-        if (Lq::ey(q) < 0) jy -= dq[q];
+        for (int q = 1; q < Q; ++q) {
+          if (Lq::ex(q) > 0) jx += dq[q];
+          if (Lq::ex(q) < 0) jx -= dq[q];
+          if (Lq::ey(q) > 0) jy += dq[q];
+          if (Lq::ey(q) < 0) jy -= dq[q];
+        }
+        sto(jout, o, jx);
+        sto(plane(jout, pl), o, jy);
       }
-      sto(jout, o, jx);
-      sto(plane(jout, pl), o, jy);
-    }
+    };
+    if (edge) stream_rows(std::true_type{});
+    else stream_rows(std::false_type{});
     __syncthreads();
   }
   if (FIELD == 0 && accum && part) {
@@ -2482,63 +2496,70 @@ __global__ __launch_bounds__(NTHR) void k_tr_scalar_ym(const Dom* __restrict__ d
     collide(cur, y + 1);
     __syncthreads();
     const int gy = y + ty;
-    if (tx < w && gy < yb) {
-      const int gx = x0 + tx, lx = tx + 1;
-      const unsigned o = (unsigned)gy * (unsigned)px + (unsigned)gx;
-      if (hasU) {   // U* of the transfer
-        const R pn = wphi[gy & 7][lx + 1];
-        const R dphi = pn - me.po;
-        const int rm = (gy - 1) & 7, r0 = gy & 7, rp = (gy + 1) & 7;
-        const R div = (wJx[r0][lx + 1] - wJx[r0][lx - 1]) * R(1.0 / 3.0) +
-                      (wJx[rp][lx + 1] - wJx[rp][lx - 1] - wJx[rm][lx - 1] + wJx[rm][lx + 1]) * R(1.0 / 12.0) +
-                      (wJy[rp][lx] - wJy[rm][lx]) * R(1.0 / 3.0) +
-                      (wJy[rp][lx + 1] + wJy[rp][lx - 1] - wJy[rm][lx - 1] - wJy[rm][lx + 1]) * R(1.0 / 12.0);
-        const R Us = me.U;
-        const R dU = ((R(1) + omk * (Us + Uref)) * dphi - R(2) * div) * rcp(opk - omk * pn);
-        amax = fmax(amax, fabs(dU));
-        sto(Uout, o, Us + dU);
-      }
-      // pull streaming (Eq. 25) of T in deviations d_i = f_i - w_i chi(y)
-      const bool edge = (wx && (x0 == 0 || x0 + w >= nx)) || (wy && (y == 0 || y + 4 >= ny));
-      const R(*co)[YCW] = wc[gy & 7];
-      const R cy = co[0][lx], dPo = co[1][lx];
-      R dq[Q];
-      dq[0] = dPo * R(Lq::w(0));
-#pragma unroll
-      for (int q = 1; q < Q; ++q) {
-        const int ex = Lq::ex(q), ey = Lq::ey(q);
-        const bool wall = edge && ((wx && ((ex > 0 && gx == 0) || (ex < 0 && gx == nx - 1))) ||
-                                   (wy && ((ey > 0 && gy == 0) || (ey < 0 && gy == ny - 1))));
-        if (edge && D.T_dirlow && ey > 0 && gy == 0) {
-          // anti-bounce-back to T0 at the wall y = -1/2 (the plane holds T - T0)
-          dq[q] = -(R(2) * cy + dPo) * R(Lq::w(q)) + R(Lq::cK) * edot2(ex, ey, co[2][lx], co[3][lx]);
-          if constexpr (Q == 9) dq[q] += R(Lq::cJ(q)) * edot2(ex, ey, co[4][lx], co[5][lx]);
-        } else if (wall) {
-          dq[q] = dPo * R(Lq::w(q)) - R(Lq::cK) * edot2(ex, ey, co[2][lx], co[3][lx]);
-          if constexpr (Q == 9) dq[q] -= R(Lq::cJ(q)) * edot2(ex, ey, co[4][lx], co[5][lx]);
-        } else {
-          const R(*cu)[YCW] = wc[(gy - ey) & 7];
-          const int ux = lx - ex;
-          dq[q] = (cu[0][ux] - cy + cu[1][ux]) * R(Lq::w(q)) + R(Lq::cK) * edot2(ex, ey, cu[2][ux], cu[3][ux]);
-          if constexpr (Q == 9) dq[q] += R(Lq::cJ(q)) * edot2(ex, ey, cu[4][ux], cu[5][ux]);
+    // walls tested only on iterations whose rows or column touch one (the
+    // test is uniform over the block)
+    const bool edge = (wx && (x0 == 0 || x0 + w >= nx)) || (wy && (y == 0 || y + 4 >= ny));
+    auto stream_rows = [&](auto edge_c) {
+      constexpr bool EDGE = decltype(edge_c)::value;
+      if (tx < w && gy < yb) {
+        const int gx = x0 + tx, lx = tx + 1;
+        const unsigned o = (unsigned)gy * (unsigned)px + (unsigned)gx;
+        if (hasU) {   // U* of the transfer
+          const R pn = wphi[gy & 7][lx + 1];
+          const R dphi = pn - me.po;
+          const int rm = (gy - 1) & 7, r0 = gy & 7, rp = (gy + 1) & 7;
+          const R div = (wJx[r0][lx + 1] - wJx[r0][lx - 1]) * R(1.0 / 3.0) +
+                        (wJx[rp][lx + 1] - wJx[rp][lx - 1] - wJx[rm][lx - 1] + wJx[rm][lx + 1]) * R(1.0 / 12.0) +
+                        (wJy[rp][lx] - wJy[rm][lx]) * R(1.0 / 3.0) +
+                        (wJy[rp][lx + 1] + wJy[rp][lx - 1] - wJy[rm][lx - 1] - wJy[rm][lx + 1]) * R(1.0 / 12.0);
+          const R Us = me.U;
+          const R dU = ((R(1) + omk * (Us + Uref)) * dphi - R(2) * div) * rcp(opk - omk * pn);
+          amax = fmax(amax, fabs(dU));
+          sto(Uout, o, Us + dU);
         }
-      }
-      R sum = dq[0];
+        // pull streaming (Eq. 25) of T in deviations d_i = f_i - w_i chi(y)
+        const R(*co)[YCW] = wc[gy & 7];
+        const R cy = co[0][lx], dPo = co[1][lx];
+        R dq[Q];
+        dq[0] = dPo * R(Lq::w(0));
 #pragma unroll
-      for (int q = 1; q < Q; ++q) sum += dq[q];
-      const R chin = cy + sum;
-      sto(cout, o, chin);
-      R jx = R(0), jy = R(0);
+        for (int q = 1; q < Q; ++q) {
+          const int ex = Lq::ex(q), ey = Lq::ey(q);
+          const bool wall = EDGE && ((wx && ((ex > 0 && gx == 0) || (ex < 0 && gx == nx - 1))) ||
+                                     (wy && ((ey > 0 && gy == 0) || (ey < 0 && gy == ny - 1))));
+          if (EDGE && D.T_dirlow && ey > 0 && gy == 0) {
+            // anti-bounce-back to T0 at the wall y = -1/2 (the plane holds T - T0)
+            dq[q] = -(R(2) * cy + dPo) * R(Lq::w(q)) + R(Lq::cK) * edot2(ex, ey, co[2][lx], co[3][lx]);
+            if constexpr (Q == 9) dq[q] += R(Lq::cJ(q)) * edot2(ex, ey, co[4][lx], co[5][lx]);
+          } else if (wall) {
+            dq[q] = dPo * R(Lq::w(q)) - R(Lq::cK) * edot2(ex, ey, co[2][lx], co[3][lx]);
+            if constexpr (Q == 9) dq[q] -= R(Lq::cJ(q)) * edot2(ex, ey, co[4][lx], co[5][lx]);
+          } else {
+            const R(*cu)[YCW] = wc[(gy - ey) & 7];
+            const int ux = lx - ex;
+            dq[q] = (cu[0][ux] - cy + cu[1][ux]) * R(Lq::w(q)) + R(Lq::cK) * edot2(ex, ey, cu[2][ux], cu[3][ux]);
+            if constexpr (Q == 9) dq[q] += R(Lq::cJ(q)) * edot2(ex, ey, cu[4][ux], cu[5][ux]);
+          }
+        }
+        R sum = dq[0];
 #pragma unroll
-      for (int q = 1; q < Q; ++q) {
-        if (Lq::ex(q) > 0) jx += dq[q];
-        if (Lq::ex(q) < 0) jx -= dq[q];
-        if (Lq::ey(q) > 0) jy += dq[q];
-        if (Lq::ey(q) < 0) jy -= dq[q];
+        for (int q = 1; q < Q; ++q) sum += dq[q];
+        const R chin = cy + sum;
+        sto(cout, o, chin);
+        R jx = R(0), jy = R(0);
+#pragma unroll
+        for (int q = 1; q < Q; ++q) {
+          if (Lq::ex(q) > 0) jx += dq[q];
+          if (Lq::ex(q) < 0) jx -= dq[q];
+          if (Lq::ey(q) > 0) jy += dq[q];
+          if (Lq::ey(q) < 0) jy -= dq[q];
+        }
+        sto(jout, o, jx);
+        sto(plane(jout, pl), o, jy);
       }
-      sto(jout, o, jx);
-      sto(plane(jout, pl), o, jy);
-    }
+    };
+    if (edge) stream_rows(std::true_type{});
+    else stream_rows(std::false_type{});
     __syncthreads();
   }
   if (part && hasU) {
