@@ -327,7 +327,9 @@ __device__ __forceinline__ void load_box2(R* box, const GLOBAL R* __restrict__ s
   const bool two = tx < BW - TX;
   const int gx1 = two ? ghost(x0 - 2 + tx + TX, nx, bcx) : 0;
 #pragma unroll
-  for (int ly = ty; ly < BH; ly += BY) {
+  for (int r = 0; r < (BH + BY - 1) / BY; ++r) {   // rows ty, ty + BY, ... below BH
+    const int ly = ty + r * BY;
+    if (ly >= BH) break;
     const unsigned row = (unsigned)(ghost(y0 - 2 + ly, ny, bcy) * px);
     box[ly * BW + tx] = ldo(src, row + gx0);
     if (two) box[ly * BW + tx + TX] = ldo(src, row + gx1);
