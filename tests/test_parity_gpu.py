@@ -331,6 +331,27 @@ def test_checkpoint_restore_is_bitwise():
         assert np.array_equal(got[n], ref[n]), n
 
 
+def test_tile_rows_and_marching_queries():
+    """lbm_tile_rows reports the fixed tile height, 0 before the autotuner
+    has run and its pick afterwards; lbm_marching follows lbm_configure."""
+    from paper_2609_25670_amd import simulation_for
+
+    wl = L.reduced(L.solutal_512(), 130, 75)
+    _say("case tile-rows and marching queries")
+    sim = simulation_for(wl, storage="f32")
+    assert sim.tile_rows == 0
+    sim.step(4)
+    assert sim.tile_rows in (4, 8, 16, 32)
+    for rows in (4, 8, 16, 32):
+        sim.configure(rows, True)
+        assert sim.tile_rows == rows
+    sim.configure(8, True, False, True)
+    assert sim.marching
+    sim.configure(8, True, False, False)
+    assert not sim.marching
+    sim.close()
+
+
 def test_nonfinite_state_is_reported():
     """A NaN written into U is caught by the diagnostics: the step call
     returns LBM_EUNSTABLE and the count is reported."""
