@@ -11,6 +11,9 @@ constexpr int TX = 64;        // tile width: one wavefront across x
 constexpr int BY = 4;         // thread rows per block (256 threads)
 constexpr int NTHR = TX * BY;
 constexpr int MAX_SEEDS = 4;
+// 2D marching runs: YCOL columns (plus one ring cell each side: one
+// wavefront) by YRUN rows (a multiple of every tile height)
+constexpr int YCOL = 62, YRUN = 64;
 // |grad phi|^2 below which the interface normal is taken as zero (a_s = 1,
 // N = 0, no anti-trapping current): gradients of 1e-8 and less are far below
 // the interface scale and their direction is not resolved in FP64.
@@ -53,6 +56,7 @@ struct Dom {
   double T_grad, V_pull, z_front;
   int u0_liquid;
   int qs;                       // scalar lattice: 5 (D2Q5), 9 (D2Q9) or 7 (D3Q7)
+  int rbase, nruns;             // 2D: first index and count of the domain's marching runs
   // base steps to add to a kernel's step argument to get the absolute step:
   // zero for direct launches, the step at replay start for a captured graph
   // (whose launches carry the steps of its first cycle)

@@ -488,17 +488,30 @@ __global__ __launch_bounds__(NTHR) void k_phase(const Dom* __restrict__ doms, co
 }
 
 // =================================================================== 2D marching in y
-// For large domains: one block owns a 64-wide column over a run of rows
-// (the host lists the runs) and walks up through it four rows at a time (one row per
-// wavefront).  The phase field is kept in an eight-row LDS ring (the
-// column plus two cells on each side), the collisions of the four rows
-// ahead go into an eight-row LDS ring (the column plus one ring cell on
-// each side), and the four current rows are streamed from the rows below,
-// at and above.  Ring collisions are recomputed only in x (3% at 64
-// columns instead of 16% for a 64 x 16 tile), and the loads of the next
-// four rows are issued before the current rows are computed.  The
-// arithmetic is the tile kernels', expression for expression.
-constexpr int YCW = TX + 2, YBW = TX + 4;
+// For large domains: one block owns a column of YOW = 62 sites over a run
+// of rows (the host lists the runs) and walks up through it four rows at a
+// time (one row per wavefront).  The phase field is kept in an eight-row
+// LDS ring (the column plus two cells on each side), the collisions of the
+// four rows ahead go into an eight-row LDS ring (the column plus one ring
+// cell on each side: 64 cells, one per lane), and the four current rows are
+// streamed from the rows below, at and above.  Ring collisions are
+// recomputed only in x (3% instead of 16% for a 64 x 16 tile), and the
+// loads of the next four rows are issued before the current rows are
+// computed.  The arithmetic is the tile kernels', expression for
+// expression.
+// A run is YOW = 62 columns wide, so that its collision row (the columns
+// plus one ring cell on each side) is exactly one wavefront of 64 lanes:
+// lane tx holds collision column tx, lanes 1 .. w the own columns.  (With
+// 64-column runs the two ring cells of every row cost wave 0 a second
+// collision pass, a quarter more collision work per block.)
+constexpr int YOW = TX - 2, YCW = TX, YBW = TX + 2;
+static_assert(YOW == YCOL, "run width shared with the host");
+
+// Slot of a run's largest |dU| (and injected U) in the per-run maxima that
+// the diagnostics reduce: the domain's runs are numbered row by row.
+__device__ __forceinline__ int ym_run(const Dom& D, int x0, int ya) {
+  return D.rbase + (ya / YRUN) * ((D.nx + YOW - 1) / YOW) + x0 / YOW;
+}
 
 // isotropic gradient with D2Q9 weights from three rows (below, at, above)
 template <class R>
@@ -509,18 +522,14 @@ __device__ __forceinline__ void iso_grad_rows(const R* rm, const R* r0, const R*
   gy = (N - S) * R(1.0 / 3.0) + (NE + NW - SW - SE) * R(1.0 / 12.0);
 }
 
-// collision cells of a thread for the four rows r0 .. r0 + 3: its column
-// cell of row r0 + ty, and for threads 0..7 one of the eight ring cells
+// collision cell of a thread for the four rows r0 .. r0 + 3: column tx of
+// row r0 + ty (columns 0 and w + 1 are the ring cells of a run w wide).
+// There is one cell per thread; the second slot (i = 1) of the callers'
+// loops is never taken.
 __device__ __forceinline__ bool ym_cell(int i, int tx, int ty, int tid, int w, int r0, int& col, int& row) {
-  if (i == 0) {
-    col = tx + 1;
-    row = r0 + ty;
-    return tx < w;
-  }
-  if (tid >= 8) return false;
-  col = (tid & 1) ? w + 1 : 0;
-  row = r0 + (tid >> 1);
-  return true;
+  col = tx;
+  row = r0 + ty;
+  return i == 0 && tx <= w + 1;
 }
 
 template <class R, class S, int Q>
@@ -579,7 +588,7 @@ __global__ __launch_bounds__(NTHR) void k_phase_ym(const Dom* __restrict__ doms,
   const int nx = D.nx, ny = D.ny, px = D.px, bcx = D.bc[0], bcy = D.bc[1];
   const long long pl = D.plane;
   const int x0 = t.y, ya = t.z, yb = t.w;
-  const int w = min(TX, nx - x0);
+  const int w = min(YOW, nx - x0);
   const unsigned np = n_phi(D, k - 1);
   const int ib = par(np), ob = ib ^ 1;
   GLOBAL const R* __restrict__ phi_in = gp<const R>(D.phi[qb(np)]);
@@ -673,9 +682,9 @@ __global__ __launch_bounds__(NTHR) void k_phase_ym(const Dom* __restrict__ doms,
     const bool edge = (wx && (x0 == 0 || x0 + w >= nx)) || (wy && (y == 0 || y + 4 >= ny));
     auto stream_rows = [&](auto edge_c) {
       constexpr bool EDGE = decltype(edge_c)::value;
-      if (tx < w && gy < yb) {
+      if (tx >= 1 && tx <= w && gy < yb) {
         // anisotropic pull streaming (Eq. 26) into the own site, in deviations
-        const int gx = x0 + tx, lx = tx + 1;
+        const int gx = x0 + tx - 1, lx = tx;
         const R A = wA[gy & 7][tx], iA = rcp(A), oA = R(1) - A;
         const R phy = wphi[gy & 7][lx + 1];
         const R(*co)[YCW] = wc[gy & 7];
@@ -922,8 +931,8 @@ template <class R>
 __device__ __forceinline__ void ym_load_own(int ny, int px, int x0, int w, int row, int tx, bool hasU,
                                             GLOBAL const R* pn, GLOBAL const R* po, GLOBAL const R* Uin,
                                             GLOBAL const R* Tsrc, YTrOwn<R>& m) {
-  if (tx >= w || row < 0 || row >= ny) return;
-  const unsigned o = (unsigned)row * (unsigned)px + (unsigned)(x0 + tx);
+  if (tx < 1 || tx > w || row < 0 || row >= ny) return;
+  const unsigned o = (unsigned)row * (unsigned)px + (unsigned)(x0 + tx - 1);
   m.po = ldo(po, o);
   if (hasU) m.U = ldo(Uin, o);
   else m.pn = ldo(pn, o);
@@ -933,13 +942,11 @@ __device__ __forceinline__ void ym_load_own(int ny, int px, int x0, int w, int r
 // phase-step transfer (Eq. 36-39) marching up a column: J on the rows
 // ahead (column plus ring; beyond a wall, the boundary node's J with the
 // normal component negated), then the compact divergence, dU, dT and the
-// injection on the current rows.  The largest |dU| of the run goes to the
-// partial slot of its first tile at the tile height in use (the run's
-// other tiles' slots are cleared), where the diagnostics reduce it.
+// injection on the current rows.  The largest |dU| of the run goes to its
+// slot of the per-run maxima, where the diagnostics reduce it.
 template <class R>
 __global__ __launch_bounds__(NTHR) void k_transfer_ym(const Dom* __restrict__ doms, const int4* __restrict__ runs,
-                                                       unsigned k, Partial* __restrict__ part,
-                                                       const int* __restrict__ slot0, int TY) {
+                                                       unsigned k, double2* __restrict__ rmax) {
   __shared__ R wphi[8][YBW];
   __shared__ R wJx[8][YCW], wJy[8][YCW];
   __shared__ R red[NTHR / 64];
@@ -950,7 +957,7 @@ __global__ __launch_bounds__(NTHR) void k_transfer_ym(const Dom* __restrict__ do
   if (k % D.N_phi) return;
   const int nx = D.nx, ny = D.ny, px = D.px, bcx = D.bc[0], bcy = D.bc[1];
   const int x0 = t.y, ya = t.z, yb = t.w;
-  const int w = min(TX, nx - x0);
+  const int w = min(YOW, nx - x0);
   GLOBAL const R* __restrict__ phi_old = gp<const R>(D.phi[qb(n_phi(D, k - 1))]);
   GLOBAL const R* __restrict__ phi_new = gp<const R>(D.phi[qb(n_phi(D, k))]);
   const unsigned nU = (D.accum ? 0u : (k - 1) / D.N_phi) + (k - 1) / D.N_U;
@@ -1037,8 +1044,8 @@ __global__ __launch_bounds__(NTHR) void k_transfer_ym(const Dom* __restrict__ do
     if (hasU) flux(cur, y + 1);
     __syncthreads();
     const int gy = y + ty;
-    if (tx < w && gy < yb) {
-      const int gx = x0 + tx, lx = tx + 1;
+    if (tx >= 1 && tx <= w && gy < yb) {
+      const int gx = x0 + tx - 1, lx = tx;
       const unsigned o = (unsigned)gy * (unsigned)px + (unsigned)gx;
       const R pn = hasU ? wphi[gy & 7][lx + 1] : me.pn;
       const R dphi = pn - me.po;
@@ -1067,19 +1074,16 @@ __global__ __launch_bounds__(NTHR) void k_transfer_ym(const Dom* __restrict__ do
     }
     __syncthreads();
   }
-  if (part && hasU) {
+  if (rmax && hasU) {
     for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_down(amax, off, 64));
     if (tx == 0) red[ty] = amax;
     __syncthreads();
     if (tid == 0) {
       R m = red[0];
       for (int wv = 1; wv < NTHR / 64; ++wv) m = fmax(m, red[wv]);
-      const int ntx = (nx + 63) / 64, tcol = x0 / 64;
-      for (int r = ya / TY; r * TY < yb; ++r) {
-        Partial& P = part[slot0[t.x] + r * ntx + tcol];
-        P.S_phi = r == ya / TY ? double(m) : 0.0;
-        if (!accum) P.J_U = r == ya / TY ? double(m) : 0.0;
-      }
+      double2& P = rmax[ym_run(D, x0, ya)];
+      P.x = double(m);
+      if (!accum) P.y = double(m);
     }
   }
 }
@@ -2061,7 +2065,8 @@ __device__ __forceinline__ void ym_load_sc(int nx, int ny, int px, int bcx, int 
     }
   }
   const int oy = r0 - 1 + ty;
-  if (pend && inputs && tx < w && oy >= 0 && oy < ny) in.pend = ldo(pend, (unsigned)oy * (unsigned)px + (unsigned)(x0 + tx));
+  if (pend && inputs && tx >= 1 && tx <= w && oy >= 0 && oy < ny)
+    in.pend = ldo(pend, (unsigned)oy * (unsigned)px + (unsigned)(x0 + tx - 1));
 }
 
 // scalar transport (U: FIELD 0, T: FIELD 1) marching up a column: the
@@ -2069,11 +2074,10 @@ __device__ __forceinline__ void ym_load_sc(int nx, int ny, int px, int bcx, int 
 // (7) or (11) and the source of Eq. (8) or (12) with grad chi from Eq. (40)
 // on the rows ahead, then the pull streaming of Eq. (25) on the current
 // rows.  With accumulated coupling the largest pending |dU| of the run goes
-// to the partial slot of its first tile at the tile height in use.
+// to its slot of the per-run maxima.
 template <class R, class S, int FIELD, int Q>
 __global__ __launch_bounds__(NTHR) void k_scalar_ym(const Dom* __restrict__ doms, const int4* __restrict__ runs,
-                                                     unsigned k, Partial* __restrict__ part,
-                                                     const int* __restrict__ slot0, int TY) {
+                                                     unsigned k, double2* __restrict__ rmax) {
   using Lq = Lat2<Q>;
   using SR = typename RawT<S>::type;
   constexpr int NV = Q == 9 ? 6 : 4;   // chi, dt Q, Kx, Ky (and j_eq in D2Q9)
@@ -2089,7 +2093,7 @@ __global__ __launch_bounds__(NTHR) void k_scalar_ym(const Dom* __restrict__ doms
   const int nx = D.nx, ny = D.ny, px = D.px, bcx = D.bc[0], bcy = D.bc[1];
   const long long pl = D.plane;
   const int x0 = t.y, ya = t.z, yb = t.w;
-  const int w = min(TX, nx - x0);
+  const int w = min(YOW, nx - x0);
   GLOBAL const R* __restrict__ cin;
   GLOBAL R* __restrict__ cout;
   GLOBAL const SR* __restrict__ jin;
@@ -2213,9 +2217,9 @@ __global__ __launch_bounds__(NTHR) void k_scalar_ym(const Dom* __restrict__ doms
     const bool edge = (wx && (x0 == 0 || x0 + w >= nx)) || (wy && (y == 0 || y + 4 >= ny));
     auto stream_rows = [&](auto edge_c) {
       constexpr bool EDGE = decltype(edge_c)::value;
-      if (tx < w && gy < yb) {
+      if (tx >= 1 && tx <= w && gy < yb) {
         // pull streaming (Eq. 25) in deviations d_i = f_i - w_i chi(y)
-        const int gx = x0 + tx, lx = tx + 1;
+        const int gx = x0 + tx - 1, lx = tx;
         const R(*co)[YCW] = wc[gy & 7];
         const R cy = co[0][lx], dPo = co[1][lx];
         R dq[Q];
@@ -2266,15 +2270,14 @@ __global__ __launch_bounds__(NTHR) void k_scalar_ym(const Dom* __restrict__ doms
     else stream_rows(std::false_type{});
     __syncthreads();
   }
-  if (FIELD == 0 && accum && part) {
+  if (FIELD == 0 && accum && rmax) {
     for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_down(amax, off, 64));
     if (tx == 0) red[ty] = amax;
     __syncthreads();
     if (tid == 0) {
       R m = red[0];
       for (int wv = 1; wv < NTHR / 64; ++wv) m = fmax(m, red[wv]);
-      const int ntx = (nx + 63) / 64, tcol = x0 / 64;
-      for (int r = ya / TY; r * TY < yb; ++r) part[slot0[t.x] + r * ntx + tcol].J_U = r == ya / TY ? double(m) : 0.0;
+      rmax[ym_run(D, x0, ya)].y = double(m);
     }
   }
 }
@@ -2340,8 +2343,7 @@ __device__ __forceinline__ void ym_load_ts(int nx, int ny, int px, int bcx, int 
 // Bitwise identical to the two separate kernels.
 template <class R, class S, int Q>
 __global__ __launch_bounds__(NTHR) void k_tr_scalar_ym(const Dom* __restrict__ doms, const int4* __restrict__ runs,
-                                                        unsigned k, Partial* __restrict__ part,
-                                                        const int* __restrict__ slot0, int TY) {
+                                                        unsigned k, double2* __restrict__ rmax) {
   using Lq = Lat2<Q>;
   using SR = typename RawT<S>::type;
   constexpr int NV = Q == 9 ? 6 : 4;   // chi, dt Q, Kx, Ky (and j_eq in D2Q9)
@@ -2357,7 +2359,7 @@ __global__ __launch_bounds__(NTHR) void k_tr_scalar_ym(const Dom* __restrict__ d
   const int nx = D.nx, ny = D.ny, px = D.px, bcx = D.bc[0], bcy = D.bc[1];
   const long long pl = D.plane;
   const int x0 = t.y, ya = t.z, yb = t.w;
-  const int w = min(TX, nx - x0);
+  const int w = min(YOW, nx - x0);
   GLOBAL const R* __restrict__ phi_old = gp<const R>(D.phi[qb(n_phi(D, k - 1))]);
   GLOBAL const R* __restrict__ phi_new = gp<const R>(D.phi[qb(n_phi(D, k))]);
   const bool hasU = D.has_U;
@@ -2503,8 +2505,8 @@ __global__ __launch_bounds__(NTHR) void k_tr_scalar_ym(const Dom* __restrict__ d
     const bool edge = (wx && (x0 == 0 || x0 + w >= nx)) || (wy && (y == 0 || y + 4 >= ny));
     auto stream_rows = [&](auto edge_c) {
       constexpr bool EDGE = decltype(edge_c)::value;
-      if (tx < w && gy < yb) {
-        const int gx = x0 + tx, lx = tx + 1;
+      if (tx >= 1 && tx <= w && gy < yb) {
+        const int gx = x0 + tx - 1, lx = tx;
         const unsigned o = (unsigned)gy * (unsigned)px + (unsigned)gx;
         if (hasU) {   // U* of the transfer
           const R pn = wphi[gy & 7][lx + 1];
@@ -2564,19 +2566,16 @@ __global__ __launch_bounds__(NTHR) void k_tr_scalar_ym(const Dom* __restrict__ d
     else stream_rows(std::false_type{});
     __syncthreads();
   }
-  if (part && hasU) {
+  if (rmax && hasU) {
     for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_down(amax, off, 64));
     if (tx == 0) red[ty] = amax;
     __syncthreads();
     if (tid == 0) {
       R m = red[0];
       for (int wv = 1; wv < NTHR / 64; ++wv) m = fmax(m, red[wv]);
-      const int ntx = (nx + 63) / 64, tcol = x0 / 64;
-      for (int r = ya / TY; r * TY < yb; ++r) {
-        Partial& P = part[slot0[t.x] + r * ntx + tcol];
-        P.S_phi = r == ya / TY ? double(m) : 0.0;
-        P.J_U = r == ya / TY ? double(m) : 0.0;
-      }
+      double2& P = rmax[ym_run(D, x0, ya)];
+      P.x = double(m);
+      P.y = double(m);
     }
   }
 }
@@ -3059,8 +3058,11 @@ __global__ __launch_bounds__(NTHR) void k_diag_tiles(const Dom* __restrict__ dom
 
 // One block per domain: fixed-order reduction of the tile partials (the
 // partial slots of a domain are listed in slot[] in spatial order).
+// (marching contexts: S_phi, and J_U with instantaneous coupling, come from
+// the per-run maxima of the marching transfer)
 __global__ void k_diag_final(const Dom* __restrict__ doms, const Partial* __restrict__ part,
-                             const int* __restrict__ slot, const int* __restrict__ slot0, DiagOut* __restrict__ out) {
+                             const int* __restrict__ slot, const int* __restrict__ slot0,
+                             const double2* __restrict__ rmax, int marching, DiagOut* __restrict__ out) {
   __shared__ double red[7][4];
   const int d = blockIdx.x;
   const int b = slot0[d], e = slot0[d + 1];
@@ -3074,6 +3076,16 @@ __global__ void k_diag_final(const Dom* __restrict__ doms, const Partial* __rest
     a[4] = fmax(a[4], P.S_phi);
     a[5] = fmax(a[5], P.J_U);
     a[6] += P.nonfinite;
+  }
+  if (marching) {
+    const Dom& D = doms[d];
+    double ms = 0.0, mj = 0.0;
+    for (int i = D.rbase + threadIdx.x; i < D.rbase + D.nruns; i += blockDim.x) {
+      ms = fmax(ms, rmax[i].x);
+      mj = fmax(mj, rmax[i].y);
+    }
+    a[4] = ms;
+    if (!D.accum) a[5] = mj;
   }
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int j = 0; j < 7; ++j) {
@@ -4571,28 +4583,27 @@ struct Launch {
   }
   // y-marching scalar transport over a list of column runs
   static void scalar_ym(int field, int Q, dim3 g, hipStream_t st, const Dom* d, const int4* runs, unsigned k,
-                        Partial* p, const int* slot0, int TY) {
+                        double2* rmax) {
     const dim3 b(TX, BY);
     if (field == 0) {
-      if (Q == 9) k_scalar_ym<R, S, 0, 9><<<g, b, 0, st>>>(d, runs, k, p, slot0, TY);
-      else k_scalar_ym<R, S, 0, 5><<<g, b, 0, st>>>(d, runs, k, p, slot0, TY);
+      if (Q == 9) k_scalar_ym<R, S, 0, 9><<<g, b, 0, st>>>(d, runs, k, rmax);
+      else k_scalar_ym<R, S, 0, 5><<<g, b, 0, st>>>(d, runs, k, rmax);
     } else {
-      if (Q == 9) k_scalar_ym<R, S, 1, 9><<<g, b, 0, st>>>(d, runs, k, p, slot0, TY);
-      else k_scalar_ym<R, S, 1, 5><<<g, b, 0, st>>>(d, runs, k, p, slot0, TY);
+      if (Q == 9) k_scalar_ym<R, S, 1, 9><<<g, b, 0, st>>>(d, runs, k, rmax);
+      else k_scalar_ym<R, S, 1, 5><<<g, b, 0, st>>>(d, runs, k, rmax);
     }
   }
   // y-marching transfer fused into the T transport of the same step
-  static void tr_scalar_ym(int Q, dim3 g, hipStream_t st, const Dom* d, const int4* runs, unsigned k, Partial* p,
-                           const int* slot0, int TY) {
+  static void tr_scalar_ym(int Q, dim3 g, hipStream_t st, const Dom* d, const int4* runs, unsigned k,
+                           double2* rmax) {
     const dim3 b(TX, BY);
-    if (Q == 9) k_tr_scalar_ym<R, S, 9><<<g, b, 0, st>>>(d, runs, k, p, slot0, TY);
-    else k_tr_scalar_ym<R, S, 5><<<g, b, 0, st>>>(d, runs, k, p, slot0, TY);
+    if (Q == 9) k_tr_scalar_ym<R, S, 9><<<g, b, 0, st>>>(d, runs, k, rmax);
+    else k_tr_scalar_ym<R, S, 5><<<g, b, 0, st>>>(d, runs, k, rmax);
   }
   // y-marching transfer over a list of column runs; slot0: partial slots of
   // the tile height TY in use
-  static void transfer_ym(dim3 g, hipStream_t st, const Dom* d, const int4* runs, unsigned k, Partial* p,
-                          const int* slot0, int TY) {
-    k_transfer_ym<R><<<g, dim3(TX, BY), 0, st>>>(d, runs, k, p, slot0, TY);
+  static void transfer_ym(dim3 g, hipStream_t st, const Dom* d, const int4* runs, unsigned k, double2* rmax) {
+    k_transfer_ym<R><<<g, dim3(TX, BY), 0, st>>>(d, runs, k, rmax);
   }
   // y-marching phase kernel over a list of column runs
   static void phase_ym(int Q, dim3 g, hipStream_t st, const Dom* d, const int4* runs, unsigned k) {
@@ -4671,8 +4682,8 @@ struct Launch {
 };
 
 void diag_final(int ndom, hipStream_t st, const Dom* d, const Partial* p, const int* slot, const int* slot0,
-                DiagOut* o) {
-  k_diag_final<<<ndom, 256, 0, st>>>(d, p, slot, slot0, o);
+                const double2* rmax, int marching, DiagOut* o) {
+  k_diag_final<<<ndom, 256, 0, st>>>(d, p, slot, slot0, rmax, marching, o);
 }
 
 template struct Launch<double, double>;

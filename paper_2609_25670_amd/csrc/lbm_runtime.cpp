@@ -34,12 +34,11 @@ struct Launch {
   static void phase_ym(int Q, dim3 g, hipStream_t st, const Dom* d, const int4* runs, unsigned k);
   static void dtr_phase(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, unsigned k, Partial* p);
   static void dtr_scalar(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, unsigned k, Partial* p);
-  static void transfer_ym(dim3 g, hipStream_t st, const Dom* d, const int4* runs, unsigned k, Partial* p,
-                          const int* slot0, int TY);
-  static void tr_scalar_ym(int Q, dim3 g, hipStream_t st, const Dom* d, const int4* runs, unsigned k, Partial* p,
-                           const int* slot0, int TY);
+  static void transfer_ym(dim3 g, hipStream_t st, const Dom* d, const int4* runs, unsigned k, double2* rmax);
+  static void tr_scalar_ym(int Q, dim3 g, hipStream_t st, const Dom* d, const int4* runs, unsigned k,
+                           double2* rmax);
   static void scalar_ym(int field, int Q, dim3 g, hipStream_t st, const Dom* d, const int4* runs, unsigned k,
-                        Partial* p, const int* slot0, int TY);
+                        double2* rmax);
   static void scalar(int field, int TY, int Q, dim3 g, hipStream_t st, const Dom* d, const int4* t, unsigned k,
                      Partial* p);
   static void flow(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, unsigned k);
@@ -52,7 +51,7 @@ struct Launch {
                     const double* src, long long n);
 };
 void diag_final(int ndom, hipStream_t st, const Dom* d, const Partial* p, const int* slot, const int* slot0,
-                DiagOut* o);
+                const double2* rmax, int marching, DiagOut* o);
 template <class R, class S>
 struct Launch3 {
   static void phase(const Dom& h, hipStream_t st, const Dom* d, unsigned k);
@@ -78,7 +77,6 @@ constexpr int kNTY = 4;
 constexpr int kTYs[kNTY] = {4, 8, 16, 32};
 constexpr long long kMaxGraphSteps = 4096;
 constexpr int kMaxCodes = 96;
-constexpr int kYRun = 64;          // rows per run of the 2D marching kernels (a multiple of every tile height)
 constexpr int kStagePlanes = 20;   // host staging planes: holds one D3Q19 population group
 
 std::string g_create_error;
@@ -91,7 +89,7 @@ struct TileSet {
 struct Group {
   int N;              // update factor shared by the domains of the group
   TileSet ts[kNTY];   // per tile height
-  TileSet runs;       // 64-wide column runs of kYRun rows (2D marching kernels)
+  TileSet runs;       // column runs, YCOL wide and YRUN rows high (2D marching kernels)
 };
 
 struct Ops {
@@ -102,9 +100,9 @@ struct Ops {
   void (*phase_ym)(int, dim3, hipStream_t, const Dom*, const int4*, unsigned);
   void (*dtr_phase)(int, dim3, hipStream_t, const Dom*, const int4*, unsigned, Partial*);
   void (*dtr_scalar)(int, dim3, hipStream_t, const Dom*, const int4*, unsigned, Partial*);
-  void (*transfer_ym)(dim3, hipStream_t, const Dom*, const int4*, unsigned, Partial*, const int*, int);
-  void (*tr_scalar_ym)(int, dim3, hipStream_t, const Dom*, const int4*, unsigned, Partial*, const int*, int);
-  void (*scalar_ym)(int, int, dim3, hipStream_t, const Dom*, const int4*, unsigned, Partial*, const int*, int);
+  void (*transfer_ym)(dim3, hipStream_t, const Dom*, const int4*, unsigned, double2*);
+  void (*tr_scalar_ym)(int, dim3, hipStream_t, const Dom*, const int4*, unsigned, double2*);
+  void (*scalar_ym)(int, int, dim3, hipStream_t, const Dom*, const int4*, unsigned, double2*);
   void (*scalar)(int, int, int, dim3, hipStream_t, const Dom*, const int4*, unsigned, Partial*);
   void (*flow)(int, dim3, hipStream_t, const Dom*, const int4*, unsigned);
   void (*diag_tiles)(int, dim3, hipStream_t, const Dom*, const int4*, long long, Partial*);
@@ -172,6 +170,8 @@ struct lbm_ctx {
   std::vector<Group> g_phi, g_U, g_T, g_F;
   Partial* d_part = nullptr;
   int* d_slot = nullptr;
+  double2* d_rmax = nullptr;   // per marching run: largest |dU| and injected U of the last transfer
+  bool tr_march = false;       // the last launched transfer marched (the diagnostics read d_rmax)
   int* d_slot0[kNTY] = {nullptr, nullptr, nullptr, nullptr};
   DiagOut* d_diag = nullptr;
   int* d_codes = nullptr;
@@ -389,13 +389,14 @@ static void launch_step(lbm_ctx* c, hipStream_t st, unsigned k, bool last = fals
   const int tf = fused ? ty_slot(c->ops.phase_tr_rows(TY)) : ti;
   for (auto& g : c->g_phi)
     if (k % g.N == 0) {
+      c->tr_march = !fused && use_march(c);
       if (fused) {
         c->ops.phase_tr(kTYs[tf], dim3(g.ts[tf].n), st, c->d_dom, g.ts[tf].d, k, c->d_part);
       } else {
         if (use_march(c)) {
           c->ops.phase_ym(c->qs, dim3(g.runs.n), st, c->d_dom, g.runs.d, k);
           if (!fuses_T(c, k))   // else inside the T transport, launched first below
-            c->ops.transfer_ym(dim3(g.runs.n), st, c->d_dom, g.runs.d, k, c->d_part, c->d_slot0[ti], TY);
+            c->ops.transfer_ym(dim3(g.runs.n), st, c->d_dom, g.runs.d, k, c->d_rmax);
         } else {
           if (c->pending)   // the previous step's transfer runs inside this phase kernel
             c->ops.dtr_phase(TY, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k, c->d_part);
@@ -413,7 +414,7 @@ static void launch_step(lbm_ctx* c, hipStream_t st, unsigned k, bool last = fals
   const bool trT = fuses_T(c, k);
   if (trT)
     for (auto& g : c->g_T)
-      c->ops.tr_scalar_ym(c->qs, dim3(g.runs.n), st, c->d_dom, g.runs.d, k, c->d_part, c->d_slot0[ti], TY);
+      c->ops.tr_scalar_ym(c->qs, dim3(g.runs.n), st, c->d_dom, g.runs.d, k, c->d_rmax);
   // (the U transport stays tiled: marching it measured slower on the
   // batched ensemble, 248 against 236 us per launch)
   for (auto& g : c->g_U)
@@ -425,7 +426,7 @@ static void launch_step(lbm_ctx* c, hipStream_t st, unsigned k, bool last = fals
     }
   for (auto& g : c->g_T)
     if (k % g.N == 0 && !trT) {
-      if (march) c->ops.scalar_ym(1, c->qs, dim3(g.runs.n), st, c->d_dom, g.runs.d, k, c->d_part, c->d_slot0[ti], TY);
+      if (march) c->ops.scalar_ym(1, c->qs, dim3(g.runs.n), st, c->d_dom, g.runs.d, k, c->d_rmax);
       else c->ops.scalar(1, TY, c->qs, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k, c->d_part);
     }
   for (auto& g : c->g_F)
@@ -504,7 +505,7 @@ size_t lbm_workspace_bytes(const lbm_params* p, int32_t n, int32_t storage) {
   size_t maxsites = 0;
   for (int i = 0; i < n; ++i) {
     if (!validate(p[i], i).empty()) return 0;
-    if (p[i].dim == 2) runs += (long long)((p[i].nx + 63) / 64) * ((p[i].ny + kYRun - 1) / kYRun);
+    if (p[i].dim == 2) runs += (long long)((p[i].nx + YCOL - 1) / YCOL) * ((p[i].ny + YRUN - 1) / YRUN);
     if ((p[i].dim == 3 && n != 1) || p[i].q_scalar != p[0].q_scalar) return 0;
     const size_t plane = (size_t)px_of(p[i].nx) * p[i].ny * (p[i].dim == 3 ? p[i].nz : 1);
     const Layout L = layout_of(p[i]);
@@ -522,6 +523,7 @@ size_t lbm_workspace_bytes(const lbm_params* p, int32_t n, int32_t storage) {
   // run lists: per field, one list per group (at most 8 groups, each padded by < 8)
   total += 4 * (sizeof(int4) * (size_t)(runs + 64) + 8 * 256);
   total += align256(sizeof(Partial) * (size_t)tilesmax);
+  total += align256(sizeof(double2) * (size_t)(runs + 1));
   total += align256(sizeof(int) * (size_t)tilesmax) + kNTY * align256(sizeof(int) * (n + 1));
   total += align256(sizeof(DiagOut) * n);
   total += align256(sizeof(int) * kMaxCodes);
@@ -604,6 +606,7 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
   // domains and their planes
   c->H.resize(n);
   long long lcm = 1;
+  int rbase = 0;
   for (int i = 0; i < n; ++i) {
     const lbm_params& q = p[i];
     Dom& D = c->H[i];
@@ -612,6 +615,9 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
     D.ny = q.ny;
     D.nz = q.dim == 3 ? q.nz : 1;
     D.dim = q.dim;
+    D.rbase = rbase;
+    D.nruns = q.dim == 2 ? ((q.nx + YCOL - 1) / YCOL) * ((q.ny + YRUN - 1) / YRUN) : 0;
+    rbase += D.nruns;
     D.px = px_of(q.nx);
     D.plane = (long long)D.px * q.ny * D.nz;
     for (int a = 0; a < 3; ++a) {
@@ -734,7 +740,7 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
   for (int i = 0; i < n; ++i) c->marchable &= p[i].dim == 2 && p[i].nx >= 16 && p[i].ny >= 16;
   {
     long long runs = 0;   // a column run is one block: marching pays when they are many
-    for (int i = 0; i < n; ++i) runs += (long long)((p[i].nx + 63) / 64) * ((p[i].ny + kYRun - 1) / kYRun);
+    for (int i = 0; i < n; ++i) runs += (long long)((p[i].nx + YCOL - 1) / YCOL) * ((p[i].ny + YRUN - 1) / YRUN);
     c->march_big = runs >= 4 * 256;
   }
   // the buffer indices of phi, U and T (write counts mod 4) repeat too;
@@ -827,8 +833,8 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
       {
         std::vector<int4> sp;
         for (int d : kv.second)
-          for (int y0 = 0; y0 < p[d].ny; y0 += kYRun)
-            for (int x0 = 0; x0 < p[d].nx; x0 += 64) sp.push_back(make_int4(d, x0, y0, std::min(p[d].ny, y0 + kYRun)));
+          for (int y0 = 0; y0 < p[d].ny; y0 += YRUN)
+            for (int x0 = 0; x0 < p[d].nx; x0 += YCOL) sp.push_back(make_int4(d, x0, y0, std::min(p[d].ny, y0 + YRUN)));
         std::vector<int4> o = xcd_order(sp);
         g.runs.d = (int4*)take(sizeof(int4) * o.size());
         g.runs.n = (int)o.size();
@@ -854,6 +860,11 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
     c->one_T &= p[i].has_T != 0 && p[i].T_mode != LBM_T_PULLED && p[i].coupling == LBM_COUPLE_INSTANT;
   }
   c->d_part = (Partial*)take(sizeof(Partial) * (size_t)tilesmax);
+  c->d_rmax = (double2*)take(sizeof(double2) * (size_t)(rbase + 1));
+  if (hipMemset(c->d_rmax, 0, sizeof(double2) * (size_t)(rbase + 1)) != hipSuccess) {
+    lbm_destroy(c);
+    return fail(nullptr, LBM_EDEVICE, "clearing the run maxima failed");
+  }
   c->d_slot = (int*)take(sizeof(int) * (size_t)tilesmax);
   for (int ti = 0; ti < kNTY; ++ti) c->d_slot0[ti] = (int*)take(sizeof(int) * (n + 1));
   c->d_diag = (DiagOut*)take(sizeof(DiagOut) * n);
@@ -1032,12 +1043,11 @@ lbm_status lbm_kernel_times(lbm_ctx* c, int32_t reps, double* ms_out, double* pe
         else if (kind == 0 && !fused)
           c->ops.phase(TY, c->qs, grid, c->stream, c->d_dom, g.ts[ti].d, k);
         if (kind == 1 && use_march(c))
-          c->ops.transfer_ym(dim3(g.runs.n), c->stream, c->d_dom, g.runs.d, k, c->d_part, c->d_slot0[ti], TY);
+          c->ops.transfer_ym(dim3(g.runs.n), c->stream, c->d_dom, g.runs.d, k, c->d_rmax);
         else if (kind == 1)
           c->ops.transfer(TY, grid, c->stream, c->d_dom, g.ts[ti].d, k, c->d_part);
         if (kind == 3 && use_march(c))
-          c->ops.scalar_ym(kind - 2, c->qs, dim3(g.runs.n), c->stream, c->d_dom, g.runs.d, k, c->d_part,
-                           c->d_slot0[ti], TY);
+          c->ops.scalar_ym(kind - 2, c->qs, dim3(g.runs.n), c->stream, c->d_dom, g.runs.d, k, c->d_rmax);
         else if (kind == 2 || kind == 3)
           c->ops.scalar(kind - 2, TY, c->qs, grid, c->stream, c->d_dom, g.ts[ti].d, k, c->d_part);
         if (kind == 4) c->ops.flow(TY, grid, c->stream, c->d_dom, g.ts[ti].d, k);
@@ -1117,8 +1127,7 @@ lbm_status lbm_kernel_times(lbm_ctx* c, int32_t reps, double* ms_out, double* pe
       const unsigned k = cycle_step(c, due(std::lcm(g.N, c->g_phi[0].N)));
       lbm_status s = time_launch(
           [&]() {
-            c->ops.tr_scalar_ym(c->qs, dim3(g.runs.n), c->stream, c->d_dom, g.runs.d, k, c->d_part,
-                                c->d_slot0[ti], TY);
+            c->ops.tr_scalar_ym(c->qs, dim3(g.runs.n), c->stream, c->d_dom, g.runs.d, k, c->d_rmax);
           },
           ms_out[7]);
       if (s != LBM_OK) return s;
@@ -1136,13 +1145,15 @@ static lbm_status run_diag(lbm_ctx* c, lbm_diag* out) {
   std::vector<double> front;
   if (c->dim == 3) {
     c->ops3.diag(c->H[0], c->stream, c->d_dom, c->k, c->d_part, c->d_front);
-    diag_final(c->ndom, c->stream, c->d_dom, c->d_part, c->d_slot, c->d_slot0[ti], c->d_diag);
+    diag_final(c->ndom, c->stream, c->d_dom, c->d_part, c->d_slot, c->d_slot0[ti], c->d_rmax,
+               c->dim == 2 && c->tr_march ? 1 : 0, c->d_diag);
     front.resize(2 * (size_t)c->nfront);
     HIPCHK(c, hipMemcpyAsync(front.data(), c->d_front, sizeof(double) * front.size(), hipMemcpyDeviceToHost,
                              c->stream));
   } else {
     c->ops.diag_tiles(TY, dim3(c->all[ti].n), c->stream, c->d_dom, c->all[ti].d, c->k, c->d_part);
-    diag_final(c->ndom, c->stream, c->d_dom, c->d_part, c->d_slot, c->d_slot0[ti], c->d_diag);
+    diag_final(c->ndom, c->stream, c->d_dom, c->d_part, c->d_slot, c->d_slot0[ti], c->d_rmax,
+               c->dim == 2 && c->tr_march ? 1 : 0, c->d_diag);
     c->ops.tips(c->ndom, c->stream, c->d_dom, c->k, c->d_diag);
   }
   HIPCHK(c, hipGetLastError());
