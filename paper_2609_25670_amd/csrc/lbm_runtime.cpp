@@ -90,6 +90,7 @@ struct Group {
   int N;              // update factor shared by the domains of the group
   TileSet ts[kNTY];   // per tile height
   TileSet runs;       // column runs, YCOL wide and YRUN rows high (2D marching kernels)
+  TileSet runs64;     // phase field: runs 64 wide (the marching phase kernel)
 };
 
 struct Ops {
@@ -394,7 +395,7 @@ static void launch_step(lbm_ctx* c, hipStream_t st, unsigned k, bool last = fals
         c->ops.phase_tr(kTYs[tf], dim3(g.ts[tf].n), st, c->d_dom, g.ts[tf].d, k, c->d_part);
       } else {
         if (use_march(c)) {
-          c->ops.phase_ym(c->qs, dim3(g.runs.n), st, c->d_dom, g.runs.d, k);
+          c->ops.phase_ym(c->qs, dim3(g.runs64.n), st, c->d_dom, g.runs64.d, k);
           if (!fuses_T(c, k))   // else inside the T transport, launched first below
             c->ops.transfer_ym(dim3(g.runs.n), st, c->d_dom, g.runs.d, k, c->d_rmax);
         } else {
@@ -505,7 +506,8 @@ size_t lbm_workspace_bytes(const lbm_params* p, int32_t n, int32_t storage) {
   size_t maxsites = 0;
   for (int i = 0; i < n; ++i) {
     if (!validate(p[i], i).empty()) return 0;
-    if (p[i].dim == 2) runs += (long long)((p[i].nx + YCOL - 1) / YCOL) * ((p[i].ny + YRUN - 1) / YRUN);
+    if (p[i].dim == 2)
+      runs += (long long)((p[i].nx + YCOL - 1) / YCOL + (p[i].nx + 63) / 64) * ((p[i].ny + YRUN - 1) / YRUN);
     if ((p[i].dim == 3 && n != 1) || p[i].q_scalar != p[0].q_scalar) return 0;
     const size_t plane = (size_t)px_of(p[i].nx) * p[i].ny * (p[i].dim == 3 ? p[i].nz : 1);
     const Layout L = layout_of(p[i]);
@@ -521,7 +523,7 @@ size_t lbm_workspace_bytes(const lbm_params* p, int32_t n, int32_t storage) {
   // domains sharing an update factor (at most 8 groups, each padded by < 8)
   total += kNTY * (5 * (sizeof(int4) * (size_t)(padded + 64)) + 40 * 256);
   // run lists: per field, one list per group (at most 8 groups, each padded by < 8)
-  total += 4 * (sizeof(int4) * (size_t)(runs + 64) + 8 * 256);
+  total += 4 * (sizeof(int4) * (size_t)(runs + 128) + 8 * 256);
   total += align256(sizeof(Partial) * (size_t)tilesmax);
   total += align256(sizeof(double2) * (size_t)(runs + 1));
   total += align256(sizeof(int) * (size_t)tilesmax) + kNTY * align256(sizeof(int) * (n + 1));
@@ -840,6 +842,16 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
         g.runs.n = (int)o.size();
         HIPCHK(c, hipMemcpy(g.runs.d, o.data(), sizeof(int4) * o.size(), hipMemcpyHostToDevice));
       }
+      if (field == 0) {   // the marching phase kernel: runs 64 wide
+        std::vector<int4> sp;
+        for (int d : kv.second)
+          for (int y0 = 0; y0 < p[d].ny; y0 += YRUN)
+            for (int x0 = 0; x0 < p[d].nx; x0 += 64) sp.push_back(make_int4(d, x0, y0, std::min(p[d].ny, y0 + YRUN)));
+        std::vector<int4> o = xcd_order(sp);
+        g.runs64.d = (int4*)take(sizeof(int4) * o.size());
+        g.runs64.n = (int)o.size();
+        HIPCHK(c, hipMemcpy(g.runs64.d, o.data(), sizeof(int4) * o.size(), hipMemcpyHostToDevice));
+      }
       gs.push_back(g);
     }
     return LBM_OK;
@@ -1039,7 +1051,7 @@ lbm_status lbm_kernel_times(lbm_ctx* c, int32_t reps, double* ms_out, double* pe
           c->ops.phase_tr(kTYs[tf], dim3(g.ts[tf].n), c->stream, c->d_dom, g.ts[tf].d, k, c->d_part);
         }
         if (kind == 0 && !fused && use_march(c))
-          c->ops.phase_ym(c->qs, dim3(g.runs.n), c->stream, c->d_dom, g.runs.d, k);
+          c->ops.phase_ym(c->qs, dim3(g.runs64.n), c->stream, c->d_dom, g.runs64.d, k);
         else if (kind == 0 && !fused)
           c->ops.phase(TY, c->qs, grid, c->stream, c->d_dom, g.ts[ti].d, k);
         if (kind == 1 && use_march(c))
