@@ -45,8 +45,8 @@ KERNEL_SOURCES = [os.path.join(ROOT, "paper_2609_25670_amd", "csrc", f)
                   for f in ("lbm_kernels.hip", "lbm_dev.h")]
 KERNEL_NAMES = {"phase": "k_phase", "phase_tr": "k_phase_tr", "transfer": "k_transfer", "U": "k_scalar<..., 0>",
                 "T": "k_scalar<..., 1>", "flow": "k_flow", "phase_dtr": "k_dtr_phase", "U_dtr": "k_dtr_scalar"}
-KERNEL_NAMES_MARCH = dict(KERNEL_NAMES, phase="k_phase_ym", transfer="k_transfer_ym", T="k_scalar_ym<..., 1>",
-                          T_tr="k_tr_scalar_ym")
+KERNEL_NAMES_MARCH = dict(KERNEL_NAMES, phase="k_phase_ym", transfer="k_transfer_ym", U="k_scalar_ym<..., 0>",
+                          T="k_scalar_ym<..., 1>", T_tr="k_tr_scalar_ym")
 KERNEL_NAMES_3D = {"phase": "k3z_phase", "transfer": "k3z_transfer", "U": "k3z_scalar<..., 0>",
                    "T": "k3z_scalar<..., 1>", "flow": "k3z_flow"}
 

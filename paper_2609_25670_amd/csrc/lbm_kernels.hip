@@ -3075,8 +3075,9 @@ __global__ __launch_bounds__(NTHR) void k_diag_tiles(const Dom* __restrict__ dom
 
 // One block per domain: fixed-order reduction of the tile partials (the
 // partial slots of a domain are listed in slot[] in spatial order).
-// (marching contexts: S_phi, and J_U with instantaneous coupling, come from
-// the per-run maxima of the marching transfer)
+// (marching contexts: S_phi and J_U come from the per-run maxima written by
+// the marching transfer, and with accumulated coupling J_U by the marching
+// U transport)
 __global__ void k_diag_final(const Dom* __restrict__ doms, const Partial* __restrict__ part,
                              const int* __restrict__ slot, const int* __restrict__ slot0,
                              const double2* __restrict__ rmax, int marching, DiagOut* __restrict__ out) {
@@ -3102,7 +3103,7 @@ __global__ void k_diag_final(const Dom* __restrict__ doms, const Partial* __rest
       mj = fmax(mj, rmax[i].y);
     }
     a[4] = ms;
-    if (!D.accum) a[5] = mj;
+    a[5] = mj;
   }
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int j = 0; j < 7; ++j) {

@@ -416,14 +416,16 @@ static void launch_step(lbm_ctx* c, hipStream_t st, unsigned k, bool last = fals
   if (trT)
     for (auto& g : c->g_T)
       c->ops.tr_scalar_ym(c->qs, dim3(g.runs.n), st, c->d_dom, g.runs.d, k, c->d_rmax);
-  // (the U transport stays tiled: marching it measured slower on the
-  // batched ensemble, 248 against 236 us per launch)
+  // (the U transport marches too since the runs are 62 columns wide: 191
+  // against 224 us per launch on the batched ensemble)
   for (auto& g : c->g_U)
     if (k % g.N == 0) {
       if (fuses_U(c, k))   // carrying this step's transfer
         c->ops.dtr_scalar(TY, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k, c->d_part);
-      else
-        c->ops.scalar(0, TY, c->qs, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k, c->d_part);
+      else if (march)
+          c->ops.scalar_ym(0, c->qs, dim3(g.runs.n), st, c->d_dom, g.runs.d, k, c->d_rmax);
+        else
+          c->ops.scalar(0, TY, c->qs, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k, c->d_part);
     }
   for (auto& g : c->g_T)
     if (k % g.N == 0 && !trT) {
@@ -1058,7 +1060,7 @@ lbm_status lbm_kernel_times(lbm_ctx* c, int32_t reps, double* ms_out, double* pe
           c->ops.transfer_ym(dim3(g.runs.n), c->stream, c->d_dom, g.runs.d, k, c->d_rmax);
         else if (kind == 1)
           c->ops.transfer(TY, grid, c->stream, c->d_dom, g.ts[ti].d, k, c->d_part);
-        if (kind == 3 && use_march(c))
+        if ((kind == 2 || kind == 3) && use_march(c))
           c->ops.scalar_ym(kind - 2, c->qs, dim3(g.runs.n), c->stream, c->d_dom, g.runs.d, k, c->d_rmax);
         else if (kind == 2 || kind == 3)
           c->ops.scalar(kind - 2, TY, c->qs, grid, c->stream, c->d_dom, g.ts[ti].d, k, c->d_part);

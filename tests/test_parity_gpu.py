@@ -305,6 +305,34 @@ def test_marching_transfer_in_T_transport_is_bitwise_identical(storage, case):
             assert diag["S_phi"] == ref[1]["S_phi"] and diag["J_U"] == ref[1]["J_U"]
 
 
+@pytest.mark.parametrize("coupling", ["accum", "instant"])
+def test_marching_U_transport_is_bitwise_identical(coupling):
+    """The U transport marches with the phase field (62-column runs): the
+    solutal case on 150 x 70 (walls, a 26-column last run, a 6-row last
+    run) with accumulated or instantaneous coupling, N_U = 4, equals the
+    tiled kernels bit for bit, with the same S_phi and J_U (with
+    accumulated coupling J_U is the largest injected U, from the U
+    transport)."""
+    from paper_2609_25670_amd import simulation_for
+
+    wl = L.reduced(L.solutal_512(), 150, 70)
+    wl["domains"][0]["coupling"] = coupling
+    names = ("phi", "U", "f_phi", "jU") + (("P_U",) if coupling == "accum" else ())
+    res = []
+    for march in (False, True):
+        _say(f"case marching U transport {coupling} march={march}")
+        sim = simulation_for(wl, storage="f64")
+        sim.configure(8, True, False, march)
+        sim.step(6)
+        diag = sim.step(33, diag=True)[0]
+        res.append((sim.read(0, names), diag))
+        sim.close()
+    for n in names:
+        assert np.array_equal(res[0][0][n], res[1][0][n]), n
+    assert res[0][1]["S_phi"] == res[1][1]["S_phi"] and res[0][1]["J_U"] == res[1][1]["J_U"]
+    assert res[1][1]["J_U"] > 0
+
+
 def test_checkpoint_restore_is_bitwise():
     """Read the full state, write it into a fresh context, continue: equal
     to the uninterrupted run, bit for bit."""
