@@ -333,6 +333,28 @@ def test_marching_U_transport_is_bitwise_identical(coupling):
     assert res[1][1]["J_U"] > 0
 
 
+@pytest.mark.parametrize("bcx", ["periodic", "wall"])
+def test_marching_one_column_last_run_fp64(bcx):
+    """Marching on 125 x 67: the 62-column runs leave a last run one column
+    wide (125 = 2 x 62 + 1), the 64-column phase runs one of 61, and the
+    row runs a last run of 3 rows; x periodic (wrapping across the narrow
+    run) or walled.  Thermosolutal (U every step, T every second step,
+    latent heat): FP64 parity with the oracle and the same state as the
+    tiled kernels."""
+    wl = L.reduced(L.thermosolutal_flow_1024(), 125, 67)
+    d = wl["domains"][0]
+    d.update(has_flow=False, N_U=1, N_T=2, tau0=40.0, bc=(bcx, "wall", "wall"))
+    names = ("phi", "U", "T", "f_phi", "jU", "jT")
+    _say(f"case marching one-column last run 125x67 x={bcx} fp64 40 steps")
+    (got,), diag = _gpu(wl, 40, names=names, tile_rows=8, march=True)
+    (ref_t,), diag_t = _gpu(wl, 40, names=names, tile_rows=8, march=False)
+    for n in names:
+        assert np.array_equal(got[n], ref_t[n]), n
+    assert diag[0]["S_phi"] == diag_t[0]["S_phi"] and diag[0]["J_U"] == diag_t[0]["J_U"]
+    dom = oracle.run(d, 40)
+    _compare(f"one-column run x={bcx}", got, _oracle_fields(dom, names), TOL64)
+
+
 def test_checkpoint_restore_is_bitwise():
     """Read the full state, write it into a fresh context, continue: equal
     to the uninterrupted run, bit for bit."""
