@@ -13,9 +13,12 @@ boundary masks, and the multirate loop of Eq. (34) with the phase-step
 transfer of Eq. (36)-(39).  Every function cites the passage it follows.
 
 Parity pins: every routine is checked by ``tests/test_oracle_*.py`` against
-closed forms, invariants, printed numbers and brute-force loops.  Routines
-listed as "parity unpinned" there (inlet/outflow flow boundaries, 3D
-extension choices) are only checked for internal consistency.
+closed forms, invariants, printed numbers and brute-force loops: the
+inlet/outflow columns by an empty channel's fixed point and inlet-flux
+balance, the accumulated coupling by its conservation invariant and the
+order of its injection, the 3D extension by its own closed forms and
+symmetries.  Long-run tip velocities, which the paper prints only as curves
+against data that is not available, remain parity unpinned.
 """
 
 from . import lattice, params, stencils, model, diag  # noqa: F401
