@@ -4,20 +4,26 @@
 A bench "step" is one multirate cycle: lcm(N_chi) base steps, in which every
 kernel of the hot path (phase collision + anisotropic streaming, phase-step
 transfer, each scalar transport, flow) runs at least once.  The default
-workload is the 2D isothermal solutal dendrite on 512 x 512 with FP32
-arithmetic and storage, N_phi : N_U = 1 : 4.
+workload is the largest single-GPU configuration: 3D directional
+solidification on 256 x 256 x 512 (33.5 M sites; D3Q7 phase, U, T and D3Q19
+flow, N_phi : N_U : N_T : N_F = 1 : 1 : 16 : 4), FP32 arithmetic with BF16
+population storage.
 
     python bench.py [--gpus 1] [--steps K] [--warmup W] [--workload NAME]
 
-Prints one JSON line.  ``value`` is coupled-field MLUPS
-(sites x base steps / wall time).  ``roofline`` describes the kernel with the
-largest share of device time per base step: its algorithmic bytes per launch
-divided by its average launch time, measured with HIP events on the stream
-the library issues its work on.  ``cpu_baseline`` times the FP64 oracle on
-a bounded sample of the same workload on one host core.  The default
-workload's state is cache-resident, so the line also carries
-``hbm_bound_workload``: the same measurement (two cycles) on the 256-domain
-ensemble, whose 2 GB state streams from HBM.
+Prints one JSON line.  Each of the K steps is timed on its own (wall clock
+between device synchronisations); ``value`` is coupled-field MLUPS
+(sites x base steps / time) of the median step, ``ms_per_step`` that
+median.  ``roofline`` describes the kernel with the largest share of device
+time per base step: its algorithmic bytes per launch divided by its average
+launch time, measured with HIP events on the stream the library issues its
+work on; ``step_roofline`` does the same for the whole step (algorithmic
+bytes of every kernel of the cycle over the median step time).
+``cpu_baseline`` times the FP64 oracle on a bounded sample of the same
+workload: one process, then one process per host core in parallel (each on
+its own copy of the sample).  The line also carries
+``batched_workload``: the same measurement on the 256-domain ensemble
+(29.7 M sites of uneven 2D domains, FP16 storage).
 """
 
 from __future__ import annotations
@@ -38,8 +44,8 @@ if ROOT not in sys.path:
 
 METRIC = ("coupled-field MLUPS + % HBM peak; FP32/FP16-store vs FP64 at stated tip-velocity error")
 HBM_PEAK_GBS = 8000.0
-DEFAULT_WORKLOAD = "solutal_512"
-HBM_WORKLOAD = "ensemble_256"
+DEFAULT_WORKLOAD = "directional_3d"
+SIDE_WORKLOAD = "ensemble_256"
 STORAGE_BYTES = {"f64": 8, "f32": 4, "f16": 2, "bf16": 2}
 KERNEL_SOURCES = [os.path.join(ROOT, "paper_2609_25670_amd", "csrc", f)
                   for f in ("lbm_kernels.hip", "lbm_dev.h")]
@@ -125,14 +131,42 @@ def traffic_from_profiles(workload: str, kernel: str, sha: str):
     return rec.get("hbm_bytes_per_dispatch")
 
 
-def cpu_baseline(workload: str, steps: int) -> dict:
-    """Time the FP64 oracle on one host core for ``steps`` base steps of the
-    workload (run in a child process pinned to one BLAS/OpenMP thread)."""
+def host_cpus() -> int:
+    """Cores this process may run on (its affinity set)."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1
+
+
+def cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or platform.machine()
+
+
+def cpu_baseline(workload: str, steps: int, procs: int) -> dict:
+    """Time the FP64 oracle for ``steps`` base steps of the workload's
+    bounded sample in ``procs`` child processes at once, each pinned to one
+    BLAS/OpenMP thread and running its own copy; returns the aggregate
+    MLUPS and the slowest child's record."""
     env = dict(os.environ, OMP_NUM_THREADS="1", OPENBLAS_NUM_THREADS="1", MKL_NUM_THREADS="1")
     cmd = [sys.executable, os.path.abspath(__file__), "--cpu-child", "--workload", workload,
            "--cpu-steps", str(steps)]
-    out = subprocess.run(cmd, env=env, capture_output=True, text=True, check=True).stdout
-    return json.loads(out.strip().splitlines()[-1])
+    kids = [subprocess.Popen(cmd, env=env, stdout=subprocess.PIPE, text=True) for _ in range(procs)]
+    recs = []
+    for p in kids:
+        out, _ = p.communicate()
+        if p.returncode != 0:
+            raise RuntimeError(f"oracle child failed with status {p.returncode}")
+        recs.append(json.loads(out.strip().splitlines()[-1]))
+    slow = max(recs, key=lambda r: r["seconds"])
+    return dict(slow, mlups=sum(r["sites"] * r["steps"] for r in recs) / slow["seconds"] / 1e6, procs=procs)
 
 
 def cpu_child(workload: str, steps: int) -> None:
@@ -156,9 +190,10 @@ def cpu_child(workload: str, steps: int) -> None:
 
 
 def measure(sim, wl: dict, storage: str, steps: int, warmup: int) -> dict:
-    """Time ``steps`` multirate cycles after ``warmup`` cycles (wall clock
-    between device synchronisations, and HIP events), then time each kernel
-    kind with HIP events on the library's stream.  Closes ``sim``."""
+    """Time ``steps`` multirate cycles one by one after ``warmup`` cycles
+    (wall clock between device synchronisations, and HIP events on the
+    library's stream), then time each kernel kind with HIP events.  Closes
+    ``sim``."""
     import torch
 
     cyc = cycle_of(wl)
@@ -166,17 +201,23 @@ def measure(sim, wl: dict, storage: str, steps: int, warmup: int) -> dict:
     # warm-up: autotune, graph capture, clocks
     sim.step(warmup * cyc)
     torch.cuda.synchronize()
-    ev0 = torch.cuda.Event(enable_timing=True)
-    ev1 = torch.cuda.Event(enable_timing=True)
-    t0 = time.perf_counter()
-    ev0.record()
-    sim.step(steps * cyc)
-    ev1.record()
-    torch.cuda.synchronize()
-    wall = time.perf_counter() - t0
+    walls, evs = [], []
+    t_all = time.perf_counter()
+    for _ in range(steps):
+        ev0 = torch.cuda.Event(enable_timing=True)
+        ev1 = torch.cuda.Event(enable_timing=True)
+        t0 = time.perf_counter()
+        ev0.record()
+        sim.step(cyc)            # synchronises at its end (non-finite screen)
+        ev1.record()
+        torch.cuda.synchronize()
+        walls.append(time.perf_counter() - t0)
+        evs.append(ev0.elapsed_time(ev1))
+    total = time.perf_counter() - t_all
     diag = sim.step(0, diag=True)
-    finite = all(dd["nonfinite"] == 0 for dd in diag)
-    mlups = sites * steps * cyc / wall / 1e6
+    finite = all(dd["nonfinite"] == 0 and dd["first_nonfinite_step"] < 0 for dd in diag)
+    med = sorted(walls)[len(walls) // 2]
+    mlups = sites * cyc / med / 1e6
 
     # per-kernel launch times (HIP events on the library's stream)
     marching = sim.marching
@@ -188,29 +229,45 @@ def measure(sim, wl: dict, storage: str, steps: int, warmup: int) -> dict:
         kt = {("phase_tr" if k == "phase" else k): v for k, v in kt.items()}
     per_kind = {}
     for kind, (ms, per) in kt.items():
-        nbytes = algorithmic_bytes(kind, d0, storage) * sites
+        nbytes = sum(algorithmic_bytes(kind, d, storage) * sites_of(d) for d in wl["domains"])
         per_kind[kind] = dict(ms_per_launch=ms, launches_per_base_step=per,
                               alg_bytes_per_launch=nbytes,
                               alg_GBs=nbytes / (ms * 1e-3) / 1e9 if ms > 0 else None,
                               share_ms_per_base_step=ms * per)
     dom_kind = max(per_kind, key=lambda k: per_kind[k]["share_ms_per_base_step"])
-    d0 = wl["domains"][0]
     names = KERNEL_NAMES_3D if d0["dim"] == 3 else KERNEL_NAMES_MARCH if marching else KERNEL_NAMES
-    return dict(mlups=mlups, wall=wall, event_ms=ev0.elapsed_time(ev1), finite=finite, kernels=per_kind,
-                dominant=dom_kind, names=names, tile_rows=rows)
+    step_bytes = sum(v["alg_bytes_per_launch"] * v["launches_per_base_step"] for v in per_kind.values()) * cyc
+    return dict(mlups=mlups, med_s=med, mean_s=total / steps, walls_ms=[round(w * 1e3, 4) for w in walls],
+                event_ms=[round(e, 4) for e in evs], finite=finite, kernels=per_kind, dominant=dom_kind,
+                names=names, tile_rows=rows, step_bytes=step_bytes)
+
+
+def roofline_of(m: dict, workload: str, sha: str) -> dict:
+    dk = m["kernels"][m["dominant"]]
+    name = m["names"][m["dominant"]]
+    return {"bound": "hbm", "kernel": name, "achieved": round(dk["alg_GBs"], 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(dk["alg_GBs"] / HBM_PEAK_GBS, 4),
+            "traffic": traffic_from_profiles(workload, name, sha)}
+
+
+def step_roofline_of(m: dict) -> dict:
+    gbs = m["step_bytes"] / m["med_s"] / 1e9
+    return {"bound": "hbm", "achieved": round(gbs, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": round(gbs / HBM_PEAK_GBS, 4), "alg_bytes_per_step": m["step_bytes"]}
 
 
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5000)
-    ap.add_argument("--warmup", type=int, default=250)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default=DEFAULT_WORKLOAD)
-    ap.add_argument("--no-hbm-line", action="store_true",
-                    help="skip the measurement of the HBM-bound ensemble beside the default workload")
+    ap.add_argument("--no-side-line", action="store_true",
+                    help="skip the measurement of the batched ensemble beside the default workload")
     ap.add_argument("--storage", default=None, help="override the workload's population storage")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=384)
+    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--cpu-procs", type=int, default=16, help="at most this many oracle processes at once")
     ap.add_argument("--cpu-child", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
                     help="only run a plain device-to-device copy of BYTES (counter calibration)")
@@ -268,25 +325,19 @@ def main() -> int:
         print(json.dumps(dict(profile_steps=args.profile_steps, workload=wl["name"], storage=storage)), flush=True)
         return 0
     m = measure(sim, wl, storage, args.steps, args.warmup)
-    mlups, wall, ev_ms, finite = m["mlups"], m["wall"], m["event_ms"], m["finite"]
-    per_kind, dom_kind = m["kernels"], m["dominant"]
+    finite = m["finite"]
     d0 = wl["domains"][0]
-    knames = m["names"]
-    dk = per_kind[dom_kind]
     sha = kernel_source_sha()
-    traffic = traffic_from_profiles(args.workload, knames[dom_kind], sha)
-    achieved = dk["alg_GBs"]
-    bytes_per_base_step = sum(algorithmic_bytes(k, d0, storage) * v["launches_per_base_step"]
-                              for k, v in per_kind.items())   # per site
+    bytes_per_base_step = m["step_bytes"] / cyc / sites   # per site
 
     result = {
         "metric": METRIC,
-        "value": round(mlups, 2),
+        "value": round(m["mlups"], 2),
         "unit": "MLUPS",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": wall / args.steps * 1e3,
+        "ms_per_step": m["med_s"] * 1e3,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -305,61 +356,55 @@ def main() -> int:
             "tile_rows": m["tile_rows"],
             "parallelism": "single_gpu",
         },
-        "roofline": {
-            "bound": "hbm",
-            "kernel": knames[dom_kind],
-            "achieved": round(achieved, 1),
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": round(achieved / HBM_PEAK_GBS, 4),
-            "traffic": traffic,
-        },
+        "roofline": roofline_of(m, args.workload, sha),
+        "step_roofline": step_roofline_of(m),
+        "timing": {"median_of": args.steps, "ms_per_step_mean": round(m["mean_s"] * 1e3, 4),
+                   "wall_ms": m["walls_ms"], "event_ms": m["event_ms"]},
         "kernels": {k: {kk: (round(vv, 6) if isinstance(vv, float) else vv) for kk, vv in v.items()}
-                    for k, v in per_kind.items()},
-        "alg_bytes_per_site_per_base_step": bytes_per_base_step,
-        "event_ms_timed_region": ev_ms,
+                    for k, v in m["kernels"].items()},
+        "alg_bytes_per_site_per_base_step": round(bytes_per_base_step, 3),
         "finite": finite,
     }
-    if args.workload == DEFAULT_WORKLOAD and not args.no_hbm_line:
-        # The default workload's state (25 MB) is cache-resident; the same
-        # measurement on the HBM-bound batched ensemble (about 2 GB) sits beside it.
-        hw = L.workload(HBM_WORKLOAD)
+    if args.workload == DEFAULT_WORKLOAD and not args.no_side_line:
+        # the batched ensemble of uneven 2D domains, measured the same way
+        hw = L.workload(SIDE_WORKLOAD)
         hsim = simulation_for(hw, storage=hw["storage"])
-        hm = measure(hsim, hw, hw["storage"], 2, 1)
+        hm = measure(hsim, hw, hw["storage"], 3, 1)
         finite = finite and hm["finite"]
-        hk = hm["kernels"][hm["dominant"]]
-        result["hbm_bound_workload"] = {
+        result["batched_workload"] = {
             "workload": hw["name"],
             "sites": sum(sites_of(d) for d in hw["domains"]),
             "storage": hw["storage"],
             "value": round(hm["mlups"], 2),
             "unit": "MLUPS",
-            "steps": 2,
+            "steps": 3,
+            "ms_per_step": round(hm["med_s"] * 1e3, 4),
             "base_steps_per_step": cycle_of(hw),
             "tile_rows": hm["tile_rows"],
-            "roofline": {
-                "bound": "hbm",
-                "kernel": hm["names"][hm["dominant"]],
-                "achieved": round(hk["alg_GBs"], 1),
-                "peak": HBM_PEAK_GBS,
-                "unit": "GB/s",
-                "frac": round(hk["alg_GBs"] / HBM_PEAK_GBS, 4),
-                "traffic": traffic_from_profiles(HBM_WORKLOAD, hm["names"][hm["dominant"]], sha),
-            },
+            "roofline": roofline_of(hm, SIDE_WORKLOAD, sha),
+            "step_roofline": step_roofline_of(hm),
             "kernels": {k: {kk: (round(vv, 6) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                         for k, v in hm["kernels"].items()},
         }
         result["finite"] = finite
     if rank == 0 and not args.no_cpu_baseline:
-        cb = cpu_baseline(args.workload, args.cpu_steps)
+        ncpu = host_cpus()
+        procs = max(1, min(ncpu, args.cpu_procs))
+        one = cpu_baseline(args.workload, args.cpu_steps, 1)
+        allc = cpu_baseline(args.workload, args.cpu_steps, procs)
         result["cpu_baseline"] = {
-            "value": round(cb["mlups"], 4),
+            "value": round(allc["mlups"], 4),
             "unit": "MLUPS",
-            "cores": 1,
+            "cores": procs,
             "kind": "oracle",
-            "sample": (f"FP64 NumPy oracle, first domain of {wl['name']} "
-                       f"({cb['grid']}), {cb['steps']} base steps, "
-                       f"{cb['seconds']:.1f} s on one core of {platform.processor() or platform.machine()}"),
+            "sample": (f"FP64 NumPy oracle on the bounded sample {allc['grid']} of {wl['name']} "
+                       f"({allc['sites']} sites), {allc['steps']} base steps per process, {procs} processes at "
+                       f"once, one thread each ({allc['seconds']:.1f} s); CPU {cpu_model()}, "
+                       f"{ncpu} cores available"),
+            "single_core": {"value": round(one["mlups"], 4), "unit": "MLUPS", "cores": 1,
+                            "seconds": round(one["seconds"], 2)},
+            "cpu_model": cpu_model(),
+            "nproc": ncpu,
         }
     if rank == 0:
         print(json.dumps(result), flush=True)

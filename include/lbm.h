@@ -20,9 +20,9 @@
  *   - Every call returns an lbm_status; no exception crosses the ABI;
  *     lbm_last_error() returns the text of the last failure of a context.
  *   - All device work is issued on the stream passed to lbm_create (NULL =
- *     the default stream).  Only lbm_step_multirate with a non-NULL diag
- *     output, lbm_read_fields to host memory and lbm_write_fields from host
- *     memory synchronise with that stream.
+ *     the default stream).  lbm_step_multirate (which reads the device's
+ *     non-finite screen at its end), lbm_read_fields to host memory and
+ *     lbm_write_fields from host memory synchronise with that stream.
  *   - The library allocates device memory only inside lbm_create (and only
  *     when no workspace is supplied) and frees it only in lbm_destroy.
  *   - A context is not thread-safe; distinct contexts are independent.
@@ -44,7 +44,7 @@ typedef enum {
   LBM_EINVAL = -1,     /* bad argument: tau <= 1/2, N_chi < 1, bad sizes, ... */
   LBM_ENOMEM = -2,     /* device allocation failed or workspace too small     */
   LBM_EDEVICE = -3,    /* a HIP call failed                                   */
-  LBM_EUNSTABLE = -4,  /* non-finite values were found by the diagnostics     */
+  LBM_EUNSTABLE = -4,  /* non-finite values were found in the state           */
   LBM_ESTATE = -5      /* call not valid in the current state                 */
 } lbm_status;
 
@@ -120,22 +120,33 @@ typedef struct {
                                            set by lbm_init_front */
 } lbm_params;
 
-/* Per-domain diagnostics (FP64 reductions on the device).  In 3D, tip[0]
- * is the highest and tip[1] the mean phi = 0 crossing height over columns. */
+/* Per-domain diagnostics (FP64 reductions on the device; Section 4.4
+ * defines S_phi, J_U, M_C and R_M).  In 3D, tip[0] is the highest and
+ * tip[1] the mean phi = 0 crossing height over columns. */
 typedef struct {
   int64_t step;            /* base steps completed                           */
   double solid;            /* sum (1 + phi)/2                                */
   double M_C;              /* sum C, C = C_inf kfac(phi)[1+(1-k)U]/2 (Eq. 5) */
   double enthalpy;         /* sum (T - rho_L L_h phi / (2 rhoCp_L))          */
   double mass;             /* sum rho                                        */
-  double S_phi;            /* max |dU_pc| of the last phase step (Sec. 4.4)  */
+  double S_phi;            /* max |dU_pc| of the last phase step             */
   double J_U;              /* max |U_post - U_pre| of the last injection     */
   double tip[16];          /* tip distances: 4 axes for each of <= 4 seeds   */
   int64_t nonfinite;       /* count of non-finite phi/U/T/rho values         */
+  double t;                /* time: step * dt_base                           */
+  double R_M;              /* [M_C(t) - M_C(0)] / M_C(0), M_C(0) taken at the
+                              first lbm_step_multirate after initialisation
+                              (0 for a domain without U)                     */
+  int64_t first_nonfinite_step; /* first base step at whose screen a
+                              non-finite phi/U/T/rho value was found, or -1  */
 } lbm_diag;
 
 /* Device bytes a context needs for these domains (states with their buffers,
- * descriptors, tile lists, reduction partials).  0 on invalid input. */
+ * descriptors, tile lists, reduction partials).  Not an operation of the
+ * method: it sizes the caller-owned workspace of lbm_create, which holds
+ * the fields the paper's Section 3 defines (distributions of Eq. 14-33 per
+ * carried field, plus the pending increments of the Section 4.4 ablation).
+ * 0 on invalid input. */
 size_t lbm_workspace_bytes(const lbm_params* p, int32_t n_domains, int32_t storage);
 
 /* Create a context for n_domains domains that are stepped together.
@@ -175,23 +186,40 @@ lbm_status lbm_init_front(lbm_ctx* ctx, int32_t domain, const double* xi);
 /* Advance every domain by n_base_steps base steps of Eq. (34): at base
  * step k a field runs iff k mod N_chi == 0, in the order phase (+ the
  * transfer of Eq. 36-39), U, T, flow.  Whole multirate cycles are replayed
- * from a captured HIP graph.  If diag_out is non-NULL, diagnostics of every
- * domain are reduced after the last step and written to diag_out[0..n-1]
- * (this synchronises); LBM_EUNSTABLE is returned if any value is non-finite. */
+ * from a captured HIP graph.
+ * Failure detection: the phi, U, T and rho planes of every domain are
+ * screened for non-finite values on the device after every replayed cycle
+ * and after the call's last step; the call synchronises at its end and
+ * returns LBM_EUNSTABLE (with the domain and step in lbm_last_error) once
+ * any screen has failed since the domain's initialisation.  The state is
+ * left readable.
+ * If diag_out is non-NULL, diagnostics of every domain are reduced after the
+ * last step and written to diag_out[0..n-1]; LBM_EUNSTABLE is then also
+ * returned when the reduction counts non-finite values.  The first call
+ * after an initialisation also reduces M_C(0) for R_M. */
 lbm_status lbm_step_multirate(lbm_ctx* ctx, int64_t n_base_steps, lbm_diag* diag_out);
 
 /* Copy the planes selected by mask of one domain into dst (caller-owned,
  * device memory if dst_is_device else host memory), as FP64 if dst_fp64
  * else FP32, packed in mask-bit order.  Populations are reconstructed from
- * the stored representation.  Synchronises when dst is host memory. */
+ * the stored representation, whose zeroth moments are the macroscopic
+ * fields of Eq. (18) and (27): f_0 = w_0 chi - sum_{i>0} s_i with chi = phi
+ * (U, T) and the stored deviations s_i = f_i - w_i chi, and likewise for
+ * the flow with rho; the first moments of U and T are stored as such.
+ * Errors: LBM_EINVAL (bad domain, NULL dst, a mask naming a field the
+ * domain does not carry), LBM_EDEVICE.  Synchronises when dst is host
+ * memory. */
 lbm_status lbm_read_fields(lbm_ctx* ctx, int32_t domain, uint32_t mask,
                            int32_t dst_is_device, int32_t dst_fp64, void* dst);
 
 /* Overwrite the planes selected by mask of one domain from src (same
  * packing as lbm_read_fields, FP64).  Used for checkpoint restore and to
  * inject faults in tests.  Populations are given in full and re-encoded
- * into the stored representation; LBM_F_POP_PHI requires LBM_F_PHI to be
- * absent (phi is the sum of the populations). */
+ * into the stored representation, their sums becoming the macroscopic
+ * fields of Eq. (18) and (27): LBM_F_POP_PHI requires LBM_F_PHI to be
+ * absent (phi is the sum of the populations), LBM_F_POP_F requires RHO and
+ * SF to be absent.  Errors: LBM_EINVAL (as for lbm_read_fields, or a
+ * conflicting mask), LBM_EDEVICE.  Synchronises when src is host memory. */
 lbm_status lbm_write_fields(lbm_ctx* ctx, int32_t domain, uint32_t mask,
                             int32_t src_is_device, const void* src);
 

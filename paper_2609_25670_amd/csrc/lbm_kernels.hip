@@ -3075,12 +3075,14 @@ __global__ __launch_bounds__(NTHR) void k_diag_tiles(const Dom* __restrict__ dom
 
 // One block per domain: fixed-order reduction of the tile partials (the
 // partial slots of a domain are listed in slot[] in spatial order).
-// (marching contexts: S_phi and J_U come from the per-run maxima written by
-// the marching transfer, and with accumulated coupling J_U by the marching
-// U transport)
+// S_phi and J_U come from whichever kernel last wrote them: the per-run
+// maxima when the transfer marched (src bit 0: S_phi, and J_U with
+// instantaneous coupling) or, with accumulated coupling, when the U
+// transport marched (src bit 1: J_U is the largest injected increment);
+// the tile partials otherwise.
 __global__ void k_diag_final(const Dom* __restrict__ doms, const Partial* __restrict__ part,
                              const int* __restrict__ slot, const int* __restrict__ slot0,
-                             const double2* __restrict__ rmax, int marching, DiagOut* __restrict__ out) {
+                             const double2* __restrict__ rmax, int src, DiagOut* __restrict__ out) {
   __shared__ double red[7][4];
   const int d = blockIdx.x;
   const int b = slot0[d], e = slot0[d + 1];
@@ -3095,15 +3097,16 @@ __global__ void k_diag_final(const Dom* __restrict__ doms, const Partial* __rest
     a[5] = fmax(a[5], P.J_U);
     a[6] += P.nonfinite;
   }
-  if (marching) {
-    const Dom& D = doms[d];
+  const Dom& D = doms[d];
+  const bool s_runs = (src & 1) != 0, j_runs = (src & (D.accum ? 2 : 1)) != 0;
+  if (s_runs || j_runs) {
     double ms = 0.0, mj = 0.0;
     for (int i = D.rbase + threadIdx.x; i < D.rbase + D.nruns; i += blockDim.x) {
       ms = fmax(ms, rmax[i].x);
       mj = fmax(mj, rmax[i].y);
     }
-    a[4] = ms;
-    a[5] = mj;
+    if (s_runs) a[4] = ms;
+    if (j_runs) a[5] = mj;
   }
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
   for (int j = 0; j < 7; ++j) {
@@ -4700,8 +4703,41 @@ struct Launch {
 };
 
 void diag_final(int ndom, hipStream_t st, const Dom* d, const Partial* p, const int* slot, const int* slot0,
-                const double2* rmax, int marching, DiagOut* o) {
-  k_diag_final<<<ndom, 256, 0, st>>>(d, p, slot, slot0, rmax, marching, o);
+                const double2* rmax, int src, DiagOut* o) {
+  k_diag_final<<<ndom, 256, 0, st>>>(d, p, slot, slot0, rmax, src, o);
+}
+
+// Non-finite screen of the macroscopic planes after base step k (absolute):
+// block (x, d) walks rows x, x + gridDim.x, ... (four per block) of domain
+// d's phi, U, T and rho planes (their latest buffers); a wavefront that
+// meets a NaN or an infinity lowers first[d] to k with an atomic minimum.
+// A diverging field reaches phi within a few steps (U and T enter the phase
+// source, the flow advects U and T), and these are the planes every kernel
+// reads, so the screen stays a plain read of four planes per check.
+template <class R>
+__global__ __launch_bounds__(256) void k_nonfinite(const Dom* __restrict__ doms, long long k,
+                                                   unsigned long long* __restrict__ first) {
+  const Dom& D = doms[blockIdx.y];
+  GLOBAL const R* pl[4];
+  int np = 0;
+  pl[np++] = gp<const R>(D.phi[qb(n_phi(D, k))]);
+  if (D.has_U) pl[np++] = gp<const R>(D.U[qb(n_U(D, k))]);
+  if (D.has_T) pl[np++] = gp<const R>(D.T[qb(n_T(D, k))]);
+  if (D.has_F) pl[np++] = gp<const R>(D.rho[par(n_F(D, k))]);
+  const long long rows = (long long)D.ny * D.nz;
+  bool bad = false;
+  for (long long r = (long long)blockIdx.x * 4 + threadIdx.y; r < rows; r += (long long)gridDim.x * 4)
+    for (int x = threadIdx.x; x < D.nx; x += 64) {
+      const long long o = r * D.px + x;
+      for (int p = 0; p < np; ++p) bad |= !isfinite(pl[p][o]);
+    }
+  if (__ballot(bad) && threadIdx.x == 0) atomicMin(&first[blockIdx.y], (unsigned long long)k);
+}
+
+void nonfinite_check(int f64, int ndom, int blocks, hipStream_t st, const Dom* d, long long k,
+                     unsigned long long* first) {
+  if (f64) k_nonfinite<double><<<dim3(blocks, ndom), dim3(64, 4), 0, st>>>(d, k, first);
+  else k_nonfinite<float><<<dim3(blocks, ndom), dim3(64, 4), 0, st>>>(d, k, first);
 }
 
 template struct Launch<double, double>;

@@ -51,7 +51,9 @@ struct Launch {
                     const double* src, long long n);
 };
 void diag_final(int ndom, hipStream_t st, const Dom* d, const Partial* p, const int* slot, const int* slot0,
-                const double2* rmax, int marching, DiagOut* o);
+                const double2* rmax, int src, DiagOut* o);
+void nonfinite_check(int f64, int ndom, int blocks, hipStream_t st, const Dom* d, long long k,
+                     unsigned long long* first);
 template <class R, class S>
 struct Launch3 {
   static void phase(const Dom& h, hipStream_t st, const Dom* d, unsigned k);
@@ -173,6 +175,11 @@ struct lbm_ctx {
   int* d_slot = nullptr;
   double2* d_rmax = nullptr;   // per marching run: largest |dU| and injected U of the last transfer
   bool tr_march = false;       // the last launched transfer marched (the diagnostics read d_rmax)
+  bool u_march = false;        // the last launched U transport marched (accumulated J_U in d_rmax)
+  unsigned long long* d_first = nullptr;   // per domain: first checked step with a non-finite value
+  int nf_blocks = 1;           // grid width of the non-finite screen
+  std::vector<double> m0;      // M_C at the start of the run (for R_M)
+  bool need_m0 = true;         // M_C(0) is taken at the first step after an initialisation
   int* d_slot0[kNTY] = {nullptr, nullptr, nullptr, nullptr};
   DiagOut* d_diag = nullptr;
   int* d_codes = nullptr;
@@ -420,6 +427,7 @@ static void launch_step(lbm_ctx* c, hipStream_t st, unsigned k, bool last = fals
   // against 224 us per launch on the batched ensemble)
   for (auto& g : c->g_U)
     if (k % g.N == 0) {
+      c->u_march = march && !fuses_U(c, k);
       if (fuses_U(c, k))   // carrying this step's transfer
         c->ops.dtr_scalar(TY, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k, c->d_part);
       else if (march)
@@ -530,6 +538,7 @@ size_t lbm_workspace_bytes(const lbm_params* p, int32_t n, int32_t storage) {
   total += align256(sizeof(double2) * (size_t)(runs + 1));
   total += align256(sizeof(int) * (size_t)tilesmax) + kNTY * align256(sizeof(int) * (n + 1));
   total += align256(sizeof(DiagOut) * n);
+  total += align256(sizeof(unsigned long long) * n);
   total += align256(sizeof(int) * kMaxCodes);
   total += align256(sizeof(double) * maxsites * kStagePlanes);
   return total;
@@ -882,7 +891,14 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
   c->d_slot = (int*)take(sizeof(int) * (size_t)tilesmax);
   for (int ti = 0; ti < kNTY; ++ti) c->d_slot0[ti] = (int*)take(sizeof(int) * (n + 1));
   c->d_diag = (DiagOut*)take(sizeof(DiagOut) * n);
+  c->d_first = (unsigned long long*)take(sizeof(unsigned long long) * n);
   c->d_codes = (int*)take(sizeof(int) * kMaxCodes);
+  c->m0.assign(n, 0.0);
+  {
+    long long rows = 0;   // the screen's blocks walk rows of the tallest domain, four per block
+    for (int i = 0; i < n; ++i) rows = std::max(rows, (long long)p[i].ny * (p[i].dim == 3 ? p[i].nz : 1));
+    c->nf_blocks = (int)std::max(1LL, std::min((rows + 3) / 4, n == 1 ? 2048LL : 64LL));
+  }
   c->stage_elems = maxsites * kStagePlanes;
   c->d_stage = (double*)take(sizeof(double) * c->stage_elems);
   if ((size_t)(cur - (char*)c->ws) > c->ws_bytes) {
@@ -901,7 +917,8 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
         lbm_destroy(c);
         return fail(nullptr, LBM_EDEVICE, "slot upload failed");
       }
-    if (hipMemset(c->d_part, 0, sizeof(Partial) * (size_t)tilesmax) != hipSuccess) {
+    if (hipMemset(c->d_first, 0xff, sizeof(unsigned long long) * n) != hipSuccess ||
+        hipMemset(c->d_part, 0, sizeof(Partial) * (size_t)tilesmax) != hipSuccess) {
       lbm_destroy(c);
       return fail(nullptr, LBM_EDEVICE, "partial clear failed");
     }
@@ -937,7 +954,9 @@ lbm_status lbm_init_seeds(lbm_ctx* c, int32_t dom, int32_t n_seeds, const double
   if (st != LBM_OK) return st;
   c->ops.init(c->stream, c->d_dom, dom, (long long)D.nx * D.ny, nullptr);
   HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipMemsetAsync(c->d_first + dom, 0xff, sizeof(unsigned long long), c->stream));
   c->initialised[dom] = true;
+  c->need_m0 = true;
   c->k = 0;
   return LBM_OK;
 }
@@ -964,8 +983,10 @@ lbm_status lbm_init_front(lbm_ctx* c, int32_t dom, const double* xi) {
     c->ops.init(c->stream, c->d_dom, dom, (long long)D.nx * D.ny, dxi);
   }
   HIPCHK(c, hipGetLastError());
+  HIPCHK(c, hipMemsetAsync(c->d_first + dom, 0xff, sizeof(unsigned long long), c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   c->initialised[dom] = true;
+  c->need_m0 = true;
   c->k = 0;
   return LBM_OK;
 }
@@ -1154,25 +1175,35 @@ lbm_status lbm_kernel_times(lbm_ctx* c, int32_t reps, double* ms_out, double* pe
   return LBM_OK;
 }
 
+// source of S_phi and J_U for the final reduction (see k_diag_final)
+static int diag_src(const lbm_ctx* c) {
+  return c->dim == 2 ? (c->tr_march ? 1 : 0) | (c->u_march ? 2 : 0) : 0;
+}
+
+// Reduce the diagnostics of every domain into out[0..ndom-1] (synchronises).
+// Does not judge finiteness: the caller does.
 static lbm_status run_diag(lbm_ctx* c, lbm_diag* out) {
   const int ti = c->ty_index, TY = kTYs[ti];
   std::vector<double> front;
   if (c->dim == 3) {
     c->ops3.diag(c->H[0], c->stream, c->d_dom, c->k, c->d_part, c->d_front);
-    diag_final(c->ndom, c->stream, c->d_dom, c->d_part, c->d_slot, c->d_slot0[ti], c->d_rmax,
-               c->dim == 2 && c->tr_march ? 1 : 0, c->d_diag);
+    diag_final(c->ndom, c->stream, c->d_dom, c->d_part, c->d_slot, c->d_slot0[ti], c->d_rmax, diag_src(c),
+               c->d_diag);
     front.resize(2 * (size_t)c->nfront);
     HIPCHK(c, hipMemcpyAsync(front.data(), c->d_front, sizeof(double) * front.size(), hipMemcpyDeviceToHost,
                              c->stream));
   } else {
     c->ops.diag_tiles(TY, dim3(c->all[ti].n), c->stream, c->d_dom, c->all[ti].d, c->k, c->d_part);
-    diag_final(c->ndom, c->stream, c->d_dom, c->d_part, c->d_slot, c->d_slot0[ti], c->d_rmax,
-               c->dim == 2 && c->tr_march ? 1 : 0, c->d_diag);
+    diag_final(c->ndom, c->stream, c->d_dom, c->d_part, c->d_slot, c->d_slot0[ti], c->d_rmax, diag_src(c),
+               c->d_diag);
     c->ops.tips(c->ndom, c->stream, c->d_dom, c->k, c->d_diag);
   }
   HIPCHK(c, hipGetLastError());
   std::vector<DiagOut> h(c->ndom);
+  std::vector<unsigned long long> first(c->ndom);
   HIPCHK(c, hipMemcpyAsync(h.data(), c->d_diag, sizeof(DiagOut) * c->ndom, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(first.data(), c->d_first, sizeof(unsigned long long) * c->ndom,
+                           hipMemcpyDeviceToHost, c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   if (c->dim == 3) {
     double m = -1e300, sm = 0.0;
@@ -1184,7 +1215,6 @@ static lbm_status run_diag(lbm_ctx* c, lbm_diag* out) {
     h[0].tip[0] = m;
     h[0].tip[1] = sm / (double(c->H[0].nx) * c->H[0].ny);
   }
-  bool bad = false;
   for (int d = 0; d < c->ndom; ++d) {
     lbm_diag& o = out[d];
     memset(&o, 0, sizeof o);
@@ -1197,10 +1227,18 @@ static lbm_status run_diag(lbm_ctx* c, lbm_diag* out) {
     o.J_U = h[d].J_U;
     for (int j = 0; j < 16; ++j) o.tip[j] = h[d].tip[j];
     o.nonfinite = h[d].nonfinite;
-    bad |= h[d].nonfinite > 0;
+    o.t = double(c->k) * c->P[d].dt_base;
+    o.R_M = c->m0[d] != 0.0 ? (h[d].M_C - c->m0[d]) / c->m0[d] : 0.0;
+    o.first_nonfinite_step = first[d] == ~0ULL ? -1 : (int64_t)first[d];
   }
-  if (bad) return fail(c, LBM_EUNSTABLE, "non-finite values in the state");
   return LBM_OK;
+}
+
+// Screen the macroscopic planes of every domain after the current step
+// (absolute step c->k) for non-finite values; the device keeps the first
+// step at which each domain failed a screen.
+static void screen(lbm_ctx* c) {
+  nonfinite_check(c->storage == LBM_STORE_F64, c->ndom, c->nf_blocks, c->stream, c->d_dom, c->k, c->d_first);
 }
 
 lbm_status lbm_step_multirate(lbm_ctx* c, int64_t n, lbm_diag* diag) {
@@ -1209,11 +1247,19 @@ lbm_status lbm_step_multirate(lbm_ctx* c, int64_t n, lbm_diag* diag) {
   for (int d = 0; d < c->ndom; ++d)
     if (!c->initialised[d]) return fail(c, LBM_ESTATE, "lbm_init_seeds has not been called for every domain");
   HIPCHK(c, hipSetDevice(c->device));
+  if (c->need_m0) {   // M_C(0) of every domain, for R_M
+    std::vector<lbm_diag> d0(c->ndom);
+    lbm_status s = run_diag(c, d0.data());
+    if (s != LBM_OK) return s;
+    for (int d = 0; d < c->ndom; ++d) c->m0[d] = d0[d].M_C;
+    c->need_m0 = false;
+  }
   if (c->autotune && !c->tuned && c->dim == 2) {
     lbm_status s = autotune(c);
     if (s != LBM_OK) return s;
   }
   long long left = n;
+  bool screened = true;
   while (left > 0) {
     const bool graphable = c->use_graph && c->cycle <= kMaxGraphSteps;
     if (graphable && c->k % c->cycle == 0 && left >= c->cycle) {
@@ -1238,6 +1284,8 @@ lbm_status lbm_step_multirate(lbm_ctx* c, int64_t n, lbm_diag* diag) {
       HIPCHK(c, hipGraphLaunch(c->gexec, c->stream));
       c->k += c->cycle;
       left -= c->cycle;
+      screen(c);   // once per replayed cycle
+      screened = true;
     } else {
       const long long base = c->k - c->k % c->cycle;
       if (c->dim == 3 && c->koff != base) {
@@ -1247,10 +1295,31 @@ lbm_status lbm_step_multirate(lbm_ctx* c, int64_t n, lbm_diag* diag) {
       launch_step(c, c->stream, cycle_step(c, c->k + 1), left == 1);
       c->k += 1;
       left -= 1;
+      screened = false;
     }
   }
+  if (!screened) screen(c);
   HIPCHK(c, hipGetLastError());
-  if (diag) return run_diag(c, diag);
+  std::vector<lbm_diag> tmp;
+  if (!diag) {
+    tmp.resize(c->ndom);
+    diag = tmp.data();
+    std::vector<unsigned long long> first(c->ndom);
+    HIPCHK(c, hipMemcpyAsync(first.data(), c->d_first, sizeof(unsigned long long) * c->ndom,
+                             hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    for (int d = 0; d < c->ndom; ++d) diag[d].first_nonfinite_step = first[d] == ~0ULL ? -1 : (int64_t)first[d];
+  } else {
+    lbm_status s = run_diag(c, diag);
+    if (s != LBM_OK) return s;
+  }
+  for (int d = 0; d < c->ndom; ++d)
+    if (diag[d].first_nonfinite_step >= 0 || (diag != tmp.data() && diag[d].nonfinite > 0)) {
+      char b[160];
+      snprintf(b, sizeof b, "non-finite values in domain %d (first found after base step %lld)", d,
+               (long long)diag[d].first_nonfinite_step);
+      return fail(c, LBM_EUNSTABLE, b);
+    }
   return LBM_OK;
 }
 

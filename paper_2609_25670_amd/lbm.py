@@ -65,6 +65,7 @@ class Diag(ctypes.Structure):
         ("step", ctypes.c_int64), ("solid", ctypes.c_double), ("M_C", ctypes.c_double),
         ("enthalpy", ctypes.c_double), ("mass", ctypes.c_double), ("S_phi", ctypes.c_double),
         ("J_U", ctypes.c_double), ("tip", ctypes.c_double * 16), ("nonfinite", ctypes.c_int64),
+        ("t", ctypes.c_double), ("R_M", ctypes.c_double), ("first_nonfinite_step", ctypes.c_int64),
     ]
 
 
@@ -219,15 +220,18 @@ class Simulation:
         _check(self.lib, self.ctx, self.lib.lbm_configure(self.ctx, int(tile_rows), flags))
 
     def step(self, n, diag=False):
-        """Advance every domain by n base steps.  With ``diag`` returns a list
-        of per-domain diagnostic dicts (synchronises)."""
+        """Advance every domain by n base steps (synchronises).  With
+        ``diag`` returns a list of per-domain diagnostic dicts.  Raises
+        LBMError with status LBM_EUNSTABLE once non-finite values are
+        found, with or without ``diag``."""
         if not diag:
             _check(self.lib, self.ctx, self.lib.lbm_step_multirate(self.ctx, int(n), None))
             return None
         out = (Diag * self.n)()
         s = self.lib.lbm_step_multirate(self.ctx, int(n), out)
         res = [dict(step=o.step, solid=o.solid, M_C=o.M_C, enthalpy=o.enthalpy, mass=o.mass, S_phi=o.S_phi,
-                    J_U=o.J_U, tip=list(o.tip), nonfinite=o.nonfinite) for o in out]
+                    J_U=o.J_U, tip=list(o.tip), nonfinite=o.nonfinite, t=o.t, R_M=o.R_M,
+                    first_nonfinite_step=o.first_nonfinite_step) for o in out]
         if s == LBM_EUNSTABLE:
             err = LBMError(s, self.lib.lbm_last_error(self.ctx).decode())
             err.diag = res

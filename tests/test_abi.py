@@ -40,12 +40,13 @@ def test_struct_layout_matches_binding(tmp_path):
     c.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "lbm.h"\n'
                  'int main(){printf("%zu %zu %zu %zu %zu %zu\\n", sizeof(lbm_params), sizeof(lbm_diag),'
                  ' offsetof(lbm_params, U0), offsetof(lbm_params, coupling), offsetof(lbm_params, bc),'
-                 ' offsetof(lbm_diag, nonfinite));}\n')
+                 ' offsetof(lbm_diag, nonfinite)); printf("%zu %zu\\n", offsetof(lbm_diag, R_M),'
+                 ' offsetof(lbm_diag, first_nonfinite_step));}\n')
     exe = tmp_path / "sz"
     subprocess.run(["gcc", "-I", os.path.dirname(HEADER), str(c), "-o", str(exe)], check=True)
     out = [int(v) for v in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
     assert out == [ctypes.sizeof(Params), ctypes.sizeof(Diag), Params.U0.offset, Params.coupling.offset,
-                   Params.bc.offset, Diag.nonfinite.offset]
+                   Params.bc.offset, Diag.nonfinite.offset, Diag.R_M.offset, Diag.first_nonfinite_step.offset]
 
 
 def test_workspace_size_and_validation():

@@ -164,6 +164,7 @@ def test_tile_shapes_graph_and_fusion_are_bitwise_identical(storage):
     ref = None
     runs = [(r, g, f, False) for r in (4, 8, 16, 32) for g in (True, False) for f in (True, False)]
     runs += [(r, g, False, True) for r in (4, 32) for g in (True, False)]
+    runs += [(r, g, True, True) for r in (8, 16) for g in (True, False)]   # fused transfer, marching transports
     for rows, g, fuse, march in runs:
         _say(f"case determinism {storage} rows={rows} graph={g} fused={fuse} march={march}")
         (got,), _ = _gpu(wl, 64, storage=storage, names=names, tile_rows=rows, use_graph=g, fuse=fuse, march=march)
@@ -305,14 +306,17 @@ def test_marching_transfer_in_T_transport_is_bitwise_identical(storage, case):
             assert diag["S_phi"] == ref[1]["S_phi"] and diag["J_U"] == ref[1]["J_U"]
 
 
+@pytest.mark.parametrize("fuse", [False, True])
 @pytest.mark.parametrize("coupling", ["accum", "instant"])
-def test_marching_U_transport_is_bitwise_identical(coupling):
+def test_marching_U_transport_is_bitwise_identical(coupling, fuse):
     """The U transport marches with the phase field (62-column runs): the
     solutal case on 150 x 70 (walls, a 26-column last run, a 6-row last
     run) with accumulated or instantaneous coupling, N_U = 4, equals the
     tiled kernels bit for bit, with the same S_phi and J_U (with
     accumulated coupling J_U is the largest injected U, from the U
-    transport)."""
+    transport).  With the transfer fused into the (tiled) phase kernel
+    the transports still march: S_phi then comes from the tiles and the
+    accumulated J_U from the marching U transport."""
     from paper_2609_25670_amd import simulation_for
 
     wl = L.reduced(L.solutal_512(), 150, 70)
@@ -320,9 +324,9 @@ def test_marching_U_transport_is_bitwise_identical(coupling):
     names = ("phi", "U", "f_phi", "jU") + (("P_U",) if coupling == "accum" else ())
     res = []
     for march in (False, True):
-        _say(f"case marching U transport {coupling} march={march}")
+        _say(f"case marching U transport {coupling} fuse={fuse} march={march}")
         sim = simulation_for(wl, storage="f64")
-        sim.configure(8, True, False, march)
+        sim.configure(8, True, fuse, march)
         sim.step(6)
         diag = sim.step(33, diag=True)[0]
         res.append((sim.read(0, names), diag))
@@ -418,7 +422,72 @@ def test_nonfinite_state_is_reported():
         sim.step(4, diag=True)
     assert ei.value.status == lbm.LBM_EUNSTABLE
     assert ei.value.diag[0]["nonfinite"] > 0
+    assert ei.value.diag[0]["first_nonfinite_step"] == 8
     sim.close()
+
+
+@pytest.mark.parametrize("case", ["direct", "graph", "batched", "3d"])
+def test_nonfinite_state_is_reported_without_diagnostics(case):
+    """Stepping without diagnostics still fails with LBM_EUNSTABLE: the
+    device screens phi, U, T and rho after every replayed cycle and after
+    the call's last step.  A NaN written into U after 8 steps is found at
+    the first screen after it (the end of the call for direct steps, the
+    end of the first replayed cycle otherwise), the right domain of a batch
+    is named, and the first failing step stays reported afterwards."""
+    from paper_2609_25670_amd import lbm, simulation_for
+
+    if case == "3d":
+        wl = L.reduced(L.directional_3d(), 64, 32, 48)
+    elif case == "batched":
+        wl = L.ensemble_256(n_domains=3, side_lo=40, side_hi=90)
+    else:
+        wl = L.reduced(L.solutal_512(), 80, 70)
+    _say(f"case nonfinite detection without diagnostics: {case}")
+    sim = simulation_for(wl, storage="f32")
+    sim.configure(0 if case == "3d" else 8, case != "direct")
+    sim.step(8)
+    bad = sim.n - 1
+    U = sim.read(bad, ("U",))["U"].copy()
+    U[(slice(None),) * (U.ndim - 2) + (5, 7)] = np.nan
+    sim.write(bad, {"U": U})
+    n = 3 if case == "direct" else 4000
+    with pytest.raises(lbm.LBMError) as ei:
+        sim.step(n)
+    assert ei.value.status == lbm.LBM_EUNSTABLE
+    assert f"domain {bad}" in str(ei.value)
+    with pytest.raises(lbm.LBMError) as ei2:
+        sim.step(1, diag=True)
+    first = ei2.value.diag[bad]["first_nonfinite_step"]
+    _say(f"  first non-finite step {first}; message: {ei.value}")
+    assert 8 < first <= 8 + n
+    if case == "direct":
+        assert first == 11
+    for i in range(sim.n):
+        if i != bad:
+            assert ei2.value.diag[i]["first_nonfinite_step"] == -1
+    sim.close()
+
+
+def test_time_and_solute_drift_match_the_oracle():
+    """t = k dt_base and R_M = [M_C(t) - M_C(0)]/M_C(0) (Section 4.4), with
+    M_C(0) taken at the first step, against the oracle's total solute."""
+    wl = L.reduced(L.solutal_512(), 96, 80)
+    d = wl["domains"][0]
+    _say("case t and R_M fp64 60 steps")
+    (got,), diag = _gpu(wl, 60, names=("phi", "U"), tile_rows=8)
+    dom0 = oracle.Domain(d)
+    dom = oracle.run(d, 60)
+
+    def total_C(o):
+        kf = (1 + d["k"]) - (1 - d["k"]) * o.phi
+        return float(np.sum(d["C_inf"] * kf * (1 + (1 - d["k"]) * o.U) / 2))
+
+    m0, m1 = total_C(dom0), total_C(dom)
+    r = (m1 - m0) / m0
+    _say(f"  R_M gpu {diag[0]['R_M']:.6e} oracle {r:.6e}; t = {diag[0]['t']}")
+    assert diag[0]["t"] == 60 * d["dt_base"]
+    assert abs(diag[0]["R_M"] - r) <= 1e-12 * max(1.0, abs(r)) + 1e-15
+    assert diag[0]["first_nonfinite_step"] == -1
 
 
 @pytest.mark.parametrize("steps,tol", [(8, 1e-7), (40, 1e-7)])
