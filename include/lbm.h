@@ -199,6 +199,29 @@ lbm_status lbm_init_front(lbm_ctx* ctx, int32_t domain, const double* xi);
  * after an initialisation also reduces M_C(0) for R_M. */
 lbm_status lbm_step_multirate(lbm_ctx* ctx, int64_t n_base_steps, lbm_diag* diag_out);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * stepping as lbm_step_multirate, with the same kernels and the same
+ * results, that allocates nothing.  The reduction scratch of its kernels
+ * (per-tile partials, per-run maxima, the reduced diagnostics, the 3D front
+ * partials) lives in a static device array of 16 MiB per GPU, held until
+ * the process ends, instead of the context's workspace; no HIP graph is
+ * captured or replayed (every step is launched directly) and the tile-height
+ * autotuner does not run (a height fixed by lbm_configure is used, else
+ * 16 rows until an lbm_step_multirate call has tuned it).
+ * Limits and semantics:
+ *   - LBM_EINVAL when the context's scratch exceeds the static array (a
+ *     2D context with more than about 200,000 64 x 4 tiles, a 3D domain of
+ *     more than about 50 M sites);
+ *   - the array is shared by every call on a GPU and keeps the last call's
+ *     contents: each call clears its partials first, so S_phi and J_U report
+ *     the phase steps and injections of this call only (n_base_steps >= 1,
+ *     and with accumulated coupling at least one U update, for a defined
+ *     J_U); calls that overlap on one GPU (several streams or threads) race;
+ *   - failure detection and its synchronisation at the end of the call are
+ *     those of lbm_step_multirate. */
+lbm_status lbm_step_multirate_static(lbm_ctx* ctx, int64_t n_base_steps, lbm_diag* diag_out);
+
 /* Copy the planes selected by mask of one domain into dst (caller-owned,
  * device memory if dst_is_device else host memory), as FP64 if dst_fp64
  * else FP32, packed in mask-bit order.  Populations are reconstructed from

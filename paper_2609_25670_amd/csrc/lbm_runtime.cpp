@@ -17,6 +17,7 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <numeric>
 #include <string>
 #include <vector>
@@ -149,6 +150,17 @@ long long ipow_lcm(long long a, long long b) { return a / std::gcd(a, b) * b; }
 
 }  // namespace
 
+// Reduction scratch of the step and diagnostics kernels: per-tile (3D:
+// per-block) partials, per-run maxima of the marching kernels, the reduced
+// diagnostics and the 3D front partials.  The workspace holds one set; the
+// allocation-free entry point carves another from a static device array.
+struct Scratch {
+  Partial* part = nullptr;
+  double2* rmax = nullptr;   // per marching run: largest |dU| and injected U of the last transfer
+  DiagOut* diag = nullptr;
+  double* front = nullptr;   // 3D front partials: (max, sum) per column block
+};
+
 struct lbm_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -159,8 +171,16 @@ struct lbm_ctx {
   Ops3 ops3{};
   int dim = 2;
   long long koff = 0;           // value of Dom::koff on the device (3D)
-  double* d_front = nullptr;   // 3D front partials: (max, sum) per column block
   int nfront = 0;
+  Scratch s;                   // the set the kernels use: ws_s, or the static one during a static call
+  Scratch ws_s;                // the workspace's set
+  size_t scratch_bytes = 0;    // bytes of one set (the static array must hold them)
+  long long nparts = 0, nrmax = 0;
+  // pinned host staging for the diagnostics, allocated at creation
+  DiagOut* h_diag = nullptr;
+  unsigned long long* h_first = nullptr;
+  double* h_front = nullptr;
+  std::vector<lbm_diag> h_d;
   int nblk3 = 0;               // 3D: site blocks of 256
   int ndom = 0;
   std::vector<lbm_params> P;
@@ -171,9 +191,7 @@ struct lbm_ctx {
   Dom* d_dom = nullptr;
   TileSet all[kNTY];
   std::vector<Group> g_phi, g_U, g_T, g_F;
-  Partial* d_part = nullptr;
   int* d_slot = nullptr;
-  double2* d_rmax = nullptr;   // per marching run: largest |dU| and injected U of the last transfer
   bool tr_march = false;       // the last launched transfer marched (the diagnostics read d_rmax)
   bool u_march = false;        // the last launched U transport marched (accumulated J_U in d_rmax)
   unsigned long long* d_first = nullptr;   // per domain: first checked step with a non-finite value
@@ -181,7 +199,6 @@ struct lbm_ctx {
   std::vector<double> m0;      // M_C at the start of the run (for R_M)
   bool need_m0 = true;         // M_C(0) is taken at the first step after an initialisation
   int* d_slot0[kNTY] = {nullptr, nullptr, nullptr, nullptr};
-  DiagOut* d_diag = nullptr;
   int* d_codes = nullptr;
   double* d_stage = nullptr;
   size_t stage_elems = 0;
@@ -340,6 +357,38 @@ std::vector<int4> xcd_order(const std::vector<int4>& spatial) {
 
 }  // namespace
 
+// ------------------------------------------------------------------ static scratch
+// Scratch of lbm_step_multirate_static, for callers that cannot allocate:
+// one array per device, held until the process ends.  Its name is a host
+// stand-in in host code; kernels get the device address that
+// hipGetSymbolAddress returns on each device, taken once per device with
+// that device current (at the first lbm_create on it).
+constexpr size_t kScratchBytes = size_t(16) << 20;
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices] = {};
+static hipError_t g_scratch_err[kMaxDevices] = {};
+static bool g_scratch_done[kMaxDevices] = {};
+
+// clears a range of the static scratch (a kernel, so that no memset node
+// lands in a caller's captured graph)
+__global__ void k_zero_words(unsigned long long* p, long long n) {
+  for (long long i = (long long)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (long long)gridDim.x * blockDim.x)
+    p[i] = 0ull;
+}
+
+static void static_scratch_setup(int device) {
+  if (device < 0 || device >= kMaxDevices) return;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (g_scratch_done[device]) return;
+  void* ptr = nullptr;
+  const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+  g_scratch_err[device] = e;
+  g_scratch_ptr[device] = e == hipSuccess ? ptr : nullptr;
+  g_scratch_done[device] = true;
+}
+
 // ------------------------------------------------------------------ helpers
 static int ty_slot(int rows) {
   for (int i = 0; i < kNTY; ++i)
@@ -389,7 +438,7 @@ static bool fuses_T(const lbm_ctx* c, unsigned k) {
 
 static void launch_step(lbm_ctx* c, hipStream_t st, unsigned k, bool last = false) {
   if (c->dim == 3) {
-    c->ops3.step(c->H[0], st, c->d_dom, k, c->d_part);
+    c->ops3.step(c->H[0], st, c->d_dom, k, c->s.part);
     return;
   }
   const int ti = c->ty_index, TY = kTYs[ti];
@@ -399,20 +448,20 @@ static void launch_step(lbm_ctx* c, hipStream_t st, unsigned k, bool last = fals
     if (k % g.N == 0) {
       c->tr_march = !fused && use_march(c);
       if (fused) {
-        c->ops.phase_tr(kTYs[tf], dim3(g.ts[tf].n), st, c->d_dom, g.ts[tf].d, k, c->d_part);
+        c->ops.phase_tr(kTYs[tf], dim3(g.ts[tf].n), st, c->d_dom, g.ts[tf].d, k, c->s.part);
       } else {
         if (use_march(c)) {
           c->ops.phase_ym(c->qs, dim3(g.runs64.n), st, c->d_dom, g.runs64.d, k);
           if (!fuses_T(c, k))   // else inside the T transport, launched first below
-            c->ops.transfer_ym(dim3(g.runs.n), st, c->d_dom, g.runs.d, k, c->d_rmax);
+            c->ops.transfer_ym(dim3(g.runs.n), st, c->d_dom, g.runs.d, k, c->s.rmax);
         } else {
           if (c->pending)   // the previous step's transfer runs inside this phase kernel
-            c->ops.dtr_phase(TY, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k, c->d_part);
+            c->ops.dtr_phase(TY, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k, c->s.part);
           else
             c->ops.phase(TY, c->qs, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k);
           c->pending = !last && defers(c, k);
           if (!c->pending && !fuses_U(c, k))   // else in the phase kernel of step k + 1 or the U transport
-            c->ops.transfer(TY, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k, c->d_part);
+            c->ops.transfer(TY, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k, c->s.part);
         }
       }
     }
@@ -422,23 +471,23 @@ static void launch_step(lbm_ctx* c, hipStream_t st, unsigned k, bool last = fals
   const bool trT = fuses_T(c, k);
   if (trT)
     for (auto& g : c->g_T)
-      c->ops.tr_scalar_ym(c->qs, dim3(g.runs.n), st, c->d_dom, g.runs.d, k, c->d_rmax);
+      c->ops.tr_scalar_ym(c->qs, dim3(g.runs.n), st, c->d_dom, g.runs.d, k, c->s.rmax);
   // (the U transport marches too since the runs are 62 columns wide: 191
   // against 224 us per launch on the batched ensemble)
   for (auto& g : c->g_U)
     if (k % g.N == 0) {
       c->u_march = march && !fuses_U(c, k);
       if (fuses_U(c, k))   // carrying this step's transfer
-        c->ops.dtr_scalar(TY, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k, c->d_part);
+        c->ops.dtr_scalar(TY, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k, c->s.part);
       else if (march)
-          c->ops.scalar_ym(0, c->qs, dim3(g.runs.n), st, c->d_dom, g.runs.d, k, c->d_rmax);
+          c->ops.scalar_ym(0, c->qs, dim3(g.runs.n), st, c->d_dom, g.runs.d, k, c->s.rmax);
         else
-          c->ops.scalar(0, TY, c->qs, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k, c->d_part);
+          c->ops.scalar(0, TY, c->qs, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k, c->s.part);
     }
   for (auto& g : c->g_T)
     if (k % g.N == 0 && !trT) {
-      if (march) c->ops.scalar_ym(1, c->qs, dim3(g.runs.n), st, c->d_dom, g.runs.d, k, c->d_rmax);
-      else c->ops.scalar(1, TY, c->qs, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k, c->d_part);
+      if (march) c->ops.scalar_ym(1, c->qs, dim3(g.runs.n), st, c->d_dom, g.runs.d, k, c->s.rmax);
+      else c->ops.scalar(1, TY, c->qs, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k, c->s.part);
     }
   for (auto& g : c->g_F)
     if (k % g.N == 0) c->ops.flow(TY, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k);
@@ -782,7 +831,7 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
   if (c->dim == 3) {
     c->nblk3 = (int)blocks3(p[0]);
     c->nfront = (int)((p[0].nx * (long long)p[0].ny + 255) / 256);
-    c->d_front = (double*)take(sizeof(double) * 2 * (c->nfront + 1));
+    c->s.front = (double*)take(sizeof(double) * 2 * (c->nfront + 1));
   }
   auto build = [&](const std::vector<int>& doms, int ti, TileSet& ts, std::vector<int>* slot0) -> lbm_status {
     const int TY = kTYs[ti];
@@ -882,15 +931,27 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
     c->one_U &= p[i].has_U != 0;
     c->one_T &= p[i].has_T != 0 && p[i].T_mode != LBM_T_PULLED && p[i].coupling == LBM_COUPLE_INSTANT;
   }
-  c->d_part = (Partial*)take(sizeof(Partial) * (size_t)tilesmax);
-  c->d_rmax = (double2*)take(sizeof(double2) * (size_t)(rbase + 1));
-  if (hipMemset(c->d_rmax, 0, sizeof(double2) * (size_t)(rbase + 1)) != hipSuccess) {
+  c->s.part = (Partial*)take(sizeof(Partial) * (size_t)tilesmax);
+  c->s.rmax = (double2*)take(sizeof(double2) * (size_t)(rbase + 1));
+  if (hipMemset(c->s.rmax, 0, sizeof(double2) * (size_t)(rbase + 1)) != hipSuccess) {
     lbm_destroy(c);
     return fail(nullptr, LBM_EDEVICE, "clearing the run maxima failed");
   }
   c->d_slot = (int*)take(sizeof(int) * (size_t)tilesmax);
   for (int ti = 0; ti < kNTY; ++ti) c->d_slot0[ti] = (int*)take(sizeof(int) * (n + 1));
-  c->d_diag = (DiagOut*)take(sizeof(DiagOut) * n);
+  c->s.diag = (DiagOut*)take(sizeof(DiagOut) * n);
+  c->ws_s = c->s;
+  c->nparts = tilesmax;
+  c->nrmax = rbase + 1;
+  c->scratch_bytes = align256(sizeof(Partial) * (size_t)tilesmax) + align256(sizeof(double2) * (size_t)(rbase + 1)) +
+                     align256(sizeof(DiagOut) * n) + align256(sizeof(double) * 2 * (size_t)(c->nfront + 1));
+  c->h_d.resize(n);
+  if (hipHostMalloc((void**)&c->h_diag, sizeof(DiagOut) * n) != hipSuccess ||
+      hipHostMalloc((void**)&c->h_first, sizeof(unsigned long long) * n) != hipSuccess ||
+      hipHostMalloc((void**)&c->h_front, sizeof(double) * (2 * (size_t)c->nfront + 2)) != hipSuccess) {
+    lbm_destroy(c);
+    return fail(nullptr, LBM_ENOMEM, "pinned host staging allocation failed");
+  }
   c->d_first = (unsigned long long*)take(sizeof(unsigned long long) * n);
   c->d_codes = (int*)take(sizeof(int) * kMaxCodes);
   c->m0.assign(n, 0.0);
@@ -918,11 +979,12 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
         return fail(nullptr, LBM_EDEVICE, "slot upload failed");
       }
     if (hipMemset(c->d_first, 0xff, sizeof(unsigned long long) * n) != hipSuccess ||
-        hipMemset(c->d_part, 0, sizeof(Partial) * (size_t)tilesmax) != hipSuccess) {
+        hipMemset(c->s.part, 0, sizeof(Partial) * (size_t)tilesmax) != hipSuccess) {
       lbm_destroy(c);
       return fail(nullptr, LBM_EDEVICE, "partial clear failed");
     }
   }
+  static_scratch_setup(device);   // the allocation-free entry point's scratch on this device
   if (hipStreamCreateWithFlags(&c->cap_stream, hipStreamNonBlocking) != hipSuccess) {
     lbm_destroy(c);
     return fail(nullptr, LBM_EDEVICE, "stream creation failed");
@@ -1063,28 +1125,28 @@ lbm_status lbm_kernel_times(lbm_ctx* c, int32_t reps, double* ms_out, double* pe
         if (c->dim == 3) {
           const Dom& h = c->H[0];
           if (kind == 0) c->ops3.phase(h, c->stream, c->d_dom, k);
-          if (kind == 1) c->ops3.transfer(h, c->stream, c->d_dom, k, c->d_part);
-          if (kind == 2) c->ops3.scalar(0, h, c->stream, c->d_dom, k, c->d_part);
-          if (kind == 3) c->ops3.scalar(1, h, c->stream, c->d_dom, k, c->d_part);
+          if (kind == 1) c->ops3.transfer(h, c->stream, c->d_dom, k, c->s.part);
+          if (kind == 2) c->ops3.scalar(0, h, c->stream, c->d_dom, k, c->s.part);
+          if (kind == 3) c->ops3.scalar(1, h, c->stream, c->d_dom, k, c->s.part);
           if (kind == 4) c->ops3.flow(h, c->stream, c->d_dom, k);
           return;
         }
         if (kind == 0 && fused) {
           const int tf = ty_slot(c->ops.phase_tr_rows(TY));
-          c->ops.phase_tr(kTYs[tf], dim3(g.ts[tf].n), c->stream, c->d_dom, g.ts[tf].d, k, c->d_part);
+          c->ops.phase_tr(kTYs[tf], dim3(g.ts[tf].n), c->stream, c->d_dom, g.ts[tf].d, k, c->s.part);
         }
         if (kind == 0 && !fused && use_march(c))
           c->ops.phase_ym(c->qs, dim3(g.runs64.n), c->stream, c->d_dom, g.runs64.d, k);
         else if (kind == 0 && !fused)
           c->ops.phase(TY, c->qs, grid, c->stream, c->d_dom, g.ts[ti].d, k);
         if (kind == 1 && use_march(c))
-          c->ops.transfer_ym(dim3(g.runs.n), c->stream, c->d_dom, g.runs.d, k, c->d_rmax);
+          c->ops.transfer_ym(dim3(g.runs.n), c->stream, c->d_dom, g.runs.d, k, c->s.rmax);
         else if (kind == 1)
-          c->ops.transfer(TY, grid, c->stream, c->d_dom, g.ts[ti].d, k, c->d_part);
+          c->ops.transfer(TY, grid, c->stream, c->d_dom, g.ts[ti].d, k, c->s.part);
         if ((kind == 2 || kind == 3) && use_march(c))
-          c->ops.scalar_ym(kind - 2, c->qs, dim3(g.runs.n), c->stream, c->d_dom, g.runs.d, k, c->d_rmax);
+          c->ops.scalar_ym(kind - 2, c->qs, dim3(g.runs.n), c->stream, c->d_dom, g.runs.d, k, c->s.rmax);
         else if (kind == 2 || kind == 3)
-          c->ops.scalar(kind - 2, TY, c->qs, grid, c->stream, c->d_dom, g.ts[ti].d, k, c->d_part);
+          c->ops.scalar(kind - 2, TY, c->qs, grid, c->stream, c->d_dom, g.ts[ti].d, k, c->s.part);
         if (kind == 4) c->ops.flow(TY, grid, c->stream, c->d_dom, g.ts[ti].d, k);
       };
       launch();
@@ -1132,7 +1194,7 @@ lbm_status lbm_kernel_times(lbm_ctx* c, int32_t reps, double* ms_out, double* pe
       }
       const Group& g = c->g_phi[0];
       lbm_status s = time_launch(
-          [&]() { c->ops.dtr_phase(TY, dim3(g.ts[ti].n), c->stream, c->d_dom, g.ts[ti].d, 2u, c->d_part); },
+          [&]() { c->ops.dtr_phase(TY, dim3(g.ts[ti].n), c->stream, c->d_dom, g.ts[ti].d, 2u, c->s.part); },
           ms_out[5]);
       if (s != LBM_OK) return s;
     }
@@ -1145,7 +1207,7 @@ lbm_status lbm_kernel_times(lbm_ctx* c, int32_t reps, double* ms_out, double* pe
       const Group& g = c->g_U[0];
       const unsigned k = cycle_step(c, due(g.N));
       lbm_status s = time_launch(
-          [&]() { c->ops.dtr_scalar(TY, dim3(g.ts[ti].n), c->stream, c->d_dom, g.ts[ti].d, k, c->d_part); },
+          [&]() { c->ops.dtr_scalar(TY, dim3(g.ts[ti].n), c->stream, c->d_dom, g.ts[ti].d, k, c->s.part); },
           ms_out[6]);
       if (s != LBM_OK) return s;
     }
@@ -1162,7 +1224,7 @@ lbm_status lbm_kernel_times(lbm_ctx* c, int32_t reps, double* ms_out, double* pe
       const unsigned k = cycle_step(c, due(std::lcm(g.N, c->g_phi[0].N)));
       lbm_status s = time_launch(
           [&]() {
-            c->ops.tr_scalar_ym(c->qs, dim3(g.runs.n), c->stream, c->d_dom, g.runs.d, k, c->d_rmax);
+            c->ops.tr_scalar_ym(c->qs, dim3(g.runs.n), c->stream, c->d_dom, g.runs.d, k, c->s.rmax);
           },
           ms_out[7]);
       if (s != LBM_OK) return s;
@@ -1181,35 +1243,34 @@ static int diag_src(const lbm_ctx* c) {
 }
 
 // Reduce the diagnostics of every domain into out[0..ndom-1] (synchronises).
-// Does not judge finiteness: the caller does.
+// Does not judge finiteness: the caller does.  Uses the host staging held
+// by the context (no allocation).
 static lbm_status run_diag(lbm_ctx* c, lbm_diag* out) {
   const int ti = c->ty_index, TY = kTYs[ti];
-  std::vector<double> front;
   if (c->dim == 3) {
-    c->ops3.diag(c->H[0], c->stream, c->d_dom, c->k, c->d_part, c->d_front);
-    diag_final(c->ndom, c->stream, c->d_dom, c->d_part, c->d_slot, c->d_slot0[ti], c->d_rmax, diag_src(c),
-               c->d_diag);
-    front.resize(2 * (size_t)c->nfront);
-    HIPCHK(c, hipMemcpyAsync(front.data(), c->d_front, sizeof(double) * front.size(), hipMemcpyDeviceToHost,
-                             c->stream));
+    c->ops3.diag(c->H[0], c->stream, c->d_dom, c->k, c->s.part, c->s.front);
+    diag_final(c->ndom, c->stream, c->d_dom, c->s.part, c->d_slot, c->d_slot0[ti], c->s.rmax, diag_src(c),
+               c->s.diag);
+    HIPCHK(c, hipMemcpyAsync(c->h_front, c->s.front, sizeof(double) * 2 * (size_t)c->nfront,
+                             hipMemcpyDeviceToHost, c->stream));
   } else {
-    c->ops.diag_tiles(TY, dim3(c->all[ti].n), c->stream, c->d_dom, c->all[ti].d, c->k, c->d_part);
-    diag_final(c->ndom, c->stream, c->d_dom, c->d_part, c->d_slot, c->d_slot0[ti], c->d_rmax, diag_src(c),
-               c->d_diag);
-    c->ops.tips(c->ndom, c->stream, c->d_dom, c->k, c->d_diag);
+    c->ops.diag_tiles(TY, dim3(c->all[ti].n), c->stream, c->d_dom, c->all[ti].d, c->k, c->s.part);
+    diag_final(c->ndom, c->stream, c->d_dom, c->s.part, c->d_slot, c->d_slot0[ti], c->s.rmax, diag_src(c),
+               c->s.diag);
+    c->ops.tips(c->ndom, c->stream, c->d_dom, c->k, c->s.diag);
   }
   HIPCHK(c, hipGetLastError());
-  std::vector<DiagOut> h(c->ndom);
-  std::vector<unsigned long long> first(c->ndom);
-  HIPCHK(c, hipMemcpyAsync(h.data(), c->d_diag, sizeof(DiagOut) * c->ndom, hipMemcpyDeviceToHost, c->stream));
-  HIPCHK(c, hipMemcpyAsync(first.data(), c->d_first, sizeof(unsigned long long) * c->ndom,
-                           hipMemcpyDeviceToHost, c->stream));
+  DiagOut* h = c->h_diag;
+  unsigned long long* first = c->h_first;
+  HIPCHK(c, hipMemcpyAsync(h, c->s.diag, sizeof(DiagOut) * c->ndom, hipMemcpyDeviceToHost, c->stream));
+  HIPCHK(c, hipMemcpyAsync(first, c->d_first, sizeof(unsigned long long) * c->ndom, hipMemcpyDeviceToHost,
+                           c->stream));
   HIPCHK(c, hipStreamSynchronize(c->stream));
   if (c->dim == 3) {
     double m = -1e300, sm = 0.0;
     for (int b = 0; b < c->nfront; ++b) {
-      m = std::max(m, front[2 * b]);
-      sm += front[2 * b + 1];
+      m = std::max(m, c->h_front[2 * b]);
+      sm += c->h_front[2 * b + 1];
     }
     for (int j = 0; j < 16; ++j) h[0].tip[j] = 0.0;
     h[0].tip[0] = m;
@@ -1241,27 +1302,24 @@ static void screen(lbm_ctx* c) {
   nonfinite_check(c->storage == LBM_STORE_F64, c->ndom, c->nf_blocks, c->stream, c->d_dom, c->k, c->d_first);
 }
 
-lbm_status lbm_step_multirate(lbm_ctx* c, int64_t n, lbm_diag* diag) {
-  if (!c) return LBM_EINVAL;
-  if (n < 0) return fail(c, LBM_EINVAL, "negative step count");
-  for (int d = 0; d < c->ndom; ++d)
-    if (!c->initialised[d]) return fail(c, LBM_ESTATE, "lbm_init_seeds has not been called for every domain");
-  HIPCHK(c, hipSetDevice(c->device));
+// The body of both stepping entry points.  With use_static the scratch is
+// the device's static array (already selected in c->s), no graph is
+// captured or replayed and the autotuner does not run.
+static lbm_status step_impl(lbm_ctx* c, int64_t n, lbm_diag* diag, bool use_static) {
   if (c->need_m0) {   // M_C(0) of every domain, for R_M
-    std::vector<lbm_diag> d0(c->ndom);
-    lbm_status s = run_diag(c, d0.data());
+    lbm_status s = run_diag(c, c->h_d.data());
     if (s != LBM_OK) return s;
-    for (int d = 0; d < c->ndom; ++d) c->m0[d] = d0[d].M_C;
+    for (int d = 0; d < c->ndom; ++d) c->m0[d] = c->h_d[d].M_C;
     c->need_m0 = false;
   }
-  if (c->autotune && !c->tuned && c->dim == 2) {
+  if (!use_static && c->autotune && !c->tuned && c->dim == 2) {
     lbm_status s = autotune(c);
     if (s != LBM_OK) return s;
   }
   long long left = n;
   bool screened = true;
   while (left > 0) {
-    const bool graphable = c->use_graph && c->cycle <= kMaxGraphSteps;
+    const bool graphable = !use_static && c->use_graph && c->cycle <= kMaxGraphSteps;
     if (graphable && c->k % c->cycle == 0 && left >= c->cycle) {
       if (!c->gexec || c->graph_ty != c->ty_index) {
         if (c->gexec) {
@@ -1296,31 +1354,85 @@ lbm_status lbm_step_multirate(lbm_ctx* c, int64_t n, lbm_diag* diag) {
       c->k += 1;
       left -= 1;
       screened = false;
+      if (c->k % c->cycle == 0 && left > 0) {   // direct launches: screen at every cycle end too
+        screen(c);
+        screened = true;
+      }
     }
   }
   if (!screened) screen(c);
   HIPCHK(c, hipGetLastError());
-  std::vector<lbm_diag> tmp;
-  if (!diag) {
-    tmp.resize(c->ndom);
-    diag = tmp.data();
-    std::vector<unsigned long long> first(c->ndom);
-    HIPCHK(c, hipMemcpyAsync(first.data(), c->d_first, sizeof(unsigned long long) * c->ndom,
+  const bool want = diag != nullptr;
+  if (!want) {
+    diag = c->h_d.data();
+    HIPCHK(c, hipMemcpyAsync(c->h_first, c->d_first, sizeof(unsigned long long) * c->ndom,
                              hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
-    for (int d = 0; d < c->ndom; ++d) diag[d].first_nonfinite_step = first[d] == ~0ULL ? -1 : (int64_t)first[d];
+    for (int d = 0; d < c->ndom; ++d) {
+      diag[d].nonfinite = 0;
+      diag[d].first_nonfinite_step = c->h_first[d] == ~0ULL ? -1 : (int64_t)c->h_first[d];
+    }
   } else {
     lbm_status s = run_diag(c, diag);
     if (s != LBM_OK) return s;
   }
   for (int d = 0; d < c->ndom; ++d)
-    if (diag[d].first_nonfinite_step >= 0 || (diag != tmp.data() && diag[d].nonfinite > 0)) {
+    if (diag[d].first_nonfinite_step >= 0 || diag[d].nonfinite > 0) {
       char b[160];
       snprintf(b, sizeof b, "non-finite values in domain %d (first found after base step %lld)", d,
                (long long)diag[d].first_nonfinite_step);
       return fail(c, LBM_EUNSTABLE, b);
     }
   return LBM_OK;
+}
+
+lbm_status lbm_step_multirate(lbm_ctx* c, int64_t n, lbm_diag* diag) {
+  if (!c) return LBM_EINVAL;
+  if (n < 0) return fail(c, LBM_EINVAL, "negative step count");
+  for (int d = 0; d < c->ndom; ++d)
+    if (!c->initialised[d]) return fail(c, LBM_ESTATE, "lbm_init_seeds has not been called for every domain");
+  HIPCHK(c, hipSetDevice(c->device));
+  return step_impl(c, n, diag, false);
+}
+
+lbm_status lbm_step_multirate_static(lbm_ctx* c, int64_t n, lbm_diag* diag) {
+  if (!c) return LBM_EINVAL;
+  if (n < 0) return fail(c, LBM_EINVAL, "negative step count");
+  if (c->scratch_bytes > kScratchBytes) {
+    char b[200];
+    snprintf(b, sizeof b, "this context needs %zu bytes of reduction scratch; the static scratch holds %zu",
+             c->scratch_bytes, kScratchBytes);
+    return fail(c, LBM_EINVAL, b);
+  }
+  for (int d = 0; d < c->ndom; ++d)
+    if (!c->initialised[d]) return fail(c, LBM_ESTATE, "lbm_init_seeds has not been called for every domain");
+  HIPCHK(c, hipSetDevice(c->device));
+  void* base = (c->device >= 0 && c->device < kMaxDevices) ? g_scratch_ptr[c->device] : nullptr;
+  if (!base) {
+    const hipError_t e = (c->device >= 0 && c->device < kMaxDevices) ? g_scratch_err[c->device] : hipErrorInvalidDevice;
+    return fail(c, LBM_EDEVICE, std::string("static scratch address unavailable: ") + hipGetErrorString(e));
+  }
+  char* cur = (char*)base;
+  auto take = [&](size_t bytes) {
+    void* r = cur;
+    cur += align256(bytes);
+    return r;
+  };
+  Scratch st;
+  st.part = (Partial*)take(sizeof(Partial) * (size_t)c->nparts);
+  st.rmax = (double2*)take(sizeof(double2) * (size_t)c->nrmax);
+  st.diag = (DiagOut*)take(sizeof(DiagOut) * c->ndom);
+  st.front = (double*)take(sizeof(double) * 2 * (size_t)(c->nfront + 1));
+  // the array keeps the previous call's contents (possibly another
+  // context's): start from zero partials and run maxima, with a kernel
+  const long long words = (long long)(((char*)st.diag - (char*)st.part) / sizeof(unsigned long long));
+  k_zero_words<<<(unsigned)std::min<long long>((words + 255) / 256, 1024), 256, 0, c->stream>>>(
+      (unsigned long long*)st.part, words);
+  HIPCHK(c, hipGetLastError());
+  c->s = st;
+  const lbm_status r = step_impl(c, n, diag, true);
+  c->s = c->ws_s;
+  return r;
 }
 
 static int codes_for(const Dom& D, uint32_t mask, int* codes) {
@@ -1469,6 +1581,9 @@ void lbm_destroy(lbm_ctx* c) {
   if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
   if (c->cap_stream) (void)hipStreamDestroy(c->cap_stream);
   if (c->own_ws && c->ws) (void)hipFree(c->ws);
+  if (c->h_diag) (void)hipHostFree(c->h_diag);
+  if (c->h_first) (void)hipHostFree(c->h_first);
+  if (c->h_front) (void)hipHostFree(c->h_front);
   delete c;
 }
 

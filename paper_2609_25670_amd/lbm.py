@@ -33,7 +33,7 @@ FIELD_BITS = [("phi", F_PHI, 1), ("U", F_U, 1), ("T", F_T, 1), ("rho", F_RHO, 1)
               ("s_U", F_SU, 1), ("s_T", F_ST, 1)]
 
 EXPORTS = ["lbm_workspace_bytes", "lbm_create", "lbm_init_seeds", "lbm_init_front", "lbm_step_multirate",
-           "lbm_read_fields",
+           "lbm_step_multirate_static", "lbm_read_fields",
            "lbm_write_fields", "lbm_configure", "lbm_kernel_times", "lbm_steps_done", "lbm_marching",
            "lbm_tile_rows", "lbm_last_error", "lbm_destroy"]
 KERNEL_KINDS = ("phase", "transfer", "U", "T", "flow", "phase_dtr", "U_dtr", "T_tr")
@@ -99,6 +99,8 @@ def load() -> ctypes.CDLL:
     lib.lbm_init_front.argtypes = [ctypes.c_void_p, ctypes.c_int32, P(ctypes.c_double)]
     lib.lbm_step_multirate.restype = ctypes.c_int
     lib.lbm_step_multirate.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
+    lib.lbm_step_multirate_static.restype = ctypes.c_int
+    lib.lbm_step_multirate_static.argtypes = [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p]
     lib.lbm_read_fields.restype = ctypes.c_int
     lib.lbm_read_fields.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_uint32, ctypes.c_int32,
                                     ctypes.c_int32, ctypes.c_void_p]
@@ -219,16 +221,18 @@ class Simulation:
         flags |= {None: 0, True: 4, False: 8}[march]
         _check(self.lib, self.ctx, self.lib.lbm_configure(self.ctx, int(tile_rows), flags))
 
-    def step(self, n, diag=False):
+    def step(self, n, diag=False, static=False):
         """Advance every domain by n base steps (synchronises).  With
         ``diag`` returns a list of per-domain diagnostic dicts.  Raises
         LBMError with status LBM_EUNSTABLE once non-finite values are
-        found, with or without ``diag``."""
+        found, with or without ``diag``.  ``static`` calls the entry point
+        that allocates nothing (lbm_step_multirate_static)."""
+        fn = self.lib.lbm_step_multirate_static if static else self.lib.lbm_step_multirate
         if not diag:
-            _check(self.lib, self.ctx, self.lib.lbm_step_multirate(self.ctx, int(n), None))
+            _check(self.lib, self.ctx, fn(self.ctx, int(n), None))
             return None
         out = (Diag * self.n)()
-        s = self.lib.lbm_step_multirate(self.ctx, int(n), out)
+        s = fn(self.ctx, int(n), out)
         res = [dict(step=o.step, solid=o.solid, M_C=o.M_C, enthalpy=o.enthalpy, mass=o.mass, S_phi=o.S_phi,
                     J_U=o.J_U, tip=list(o.tip), nonfinite=o.nonfinite, t=o.t, R_M=o.R_M,
                     first_nonfinite_step=o.first_nonfinite_step) for o in out]
