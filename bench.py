@@ -38,6 +38,8 @@ import subprocess
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
@@ -89,17 +91,17 @@ def algorithmic_bytes(kind: str, d: dict, storage: str) -> int:
         # s in; U, T, phi^{q+1}, s out
         return 2 * (qs - 1) * s + (3 + 2 * U + 2 * T) * r
     if kind == "U_dtr":      # U transport carrying its step's transfer: phi^q, phi^{q+1}, U, j_U, [u],
-        # T in; U, j_U, T out (the transferred U stays on chip)
+        # T in; U, j_U, T out (the transferred U stays on chip; j_U is stored at the compute precision)
         Tl = T if d.get("T_mode", "transport") != "pulled" else 0
-        return (4 + dim * F + 2 * Tl) * r + 2 * dim * s
+        return (4 + dim * F + 2 * Tl) * r + 2 * dim * r
     if kind == "T_tr":       # T transport carrying its step's transfer: phi^q, phi^{q+1}, U, T, j_T, [u] in;
         # U*, T, j_T out (the transferred T stays on chip)
         return (4 + 2 * U + dim * F) * r + 2 * dim * s
     if kind == "transfer":   # phi^q, phi^{q+1}; U in, U out (or pending), T in, T out (not a pulled T)
         Tl = T if d.get("T_mode", "transport") != "pulled" else 0
         return (2 + 2 * U + 2 * Tl) * r
-    if kind == "U":          # U, j_U, phi*, [u]; U, j_U out; [pending]
-        return (3 + dim * F + 2 * acc) * r + 2 * dim * s
+    if kind == "U":          # U, j_U, phi*, [u]; U, j_U out; [pending] (j_U at the compute precision)
+        return (3 + dim * F + 2 * acc) * r + 2 * dim * r
     if kind == "T":          # as U; phi* only with phi-dependent properties
         tvar = d["kappa_S"] != d["kappa_L"] or d["rhoCp_S"] != d["rhoCp_L"]
         return (2 + int(tvar) + dim * F + 2 * acc) * r + 2 * dim * s
@@ -256,6 +258,67 @@ def step_roofline_of(m: dict) -> dict:
             "frac": round(gbs / HBM_PEAK_GBS, 4), "alg_bytes_per_step": m["step_bytes"]}
 
 
+def directional_run(args) -> int:
+    """The long runs of Section 4.4 (2D directional saline solidification,
+    1000 x 1000, Table 1 set, N_U = Le): every Lewis number of ``--le``
+    (comma-separated) is one domain of a single batched context.  Steps to
+    ``--t-end-ms`` (dt_base = 2e-9 s, so 20 ms = 1e7 base steps) and prints
+    one JSON line per domain every ``--every-ms`` with the time, S_phi, J_U,
+    R_M and the largest phi (read back), then a summary line per domain.
+    A domain whose state turns non-finite is reported with the step at which
+    the device screen found it, and the run stops there."""
+    import lbm_inputs as L
+    from paper_2609_25670_amd import lbm, simulation_for
+
+    les = [int(v) for v in str(args.le).split(",")]
+    doms = []
+    for le in les:
+        d = L.directional_2d(Le=le, coupling=args.coupling)["domains"][0]
+        d["q_scalar"] = args.q_scalar
+        doms.append(d)
+    storage = args.storage or "f32"
+    steps_per_ms = int(round(1e-3 / 2e-9))
+    every = max(1, int(round(args.every_ms * steps_per_ms)))
+    total = int(round(args.t_end_ms * steps_per_ms))
+    sim = simulation_for(dict(domains=doms), storage=storage)
+    head = dict(run="directional_2d", Le=les, coupling=args.coupling, q_scalar=args.q_scalar,
+                storage=storage, t_end_ms=args.t_end_ms, every_steps=every)
+    print(json.dumps(head), flush=True)
+    done, t0 = 0, time.perf_counter()
+    first_bad = [-1] * len(les)
+    peak = [dict(S_phi=0.0, J_U=0.0, phi=-1.0) for _ in les]
+    last = [None] * len(les)
+    stop = False
+    while done < total and not stop:
+        n = min(every, total - done)
+        try:
+            dd = sim.step(n, diag=True)
+        except lbm.LBMError as e:
+            if e.status != lbm.LBM_EUNSTABLE:
+                raise
+            dd = e.diag
+            stop = True
+        done += n
+        for i, le in enumerate(les):
+            x = dd[i]
+            phimax = float(np.max(sim.read(i, ("phi",))["phi"]))
+            first_bad[i] = x["first_nonfinite_step"]
+            pk = peak[i]
+            pk["S_phi"], pk["J_U"] = max(pk["S_phi"], x["S_phi"]), max(pk["J_U"], x["J_U"])
+            pk["phi"] = max(pk["phi"], phimax) if np.isfinite(phimax) else phimax
+            last[i] = dict(Le=le, step=x["step"], t_ms=x["step"] / steps_per_ms, S_phi=x["S_phi"], J_U=x["J_U"],
+                           R_M=x["R_M"], phi_max=phimax, nonfinite=x["nonfinite"],
+                           wall_s=round(time.perf_counter() - t0, 1))
+            print(json.dumps(last[i]), flush=True)
+    sim.close()
+    for i, le in enumerate(les):
+        fb = first_bad[i]
+        print(json.dumps(dict(head, Le=le, summary=True, steps=done, final=last[i], max_S_phi=peak[i]["S_phi"],
+                              max_J_U=peak[i]["J_U"], max_phi=peak[i]["phi"], first_nonfinite_step=fb,
+                              first_nonfinite_ms=(fb / steps_per_ms if fb >= 0 else None))), flush=True)
+    return 0
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -266,7 +329,7 @@ def main() -> int:
                     help="skip the measurement of the batched ensemble beside the default workload")
     ap.add_argument("--storage", default=None, help="override the workload's population storage")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-steps", type=int, default=8)
+    ap.add_argument("--cpu-steps", type=int, default=32)
     ap.add_argument("--cpu-procs", type=int, default=16, help="at most this many oracle processes at once")
     ap.add_argument("--cpu-child", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--copy-probe", type=int, default=0, metavar="BYTES",
@@ -274,7 +337,16 @@ def main() -> int:
     ap.add_argument("--profile-steps", type=int, default=0, metavar="N",
                     help="only run N warm-up and N measured base steps (for profiler runs); no JSON")
     ap.add_argument("--tile-rows", type=int, default=0, help="fix the tile height (0 = autotune)")
+    ap.add_argument("--run", choices=["directional_2d"], default=None,
+                    help="instead of the benchmark: a long run of the Section 4.4 case (see directional_run)")
+    ap.add_argument("--le", default="1", help="Lewis numbers of --run, comma-separated (N_U = Le)")
+    ap.add_argument("--coupling", choices=["instant", "accum"], default="instant")
+    ap.add_argument("--q-scalar", type=int, default=5, help="scalar lattice of --run: 5 (D2Q5) or 9 (D2Q9)")
+    ap.add_argument("--t-end-ms", type=float, default=20.0)
+    ap.add_argument("--every-ms", type=float, default=0.5)
     args = ap.parse_args()
+    if args.run:
+        return directional_run(args)
 
     if args.cpu_child:
         cpu_child(args.workload, args.cpu_steps)

@@ -80,17 +80,46 @@ __device__ __forceinline__ uint32_t mix32(uint32_t x) {
   x ^= x >> 16;
   return x;
 }
+// gfx950's v_cvt_sr_bf16_f32 adds the top 16 bits of r below the kept
+// mantissa of a finite value and truncates (infinities and NaN pass
+// through): the integer form of this rounding in one instruction, bit for
+// bit.
+typedef __attribute__((ext_vector_type(2))) __bf16 bf16x2_t;
+__device__ __forceinline__ uint16_t bf16_sr_hw(float v, uint32_t r) {
+  const bf16x2_t b = __builtin_amdgcn_cvt_sr_bf16_f32((bf16x2_t){0, 0}, v, r, false);
+  return (uint16_t)(__builtin_bit_cast(uint32_t, b) & 0xffffu);
+}
 __device__ __forceinline__ uint16_t bf16_sr(float v, long long i) {
-  uint32_t u = __float_as_uint(v);
-  if ((u & 0x7f800000u) != 0x7f800000u)   // finite: add 16 random bits below the kept mantissa, truncate
-    u += mix32(u + 0x9e3779b9u * (uint32_t)i) & 0xffffu;
-  else
-    u = __float_as_uint(__bfloat162float(__float2bfloat16(v)));
-  return (uint16_t)(u >> 16);
+  const uint32_t u = __float_as_uint(v);
+  return bf16_sr_hw(v, mix32(u + 0x9e3779b9u * (uint32_t)i) << 16);
 }
 __device__ __forceinline__ void st(__hip_bfloat16* p, long long i, float v) { ((uint16_t*)p)[i] = bf16_sr(v, i); }
 __device__ __forceinline__ void st(GLOBAL __hip_bfloat16* p, long long i, float v) {
   ((GLOBAL uint16_t*)p)[i] = bf16_sr(v, i);
+}
+
+// Stochastic BF16 rounding of the 3D kernels: one stream of random words
+// per site and launch.  The stream is seeded by hashing the site's offset,
+// the absolute base step and a per-kernel constant, and advanced by one
+// xorshift32 step (Marsaglia 2003) per store; gfx950's v_cvt_sr_bf16_f32
+// adds the word's top 16 bits below the kept mantissa and truncates (the
+// rounding of bf16_sr, in one instruction).  A store is then a pure
+// function of the site, the step and the value, so runs stay bitwise
+// reproducible across launch shapes and graph replays, and a value held
+// constant over many steps is still rounded up and down in proportion.
+// One hash per site instead of one per store: the D3Q19 flow stores 18
+// values per site.
+struct SRStream {
+  uint32_t s;
+  __device__ __forceinline__ uint32_t next() {
+    s ^= s << 13;
+    s ^= s >> 17;
+    s ^= s << 5;
+    return s;
+  }
+};
+__device__ __forceinline__ SRStream sr_stream(unsigned o, long long step, uint32_t salt) {
+  return SRStream{mix32(o ^ ((uint32_t)step * 0x9e3779b9u) ^ salt) | 1u};
 }
 
 // Element i of a plane addressed through a 32-bit byte offset.  The plane
@@ -133,6 +162,16 @@ __device__ __forceinline__ void sto(GLOBAL __half* p, unsigned i, float v) {
 }
 __device__ __forceinline__ void sto(GLOBAL __hip_bfloat16* p, unsigned i, float v) {
   *at((GLOBAL uint16_t*)p, i) = bf16_sr(v, i);
+}
+
+// Stores that draw their rounding from a site's stream (3D kernels): BF16
+// rounds stochastically with the next word, every other format as sto().
+template <class T, class V>
+__device__ __forceinline__ void sto_sr(GLOBAL T* p, unsigned i, V v, SRStream&) {
+  sto(p, i, v);
+}
+__device__ __forceinline__ void sto_sr(GLOBAL __hip_bfloat16* p, unsigned i, float v, SRStream& rs) {
+  *at((GLOBAL uint16_t*)p, i) = bf16_sr_hw(v, rs.next());
 }
 
 // Raw storage bits of a population plane (16-bit formats as their bit
@@ -2837,8 +2876,8 @@ __global__ void k_init(const Dom* __restrict__ doms, int dom, const double* __re
     const double dtU = D.N_U * D.dt_base;
     for (int b = 0; b < 4; ++b) (gp<R>(D.U[b]))[o] = R(0);    // U - U0
     for (int b = 0; b < 2; ++b) {
-      st(gp<S>(D.jU[b]), o, R(D.U0 * ux * dtU));
-      st(gp<S>(D.jU[b]), o + pl, R(0));
+      (gp<R>(D.jU[b]))[o] = R(D.U0 * ux * dtU);   // the U first moment is stored in R
+      (gp<R>(D.jU[b]))[o + pl] = R(0);
     }
     (gp<R>(D.PU))[o] = R(0);
   }
@@ -2885,7 +2924,7 @@ __device__ double read_plane(const Dom& D, long long k, int code, long long o) {
     case 3: return double((gp<const R>(D.rho[par(n_F(D, k))]))[o]);
     case 4: return double((gp<const R>(D.vel[par(n_F(D, k))]))[o]);
     case 5: return double((gp<const R>(D.vel[par(n_F(D, k))]))[o + pl]);
-    case 20: case 21: return double(ld(gp<const S>(D.jU[par(n_jU(D, k))]), o + (code - 20) * pl));
+    case 20: case 21: return double((gp<const R>(D.jU[par(n_jU(D, k))]))[o + (code - 20) * pl]);
     case 30: case 31: return double(ld(gp<const S>(D.jT[par(n_jT(D, k))]), o + (code - 30) * pl));
     case 50: return double((gp<const R>(D.PU))[o]);
     case 51: return double((gp<const R>(D.PT))[o]);
@@ -2965,7 +3004,7 @@ __global__ void k_write(const Dom* __restrict__ doms, int dom, long long k, cons
       case 3: (gp<R>(D.rho[par(n_F(D, k))]))[o] = R(v); break;
       case 4: (gp<R>(D.vel[par(n_F(D, k))]))[o] = R(v); break;
       case 5: (gp<R>(D.vel[par(n_F(D, k))]))[o + pl] = R(v); break;
-      case 20: case 21: st(gp<S>(D.jU[par(n_jU(D, k))]), o + (code - 20) * pl, R(v)); break;
+      case 20: case 21: (gp<R>(D.jU[par(n_jU(D, k))]))[o + (code - 20) * pl] = R(v); break;
       case 30: case 31: st(gp<S>(D.jT[par(n_jT(D, k))]), o + (code - 30) * pl, R(v)); break;
       case 50: (gp<R>(D.PU))[o] = R(v); break;
       case 51: (gp<R>(D.PT))[o] = R(v); break;
@@ -3450,6 +3489,7 @@ __global__ __launch_bounds__(256) void k3z_phase(const Dom* __restrict__ doms, u
   if (!zcol(G, blockIdx.x, zrun, c) || k % D.N_phi) return;
   const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
   const long long pl = D.plane;
+  const long long kabs = D.koff + (long long)k;   // absolute base step (rounding streams)
   const unsigned np = n_phi(D, k - 1);
   const int ib = par(np), ob = ib ^ 1;
   GLOBAL const R* phi = gp<const R>(D.phi[qb(np)]);
@@ -3571,8 +3611,9 @@ __global__ __launch_bounds__(256) void k3z_phase(const Dom* __restrict__ doms, u
       }
       const unsigned o = zoff(G, gx, gy, z);
       sto(phi_out, o, py + sum);
+      SRStream rs = sr_stream(o, kabs, 0x243f6a88u);
 #pragma unroll
-      for (int q = 1; q < 7; ++q) sto(plane(s_out, (q - 1) * pl), o, dn[q] - R(0.125) * sum);
+      for (int q = 1; q < 7; ++q) sto_sr(plane(s_out, (q - 1) * pl), o, dn[q] - R(0.125) * sum, rs);
     }
     Acur = Anext;
 #pragma unroll
@@ -3628,6 +3669,7 @@ __global__ __launch_bounds__(256) void k3z_scalar(const Dom* __restrict__ doms, 
   if (!zcol(G, blockIdx.x, zrun, c) || k % N) return;
   const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
   const long long pl = D.plane;
+  const long long kabs = D.koff + (long long)k;   // absolute base step (rounding streams)
   GLOBAL const R* cin;
   GLOBAL R* cout;
   GLOBAL const SR* jin;
@@ -3806,8 +3848,9 @@ __global__ __launch_bounds__(256) void k3z_scalar(const Dom* __restrict__ doms, 
         amax = fmax(amax, fabs(p));
       }
       sto(cout, o, chin);
+      SRStream rs = sr_stream(o, kabs, FIELD == 0 ? 0x85a308d3u : 0x13198a2eu);
 #pragma unroll
-      for (int a = 0; a < 3; ++a) sto(plane(jout, a * pl), o, j[a]);
+      for (int a = 0; a < 3; ++a) sto_sr(plane(jout, a * pl), o, j[a], rs);
     }
     __syncthreads();
   }
@@ -4097,6 +4140,85 @@ __device__ __forceinline__ void flow_collide3(R rho, R* d, R dt, R c, const R* F
   }
 }
 
+// The unforced D3Q19 collision, by pairs of opposite directions (q, q + 1
+// for odd q).  With F_b = 0 the non-equilibrium part x = f - f^eq carries no
+// mass and no momentum, so the conserved projector of mrt19_op drops out;
+// the odd part of x (momentum, heat flux and ghost vectors, every one but
+// the conserved momentum relaxing at s_q) relaxes at s_q alone; and the
+// even part needs only the energy, energy-squared and five stress moments,
+// sums over x_0 and the nine pair sums x_q + x_qbar.  Per pair the
+// equilibrium deviations are B + A and B - A with A = 3 w rho (e.U) and
+// B = w rho (4.5 (e.U)^2 - 1.5 U^2), so
+//   p_q    = (1 - s_q) d_q    + s_q (B + A) + E_pair,
+//   p_qbar = (1 - s_q) d_qbar + s_q (B - A) + E_pair,
+// with E_pair the even correction of the pair.  The same relaxation as
+// flow_collide3 (equal up to rounding); a quarter of its arithmetic.
+template <class R>
+__device__ __forceinline__ void flow_collide3_pairs(R rho, R* d, R dt, R c, R sq, R se, R seps, R snu, R* p) {
+  R es[9], od[9];
+  R sum = R(0);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    es[k] = d[2 * k + 1] + d[2 * k + 2];
+    od[k] = d[2 * k + 1] - d[2 * k + 2];
+    sum += es[k];
+  }
+  d[0] = -sum;
+  R j[3] = {R(0), R(0), R(0)};
+#pragma unroll
+  for (int k = 0; k < 9; ++k)
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+      if (e19(2 * k + 1, a) != 0) j[a] += R(e19(2 * k + 1, a)) * od[k];
+  const R irho = rcp(rho);
+  R U[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) U[a] = (c * j[a]) * irho * dt;   // u dt (Eq. 27, F_b = 0)
+  const R U2 = U[0] * U[0] + U[1] * U[1] + U[2] * U[2];
+  R A[9], B[9];
+  R x0 = d[0] + R(0.5) * rho * U2;   // B_0 = -1.5 w_0 rho U^2
+  R ce = R(-30) * x0, cp = R(12) * x0, cn[5] = {R(0), R(0), R(0), R(0), R(0)};
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    const int q = 2 * k + 1;
+    const int ex = e19(q, 0), ey = e19(q, 1), ez = e19(q, 2), e2 = ex * ex + ey * ey + ez * ez;
+    const int kn[5] = {3 * ex * ex - e2, ey * ey - ez * ez, ex * ey, ey * ez, ex * ez};
+    const R wr = rho * R(w19(q));
+    const R eU = edot3(ex, ey, ez, U[0], U[1], U[2]);
+    A[k] = R(3) * wr * eU;
+    B[k] = wr * (R(4.5) * eU * eU - R(1.5) * U2);
+    const R S = es[k] - R(2) * B[k];     // x_q + x_qbar
+    ce += R(19 * e2 - 30) * S;
+    cp += R((21 * e2 * e2 - 53 * e2 + 24) / 2) * S;
+#pragma unroll
+    for (int i = 0; i < 5; ++i)
+      if (kn[i] != 0) cn[i] += R(kn[i]) * S;
+  }
+  ce *= (sq - se) * R(1.0 / 2394);
+  cp *= (sq - seps) * R(1.0 / 252);
+  const R an = sq - snu;
+  cn[0] *= an * R(1.0 / 36);
+  cn[1] *= an * R(1.0 / 12);
+  cn[2] *= an * R(0.25);
+  cn[3] *= an * R(0.25);
+  cn[4] *= an * R(0.25);
+  const R om = R(1) - sq;
+  p[0] = om * d[0] + sq * (R(-0.5) * rho * U2) + (R(-30) * ce + R(12) * cp);
+#pragma unroll
+  for (int k = 0; k < 9; ++k) {
+    const int q = 2 * k + 1;
+    const int ex = e19(q, 0), ey = e19(q, 1), ez = e19(q, 2), e2 = ex * ex + ey * ey + ez * ez;
+    const int kn[5] = {3 * ex * ex - e2, ey * ey - ez * ez, ex * ey, ey * ez, ex * ez};
+    R E = R(19 * e2 - 30) * ce + R((21 * e2 * e2 - 53 * e2 + 24) / 2) * cp;
+#pragma unroll
+    for (int i = 0; i < 5; ++i)
+      if (kn[i] != 0) E += R(kn[i]) * cn[i];
+    const R G = sq * B[k] + E, H = sq * A[k];
+    p[q] = om * d[q] + (G + H);
+    p[q + 1] = om * d[q + 1] + (G - H);
+  }
+}
+
 // D3Q19 direction groups by z component: the components a plane streams to
 // the plane above (ez = +1), within itself (ez = 0, q >= 1) and below
 __host__ __device__ constexpr int zgroup(int q) { return e19(q, 2) > 0 ? 0 : e19(q, 2) == 0 ? 1 : 2; }
@@ -4149,6 +4271,7 @@ __global__ __launch_bounds__(256) void k3z_flow(const Dom* __restrict__ doms, un
   if (!zcol(G, blockIdx.x, zrun, c) || k % D.N_F) return;
   const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
   const long long pl = D.plane;
+  const long long kabs = D.koff + (long long)k;   // absolute base step (rounding streams)
   const int ib = par(n_F(D, k - 1)), ob = par(n_F(D, k));
   GLOBAL const R* rin = gp<const R>(D.rho[ib]);
   GLOBAL const SR* sp = gp<const SR>(D.sF[ib]);
@@ -4180,7 +4303,8 @@ __global__ __launch_bounds__(256) void k3z_flow(const Dom* __restrict__ doms, un
 #pragma unroll
       for (int q = 1; q < 19; ++q) d[q] = cvt_raw(in.s[i][q - 1], (S*)nullptr);
       const R rho = in.rho[i];
-      flow_collide3(rho, d, dt, cdt, F, forced, sq, se, seps, snu, p);
+      if (forced) flow_collide3(rho, d, dt, cdt, F, true, sq, se, seps, snu, p);
+      else flow_collide3_pairs(rho, d, dt, cdt, sq, se, seps, snu, p);
       const R fl = (R(1) - in.phi[i]) * R(0.5);
 #pragma unroll
       for (int q = 1; q < 19; ++q) {
@@ -4251,8 +4375,9 @@ __global__ __launch_bounds__(256) void k3z_flow(const Dom* __restrict__ doms, un
       sto(rho_out, o, rho);
 #pragma unroll
       for (int a = 0; a < 3; ++a) sto(plane(vel, a * pl), o, (cdt * j[a] + dt * F[a] * R(0.5)) * irho);
+      SRStream rs = sr_stream(o, kabs, 0x03707344u);
 #pragma unroll
-      for (int q = 1; q < 19; ++q) sto(plane(s_out, (q - 1) * pl), o, dn[q] - R(w19(q)) * drho);
+      for (int q = 1; q < 19; ++q) sto_sr(plane(s_out, (q - 1) * pl), o, dn[q] - R(w19(q)) * drho, rs);
     }
 #pragma unroll
     for (int q = 0; q < 19; ++q) pcur[q] = pnext[q];
@@ -4279,7 +4404,7 @@ __global__ void k3_init(const Dom* __restrict__ doms, const double* __restrict__
   if (D.has_U) {
     for (int b = 0; b < 4; ++b) (gp<R>(D.U[b]))[s.o] = R(0);   // U - U0
     for (int b = 0; b < 2; ++b)
-      for (int a = 0; a < 3; ++a) st(gp<S>(D.jU[b]), s.o + a * pl, R(0));
+      for (int a = 0; a < 3; ++a) (gp<R>(D.jU[b]))[s.o + a * pl] = R(0);   // stored in R
     (gp<R>(D.PU))[s.o] = R(0);
   }
   if (D.has_T) {
@@ -4317,7 +4442,7 @@ __device__ double read_plane3(const Dom& D, long long k, int code, unsigned o) {
   if (code == 9) return double((gp<const R>(D.T[qb(n_T(D, k))]))[o]);
   if (code == 3) return double((gp<const R>(D.rho[par(n_F(D, k))]))[o]);
   if (code >= 4 && code <= 6) return double((gp<const R>(D.vel[par(n_F(D, k))]))[o + (code - 4) * pl]);
-  if (code >= 20 && code <= 22) return double(ld(gp<const S>(D.jU[par(n_jU(D, k))]), o + (code - 20) * pl));
+  if (code >= 20 && code <= 22) return double((gp<const R>(D.jU[par(n_jU(D, k))]))[o + (code - 20) * pl]);
   if (code >= 30 && code <= 32) return double(ld(gp<const S>(D.jT[par(n_jT(D, k))]), o + (code - 30) * pl));
   if (code == 90) return double((gp<const R>(D.PU))[o]);
   if (code == 91) return double((gp<const R>(D.PT))[o]);
@@ -4383,7 +4508,7 @@ __global__ void k3_write(const Dom* __restrict__ doms, long long k, const int* _
     else if (code == 9) (gp<R>(D.T[qb(n_T(D, k))]))[o] = R(v);
     else if (code == 3) (gp<R>(D.rho[par(n_F(D, k))]))[o] = R(v);
     else if (code >= 4 && code <= 6) (gp<R>(D.vel[par(n_F(D, k))]))[o + (code - 4) * pl] = R(v);
-    else if (code >= 20 && code <= 22) st(gp<S>(D.jU[par(n_jU(D, k))]), o + (code - 20) * pl, R(v));
+    else if (code >= 20 && code <= 22) (gp<R>(D.jU[par(n_jU(D, k))]))[o + (code - 20) * pl] = R(v);
     else if (code >= 30 && code <= 32) st(gp<S>(D.jT[par(n_jT(D, k))]), o + (code - 30) * pl, R(v));
     else if (code == 90) (gp<R>(D.PU))[o] = R(v);
     else if (code == 91) (gp<R>(D.PT))[o] = R(v);
@@ -4529,7 +4654,8 @@ struct Launch3 {
     k3z_transfer<R><<<zblocks(h), 256, 0, st>>>(d, k, zrun(h), p);
   }
   static void scalar(int field, const Dom& h, hipStream_t st, const Dom* d, unsigned k, Partial* p) {
-    if (field == 0) k3z_scalar<R, S, 0><<<zblocks(h), 256, 0, st>>>(d, k, zrun(h), p);
+    // (the U transport stores its first moment in R: its storage type is R)
+    if (field == 0) k3z_scalar<R, R, 0><<<zblocks(h), 256, 0, st>>>(d, k, zrun(h), p);
     else k3z_scalar<R, S, 1><<<zblocks(h), 256, 0, st>>>(d, k, zrun(h), p);
   }
   static void flow(const Dom& h, hipStream_t st, const Dom* d, unsigned k) {
@@ -4597,18 +4723,18 @@ struct Launch {
   // transfer of step k fused into the U transport of step k (D2Q5)
   static void dtr_scalar(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, unsigned k, Partial* p) {
     const dim3 b(TX, BY);
-    if (TY == 4) k_dtr_scalar<R, S, 4><<<g, b, 0, st>>>(d, t, k, p);
-    else if (TY == 8) k_dtr_scalar<R, S, 8><<<g, b, 0, st>>>(d, t, k, p);
-    else if (TY == 16) k_dtr_scalar<R, S, 16><<<g, b, 0, st>>>(d, t, k, p);
-    else k_dtr_scalar<R, S, 32><<<g, b, 0, st>>>(d, t, k, p);
+    if (TY == 4) k_dtr_scalar<R, R, 4><<<g, b, 0, st>>>(d, t, k, p);
+    else if (TY == 8) k_dtr_scalar<R, R, 8><<<g, b, 0, st>>>(d, t, k, p);
+    else if (TY == 16) k_dtr_scalar<R, R, 16><<<g, b, 0, st>>>(d, t, k, p);
+    else k_dtr_scalar<R, R, 32><<<g, b, 0, st>>>(d, t, k, p);
   }
   // y-marching scalar transport over a list of column runs
   static void scalar_ym(int field, int Q, dim3 g, hipStream_t st, const Dom* d, const int4* runs, unsigned k,
                         double2* rmax) {
     const dim3 b(TX, BY);
     if (field == 0) {
-      if (Q == 9) k_scalar_ym<R, S, 0, 9><<<g, b, 0, st>>>(d, runs, k, rmax);
-      else k_scalar_ym<R, S, 0, 5><<<g, b, 0, st>>>(d, runs, k, rmax);
+      if (Q == 9) k_scalar_ym<R, R, 0, 9><<<g, b, 0, st>>>(d, runs, k, rmax);
+      else k_scalar_ym<R, R, 0, 5><<<g, b, 0, st>>>(d, runs, k, rmax);
     } else {
       if (Q == 9) k_scalar_ym<R, S, 1, 9><<<g, b, 0, st>>>(d, runs, k, rmax);
       else k_scalar_ym<R, S, 1, 5><<<g, b, 0, st>>>(d, runs, k, rmax);
@@ -4650,26 +4776,29 @@ struct Launch {
     else if (TY == 16) k_transfer<R, 16><<<g, b, 0, st>>>(d, t, k, p);
     else k_transfer<R, 32><<<g, b, 0, st>>>(d, t, k, p);
   }
-  template <int F>
+  // SF: storage type of the field's first moment (R for U, S for T)
+  template <int F, class SF>
   static void scalar_f(int TY, int Q, dim3 g, hipStream_t st, const Dom* d, const int4* t, unsigned k,
                        Partial* p) {
     const dim3 b(TX, BY);
     if (Q == 9) {
-      if (TY == 4) k_scalar<R, S, 4, F, 9><<<g, b, 0, st>>>(d, t, k, p);
-      else if (TY == 8) k_scalar<R, S, 8, F, 9><<<g, b, 0, st>>>(d, t, k, p);
-      else if (TY == 16) k_scalar<R, S, 16, F, 9><<<g, b, 0, st>>>(d, t, k, p);
-      else k_scalar<R, S, 32, F, 9><<<g, b, 0, st>>>(d, t, k, p);
+      if (TY == 4) k_scalar<R, SF, 4, F, 9><<<g, b, 0, st>>>(d, t, k, p);
+      else if (TY == 8) k_scalar<R, SF, 8, F, 9><<<g, b, 0, st>>>(d, t, k, p);
+      else if (TY == 16) k_scalar<R, SF, 16, F, 9><<<g, b, 0, st>>>(d, t, k, p);
+      else k_scalar<R, SF, 32, F, 9><<<g, b, 0, st>>>(d, t, k, p);
       return;
     }
-    if (TY == 4) k_scalar<R, S, 4, F, 5><<<g, b, 0, st>>>(d, t, k, p);
-    else if (TY == 8) k_scalar<R, S, 8, F, 5><<<g, b, 0, st>>>(d, t, k, p);
-    else if (TY == 16) k_scalar<R, S, 16, F, 5><<<g, b, 0, st>>>(d, t, k, p);
-    else k_scalar<R, S, 32, F, 5><<<g, b, 0, st>>>(d, t, k, p);
+    if (TY == 4) k_scalar<R, SF, 4, F, 5><<<g, b, 0, st>>>(d, t, k, p);
+    else if (TY == 8) k_scalar<R, SF, 8, F, 5><<<g, b, 0, st>>>(d, t, k, p);
+    else if (TY == 16) k_scalar<R, SF, 16, F, 5><<<g, b, 0, st>>>(d, t, k, p);
+    else k_scalar<R, SF, 32, F, 5><<<g, b, 0, st>>>(d, t, k, p);
   }
   static void scalar(int field, int TY, int Q, dim3 g, hipStream_t st, const Dom* d, const int4* t, unsigned k,
                      Partial* p) {
-    if (field == 0) scalar_f<0>(TY, Q, g, st, d, t, k, p);
-    else scalar_f<1>(TY, Q, g, st, d, t, k, p);
+    // the U transport stores its first moment in R (solute conservation is
+    // the accuracy target of the reduced-precision formats)
+    if (field == 0) scalar_f<0, R>(TY, Q, g, st, d, t, k, p);
+    else scalar_f<1, S>(TY, Q, g, st, d, t, k, p);
   }
   static void flow(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, unsigned k) {
     constexpr int SUB = sizeof(R) == 8 ? 8 : 16;

@@ -254,7 +254,7 @@ Layout layout_of(const lbm_params& p) {
   const int d = p.dim;
   L.rplanes = 4;                           // phi, four buffers
   L.splanes = 2 * (p.q_scalar - 1);        // phase s_i, two buffers
-  if (p.has_U) { L.rplanes += 5; L.splanes += 2 * d; }   // U (four buffers), pending U
+  if (p.has_U) L.rplanes += 5 + 2 * d;                    // U (four buffers), pending U, first moment
   if (p.has_T) { L.rplanes += 5; L.splanes += 2 * d; }   // T (four buffers), pending T
   if (p.has_flow) { L.rplanes += 2 + 2 * d; L.splanes += 2 * (d == 3 ? 18 : 8); }
   return L;
@@ -772,7 +772,7 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
     for (int b = 0; b < 2; ++b) D.sphi[b] = take(align256(ps) * (q.q_scalar - 1));
     if (q.has_U) {
       for (int b = 0; b < 4; ++b) D.U[b] = take(pr);
-      for (int b = 0; b < 2; ++b) D.jU[b] = take(align256(ps) * q.dim);
+      for (int b = 0; b < 2; ++b) D.jU[b] = take(align256(pr) * q.dim);   // first moment in R
       D.PU = take(pr);
     }
     if (q.has_T) {

@@ -24,7 +24,7 @@ import lbm_inputs as L
 pytestmark = pytest.mark.gpu
 
 
-def _run(wl, storage, steps, every):
+def _run(wl, storage, steps, every, names):
     from paper_2609_25670_amd import simulation_for
 
     sim = simulation_for(wl, storage=storage)
@@ -35,7 +35,6 @@ def _run(wl, storage, steps, every):
         # 2D: mean of the four arm lengths of the first seed; 3D: mean front height
         tip = dd["tip"][1] if wl["domains"][0]["dim"] == 3 else float(np.mean(dd["tip"][:4]))
         hist.append((dd["step"], tip, dd["M_C"]))
-    names = ("phi", "U") if wl["domains"][0]["has_U"] else ("phi", "T")
     f = sim.read(0, names)
     sim.close()
     return d0, hist, f
@@ -46,31 +45,57 @@ def _tip_velocity(hist):
     return (hist[-1][1] - hist[a][1]) / (hist[-1][0] - hist[a][0])
 
 
-# Field relative L2 bars.  FP16 and BF16 keep 11 and 8 mantissa bits of the
-# stored deviations and fluxes; where a field has no background value (U
-# starts at 0 in the directional case) its relative L2 is dominated by those
-# roundings, while the front position, which the flux errors only perturb
-# diffusively, stays within the tip-velocity bar.
-L2_BAR = {"f32": 1e-3, "f16": 1e-1, "bf16": 1e-1}
+# Field relative L2 bars (phi, U, T, u).  FP16 and BF16 keep 11 and 8
+# mantissa bits (unit roundoff 4.9e-4 and 3.9e-3) of the stored phase, T
+# and flow deviations; the U transport keeps its first moment at the compute
+# precision.  The largest errors measured over these runs are 4.9e-5 (FP32),
+# 4.0e-3 (FP16: the 3D velocity, U 2.6e-3) and 1.8e-3 (BF16: the 2D
+# velocity); before the U first moment moved to FP32 the 3D U field was off
+# by 1.5-3.5 % in both 16-bit formats.  The bars sit at about 2.5 times the
+# largest measured error.
+L2_BAR = {"f32": 1.5e-4, "f16": 1e-2, "bf16": 5e-3}
+
+
+def _four_field(nx, ny):
+    """The Section 4.3 forced-convection case (phi, U, T D2Q5 and D2Q9 flow,
+    N = 1:1:4:2, inlet u_in = 0.01) at the stable tau0 = 100 scale, reduced."""
+    wl = L.reduced(L.thermosolutal_flow_4096(), nx, ny)
+    return wl
+
+
+def _forced_3d():
+    """The 3D directional case reduced to 64 x 64 x 256 with a body force
+    F_x = 2e-6 along the front (Eq. 13, 27, 30): the D3Q19 populations carry
+    a growing shear flow (|u| of a few 1e-3 by the end) in every format."""
+    wl = L.reduced(L.directional_3d(), 64, 64, 256)
+    wl["domains"][0]["Fb"] = (2.0e-6, 0.0, 0.0)
+    return wl
+
 
 CASES = {
-    "solutal_256": (lambda: L.reduced(L.solutal_512(), 256, 256), 16000, 400),
-    "thermal_128": (L.thermal_128, 3000, 100),
-    "directional_64x64x256": (lambda: L.reduced(L.directional_3d(), 64, 64, 256), 4000, 200),
+    "solutal_256": (lambda: L.reduced(L.solutal_512(), 256, 256), 16000, 400, ("phi", "U")),
+    "thermal_128": (L.thermal_128, 3000, 100, ("phi", "T")),
+    "directional_64x64x256": (lambda: L.reduced(L.directional_3d(), 64, 64, 256), 4000, 200, ("phi", "U")),
+    "four_field_flow_256": (lambda: _four_field(256, 256), 3000, 100, ("phi", "U", "T", "vel")),
+    "directional_64x64x256_forced": (_forced_3d, 4000, 200, ("phi", "U", "vel")),
 }
 
 
 @pytest.mark.parametrize("case", sorted(CASES))
 def test_mixed_precision_storage(case):
-    make, steps, every = CASES[case]
+    make, steps, every, names = CASES[case]
     wl = make()
     print(f"case precision {case} f64 reference", flush=True)
-    r0, rh, rf = _run(wl, "f64", steps, every)
+    r0, rh, rf = _run(wl, "f64", steps, every, names)
     vref = _tip_velocity(rh)
     assert vref > 0
+    if "vel" in names:
+        umax = float(np.max(np.abs(rf["vel"])))
+        print(f"  {case} f64: max |u| = {umax:.3e}", flush=True)
+        assert umax > 1e-3   # the flow populations do move
     for st in ("f32", "f16", "bf16"):
         print(f"case precision {case} {st}", flush=True)
-        d0, h, f = _run(wl, st, steps, every)
+        d0, h, f = _run(wl, st, steps, every, names)
         v = _tip_velocity(h)
         tip_err = abs(v - vref) / vref
         l2 = {k: float(np.linalg.norm(f[k] - rf[k]) / np.linalg.norm(rf[k])) for k in f}
