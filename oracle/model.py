@@ -43,7 +43,14 @@ notes of the HIP library):
     T keeps its latent-heat transfer and the low wall of the last axis is
     held at T0 by the same anti-bounce-back; the other walls stay zero-flux;
   * planar fronts (Eq. 41 and its 3D random form): phi = tanh[(z_front +
-    xi - z)/(sqrt2 W0)] along the last axis with a per-column offset xi.
+    xi - z)/(sqrt2 W0)] along the last axis with a per-column offset xi;
+  * the variant grad_phi = "eq40" (2D) takes grad(phi) for n, a_s and N
+    from the non-equilibrium phase populations by Eq. (40), with the
+    equilibrium and tau_phi of the previous phase step at the site (v_n and
+    A lagged one step; the first step sees v_n = 0 and A = 1, the initial
+    equilibrium): grad phi = -(3 / tau_prev) (j - v_n,prev dt_phi), since
+    sum_i e_i f_i^eq = v_n dt_phi.  The transfer's normal and the transport
+    sources keep the isotropic stencil.
 """
 
 from __future__ import annotations
@@ -204,6 +211,9 @@ class Domain:
             self.f_F = self.flow_eq(self.rho, self.u, P.dt_field(d, "F"))
         self.P_U = np.zeros(self.shape)
         self.P_T = np.zeros(self.shape)
+        if d.get("grad_phi", "fd") == "eq40":
+            self.vn_prev = np.zeros((nd,) + self.shape)   # v_n of the previous phase step
+            self.A_prev = np.ones(self.shape)               # a_s^2 of the previous phase step
 
     # ------------------------------------------------------------- equilibria
     def scalar_eq(self, chi, dt, u=None):
@@ -249,11 +259,18 @@ class Domain:
         dt = P.dt_field(d, "phi")
         f = self.f_phi
         phi_q = f.sum(axis=0)
-        g = grad_iso(phi_q, self.bc)
+        eq40 = d.get("grad_phi", "fd") == "eq40"
+        if eq40:   # Eq. (40) with the previous step's equilibrium and tau_phi
+            j = np.tensordot(ls.e.astype(np.float64).T, f, axes=(1, 0))
+            g = -(self.inv_cs2 / P.tau_phi(d, self.A_prev))[None] * (j - self.vn_prev * dt)
+        else:
+            g = grad_iso(phi_q, self.bc)
         a_s, N, _ = anisotropy(d, g)
         A = a_s * a_s
         v_n = -d["W0"] ** 2 * N / d["tau0"]                  # Eq. (21)
         tau = P.tau_phi(d, A)                                  # Eq. (24)
+        if eq40:
+            self.A_prev, self.vn_prev = A, v_n
         Ustar = self.U if d["has_U"] else np.zeros(self.shape)
         theta = P.theta_of_T(d, self.T) if d["has_T"] else np.zeros(self.shape)
         om = 1.0 - phi_q * phi_q

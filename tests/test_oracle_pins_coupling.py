@@ -268,3 +268,38 @@ def test_oracle_flux_mode_grows_at_the_closed_form_rate(q, diagonal, tau0):
         assert abs(g) > 1.035
     else:
         assert abs(g) < 0.9
+
+
+# ------------------------------------------------- Eq. (40) for the phase field
+@pytest.mark.parametrize("q", [5, 9])
+def test_eq40_phase_gradient_recovers_the_wave_gradient(q):
+    """The grad_phi = "eq40" variant: grad phi = -(3/tau_prev)(j - v_n,prev
+    dt_phi) from the phase populations (Eq. 40 with the previous step's
+    equilibrium).  On a small oblique plane wave (wave vector 2pi(2, 1)/64,
+    so the normal is off both axes and the correction vector N, hence v_n,
+    does not vanish; amplitude 1e-3, so the wave stays a single mode) the
+    recovered gradient equals the mode's analytic gradient to 1.5 % after
+    40 steps, while leaving out the equilibrium flux v_n dt would be off by
+    about 7 %."""
+    n = 64
+    d = _dom(nx=n, ny=n, W0=2.0, tau0=40.0, eps_s=0.05, lam=0.0, q_scalar=q, grad_phi="eq40")
+    dom = oracle.Domain(d)
+    X, Y = np.meshgrid(np.arange(float(n)), np.arange(float(n)))
+    arg = 2 * math.pi * (2 * X + Y) / n
+    w = dom.ls.w.reshape((dom.ls.Q, 1, 1))
+    dom.f_phi = w * (1e-3 * np.sin(arg))[None]
+    for _ in range(40):
+        dom.step()
+    phi = dom.f_phi.sum(axis=0)
+    E = dom.ls.e.astype(float)
+    j = np.tensordot(E.T, dom.f_phi, axes=(1, 0))
+    tau = 3.0 * dom.A_prev * d["W0"] ** 2 / d["tau0"] + 0.5        # Eq. (24), dt_phi = 1
+    g40 = -(3.0 / tau)[None] * (j - dom.vn_prev)                   # Eq. (40)
+    s, c = np.sin(arg), np.cos(arg)
+    a_s, a_c = np.sum(phi * s) / np.sum(s * s), np.sum(phi * c) / np.sum(c * c)
+    kx, ky = 2 * math.pi * 2 / n, 2 * math.pi / n
+    ga = np.stack([kx * (a_s * c - a_c * s), ky * (a_s * c - a_c * s)])
+    scale = np.max(np.abs(ga))
+    assert np.max(np.abs(g40 - ga)) <= 0.015 * scale
+    assert np.max(np.abs(3.0 / tau[None] * dom.vn_prev)) >= 0.05 * scale   # the v_n term matters
+    assert np.max(np.abs(-(3.0 / tau)[None] * j - ga)) >= 0.04 * scale
