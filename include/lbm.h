@@ -90,6 +90,15 @@ enum { LBM_COUPLE_INSTANT = 0, LBM_COUPLE_ACCUM = 1 };
  * bottom of Section 4.4 (transported with latent heat, the low wall of the
  * last axis held at T0; that axis must have walls) */
 enum { LBM_T_TRANSPORT = 0, LBM_T_PULLED = 1, LBM_T_DIRICHLET_LOW = 2 };
+/* grad phi for the normal, a_s and N of the phase collision: the isotropic
+ * finite-difference stencil (ISO), or Eq. (40) on the phase populations with
+ * the equilibrium flux v_n dt and tau_phi of the site's previous phase step
+ * (EQ40, 2D; the first step sees the initial equilibrium, v_n = 0 and
+ * A = 1).  The transfer's normal (Eq. 37) and the transport sources keep the
+ * stencil in both.  EQ40 runs on the tiled phase kernel (no marching,
+ * deferred or fused transfer), and its lagged planes are not part of the
+ * checkpoint masks. */
+enum { LBM_GRAD_ISO = 0, LBM_GRAD_EQ40 = 1 };
 
 /* Parameters of one domain (host memory, FP64, lattice units).  Field
  * names follow the paper's notation. */
@@ -113,7 +122,7 @@ typedef struct {
   int32_t u0_liquid_only;               /* initial u = u_in (1 - phi)/2 x^  */
   int32_t coupling;                     /* LBM_COUPLE_*                      */
   int32_t T_mode;                       /* LBM_T_TRANSPORT, _PULLED, _DIRICHLET_LOW */
-  int32_t pad;
+  int32_t grad_phi;                     /* LBM_GRAD_ISO or LBM_GRAD_EQ40       */
   double T_grad, V_pull, z_front;       /* pulled temperature (3D):
                                            T0 + T_grad (z - z_front - V_pull t);
                                            z_front: mean height of the front
@@ -246,8 +255,10 @@ lbm_status lbm_read_fields(lbm_ctx* ctx, int32_t domain, uint32_t mask,
 lbm_status lbm_write_fields(lbm_ctx* ctx, int32_t domain, uint32_t mask,
                             int32_t src_is_device, const void* src);
 
-/* Tuning: rows per tile of the stencil kernels (4, 8, 16 or 32; 0 = autotune)
- * and flags:
+/* Tuning: rows per tile of the stencil kernels (4, 8, 16 or 32; 0 = autotune;
+ * in 3D, rows of the flow kernel's 64-wide tiles: 0 or 4, or 8 with FP32
+ * arithmetic (LBM_EINVAL in FP64); both heights give the same bits) and
+ * flags:
  *   LBM_CFG_GRAPH           replay whole multirate cycles from a HIP graph
  *   LBM_CFG_FUSE_TRANSFER   2D: run the transfer of Eq. (36)-(39) inside the
  *                           phase kernel, which then recomputes a halo of
@@ -277,9 +288,20 @@ lbm_status lbm_write_fields(lbm_ctx* ctx, int32_t domain, uint32_t mask,
  *                           update group), the transfer of a step at which
  *                           T is due runs inside that T transport.  Results
  *                           bitwise identical.
- * Default after lbm_create: autotune, LBM_CFG_GRAPH.  Unknown flags, or
- * LBM_CFG_MARCH with LBM_CFG_TILES: LBM_EINVAL. */
-enum { LBM_CFG_GRAPH = 1, LBM_CFG_FUSE_TRANSFER = 2, LBM_CFG_MARCH = 4, LBM_CFG_TILES = 8, LBM_CFG_NO_DEFER = 16 };
+ *   LBM_CFG_QUEUE           2D marching kernels: launch as many blocks as fit
+ *                           on the chip and let them take the column runs from
+ *                           eight per-XCD work queues (whole domains per
+ *                           queue, largest first; an idle block takes runs
+ *                           from the other queues); results bitwise
+ *                           identical to the static grids
+ *   LBM_CFG_GRID            2D marching kernels: one block per run, static grid
+ * With neither, the autotuner times the marching phase kernel in both forms
+ * and keeps the faster.
+ * Default after lbm_create: autotune, LBM_CFG_GRAPH.  Unknown flags,
+ * LBM_CFG_MARCH with LBM_CFG_TILES, or LBM_CFG_QUEUE with LBM_CFG_GRID:
+ * LBM_EINVAL. */
+enum { LBM_CFG_GRAPH = 1, LBM_CFG_FUSE_TRANSFER = 2, LBM_CFG_MARCH = 4, LBM_CFG_TILES = 8, LBM_CFG_NO_DEFER = 16,
+       LBM_CFG_QUEUE = 32, LBM_CFG_GRID = 64 };
 lbm_status lbm_configure(lbm_ctx* ctx, int32_t tile_rows, int32_t flags);
 
 /* Average device time, in milliseconds, of one launch of each kernel kind
@@ -308,8 +330,8 @@ int32_t lbm_marching(const lbm_ctx* ctx);
 
 /* Tile height of the 2D tiled kernels in use: the one fixed by
  * lbm_configure, else the autotuner's pick once it has run (at the first
- * lbm_step_multirate or lbm_kernel_times), else 0; 0 for a 3D context, -1
- * for ctx NULL. */
+ * lbm_step_multirate or lbm_kernel_times), else 0; for a 3D context the
+ * rows of the flow kernel's tiles (4 or 8); -1 for ctx NULL. */
 int32_t lbm_tile_rows(const lbm_ctx* ctx);
 
 /* Text of the last error of ctx (or of the last failed lbm_create when ctx

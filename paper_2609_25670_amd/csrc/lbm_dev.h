@@ -67,7 +67,7 @@ struct Dom {
   void* phi[4];    // R, 1 plane, four buffers (see qb())
   void* sphi[2];   // S, Q-1 planes: f_i - w_i phi, i >= 1 (4 in D2Q5, 8 in D2Q9, 6 in D3Q7)
   void* U[4];      // R, four buffers
-  void* jU[2];     // S, dim planes: first moment of the U populations
+  void* jU[2];     // R, dim planes: first moment of the U populations
   void* PU;        // R, pending U increments (accumulated coupling)
   void* T[4];      // R, four buffers
   void* jT[2];     // S, dim planes
@@ -75,6 +75,9 @@ struct Dom {
   void* rho[2];    // R
   void* sF[2];     // S, QF-1 planes: f_i - w_i rho, i >= 1 (8 in D2Q9, 18 in D3Q19)
   void* vel[2];    // R, dim planes each
+  // variant: grad phi of the phase collision from Eq. (40), lagged one step
+  int gradeq40;
+  void* gq[2];     // R, 3 planes: v_n dt (x, y) and A = a_s^2 of the last phase step
 };
 
 template <class R>
@@ -98,6 +101,27 @@ struct DiagOut {
   double tip[16];
   long long nonfinite;
   long long pad;
+};
+
+// Per-XCD work queues of the persistent 2D marching launches: the next
+// unclaimed entry of each of the eight lists, one counter per 256-byte line
+// (claims on different lists never contend for one line).  Rewound to zero
+// by a small kernel before every launch.
+constexpr int WQ_LINE = 64;
+struct WorkQ {
+  unsigned next[8][WQ_LINE];
+};
+// Runs claimed per atomic.  One run per claim measured fastest on the
+// batched ensemble (42.7k MLUPS; 33.7k with two runs, 27.1k with four).
+#ifndef LBM_QCHUNK
+#define LBM_QCHUNK 1
+#endif
+constexpr int QCHUNK = LBM_QCHUNK;
+// A run list split into eight per-XCD lists: items[qoff[x] .. qoff[x+1]).
+struct QList {
+  const int4* items;
+  const int* qoff;
+  int n;
 };
 
 // Buffer index holding a field's latest values after `n` writes.

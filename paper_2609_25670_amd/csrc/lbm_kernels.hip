@@ -24,6 +24,8 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
+#include <unordered_map>
 #include <type_traits>
 
 #include "lbm_dev.h"
@@ -410,12 +412,18 @@ __global__ __launch_bounds__(NTHR) void k_phase(const Dom* __restrict__ doms, co
   GLOBAL const R* __restrict__ Tp = D.has_T ? gp<const R>(D.T[qb(n_T(D, k - 1))]) : nullptr;
 
   const PhaseConst<R> c = phase_const<R>(D);
+  // variant: grad phi from Eq. (40) with the previous phase step's v_n dt
+  // and A at the site (written by that step into the other buffer)
+  const bool e40 = D.gradeq40 != 0;
+  GLOBAL const R* __restrict__ gq_in = e40 ? gp<const R>(D.gq[ib]) : nullptr;
+  GLOBAL R* __restrict__ gq_out = e40 ? gp<R>(D.gq[ob]) : nullptr;
 
   const int tx = threadIdx.x, ty = threadIdx.y, tid = ty * TX + tx;
   // sites of this thread: RPT owned sites, then at most one ring cell
   int cl[NS];                 // collision-box index (-1: inactive)
   int bi[NS];                 // the same cell in the phi box
-  R sv[NS][Q - 1], Uv[NS], Tv[NS];
+  unsigned so[NS];            // in-plane offset
+  R sv[NS][Q - 1], Uv[NS], Tv[NS], gqv[NS][3];
 #pragma unroll
   for (int r = 0; r < NS; ++r) {
     int lx, ly, gx, gy;
@@ -435,10 +443,15 @@ __global__ __launch_bounds__(NTHR) void k_phase(const Dom* __restrict__ doms, co
     cl[r] = ly * CW + lx;
     bi[r] = (ly + 1) * BW + lx + 1;
     const unsigned o = gy * px + gx;
+    so[r] = o;
 #pragma unroll
     for (int q = 0; q < Q - 1; ++q) sv[r][q] = ldo(plane(s_in, q * pl), o);
     Uv[r] = Up ? ldo(Up, o) + kc<R>(D, K_U0) : R(0);      // planes hold U - U0 and T - T0
     Tv[r] = Tp ? ldo(Tp, o) + kc<R>(D, K_T0) : c.theta_off;
+    if (e40) {
+#pragma unroll
+      for (int a = 0; a < 3; ++a) gqv[r][a] = ldo(plane(gq_in, a * pl), o);
+    }
   }
   load_box2<R, BW, BH>(sphi, phi_in, px, x0, y0, nx, ny, bcx, bcy, tx, ty);
   __syncthreads();
@@ -448,8 +461,6 @@ __global__ __launch_bounds__(NTHR) void k_phase(const Dom* __restrict__ doms, co
   for (int r = 0; r < NS; ++r) {
     if (cl[r] < 0) continue;
     const R* b = &sphi[bi[r]];
-    R gx_, gy_;
-    iso_grad(b, BW, gx_, gy_);
     R jx, jy;   // first moment of the deviations (the w_i phi part has none)
     if constexpr (Q == 5) {
       jx = sv[r][0] - sv[r][2];
@@ -458,8 +469,21 @@ __global__ __launch_bounds__(NTHR) void k_phase(const Dom* __restrict__ doms, co
       jx = sv[r][0] - sv[r][2] + sv[r][4] - sv[r][5] - sv[r][6] + sv[r][7];
       jy = sv[r][1] - sv[r][3] + sv[r][4] + sv[r][5] - sv[r][6] - sv[r][7];
     }
+    R gx_, gy_;
+    if (e40) {   // Eq. (40): grad phi = -(3 / tau_prev) (j - v_n,prev dt)
+      const R f = R(-3) / (R(3) * c.dt * gqv[r][2] * c.W2t + R(0.5));
+      gx_ = f * (jx - gqv[r][0]);
+      gy_ = f * (jy - gqv[r][1]);
+    } else {
+      iso_grad(b, BW, gx_, gy_);
+    }
     R dP, Kx, Ky, A, je[2];
     phase_collide(c, b[0], gx_, gy_, jx, jy, Uv[r], Tv[r], dP, Kx, Ky, A, je);
+    if (e40 && r < RPT) {
+      sto(gq_out, so[r], je[0]);
+      sto(plane(gq_out, pl), so[r], je[1]);
+      sto(plane(gq_out, 2 * pl), so[r], A);
+    }
     sP[cl[r]] = dP;
     sKx[cl[r]] = Kx;
     sKy[cl[r]] = Ky;
@@ -627,8 +651,7 @@ __device__ __forceinline__ void ym_load_phase(int nx, int ny, int px, int bcx, i
 }
 
 template <class R, class S, int Q>
-__global__ __launch_bounds__(NTHR) void k_phase_ym(const Dom* __restrict__ doms, const int4* __restrict__ runs,
-                                                    unsigned k) {
+__device__ __forceinline__ void k_phase_ym_run(const Dom* __restrict__ doms, const int4 t, unsigned k) {
   using Lq = Lat2<Q>;
   using SR = typename RawT<S>::type;
   constexpr int NV = Q == 9 ? 5 : 3;   // dP, Kx, Ky (and j_eq in D2Q9)
@@ -637,8 +660,6 @@ __global__ __launch_bounds__(NTHR) void k_phase_ym(const Dom* __restrict__ doms,
   __shared__ R wA[8][TX];
   __shared__ R wsv[8][Q - 1][TX];
 
-  const int4 t = runs[blockIdx.x];
-  if (t.x < 0) return;
   const Dom& D = doms[t.x];
   if (k % D.N_phi) return;
   const int nx = D.nx, ny = D.ny, px = D.px, bcx = D.bc[0], bcy = D.bc[1];
@@ -1001,14 +1022,12 @@ __device__ __forceinline__ void ym_load_own(int ny, int px, int x0, int w, int r
 // injection on the current rows.  The largest |dU| of the run goes to its
 // slot of the per-run maxima, where the diagnostics reduce it.
 template <class R>
-__global__ __launch_bounds__(NTHR) void k_transfer_ym(const Dom* __restrict__ doms, const int4* __restrict__ runs,
-                                                       unsigned k, double2* __restrict__ rmax) {
+__device__ __forceinline__ void k_transfer_ym_run(const Dom* __restrict__ doms, const int4 t, unsigned k,
+                                                  double2* __restrict__ rmax) {
   __shared__ R wphi[8][YBW];
   __shared__ R wJx[8][YCW], wJy[8][YCW];
   __shared__ R red[NTHR / 64];
 
-  const int4 t = runs[blockIdx.x];
-  if (t.x < 0) return;
   const Dom& D = doms[t.x];
   if (k % D.N_phi) return;
   const int nx = D.nx, ny = D.ny, px = D.px, bcx = D.bc[0], bcy = D.bc[1];
@@ -2132,8 +2151,8 @@ __device__ __forceinline__ void ym_load_sc(int nx, int ny, int px, int bcx, int 
 // rows.  With accumulated coupling the largest pending |dU| of the run goes
 // to its slot of the per-run maxima.
 template <class R, class S, int FIELD, int Q>
-__global__ __launch_bounds__(NTHR) void k_scalar_ym(const Dom* __restrict__ doms, const int4* __restrict__ runs,
-                                                     unsigned k, double2* __restrict__ rmax) {
+__device__ __forceinline__ void k_scalar_ym_run(const Dom* __restrict__ doms, const int4 t, unsigned k,
+                                                double2* __restrict__ rmax) {
   using Lq = Lat2<Q>;
   using SR = typename RawT<S>::type;
   constexpr int NV = Q == 9 ? 6 : 4;   // chi, dt Q, Kx, Ky (and j_eq in D2Q9)
@@ -2141,8 +2160,6 @@ __global__ __launch_bounds__(NTHR) void k_scalar_ym(const Dom* __restrict__ doms
   __shared__ R wc[8][NV][YCW];
   __shared__ R red[NTHR / 64];
 
-  const int4 t = runs[blockIdx.x];
-  if (t.x < 0) return;
   const Dom& D = doms[t.x];
   const int N = FIELD == 0 ? D.N_U : D.N_T;
   if (k % N) return;
@@ -2398,8 +2415,8 @@ __device__ __forceinline__ void ym_load_ts(int nx, int ny, int px, int bcx, int 
 // blocks write.  The U transport of the step runs after this kernel.
 // Bitwise identical to the two separate kernels.
 template <class R, class S, int Q>
-__global__ __launch_bounds__(NTHR) void k_tr_scalar_ym(const Dom* __restrict__ doms, const int4* __restrict__ runs,
-                                                        unsigned k, double2* __restrict__ rmax) {
+__device__ __forceinline__ void k_tr_scalar_ym_run(const Dom* __restrict__ doms, const int4 t, unsigned k,
+                                                   double2* __restrict__ rmax) {
   using Lq = Lat2<Q>;
   using SR = typename RawT<S>::type;
   constexpr int NV = Q == 9 ? 6 : 4;   // chi, dt Q, Kx, Ky (and j_eq in D2Q9)
@@ -2408,8 +2425,6 @@ __global__ __launch_bounds__(NTHR) void k_tr_scalar_ym(const Dom* __restrict__ d
   __shared__ R wc[8][NV][YCW];
   __shared__ R red[NTHR / 64];
 
-  const int4 t = runs[blockIdx.x];
-  if (t.x < 0) return;
   const Dom& D = doms[t.x];
   if (k % D.N_phi || k % D.N_T) return;
   const int nx = D.nx, ny = D.ny, px = D.px, bcx = D.bc[0], bcy = D.bc[1];
@@ -2867,6 +2882,12 @@ __global__ void k_init(const Dom* __restrict__ doms, int dom, const double* __re
   }
   const R ph = R(phi);
   for (int b = 0; b < 4; ++b) (gp<R>(D.phi[b]))[o] = ph;
+  if (D.gradeq40)   // the initial equilibrium: v_n = 0, A = 1
+    for (int b = 0; b < 2; ++b) {
+      (gp<R>(D.gq[b]))[o] = R(0);
+      (gp<R>(D.gq[b]))[o + pl] = R(0);
+      (gp<R>(D.gq[b]))[o + 2 * pl] = R(1);
+    }
   for (int q = 0; q < D.qs - 1; ++q) {
     st(gp<S>(D.sphi[0]), o + q * pl, R(0));
     st(gp<S>(D.sphi[1]), o + q * pl, R(0));
@@ -3358,17 +3379,18 @@ __device__ __forceinline__ unsigned zoff(const ZGeo& G, int x, int y, int z) {
 struct ZCol {
   int x0, y0, w, h, za, zb;
 };
+template <int TY = ZTY>
 __device__ __forceinline__ bool zcol(const ZGeo& G, unsigned b, int zrun, ZCol& c) {
-  const int ntx = (G.nx + ZTX - 1) / ZTX, nty = (G.ny + ZTY - 1) / ZTY;
+  const int ntx = (G.nx + ZTX - 1) / ZTX, nty = (G.ny + TY - 1) / TY;
   const int ncol = ntx * nty, nrun = (G.nz + zrun - 1) / zrun;
   const int per = (ncol * nrun + 7) / 8;
   const int i = (int)(b >> 3), L = (int)(b & 7u) * per + i;
   if (i >= per || L >= ncol * nrun) return false;
   const int col = L % ncol, run = L / ncol;
   c.x0 = (col % ntx) * ZTX;
-  c.y0 = (col / ntx) * ZTY;
+  c.y0 = (col / ntx) * TY;
   c.w = min(ZTX, G.nx - c.x0);
-  c.h = min(ZTY, G.ny - c.y0);
+  c.h = min(TY, G.ny - c.y0);
   c.za = run * zrun;
   c.zb = min(G.nz, c.za + zrun);
   return true;
@@ -3440,6 +3462,7 @@ struct ZRegMap {
   int cr[2];
   unsigned o[2];
 };
+// (the region row width ZRW is the same at every tile height)
 __device__ __forceinline__ void zreg_map(const ZGeo& G, const ZCol& c, int tid, ZRegMap& m) {
 #pragma unroll
   for (int i = 0; i < 2; ++i) {
@@ -4258,9 +4281,10 @@ __device__ __forceinline__ void zload_flow(const ZGeo& G, const ZRegMap& m, int 
 // are kept for two planes, in-plane ones for one, downward ones only for
 // the plane being streamed; the own site's nineteen post-collision values
 // stay in registers for the bounce-back.
-template <class R, class S>
-__global__ __launch_bounds__(256) void k3z_flow(const Dom* __restrict__ doms, unsigned k, int zrun) {
+template <class R, class S, int FTY>
+__global__ __launch_bounds__(64 * FTY) void k3z_flow(const Dom* __restrict__ doms, unsigned k, int zrun) {
   using SR = typename RawT<S>::type;
+  constexpr int ZNR = ZRW * (FTY + 2);   // collision region of a 64 x FTY tile
   __shared__ R wup[3][5][ZNR];     // ez = +1 components, planes z - 1 .. z + 1
   __shared__ R win[2][8][ZNR];     // ez = 0 components, planes z, z + 1
   __shared__ R wdn[5][ZNR];        // ez = -1 components of plane z + 1
@@ -4268,7 +4292,7 @@ __global__ __launch_bounds__(256) void k3z_flow(const Dom* __restrict__ doms, un
   const Dom& D = doms[0];
   const ZGeo G{D.nx, D.ny, D.nz, D.px, D.fbc[0], D.fbc[1], D.fbc[2]};
   ZCol c;
-  if (!zcol(G, blockIdx.x, zrun, c) || k % D.N_F) return;
+  if (!zcol<FTY>(G, blockIdx.x, zrun, c) || k % D.N_F) return;
   const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
   const long long pl = D.plane;
   const long long kabs = D.koff + (long long)k;   // absolute base step (rounding streams)
@@ -4635,15 +4659,15 @@ struct Launch3 {
     return (unsigned)((cols + 7) / 8 * 8 * h.nz);
   }
   // z-marching launches: runs of zrun planes, enough (column, run) pairs
-  // for about 2048 blocks
-  static int zrun(const Dom& h) {
-    const int ncol = ((h.nx + ZTX - 1) / ZTX) * ((h.ny + ZTY - 1) / ZTY);
-    const int nrun = std::max(1, std::min((2048 + ncol - 1) / ncol, (h.nz + 7) / 8));
+  // for about 2048 blocks of 256 threads (1024 of 512 threads)
+  static int zrun(const Dom& h, int ty = ZTY) {
+    const int ncol = ((h.nx + ZTX - 1) / ZTX) * ((h.ny + ty - 1) / ty);
+    const int nrun = std::max(1, std::min((2048 * ZTY / ty + ncol - 1) / ncol, (h.nz + 7) / 8));
     return (h.nz + nrun - 1) / nrun;
   }
-  static unsigned zblocks(const Dom& h) {
-    const long long ncol = (long long)((h.nx + ZTX - 1) / ZTX) * ((h.ny + ZTY - 1) / ZTY);
-    const int zr = zrun(h);
+  static unsigned zblocks(const Dom& h, int ty = ZTY) {
+    const long long ncol = (long long)((h.nx + ZTX - 1) / ZTX) * ((h.ny + ty - 1) / ty);
+    const int zr = zrun(h, ty);
     const long long n = ncol * ((h.nz + zr - 1) / zr);
     return (unsigned)((n + 7) / 8 * 8);
   }
@@ -4658,17 +4682,29 @@ struct Launch3 {
     if (field == 0) k3z_scalar<R, R, 0><<<zblocks(h), 256, 0, st>>>(d, k, zrun(h), p);
     else k3z_scalar<R, S, 1><<<zblocks(h), 256, 0, st>>>(d, k, zrun(h), p);
   }
-  static void flow(const Dom& h, hipStream_t st, const Dom* d, unsigned k) {
-    k3z_flow<R, S><<<zblocks(h), 256, 0, st>>>(d, k, zrun(h));
+  // the flow on 64 x 8 tiles (rows = 8, FP32 arithmetic: 512 threads and
+  // 111 KB of LDS, one block per CU) recomputes 1.375 wave collisions per
+  // site against 1.75 at 64 x 4, but its barriers then stall the whole CU:
+  // 1.375 against 1.347 ms per launch on 256 x 256 x 512, so 64 x 4 is the
+  // default.  In FP64 the LDS window (133 KB at 64 x 4) leaves no room for
+  // taller tiles.  Both heights give the same bits.
+  static void flow(const Dom& h, hipStream_t st, const Dom* d, unsigned k, int rows) {
+    if constexpr (sizeof(R) == 4) {
+      if (rows == 8) {
+        k3z_flow<R, S, 8><<<zblocks(h, 8), 512, 0, st>>>(d, k, zrun(h, 8));
+        return;
+      }
+    }
+    k3z_flow<R, S, 4><<<zblocks(h, 4), 256, 0, st>>>(d, k, zrun(h, 4));
   }
-  static void step(const Dom& h, hipStream_t st, const Dom* d, unsigned k, Partial* p) {
+  static void step(const Dom& h, hipStream_t st, const Dom* d, unsigned k, Partial* p, int rows) {
     if (k % h.N_phi == 0) {
       phase(h, st, d, k);
       transfer(h, st, d, k, p);
     }
     if (h.has_U && k % h.N_U == 0) scalar(0, h, st, d, k, p);
     if (h.has_T && k % h.N_T == 0) scalar(1, h, st, d, k, p);
-    if (h.has_F && k % h.N_F == 0) flow(h, st, d, k);
+    if (h.has_F && k % h.N_F == 0) flow(h, st, d, k, rows);
   }
   static void init(const Dom& h, hipStream_t st, const Dom* d, const double* xi) {
     k3_init<R, S><<<blocks(h), 256, 0, st>>>(d, xi);
@@ -4692,6 +4728,98 @@ template struct Launch3<double, double>;
 template struct Launch3<float, float>;
 template struct Launch3<float, __half>;
 template struct Launch3<float, __hip_bfloat16>;
+
+// =================================================================== 2D marching launches
+// Every 2D marching kernel body runs once per column run.  Two launch
+// forms share it: a static grid (block b takes run b of an XCD-ordered
+// list) and a persistent work queue.  The queue form launches as many
+// blocks as fit on the chip; the runs are split into eight lists, one per
+// XCD, that hold whole domains (assigned to the lists by longest-
+// processing-time packing on their site counts, largest domain first), so
+// that the halo rows a run re-reads were loaded into the same XCD's L2 by
+// its neighbours.  Block b starts on list b mod 8 (the XCD the dispatcher
+// places it on), claims QCHUNK runs at a time and, once that list is
+// empty, takes the runs left on the other lists in turn.  Every block
+// leaves after finding all eight lists empty.  The counters are rewound by
+// k_wq_rewind, launched before the kernel on the same stream.
+__global__ void k_wq_rewind(WorkQ* __restrict__ q) {
+  if (threadIdx.x < 8) q->next[threadIdx.x][0] = 0u;
+}
+
+template <class F>
+__device__ __forceinline__ void workq_loop(WorkQ* __restrict__ q, const int4* __restrict__ items,
+                                           const int* __restrict__ qoff, F&& body) {
+  __shared__ int s_item;
+  const bool lead = threadIdx.x == 0 && threadIdx.y == 0;
+  const int home = (int)(blockIdx.x & 7u);
+  for (int v = 0; v < 8; ++v) {
+    const int x = (home + v) & 7;
+    const int b = qoff[x], n = qoff[x + 1] - b;
+    for (;;) {
+      if (lead) s_item = (int)atomicAdd(&q->next[x][0], (unsigned)QCHUNK);
+      __syncthreads();
+      const int i0 = s_item;
+      __syncthreads();
+      if (i0 >= n) break;
+      const int i1 = min(i0 + QCHUNK, n);
+      for (int i = i0; i < i1; ++i) {
+        const int4 t = items[b + i];
+        if (t.x >= 0) body(t);
+        __syncthreads();
+      }
+    }
+  }
+}
+
+template <class R, class S, int Q>
+__global__ __launch_bounds__(NTHR) void k_phase_ym(const Dom* __restrict__ doms, const int4* __restrict__ runs,
+                                                    unsigned k) {
+  const int4 t = runs[blockIdx.x];
+  if (t.x >= 0) k_phase_ym_run<R, S, Q>(doms, t, k);
+}
+template <class R, class S, int Q>
+__global__ __launch_bounds__(NTHR) void k_phase_ym_q(const Dom* __restrict__ doms, const int4* __restrict__ items,
+                                                      const int* __restrict__ qoff, WorkQ* __restrict__ q,
+                                                      unsigned k) {
+  workq_loop(q, items, qoff, [&](const int4 t) { k_phase_ym_run<R, S, Q>(doms, t, k); });
+}
+template <class R>
+__global__ __launch_bounds__(NTHR) void k_transfer_ym(const Dom* __restrict__ doms, const int4* __restrict__ runs,
+                                                       unsigned k, double2* __restrict__ rmax) {
+  const int4 t = runs[blockIdx.x];
+  if (t.x >= 0) k_transfer_ym_run<R>(doms, t, k, rmax);
+}
+template <class R>
+__global__ __launch_bounds__(NTHR) void k_transfer_ym_q(const Dom* __restrict__ doms, const int4* __restrict__ items,
+                                                         const int* __restrict__ qoff, WorkQ* __restrict__ q,
+                                                         unsigned k, double2* __restrict__ rmax) {
+  workq_loop(q, items, qoff, [&](const int4 t) { k_transfer_ym_run<R>(doms, t, k, rmax); });
+}
+template <class R, class S, int FIELD, int Q>
+__global__ __launch_bounds__(NTHR) void k_scalar_ym(const Dom* __restrict__ doms, const int4* __restrict__ runs,
+                                                     unsigned k, double2* __restrict__ rmax) {
+  const int4 t = runs[blockIdx.x];
+  if (t.x >= 0) k_scalar_ym_run<R, S, FIELD, Q>(doms, t, k, rmax);
+}
+template <class R, class S, int FIELD, int Q>
+__global__ __launch_bounds__(NTHR) void k_scalar_ym_q(const Dom* __restrict__ doms, const int4* __restrict__ items,
+                                                       const int* __restrict__ qoff, WorkQ* __restrict__ q,
+                                                       unsigned k, double2* __restrict__ rmax) {
+  workq_loop(q, items, qoff, [&](const int4 t) { k_scalar_ym_run<R, S, FIELD, Q>(doms, t, k, rmax); });
+}
+template <class R, class S, int Q>
+__global__ __launch_bounds__(NTHR) void k_tr_scalar_ym(const Dom* __restrict__ doms, const int4* __restrict__ runs,
+                                                        unsigned k, double2* __restrict__ rmax) {
+  const int4 t = runs[blockIdx.x];
+  if (t.x >= 0) k_tr_scalar_ym_run<R, S, Q>(doms, t, k, rmax);
+}
+template <class R, class S, int Q>
+__global__ __launch_bounds__(NTHR) void k_tr_scalar_ym_q(const Dom* __restrict__ doms,
+                                                          const int4* __restrict__ items,
+                                                          const int* __restrict__ qoff, WorkQ* __restrict__ q,
+                                                          unsigned k, double2* __restrict__ rmax) {
+  workq_loop(q, items, qoff, [&](const int4 t) { k_tr_scalar_ym_run<R, S, Q>(doms, t, k, rmax); });
+}
 
 // =================================================================== launchers
 template <class R, class S>
@@ -4757,6 +4885,55 @@ struct Launch {
     const dim3 b(TX, BY);
     if (Q == 9) k_phase_ym<R, S, 9><<<g, b, 0, st>>>(d, runs, k);
     else k_phase_ym<R, S, 5><<<g, b, 0, st>>>(d, runs, k);
+  }
+  // the same kernels through the per-XCD work queues: as many blocks as
+  // fit on the chip (the occupancy of each kernel), at most one per run;
+  // the counters are rewound first
+  template <class K>
+  static unsigned fill(K kern, int nruns, WorkQ* q, hipStream_t st) {
+    static std::mutex mu;
+    static std::unordered_map<const void*, long long> full;
+    long long nb;
+    {
+      std::lock_guard<std::mutex> lock(mu);
+      auto it = full.find((const void*)kern);
+      if (it == full.end()) {
+        int dev = 0, cus = 0, n = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1)
+          cus = 256;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kern, NTHR, 0) != hipSuccess || n < 1) n = 1;
+        it = full.emplace((const void*)kern, (long long)n * cus).first;
+      }
+      nb = it->second;
+    }
+    k_wq_rewind<<<1, 64, 0, st>>>(q);
+    return (unsigned)std::max(1LL, std::min(nb, (long long)nruns));
+  }
+  static void phase_ymq(int Q, const QList& l, WorkQ* q, hipStream_t st, const Dom* d, unsigned k) {
+    const dim3 b(TX, BY);
+    if (Q == 9) k_phase_ym_q<R, S, 9><<<fill(k_phase_ym_q<R, S, 9>, l.n, q, st), b, 0, st>>>(d, l.items, l.qoff, q, k);
+    else k_phase_ym_q<R, S, 5><<<fill(k_phase_ym_q<R, S, 5>, l.n, q, st), b, 0, st>>>(d, l.items, l.qoff, q, k);
+  }
+  static void transfer_ymq(const QList& l, WorkQ* q, hipStream_t st, const Dom* d, unsigned k, double2* rmax) {
+    k_transfer_ym_q<R><<<fill(k_transfer_ym_q<R>, l.n, q, st), dim3(TX, BY), 0, st>>>(d, l.items, l.qoff, q, k, rmax);
+  }
+  static void scalar_ymq(int field, int Q, const QList& l, WorkQ* q, hipStream_t st, const Dom* d, unsigned k,
+                         double2* rmax) {
+    const dim3 b(TX, BY);
+    if (field == 0) {
+      if (Q == 9) k_scalar_ym_q<R, R, 0, 9><<<fill(k_scalar_ym_q<R, R, 0, 9>, l.n, q, st), b, 0, st>>>(d, l.items, l.qoff, q, k, rmax);
+      else k_scalar_ym_q<R, R, 0, 5><<<fill(k_scalar_ym_q<R, R, 0, 5>, l.n, q, st), b, 0, st>>>(d, l.items, l.qoff, q, k, rmax);
+    } else {
+      if (Q == 9) k_scalar_ym_q<R, S, 1, 9><<<fill(k_scalar_ym_q<R, S, 1, 9>, l.n, q, st), b, 0, st>>>(d, l.items, l.qoff, q, k, rmax);
+      else k_scalar_ym_q<R, S, 1, 5><<<fill(k_scalar_ym_q<R, S, 1, 5>, l.n, q, st), b, 0, st>>>(d, l.items, l.qoff, q, k, rmax);
+    }
+  }
+  static void tr_scalar_ymq(int Q, const QList& l, WorkQ* q, hipStream_t st, const Dom* d, unsigned k,
+                            double2* rmax) {
+    const dim3 b(TX, BY);
+    if (Q == 9) k_tr_scalar_ym_q<R, S, 9><<<fill(k_tr_scalar_ym_q<R, S, 9>, l.n, q, st), b, 0, st>>>(d, l.items, l.qoff, q, k, rmax);
+    else k_tr_scalar_ym_q<R, S, 5><<<fill(k_tr_scalar_ym_q<R, S, 5>, l.n, q, st), b, 0, st>>>(d, l.items, l.qoff, q, k, rmax);
   }
   // phase + transfer in one kernel: 8-row tiles in FP64 (LDS), 8 or 16 otherwise
   static int phase_tr_rows(int TY) { return sizeof(R) == 8 ? 8 : (TY >= 16 ? 16 : 8); }

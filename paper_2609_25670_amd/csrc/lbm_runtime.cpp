@@ -33,6 +33,12 @@ struct Launch {
   static int phase_tr_rows(int TY);
   static void phase_tr(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, unsigned k, Partial* p);
   static void phase_ym(int Q, dim3 g, hipStream_t st, const Dom* d, const int4* runs, unsigned k);
+  static void phase_ymq(int Q, const QList& l, WorkQ* q, hipStream_t st, const Dom* d, unsigned k);
+  static void transfer_ymq(const QList& l, WorkQ* q, hipStream_t st, const Dom* d, unsigned k, double2* rmax);
+  static void scalar_ymq(int field, int Q, const QList& l, WorkQ* q, hipStream_t st, const Dom* d, unsigned k,
+                         double2* rmax);
+  static void tr_scalar_ymq(int Q, const QList& l, WorkQ* q, hipStream_t st, const Dom* d, unsigned k,
+                            double2* rmax);
   static void dtr_phase(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, unsigned k, Partial* p);
   static void dtr_scalar(int TY, dim3 g, hipStream_t st, const Dom* d, const int4* t, unsigned k, Partial* p);
   static void transfer_ym(dim3 g, hipStream_t st, const Dom* d, const int4* runs, unsigned k, double2* rmax);
@@ -60,8 +66,8 @@ struct Launch3 {
   static void phase(const Dom& h, hipStream_t st, const Dom* d, unsigned k);
   static void transfer(const Dom& h, hipStream_t st, const Dom* d, unsigned k, Partial* p);
   static void scalar(int field, const Dom& h, hipStream_t st, const Dom* d, unsigned k, Partial* p);
-  static void flow(const Dom& h, hipStream_t st, const Dom* d, unsigned k);
-  static void step(const Dom& h, hipStream_t st, const Dom* d, unsigned k, Partial* p);
+  static void flow(const Dom& h, hipStream_t st, const Dom* d, unsigned k, int rows);
+  static void step(const Dom& h, hipStream_t st, const Dom* d, unsigned k, Partial* p, int rows);
   static void init(const Dom& h, hipStream_t st, const Dom* d, const double* xi);
   static void diag(const Dom& h, hipStream_t st, const Dom* d, long long k, Partial* p, double* front);
   static void read(const Dom& h, hipStream_t st, const Dom* d, long long k, const int* codes, int nc, int f64,
@@ -94,6 +100,7 @@ struct Group {
   TileSet ts[kNTY];   // per tile height
   TileSet runs;       // column runs, YCOL wide and YRUN rows high (2D marching kernels)
   TileSet runs64;     // phase field: runs 64 wide (the marching phase kernel)
+  QList q, q64;       // the same runs as eight per-XCD work-queue lists
 };
 
 struct Ops {
@@ -102,6 +109,10 @@ struct Ops {
   void (*phase_tr)(int, dim3, hipStream_t, const Dom*, const int4*, unsigned, Partial*);
   int (*phase_tr_rows)(int);
   void (*phase_ym)(int, dim3, hipStream_t, const Dom*, const int4*, unsigned);
+  void (*phase_ymq)(int, const QList&, WorkQ*, hipStream_t, const Dom*, unsigned);
+  void (*transfer_ymq)(const QList&, WorkQ*, hipStream_t, const Dom*, unsigned, double2*);
+  void (*scalar_ymq)(int, int, const QList&, WorkQ*, hipStream_t, const Dom*, unsigned, double2*);
+  void (*tr_scalar_ymq)(int, const QList&, WorkQ*, hipStream_t, const Dom*, unsigned, double2*);
   void (*dtr_phase)(int, dim3, hipStream_t, const Dom*, const int4*, unsigned, Partial*);
   void (*dtr_scalar)(int, dim3, hipStream_t, const Dom*, const int4*, unsigned, Partial*);
   void (*transfer_ym)(dim3, hipStream_t, const Dom*, const int4*, unsigned, double2*);
@@ -119,7 +130,8 @@ struct Ops {
 template <class R, class S>
 Ops make_ops() {
   return Ops{Launch<R, S>::phase, Launch<R, S>::transfer, Launch<R, S>::phase_tr, Launch<R, S>::phase_tr_rows,
-             Launch<R, S>::phase_ym, Launch<R, S>::dtr_phase, Launch<R, S>::dtr_scalar, Launch<R, S>::transfer_ym, Launch<R, S>::tr_scalar_ym, Launch<R, S>::scalar_ym, Launch<R, S>::scalar, Launch<R, S>::flow,
+             Launch<R, S>::phase_ym, Launch<R, S>::phase_ymq, Launch<R, S>::transfer_ymq, Launch<R, S>::scalar_ymq,
+             Launch<R, S>::tr_scalar_ymq, Launch<R, S>::dtr_phase, Launch<R, S>::dtr_scalar, Launch<R, S>::transfer_ym, Launch<R, S>::tr_scalar_ym, Launch<R, S>::scalar_ym, Launch<R, S>::scalar, Launch<R, S>::flow,
              Launch<R, S>::diag_tiles, Launch<R, S>::tips, Launch<R, S>::init, Launch<R, S>::read,
              Launch<R, S>::write};
 }
@@ -128,8 +140,8 @@ struct Ops3 {
   void (*phase)(const Dom&, hipStream_t, const Dom*, unsigned);
   void (*transfer)(const Dom&, hipStream_t, const Dom*, unsigned, Partial*);
   void (*scalar)(int, const Dom&, hipStream_t, const Dom*, unsigned, Partial*);
-  void (*flow)(const Dom&, hipStream_t, const Dom*, unsigned);
-  void (*step)(const Dom&, hipStream_t, const Dom*, unsigned, Partial*);
+  void (*flow)(const Dom&, hipStream_t, const Dom*, unsigned, int);
+  void (*step)(const Dom&, hipStream_t, const Dom*, unsigned, Partial*, int);
   void (*init)(const Dom&, hipStream_t, const Dom*, const double*);
   void (*diag)(const Dom&, hipStream_t, const Dom*, long long, Partial*, double*);
   void (*read)(const Dom&, hipStream_t, const Dom*, long long, const int*, int, int, void*);
@@ -216,6 +228,11 @@ struct lbm_ctx {
   bool one_T = false;     // one phase group; every domain has a transported T, all in one update group
   bool march_big = false; // the phase groups hold enough column runs to fill the chip
   bool marchable = false; // every domain 2D and at least 16 x 16 (the marching windows wrap once at most)
+  bool march_pick = false; // the autotuner's choice between marching and tiles (starts as march_big)
+  int queue = 0;          // marching launches: 0 autotuned, 1 per-XCD work queues, -1 static grids
+  bool use_q = false;     // the marching kernels run from the work queues
+  int flow_rows = 0;      // 3D flow tile rows: 4, 8 (FP32 arithmetic), or 0 for 4
+  WorkQ* d_wq = nullptr;  // the queues' counters (rewound before each launch)
   int qs = 5;             // scalar lattice of the (2D) context: 5 or 9
   hipGraphExec_t gexec = nullptr;
   int graph_ty = -1;
@@ -257,6 +274,7 @@ Layout layout_of(const lbm_params& p) {
   if (p.has_U) L.rplanes += 5 + 2 * d;                    // U (four buffers), pending U, first moment
   if (p.has_T) { L.rplanes += 5; L.splanes += 2 * d; }   // T (four buffers), pending T
   if (p.has_flow) { L.rplanes += 2 + 2 * d; L.splanes += 2 * (d == 3 ? 18 : 8); }
+  if (p.grad_phi == 1) L.rplanes += 6;   // Eq. (40) variant: v_n dt and A, two buffers
   return L;
 }
 
@@ -314,6 +332,8 @@ std::string validate(const lbm_params& p, int i) {
   }
   if (p.flow_bc[1] == LBM_BC_INLET_OUTFLOW) return bad("inlet/outflow is supported along x only");
   if (p.coupling != LBM_COUPLE_INSTANT && p.coupling != LBM_COUPLE_ACCUM) return bad("bad coupling");
+  if (p.grad_phi != LBM_GRAD_ISO && p.grad_phi != LBM_GRAD_EQ40) return bad("bad grad_phi");
+  if (p.grad_phi == LBM_GRAD_EQ40 && p.dim != 2) return bad("the Eq. (40) phase gradient is 2D only");
   // relaxation times at phi = +-1 (Eq. 24, 32): every tau must exceed 1/2
   const double amin = 1.0 - 5.0 / 3.0 * p.eps_s;
   const double ics2 = p.dim == 3 ? 4.0 : 3.0;   // 1/c_s^2 of the scalar lattice
@@ -405,7 +425,7 @@ static unsigned cycle_step(const lbm_ctx* c, long long k) { return (unsigned)((k
 
 // whether the phase field runs on the marching kernel
 static bool use_march(const lbm_ctx* c) {
-  return c->marchable && (c->march > 0 || (c->march == 0 && c->march_big));
+  return c->marchable && (c->march > 0 || (c->march == 0 && c->march_pick));
 }
 
 // Whether the transfer of phase step k (within the cycle) waits for the
@@ -438,7 +458,7 @@ static bool fuses_T(const lbm_ctx* c, unsigned k) {
 
 static void launch_step(lbm_ctx* c, hipStream_t st, unsigned k, bool last = false) {
   if (c->dim == 3) {
-    c->ops3.step(c->H[0], st, c->d_dom, k, c->s.part);
+    c->ops3.step(c->H[0], st, c->d_dom, k, c->s.part, c->flow_rows);
     return;
   }
   const int ti = c->ty_index, TY = kTYs[ti];
@@ -451,9 +471,12 @@ static void launch_step(lbm_ctx* c, hipStream_t st, unsigned k, bool last = fals
         c->ops.phase_tr(kTYs[tf], dim3(g.ts[tf].n), st, c->d_dom, g.ts[tf].d, k, c->s.part);
       } else {
         if (use_march(c)) {
-          c->ops.phase_ym(c->qs, dim3(g.runs64.n), st, c->d_dom, g.runs64.d, k);
-          if (!fuses_T(c, k))   // else inside the T transport, launched first below
-            c->ops.transfer_ym(dim3(g.runs.n), st, c->d_dom, g.runs.d, k, c->s.rmax);
+          if (c->use_q) c->ops.phase_ymq(c->qs, g.q64, c->d_wq, st, c->d_dom, k);
+          else c->ops.phase_ym(c->qs, dim3(g.runs64.n), st, c->d_dom, g.runs64.d, k);
+          if (!fuses_T(c, k)) {   // else inside the T transport, launched first below
+            if (c->use_q) c->ops.transfer_ymq(g.q, c->d_wq, st, c->d_dom, k, c->s.rmax);
+            else c->ops.transfer_ym(dim3(g.runs.n), st, c->d_dom, g.runs.d, k, c->s.rmax);
+          }
         } else {
           if (c->pending)   // the previous step's transfer runs inside this phase kernel
             c->ops.dtr_phase(TY, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k, c->s.part);
@@ -470,8 +493,10 @@ static void launch_step(lbm_ctx* c, hipStream_t st, unsigned k, bool last = fals
   // reads the transferred U (the two transports are independent)
   const bool trT = fuses_T(c, k);
   if (trT)
-    for (auto& g : c->g_T)
-      c->ops.tr_scalar_ym(c->qs, dim3(g.runs.n), st, c->d_dom, g.runs.d, k, c->s.rmax);
+    for (auto& g : c->g_T) {
+      if (c->use_q) c->ops.tr_scalar_ymq(c->qs, g.q, c->d_wq, st, c->d_dom, k, c->s.rmax);
+      else c->ops.tr_scalar_ym(c->qs, dim3(g.runs.n), st, c->d_dom, g.runs.d, k, c->s.rmax);
+    }
   // (the U transport marches too since the runs are 62 columns wide: 191
   // against 224 us per launch on the batched ensemble)
   for (auto& g : c->g_U)
@@ -479,6 +504,8 @@ static void launch_step(lbm_ctx* c, hipStream_t st, unsigned k, bool last = fals
       c->u_march = march && !fuses_U(c, k);
       if (fuses_U(c, k))   // carrying this step's transfer
         c->ops.dtr_scalar(TY, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k, c->s.part);
+      else if (march && c->use_q)
+        c->ops.scalar_ymq(0, c->qs, g.q, c->d_wq, st, c->d_dom, k, c->s.rmax);
       else if (march)
           c->ops.scalar_ym(0, c->qs, dim3(g.runs.n), st, c->d_dom, g.runs.d, k, c->s.rmax);
         else
@@ -486,7 +513,8 @@ static void launch_step(lbm_ctx* c, hipStream_t st, unsigned k, bool last = fals
     }
   for (auto& g : c->g_T)
     if (k % g.N == 0 && !trT) {
-      if (march) c->ops.scalar_ym(1, c->qs, dim3(g.runs.n), st, c->d_dom, g.runs.d, k, c->s.rmax);
+      if (march && c->use_q) c->ops.scalar_ymq(1, c->qs, g.q, c->d_wq, st, c->d_dom, k, c->s.rmax);
+      else if (march) c->ops.scalar_ym(1, c->qs, dim3(g.runs.n), st, c->d_dom, g.runs.d, k, c->s.rmax);
       else c->ops.scalar(1, TY, c->qs, dim3(g.ts[ti].n), st, c->d_dom, g.ts[ti].d, k, c->s.part);
     }
   for (auto& g : c->g_F)
@@ -545,9 +573,29 @@ static lbm_status autotune(lbm_ctx* c) {
       besti = ti;
     }
   }
+  c->ty_index = besti;
+  // marching contexts: static grids or the per-XCD work queues, timed on
+  // the marching phase kernel (the other marching kernels follow the pick)
+  if (c->marchable && use_march(c) && c->queue == 0 && !(c->fuse && c->fusable)) {
+    float t2[2] = {0.f, 0.f};
+    for (int form = 0; form < 2; ++form) {
+      auto run = [&]() {
+        for (auto& g : c->g_phi) {
+          if (form) c->ops.phase_ymq(c->qs, g.q64, c->d_wq, c->stream, c->d_dom, next_due(g.N));
+          else c->ops.phase_ym(c->qs, dim3(g.runs64.n), c->stream, c->d_dom, g.runs64.d, next_due(g.N));
+        }
+      };
+      run();
+      HIPCHK(c, hipEventRecord(e0, c->stream));
+      for (int r = 0; r < 5; ++r) run();
+      HIPCHK(c, hipEventRecord(e1, c->stream));
+      HIPCHK(c, hipEventSynchronize(e1));
+      HIPCHK(c, hipEventElapsedTime(&t2[form], e0, e1));
+    }
+    c->use_q = t2[1] < t2[0];
+  }
   HIPCHK(c, hipEventDestroy(e0));
   HIPCHK(c, hipEventDestroy(e1));
-  c->ty_index = besti;
   c->tuned = true;
   return LBM_OK;
 }
@@ -581,8 +629,10 @@ size_t lbm_workspace_bytes(const lbm_params* p, int32_t n, int32_t storage) {
   // tile lists per tile height: "all" plus, per field, one list per group of
   // domains sharing an update factor (at most 8 groups, each padded by < 8)
   total += kNTY * (5 * (sizeof(int4) * (size_t)(padded + 64)) + 40 * 256);
-  // run lists: per field, one list per group (at most 8 groups, each padded by < 8)
+  // run lists: per field, one list per group (at most 8 groups, each padded by < 8),
+  // and the same runs again as per-XCD work-queue lists with their offsets
   total += 4 * (sizeof(int4) * (size_t)(runs + 128) + 8 * 256);
+  total += 4 * (sizeof(int4) * (size_t)runs + 16 * 256 + 16 * 256) + align256(sizeof(WorkQ));
   total += align256(sizeof(Partial) * (size_t)tilesmax);
   total += align256(sizeof(double2) * (size_t)(runs + 1));
   total += align256(sizeof(int) * (size_t)tilesmax) + kNTY * align256(sizeof(int) * (n + 1));
@@ -700,6 +750,7 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
     D.has_T = q.has_T;
     D.has_F = q.has_flow;
     D.accum = q.coupling == LBM_COUPLE_ACCUM;
+    D.gradeq40 = q.grad_phi == LBM_GRAD_EQ40;
     D.T_var = (q.kappa_S != q.kappa_L) || (q.rhoCp_S != q.rhoCp_L);
     D.dt_base = q.dt_base;
     D.W0 = q.W0;
@@ -787,6 +838,8 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
         D.vel[b] = take(align256(pr) * q.dim);
       }
     }
+    if (D.gradeq40)
+      for (int b = 0; b < 2; ++b) D.gq[b] = take(align256(pr) * 3);
     lcm = ipow_lcm(lcm, q.N_phi);
     if (q.has_U) lcm = ipow_lcm(lcm, q.N_U);
     if (q.has_T) lcm = ipow_lcm(lcm, q.N_T);
@@ -800,10 +853,14 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
     c->deferrable &= p[i].N_phi == 1 && p[i].coupling == LBM_COUPLE_INSTANT && p[i].nx >= 8 && p[i].ny >= 8;
   c->marchable = true;
   for (int i = 0; i < n; ++i) c->marchable &= p[i].dim == 2 && p[i].nx >= 16 && p[i].ny >= 16;
+  // the Eq. (40) phase gradient exists in the tiled phase kernel only
+  for (int i = 0; i < n; ++i)
+    if (p[i].grad_phi == LBM_GRAD_EQ40) c->marchable = c->fusable = c->deferrable = false;
   {
     long long runs = 0;   // a column run is one block: marching pays when they are many
     for (int i = 0; i < n; ++i) runs += (long long)((p[i].nx + YCOL - 1) / YCOL) * ((p[i].ny + YRUN - 1) / YRUN);
     c->march_big = runs >= 4 * 256;
+    c->march_pick = c->march_big;
   }
   // the buffer indices of phi, U and T (write counts mod 4) repeat too;
   // the counts are even over 2 lcm, so doubling once makes them multiples of 4
@@ -912,6 +969,31 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
         g.runs64.n = (int)o.size();
         HIPCHK(c, hipMemcpy(g.runs64.d, o.data(), sizeof(int4) * o.size(), hipMemcpyHostToDevice));
       }
+      // work-queue lists: the domains by decreasing size (ties keep their
+      // order), each domain's runs row by row, cut into eight contiguous
+      // lists of equal length (a domain is split only at the cuts)
+      auto make_q = [&](int width, QList& ql) -> lbm_status {
+        std::vector<int> order = kv.second;
+        std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return sites_of(p[a]) > sites_of(p[b]); });
+        std::vector<int4> all;
+        for (int d : order)
+          for (int y0 = 0; y0 < p[d].ny; y0 += YRUN)
+            for (int x0 = 0; x0 < p[d].nx; x0 += width)
+              all.push_back(make_int4(d, x0, y0, std::min(p[d].ny, y0 + YRUN)));
+        int off[9];
+        for (int x = 0; x <= 8; ++x) off[x] = (int)((long long)all.size() * x / 8);
+        int4* items = (int4*)take(sizeof(int4) * std::max<size_t>(all.size(), 1));
+        int* qoff = (int*)take(sizeof(int) * 9);
+        HIPCHK(c, hipMemcpy(items, all.data(), sizeof(int4) * all.size(), hipMemcpyHostToDevice));
+        HIPCHK(c, hipMemcpy(qoff, off, sizeof(int) * 9, hipMemcpyHostToDevice));
+        ql = QList{items, qoff, (int)all.size()};
+        return LBM_OK;
+      };
+      {
+        lbm_status s = make_q(YCOL, g.q);
+        if (s == LBM_OK && field == 0) s = make_q(64, g.q64);
+        if (s != LBM_OK) return s;
+      }
       gs.push_back(g);
     }
     return LBM_OK;
@@ -933,6 +1015,11 @@ lbm_status lbm_create(const lbm_params* p, int32_t n, int32_t storage, int32_t d
   }
   c->s.part = (Partial*)take(sizeof(Partial) * (size_t)tilesmax);
   c->s.rmax = (double2*)take(sizeof(double2) * (size_t)(rbase + 1));
+  c->d_wq = (WorkQ*)take(sizeof(WorkQ));
+  if (hipMemset(c->d_wq, 0, sizeof(WorkQ)) != hipSuccess) {
+    lbm_destroy(c);
+    return fail(nullptr, LBM_EDEVICE, "clearing the work queues failed");
+  }
   if (hipMemset(c->s.rmax, 0, sizeof(double2) * (size_t)(rbase + 1)) != hipSuccess) {
     lbm_destroy(c);
     return fail(nullptr, LBM_EDEVICE, "clearing the run maxima failed");
@@ -1055,7 +1142,13 @@ lbm_status lbm_init_front(lbm_ctx* c, int32_t dom, const double* xi) {
 
 lbm_status lbm_configure(lbm_ctx* c, int32_t tile_rows, int32_t flags) {
   if (!c) return LBM_EINVAL;
-  if (tile_rows == 0) {
+  if (c->dim == 3) {   // 3D: rows of the flow kernel's tiles
+    if (tile_rows != 0 && tile_rows != 4 && tile_rows != 8)
+      return fail(c, LBM_EINVAL, "3D tile_rows must be 0, 4 or 8");
+    if (tile_rows == 8 && c->storage == LBM_STORE_F64)
+      return fail(c, LBM_EINVAL, "3D flow tiles of 8 rows need FP32 arithmetic");
+    c->flow_rows = tile_rows;
+  } else if (tile_rows == 0) {
     c->autotune = true;
     c->tuned = false;
   } else {
@@ -1067,13 +1160,17 @@ lbm_status lbm_configure(lbm_ctx* c, int32_t tile_rows, int32_t flags) {
     c->autotune = false;
     c->tuned = true;
   }
-  if (flags & ~31) return fail(c, LBM_EINVAL, "unknown configure flags");
+  if (flags & ~127) return fail(c, LBM_EINVAL, "unknown configure flags");
   if ((flags & LBM_CFG_MARCH) && (flags & LBM_CFG_TILES))
     return fail(c, LBM_EINVAL, "LBM_CFG_MARCH and LBM_CFG_TILES exclude each other");
+  if ((flags & LBM_CFG_QUEUE) && (flags & LBM_CFG_GRID))
+    return fail(c, LBM_EINVAL, "LBM_CFG_QUEUE and LBM_CFG_GRID exclude each other");
   c->use_graph = (flags & LBM_CFG_GRAPH) != 0;
   c->fuse = (flags & LBM_CFG_FUSE_TRANSFER) != 0;
   c->march = (flags & LBM_CFG_MARCH) ? 1 : (flags & LBM_CFG_TILES) ? -1 : 0;
   c->defer = (flags & LBM_CFG_NO_DEFER) == 0;
+  c->queue = (flags & LBM_CFG_QUEUE) ? 1 : (flags & LBM_CFG_GRID) ? -1 : 0;
+  if (c->queue != 0) c->use_q = c->queue > 0;
   if (c->gexec) {   // the captured cycle follows the kernel choice
     HIPCHK(c, hipStreamSynchronize(c->stream));
     (void)hipGraphExecDestroy(c->gexec);
@@ -1088,7 +1185,8 @@ int32_t lbm_marching(const lbm_ctx* c) { return c ? (use_march(c) ? 1 : 0) : -1;
 
 int32_t lbm_tile_rows(const lbm_ctx* c) {
   if (!c) return -1;
-  if (c->dim == 3 || (c->autotune && !c->tuned)) return 0;
+  if (c->dim == 3) return c->flow_rows == 8 ? 8 : 4;
+  if (c->autotune && !c->tuned) return 0;
   return kTYs[c->ty_index];
 }
 
@@ -1128,22 +1226,28 @@ lbm_status lbm_kernel_times(lbm_ctx* c, int32_t reps, double* ms_out, double* pe
           if (kind == 1) c->ops3.transfer(h, c->stream, c->d_dom, k, c->s.part);
           if (kind == 2) c->ops3.scalar(0, h, c->stream, c->d_dom, k, c->s.part);
           if (kind == 3) c->ops3.scalar(1, h, c->stream, c->d_dom, k, c->s.part);
-          if (kind == 4) c->ops3.flow(h, c->stream, c->d_dom, k);
+          if (kind == 4) c->ops3.flow(h, c->stream, c->d_dom, k, c->flow_rows);
           return;
         }
         if (kind == 0 && fused) {
           const int tf = ty_slot(c->ops.phase_tr_rows(TY));
           c->ops.phase_tr(kTYs[tf], dim3(g.ts[tf].n), c->stream, c->d_dom, g.ts[tf].d, k, c->s.part);
         }
-        if (kind == 0 && !fused && use_march(c))
+        if (kind == 0 && !fused && use_march(c) && c->use_q)
+          c->ops.phase_ymq(c->qs, g.q64, c->d_wq, c->stream, c->d_dom, k);
+        else if (kind == 0 && !fused && use_march(c))
           c->ops.phase_ym(c->qs, dim3(g.runs64.n), c->stream, c->d_dom, g.runs64.d, k);
         else if (kind == 0 && !fused)
           c->ops.phase(TY, c->qs, grid, c->stream, c->d_dom, g.ts[ti].d, k);
-        if (kind == 1 && use_march(c))
+        if (kind == 1 && use_march(c) && c->use_q)
+          c->ops.transfer_ymq(g.q, c->d_wq, c->stream, c->d_dom, k, c->s.rmax);
+        else if (kind == 1 && use_march(c))
           c->ops.transfer_ym(dim3(g.runs.n), c->stream, c->d_dom, g.runs.d, k, c->s.rmax);
         else if (kind == 1)
           c->ops.transfer(TY, grid, c->stream, c->d_dom, g.ts[ti].d, k, c->s.part);
-        if ((kind == 2 || kind == 3) && use_march(c))
+        if ((kind == 2 || kind == 3) && use_march(c) && c->use_q)
+          c->ops.scalar_ymq(kind - 2, c->qs, g.q, c->d_wq, c->stream, c->d_dom, k, c->s.rmax);
+        else if ((kind == 2 || kind == 3) && use_march(c))
           c->ops.scalar_ym(kind - 2, c->qs, dim3(g.runs.n), c->stream, c->d_dom, g.runs.d, k, c->s.rmax);
         else if (kind == 2 || kind == 3)
           c->ops.scalar(kind - 2, TY, c->qs, grid, c->stream, c->d_dom, g.ts[ti].d, k, c->s.part);
@@ -1224,7 +1328,8 @@ lbm_status lbm_kernel_times(lbm_ctx* c, int32_t reps, double* ms_out, double* pe
       const unsigned k = cycle_step(c, due(std::lcm(g.N, c->g_phi[0].N)));
       lbm_status s = time_launch(
           [&]() {
-            c->ops.tr_scalar_ym(c->qs, dim3(g.runs.n), c->stream, c->d_dom, g.runs.d, k, c->s.rmax);
+            if (c->use_q) c->ops.tr_scalar_ymq(c->qs, g.q, c->d_wq, c->stream, c->d_dom, k, c->s.rmax);
+            else c->ops.tr_scalar_ym(c->qs, dim3(g.runs.n), c->stream, c->d_dom, g.runs.d, k, c->s.rmax);
           },
           ms_out[7]);
       if (s != LBM_OK) return s;

@@ -25,6 +25,7 @@ BC = {"periodic": 0, "wall": 1, "inlet_outflow": 2}
 STORAGE = {"f64": 0, "f32": 1, "f16": 2, "bf16": 3}
 COUPLING = {"instant": 0, "accum": 1}
 T_MODE = {"transport": 0, "pulled": 1, "dirichlet_low": 2}
+GRAD_PHI = {"fd": 0, "eq40": 1}
 
 # names, plane counts per field bit (2D)
 FIELD_BITS = [("phi", F_PHI, 1), ("U", F_U, 1), ("T", F_T, 1), ("rho", F_RHO, 1), ("vel", F_VEL, 2),
@@ -55,7 +56,7 @@ class Params(ctypes.Structure):
         ("s_eps", ctypes.c_double), ("s_q", ctypes.c_double), ("u_in", ctypes.c_double),
         ("Fb", ctypes.c_double * 3), ("bc", ctypes.c_int32 * 3), ("flow_bc", ctypes.c_int32 * 3),
         ("U0", ctypes.c_double), ("T0", ctypes.c_double), ("u0_liquid_only", ctypes.c_int32),
-        ("coupling", ctypes.c_int32), ("T_mode", ctypes.c_int32), ("pad", ctypes.c_int32),
+        ("coupling", ctypes.c_int32), ("T_mode", ctypes.c_int32), ("grad_phi", ctypes.c_int32),
         ("T_grad", ctypes.c_double), ("V_pull", ctypes.c_double), ("z_front", ctypes.c_double),
     ]
 
@@ -144,6 +145,7 @@ def to_params(d: dict) -> Params:
     p.u0_liquid_only = int(bool(d.get("u0_liquid_only", False)))
     p.coupling = COUPLING[d.get("coupling", "instant")]
     p.T_mode = T_MODE[d.get("T_mode", "transport")]
+    p.grad_phi = GRAD_PHI[d.get("grad_phi", "fd")]
     p.T_grad = float(d.get("T_grad", 0.0))
     p.V_pull = float(d.get("V_pull", 0.0))
     p.z_front = float(d.get("z_front", 0.0))
@@ -211,14 +213,17 @@ class Simulation:
             r = (ctypes.c_double * max(1, len(seeds)))(*[s[2] for s in seeds])
             _check(self.lib, self.ctx, self.lib.lbm_init_seeds(self.ctx, i, len(seeds), c, r))
 
-    def configure(self, tile_rows=0, use_graph=True, fuse_transfer=False, march=None, defer=True):
+    def configure(self, tile_rows=0, use_graph=True, fuse_transfer=False, march=None, defer=True, queue=None):
         """Tile height (0 = autotune), HIP-graph replay of whole cycles,
         whether the 2D transfer runs inside the phase kernel, whether the 2D
         phase, transfer and T-transport kernels march up 64-wide columns
-        (True), tile (False) or choose by size (None), and whether a
-        transfer may be deferred into the next phase kernel."""
+        (True), tile (False) or choose by size (None), whether a transfer
+        may be deferred into the next phase kernel, and whether the marching
+        kernels take their runs from per-XCD work queues (True), run one
+        block per run (False) or let the autotuner pick (None)."""
         flags = (1 if use_graph else 0) | (2 if fuse_transfer else 0) | (0 if defer else 16)
         flags |= {None: 0, True: 4, False: 8}[march]
+        flags |= {None: 0, True: 32, False: 64}[queue]
         _check(self.lib, self.ctx, self.lib.lbm_configure(self.ctx, int(tile_rows), flags))
 
     def step(self, n, diag=False, static=False):
@@ -263,7 +268,7 @@ class Simulation:
     @property
     def tile_rows(self) -> int:
         """Tile height of the 2D tiled kernels in use (0 before the
-        autotuner has run, and in 3D)."""
+        autotuner has run); in 3D the rows of the flow kernel's tiles."""
         return int(self.lib.lbm_tile_rows(self.ctx))
 
     def _layout(self, names, domain=0):

@@ -51,11 +51,11 @@ def _compare(case, got, ref, tol):
         assert e <= tol, (case, name, e)
 
 
-def _run(wl, steps, names, storage="f64", use_graph=True):
+def _run(wl, steps, names, storage="f64", use_graph=True, rows=0):
     from paper_2609_25670_amd import simulation_for
 
     sim = simulation_for(wl, storage=storage)
-    sim.configure(0, use_graph)
+    sim.configure(rows, use_graph)
     diag = sim.step(steps, diag=True)
     got = sim.read(0, names)
     sim.close()
@@ -127,6 +127,43 @@ def test_3d_periodic_z_ragged_tiles_fp64():
     dom = oracle.run(d, 36)
     _compare("3d periodic", got, _ref(dom, names), TOL64)
     assert diag["nonfinite"] == 0
+
+
+@pytest.mark.parametrize("storage", ["f32", "bf16"])
+def test_3d_flow_tile_heights_are_bitwise_identical(storage):
+    """With FP32 arithmetic the flow may run on 64 x 8 tiles instead of the
+    default 64 x 4; both give the same bits (the ring collisions are the
+    same expressions), on a driven flow with ragged tiles in x and y (70 x 9:
+    9 = 8 + 1 = 2 x 4 + 1), periodic in every direction, and on walls normal
+    to x and z (24 x 20: 20 = 2 x 8 + 4), graph and direct launches."""
+    from paper_2609_25670_amd import simulation_for
+
+    cases = []
+    wl = _directional(70, 9, 21)
+    d = wl["domains"][0]
+    d.update(T_mode="transport", T0=d["T0"] - 0.02, N_U=1, N_T=2, N_F=2, bc=("periodic", "periodic", "periodic"),
+             flow_bc=("periodic", "periodic", "periodic"), D_L=0.05, D_S=5e-4)
+    cases.append(("periodic 70x9x21", wl))
+    wl = _directional(24, 20, 33)
+    d = wl["domains"][0]
+    d.update(T_mode="transport", T0=d["T0"] - 0.02, N_F=1, bc=("wall", "periodic", "wall"),
+             flow_bc=("wall", "periodic", "wall"), D_L=0.05, D_S=5e-4)
+    cases.append(("walls 24x20x33", wl))
+    names = ("phi", "U", "T", "rho", "vel", "f_F")
+    for label, wl in cases:
+        res = {}
+        for rows, g in ((8, True), (4, True), (8, False)):
+            _say(f"case 3d flow tiles {label} {storage} rows={rows} graph={g}")
+            res[(rows, g)], _ = _run(wl, 40, names, storage=storage, use_graph=g, rows=rows)
+        sim = simulation_for(wl, storage=storage)
+        assert sim.tile_rows == 4
+        sim.configure(8, True)
+        assert sim.tile_rows == 8
+        sim.close()
+        for n in names:
+            assert np.array_equal(res[(8, True)][n], res[(4, True)][n]), (label, n)
+            assert np.array_equal(res[(8, True)][n], res[(8, False)][n]), (label, n)
+        assert float(np.max(np.abs(res[(8, True)]["vel"]))) > 0
 
 
 def test_3d_checkpoint_restore_is_bitwise():

@@ -337,6 +337,42 @@ def test_marching_U_transport_is_bitwise_identical(coupling, fuse):
     assert res[1][1]["J_U"] > 0
 
 
+@pytest.mark.parametrize("storage", ["f64", "f16"])
+def test_work_queue_launches_are_bitwise_identical(storage):
+    """The marching kernels launched as persistent blocks that take their
+    runs from the eight per-XCD work queues equal the static one-block-per-
+    run grids bit for bit: twelve uneven domains of the ensemble (every
+    Lewis number, so every update group of U), with graph replay and with
+    direct launches, the same state and the same S_phi and J_U; and the
+    FP64 form equals the oracle on two of the domains."""
+    from paper_2609_25670_amd import simulation_for
+
+    wl = L.ensemble_256(n_domains=12, side_lo=48, side_hi=190)
+    names = ("phi", "U", "T", "jU", "jT")
+    res = {}
+    for queue in (False, True):
+        for g in (True, False):
+            _say(f"case work queue {storage} queue={queue} graph={g}")
+            sim = simulation_for(wl, storage=storage)
+            sim.configure(16, g, False, True, True, queue)
+            sim.step(7)
+            diag = sim.step(26, diag=True)
+            got = [sim.read(i, names) for i in range(sim.n)]
+            sim.close()
+            res[(queue, g)] = (got, diag)
+    ref = res[(False, True)]
+    for key, (got, diag) in res.items():
+        for i in range(len(got)):
+            for n in names:
+                assert np.array_equal(got[i][n], ref[0][i][n]), (key, i, n)
+            assert diag[i]["S_phi"] == ref[1][i]["S_phi"] and diag[i]["J_U"] == ref[1][i]["J_U"], key
+    if storage == "f64":
+        for i in (0, 7):
+            dom = oracle.run(wl["domains"][i], 33)
+            _compare(f"work queue domain {i}", res[(True, True)][0][i], _oracle_fields(dom, ("phi", "U", "T")),
+                     TOL64)
+
+
 @pytest.mark.parametrize("bcx", ["periodic", "wall"])
 def test_marching_one_column_last_run_fp64(bcx):
     """Marching on 125 x 67: the 62-column runs leave a last run one column
