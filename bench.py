@@ -264,7 +264,8 @@ def directional_run(args) -> int:
     (comma-separated) is one domain of a single batched context.  Steps to
     ``--t-end-ms`` (dt_base = 2e-9 s, so 20 ms = 1e7 base steps) and prints
     one JSON line per domain every ``--every-ms`` with the time, S_phi, J_U,
-    R_M and the largest phi (read back), then a summary line per domain.
+    R_M, the range of phi and of U (read back), then a summary line per
+    domain.
     A domain whose state turns non-finite is reported with the step at which
     the device screen found it, and the run stops there."""
     import lbm_inputs as L
@@ -301,13 +302,15 @@ def directional_run(args) -> int:
         done += n
         for i, le in enumerate(les):
             x = dd[i]
-            phimax = float(np.max(sim.read(i, ("phi",))["phi"]))
+            fld = sim.read(i, ("phi", "U"))
+            phimax = float(np.max(fld["phi"]))
             first_bad[i] = x["first_nonfinite_step"]
             pk = peak[i]
             pk["S_phi"], pk["J_U"] = max(pk["S_phi"], x["S_phi"]), max(pk["J_U"], x["J_U"])
             pk["phi"] = max(pk["phi"], phimax) if np.isfinite(phimax) else phimax
             last[i] = dict(Le=le, step=x["step"], t_ms=x["step"] / steps_per_ms, S_phi=x["S_phi"], J_U=x["J_U"],
-                           R_M=x["R_M"], phi_max=phimax, nonfinite=x["nonfinite"],
+                           R_M=x["R_M"], phi_max=phimax, phi_min=float(np.min(fld["phi"])),
+                           U_min=float(np.min(fld["U"])), U_max=float(np.max(fld["U"])), nonfinite=x["nonfinite"],
                            wall_s=round(time.perf_counter() - t0, 1))
             print(json.dumps(last[i]), flush=True)
     sim.close()

@@ -19,5 +19,6 @@ from .configs import (  # noqa: F401
     directional_2d,
     thermal_forced_512,
     solutal_forced_1000,
+    thermosolutal_forced_1500,
     reduced,
 )

@@ -321,6 +321,38 @@ def solutal_forced_1000(N_U: int = 15) -> dict:
                 dtype="f32", storage="f32")
 
 
+def thermosolutal_forced_1500(N_U: int = 30, tau0: float = 500.0) -> dict:
+    """Section 4.3 thermosolutal dendrite under forced convection, 1500 x 1500.
+
+    The printed set (W0 = 2, eps_s = 0.02, d0 = 0.554 W0, lambda = 1.5955,
+    M_c = 0.1, k = 0.15, U0 = 0, theta0 = -0.55, Le = alpha_L / D_L = 50,
+    D_S = 1e-2 D_L, Pr = nu / alpha_L = 23.1, u_in = W0 / (5 tau0), seed
+    R_s = 45 at the centre, N_phi = N_T = N_F = 1) with tau0 = 500 instead of
+    the printed 1000: at tau0 = 1000 the phase update of Eq. (26) has modes
+    that grow at every reading (tau_phi = 0.512 < 1/(2 A) on diagonal
+    normals), at 500 it has none (tau_phi = 0.523).  D_L follows from the
+    printed D~_L = D_L tau0 / W0^2 = 1, so D_L = 0.008, alpha_L = 0.4,
+    nu = 9.24; N_U in {30, 40, 50} (Fig. 10b, c).
+    """
+    d = _base_domain()
+    W0 = 2.0
+    D_L = W0 * W0 / tau0
+    alpha = 50.0 * D_L
+    d.update(
+        nx=1500, ny=1500, has_U=True, has_T=True, has_flow=True,
+        N_phi=1, N_U=int(N_U), N_T=1, N_F=1, dt_base=1.0,
+        W0=W0, tau0=float(tau0), eps_s=0.02, lam=1.5955, Mc=0.1, k=0.15,
+        D_L=D_L, D_S=1.0e-2 * D_L, C_inf=1.0,
+        kappa_S=alpha, kappa_L=alpha, rhoCp_S=1.0, rhoCp_L=1.0,
+        rho_L=1.0, L_h=1.0, Cp_L=1.0, T_m=0.0, m_L=0.0, T0=-0.55, U0=0.0,
+        nu=23.1 * alpha, u_in=W0 / (5.0 * tau0), u0_liquid_only=True,
+        bc=("wall", "wall", "wall"), flow_bc=("inlet_outflow", "periodic", "periodic"),
+        seeds=[(749.5, 749.5, 45.0)],
+    )
+    return dict(name=f"thermosolutal_forced_1500_NU{N_U}", domains=[d], steps=540000, steps_timed=15000,
+                dtype="f32", storage="f32")
+
+
 WORKLOADS = {
     "thermal_128": thermal_128,
     "solutal_512": solutal_512,
@@ -331,6 +363,7 @@ WORKLOADS = {
     "directional_2d": directional_2d,
     "thermal_forced_512": thermal_forced_512,
     "solutal_forced_1000": solutal_forced_1000,
+    "thermosolutal_forced_1500": thermosolutal_forced_1500,
 }
 
 

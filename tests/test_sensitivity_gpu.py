@@ -79,3 +79,18 @@ def test_solutal_forced_convection_update_factor_sensitivity():
         _say(f"case solutal forced convection N_U={N_U}, t/tau0 = 200")
         runs.append((N_U,) + _tip_history(L.solutal_forced_1000(N_U), t_end=10000.0, every_t=100.0))
     _check("solutal", runs, tol_pos=0.02, tol_vel=0.05)
+
+
+def test_thermosolutal_forced_convection_update_factor_sensitivity():
+    """Section 4.3 (Fig. 10b, c): N_U = 30, 40, 50 with N_phi = N_T = N_F = 1,
+    Le = 50, at tau0 = 500 (the printed 1000 is linearly unstable under
+    Eq. 26), to t D_L / d0^2 = 1000 (about 150k base steps)."""
+    runs = []
+    for N_U in (30, 40, 50):
+        wl = L.thermosolutal_forced_1500(N_U)
+        d = wl["domains"][0]
+        d0 = 0.554 * d["W0"]
+        t_end = 1000.0 * d0 * d0 / d["D_L"]
+        _say(f"case thermosolutal forced convection N_U={N_U}, t D_L/d0^2 = 1000 ({t_end:.0f} steps)")
+        runs.append((N_U,) + _tip_history(wl, t_end=round(t_end, -3), every_t=2000.0))
+    _check("thermosolutal", runs, tol_pos=0.02, tol_vel=0.05)
