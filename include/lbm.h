@@ -256,9 +256,10 @@ lbm_status lbm_write_fields(lbm_ctx* ctx, int32_t domain, uint32_t mask,
                             int32_t src_is_device, const void* src);
 
 /* Tuning: rows per tile of the stencil kernels (4, 8, 16 or 32; 0 = autotune;
- * in 3D, rows of the flow kernel's 64-wide tiles: 0 or 4, or 8 with FP32
- * arithmetic (LBM_EINVAL in FP64); both heights give the same bits) and
- * flags:
+ * in 3D, rows of every kernel's 64-wide tiles, 4 or 8 (the flow keeps 4 in
+ * FP64), or 0 for per-kernel defaults (8 for the phase and scalar
+ * kernels, 4 for the transfer and the flow); both heights give the same
+ * bits) and flags:
  *   LBM_CFG_GRAPH           replay whole multirate cycles from a HIP graph
  *   LBM_CFG_FUSE_TRANSFER   2D: run the transfer of Eq. (36)-(39) inside the
  *                           phase kernel, which then recomputes a halo of
@@ -331,7 +332,8 @@ int32_t lbm_marching(const lbm_ctx* ctx);
 /* Tile height of the 2D tiled kernels in use: the one fixed by
  * lbm_configure, else the autotuner's pick once it has run (at the first
  * lbm_step_multirate or lbm_kernel_times), else 0; for a 3D context the
- * rows of the flow kernel's tiles (4 or 8); -1 for ctx NULL. */
+ * rows fixed by lbm_configure, 0 for the per-kernel defaults; -1 for ctx
+ * NULL. */
 int32_t lbm_tile_rows(const lbm_ctx* ctx);
 
 /* Text of the last error of ctx (or of the last failed lbm_create when ctx

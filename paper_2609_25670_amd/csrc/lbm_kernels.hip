@@ -101,27 +101,27 @@ __device__ __forceinline__ void st(GLOBAL __hip_bfloat16* p, long long i, float 
 }
 
 // Stochastic BF16 rounding of the 3D kernels: one stream of random words
-// per site and launch.  The stream is seeded by hashing the site's offset,
-// the absolute base step and a per-kernel constant, and advanced by one
-// xorshift32 step (Marsaglia 2003) per store; gfx950's v_cvt_sr_bf16_f32
-// adds the word's top 16 bits below the kept mantissa and truncates (the
-// rounding of bf16_sr, in one instruction).  A store is then a pure
-// function of the site, the step and the value, so runs stay bitwise
-// reproducible across launch shapes and graph replays, and a value held
-// constant over many steps is still rounded up and down in proportion.
-// One hash per site instead of one per store: the D3Q19 flow stores 18
-// values per site.
+// per site and launch.  The stream starts at a hash of the site's offset,
+// the absolute base step and a per-kernel constant, and advances by the
+// golden-ratio increment per store (a Weyl sequence: one add); gfx950's
+// v_cvt_sr_bf16_f32 adds the word's top 16 bits below the kept mantissa
+// and truncates (the rounding of bf16_sr, in one instruction).  Each word
+// is uniform over steps since its start is, so every store rounds up with
+// the probability of its remainder (unbiased), while the words of one site
+// are spread evenly.  A store is a pure function of the site, the step and
+// the value, so runs stay bitwise reproducible across launch shapes and
+// graph replays, and a value held constant over many steps is still
+// rounded up and down in proportion.  One hash per site instead of one per
+// store: the D3Q19 flow stores 18 values per site.
 struct SRStream {
   uint32_t s;
   __device__ __forceinline__ uint32_t next() {
-    s ^= s << 13;
-    s ^= s >> 17;
-    s ^= s << 5;
+    s += 0x9e3779b9u;
     return s;
   }
 };
 __device__ __forceinline__ SRStream sr_stream(unsigned o, long long step, uint32_t salt) {
-  return SRStream{mix32(o ^ ((uint32_t)step * 0x9e3779b9u) ^ salt) | 1u};
+  return SRStream{mix32(o ^ ((uint32_t)step * 0x9e3779b9u) ^ salt)};
 }
 
 // Element i of a plane addressed through a 32-bit byte offset.  The plane
@@ -3355,7 +3355,6 @@ constexpr int ZTX = 64, ZTY = 4;                  // tile: one site per thread a
 constexpr int ZRW = ZTX + 2, ZRH = ZTY + 2;       // collision region (ring 1)
 constexpr int ZBW = ZTX + 4, ZBH = ZTY + 4;       // phase window (ring 2)
 constexpr int ZNR = ZRW * ZRH, ZNB = ZBW * ZBH;
-constexpr int ZNBL = (ZNB + 255) / 256;           // window cells per thread
 
 __device__ __forceinline__ int zslot4(int z) { return (z + 8) & 3; }
 __device__ __forceinline__ int zslot3(int z) { return (z + 9) % 3; }
@@ -3425,35 +3424,45 @@ __device__ __forceinline__ void zgrad(const R* p0, const R* p1, const R* p2, int
 }
 
 // window cells of a thread: the in-plane offset of the ghosted site (walls
-// clamp to the boundary node, periodic axes wrap)
-struct ZWinMap {
-  unsigned o[ZNBL];    // in-plane offset of the ghosted site
+// clamp to the boundary node, periodic axes wrap).  A 64 x TY tile has
+// 64 TY threads and a window of ZBW x (TY + 4) cells.
+template <int TY>
+struct ZWinT {
+  static constexpr int NT = 64 * TY, NB = ZBW * (TY + 4), NBL = (NB + NT - 1) / NT;
 };
-__device__ __forceinline__ void zwin_map(const ZGeo& G, const ZCol& c, int tid, ZWinMap& m) {
+template <int TY = ZTY>
+struct ZWinMap {
+  unsigned o[ZWinT<TY>::NBL];    // in-plane offset of the ghosted site
+};
+template <int TY>
+__device__ __forceinline__ void zwin_map(const ZGeo& G, const ZCol& c, int tid, ZWinMap<TY>& m) {
+  using W = ZWinT<TY>;
 #pragma unroll
-  for (int i = 0; i < ZNBL; ++i) {
-    const int cc = min(tid + 256 * i, ZNB - 1);
+  for (int i = 0; i < W::NBL; ++i) {
+    const int cc = min(tid + W::NT * i, W::NB - 1);
     const int gx = ghost(c.x0 - 2 + cc % ZBW, G.nx, G.bcx), gy = ghost(c.y0 - 2 + cc / ZBW, G.ny, G.bcy);
     m.o[i] = (unsigned)gy * (unsigned)G.px + (unsigned)gx;
   }
 }
-template <class R>
+template <class R, int TY = ZTY>
 struct ZWin {
-  R v[ZNBL];
+  R v[ZWinT<TY>::NBL];
 };
-template <class R>
-__device__ __forceinline__ void zload_win(const ZGeo& G, const ZWinMap& m, int zw, int tid, GLOBAL const R* f,
-                                          ZWin<R>& w) {
+template <class R, int TY>
+__device__ __forceinline__ void zload_win(const ZGeo& G, const ZWinMap<TY>& m, int zw, int tid, GLOBAL const R* f,
+                                          ZWin<R, TY>& w) {
+  using W = ZWinT<TY>;
   const unsigned pz = (unsigned)ghost(zw, G.nz, G.bcz) * (unsigned)G.ny * (unsigned)G.px;
 #pragma unroll
-  for (int i = 0; i < ZNBL; ++i)
-    if (tid + 256 * i < ZNB) w.v[i] = ldo(f, pz + m.o[i]);
+  for (int i = 0; i < W::NBL; ++i)
+    if (tid + W::NT * i < W::NB) w.v[i] = ldo(f, pz + m.o[i]);
 }
-template <class R>
-__device__ __forceinline__ void zput_win(R* dst, const ZWin<R>& w, int tid) {
+template <class R, int TY>
+__device__ __forceinline__ void zput_win(R* dst, const ZWin<R, TY>& w, int tid) {
+  using W = ZWinT<TY>;
 #pragma unroll
-  for (int i = 0; i < ZNBL; ++i)
-    if (tid + 256 * i < ZNB) dst[tid + 256 * i] = w.v[i];
+  for (int i = 0; i < W::NBL; ++i)
+    if (tid + W::NT * i < W::NB) dst[tid + W::NT * i] = w.v[i];
 }
 
 // region cells of a thread: region index and in-plane offset (-1: none,
@@ -3501,15 +3510,16 @@ __device__ __forceinline__ void zload_phase(const ZGeo& G, const ZRegMap& m, int
   }
 }
 
-template <class R, class S>
-__global__ __launch_bounds__(256) void k3z_phase(const Dom* __restrict__ doms, unsigned k, int zrun) {
+template <class R, class S, int TY>
+__global__ __launch_bounds__(64 * TY) void k3z_phase(const Dom* __restrict__ doms, unsigned k, int zrun) {
   using SR = typename RawT<S>::type;
+  constexpr int ZNR = ZRW * (TY + 2), ZNB = ZWinT<TY>::NB;   // collision region and window of a 64 x TY tile
   __shared__ R wphi[4][ZNB];
   __shared__ R wcol[3][4][ZNR];   // dP, Kx, Ky, Kz per region cell
   const Dom& D = doms[0];
   const ZGeo G = zgeo(D);
   ZCol c;
-  if (!zcol(G, blockIdx.x, zrun, c) || k % D.N_phi) return;
+  if (!zcol<TY>(G, blockIdx.x, zrun, c) || k % D.N_phi) return;
   const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
   const long long pl = D.plane;
   const long long kabs = D.koff + (long long)k;   // absolute base step (rounding streams)
@@ -3526,7 +3536,7 @@ __global__ __launch_bounds__(256) void k3z_phase(const Dom* __restrict__ doms, u
   const R U0 = kc<R>(D, K_U0), T0 = kc<R>(D, K_T0);
   const bool own = tx < c.w && ty < c.h;
   const int gx = c.x0 + tx, gy = c.y0 + ty;
-  ZWinMap wm;
+  ZWinMap<TY> wm;
   zwin_map(G, c, tid, wm);
   ZRegMap rm;
   zreg_map(G, c, tid, rm);
@@ -3572,7 +3582,7 @@ __global__ __launch_bounds__(256) void k3z_phase(const Dom* __restrict__ doms, u
   R Acur = R(1), Anext = R(1), svcur[6], svnext[6];
   ZPhaseIn<R, S> in0, in1;
   {
-    ZWin<R> w0, w1, w2, w3;
+    ZWin<R, TY> w0, w1, w2, w3;
     zload_win(G, wm, c.za - 2, tid, phi, w0);
     zload_win(G, wm, c.za - 1, tid, phi, w1);
     zload_win(G, wm, c.za, tid, phi, w2);
@@ -3587,20 +3597,25 @@ __global__ __launch_bounds__(256) void k3z_phase(const Dom* __restrict__ doms, u
   __syncthreads();
   collide(in0, c.za - 1, Anext, svnext);
   collide(in1, c.za, Acur, svcur);
-  ZWin<R> wn;
+  ZWin<R, TY> wn;
   zload_win(G, wm, c.za + 2, tid, phi, wn);
   zload_phase(G, rm, c.za + 1, pl, sp, Up, Tp, in0);
   __syncthreads();
 
-  for (int z = c.za; z < c.zb; ++z) {
+  // one plane: `cur` holds the inputs of plane z + 1 and the prefetch for
+  // plane z + 2 goes to `nxt`; (Ac, svc) are the own site's A and
+  // deviations of plane z, (An, svn) receive those of plane z + 1.  The
+  // loop runs two planes per iteration with the roles swapped, so no
+  // register state is copied between planes.
+  ZPhaseIn<R, S> in1b;
+  auto plane_step = [&](int z, ZPhaseIn<R, S>& cur, ZPhaseIn<R, S>& nxt, R& Ac, R* svc, R& An, R* svn) {
     zput_win(wphi[zslot4(z + 2)], wn, tid);
-    const ZPhaseIn<R, S> cur = in0;
     if (z + 1 < c.zb) {   // prefetch for the next plane
       zload_win(G, wm, z + 3, tid, phi, wn);
-      zload_phase(G, rm, z + 2, pl, sp, Up, Tp, in0);
+      zload_phase(G, rm, z + 2, pl, sp, Up, Tp, nxt);
     }
     __syncthreads();
-    collide(cur, z + 1, Anext, svnext);   // the plane above: its halo for this plane
+    collide(cur, z + 1, An, svn);   // the plane above: its halo for this plane
     __syncthreads();
     if (own) {
       // anisotropic pull streaming (Eq. 26) in deviations from w_i phi(y)
@@ -3608,11 +3623,11 @@ __global__ __launch_bounds__(256) void k3z_phase(const Dom* __restrict__ doms, u
       const R* c1 = &wcol[zslot3(z)][0][0];
       const R py = wphi[zslot4(z)][cb];
       const R dPy = c1[cr], Ky[3] = {c1[ZNR + cr], c1[2 * ZNR + cr], c1[3 * ZNR + cr]};
-      const R A = Acur, iA = rcp(A), oA = R(1) - A;
+      const R A = Ac, iA = rcp(A), oA = R(1) - A;
       const bool upz[2] = {resolve(z - 1, G.nz, G.bcz) >= 0, resolve(z + 1, G.nz, G.bcz) >= 0};
       R s0 = R(0);
 #pragma unroll
-      for (int q = 0; q < 6; ++q) s0 -= svcur[q];
+      for (int q = 0; q < 6; ++q) s0 -= svc[q];
       R dn[7], sum;
       dn[0] = (dPy * R(0.25) - oA * s0) * iA;
       sum = dn[0];
@@ -3629,7 +3644,7 @@ __global__ __launch_bounds__(256) void k3z_phase(const Dom* __restrict__ doms, u
         } else {
           dpost = dPy * R(0.125) - R(0.5) * edot3(ex, ey, ez, Ky[0], Ky[1], Ky[2]);
         }
-        dn[q] = (dpost - oA * svcur[q - 1]) * iA;
+        dn[q] = (dpost - oA * svc[q - 1]) * iA;
         sum += dn[q];
       }
       const unsigned o = zoff(G, gx, gy, z);
@@ -3638,10 +3653,11 @@ __global__ __launch_bounds__(256) void k3z_phase(const Dom* __restrict__ doms, u
 #pragma unroll
       for (int q = 1; q < 7; ++q) sto_sr(plane(s_out, (q - 1) * pl), o, dn[q] - R(0.125) * sum, rs);
     }
-    Acur = Anext;
-#pragma unroll
-    for (int q = 0; q < 6; ++q) svcur[q] = svnext[q];
     __syncthreads();
+  };
+  for (int z = c.za; z < c.zb; z += 2) {
+    plane_step(z, in0, in1b, Acur, svcur, Anext, svnext);
+    if (z + 1 < c.zb) plane_step(z + 1, in1b, in0, Anext, svnext, Acur, svcur);
   }
 }
 
@@ -3677,19 +3693,20 @@ __device__ __forceinline__ void zload_scal(const ZGeo& G, const ZRegMap& m, int 
 // (dP, K) on the region of the plane above, pull streaming (Eq. 25) of the
 // current plane with bounce-back, or anti-bounce-back to the moving
 // profile on the z walls of the pulled T
-template <class R, class S, int FIELD>
-__global__ __launch_bounds__(256) void k3z_scalar(const Dom* __restrict__ doms, unsigned k, int zrun,
+template <class R, class S, int FIELD, int TY>
+__global__ __launch_bounds__(64 * TY) void k3z_scalar(const Dom* __restrict__ doms, unsigned k, int zrun,
                                                   Partial* __restrict__ part) {
   using SR = typename RawT<S>::type;
+  constexpr int ZNR = ZRW * (TY + 2), ZNB = ZWinT<TY>::NB;   // collision region and window of a 64 x TY tile
   __shared__ R wphi[4][ZNB];
   __shared__ R wchi[3][ZNR];
   __shared__ R wcol[3][4][ZNR];   // dP, Kx, Ky, Kz per region cell
-  __shared__ R red[4];
+  __shared__ R red[TY];
   const Dom& D = doms[0];
   const ZGeo G = zgeo(D);
   const int N = FIELD == 0 ? D.N_U : D.N_T;
   ZCol c;
-  if (!zcol(G, blockIdx.x, zrun, c) || k % N) return;
+  if (!zcol<TY>(G, blockIdx.x, zrun, c) || k % N) return;
   const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
   const long long pl = D.plane;
   const long long kabs = D.koff + (long long)k;   // absolute base step (rounding streams)
@@ -3730,7 +3747,7 @@ __global__ __launch_bounds__(256) void k3z_scalar(const Dom* __restrict__ doms, 
   const R Tw_hi = pulled ? R(D.T_grad) * (R(G.nz - 0.5) - R(D.z_front) - R(D.V_pull) * tmid) : R(0);
   const bool own = tx < c.w && ty < c.h;
   const int gx = c.x0 + tx, gy = c.y0 + ty;
-  ZWinMap wm;
+  ZWinMap<TY> wm;
   zwin_map(G, c, tid, wm);
   ZRegMap rm;
   zreg_map(G, c, tid, rm);
@@ -3796,7 +3813,7 @@ __global__ __launch_bounds__(256) void k3z_scalar(const Dom* __restrict__ doms, 
   R amax = R(0);
   ZScalIn<R, S> in0, in1;
   {
-    ZWin<R> w0, w1, w2, w3;
+    ZWin<R, TY> w0, w1, w2, w3;
     if (var) {
       zload_win(G, wm, c.za - 2, tid, phis, w0);
       zload_win(G, wm, c.za - 1, tid, phis, w1);
@@ -3815,7 +3832,7 @@ __global__ __launch_bounds__(256) void k3z_scalar(const Dom* __restrict__ doms, 
   __syncthreads();
   collide(in0, c.za - 1);
   collide(in1, c.za);
-  ZWin<R> wn;
+  ZWin<R, TY> wn;
   if (var) zload_win(G, wm, c.za + 2, tid, phis, wn);
   zload_scal(G, rm, c.za + 1, pl, cin, jin, vel, in0);
   __syncthreads();
@@ -3881,7 +3898,11 @@ __global__ __launch_bounds__(256) void k3z_scalar(const Dom* __restrict__ doms, 
     for (int off = 32; off > 0; off >>= 1) amax = fmax(amax, __shfl_down(amax, off, 64));
     if ((tid & 63) == 0) red[tid >> 6] = amax;
     __syncthreads();
-    if (tid == 0) part[blockIdx.x].J_U = double(fmax(fmax(red[0], red[1]), fmax(red[2], red[3])));
+    if (tid == 0) {
+      R m = red[0];
+      for (int i = 1; i < TY; ++i) m = fmax(m, red[i]);
+      part[blockIdx.x].J_U = double(m);
+    }
   }
 }
 
@@ -3911,16 +3932,17 @@ __device__ __forceinline__ void zload_tr(const ZGeo& G, const ZRegMap& m, int zc
 // divergence (a neighbour beyond a wall is the boundary node, its J
 // mirrored with the normal component negated), dU and dT of Eq. (38) and
 // the injection (Eq. 39) on the current plane
-template <class R>
-__global__ __launch_bounds__(256) void k3z_transfer(const Dom* __restrict__ doms, unsigned k, int zrun,
+template <class R, int TY>
+__global__ __launch_bounds__(64 * TY) void k3z_transfer(const Dom* __restrict__ doms, unsigned k, int zrun,
                                                     Partial* __restrict__ part) {
+  constexpr int ZNR = ZRW * (TY + 2), ZNB = ZWinT<TY>::NB;   // collision region and window of a 64 x TY tile
   __shared__ R wpn[4][ZNB];
   __shared__ R wJ[3][3][ZNR];
-  __shared__ R red[4];
+  __shared__ R red[TY];
   const Dom& D = doms[0];
   const ZGeo G = zgeo(D);
   ZCol c;
-  if (!zcol(G, blockIdx.x, zrun, c) || k % D.N_phi) return;
+  if (!zcol<TY>(G, blockIdx.x, zrun, c) || k % D.N_phi) return;
   const int tid = threadIdx.x, tx = tid & 63, ty = tid >> 6;
   GLOBAL const R* pn = gp<const R>(D.phi[qb(n_phi(D, k))]);
   GLOBAL const R* po = gp<const R>(D.phi[qb(n_phi(D, k - 1))]);
@@ -3936,7 +3958,7 @@ __global__ __launch_bounds__(256) void k3z_transfer(const Dom* __restrict__ doms
   const R hrcS = kc<R>(D, K_HRCS), hrcL = kc<R>(D, K_HRCL), cT = kc<R>(D, K_CT);
   const bool own = tx < c.w && ty < c.h;
   const int gx = c.x0 + tx, gy = c.y0 + ty;
-  ZWinMap wm;
+  ZWinMap<TY> wm;
   zwin_map(G, c, tid, wm);
   ZRegMap rm;
   zreg_map(G, c, tid, rm);
@@ -3972,7 +3994,7 @@ __global__ __launch_bounds__(256) void k3z_transfer(const Dom* __restrict__ doms
   R amax = R(0);
   ZTrIn<R> in0, in1;
   if (hasU) {
-    ZWin<R> w0, w1, w2, w3;
+    ZWin<R, TY> w0, w1, w2, w3;
     zload_win(G, wm, c.za - 2, tid, pn, w0);
     zload_win(G, wm, c.za - 1, tid, pn, w1);
     zload_win(G, wm, c.za, tid, pn, w2);
@@ -3990,7 +4012,7 @@ __global__ __launch_bounds__(256) void k3z_transfer(const Dom* __restrict__ doms
     zload_tr(G, rm, c.za, po, Uin, Tin, own, in1);
   }
   ZTrIn<R> cur = in1;   // inputs of the plane being applied (own cell)
-  ZWin<R> wn;
+  ZWin<R, TY> wn;
   if (hasU) zload_win(G, wm, c.za + 2, tid, pn, wn);
   zload_tr(G, rm, c.za + 1, po, Uin, Tin, own, in0);
   __syncthreads();
@@ -4051,7 +4073,8 @@ __global__ __launch_bounds__(256) void k3z_transfer(const Dom* __restrict__ doms
     if ((tid & 63) == 0) red[tid >> 6] = amax;
     __syncthreads();
     if (tid == 0) {
-      const R m = fmax(fmax(red[0], red[1]), fmax(red[2], red[3]));
+      R m = red[0];
+      for (int i = 1; i < TY; ++i) m = fmax(m, red[i]);
       part[blockIdx.x].S_phi = double(m);
       if (!accum) part[blockIdx.x].J_U = double(m);
     }
@@ -4671,16 +4694,24 @@ struct Launch3 {
     const long long n = ncol * ((h.nz + zr - 1) / zr);
     return (unsigned)((n + 7) / 8 * 8);
   }
-  static void phase(const Dom& h, hipStream_t st, const Dom* d, unsigned k) {
-    k3z_phase<R, S><<<zblocks(h), 256, 0, st>>>(d, k, zrun(h));
+  // rows: tile rows of the phase, transfer and scalar kernels (4 or 8)
+  static void phase(const Dom& h, hipStream_t st, const Dom* d, unsigned k, int rows) {
+    if (rows == 8) k3z_phase<R, S, 8><<<zblocks(h, 8), 512, 0, st>>>(d, k, zrun(h, 8));
+    else k3z_phase<R, S, 4><<<zblocks(h, 4), 256, 0, st>>>(d, k, zrun(h, 4));
   }
-  static void transfer(const Dom& h, hipStream_t st, const Dom* d, unsigned k, Partial* p) {
-    k3z_transfer<R><<<zblocks(h), 256, 0, st>>>(d, k, zrun(h), p);
+  static void transfer(const Dom& h, hipStream_t st, const Dom* d, unsigned k, Partial* p, int rows) {
+    if (rows == 8) k3z_transfer<R, 8><<<zblocks(h, 8), 512, 0, st>>>(d, k, zrun(h, 8), p);
+    else k3z_transfer<R, 4><<<zblocks(h, 4), 256, 0, st>>>(d, k, zrun(h, 4), p);
   }
-  static void scalar(int field, const Dom& h, hipStream_t st, const Dom* d, unsigned k, Partial* p) {
+  static void scalar(int field, const Dom& h, hipStream_t st, const Dom* d, unsigned k, Partial* p, int rows) {
     // (the U transport stores its first moment in R: its storage type is R)
-    if (field == 0) k3z_scalar<R, R, 0><<<zblocks(h), 256, 0, st>>>(d, k, zrun(h), p);
-    else k3z_scalar<R, S, 1><<<zblocks(h), 256, 0, st>>>(d, k, zrun(h), p);
+    if (rows == 8) {
+      if (field == 0) k3z_scalar<R, R, 0, 8><<<zblocks(h, 8), 512, 0, st>>>(d, k, zrun(h, 8), p);
+      else k3z_scalar<R, S, 1, 8><<<zblocks(h, 8), 512, 0, st>>>(d, k, zrun(h, 8), p);
+    } else {
+      if (field == 0) k3z_scalar<R, R, 0, 4><<<zblocks(h, 4), 256, 0, st>>>(d, k, zrun(h, 4), p);
+      else k3z_scalar<R, S, 1, 4><<<zblocks(h, 4), 256, 0, st>>>(d, k, zrun(h, 4), p);
+    }
   }
   // the flow on 64 x 8 tiles (rows = 8, FP32 arithmetic: 512 threads and
   // 111 KB of LDS, one block per CU) recomputes 1.375 wave collisions per
@@ -4697,14 +4728,15 @@ struct Launch3 {
     }
     k3z_flow<R, S, 4><<<zblocks(h, 4), 256, 0, st>>>(d, k, zrun(h, 4));
   }
-  static void step(const Dom& h, hipStream_t st, const Dom* d, unsigned k, Partial* p, int rows) {
+  // rows[5]: tile rows of the phase, transfer, U, T and flow kernels
+  static void step(const Dom& h, hipStream_t st, const Dom* d, unsigned k, Partial* p, const int* rows) {
     if (k % h.N_phi == 0) {
-      phase(h, st, d, k);
-      transfer(h, st, d, k, p);
+      phase(h, st, d, k, rows[0]);
+      transfer(h, st, d, k, p, rows[1]);
     }
-    if (h.has_U && k % h.N_U == 0) scalar(0, h, st, d, k, p);
-    if (h.has_T && k % h.N_T == 0) scalar(1, h, st, d, k, p);
-    if (h.has_F && k % h.N_F == 0) flow(h, st, d, k, rows);
+    if (h.has_U && k % h.N_U == 0) scalar(0, h, st, d, k, p, rows[2]);
+    if (h.has_T && k % h.N_T == 0) scalar(1, h, st, d, k, p, rows[3]);
+    if (h.has_F && k % h.N_F == 0) flow(h, st, d, k, rows[4]);
   }
   static void init(const Dom& h, hipStream_t st, const Dom* d, const double* xi) {
     k3_init<R, S><<<blocks(h), 256, 0, st>>>(d, xi);

@@ -63,11 +63,11 @@ void nonfinite_check(int f64, int ndom, int blocks, hipStream_t st, const Dom* d
                      unsigned long long* first);
 template <class R, class S>
 struct Launch3 {
-  static void phase(const Dom& h, hipStream_t st, const Dom* d, unsigned k);
-  static void transfer(const Dom& h, hipStream_t st, const Dom* d, unsigned k, Partial* p);
-  static void scalar(int field, const Dom& h, hipStream_t st, const Dom* d, unsigned k, Partial* p);
+  static void phase(const Dom& h, hipStream_t st, const Dom* d, unsigned k, int rows);
+  static void transfer(const Dom& h, hipStream_t st, const Dom* d, unsigned k, Partial* p, int rows);
+  static void scalar(int field, const Dom& h, hipStream_t st, const Dom* d, unsigned k, Partial* p, int rows);
   static void flow(const Dom& h, hipStream_t st, const Dom* d, unsigned k, int rows);
-  static void step(const Dom& h, hipStream_t st, const Dom* d, unsigned k, Partial* p, int rows);
+  static void step(const Dom& h, hipStream_t st, const Dom* d, unsigned k, Partial* p, const int* rows);
   static void init(const Dom& h, hipStream_t st, const Dom* d, const double* xi);
   static void diag(const Dom& h, hipStream_t st, const Dom* d, long long k, Partial* p, double* front);
   static void read(const Dom& h, hipStream_t st, const Dom* d, long long k, const int* codes, int nc, int f64,
@@ -137,11 +137,11 @@ Ops make_ops() {
 }
 
 struct Ops3 {
-  void (*phase)(const Dom&, hipStream_t, const Dom*, unsigned);
-  void (*transfer)(const Dom&, hipStream_t, const Dom*, unsigned, Partial*);
-  void (*scalar)(int, const Dom&, hipStream_t, const Dom*, unsigned, Partial*);
+  void (*phase)(const Dom&, hipStream_t, const Dom*, unsigned, int);
+  void (*transfer)(const Dom&, hipStream_t, const Dom*, unsigned, Partial*, int);
+  void (*scalar)(int, const Dom&, hipStream_t, const Dom*, unsigned, Partial*, int);
   void (*flow)(const Dom&, hipStream_t, const Dom*, unsigned, int);
-  void (*step)(const Dom&, hipStream_t, const Dom*, unsigned, Partial*, int);
+  void (*step)(const Dom&, hipStream_t, const Dom*, unsigned, Partial*, const int*);
   void (*init)(const Dom&, hipStream_t, const Dom*, const double*);
   void (*diag)(const Dom&, hipStream_t, const Dom*, long long, Partial*, double*);
   void (*read)(const Dom&, hipStream_t, const Dom*, long long, const int*, int, int, void*);
@@ -231,7 +231,7 @@ struct lbm_ctx {
   bool march_pick = false; // the autotuner's choice between marching and tiles (starts as march_big)
   int queue = 0;          // marching launches: 0 autotuned, 1 per-XCD work queues, -1 static grids
   bool use_q = false;     // the marching kernels run from the work queues
-  int flow_rows = 0;      // 3D flow tile rows: 4, 8 (FP32 arithmetic), or 0 for 4
+  int rows3 = 0;          // 3D tile rows of every kernel: 4, 8, or 0 for the per-kernel defaults
   WorkQ* d_wq = nullptr;  // the queues' counters (rewound before each launch)
   int qs = 5;             // scalar lattice of the (2D) context: 5 or 9
   hipGraphExec_t gexec = nullptr;
@@ -456,9 +456,22 @@ static bool fuses_T(const lbm_ctx* c, unsigned k) {
   return k % c->g_T[0].N == 0 && k % c->g_phi[0].N == 0;
 }
 
+// 3D tile rows per kernel kind (0 phase, 1 transfer, 2 U, 3 T, 4 flow):
+// those fixed by lbm_configure, else the faster height measured on the
+// 256 x 256 x 512 directional workload (the flow's LDS window allows 8
+// rows with FP32 arithmetic only)
+// (ms per launch at 4 / 8 rows: phase 0.451 / 0.432, transfer 0.258 /
+// 0.260, U 0.467 / 0.451, T 0.349 / 0.337, flow 1.348 / 1.374)
+constexpr int kRows3Default[5] = {8, 4, 8, 8, 4};
+static int rows3(const lbm_ctx* c, int kind) {
+  const int r = c->rows3 != 0 ? c->rows3 : kRows3Default[kind];
+  return kind == 4 && c->storage == LBM_STORE_F64 ? 4 : r;
+}
+
 static void launch_step(lbm_ctx* c, hipStream_t st, unsigned k, bool last = false) {
   if (c->dim == 3) {
-    c->ops3.step(c->H[0], st, c->d_dom, k, c->s.part, c->flow_rows);
+    const int rows[5] = {rows3(c, 0), rows3(c, 1), rows3(c, 2), rows3(c, 3), rows3(c, 4)};
+    c->ops3.step(c->H[0], st, c->d_dom, k, c->s.part, rows);
     return;
   }
   const int ti = c->ty_index, TY = kTYs[ti];
@@ -1142,12 +1155,16 @@ lbm_status lbm_init_front(lbm_ctx* c, int32_t dom, const double* xi) {
 
 lbm_status lbm_configure(lbm_ctx* c, int32_t tile_rows, int32_t flags) {
   if (!c) return LBM_EINVAL;
-  if (c->dim == 3) {   // 3D: rows of the flow kernel's tiles
+  if (c->dim == 3) {   // 3D: rows of the stencil kernels' 64-wide tiles
     if (tile_rows != 0 && tile_rows != 4 && tile_rows != 8)
       return fail(c, LBM_EINVAL, "3D tile_rows must be 0, 4 or 8");
-    if (tile_rows == 8 && c->storage == LBM_STORE_F64)
-      return fail(c, LBM_EINVAL, "3D flow tiles of 8 rows need FP32 arithmetic");
-    c->flow_rows = tile_rows;
+    if (tile_rows != c->rows3) {
+      // fewer blocks at other heights: the transfer and U partials of the
+      // blocks that no longer exist must not linger in the reductions
+      HIPCHK(c, hipStreamSynchronize(c->stream));
+      HIPCHK(c, hipMemset(c->ws_s.part, 0, sizeof(Partial) * (size_t)c->nparts));
+    }
+    c->rows3 = tile_rows;
   } else if (tile_rows == 0) {
     c->autotune = true;
     c->tuned = false;
@@ -1185,7 +1202,7 @@ int32_t lbm_marching(const lbm_ctx* c) { return c ? (use_march(c) ? 1 : 0) : -1;
 
 int32_t lbm_tile_rows(const lbm_ctx* c) {
   if (!c) return -1;
-  if (c->dim == 3) return c->flow_rows == 8 ? 8 : 4;
+  if (c->dim == 3) return c->rows3;
   if (c->autotune && !c->tuned) return 0;
   return kTYs[c->ty_index];
 }
@@ -1222,11 +1239,11 @@ lbm_status lbm_kernel_times(lbm_ctx* c, int32_t reps, double* ms_out, double* pe
       auto launch = [&]() {
         if (c->dim == 3) {
           const Dom& h = c->H[0];
-          if (kind == 0) c->ops3.phase(h, c->stream, c->d_dom, k);
-          if (kind == 1) c->ops3.transfer(h, c->stream, c->d_dom, k, c->s.part);
-          if (kind == 2) c->ops3.scalar(0, h, c->stream, c->d_dom, k, c->s.part);
-          if (kind == 3) c->ops3.scalar(1, h, c->stream, c->d_dom, k, c->s.part);
-          if (kind == 4) c->ops3.flow(h, c->stream, c->d_dom, k, c->flow_rows);
+          if (kind == 0) c->ops3.phase(h, c->stream, c->d_dom, k, rows3(c, 0));
+          if (kind == 1) c->ops3.transfer(h, c->stream, c->d_dom, k, c->s.part, rows3(c, 1));
+          if (kind == 2) c->ops3.scalar(0, h, c->stream, c->d_dom, k, c->s.part, rows3(c, 2));
+          if (kind == 3) c->ops3.scalar(1, h, c->stream, c->d_dom, k, c->s.part, rows3(c, 3));
+          if (kind == 4) c->ops3.flow(h, c->stream, c->d_dom, k, rows3(c, 4));
           return;
         }
         if (kind == 0 && fused) {

@@ -268,7 +268,8 @@ class Simulation:
     @property
     def tile_rows(self) -> int:
         """Tile height of the 2D tiled kernels in use (0 before the
-        autotuner has run); in 3D the rows of the flow kernel's tiles."""
+        autotuner has run); in 3D the rows fixed by ``configure`` (0: the
+        per-kernel defaults)."""
         return int(self.lib.lbm_tile_rows(self.ctx))
 
     def _layout(self, names, domain=0):

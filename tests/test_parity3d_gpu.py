@@ -112,30 +112,34 @@ def test_3d_transport_T_accumulated_walls_fp64():
         oracle.diag.totals(dom)["enthalpy"])
 
 
-def test_3d_periodic_z_ragged_tiles_fp64():
+@pytest.mark.parametrize("rows", [4, 8])
+def test_3d_periodic_z_ragged_tiles_fp64(rows):
     """Periodic in all three directions, transported T with phi-dependent
     properties, on 70 x 9 x 21: ragged tiles in x (70 = 64 + 6) and y
-    (9 = 2 x 4 + 1), and z runs that wrap around the periodic boundary."""
+    (9 = 2 x 4 + 1 = 8 + 1), and z runs that wrap around the periodic
+    boundary; tiles of 4 and 8 rows."""
     wl = _directional(70, 9, 21)
     d = wl["domains"][0]
     d.update(T_mode="transport", T0=d["T0"] - 0.02, kappa_S=2 * d["kappa_L"], rhoCp_S=1.2 * d["rhoCp_L"],
              N_U=1, N_T=2, N_F=2, bc=("periodic", "periodic", "periodic"),
              flow_bc=("periodic", "periodic", "periodic"), D_L=0.05, D_S=5e-4)
     names = ("phi", "U", "T", "rho", "vel", "jU", "jT", "f_phi")
-    _say("case 3d periodic xyz ragged 70x9x21 fp64 36 steps")
-    got, diag = _run(wl, 36, names)
+    _say(f"case 3d periodic xyz ragged 70x9x21 fp64 36 steps, {rows}-row tiles")
+    got, diag = _run(wl, 36, names, rows=rows)
     dom = oracle.run(d, 36)
     _compare("3d periodic", got, _ref(dom, names), TOL64)
     assert diag["nonfinite"] == 0
 
 
-@pytest.mark.parametrize("storage", ["f32", "bf16"])
-def test_3d_flow_tile_heights_are_bitwise_identical(storage):
-    """With FP32 arithmetic the flow may run on 64 x 8 tiles instead of the
-    default 64 x 4; both give the same bits (the ring collisions are the
-    same expressions), on a driven flow with ragged tiles in x and y (70 x 9:
-    9 = 8 + 1 = 2 x 4 + 1), periodic in every direction, and on walls normal
-    to x and z (24 x 20: 20 = 2 x 8 + 4), graph and direct launches."""
+@pytest.mark.parametrize("storage", ["f64", "f32", "bf16"])
+def test_3d_tile_heights_are_bitwise_identical(storage):
+    """The 3D stencil kernels may run on 64 x 8 tiles (512 threads) or
+    64 x 4 (the flow on 8 rows only with FP32 arithmetic), or on the
+    per-kernel defaults; all give the same bits (the ring collisions are the
+    same expressions), on a driven flow with
+    ragged tiles in x and y (70 x 9: 9 = 8 + 1 = 2 x 4 + 1), periodic in
+    every direction, and on walls normal to x and z (24 x 20: 20 = 2 x 8 +
+    4), graph and direct launches."""
     from paper_2609_25670_amd import simulation_for
 
     cases = []
@@ -152,17 +156,18 @@ def test_3d_flow_tile_heights_are_bitwise_identical(storage):
     names = ("phi", "U", "T", "rho", "vel", "f_F")
     for label, wl in cases:
         res = {}
-        for rows, g in ((8, True), (4, True), (8, False)):
+        for rows, g in ((8, True), (4, True), (8, False), (0, True)):
             _say(f"case 3d flow tiles {label} {storage} rows={rows} graph={g}")
             res[(rows, g)], _ = _run(wl, 40, names, storage=storage, use_graph=g, rows=rows)
         sim = simulation_for(wl, storage=storage)
-        assert sim.tile_rows == 4
+        assert sim.tile_rows == 0
         sim.configure(8, True)
         assert sim.tile_rows == 8
         sim.close()
         for n in names:
             assert np.array_equal(res[(8, True)][n], res[(4, True)][n]), (label, n)
             assert np.array_equal(res[(8, True)][n], res[(8, False)][n]), (label, n)
+            assert np.array_equal(res[(8, True)][n], res[(0, True)][n]), (label, n)
         assert float(np.max(np.abs(res[(8, True)]["vel"]))) > 0
 
 
