@@ -119,11 +119,23 @@ def cycle_of(wl: dict) -> int:
     return L
 
 
+def counters_key(kernel: str) -> str:
+    """File key of a kernel's counter summary: its name, and for the scalar
+    transports the field (template argument 0: U, 1: T), whether given in
+    full (``lbm::k3z_scalar<float, float, 0, 8>``) or short
+    (``k3z_scalar<..., 0>``)."""
+    base = kernel.split("<")[0].split("::")[-1]
+    if base in ("k_scalar", "k_scalar_ym", "k_scalar_ym_q", "k3z_scalar") and "<" in kernel:
+        args = [a.strip() for a in kernel.split("<", 1)[1].rstrip(">").split(",")]
+        field = args[2] if len(args) >= 3 and args[1] != "..." else args[-1]
+        base += "_U" if field == "0" else "_T"
+    return base
+
+
 def traffic_from_profiles(workload: str, kernel: str, sha: str):
     """HBM bytes per launch of a kernel from the committed rocprofv3 counter
     summary, if it was taken on the current kernel source; else None."""
-    name = kernel.split("<")[0]
-    path = os.path.join(ROOT, "profiles", f"counters_{name}_{workload}.json")
+    path = os.path.join(ROOT, "profiles", f"counters_{counters_key(kernel)}_{workload}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -322,6 +334,11 @@ def directional_run(args) -> int:
     return 0
 
 
+def _progress(msg: str) -> None:
+    """A progress line on stderr (the JSON result alone goes to stdout)."""
+    print(f"bench.py: {msg}", file=sys.stderr, flush=True)
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -400,6 +417,7 @@ def main() -> int:
         print(json.dumps(dict(profile_steps=args.profile_steps, workload=wl["name"], storage=storage)), flush=True)
         return 0
     m = measure(sim, wl, storage, args.steps, args.warmup)
+    _progress(f"measured {wl['name']}: {m['mlups']:.0f} MLUPS")
     finite = m["finite"]
     d0 = wl["domains"][0]
     sha = kernel_source_sha()
@@ -445,6 +463,7 @@ def main() -> int:
         hw = L.workload(SIDE_WORKLOAD)
         hsim = simulation_for(hw, storage=hw["storage"])
         hm = measure(hsim, hw, hw["storage"], 3, 1)
+        _progress(f"measured {hw['name']}: {hm['mlups']:.0f} MLUPS")
         finite = finite and hm["finite"]
         result["batched_workload"] = {
             "workload": hw["name"],
@@ -466,7 +485,9 @@ def main() -> int:
         ncpu = host_cpus()
         procs = max(1, min(ncpu, args.cpu_procs))
         one = cpu_baseline(args.workload, args.cpu_steps, 1)
+        _progress(f"cpu baseline, one process: {one['mlups']:.2f} MLUPS")
         allc = cpu_baseline(args.workload, args.cpu_steps, procs)
+        _progress(f"cpu baseline, {procs} processes: {allc['mlups']:.2f} MLUPS")
         result["cpu_baseline"] = {
             "value": round(allc["mlups"], 4),
             "unit": "MLUPS",

@@ -4681,62 +4681,69 @@ struct Launch3 {
     const long long cols = (long long)((h.nx + 63) / 64) * ((h.ny + 3) / 4);
     return (unsigned)((cols + 7) / 8 * 8 * h.nz);
   }
-  // z-marching launches: runs of zrun planes, enough (column, run) pairs
-  // for about 2048 blocks of 256 threads (1024 of 512 threads)
-  static int zrun(const Dom& h, int ty = ZTY) {
+  // z-marching launches of 64 x ty tiles: runs of zrun planes, enough
+  // (column, run) pairs for about zblk blocks of 256 threads (zblk / 2 of
+  // 512), runs of at least 8 planes
+  static int zrun(const Dom& h, int ty, int zblk) {
     const int ncol = ((h.nx + ZTX - 1) / ZTX) * ((h.ny + ty - 1) / ty);
-    const int nrun = std::max(1, std::min((2048 * ZTY / ty + ncol - 1) / ncol, (h.nz + 7) / 8));
+    const int nrun = std::max(1, std::min((zblk * ZTY / ty + ncol - 1) / ncol, (h.nz + 7) / 8));
     return (h.nz + nrun - 1) / nrun;
   }
-  static unsigned zblocks(const Dom& h, int ty = ZTY) {
+  static unsigned zblocks(const Dom& h, int ty, int zblk) {
     const long long ncol = (long long)((h.nx + ZTX - 1) / ZTX) * ((h.ny + ty - 1) / ty);
-    const int zr = zrun(h, ty);
+    const int zr = zrun(h, ty, zblk);
     const long long n = ncol * ((h.nz + zr - 1) / zr);
     return (unsigned)((n + 7) / 8 * 8);
   }
-  // rows: tile rows of the phase, transfer and scalar kernels (4 or 8)
-  static void phase(const Dom& h, hipStream_t st, const Dom* d, unsigned k, int rows) {
-    if (rows == 8) k3z_phase<R, S, 8><<<zblocks(h, 8), 512, 0, st>>>(d, k, zrun(h, 8));
-    else k3z_phase<R, S, 4><<<zblocks(h, 4), 256, 0, st>>>(d, k, zrun(h, 4));
+  // rows: tile rows (4 or 8); zblk: the block count the z runs aim at
+  static void phase(const Dom& h, hipStream_t st, const Dom* d, unsigned k, int rows, int zblk) {
+    if (rows == 8) k3z_phase<R, S, 8><<<zblocks(h, 8, zblk), 512, 0, st>>>(d, k, zrun(h, 8, zblk));
+    else k3z_phase<R, S, 4><<<zblocks(h, 4, zblk), 256, 0, st>>>(d, k, zrun(h, 4, zblk));
   }
-  static void transfer(const Dom& h, hipStream_t st, const Dom* d, unsigned k, Partial* p, int rows) {
-    if (rows == 8) k3z_transfer<R, 8><<<zblocks(h, 8), 512, 0, st>>>(d, k, zrun(h, 8), p);
-    else k3z_transfer<R, 4><<<zblocks(h, 4), 256, 0, st>>>(d, k, zrun(h, 4), p);
+  static void transfer(const Dom& h, hipStream_t st, const Dom* d, unsigned k, Partial* p, int rows, int zblk) {
+    if (rows == 8) k3z_transfer<R, 8><<<zblocks(h, 8, zblk), 512, 0, st>>>(d, k, zrun(h, 8, zblk), p);
+    else k3z_transfer<R, 4><<<zblocks(h, 4, zblk), 256, 0, st>>>(d, k, zrun(h, 4, zblk), p);
   }
-  static void scalar(int field, const Dom& h, hipStream_t st, const Dom* d, unsigned k, Partial* p, int rows) {
+  static void scalar(int field, const Dom& h, hipStream_t st, const Dom* d, unsigned k, Partial* p, int rows,
+                     int zblk) {
     // (the U transport stores its first moment in R: its storage type is R)
     if (rows == 8) {
-      if (field == 0) k3z_scalar<R, R, 0, 8><<<zblocks(h, 8), 512, 0, st>>>(d, k, zrun(h, 8), p);
-      else k3z_scalar<R, S, 1, 8><<<zblocks(h, 8), 512, 0, st>>>(d, k, zrun(h, 8), p);
+      const unsigned g = zblocks(h, 8, zblk);
+      const int zr = zrun(h, 8, zblk);
+      if (field == 0) k3z_scalar<R, R, 0, 8><<<g, 512, 0, st>>>(d, k, zr, p);
+      else k3z_scalar<R, S, 1, 8><<<g, 512, 0, st>>>(d, k, zr, p);
     } else {
-      if (field == 0) k3z_scalar<R, R, 0, 4><<<zblocks(h, 4), 256, 0, st>>>(d, k, zrun(h, 4), p);
-      else k3z_scalar<R, S, 1, 4><<<zblocks(h, 4), 256, 0, st>>>(d, k, zrun(h, 4), p);
+      const unsigned g = zblocks(h, 4, zblk);
+      const int zr = zrun(h, 4, zblk);
+      if (field == 0) k3z_scalar<R, R, 0, 4><<<g, 256, 0, st>>>(d, k, zr, p);
+      else k3z_scalar<R, S, 1, 4><<<g, 256, 0, st>>>(d, k, zr, p);
     }
   }
   // the flow on 64 x 8 tiles (rows = 8, FP32 arithmetic: 512 threads and
   // 111 KB of LDS, one block per CU) recomputes 1.375 wave collisions per
-  // site against 1.75 at 64 x 4, but its barriers then stall the whole CU:
-  // 1.375 against 1.347 ms per launch on 256 x 256 x 512, so 64 x 4 is the
-  // default.  In FP64 the LDS window (133 KB at 64 x 4) leaves no room for
-  // taller tiles.  Both heights give the same bits.
-  static void flow(const Dom& h, hipStream_t st, const Dom* d, unsigned k, int rows) {
+  // site against 1.75 at 64 x 4, but its barriers then stall the whole CU.
+  // In FP64 the LDS window (133 KB at 64 x 4) leaves no room for taller
+  // tiles.  Both heights give the same bits.
+  static void flow(const Dom& h, hipStream_t st, const Dom* d, unsigned k, int rows, int zblk) {
     if constexpr (sizeof(R) == 4) {
       if (rows == 8) {
-        k3z_flow<R, S, 8><<<zblocks(h, 8), 512, 0, st>>>(d, k, zrun(h, 8));
+        k3z_flow<R, S, 8><<<zblocks(h, 8, zblk), 512, 0, st>>>(d, k, zrun(h, 8, zblk));
         return;
       }
     }
-    k3z_flow<R, S, 4><<<zblocks(h, 4), 256, 0, st>>>(d, k, zrun(h, 4));
+    k3z_flow<R, S, 4><<<zblocks(h, 4, zblk), 256, 0, st>>>(d, k, zrun(h, 4, zblk));
   }
-  // rows[5]: tile rows of the phase, transfer, U, T and flow kernels
-  static void step(const Dom& h, hipStream_t st, const Dom* d, unsigned k, Partial* p, const int* rows) {
+  // rows[5], zblk[5]: tile rows and block targets of the phase, transfer,
+  // U, T and flow kernels
+  static void step(const Dom& h, hipStream_t st, const Dom* d, unsigned k, Partial* p, const int* rows,
+                   const int* zblk) {
     if (k % h.N_phi == 0) {
-      phase(h, st, d, k, rows[0]);
-      transfer(h, st, d, k, p, rows[1]);
+      phase(h, st, d, k, rows[0], zblk[0]);
+      transfer(h, st, d, k, p, rows[1], zblk[1]);
     }
-    if (h.has_U && k % h.N_U == 0) scalar(0, h, st, d, k, p, rows[2]);
-    if (h.has_T && k % h.N_T == 0) scalar(1, h, st, d, k, p, rows[3]);
-    if (h.has_F && k % h.N_F == 0) flow(h, st, d, k, rows[4]);
+    if (h.has_U && k % h.N_U == 0) scalar(0, h, st, d, k, p, rows[2], zblk[2]);
+    if (h.has_T && k % h.N_T == 0) scalar(1, h, st, d, k, p, rows[3], zblk[3]);
+    if (h.has_F && k % h.N_F == 0) flow(h, st, d, k, rows[4], zblk[4]);
   }
   static void init(const Dom& h, hipStream_t st, const Dom* d, const double* xi) {
     k3_init<R, S><<<blocks(h), 256, 0, st>>>(d, xi);

@@ -63,11 +63,13 @@ void nonfinite_check(int f64, int ndom, int blocks, hipStream_t st, const Dom* d
                      unsigned long long* first);
 template <class R, class S>
 struct Launch3 {
-  static void phase(const Dom& h, hipStream_t st, const Dom* d, unsigned k, int rows);
-  static void transfer(const Dom& h, hipStream_t st, const Dom* d, unsigned k, Partial* p, int rows);
-  static void scalar(int field, const Dom& h, hipStream_t st, const Dom* d, unsigned k, Partial* p, int rows);
-  static void flow(const Dom& h, hipStream_t st, const Dom* d, unsigned k, int rows);
-  static void step(const Dom& h, hipStream_t st, const Dom* d, unsigned k, Partial* p, const int* rows);
+  static void phase(const Dom& h, hipStream_t st, const Dom* d, unsigned k, int rows, int zblk);
+  static void transfer(const Dom& h, hipStream_t st, const Dom* d, unsigned k, Partial* p, int rows, int zblk);
+  static void scalar(int field, const Dom& h, hipStream_t st, const Dom* d, unsigned k, Partial* p, int rows,
+                     int zblk);
+  static void flow(const Dom& h, hipStream_t st, const Dom* d, unsigned k, int rows, int zblk);
+  static void step(const Dom& h, hipStream_t st, const Dom* d, unsigned k, Partial* p, const int* rows,
+                   const int* zblk);
   static void init(const Dom& h, hipStream_t st, const Dom* d, const double* xi);
   static void diag(const Dom& h, hipStream_t st, const Dom* d, long long k, Partial* p, double* front);
   static void read(const Dom& h, hipStream_t st, const Dom* d, long long k, const int* codes, int nc, int f64,
@@ -137,11 +139,11 @@ Ops make_ops() {
 }
 
 struct Ops3 {
-  void (*phase)(const Dom&, hipStream_t, const Dom*, unsigned, int);
-  void (*transfer)(const Dom&, hipStream_t, const Dom*, unsigned, Partial*, int);
-  void (*scalar)(int, const Dom&, hipStream_t, const Dom*, unsigned, Partial*, int);
-  void (*flow)(const Dom&, hipStream_t, const Dom*, unsigned, int);
-  void (*step)(const Dom&, hipStream_t, const Dom*, unsigned, Partial*, const int*);
+  void (*phase)(const Dom&, hipStream_t, const Dom*, unsigned, int, int);
+  void (*transfer)(const Dom&, hipStream_t, const Dom*, unsigned, Partial*, int, int);
+  void (*scalar)(int, const Dom&, hipStream_t, const Dom*, unsigned, Partial*, int, int);
+  void (*flow)(const Dom&, hipStream_t, const Dom*, unsigned, int, int);
+  void (*step)(const Dom&, hipStream_t, const Dom*, unsigned, Partial*, const int*, const int*);
   void (*init)(const Dom&, hipStream_t, const Dom*, const double*);
   void (*diag)(const Dom&, hipStream_t, const Dom*, long long, Partial*, double*);
   void (*read)(const Dom&, hipStream_t, const Dom*, long long, const int*, int, int, void*);
@@ -463,6 +465,13 @@ static bool fuses_T(const lbm_ctx* c, unsigned k) {
 // (ms per launch at 4 / 8 rows: phase 0.451 / 0.432, transfer 0.258 /
 // 0.260, U 0.467 / 0.451, T 0.349 / 0.337, flow 1.348 / 1.374)
 constexpr int kRows3Default[5] = {8, 4, 8, 8, 4};
+// z-run lengths: each kernel's runs aim at this many blocks of 256 threads
+// (half as many of 512), the fastest of 512 ... 8192 on the same workload
+// (ms per launch at 1024 / 2048 / 4096 / 8192: phase 0.409 / 0.427 /
+// 0.441 / 0.463, transfer 0.277 / 0.261 / 0.228 / 0.229, U 0.472 / 0.450 /
+// 0.410 / 0.414, T 0.343 / 0.337 / 0.290 / 0.283, flow 1.281 / 1.300 /
+// 1.341 / 1.412)
+constexpr int kZBlocks3[5] = {1024, 4096, 4096, 8192, 1024};
 static int rows3(const lbm_ctx* c, int kind) {
   const int r = c->rows3 != 0 ? c->rows3 : kRows3Default[kind];
   return kind == 4 && c->storage == LBM_STORE_F64 ? 4 : r;
@@ -471,7 +480,7 @@ static int rows3(const lbm_ctx* c, int kind) {
 static void launch_step(lbm_ctx* c, hipStream_t st, unsigned k, bool last = false) {
   if (c->dim == 3) {
     const int rows[5] = {rows3(c, 0), rows3(c, 1), rows3(c, 2), rows3(c, 3), rows3(c, 4)};
-    c->ops3.step(c->H[0], st, c->d_dom, k, c->s.part, rows);
+    c->ops3.step(c->H[0], st, c->d_dom, k, c->s.part, rows, kZBlocks3);
     return;
   }
   const int ti = c->ty_index, TY = kTYs[ti];
@@ -1239,11 +1248,11 @@ lbm_status lbm_kernel_times(lbm_ctx* c, int32_t reps, double* ms_out, double* pe
       auto launch = [&]() {
         if (c->dim == 3) {
           const Dom& h = c->H[0];
-          if (kind == 0) c->ops3.phase(h, c->stream, c->d_dom, k, rows3(c, 0));
-          if (kind == 1) c->ops3.transfer(h, c->stream, c->d_dom, k, c->s.part, rows3(c, 1));
-          if (kind == 2) c->ops3.scalar(0, h, c->stream, c->d_dom, k, c->s.part, rows3(c, 2));
-          if (kind == 3) c->ops3.scalar(1, h, c->stream, c->d_dom, k, c->s.part, rows3(c, 3));
-          if (kind == 4) c->ops3.flow(h, c->stream, c->d_dom, k, rows3(c, 4));
+          if (kind == 0) c->ops3.phase(h, c->stream, c->d_dom, k, rows3(c, 0), kZBlocks3[0]);
+          if (kind == 1) c->ops3.transfer(h, c->stream, c->d_dom, k, c->s.part, rows3(c, 1), kZBlocks3[1]);
+          if (kind == 2) c->ops3.scalar(0, h, c->stream, c->d_dom, k, c->s.part, rows3(c, 2), kZBlocks3[2]);
+          if (kind == 3) c->ops3.scalar(1, h, c->stream, c->d_dom, k, c->s.part, rows3(c, 3), kZBlocks3[3]);
+          if (kind == 4) c->ops3.flow(h, c->stream, c->d_dom, k, rows3(c, 4), kZBlocks3[4]);
           return;
         }
         if (kind == 0 && fused) {
