@@ -2464,7 +2464,9 @@ __device__ __forceinline__ void k_tr_scalar_ym_run(const Dom* __restrict__ doms,
     }
   };
   // J of rows r0 .. r0 + 3 (phi^{q+1} rows r0 - 1 .. r0 + 4 in LDS), as the
-  // marching transfer computes it
+  // marching transfer computes it; the gradient of each cell is kept for
+  // the T collision of the same cells (the same stencil on the same rows)
+  R gsx[2], gsy[2];
   auto flux = [&](const YTsIn<R, S>& in, int r0) {
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
@@ -2479,6 +2481,8 @@ __device__ __forceinline__ void k_tr_scalar_ym_run(const Dom* __restrict__ doms,
       const int bcol = rx - (x0 - 2);   // window column of the (boundary) node
       R gxv, gyv;
       iso_grad_rows(wphi[(ry - 1) & 7], wphi[ry & 7], wphi[(ry + 1) & 7], bcol, gxv, gyv);
+      gsx[i] = gxv;   // at a collision cell (inside the domain) the T collision's grad phi*
+      gsy[i] = gyv;
       const R gg = gxv * gxv + gyv * gyv;
       R Jx = R(0), Jy = R(0);
       if (gg >= R(GRAD_EPS2)) {
@@ -2517,7 +2521,12 @@ __device__ __forceinline__ void k_tr_scalar_ym_run(const Dom* __restrict__ doms,
         itau = rcp(R(3) * dt * coeff + R(0.5));
         const R gcx = -R(3) * itau * (jxv - jex), gcy = -R(3) * itau * (jyv - jey);
         R gpx, gpy;
-        iso_grad_rows(wphi[(row - 1) & 7], r0p, wphi[(row + 1) & 7], col + 1, gpx, gpy);
+        if (hasU) {   // computed with J (the cell is inside the domain: no clamp)
+          gpx = gsx[i];
+          gpy = gsy[i];
+        } else {
+          iso_grad_rows(wphi[(row - 1) & 7], r0p, wphi[(row + 1) & 7], col + 1, gpx, gpy);
+        }
         Qs = (hrcS - hrcL) * irc * coeff * (gcx * gpx + gcy * gpy);               // Eq. (12), 1st term
       } else {
         itau = itau_const;
