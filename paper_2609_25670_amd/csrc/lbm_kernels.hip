@@ -4730,8 +4730,8 @@ struct Launch3 {
   }
   // the flow on 64 x 8 tiles (rows = 8, FP32 arithmetic: 512 threads and
   // 111 KB of LDS, one block per CU) recomputes 1.375 wave collisions per
-  // site against 1.75 at 64 x 4, but its barriers then stall the whole CU.
-  // In FP64 the LDS window (133 KB at 64 x 4) leaves no room for taller
+  // site against 1.75 at 64 x 4, and its barriers then stall the whole CU;
+  // in FP64 the LDS window (133 KB at 64 x 4) leaves no room for taller
   // tiles.  Both heights give the same bits.
   static void flow(const Dom& h, hipStream_t st, const Dom* d, unsigned k, int rows, int zblk) {
     if constexpr (sizeof(R) == 4) {

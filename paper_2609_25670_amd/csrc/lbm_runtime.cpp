@@ -459,12 +459,13 @@ static bool fuses_T(const lbm_ctx* c, unsigned k) {
 }
 
 // 3D tile rows per kernel kind (0 phase, 1 transfer, 2 U, 3 T, 4 flow):
-// those fixed by lbm_configure, else the faster height measured on the
+// those fixed by lbm_configure, else the height measured best on the
 // 256 x 256 x 512 directional workload (the flow's LDS window allows 8
-// rows with FP32 arithmetic only)
-// (ms per launch at 4 / 8 rows: phase 0.451 / 0.432, transfer 0.258 /
-// 0.260, U 0.467 / 0.451, T 0.349 / 0.337, flow 1.348 / 1.374)
-constexpr int kRows3Default[5] = {8, 4, 8, 8, 4};
+// rows with FP32 arithmetic only).  ms per launch at 4 / 8 rows, with the
+// z runs below: phase 0.436 / 0.408, transfer 0.227 / 0.230, U 0.476 /
+// 0.411, T 0.338 / 0.284, flow 1.282 / 1.284 (the flow's HBM reads 76 /
+// 46 B per site: at equal time the taller tiles re-read less)
+constexpr int kRows3Default[5] = {8, 4, 8, 8, 8};
 // z-run lengths: each kernel's runs aim at this many blocks of 256 threads
 // (half as many of 512), the fastest of 512 ... 8192 on the same workload
 // (ms per launch at 1024 / 2048 / 4096 / 8192: phase 0.409 / 0.427 /
