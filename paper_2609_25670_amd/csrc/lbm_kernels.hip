@@ -3552,6 +3552,9 @@ __global__ __launch_bounds__(64 * TY) void k3z_phase(const Dom* __restrict__ dom
   // upstream neighbours of the own site in x and y (false: beyond a wall)
   const bool upx[2] = {resolve(gx - 1, G.nx, G.bcx) >= 0, resolve(gx + 1, G.nx, G.bcx) >= 0};
   const bool upy[2] = {resolve(gy - 1, G.ny, G.bcy) >= 0, resolve(gy + 1, G.ny, G.bcy) >= 0};
+  // whether the block's column touches a wall in x or y
+  const bool edge_blk = (G.bcx != BC_PER && (c.x0 == 0 || c.x0 + c.w >= G.nx)) ||
+                        (G.bcy != BC_PER && (c.y0 == 0 || c.y0 + c.h >= G.ny));
 
   // collide plane zc on the region from its loaded inputs and the window
   // planes zc - 1, zc, zc + 1; the own site's A and deviations are returned
@@ -3626,42 +3629,49 @@ __global__ __launch_bounds__(64 * TY) void k3z_phase(const Dom* __restrict__ dom
     __syncthreads();
     collide(cur, z + 1, An, svn);   // the plane above: its halo for this plane
     __syncthreads();
-    if (own) {
-      // anisotropic pull streaming (Eq. 26) in deviations from w_i phi(y)
-      const int cr = (ty + 1) * ZRW + tx + 1, cb = (ty + 2) * ZBW + tx + 2;
-      const R* c1 = &wcol[zslot3(z)][0][0];
-      const R py = wphi[zslot4(z)][cb];
-      const R dPy = c1[cr], Ky[3] = {c1[ZNR + cr], c1[2 * ZNR + cr], c1[3 * ZNR + cr]};
-      const R A = Ac, iA = rcp(A), oA = R(1) - A;
-      const bool upz[2] = {resolve(z - 1, G.nz, G.bcz) >= 0, resolve(z + 1, G.nz, G.bcz) >= 0};
-      R s0 = R(0);
+    // the streaming of a plane that touches no wall (uniform over the
+    // block) takes every neighbour from the windows
+    auto stream_plane = [&](auto edge_c) {
+      constexpr bool EDGE = decltype(edge_c)::value;
+      if (own) {
+        // anisotropic pull streaming (Eq. 26) in deviations from w_i phi(y)
+        const int cr = (ty + 1) * ZRW + tx + 1, cb = (ty + 2) * ZBW + tx + 2;
+        const R* c1 = &wcol[zslot3(z)][0][0];
+        const R py = wphi[zslot4(z)][cb];
+        const R dPy = c1[cr], Ky[3] = {c1[ZNR + cr], c1[2 * ZNR + cr], c1[3 * ZNR + cr]};
+        const R A = Ac, iA = rcp(A), oA = R(1) - A;
+        const bool upz[2] = {resolve(z - 1, G.nz, G.bcz) >= 0, resolve(z + 1, G.nz, G.bcz) >= 0};
+        R s0 = R(0);
 #pragma unroll
-      for (int q = 0; q < 6; ++q) s0 -= svc[q];
-      R dn[7], sum;
-      dn[0] = (dPy * R(0.25) - oA * s0) * iA;
-      sum = dn[0];
+        for (int q = 0; q < 6; ++q) s0 -= svc[q];
+        R dn[7], sum;
+        dn[0] = (dPy * R(0.25) - oA * s0) * iA;
+        sum = dn[0];
 #pragma unroll
-      for (int q = 1; q < 7; ++q) {
-        const int ex = e19(q, 0), ey = e19(q, 1), ez = e19(q, 2);
-        const bool up = ex > 0 ? upx[0] : ex < 0 ? upx[1] : ey > 0 ? upy[0] : ey < 0 ? upy[1] : ez > 0 ? upz[0] : upz[1];
-        R dpost;
-        if (up) {
-          const R* cu = &wcol[zslot3(z - ez)][0][0];
-          const int ur = cr - ey * ZRW - ex;
-          const R Ke = edot3(ex, ey, ez, cu[ZNR + ur], cu[2 * ZNR + ur], cu[3 * ZNR + ur]);
-          dpost = (wphi[zslot4(z - ez)][cb - ey * ZBW - ex] - py + cu[ur]) * R(0.125) + R(0.5) * Ke;
-        } else {
-          dpost = dPy * R(0.125) - R(0.5) * edot3(ex, ey, ez, Ky[0], Ky[1], Ky[2]);
+        for (int q = 1; q < 7; ++q) {
+          const int ex = e19(q, 0), ey = e19(q, 1), ez = e19(q, 2);
+          const bool up = !EDGE || (ex > 0 ? upx[0] : ex < 0 ? upx[1] : ey > 0 ? upy[0] : ey < 0 ? upy[1] : ez > 0 ? upz[0] : upz[1]);
+          R dpost;
+          if (up) {
+            const R* cu = &wcol[zslot3(z - ez)][0][0];
+            const int ur = cr - ey * ZRW - ex;
+            const R Ke = edot3(ex, ey, ez, cu[ZNR + ur], cu[2 * ZNR + ur], cu[3 * ZNR + ur]);
+            dpost = (wphi[zslot4(z - ez)][cb - ey * ZBW - ex] - py + cu[ur]) * R(0.125) + R(0.5) * Ke;
+          } else {
+            dpost = dPy * R(0.125) - R(0.5) * edot3(ex, ey, ez, Ky[0], Ky[1], Ky[2]);
+          }
+          dn[q] = (dpost - oA * svc[q - 1]) * iA;
+          sum += dn[q];
         }
-        dn[q] = (dpost - oA * svc[q - 1]) * iA;
-        sum += dn[q];
-      }
-      const unsigned o = zoff(G, gx, gy, z);
-      sto(phi_out, o, py + sum);
-      SRStream rs = sr_stream(o, kabs, 0x243f6a88u);
+        const unsigned o = zoff(G, gx, gy, z);
+        sto(phi_out, o, py + sum);
+        SRStream rs = sr_stream(o, kabs, 0x243f6a88u);
 #pragma unroll
-      for (int q = 1; q < 7; ++q) sto_sr(plane(s_out, (q - 1) * pl), o, dn[q] - R(0.125) * sum, rs);
-    }
+        for (int q = 1; q < 7; ++q) sto_sr(plane(s_out, (q - 1) * pl), o, dn[q] - R(0.125) * sum, rs);
+      }
+    };
+    if (edge_blk || (G.bcz != BC_PER && (z == 0 || z == G.nz - 1))) stream_plane(std::true_type{});
+    else stream_plane(std::false_type{});
     __syncthreads();
   };
   for (int z = c.za; z < c.zb; z += 2) {
@@ -3762,6 +3772,9 @@ __global__ __launch_bounds__(64 * TY) void k3z_scalar(const Dom* __restrict__ do
   zreg_map(G, c, tid, rm);
   const bool upx[2] = {resolve(gx - 1, G.nx, G.bcx) >= 0, resolve(gx + 1, G.nx, G.bcx) >= 0};
   const bool upy[2] = {resolve(gy - 1, G.ny, G.bcy) >= 0, resolve(gy + 1, G.ny, G.bcy) >= 0};
+  // whether the block's column touches a wall in x or y
+  const bool edge_blk = (G.bcx != BC_PER && (c.x0 == 0 || c.x0 + c.w >= G.nx)) ||
+                        (G.bcy != BC_PER && (c.y0 == 0 || c.y0 + c.h >= G.ny));
 
   auto collide = [&](const ZScalIn<R, S>& in, int zc) {
     if (resolve(zc, G.nz, G.bcz) < 0) return;   // beyond a wall: never pulled from
@@ -3856,51 +3869,58 @@ __global__ __launch_bounds__(64 * TY) void k3z_scalar(const Dom* __restrict__ do
     __syncthreads();
     collide(cur, z + 1);
     __syncthreads();
-    if (own) {
-      const int cr = (ty + 1) * ZRW + tx + 1;
-      const R* c1 = &wcol[zslot3(z)][0][0];
-      const R cy = wchi[zslot3(z)][cr], dPy = c1[cr];
-      const R Ky[3] = {c1[ZNR + cr], c1[2 * ZNR + cr], c1[3 * ZNR + cr]};
-      const bool upz[2] = {resolve(z - 1, G.nz, G.bcz) >= 0, resolve(z + 1, G.nz, G.bcz) >= 0};
-      R dq[7];
-      dq[0] = dPy * R(0.25);
-      R chin = dq[0], j[3] = {R(0), R(0), R(0)};
+    // the streaming of a plane that touches no wall (uniform over the
+    // block) takes every neighbour from the windows
+    auto stream_plane = [&](auto edge_c) {
+      constexpr bool EDGE = decltype(edge_c)::value;
+      if (own) {
+        const int cr = (ty + 1) * ZRW + tx + 1;
+        const R* c1 = &wcol[zslot3(z)][0][0];
+        const R cy = wchi[zslot3(z)][cr], dPy = c1[cr];
+        const R Ky[3] = {c1[ZNR + cr], c1[2 * ZNR + cr], c1[3 * ZNR + cr]};
+        const bool upz[2] = {resolve(z - 1, G.nz, G.bcz) >= 0, resolve(z + 1, G.nz, G.bcz) >= 0};
+        R dq[7];
+        dq[0] = dPy * R(0.25);
+        R chin = dq[0], j[3] = {R(0), R(0), R(0)};
 #pragma unroll
-      for (int q = 1; q < 7; ++q) {
-        const int ex = e19(q, 0), ey = e19(q, 1), ez = e19(q, 2);
-        const bool up = ex > 0 ? upx[0] : ex < 0 ? upx[1] : ey > 0 ? upy[0] : ey < 0 ? upy[1] : ez > 0 ? upz[0] : upz[1];
-        if (up) {
-          const R* cu = &wcol[zslot3(z - ez)][0][0];
-          const int ur = cr - ey * ZRW - ex;
-          const R Ke = edot3(ex, ey, ez, cu[ZNR + ur], cu[2 * ZNR + ur], cu[3 * ZNR + ur]);
-          dq[q] = (wchi[zslot3(z - ez)][ur] - cy + cu[ur]) * R(0.125) + R(0.5) * Ke;
-        } else {
-          const R Ke = edot3(ex, ey, ez, Ky[0], Ky[1], Ky[2]);
-          if (dir && (ez > 0 || (ez < 0 && pulled))) {
-            const R Tw = ez > 0 ? Tw_lo : Tw_hi;
-            dq[q] = R(0.125) * (R(2) * Tw - R(2) * cy - dPy) + R(0.5) * Ke;
+        for (int q = 1; q < 7; ++q) {
+          const int ex = e19(q, 0), ey = e19(q, 1), ez = e19(q, 2);
+          const bool up = !EDGE || (ex > 0 ? upx[0] : ex < 0 ? upx[1] : ey > 0 ? upy[0] : ey < 0 ? upy[1] : ez > 0 ? upz[0] : upz[1]);
+          if (up) {
+            const R* cu = &wcol[zslot3(z - ez)][0][0];
+            const int ur = cr - ey * ZRW - ex;
+            const R Ke = edot3(ex, ey, ez, cu[ZNR + ur], cu[2 * ZNR + ur], cu[3 * ZNR + ur]);
+            dq[q] = (wchi[zslot3(z - ez)][ur] - cy + cu[ur]) * R(0.125) + R(0.5) * Ke;
           } else {
-            dq[q] = dPy * R(0.125) - R(0.5) * Ke;
+            const R Ke = edot3(ex, ey, ez, Ky[0], Ky[1], Ky[2]);
+            if (dir && (ez > 0 || (ez < 0 && pulled))) {
+              const R Tw = ez > 0 ? Tw_lo : Tw_hi;
+              dq[q] = R(0.125) * (R(2) * Tw - R(2) * cy - dPy) + R(0.5) * Ke;
+            } else {
+              dq[q] = dPy * R(0.125) - R(0.5) * Ke;
+            }
           }
+          chin += dq[q];
+          if (ex != 0) j[0] += R(ex) * dq[q];
+          if (ey != 0) j[1] += R(ey) * dq[q];
+          if (ez != 0) j[2] += R(ez) * dq[q];
         }
-        chin += dq[q];
-        if (ex != 0) j[0] += R(ex) * dq[q];
-        if (ey != 0) j[1] += R(ey) * dq[q];
-        if (ez != 0) j[2] += R(ez) * dq[q];
-      }
-      chin += cy;
-      const unsigned o = zoff(G, gx, gy, z);
-      if (accum) {
-        const R p = ldo(pend, o);
-        chin += p;
-        sto(pend, o, R(0));
-        amax = fmax(amax, fabs(p));
-      }
-      sto(cout, o, chin);
-      SRStream rs = sr_stream(o, kabs, FIELD == 0 ? 0x85a308d3u : 0x13198a2eu);
+        chin += cy;
+        const unsigned o = zoff(G, gx, gy, z);
+        if (accum) {
+          const R p = ldo(pend, o);
+          chin += p;
+          sto(pend, o, R(0));
+          amax = fmax(amax, fabs(p));
+        }
+        sto(cout, o, chin);
+        SRStream rs = sr_stream(o, kabs, FIELD == 0 ? 0x85a308d3u : 0x13198a2eu);
 #pragma unroll
-      for (int a = 0; a < 3; ++a) sto_sr(plane(jout, a * pl), o, j[a], rs);
-    }
+        for (int a = 0; a < 3; ++a) sto_sr(plane(jout, a * pl), o, j[a], rs);
+      }
+    };
+    if (edge_blk || (G.bcz != BC_PER && (z == 0 || z == G.nz - 1))) stream_plane(std::true_type{});
+    else stream_plane(std::false_type{});
     __syncthreads();
   }
   if (FIELD == 0 && accum && part) {
