@@ -334,6 +334,40 @@ def directional_run(args) -> int:
     return 0
 
 
+def directional3d_run(args) -> int:
+    """A long run of the 3D directional workload (256 x 256 x 512, the
+    storage of ``--storage``, BF16 by default) for ``--run-steps`` base
+    steps: one JSON line every ``--every-steps`` with R_M, the largest and
+    the mean front height, S_phi and the wall time, then a summary line."""
+    import lbm_inputs as L
+    from paper_2609_25670_amd import lbm, simulation_for
+
+    wl = L.directional_3d()
+    storage = args.storage or wl["storage"]
+    sim = simulation_for(wl, storage=storage)
+    head = dict(run="directional_3d", storage=storage, steps=args.run_steps, every_steps=args.every_steps)
+    print(json.dumps(head), flush=True)
+    done, t0, last, bad = 0, time.perf_counter(), None, -1
+    while done < args.run_steps:
+        n = min(args.every_steps, args.run_steps - done)
+        try:
+            x = sim.step(n, diag=True)[0]
+        except lbm.LBMError as e:
+            if e.status != lbm.LBM_EUNSTABLE:
+                raise
+            x = e.diag[0]
+            bad = x["first_nonfinite_step"]
+            done += n
+            break
+        done += n
+        last = dict(step=x["step"], R_M=x["R_M"], front_max=x["tip"][0], front_mean=x["tip"][1],
+                    S_phi=x["S_phi"], nonfinite=x["nonfinite"], wall_s=round(time.perf_counter() - t0, 1))
+        print(json.dumps(last), flush=True)
+    sim.close()
+    print(json.dumps(dict(head, summary=True, final=last, first_nonfinite_step=bad)), flush=True)
+    return 0 if bad < 0 else 1
+
+
 def _progress(msg: str) -> None:
     """A progress line on stderr (the JSON result alone goes to stdout)."""
     print(f"bench.py: {msg}", file=sys.stderr, flush=True)
@@ -357,14 +391,19 @@ def main() -> int:
     ap.add_argument("--profile-steps", type=int, default=0, metavar="N",
                     help="only run N warm-up and N measured base steps (for profiler runs); no JSON")
     ap.add_argument("--tile-rows", type=int, default=0, help="fix the tile height (0 = autotune)")
-    ap.add_argument("--run", choices=["directional_2d"], default=None,
-                    help="instead of the benchmark: a long run of the Section 4.4 case (see directional_run)")
+    ap.add_argument("--run", choices=["directional_2d", "directional_3d"], default=None,
+                    help="instead of the benchmark: a long run of the Section 4.4 case (see directional_run) "
+                         "or of the 3D directional workload (see directional3d_run)")
+    ap.add_argument("--run-steps", type=int, default=20000, help="base steps of --run directional_3d")
+    ap.add_argument("--every-steps", type=int, default=2000, help="report interval of --run directional_3d")
     ap.add_argument("--le", default="1", help="Lewis numbers of --run, comma-separated (N_U = Le)")
     ap.add_argument("--coupling", choices=["instant", "accum"], default="instant")
     ap.add_argument("--q-scalar", type=int, default=5, help="scalar lattice of --run: 5 (D2Q5) or 9 (D2Q9)")
     ap.add_argument("--t-end-ms", type=float, default=20.0)
     ap.add_argument("--every-ms", type=float, default=0.5)
     args = ap.parse_args()
+    if args.run == "directional_3d":
+        return directional3d_run(args)
     if args.run:
         return directional_run(args)
 
