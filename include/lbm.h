@@ -257,8 +257,11 @@ lbm_status lbm_write_fields(lbm_ctx* ctx, int32_t domain, uint32_t mask,
 
 /* Tuning: rows per tile of the stencil kernels (4, 8, 16 or 32; 0 = autotune;
  * in 3D, rows of every kernel's 64-wide tiles, 4 or 8 (the flow keeps 4 in
- * FP64), or 0 for per-kernel defaults (4 for the transfer and for the
- * flow in FP64, else 8); both heights give the same bits) and flags:
+ * FP64), or 0: the autotuner times the phase kernel, the flow and (with
+ * N_phi = 1 and instantaneous coupling) the transfer at both heights and
+ * four z-run lengths at the next lbm_step_multirate and keeps the fastest
+ * of each; the U and T transports take measured defaults (8 rows); every
+ * choice gives the same bits) and flags:
  *   LBM_CFG_GRAPH           replay whole multirate cycles from a HIP graph
  *   LBM_CFG_FUSE_TRANSFER   2D: run the transfer of Eq. (36)-(39) inside the
  *                           phase kernel, which then recomputes a halo of

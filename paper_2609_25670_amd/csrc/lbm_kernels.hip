@@ -4857,7 +4857,7 @@ __global__ __launch_bounds__(NTHR) void k_phase_ym_q(const Dom* __restrict__ dom
   workq_loop(q, items, qoff, [&](const int4 t) { k_phase_ym_run<R, S, Q>(doms, t, k); });
 }
 template <class R>
-__global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(8))) void k_transfer_ym(const Dom* __restrict__ doms, const int4* __restrict__ runs,
+__global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(sizeof(R) == 4 ? 8 : 1))) void k_transfer_ym(const Dom* __restrict__ doms, const int4* __restrict__ runs,
                                                        unsigned k, double2* __restrict__ rmax) {
   const int4 t = runs[blockIdx.x];
   if (t.x >= 0) k_transfer_ym_run<R>(doms, t, k, rmax);
@@ -4869,7 +4869,7 @@ __global__ __launch_bounds__(NTHR) void k_transfer_ym_q(const Dom* __restrict__ 
   workq_loop(q, items, qoff, [&](const int4 t) { k_transfer_ym_run<R>(doms, t, k, rmax); });
 }
 template <class R, class S, int FIELD, int Q>
-__global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(Q == 5 ? 8 : 1))) void k_scalar_ym(const Dom* __restrict__ doms, const int4* __restrict__ runs,
+__global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(Q == 5 && sizeof(R) == 4 ? 8 : 1))) void k_scalar_ym(const Dom* __restrict__ doms, const int4* __restrict__ runs,
                                                      unsigned k, double2* __restrict__ rmax) {
   const int4 t = runs[blockIdx.x];
   if (t.x >= 0) k_scalar_ym_run<R, S, FIELD, Q>(doms, t, k, rmax);
@@ -4881,7 +4881,7 @@ __global__ __launch_bounds__(NTHR) void k_scalar_ym_q(const Dom* __restrict__ do
   workq_loop(q, items, qoff, [&](const int4 t) { k_scalar_ym_run<R, S, FIELD, Q>(doms, t, k, rmax); });
 }
 template <class R, class S, int Q>
-__global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(Q == 5 ? 8 : 1))) void k_tr_scalar_ym(const Dom* __restrict__ doms, const int4* __restrict__ runs,
+__global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(Q == 5 && sizeof(R) == 4 ? 8 : 1))) void k_tr_scalar_ym(const Dom* __restrict__ doms, const int4* __restrict__ runs,
                                                         unsigned k, double2* __restrict__ rmax) {
   const int4 t = runs[blockIdx.x];
   if (t.x >= 0) k_tr_scalar_ym_run<R, S, Q>(doms, t, k, rmax);

@@ -230,10 +230,12 @@ struct lbm_ctx {
   bool one_T = false;     // one phase group; every domain has a transported T, all in one update group
   bool march_big = false; // the phase groups hold enough column runs to fill the chip
   bool marchable = false; // every domain 2D and at least 16 x 16 (the marching windows wrap once at most)
-  bool march_pick = false; // the autotuner's choice between marching and tiles (starts as march_big)
+  bool march_pick = false; // marching or tiles by the size rule (march_big); lbm_configure can force either
   int queue = 0;          // marching launches: 0 autotuned, 1 per-XCD work queues, -1 static grids
   bool use_q = false;     // the marching kernels run from the work queues
-  int rows3 = 0;          // 3D tile rows of every kernel: 4, 8, or 0 for the per-kernel defaults
+  int rows3 = 0;          // 3D tile rows of every kernel: 4, 8, or 0 for the per-kernel choice
+  int rows3k[5] = {0, 0, 0, 0, 0};   // 3D per-kernel tile rows (0: the default) ...
+  int zblk3k[5] = {0, 0, 0, 0, 0};   // ... and z-run block targets, as the autotuner picked them
   WorkQ* d_wq = nullptr;  // the queues' counters (rewound before each launch)
   int qs = 5;             // scalar lattice of the (2D) context: 5 or 9
   hipGraphExec_t gexec = nullptr;
@@ -459,8 +461,9 @@ static bool fuses_T(const lbm_ctx* c, unsigned k) {
 }
 
 // 3D tile rows per kernel kind (0 phase, 1 transfer, 2 U, 3 T, 4 flow):
-// those fixed by lbm_configure, else the height measured best on the
-// 256 x 256 x 512 directional workload (the flow's LDS window allows 8
+// those fixed by lbm_configure, else the autotuner's pick (phase, transfer,
+// flow), else the height measured best on the 256 x 256 x 512 directional
+// workload (the flow's LDS window allows 8
 // rows with FP32 arithmetic only).  ms per launch at 4 / 8 rows, with the
 // z runs below: phase 0.436 / 0.408, transfer 0.227 / 0.230, U 0.476 /
 // 0.411, T 0.338 / 0.284, flow 1.282 / 1.284 (the flow's HBM reads 76 /
@@ -474,14 +477,16 @@ constexpr int kRows3Default[5] = {8, 4, 8, 8, 8};
 // 1.341 / 1.412)
 constexpr int kZBlocks3[5] = {1024, 4096, 4096, 8192, 1024};
 static int rows3(const lbm_ctx* c, int kind) {
-  const int r = c->rows3 != 0 ? c->rows3 : kRows3Default[kind];
+  const int r = c->rows3 != 0 ? c->rows3 : c->rows3k[kind] != 0 ? c->rows3k[kind] : kRows3Default[kind];
   return kind == 4 && c->storage == LBM_STORE_F64 ? 4 : r;
 }
+static int zblk3(const lbm_ctx* c, int kind) { return c->zblk3k[kind] != 0 ? c->zblk3k[kind] : kZBlocks3[kind]; }
 
 static void launch_step(lbm_ctx* c, hipStream_t st, unsigned k, bool last = false) {
   if (c->dim == 3) {
     const int rows[5] = {rows3(c, 0), rows3(c, 1), rows3(c, 2), rows3(c, 3), rows3(c, 4)};
-    c->ops3.step(c->H[0], st, c->d_dom, k, c->s.part, rows, kZBlocks3);
+    const int zblk[5] = {zblk3(c, 0), zblk3(c, 1), zblk3(c, 2), zblk3(c, 3), zblk3(c, 4)};
+    c->ops3.step(c->H[0], st, c->d_dom, k, c->s.part, rows, zblk);
     return;
   }
   const int ti = c->ty_index, TY = kTYs[ti];
@@ -617,6 +622,75 @@ static lbm_status autotune(lbm_ctx* c) {
     }
     c->use_q = t2[1] < t2[0];
   }
+  HIPCHK(c, hipEventDestroy(e0));
+  HIPCHK(c, hipEventDestroy(e1));
+  c->tuned = true;
+  return LBM_OK;
+}
+
+// 3D: time each of the phase kernel, the flow and (with N_phi = 1 and
+// instantaneous coupling) the transfer at both tile heights and four z-run
+// block targets, on launches that leave the state unchanged (at the next
+// due step they read the current buffers and write only the next ones),
+// and keep the fastest for each.  The U and T transports keep the measured
+// defaults: at their next due step they would write a current buffer (the
+// transfer of that step has not run) or clear the pending planes.  The
+// transfer's partials are cleared afterwards.
+static lbm_status autotune3(lbm_ctx* c) {
+  const Dom& h = c->H[0];
+  hipEvent_t e0, e1;
+  HIPCHK(c, hipEventCreate(&e0));
+  HIPCHK(c, hipEventCreate(&e1));
+  auto next_due = [&](int N) { return cycle_step(c, (c->k / N + 1) * (long long)N); };
+  const bool f64 = c->storage == LBM_STORE_F64;
+  const bool tr_ok = h.N_phi == 1 && !h.accum;
+  const int zs[4] = {1024, 2048, 4096, 8192};
+  for (int kind : {0, 1, 4}) {
+    if (kind == 1 && !tr_ok) continue;
+    if (kind == 4 && !h.has_F) continue;
+    auto time_of = [&](int rows, int z) -> float {
+      auto run = [&]() {
+        if (kind == 0) c->ops3.phase(h, c->stream, c->d_dom, next_due(h.N_phi), rows, z);
+        if (kind == 1) c->ops3.transfer(h, c->stream, c->d_dom, next_due(h.N_phi), c->s.part, rows, z);
+        if (kind == 4) c->ops3.flow(h, c->stream, c->d_dom, next_due(h.N_F), rows, z);
+      };
+      run();
+      (void)hipEventRecord(e0, c->stream);
+      for (int r = 0; r < 3; ++r) run();
+      (void)hipEventRecord(e1, c->stream);
+      (void)hipEventSynchronize(e1);
+      float ms = 0;
+      return hipEventElapsedTime(&ms, e0, e1) == hipSuccess ? ms : 1e30f;
+    };
+    // every choice is timed in two passes and keeps its faster time (the
+    // first launches of a context run while the clocks still ramp up); the
+    // measured default stands unless another choice is faster by more than
+    // 2 % (the spread of repeated timings)
+    const int r0 = (kind == 4 && f64) ? 4 : kRows3Default[kind], z0 = kZBlocks3[kind];
+    float t[2][4];
+    for (int pass = 0; pass < 2; ++pass)
+      for (int ri = 0; ri < 2; ++ri)
+        for (int zi = 0; zi < 4; ++zi) {
+          const bool skip = kind == 4 && ri == 1 && f64;
+          const float ms = skip ? 1e30f : time_of(4 + 4 * ri, zs[zi]);
+          t[ri][zi] = pass == 0 ? ms : std::min(t[ri][zi], ms);
+        }
+    float best = 1e30f;
+    for (int zi = 0; zi < 4; ++zi)
+      if (zs[zi] == z0) best = t[r0 == 8 ? 1 : 0][zi];
+    c->rows3k[kind] = r0;
+    c->zblk3k[kind] = z0;
+    for (int ri = 0; ri < 2; ++ri)
+      for (int zi = 0; zi < 4; ++zi)
+        if (t[ri][zi] < 0.98f * best) {
+          best = t[ri][zi];
+          c->rows3k[kind] = 4 + 4 * ri;
+          c->zblk3k[kind] = zs[zi];
+        }
+    HIPCHK(c, hipGetLastError());
+  }
+  HIPCHK(c, hipMemsetAsync(c->ws_s.part, 0, sizeof(Partial) * (size_t)c->nparts, c->stream));
+  HIPCHK(c, hipStreamSynchronize(c->stream));
   HIPCHK(c, hipEventDestroy(e0));
   HIPCHK(c, hipEventDestroy(e1));
   c->tuned = true;
@@ -1175,6 +1249,10 @@ lbm_status lbm_configure(lbm_ctx* c, int32_t tile_rows, int32_t flags) {
       HIPCHK(c, hipMemset(c->ws_s.part, 0, sizeof(Partial) * (size_t)c->nparts));
     }
     c->rows3 = tile_rows;
+    // 0: the autotuner picks each kernel's height and z runs at the next
+    // step; a fixed height keeps the z runs picked so far (or the defaults)
+    c->autotune = tile_rows == 0;
+    if (tile_rows == 0) c->tuned = false;
   } else if (tile_rows == 0) {
     c->autotune = true;
     c->tuned = false;
@@ -1222,8 +1300,8 @@ lbm_status lbm_kernel_times(lbm_ctx* c, int32_t reps, double* ms_out, double* pe
   for (int d = 0; d < c->ndom; ++d)
     if (!c->initialised[d]) return fail(c, LBM_ESTATE, "lbm_init_seeds has not been called for every domain");
   HIPCHK(c, hipSetDevice(c->device));
-  if (c->autotune && !c->tuned && c->dim == 2) {
-    lbm_status s = autotune(c);
+  if (c->autotune && !c->tuned) {
+    lbm_status s = c->dim == 3 ? autotune3(c) : autotune(c);
     if (s != LBM_OK) return s;
   }
   const int ti = c->ty_index, TY = kTYs[ti];
@@ -1249,11 +1327,11 @@ lbm_status lbm_kernel_times(lbm_ctx* c, int32_t reps, double* ms_out, double* pe
       auto launch = [&]() {
         if (c->dim == 3) {
           const Dom& h = c->H[0];
-          if (kind == 0) c->ops3.phase(h, c->stream, c->d_dom, k, rows3(c, 0), kZBlocks3[0]);
-          if (kind == 1) c->ops3.transfer(h, c->stream, c->d_dom, k, c->s.part, rows3(c, 1), kZBlocks3[1]);
-          if (kind == 2) c->ops3.scalar(0, h, c->stream, c->d_dom, k, c->s.part, rows3(c, 2), kZBlocks3[2]);
-          if (kind == 3) c->ops3.scalar(1, h, c->stream, c->d_dom, k, c->s.part, rows3(c, 3), kZBlocks3[3]);
-          if (kind == 4) c->ops3.flow(h, c->stream, c->d_dom, k, rows3(c, 4), kZBlocks3[4]);
+          if (kind == 0) c->ops3.phase(h, c->stream, c->d_dom, k, rows3(c, 0), zblk3(c, 0));
+          if (kind == 1) c->ops3.transfer(h, c->stream, c->d_dom, k, c->s.part, rows3(c, 1), zblk3(c, 1));
+          if (kind == 2) c->ops3.scalar(0, h, c->stream, c->d_dom, k, c->s.part, rows3(c, 2), zblk3(c, 2));
+          if (kind == 3) c->ops3.scalar(1, h, c->stream, c->d_dom, k, c->s.part, rows3(c, 3), zblk3(c, 3));
+          if (kind == 4) c->ops3.flow(h, c->stream, c->d_dom, k, rows3(c, 4), zblk3(c, 4));
           return;
         }
         if (kind == 0 && fused) {
@@ -1444,8 +1522,8 @@ static lbm_status step_impl(lbm_ctx* c, int64_t n, lbm_diag* diag, bool use_stat
     for (int d = 0; d < c->ndom; ++d) c->m0[d] = c->h_d[d].M_C;
     c->need_m0 = false;
   }
-  if (!use_static && c->autotune && !c->tuned && c->dim == 2) {
-    lbm_status s = autotune(c);
+  if (!use_static && c->autotune && !c->tuned) {
+    lbm_status s = c->dim == 3 ? autotune3(c) : autotune(c);
     if (s != LBM_OK) return s;
   }
   long long left = n;
