@@ -3614,20 +3614,18 @@ __global__ __launch_bounds__(64 * TY) void k3z_phase(const Dom* __restrict__ dom
   zload_phase(G, rm, c.za + 1, pl, sp, Up, Tp, in0);
   __syncthreads();
 
-  // one plane: `cur` holds the inputs of plane z + 1 and the prefetch for
-  // plane z + 2 goes to `nxt`; (Ac, svc) are the own site's A and
-  // deviations of plane z, (An, svn) receive those of plane z + 1.  The
-  // loop runs two planes per iteration with the roles swapped, so no
+  // one plane: `in0` holds the inputs of plane z + 1; once the collision
+  // has consumed them the loads for plane z + 2 go to the same registers
+  // and are in flight during the streaming.  (Ac, svc) are the own site's
+  // A and deviations of plane z, (An, svn) receive those of plane z + 1.
+  // The loop runs two planes per iteration with the roles swapped, so no
   // register state is copied between planes.
-  ZPhaseIn<R, S> in1b;
-  auto plane_step = [&](int z, ZPhaseIn<R, S>& cur, ZPhaseIn<R, S>& nxt, R& Ac, R* svc, R& An, R* svn) {
+  auto plane_step = [&](int z, R& Ac, R* svc, R& An, R* svn) {
     zput_win(wphi[zslot4(z + 2)], wn, tid);
-    if (z + 1 < c.zb) {   // prefetch for the next plane
-      zload_win(G, wm, z + 3, tid, phi, wn);
-      zload_phase(G, rm, z + 2, pl, sp, Up, Tp, nxt);
-    }
+    if (z + 1 < c.zb) zload_win(G, wm, z + 3, tid, phi, wn);   // window prefetch
     __syncthreads();
-    collide(cur, z + 1, An, svn);   // the plane above: its halo for this plane
+    collide(in0, z + 1, An, svn);   // the plane above: its halo for this plane
+    if (z + 1 < c.zb) zload_phase(G, rm, z + 2, pl, sp, Up, Tp, in0);
     __syncthreads();
     // the streaming of a plane that touches no wall (uniform over the
     // block) takes every neighbour from the windows
@@ -3675,8 +3673,8 @@ __global__ __launch_bounds__(64 * TY) void k3z_phase(const Dom* __restrict__ dom
     __syncthreads();
   };
   for (int z = c.za; z < c.zb; z += 2) {
-    plane_step(z, in0, in1b, Acur, svcur, Anext, svnext);
-    if (z + 1 < c.zb) plane_step(z + 1, in1b, in0, Anext, svnext, Acur, svcur);
+    plane_step(z, Acur, svcur, Anext, svnext);
+    if (z + 1 < c.zb) plane_step(z + 1, Anext, svnext, Acur, svcur);
   }
 }
 
