@@ -746,12 +746,13 @@ __device__ __forceinline__ void k_phase_ym_run(const Dom* __restrict__ doms, con
 
   for (int y = ya; y < yb; y += 4) {
     // in0: collision inputs of rows y + 1 .. y + 4 and phase-field rows y + 2 .. y + 5
+    // once the collision has consumed them, the loads for the next rows go
+    // to the same registers and are in flight during the streaming
     put_phi(in0, y + 1);
-    const YPhaseIn<R, S, Q> cur = in0;
+    __syncthreads();
+    collide(in0, y + 1);
     if (y + 4 < yb)
       ym_load_phase<R, S, Q>(nx, ny, px, bcx, bcy, x0, w, y + 5, pl, tx, ty, tid, phi_in, s_in, Up, Tp, in0);
-    __syncthreads();
-    collide(cur, y + 1);
     __syncthreads();
     const int gy = y + ty;
     // walls tested only on iterations whose rows or column touch one (the
@@ -4799,8 +4800,13 @@ template struct Launch3<float, __hip_bfloat16>;
 // The D2Q5 transfer and scalar transports are compiled for eight waves per
 // SIMD (at most 64 VGPRs; without spills): on the batched ensemble the
 // fused transfer + T transport went from 0.296 to 0.286 ms, the transfer
-// from 0.211 to 0.205 ms.  The marching phase kernel spills at 64 and
-// keeps seven.
+// from 0.211 to 0.205 ms.  With BF16 storage the fused transfer + T
+// transport would spill at 64 and keeps its own count.  The marching
+// phase kernel loads the next rows' inputs into the registers its
+// collision has just consumed; with that its D2Q5 form also fits eight
+// waves (61 VGPRs; the target caps its SGPRs, which alone held it at
+// seven).  The same order in the scalar transports, already at eight
+// waves, only shortened their prefetch distance (0.286 -> 0.298 ms).
 // Every 2D marching kernel body runs once per column run.  Two launch
 // forms share it: a static grid (block b takes run b of an XCD-ordered
 // list) and a persistent work queue.  The queue form launches as many
@@ -4843,7 +4849,7 @@ __device__ __forceinline__ void workq_loop(WorkQ* __restrict__ q, const int4* __
 }
 
 template <class R, class S, int Q>
-__global__ __launch_bounds__(NTHR) void k_phase_ym(const Dom* __restrict__ doms, const int4* __restrict__ runs,
+__global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(Q == 5 && sizeof(R) == 4 ? 8 : 1))) void k_phase_ym(const Dom* __restrict__ doms, const int4* __restrict__ runs,
                                                     unsigned k) {
   const int4 t = runs[blockIdx.x];
   if (t.x >= 0) k_phase_ym_run<R, S, Q>(doms, t, k);
@@ -4879,7 +4885,7 @@ __global__ __launch_bounds__(NTHR) void k_scalar_ym_q(const Dom* __restrict__ do
   workq_loop(q, items, qoff, [&](const int4 t) { k_scalar_ym_run<R, S, FIELD, Q>(doms, t, k, rmax); });
 }
 template <class R, class S, int Q>
-__global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(Q == 5 && sizeof(R) == 4 ? 8 : 1))) void k_tr_scalar_ym(const Dom* __restrict__ doms, const int4* __restrict__ runs,
+__global__ __launch_bounds__(NTHR) __attribute__((amdgpu_waves_per_eu(Q == 5 && sizeof(R) == 4 && !std::is_same<S, __hip_bfloat16>::value ? 8 : 1))) void k_tr_scalar_ym(const Dom* __restrict__ doms, const int4* __restrict__ runs,
                                                         unsigned k, double2* __restrict__ rmax) {
   const int4 t = runs[blockIdx.x];
   if (t.x >= 0) k_tr_scalar_ym_run<R, S, Q>(doms, t, k, rmax);
