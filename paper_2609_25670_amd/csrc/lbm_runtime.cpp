@@ -15,6 +15,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -471,11 +472,13 @@ static bool fuses_T(const lbm_ctx* c, unsigned k) {
 constexpr int kRows3Default[5] = {8, 4, 8, 8, 8};
 // z-run lengths: each kernel's runs aim at this many blocks of 256 threads
 // (half as many of 512), the fastest of 512 ... 8192 on the same workload
-// (ms per launch at 1024 / 2048 / 4096 / 8192: phase 0.409 / 0.427 /
-// 0.441 / 0.463, transfer 0.277 / 0.261 / 0.228 / 0.229, U 0.472 / 0.450 /
-// 0.410 / 0.414, T 0.343 / 0.337 / 0.290 / 0.283, flow 1.281 / 1.300 /
-// 1.341 / 1.412)
-constexpr int kZBlocks3[5] = {1024, 4096, 4096, 8192, 1024};
+// (ms per launch at 1024 / 1536 / 2048 / 3072 / 4096 / 8192: phase at 8
+// rows 0.382 / 0.361 / 0.395 / 0.366 / 0.371 / 0.377 (1536: one round of
+// three blocks per CU), transfer at 4 rows 0.274 / 0.233 / 0.257 / 0.224 /
+// 0.223 / 0.223, flow 1.278 / 1.288 / 1.301 / 1.326 / 1.336 / 1.404; U at
+// 1536 / 2048 / 3072 / 4096 0.397 / 0.430 / 0.394 / 0.403, T at 1536 /
+// 3072 / 4096 / 8192 0.294 / 0.280 / 0.276 / 0.272)
+constexpr int kZBlocks3[5] = {1536, 4096, 3072, 8192, 1024};
 static int rows3(const lbm_ctx* c, int kind) {
   const int r = c->rows3 != 0 ? c->rows3 : c->rows3k[kind] != 0 ? c->rows3k[kind] : kRows3Default[kind];
   return kind == 4 && c->storage == LBM_STORE_F64 ? 4 : r;
@@ -644,7 +647,11 @@ static lbm_status autotune3(lbm_ctx* c) {
   auto next_due = [&](int N) { return cycle_step(c, (c->k / N + 1) * (long long)N); };
   const bool f64 = c->storage == LBM_STORE_F64;
   const bool tr_ok = h.N_phi == 1 && !h.accum;
-  const int zs[4] = {1024, 2048, 4096, 8192};
+  // z-run block targets: 1536 and 3072 fill the chip in one and two rounds
+  // of 64 x 8 blocks at three blocks per CU
+  constexpr int NZ = 6;
+  const int zs[NZ] = {1024, 1536, 2048, 3072, 4096, 8192};
+  const bool log = std::getenv("LBM_AUTOTUNE_LOG") != nullptr;
   for (int kind : {0, 1, 4}) {
     if (kind == 1 && !tr_ok) continue;
     if (kind == 4 && !h.has_F) continue;
@@ -667,26 +674,35 @@ static lbm_status autotune3(lbm_ctx* c) {
     // measured default stands unless another choice is faster by more than
     // 2 % (the spread of repeated timings)
     const int r0 = (kind == 4 && f64) ? 4 : kRows3Default[kind], z0 = kZBlocks3[kind];
-    float t[2][4];
+    float t[2][NZ];
     for (int pass = 0; pass < 2; ++pass)
       for (int ri = 0; ri < 2; ++ri)
-        for (int zi = 0; zi < 4; ++zi) {
+        for (int zi = 0; zi < NZ; ++zi) {
           const bool skip = kind == 4 && ri == 1 && f64;
           const float ms = skip ? 1e30f : time_of(4 + 4 * ri, zs[zi]);
           t[ri][zi] = pass == 0 ? ms : std::min(t[ri][zi], ms);
         }
     float best = 1e30f;
-    for (int zi = 0; zi < 4; ++zi)
+    for (int zi = 0; zi < NZ; ++zi)
       if (zs[zi] == z0) best = t[r0 == 8 ? 1 : 0][zi];
     c->rows3k[kind] = r0;
     c->zblk3k[kind] = z0;
     for (int ri = 0; ri < 2; ++ri)
-      for (int zi = 0; zi < 4; ++zi)
+      for (int zi = 0; zi < NZ; ++zi)
         if (t[ri][zi] < 0.98f * best) {
           best = t[ri][zi];
           c->rows3k[kind] = 4 + 4 * ri;
           c->zblk3k[kind] = zs[zi];
         }
+    if (log) {   // ms per launch (three launches), then the pick
+      for (int ri = 0; ri < 2; ++ri) {
+        std::fprintf(stderr, "lbm autotune3 kind %d rows %d:", kind, 4 + 4 * ri);
+        for (int zi = 0; zi < NZ; ++zi) std::fprintf(stderr, " %d=%.4f", zs[zi], t[ri][zi] / 3.0f);
+        std::fprintf(stderr, "\n");
+      }
+      std::fprintf(stderr, "lbm autotune3 kind %d pick rows %d z-blocks %d\n", kind, c->rows3k[kind],
+                   c->zblk3k[kind]);
+    }
     HIPCHK(c, hipGetLastError());
   }
   HIPCHK(c, hipMemsetAsync(c->ws_s.part, 0, sizeof(Partial) * (size_t)c->nparts, c->stream));
