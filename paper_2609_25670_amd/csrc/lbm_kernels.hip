@@ -4365,6 +4365,9 @@ __global__ __launch_bounds__(64 * FTY) void k3z_flow(const Dom* __restrict__ dom
   zreg_map(G, c, tid, rm);
   const bool upx[2] = {resolve(gx - 1, G.nx, G.bcx) >= 0, resolve(gx + 1, G.nx, G.bcx) >= 0};
   const bool upy[2] = {resolve(gy - 1, G.ny, G.bcy) >= 0, resolve(gy + 1, G.ny, G.bcy) >= 0};
+  // whether the block's column touches a wall or an open boundary in x or y
+  const bool edge_blk = (G.bcx != BC_PER && (c.x0 == 0 || c.x0 + c.w >= G.nx)) ||
+                        (G.bcy != BC_PER && (c.y0 == 0 || c.y0 + c.h >= G.ny));
 
   // collide plane zc on the region; the own site's values are returned
   auto collide = [&](const ZFlowIn<R, S>& in, int zc, R* pown, R& rown, R& flown) {
@@ -4416,7 +4419,11 @@ __global__ __launch_bounds__(64 * FTY) void k3z_flow(const Dom* __restrict__ dom
     if (z + 1 < c.zb) zload_flow(G, rm, z + 2, pl, rin, phis, sp, in0);   // prefetch
     collide(cur, z + 1, pnext, rnext, fnext);
     __syncthreads();
-    if (own) {
+    // the streaming of a plane that touches no wall (uniform over the
+    // block) pulls every direction from the windows
+    auto stream_plane = [&](auto edge_c) {
+      constexpr bool EDGE = decltype(edge_c)::value;
+      if (!own) return;
       const int cr = (ty + 1) * ZRW + tx + 1;
       const bool upz[2] = {resolve(z - 1, G.nz, G.bcz) >= 0, resolve(z + 1, G.nz, G.bcz) >= 0};
       const R ry = rcur, fly = fcur;
@@ -4428,8 +4435,8 @@ __global__ __launch_bounds__(64 * FTY) void k3z_flow(const Dom* __restrict__ dom
         if (q == 0) {
           dn[0] = pcur[0];
         } else {
-          const bool up = (ex == 0 || upx[ex > 0 ? 0 : 1]) && (ey == 0 || upy[ey > 0 ? 0 : 1]) &&
-                          (ez == 0 || upz[ez > 0 ? 0 : 1]);
+          const bool up = !EDGE || ((ex == 0 || upx[ex > 0 ? 0 : 1]) && (ey == 0 || upy[ey > 0 ? 0 : 1]) &&
+                                    (ez == 0 || upz[ez > 0 ? 0 : 1]));
           if (up) {
             const int ur = cr - ey * ZRW - ex, s3 = zslot3(z - ez);
             const R pu = zgroup(q) == 0 ? wup[zslot3(z - 1)][zindex(q)][ur]
@@ -4453,7 +4460,9 @@ __global__ __launch_bounds__(64 * FTY) void k3z_flow(const Dom* __restrict__ dom
       SRStream rs = sr_stream(o, kabs, 0x03707344u);
 #pragma unroll
       for (int q = 1; q < 19; ++q) sto_sr(plane(s_out, (q - 1) * pl), o, dn[q] - R(w19(q)) * drho, rs);
-    }
+    };
+    if (edge_blk || (G.bcz != BC_PER && (z == 0 || z == G.nz - 1))) stream_plane(std::true_type{});
+    else stream_plane(std::false_type{});
 #pragma unroll
     for (int q = 0; q < 19; ++q) pcur[q] = pnext[q];
     rcur = rnext;
