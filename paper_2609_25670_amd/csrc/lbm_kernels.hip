@@ -3993,6 +3993,9 @@ __global__ __launch_bounds__(64 * TY) void k3z_transfer(const Dom* __restrict__ 
   // mirror flags of the own site's neighbours in x and y (beyond a wall)
   const bool mxl = gx - 1 < 0 && G.bcx != BC_PER, mxh = gx + 1 >= G.nx && G.bcx != BC_PER;
   const bool myl = gy - 1 < 0 && G.bcy != BC_PER, myh = gy + 1 >= G.ny && G.bcy != BC_PER;
+  // whether the block's column touches a wall in x or y
+  const bool edge_blk = (G.bcx != BC_PER && (c.x0 == 0 || c.x0 + c.w >= G.nx)) ||
+                        (G.bcy != BC_PER && (c.y0 == 0 || c.y0 + c.h >= G.ny));
 
   // J on the region of plane zc from the window planes zc - 1 .. zc + 1
   auto flux = [&](const ZTrIn<R>& in, int zc) {
@@ -4062,24 +4065,33 @@ __global__ __launch_bounds__(64 * TY) void k3z_transfer(const Dom* __restrict__ 
       const R dphi = p1 - cur.po[0];
       if (hasU) {
         const bool mzl = z - 1 < 0 && G.bcz != BC_PER, mzh = z + 1 >= G.nz && G.bcz != BC_PER;
-        R div = R(0);
+        // the divergence of a plane that touches no wall (uniform over the
+        // block) takes every neighbour unmirrored
+        auto divergence = [&](auto edge_c) {
+          constexpr bool EDGE = decltype(edge_c)::value;
+          R div = R(0);
 #pragma unroll
-        for (int q = 1; q < 19; ++q) {
-          const int ex = e19(q, 0), ey = e19(q, 1), ez = e19(q, 2);
-          const bool mir[3] = {ex < 0 ? mxl : ex > 0 ? mxh : false, ey < 0 ? myl : ey > 0 ? myh : false,
-                               ez < 0 ? mzl : ez > 0 ? mzh : false};
-          // a neighbour beyond a wall is the boundary node itself (ghost)
-          const int dx = mir[0] ? 0 : ex, dy = mir[1] ? 0 : ey, dz = mir[2] ? 0 : ez;
-          const R* Jq = &wJ[zslot3(z + dz)][0][0];
-          const int nr = cr + dy * ZRW + dx;
-          const R cq = q <= 6 ? R(1.0 / 6.0) : R(1.0 / 12.0);
+          for (int q = 1; q < 19; ++q) {
+            const int ex = e19(q, 0), ey = e19(q, 1), ez = e19(q, 2);
+            const bool mir[3] = {EDGE && (ex < 0 ? mxl : ex > 0 ? mxh : false),
+                                 EDGE && (ey < 0 ? myl : ey > 0 ? myh : false),
+                                 EDGE && (ez < 0 ? mzl : ez > 0 ? mzh : false)};
+            // a neighbour beyond a wall is the boundary node itself (ghost)
+            const int dx = mir[0] ? 0 : ex, dy = mir[1] ? 0 : ey, dz = mir[2] ? 0 : ez;
+            const R* Jq = &wJ[zslot3(z + dz)][0][0];
+            const int nr = cr + dy * ZRW + dx;
+            const R cq = q <= 6 ? R(1.0 / 6.0) : R(1.0 / 12.0);
 #pragma unroll
-          for (int a = 0; a < 3; ++a)
-            if (e19(q, a) != 0) {
-              const R v = Jq[a * ZNR + nr];
-              div += R(e19(q, a)) * cq * (mir[a] ? -v : v);
-            }
-        }
+            for (int a = 0; a < 3; ++a)
+              if (e19(q, a) != 0) {
+                const R v = Jq[a * ZNR + nr];
+                div += R(e19(q, a)) * cq * (mir[a] ? -v : v);
+              }
+          }
+          return div;
+        };
+        const R div = edge_blk || (G.bcz != BC_PER && (z == 0 || z == G.nz - 1)) ? divergence(std::true_type{})
+                                                                                  : divergence(std::false_type{});
         const R Us = cur.U[0];   // U - U0
         const R dU = ((R(1) + omk * (Us + U0)) * dphi - R(2) * div) * rcp(opk - omk * p1);
         amax = fmax(amax, fabs(dU));

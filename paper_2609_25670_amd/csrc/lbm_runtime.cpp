@@ -464,21 +464,20 @@ static bool fuses_T(const lbm_ctx* c, unsigned k) {
 // 3D tile rows per kernel kind (0 phase, 1 transfer, 2 U, 3 T, 4 flow):
 // those fixed by lbm_configure, else the autotuner's pick (phase, transfer,
 // flow), else the height measured best on the 256 x 256 x 512 directional
-// workload (the flow's LDS window allows 8
-// rows with FP32 arithmetic only).  ms per launch at 4 / 8 rows, with the
-// z runs below: phase 0.436 / 0.408, transfer 0.227 / 0.230, U 0.476 /
-// 0.411, T 0.338 / 0.284, flow 1.282 / 1.284 (the flow's HBM reads 76 /
-// 46 B per site: at equal time the taller tiles re-read less)
-constexpr int kRows3Default[5] = {8, 4, 8, 8, 8};
+// workload (the flow's LDS window allows 8 rows with FP32 arithmetic only).
+// ms per launch at 4 / 8 rows, each at its best z runs: phase 0.433 /
+// 0.363, transfer 0.228 / 0.216, U 0.476 / 0.411, T 0.338 / 0.284, flow
+// 1.198 / 1.132
+constexpr int kRows3Default[5] = {8, 8, 8, 8, 8};
 // z-run lengths: each kernel's runs aim at this many blocks of 256 threads
 // (half as many of 512), the fastest of 512 ... 8192 on the same workload
-// (ms per launch at 1024 / 1536 / 2048 / 3072 / 4096 / 8192: phase at 8
-// rows 0.382 / 0.361 / 0.395 / 0.366 / 0.371 / 0.377 (1536: one round of
-// three blocks per CU), transfer at 4 rows 0.274 / 0.233 / 0.257 / 0.224 /
-// 0.223 / 0.223, flow 1.278 / 1.288 / 1.301 / 1.326 / 1.336 / 1.404; U at
-// 1536 / 2048 / 3072 / 4096 0.397 / 0.430 / 0.394 / 0.403, T at 1536 /
-// 3072 / 4096 / 8192 0.294 / 0.280 / 0.276 / 0.272)
-constexpr int kZBlocks3[5] = {1536, 4096, 3072, 8192, 1024};
+// (ms per launch at 1024 / 1536 / 2048 / 3072 / 4096 / 8192, 8 rows: phase
+// 0.384 / 0.363 / 0.399 / 0.368 / 0.374 / 0.379 (1536: one round of three
+// blocks per CU), transfer 0.247 / 0.216 / 0.262 / 0.222 / 0.224 / 0.233,
+// flow 1.132 / 1.142 / 1.158 / 1.185 / 1.196 / 1.269; U at 1536 / 2048 /
+// 3072 / 4096 0.397 / 0.430 / 0.394 / 0.403, T at 1536 / 3072 / 4096 /
+// 8192 0.294 / 0.280 / 0.276 / 0.272)
+constexpr int kZBlocks3[5] = {1536, 1536, 3072, 8192, 1024};
 static int rows3(const lbm_ctx* c, int kind) {
   const int r = c->rows3 != 0 ? c->rows3 : c->rows3k[kind] != 0 ? c->rows3k[kind] : kRows3Default[kind];
   return kind == 4 && c->storage == LBM_STORE_F64 ? 4 : r;
