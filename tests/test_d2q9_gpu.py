@@ -54,15 +54,23 @@ def _parity(case, wl, steps, names, storage="f64", tol=TOL64):
         dom = oracle.run(d, steps)
         refs = _ref(dom, names)
         for n, r in refs.items():
+            e = _rel(got[i][n], r)
+            bar = tol
             if n in ("jU", "jT"):
                 # a first moment is a difference of populations of the size of
-                # the zeroth moment: its error is measured on that scale
+                # the zeroth moment, so any FP64 evaluation loses the digits of
+                # that cancellation: its relative bar is the field's scaled by
+                # |zeroth| / |first| (1 where the first moment is the larger);
+                # the error on the zeroth moment's scale is printed beside
                 z = dom.U if n == "jU" else dom.T
-                e = np.linalg.norm(got[i][n] - r) / np.linalg.norm(z)
+                ratio = np.linalg.norm(z) / max(np.linalg.norm(r), 1e-300)
+                bar = tol * max(1.0, ratio)
+                ez = np.linalg.norm(got[i][n] - r) / np.linalg.norm(z)
+                _say(f"  {case} domain {i}: {n} rel L2 = {e:.3e} (bar {bar:.1e}; on the scale of the zeroth "
+                     f"moment {ez:.3e})")
             else:
-                e = _rel(got[i][n], r)
-            _say(f"  {case} domain {i}: {n} rel L2 = {e:.3e}")
-            assert e <= tol, (case, i, n, e)
+                _say(f"  {case} domain {i}: {n} rel L2 = {e:.3e}")
+            assert e <= bar, (case, i, n, e, bar)
     return diag
 
 

@@ -152,6 +152,30 @@ def test_batched_uneven_domains_fp64(use_graph):
         _compare(f"domain{i}", gots[i], _oracle_fields(dom, names), TOL64)
 
 
+@pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16"])
+def test_batched_domains_are_bitwise_equal_to_each_domain_alone(storage):
+    """Each domain of a batched context (uneven sizes and update factors)
+    ends bit for bit where the same domain ends in a context of its own:
+    the batch shares launches, never arithmetic or rounding streams."""
+    wl = L.ensemble_256(n_domains=4, side_lo=40, side_hi=100)
+    for i, d in enumerate(wl["domains"]):
+        d["tau0"] = 30.0
+        Le = [1, 10, 2, 10][i]
+        d["N_U"] = Le
+        d["D_L"] = 0.026 / Le
+        d["D_S"] = 1e-2 * d["D_L"]
+    names = ("phi", "U", "T", "jU", "jT")
+    steps = 200
+    _say(f"case batched vs alone {storage} {steps} steps")
+    batch, _ = _gpu(wl, steps, storage=storage, names=names)
+    for i, d in enumerate(wl["domains"]):
+        alone, _ = _gpu(dict(wl, domains=[d]), steps, storage=storage, names=names)
+        for n in names:
+            same = np.array_equal(batch[i][n], alone[0][n])
+            _say(f"  domain {i} ({d['nx']} x {d['ny']}, N_U = {d['N_U']}): {n} bitwise equal = {same}")
+            assert same, (storage, i, n)
+
+
 @pytest.mark.parametrize("storage", ["f64", "f32"])
 def test_tile_shapes_graph_and_fusion_are_bitwise_identical(storage):
     """Race detector: every tile height, graph replay versus eager launches,
