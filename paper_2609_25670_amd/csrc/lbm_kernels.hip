@@ -3717,8 +3717,12 @@ __global__ __launch_bounds__(64 * TY) void k3z_scalar(const Dom* __restrict__ do
   using SR = typename RawT<S>::type;
   constexpr int ZNR = ZRW * (TY + 2), ZNB = ZWinT<TY>::NB;   // collision region and window of a 64 x TY tile
   __shared__ R wphi[4][ZNB];
-  __shared__ R wchi[3][ZNR];
-  __shared__ R wcol[3][4][ZNR];   // dP, Kx, Ky, Kz per region cell
+  // collisions of the planes z and z + 1 (slot z & 1): the streaming of
+  // plane z pulls its in-plane neighbours from them; its pulls along z come
+  // from the own column, whose collisions this thread computed and keeps in
+  // registers
+  __shared__ R wchi[2][ZNR];
+  __shared__ R wcol[2][4][ZNR];   // dP, Kx, Ky, Kz per region cell
   __shared__ R red[TY];
   const Dom& D = doms[0];
   const ZGeo G = zgeo(D);
@@ -3775,13 +3779,17 @@ __global__ __launch_bounds__(64 * TY) void k3z_scalar(const Dom* __restrict__ do
   const bool edge_blk = (G.bcx != BC_PER && (c.x0 == 0 || c.x0 + c.w >= G.nx)) ||
                         (G.bcy != BC_PER && (c.y0 == 0 || c.y0 + c.h >= G.ny));
 
-  auto collide = [&](const ZScalIn<R, S>& in, int zc) {
+  // the own column's (chi - chi_ref, dt Q, K_z) of a plane
+  struct OwnZ {
+    R chi, dP, Kz;
+  };
+  auto collide = [&](const ZScalIn<R, S>& in, int zc, OwnZ& ownz) {
     if (resolve(zc, G.nz, G.bcz) < 0) return;   // beyond a wall: never pulled from
     const R* p0 = wphi[zslot4(zc - 1)];
     const R* p1 = wphi[zslot4(zc)];
     const R* p2 = wphi[zslot4(zc + 1)];
-    R* out = &wcol[zslot3(zc)][0][0];
-    R* cw = wchi[zslot3(zc)];
+    R* out = &wcol[zc & 1][0][0];
+    R* cw = wchi[zc & 1];
 #pragma unroll
     for (int i = 0; i < 2; ++i) {
       if (rm.cr[i] < 0) continue;
@@ -3824,10 +3832,14 @@ __global__ __launch_bounds__(64 * TY) void k3z_scalar(const Dom* __restrict__ do
         itau = itau_const;
       }
       const R om = R(1) - itau;
+      R K[3];
+#pragma unroll
+      for (int a = 0; a < 3; ++a) K[a] = je[a] + om * (j[a] - je[a]);
       cw[cr] = in.chi[i];
       out[cr] = dt * Q;
 #pragma unroll
-      for (int a = 0; a < 3; ++a) out[(a + 1) * ZNR + cr] = je[a] + om * (j[a] - je[a]);
+      for (int a = 0; a < 3; ++a) out[(a + 1) * ZNR + cr] = K[a];
+      if (i == 0) ownz = OwnZ{in.chi[i], dt * Q, K[2]};
     }
   };
 
@@ -3851,8 +3863,9 @@ __global__ __launch_bounds__(64 * TY) void k3z_scalar(const Dom* __restrict__ do
     }
   }
   __syncthreads();
-  collide(in0, c.za - 1);
-  collide(in1, c.za);
+  OwnZ zlo{}, zmid{}, zhi{};   // own column at z - 1, z, z + 1
+  collide(in0, c.za - 1, zlo);
+  collide(in1, c.za, zmid);
   ZWin<R, TY> wn;
   if (var) zload_win(G, wm, c.za + 2, tid, phis, wn);
   zload_scal(G, rm, c.za + 1, pl, cin, jin, vel, in0);
@@ -3860,13 +3873,12 @@ __global__ __launch_bounds__(64 * TY) void k3z_scalar(const Dom* __restrict__ do
 
   for (int z = c.za; z < c.zb; ++z) {
     if (var) zput_win(wphi[zslot4(z + 2)], wn, tid);
-    const ZScalIn<R, S> cur = in0;
-    if (z + 1 < c.zb) {   // prefetch for the next plane
-      if (var) zload_win(G, wm, z + 3, tid, phis, wn);
-      zload_scal(G, rm, z + 2, pl, cin, jin, vel, in0);
-    }
+    if (z + 1 < c.zb && var) zload_win(G, wm, z + 3, tid, phis, wn);   // window prefetch
     __syncthreads();
-    collide(cur, z + 1);
+    collide(in0, z + 1, zhi);
+    // the next plane's inputs go to the registers the collision consumed,
+    // in flight during the streaming
+    if (z + 1 < c.zb) zload_scal(G, rm, z + 2, pl, cin, jin, vel, in0);
     __syncthreads();
     // the streaming of a plane that touches no wall (uniform over the
     // block) takes every neighbour from the windows
@@ -3874,8 +3886,8 @@ __global__ __launch_bounds__(64 * TY) void k3z_scalar(const Dom* __restrict__ do
       constexpr bool EDGE = decltype(edge_c)::value;
       if (own) {
         const int cr = (ty + 1) * ZRW + tx + 1;
-        const R* c1 = &wcol[zslot3(z)][0][0];
-        const R cy = wchi[zslot3(z)][cr], dPy = c1[cr];
+        const R* c1 = &wcol[z & 1][0][0];
+        const R cy = wchi[z & 1][cr], dPy = c1[cr];
         const R Ky[3] = {c1[ZNR + cr], c1[2 * ZNR + cr], c1[3 * ZNR + cr]};
         const bool upz[2] = {resolve(z - 1, G.nz, G.bcz) >= 0, resolve(z + 1, G.nz, G.bcz) >= 0};
         R dq[7];
@@ -3885,11 +3897,15 @@ __global__ __launch_bounds__(64 * TY) void k3z_scalar(const Dom* __restrict__ do
         for (int q = 1; q < 7; ++q) {
           const int ex = e19(q, 0), ey = e19(q, 1), ez = e19(q, 2);
           const bool up = !EDGE || (ex > 0 ? upx[0] : ex < 0 ? upx[1] : ey > 0 ? upy[0] : ey < 0 ? upy[1] : ez > 0 ? upz[0] : upz[1]);
-          if (up) {
-            const R* cu = &wcol[zslot3(z - ez)][0][0];
+          if (up && ez != 0) {   // from the own column below or above
+            const OwnZ& u = ez > 0 ? zlo : zhi;
+            const R Ke = edot3(ex, ey, ez, R(0), R(0), u.Kz);
+            dq[q] = (u.chi - cy + u.dP) * R(0.125) + R(0.5) * Ke;
+          } else if (up) {
+            const R* cu = &wcol[z & 1][0][0];
             const int ur = cr - ey * ZRW - ex;
             const R Ke = edot3(ex, ey, ez, cu[ZNR + ur], cu[2 * ZNR + ur], cu[3 * ZNR + ur]);
-            dq[q] = (wchi[zslot3(z - ez)][ur] - cy + cu[ur]) * R(0.125) + R(0.5) * Ke;
+            dq[q] = (wchi[z & 1][ur] - cy + cu[ur]) * R(0.125) + R(0.5) * Ke;
           } else {
             const R Ke = edot3(ex, ey, ez, Ky[0], Ky[1], Ky[2]);
             if (dir && (ez > 0 || (ez < 0 && pulled))) {
@@ -3920,6 +3936,8 @@ __global__ __launch_bounds__(64 * TY) void k3z_scalar(const Dom* __restrict__ do
     };
     if (edge_blk || (G.bcz != BC_PER && (z == 0 || z == G.nz - 1))) stream_plane(std::true_type{});
     else stream_plane(std::false_type{});
+    zlo = zmid;
+    zmid = zhi;
     __syncthreads();
   }
   if (FIELD == 0 && accum && part) {
