@@ -3863,9 +3863,11 @@ __global__ __launch_bounds__(64 * TY) void k3z_scalar(const Dom* __restrict__ do
     }
   }
   __syncthreads();
-  OwnZ zlo{}, zmid{}, zhi{};   // own column at z - 1, z, z + 1
+  // own column at z - 1 and z + 1 (that of z is read back from the
+  // window by the streaming, which then keeps it as the next plane's z - 1)
+  OwnZ zlo{}, zhi{};
   collide(in0, c.za - 1, zlo);
-  collide(in1, c.za, zmid);
+  collide(in1, c.za, zhi);
   ZWin<R, TY> wn;
   if (var) zload_win(G, wm, c.za + 2, tid, phis, wn);
   zload_scal(G, rm, c.za + 1, pl, cin, jin, vel, in0);
@@ -3932,12 +3934,11 @@ __global__ __launch_bounds__(64 * TY) void k3z_scalar(const Dom* __restrict__ do
         SRStream rs = sr_stream(o, kabs, FIELD == 0 ? 0x85a308d3u : 0x13198a2eu);
 #pragma unroll
         for (int a = 0; a < 3; ++a) sto_sr(plane(jout, a * pl), o, j[a], rs);
+        zlo = OwnZ{cy, dPy, Ky[2]};   // the next plane's z - 1
       }
     };
     if (edge_blk || (G.bcz != BC_PER && (z == 0 || z == G.nz - 1))) stream_plane(std::true_type{});
     else stream_plane(std::false_type{});
-    zlo = zmid;
-    zmid = zhi;
     __syncthreads();
   }
   if (FIELD == 0 && accum && part) {
