@@ -113,6 +113,26 @@ def test_3d_transport_T_accumulated_walls_fp64():
 
 
 @pytest.mark.parametrize("rows", [4, 8])
+def test_3d_walls_in_every_direction_fp64(rows):
+    """Walls normal to x, y and z (scalars and flow), instantaneous coupling,
+    transported T, a driven flow, on 20 x 18 x 26: every kernel's wall
+    handling (the mirrored transfer divergence, bounce-back of the phase,
+    scalar and flow populations) at tile edges in x and y, with the
+    interior planes taking the wall-free code."""
+    wl = _directional(20, 18, 26)
+    d = wl["domains"][0]
+    d.update(T_mode="transport", T0=d["T0"] - 0.02, kappa_S=2 * d["kappa_L"], rhoCp_S=1.2 * d["rhoCp_L"],
+             N_U=1, N_T=2, N_F=2, bc=("wall", "wall", "wall"), flow_bc=("wall", "wall", "wall"),
+             D_L=0.05, D_S=5e-4)
+    names = ("phi", "U", "T", "rho", "vel", "jU", "jT", "f_phi")
+    _say(f"case 3d walls xyz 20x18x26 fp64 40 steps, {rows}-row tiles")
+    got, diag = _run(wl, 40, names, rows=rows)
+    dom = oracle.run(d, 40)
+    _compare("3d walls xyz", got, _ref(dom, names), TOL64)
+    assert diag["nonfinite"] == 0
+
+
+@pytest.mark.parametrize("rows", [4, 8])
 def test_3d_periodic_z_ragged_tiles_fp64(rows):
     """Periodic in all three directions, transported T with phi-dependent
     properties, on 70 x 9 x 21: ragged tiles in x (70 = 64 + 6) and y
