@@ -3719,8 +3719,8 @@ __global__ __launch_bounds__(64 * TY) void k3z_scalar(const Dom* __restrict__ do
   __shared__ R wphi[4][ZNB];
   // collisions of the planes z and z + 1 (slot z & 1): the streaming of
   // plane z pulls its in-plane neighbours from them; its pulls along z come
-  // from the own column, whose collisions this thread computed and keeps in
-  // registers
+  // from the own column's values of planes z - 1 and z + 1, which this
+  // thread keeps in registers
   __shared__ R wchi[2][ZNR];
   __shared__ R wcol[2][4][ZNR];   // dP, Kx, Ky, Kz per region cell
   __shared__ R red[TY];
