@@ -132,6 +132,25 @@ def test_3d_walls_in_every_direction_fp64(rows):
     assert diag["nonfinite"] == 0
 
 
+@pytest.mark.parametrize("N", [(2, 2, 4, 4), (2, 4, 4, 2)])
+def test_3d_phase_every_other_step_fp64(N):
+    """Multirate schedules in which the phase field itself runs only every
+    second base step (N_phi = 2), so the transfer, the U transport and the
+    flow see the phase field and its increments at multiples of N_phi, on
+    20 x 18 x 26 with walls normal to x and z."""
+    wl = _directional(20, 18, 26)
+    d = wl["domains"][0]
+    d.update(T_mode="transport", T0=d["T0"] - 0.02, kappa_S=2 * d["kappa_L"], rhoCp_S=1.2 * d["rhoCp_L"],
+             N_phi=N[0], N_U=N[1], N_T=N[2], N_F=N[3], bc=("wall", "periodic", "wall"),
+             flow_bc=("wall", "periodic", "wall"), D_L=0.05, D_S=5e-4)
+    names = ("phi", "U", "T", "rho", "vel", "jU", "jT", "f_phi")
+    _say(f"case 3d N = {N} 20x18x26 fp64 48 steps")
+    got, diag = _run(wl, 48, names)
+    dom = oracle.run(d, 48)
+    _compare(f"3d N={N}", got, _ref(dom, names), TOL64)
+    assert diag["nonfinite"] == 0
+
+
 @pytest.mark.parametrize("rows", [4, 8])
 def test_3d_periodic_z_ragged_tiles_fp64(rows):
     """Periodic in all three directions, transported T with phi-dependent
