@@ -151,6 +151,28 @@ def test_3d_phase_every_other_step_fp64(N):
     assert diag["nonfinite"] == 0
 
 
+@pytest.mark.parametrize("case", ["thermal", "isothermal"])
+def test_3d_single_scalar_fp64(case):
+    """3D with one scalar field only: a thermal dendrite (transported T with
+    latent heat, no U) and an isothermal solutal one (U, no T), each with
+    a driven flow, on 20 x 18 x 26 with walls normal to x and z."""
+    wl = _directional(20, 18, 26)
+    d = wl["domains"][0]
+    if case == "thermal":
+        d.update(T_mode="transport", T0=d["T0"] - 0.02, kappa_S=2 * d["kappa_L"], rhoCp_S=1.2 * d["rhoCp_L"],
+                 has_U=False, N_T=2, N_F=2)
+        names = ("phi", "T", "rho", "vel", "jT", "f_phi")
+    else:
+        d.update(has_T=False, N_U=2, N_F=2, D_L=0.05, D_S=5e-4)
+        names = ("phi", "U", "rho", "vel", "jU", "f_phi")
+    d.update(bc=("wall", "periodic", "wall"), flow_bc=("wall", "periodic", "wall"))
+    _say(f"case 3d {case} 20x18x26 fp64 40 steps")
+    got, diag = _run(wl, 40, names)
+    dom = oracle.run(d, 40)
+    _compare(f"3d {case}", got, _ref(dom, names), TOL64)
+    assert diag["nonfinite"] == 0
+
+
 @pytest.mark.parametrize("rows", [4, 8])
 def test_3d_periodic_z_ragged_tiles_fp64(rows):
     """Periodic in all three directions, transported T with phi-dependent
