@@ -152,6 +152,51 @@ def test_batched_uneven_domains_fp64(use_graph):
         _compare(f"domain{i}", gots[i], _oracle_fields(dom, names), TOL64)
 
 
+SMALLEST_2D = {
+    "solutal_3x3_walls": (L.solutal_512, 3, 3, ("wall", "wall", "wall"), None),
+    "solutal_5x4_wall_periodic": (L.solutal_512, 5, 4, ("wall", "periodic", "wall"), None),
+    "four_field_4x3_inlet": (L.thermosolutal_flow_1024, 4, 3, ("wall", "wall", "wall"), None),
+    "four_field_5x4_periodic": (L.thermosolutal_flow_1024, 5, 4, ("periodic", "periodic", "wall"),
+                                ("periodic", "periodic", "periodic")),
+}
+
+
+@pytest.mark.parametrize("case", sorted(SMALLEST_2D))
+def test_smallest_2d_grids_fp64(case):
+    """Domains smaller than one tile, down to the smallest side accepted (3),
+    with a seed of radius 1.2 in the middle: the tiles' rings and the
+    phase window wrap across the whole periodic domain or fold onto the
+    walls, and the inlet and outflow columns of the four-field case are
+    neighbours."""
+    make, nx, ny, bc, fbc = SMALLEST_2D[case]
+    wl = L.reduced(make(), nx, ny)
+    d = wl["domains"][0]
+    d.update(bc=bc, seeds=[(nx / 2 - 0.5, ny / 2 - 0.5, 1.2)])
+    if fbc:
+        d.update(flow_bc=fbc)
+    names = ("phi", "U", "T", "rho", "vel") if d.get("has_flow") else ("phi", "U")
+    _say(f"case smallest 2d {case} fp64 24 steps")
+    gots, diag = _gpu(wl, 24, names=names)
+    dom = oracle.run(d, 24)
+    ref = _oracle_fields(dom, names)
+    for n, r in ref.items():
+        e = _rel(gots[0][n], r)
+        bar = TOL64
+        if n == "vel":
+            # the velocity is a first moment of populations the size of rho:
+            # its relative bar is scaled by |rho| / |rho u| (the cancellation
+            # any FP64 evaluation goes through); printed with its error on
+            # the scale of rho
+            z = np.linalg.norm(dom.rho)
+            bar = TOL64 * max(1.0, z / max(np.linalg.norm(r * dom.rho), 1e-300))
+            _say(f"  {case}: vel rel L2 = {e:.3e} (bar {bar:.1e}; on the scale of rho "
+                 f"{np.linalg.norm(gots[0][n] - r) / z:.3e})")
+        else:
+            _say(f"  {case}: {n} rel L2 = {e:.3e}")
+        assert e <= bar, (case, n, e, bar)
+    assert diag[0]["nonfinite"] == 0
+
+
 @pytest.mark.parametrize("storage", ["f64", "f32", "f16", "bf16"])
 def test_batched_domains_are_bitwise_equal_to_each_domain_alone(storage):
     """Each domain of a batched context (uneven sizes and update factors)
