@@ -258,11 +258,12 @@ lbm_status lbm_write_fields(lbm_ctx* ctx, int32_t domain, uint32_t mask,
 /* Tuning: rows per tile of the stencil kernels (4, 8, 16 or 32; 0 = autotune;
  * in 3D, rows of every kernel's 64-wide tiles, 4 or 8 (the flow keeps 4 in
  * FP64), or 0: the autotuner times the phase kernel, the flow and (with
- * N_phi = 1 and instantaneous coupling) the transfer at both heights and
- * six z-run lengths at the next lbm_step_multirate and keeps the fastest
- * of each (with the environment variable LBM_AUTOTUNE_LOG set, the times
- * and picks go to stderr); the U and T transports take measured defaults
- * (8 rows); every choice gives the same bits) and flags:
+ * N_phi = 1 and instantaneous coupling) the transfer, and with N_U = 1 as
+ * well the U transport, at both heights and six z-run lengths at the next
+ * lbm_step_multirate and keeps the fastest of each (with the environment
+ * variable LBM_AUTOTUNE_LOG set, the times and picks go to stderr); the
+ * other transports take measured defaults (8 rows); every choice gives the
+ * same bits) and flags:
  *   LBM_CFG_GRAPH           replay whole multirate cycles from a HIP graph
  *   LBM_CFG_FUSE_TRANSFER   2D: run the transfer of Eq. (36)-(39) inside the
  *                           phase kernel, which then recomputes a halo of

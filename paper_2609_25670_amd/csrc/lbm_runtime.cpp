@@ -463,7 +463,7 @@ static bool fuses_T(const lbm_ctx* c, unsigned k) {
 
 // 3D tile rows per kernel kind (0 phase, 1 transfer, 2 U, 3 T, 4 flow):
 // those fixed by lbm_configure, else the autotuner's pick (phase, transfer,
-// flow), else the height measured best on the 256 x 256 x 512 directional
+// U transport, flow), else the height measured best on the 256 x 256 x 512 directional
 // workload (the flow's LDS window allows 8 rows with FP32 arithmetic only).
 // ms per launch at 4 / 8 rows, each at its best z runs: phase 0.433 /
 // 0.363, transfer 0.228 / 0.216, U 0.476 / 0.411, T 0.338 / 0.284, flow
@@ -474,10 +474,10 @@ constexpr int kRows3Default[5] = {8, 8, 8, 8, 8};
 // (ms per launch at 1024 / 1536 / 2048 / 3072 / 4096 / 8192, 8 rows: phase
 // 0.384 / 0.363 / 0.399 / 0.368 / 0.374 / 0.379 (1536: one round of three
 // blocks per CU), transfer 0.247 / 0.216 / 0.262 / 0.222 / 0.224 / 0.233,
-// flow 1.132 / 1.142 / 1.158 / 1.185 / 1.196 / 1.269; U at 1536 / 2048 /
-// 3072 / 4096 0.397 / 0.430 / 0.394 / 0.403, T at 1536 / 3072 / 4096 /
-// 8192 0.294 / 0.280 / 0.276 / 0.272)
-constexpr int kZBlocks3[5] = {1536, 1536, 3072, 8192, 1024};
+// flow 1.132 / 1.142 / 1.158 / 1.185 / 1.196 / 1.269, U transport 0.396 /
+// 0.376 / 0.428 / 0.388 / 0.399 / 0.405; T at 1536 / 3072 / 4096 / 8192
+// 0.294 / 0.280 / 0.276 / 0.272)
+constexpr int kZBlocks3[5] = {1536, 1536, 1536, 8192, 1024};
 static int rows3(const lbm_ctx* c, int kind) {
   const int r = c->rows3 != 0 ? c->rows3 : c->rows3k[kind] != 0 ? c->rows3k[kind] : kRows3Default[kind];
   return kind == 4 && c->storage == LBM_STORE_F64 ? 4 : r;
@@ -646,18 +646,25 @@ static lbm_status autotune3(lbm_ctx* c) {
   auto next_due = [&](int N) { return cycle_step(c, (c->k / N + 1) * (long long)N); };
   const bool f64 = c->storage == LBM_STORE_F64;
   const bool tr_ok = h.N_phi == 1 && !h.accum;
+  // the U transport of the next step reads the transfer's output buffer
+  // (not yet written) and writes a buffer two updates old, which that step
+  // overwrites again: it can be timed in place when U and phi advance
+  // together with instantaneous coupling
+  const bool u_ok = tr_ok && h.has_U && h.N_U == 1;
   // z-run block targets: 1536 and 3072 fill the chip in one and two rounds
   // of 64 x 8 blocks at three blocks per CU
   constexpr int NZ = 6;
   const int zs[NZ] = {1024, 1536, 2048, 3072, 4096, 8192};
   const bool log = std::getenv("LBM_AUTOTUNE_LOG") != nullptr;
-  for (int kind : {0, 1, 4}) {
+  for (int kind : {0, 1, 2, 4}) {
     if (kind == 1 && !tr_ok) continue;
+    if (kind == 2 && !u_ok) continue;
     if (kind == 4 && !h.has_F) continue;
     auto time_of = [&](int rows, int z) -> float {
       auto run = [&]() {
         if (kind == 0) c->ops3.phase(h, c->stream, c->d_dom, next_due(h.N_phi), rows, z);
         if (kind == 1) c->ops3.transfer(h, c->stream, c->d_dom, next_due(h.N_phi), c->s.part, rows, z);
+        if (kind == 2) c->ops3.scalar(0, h, c->stream, c->d_dom, next_due(h.N_U), c->s.part, rows, z);
         if (kind == 4) c->ops3.flow(h, c->stream, c->d_dom, next_due(h.N_F), rows, z);
       };
       run();
