@@ -463,11 +463,11 @@ static bool fuses_T(const lbm_ctx* c, unsigned k) {
 
 // 3D tile rows per kernel kind (0 phase, 1 transfer, 2 U, 3 T, 4 flow):
 // those fixed by lbm_configure, else the autotuner's pick (phase, transfer,
-// U transport, flow), else the height measured best on the 256 x 256 x 512 directional
-// workload (the flow's LDS window allows 8 rows with FP32 arithmetic only).
-// ms per launch at 4 / 8 rows, each at its best z runs: phase 0.433 /
-// 0.363, transfer 0.228 / 0.216, U 0.476 / 0.411, T 0.338 / 0.284, flow
-// 1.198 / 1.132
+// U transport, flow), else the height measured best on the 256 x 256 x 512
+// directional workload (the flow's LDS window allows 8 rows with FP32
+// arithmetic only).  ms per launch at 4 / 8 rows, each at its best z runs:
+// phase 0.433 / 0.363, transfer 0.228 / 0.216, U 0.418 / 0.376, T 0.338 /
+// 0.284, flow 1.198 / 1.132
 constexpr int kRows3Default[5] = {8, 8, 8, 8, 8};
 // z-run lengths: each kernel's runs aim at this many blocks of 256 threads
 // (half as many of 512), the fastest of 512 ... 8192 on the same workload
